@@ -1,0 +1,214 @@
+/*
+ * bddc.h -- C ABI of the MI355X (gfx950) deflated-PCG / three-level BDDC solver.
+ *
+ * Solves a sequence of systems K u_k = F_k that share one SPD matrix K, the
+ * Q1 (trilinear) discretisation of -div(c grad u) on a structured box with a
+ * Dirichlet part of the boundary (Hanek, Papez & Sistek, arXiv 2412.17543,
+ * Section 2: the pressure-corrector Poisson system with a fixed matrix and a
+ * new right-hand side each time step).  Each system is reduced to the
+ * interface between subdomains (Section 3.1, eq. Sug), solved by deflated
+ * PCG (Section 4.1, Algorithm 1) preconditioned by two- or three-level BDDC
+ * (Section 3.2, eqs. averaging_subdomain_solves, coarse_problem, localCorr),
+ * with the deflation basis recycled from earlier solves (Section 4.2, eqs.
+ * harmonicRitz and harmritzstopcrit), and the interior unknowns recovered.
+ *
+ * Conventions shared by every entry point
+ *   - mesh: nx*ny*nz hexahedra of size h; node (ix,iy,iz) has index
+ *     ix + (nx+1)*(iy + (ny+1)*iz), element (ex,ey,ez) has index
+ *     ex + nx*(ey + ny*ez), element vertex v = a + 2b + 4c at offset (a,b,c).
+ *   - nodal vectors are float64, length n_nodes = (nx+1)(ny+1)(nz+1), in that
+ *     node order.  Entries at Dirichlet nodes and at nodes touched by no kept
+ *     element are ignored on input and written as 0 on output.
+ *   - "device" pointers are HIP device memory on the current device; "host"
+ *     pointers are ordinary host memory.  The caller owns every buffer it
+ *     passes; bddc_setup copies what it needs and the context owns all
+ *     operators and the recycling state.
+ *   - all GPU work is enqueued on the stream given to bddc_setup; a context is
+ *     not thread-safe.  Entry points that return host results synchronise that
+ *     stream before returning.
+ *   - return value: 0 on success, a negative BDDC_E* code on failure; the
+ *     message of the last failure of the calling thread is bddc_last_error().
+ *     On failure no output is guaranteed except where stated.
+ */
+#ifndef BDDC_H
+#define BDDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define BDDC_OK          0
+#define BDDC_EINVAL     -1   /* bad argument (sizes, null pointers, options)       */
+#define BDDC_ENOMEM     -2   /* device or host allocation failed                   */
+#define BDDC_EHIP       -3   /* a HIP runtime call failed                          */
+#define BDDC_ESINGULAR  -4   /* a local, coarse or deflation matrix is singular    */
+#define BDDC_ENOTCONV   -5   /* max_it reached without meeting the tolerance       */
+#define BDDC_EBREAKDOWN -6   /* r^T z <= 0, p^T A p <= 0 or a NaN in the iteration */
+
+/* constraint bit mask (Section 3.2: corners, face and edge averages) */
+#define BDDC_CORNERS 1
+#define BDDC_FACES   2
+#define BDDC_EDGES   4
+
+typedef struct bddc_ctx bddc_ctx;   /* opaque, owned by the library */
+
+/* Structured box mesh.  h is the element size (the box is [0, nx*h] x ...). */
+typedef struct {
+    int32_t nx, ny, nz;
+    double h;
+    const uint8_t *elem_keep;       /* host, n_elem, nullable: 0 removes an element (holes) */
+    const uint8_t *node_dirichlet;  /* host, n_nodes, nullable: default = nodes with ix == nx */
+} bddc_mesh;
+
+/* Element partition (Section 3.1: non-overlapping subdomains along element
+ * boundaries) and, for three levels, the grouping of subdomains into
+ * subregions (Section 3.2, multilevel paragraph).  Subdomains must be
+ * connected through faces; removed elements carry any value. */
+typedef struct {
+    int32_t n_sub;
+    const int32_t *elem_to_sub;      /* host, n_elem, values in [0, n_sub)          */
+    int32_t n_subregion;             /* 0 -> two-level BDDC                          */
+    const int32_t *sub_to_subregion; /* host, n_sub, values in [0, n_subregion)      */
+} bddc_partition;
+
+typedef struct {
+    int32_t constraints;     /* BDDC_CORNERS | BDDC_FACES (| BDDC_EDGES)               */
+    int32_t weights;         /* 0: card (1/multiplicity), 1: diag (stiffness diagonal) */
+    int32_t local_prec;      /* storage of the constrained-Neumann operators N_i and
+                                coarse bases Phi_i: 64 (float64), 32 (float32, float32
+                                accumulation), 16 (bfloat16, float32 accumulation).
+                                The Schur products, residuals, dot products, coarse
+                                levels and deflation stay float64.                   */
+    int32_t recycle_R;       /* maximal deflation-basis size R, 0 = plain PCG          */
+    int32_t recycle_strategy;/* 4 = B4 (largest harmonic Ritz values, default),
+                                3 = B3 (smallest), 2 = B2 (last R directions),
+                                1 = B1 (first R directions)                          */
+    double  ritz_freeze_tol; /* eq. harmritzstopcrit threshold (paper: 1e-5)            */
+    int32_t stop_rule;       /* 0: ||r_k||/||b|| (eq. stopping_rhs), 1: ||r_k||/||r_0|| */
+    int32_t init_guess;      /* 0: previous solution (default), 1: zero                 */
+    int32_t max_it;          /* per right-hand side, e.g. 1000                          */
+    int32_t save_cap;        /* max search directions stored per solve for recycling   */
+    int32_t use_graph;       /* 1: capture the iteration as a hipGraph and poll the
+                                device convergence flag asynchronously                 */
+    int32_t reserved[4];
+} bddc_opts;
+
+/* Fills *o with the defaults: corners+faces, diag weights, float64 local
+ * operators, R = 0, B4, freeze 1e-5, ||r||/||b||, previous-solution guess,
+ * max_it 1000, save_cap 256, no graph. */
+void bddc_default_opts(bddc_opts *o);
+
+/*
+ * bddc_setup -- build the preconditioner and every operator of the solve.
+ *   mesh, part, opts : host structs (see above).
+ *   coef             : host, n_elem float64 element coefficients c_e > 0
+ *                      (element matrix c_e * h * Kref, Section 2).
+ *   hip_stream       : hipStream_t (NULL = default stream) used for all work.
+ *   out              : receives the new context.
+ * Computes, all on the device: local matrices K_i, interior elimination and
+ * the interface Schur complements S_i (Section 3.1), the constrained-Neumann
+ * operators N_i and coarse bases Phi_i of eq. localCorr, the coarse matrices
+ * of eq. coarse_problem and, for three levels, the subregion operators and
+ * the dense level-3 inverse.  Errors: EINVAL (sizes, partition values,
+ * non-positive coefficients), ESINGULAR (a subdomain without enough
+ * constraints), ENOMEM, EHIP.
+ */
+int bddc_setup(const bddc_mesh *mesh, const bddc_partition *part, const double *coef,
+               const bddc_opts *opts, void *hip_stream, bddc_ctx **out);
+
+/*
+ * dpcg_solve -- solve K u_k = F_k for k = 0..n_rhs-1 in order.
+ *   rhs_seq     : device, n_rhs x n_nodes float64 load vectors F_k (row k contiguous).
+ *   rtol        : relative tolerance of the stopping rule (Section 5).
+ *   x_seq       : device, n_rhs x n_nodes float64 output u_k.
+ *   iters       : host, n_rhs int32 (nullable): PCG iterations of each solve.
+ *   true_relres : host, n_rhs float64 (nullable): ||b - A x||/||b|| of the
+ *                 interface problem at exit, recomputed in float64.
+ * Each solve condenses F_k to the interface, runs Algorithm 1 from the
+ * previous solution with the current deflation basis, recovers the interior
+ * and, unless the basis is frozen, calls recycle_update.  On ENOTCONV the
+ * outputs of the failing solve hold the last iterate and iters = max_it;
+ * later right-hand sides are not solved.
+ */
+int dpcg_solve(bddc_ctx *ctx, const double *rhs_seq, int32_t n_rhs, double rtol,
+               double *x_seq, int32_t *iters, double *true_relres);
+
+/*
+ * recycle_update -- rebuild the deflation basis from the last solve
+ * (Section 4.2): V = [W, P], small matrices V^T A V and V^T A M^{-1} A V from
+ * the solve's own scalars, generalized eigenproblem, keep R vectors (B4:
+ * largest harmonic Ritz values), W <- V Y, A W <- [A W, A P] Y, W^T A W by a
+ * float64 Gram product, freeze test of eq. harmritzstopcrit.  dpcg_solve
+ * calls it after every solve; calling it again without a new solve is a no-op.
+ * Errors: ESINGULAR when the new W^T A W is not positive definite (the old
+ * basis is kept).
+ */
+int recycle_update(bddc_ctx *ctx);
+
+/* Forget the deflation basis and the previous solution (W = empty, x_prev = 0). */
+int bddc_reset_recycle(bddc_ctx *ctx);
+
+/*
+ * bddc_adjoint_grad -- gradient of a loss L(u_0..u_{n-1}) given dL/du_k.
+ *   dLdu_seq      : device, n_rhs x n_nodes, dL/du_k.
+ *   u_seq         : device, n_rhs x n_nodes, the forward solutions u_k.
+ *   rtol          : tolerance of the adjoint solves.
+ *   grad_logcoef  : device, n_elem float64 output dL/dtheta_e for c_e = exp(theta_e):
+ *                   - sum_k c_e h lambda_{k,e}^T Kref u_{k,e}.
+ *   grad_rhs_seq  : device, n_rhs x n_nodes output dL/dF_k = lambda_k = K^{-1} dL/du_k.
+ * The adjoint systems use the same preconditioner and the current deflation
+ * basis without updating it (K is symmetric).
+ */
+int bddc_adjoint_grad(bddc_ctx *ctx, const double *dLdu_seq, int32_t n_rhs, const double *u_seq,
+                      double rtol, double *grad_logcoef, double *grad_rhs_seq);
+
+/* ----- single operator applications on interface vectors (for testing) -----
+ * Interface vectors are float64 device arrays of length bddc_info(...)[1] in
+ * increasing node order of the interface nodes (free nodes shared by >= 2
+ * subdomains). */
+
+/* q = A p, the interface Schur complement product (Section 3.1, eq. Sug). */
+int bddc_apply_schur(bddc_ctx *ctx, const double *p, double *q);
+/* z = M^{-1} r, one BDDC application (eqs. averaging_subdomain_solves,
+ * coarse_problem, localCorr; three levels when subregions were given). */
+int bddc_apply_precond(bddc_ctx *ctx, const double *r, double *z);
+/* b = F_Gamma - sum_i R_i^T K_BI K_II^{-1} F_I  (Section 3.1), F nodal. */
+int bddc_condense(bddc_ctx *ctx, const double *F, double *b);
+
+/*
+ * bddc_info -- sizes, host int64 array of at least 16 entries:
+ *  [0] n_nodes [1] n_gamma (interface size) [2] n_sub [3] n_coarse (level-1)
+ *  [4] corners [5] faces [6] edges [7] level-2 interface [8] level-2 interior
+ *  [9] level-3 size [10] deflation columns now [11] frozen (0/1)
+ *  [12] bytes of the Schur operators [13] bytes of the Neumann operators
+ *  [14] max nB [15] total device bytes held
+ */
+int bddc_info(const bddc_ctx *ctx, int64_t *info);
+
+/* Interface node ids (host int64 out[n_gamma]) in interface-vector order. */
+int bddc_interface_nodes(const bddc_ctx *ctx, int64_t *out);
+
+/*
+ * bddc_stats -- per-kernel device time accumulated with HIP events while
+ * enabled (bddc_enable_timing).  out (host float64[3*n]) receives, for kernel
+ * class k: total milliseconds, launch count, algorithmic bytes per launch.
+ * Classes: 0 Schur product, 1 preconditioner local product, 2 coarse levels,
+ * 3 vector updates/reductions, 4 condensation/recovery, 5 recycle.
+ */
+int bddc_enable_timing(bddc_ctx *ctx, int32_t enable);
+int bddc_stats(const bddc_ctx *ctx, double *out, int32_t n);
+
+/* Theta (selected harmonic Ritz values, host float64[R]) of the last update. */
+int bddc_ritz_values(const bddc_ctx *ctx, double *theta, int32_t cap, int32_t *count);
+
+void bddc_destroy(bddc_ctx *ctx);
+const char *bddc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BDDC_H */

@@ -1,0 +1,56 @@
+"""Pins of the adjoint gradient against central finite differences and an identity."""
+import numpy as np
+
+import workload
+from oracle import adjoint, q1
+
+
+def _setup(nx=8, n_rhs=3):
+    F = workload.rhs_sequence(nx, n_rhs)
+    g = np.random.default_rng(4)
+    theta_t = 0.5 * g.standard_normal(nx ** 3)
+    T = q1.direct_solve(nx, np.exp(theta_t), F)
+    theta = 0.3 * g.standard_normal(nx ** 3)
+    return F, T, theta
+
+
+def test_gradient_matches_central_differences():
+    nx = 8
+    F, T, theta = _setup(nx)
+    L, g, lam, U = adjoint.loss_and_grad(nx, theta, F, T)
+    # step 1e-4: truncation O(eps^2) ~ 1e-8; at 1e-6 the rounding of the solves
+    # (~1e-13 L) divided by 2 eps dominates
+    eps = 1e-4
+    idx = np.random.default_rng(1).choice(nx ** 3, 12, replace=False)
+    fd = []
+    for e in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[e] += eps
+        tm[e] -= eps
+        fd.append((adjoint.loss(nx, tp, F, T) - adjoint.loss(nx, tm, F, T)) / (2 * eps))
+    fd = np.array(fd)
+    err = np.abs(g[idx] - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
+    assert err.max() < 1e-5, err
+
+
+def test_gradient_scaling_identity():
+    # K(theta + t 1) = e^t K(theta)  =>  sum_e dL/dtheta_e = - sum_k lambda_k^T F_k
+    nx = 8
+    F, T, theta = _setup(nx)
+    L, g, lam, U = adjoint.loss_and_grad(nx, theta, F, T)
+    fr = q1.free_nodes(nx)
+    rhs = -sum(lam[k, fr] @ F[k, fr] for k in range(len(F)))
+    assert abs(g.sum() - rhs) <= 1e-10 * abs(rhs)
+
+
+def test_rhs_gradient_is_adjoint():
+    # L is quadratic in F: a central difference along any direction is exact to roundoff
+    nx = 8
+    F, T, theta = _setup(nx)
+    L, g, lam, U = adjoint.loss_and_grad(nx, theta, F, T)
+    d = np.random.default_rng(2).standard_normal(F.shape)
+    eps = 1e-3 * np.abs(F).max()
+    Lp = adjoint.loss(nx, theta, F + eps * d, T)
+    Lm = adjoint.loss(nx, theta, F - eps * d, T)
+    fr = q1.free_nodes(nx)
+    np.testing.assert_allclose((Lp - Lm) / (2 * eps), (lam[:, fr] * d[:, fr]).sum(), rtol=1e-7)

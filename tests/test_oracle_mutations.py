@@ -1,0 +1,57 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that a pin fails.
+
+Each planted bug is a monkeypatch of one oracle function; the pin that should
+catch it is re-run and must raise.
+"""
+import numpy as np
+import pytest
+
+from oracle import bddc, q1
+from tests import test_oracle_bddc as tb
+from tests import test_oracle_q1 as tq
+
+
+def test_wrong_kref_entry_is_caught(monkeypatch):
+    orig = q1.kref
+
+    def bad():
+        K = orig()
+        K[0, 7] = K[7, 0] = 0.0          # dropped body-diagonal coupling
+        return K
+    monkeypatch.setattr(q1, "kref", bad)
+    with pytest.raises(AssertionError):
+        tq.test_kref_matches_quadrature()
+    with pytest.raises(AssertionError):
+        tq.test_kref_kernel_is_constants()
+
+
+def test_unnormalised_weights_are_caught(monkeypatch):
+    orig = bddc.weights
+    monkeypatch.setattr(bddc, "weights", lambda ss, kind="diag": [np.ones_like(d) for d in orig(ss, kind)])
+    with pytest.raises(AssertionError):
+        tb.test_partition_of_unity("diag")
+
+
+def test_dropped_coarse_correction_is_caught(monkeypatch):
+    monkeypatch.setattr(bddc.BDDC, "coarse_solve", lambda self, rC: np.zeros_like(rC))
+    with pytest.raises(AssertionError):
+        tb.test_all_corners_gives_exact_inverse()
+
+
+def test_transposed_coarse_basis_is_caught(monkeypatch):
+    orig_init = bddc._LocalSaddle.__init__
+
+    def bad_init(self, *a, **k):
+        orig_init(self, *a, **k)
+        self.Phi = self.Phi[::-1, :].copy()   # wrong row order of Phi_i
+    monkeypatch.setattr(bddc._LocalSaddle, "__init__", bad_init)
+    with pytest.raises(AssertionError):
+        tb.test_coarse_basis_satisfies_constraints()
+
+
+def test_dropped_interior_correction_is_caught(monkeypatch):
+    from oracle.substructure import Substructuring
+    # S_i = K_BB without the - K_BI K_II^{-1} K_IB term
+    monkeypatch.setattr(Substructuring, "apply_S_local", lambda self, i, xb: self.sub[i]["KBB"] @ xb)
+    with pytest.raises(AssertionError):
+        tb.test_schur_equals_global_elimination()

@@ -1,0 +1,217 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU library.
+
+This module only *generates input data* (meshes, partitions, coefficient
+fields, right-hand-side sequences).  It holds none of the solver's arithmetic:
+no stiffness matrices, no substructuring, no preconditioner, no Krylov method.
+Both the CPU oracle (``oracle/``) and the HIP path (``paper_2412_17543_amd``)
+consume what it returns, the way they would both read the same input file.
+
+Conventions (used by every consumer):
+
+* structured box of ``nx*ny*nz`` hexahedral elements on the unit cube,
+  element size ``h = 1/nx``;
+* node ``(ix, iy, iz)`` has index ``ix + (nx+1)*(iy + (ny+1)*iz)``
+  (x fastest), element ``(ex, ey, ez)`` has index ``ex + nx*(ey + ny*ez)``;
+* element vertex ``v = a + 2b + 4c`` sits at offset ``(a, b, c)``.
+
+Seeds come from one root ``SeedSequence`` split per purpose, so that e.g. the
+noise of step k never changes when the number of steps changes.
+
+The right-hand side of the pressure-corrector problem (Section 2, eq. of the
+algebraic systems) changes every time step while the matrix is fixed; the paper's
+sequence comes from a flow solver that is not available, so a drifting sum of
+Gaussians with additive noise stands in for it (the paper only fixes "fixed SPD
+matrix, new right-hand side each step").
+"""
+from __future__ import annotations
+
+import numpy as np
+
+ROOT_SEED = 20241217
+PURPOSES = ("centres", "directions", "noise", "coef", "partition", "target", "fd", "misc")
+
+
+def seed(purpose: str) -> np.random.SeedSequence:
+    """Per-purpose child of the root seed sequence."""
+    kids = np.random.SeedSequence(ROOT_SEED).spawn(len(PURPOSES))
+    return kids[PURPOSES.index(purpose)]
+
+
+def rng(purpose: str, *sub: int) -> np.random.Generator:
+    ss = seed(purpose)
+    for s in sub:
+        ss = ss.spawn(s + 1)[s]
+    return np.random.default_rng(ss)
+
+
+# ----------------------------------------------------------------------------
+# mesh index helpers (pure bookkeeping)
+# ----------------------------------------------------------------------------
+
+def n_nodes(nx: int, ny: int | None = None, nz: int | None = None) -> int:
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    return (nx + 1) * (ny + 1) * (nz + 1)
+
+
+def element_nodes(nx: int, ny: int | None = None, nz: int | None = None) -> np.ndarray:
+    """(n_elem, 8) int64 array of node indices, vertex v = a + 2b + 4c."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    e = np.arange(nx * ny * nz, dtype=np.int64)
+    ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+    out = np.empty((e.size, 8), dtype=np.int64)
+    for v in range(8):
+        a, b, c = v & 1, (v >> 1) & 1, (v >> 2) & 1
+        out[:, v] = (ex + a) + (nx + 1) * ((ey + b) + (ny + 1) * (ez + c))
+    return out
+
+
+def node_coords(nx: int, ny: int | None = None, nz: int | None = None) -> np.ndarray:
+    """(n_nodes, 3) coordinates, h = 1/nx in every direction."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    h = 1.0 / nx
+    n = np.arange((nx + 1) * (ny + 1) * (nz + 1), dtype=np.int64)
+    ix, iy, iz = n % (nx + 1), (n // (nx + 1)) % (ny + 1), n // ((nx + 1) * (ny + 1))
+    return np.stack([ix * h, iy * h, iz * h], axis=1)
+
+
+def element_centroids(nx: int) -> np.ndarray:
+    h = 1.0 / nx
+    e = np.arange(nx ** 3, dtype=np.int64)
+    ex, ey, ez = e % nx, (e // nx) % nx, e // (nx * nx)
+    return np.stack([(ex + 0.5) * h, (ey + 0.5) * h, (ez + 0.5) * h], axis=1)
+
+
+# ----------------------------------------------------------------------------
+# partitions (element -> subdomain, subdomain -> subregion)
+# ----------------------------------------------------------------------------
+
+def cube_partition(nx: int, sub_elems: int) -> np.ndarray:
+    """Split an nx^3 box into (nx/sub_elems)^3 cube subdomains, lexicographic."""
+    assert nx % sub_elems == 0
+    m = nx // sub_elems
+    e = np.arange(nx ** 3)
+    ex, ey, ez = e % nx, (e // nx) % nx, e // (nx * nx)
+    sx, sy, sz = ex // sub_elems, ey // sub_elems, ez // sub_elems
+    return (sx + m * (sy + m * sz)).astype(np.int32)
+
+
+def cube_subregions(m: int, group: int) -> np.ndarray:
+    """Group an m^3 lattice of subdomains into (m/group)^3 subregions."""
+    assert m % group == 0
+    g = m // group
+    s = np.arange(m ** 3)
+    sx, sy, sz = s % m, (s // m) % m, s // (m * m)
+    return ((sx // group) + g * ((sy // group) + g * (sz // group))).astype(np.int32)
+
+
+def sphere_hole_keep(nx: int, centre=(0.5, 0.5, 0.5), radius: float = 0.15) -> np.ndarray:
+    """uint8 mask: 1 for elements kept, 0 for elements whose centroid lies in the ball."""
+    c = element_centroids(nx)
+    d2 = ((c - np.asarray(centre)) ** 2).sum(axis=1)
+    return (d2 > radius * radius).astype(np.uint8)
+
+
+def lognormal_coef(n_elem: int, sigma: float, purpose: str = "coef", sub: int = 0) -> np.ndarray:
+    """Per-element coefficient exp(sigma * xi), xi ~ N(0, 1)."""
+    g = rng(purpose, sub)
+    return np.exp(sigma * g.standard_normal(n_elem))
+
+
+# ----------------------------------------------------------------------------
+# right-hand-side sequence
+# ----------------------------------------------------------------------------
+
+def _reflect01(x: np.ndarray) -> np.ndarray:
+    """Reflect coordinates back into [0, 1] (mirror at the box faces)."""
+    y = np.mod(x, 2.0)
+    return np.where(y > 1.0, 2.0 - y, y)
+
+
+def gaussian_centres(n_rhs: int, n_gauss: int = 4, drift: float = 0.01) -> np.ndarray:
+    """(n_rhs, n_gauss, 3) drifting centres c_{g,k} = c_{g,0} + drift*k*d_g, reflected."""
+    c0 = rng("centres").uniform(0.2, 0.8, size=(n_gauss, 3))
+    d = rng("directions").standard_normal((n_gauss, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    k = np.arange(n_rhs)[:, None, None]
+    return _reflect01(c0[None] + drift * k * d[None])
+
+
+def nodal_source(nx: int, k: int, centres: np.ndarray, width: float = 0.1,
+                 noise: float = 1e-3) -> np.ndarray:
+    """Nodal values of f_k = sum_g exp(-|x-c|^2/(2 w^2)) + noise * N(0,1)."""
+    x = node_coords(nx)
+    f = np.zeros(x.shape[0])
+    for c in centres[k]:
+        f += np.exp(-((x - c) ** 2).sum(axis=1) / (2.0 * width * width))
+    f += noise * rng("noise", k).standard_normal(x.shape[0])
+    return f
+
+
+_M1 = np.array([[1.0 / 3.0, 1.0 / 6.0], [1.0 / 6.0, 1.0 / 3.0]])
+
+
+def consistent_load(nx: int, f_nodal: np.ndarray, elem_keep: np.ndarray | None = None) -> np.ndarray:
+    """Load vector F = M f of trilinear interpolant f with the consistent Q1 mass.
+
+    This is input preparation (turning a nodal source into a load vector), the
+    same for every consumer; M_e = h^3 (M1 (x) M1 (x) M1).
+    """
+    h = 1.0 / nx
+    mref = np.kron(_M1, np.kron(_M1, _M1)) * h ** 3  # vertex v = a + 2b + 4c, x fastest
+    en = element_nodes(nx)
+    if elem_keep is not None:
+        en = en[elem_keep.astype(bool)]
+    fe = f_nodal[en] @ mref.T
+    return np.bincount(en.ravel(), weights=fe.ravel(), minlength=n_nodes(nx))
+
+
+def rhs_sequence(nx: int, n_rhs: int, elem_keep: np.ndarray | None = None,
+                 first: int = 0) -> np.ndarray:
+    """(n_rhs, n_nodes) float64 load vectors F_k, k = first .. first+n_rhs-1."""
+    cen = gaussian_centres(first + n_rhs)
+    out = np.empty((n_rhs, n_nodes(nx)))
+    for i in range(n_rhs):
+        out[i] = consistent_load(nx, nodal_source(nx, first + i, cen), elem_keep)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# named workloads
+# ----------------------------------------------------------------------------
+
+def workload(name: str) -> dict:
+    """Mesh/partition/options of the named synthetic workloads.
+
+    * ``c16``: 16^3 elements, 2x2x2 subdomains of 8^3, two-level, plain PCG, 10 RHS.
+    * ``c64``: 64^3 elements, 8^3 subdomains of 8^3, three-level (subregions of
+      2x2x2 subdomains), deflated PCG with a 20-vector recycled basis, 50 RHS.
+    * ``c96``: 96^3 elements, 12^3 subdomains, three-level, 20 RHS (adjoint form).
+    * ``c192``: 192^3 elements, 24^3 subdomains, three-level, 40-vector basis.
+    * ``tiny``: 8^3 elements, 2x2x2 subdomains of 4^3 (tests).
+    """
+    specs = {
+        "tiny": dict(nx=8, sub=4, group=0, R=0, n_rhs=3),
+        "tiny3": dict(nx=16, sub=4, group=2, R=0, n_rhs=3),
+        "c16": dict(nx=16, sub=8, group=0, R=0, n_rhs=10),
+        "c64": dict(nx=64, sub=8, group=2, R=20, n_rhs=50),
+        "c96": dict(nx=96, sub=8, group=2, R=20, n_rhs=20),
+        "c192": dict(nx=192, sub=8, group=2, R=40, n_rhs=200),
+    }
+    s = dict(specs[name])
+    nx, sub, group = s["nx"], s["sub"], s["group"]
+    m = nx // sub
+    s["elem_to_sub"] = cube_partition(nx, sub)
+    s["n_sub"] = m ** 3
+    if group:
+        s["sub_to_subregion"] = cube_subregions(m, group)
+        s["n_subregion"] = (m // group) ** 3
+    else:
+        s["sub_to_subregion"] = None
+        s["n_subregion"] = 0
+    s["coef"] = np.ones(nx ** 3)
+    s["elem_keep"] = None
+    s["name"] = name
+    return s
