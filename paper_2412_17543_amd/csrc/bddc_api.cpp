@@ -1,0 +1,1209 @@
+// C ABI of the solver: setup, deflated PCG over a right-hand-side sequence,
+// Krylov subspace recycling, adjoint gradient (see include/bddc.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+
+#include "internal.h"
+#include "kernels.h"
+
+using namespace bddc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                        \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess)                                                            \
+            return fail(BDDC_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+enum { TK_SCHUR = 0, TK_PREC, TK_COARSE, TK_VEC, TK_COND, TK_REC, TK_N };
+
+}  // namespace
+
+struct bddc_ctx {
+    hipStream_t stream = nullptr;
+    bddc_opts opts{};
+    Structure st;
+    int prec = 64;
+    int n_gamma = 0, n_sub = 0, nC = 0;
+    int64_t n_nodes = 0;
+    std::vector<void *> allocs;
+    size_t dev_bytes = 0;
+    size_t bytes_S = 0, bytes_N = 0;
+
+    // level 1
+    int32_t *d_nB = nullptr, *d_nI = nullptr, *d_b_off = nullptr, *d_i_off = nullptr, *d_nc = nullptr,
+            *d_c_off = nullptr, *d_gB = nullptr, *d_nodesI = nullptr, *d_cidx = nullptr, *d_cL = nullptr,
+            *d_gamma = nullptr;
+    int64_t *d_k_off = nullptr, *d_s_off = nullptr, *d_n_off = nullptr;
+    double *d_K = nullptr, *d_S = nullptr, *d_KC = nullptr;
+    void *d_N = nullptr;
+    int32_t *d_asm_ptr = nullptr, *d_asm_idx = nullptr, *d_casm_ptr = nullptr, *d_casm_idx = nullptr;
+    int max_nI = 0, max_nB = 0, max_nc = 0;
+    size_t smem_S = 0, smem_N = 0, smem_prol = 0;
+    // iteration vectors
+    double *d_b = nullptr, *d_x = nullptr, *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_tmp = nullptr;
+    double *d_locq = nullptr, *d_locu = nullptr, *d_locc = nullptr, *d_yI = nullptr, *d_partial = nullptr;
+    // coarse
+    bool three = false;
+    double *d_KCinv = nullptr, *d_uC = nullptr;
+    int nsr = 0, n3 = 0, max_nL = 0;
+    int32_t *d_nL = nullptr, *d_nI2 = nullptr, *d_L_off = nullptr, *d_L = nullptr, *d_I2_off = nullptr,
+            *d_B2_off = nullptr, *d_g2 = nullptr, *d_asm2_ptr = nullptr, *d_asm2_idx = nullptr,
+            *d_pos_sr = nullptr, *d_nc3 = nullptr, *d_C3_off = nullptr, *d_c3 = nullptr,
+            *d_sr_of_sub = nullptr, *d_asm3_ptr = nullptr, *d_asm3_idx = nullptr;
+    int64_t *d_K2_off = nullptr, *d_N2_off = nullptr, *d_P2_off = nullptr;
+    double *d_K2 = nullptr, *d_N2 = nullptr, *d_Phi2 = nullptr, *d_K3inv = nullptr, *d_vI2 = nullptr,
+           *d_t2 = nullptr, *d_rB2 = nullptr, *d_u2 = nullptr, *d_c3loc = nullptr, *d_u3 = nullptr;
+    // deflation / recycling
+    int R = 0, k = 0, save_cap = 0;
+    int64_t ld = 0;
+    double *d_W = nullptr, *d_AW = nullptr, *d_Wn = nullptr, *d_AWn = nullptr, *d_P = nullptr, *d_AP = nullptr;
+    double *d_Lc = nullptr, *d_Y = nullptr, *d_G = nullptr;
+    std::vector<double> WAW, GWW, theta;
+    bool frozen = false;
+    int freeze_step = -1, n_updates = 0;
+    // histories of the last solve
+    int hist_cap = 0;
+    double *d_ahist = nullptr, *d_dhist = nullptr, *d_rhohist = nullptr, *d_bhist = nullptr, *d_muhist = nullptr,
+           *d_reshist = nullptr;
+    // control
+    Ctl *d_ctl = nullptr, *h_ctl = nullptr;
+    int32_t *d_status = nullptr;
+    bool have_solve = false;
+    int last_iters = 0, last_restarts = 0, last_status = 0;
+    // element data for the adjoint gradient
+    double *d_coefh = nullptr;
+    uint8_t *d_keep = nullptr, *d_free = nullptr;
+    // timing
+    bool timing = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> ev_pool;
+    double t_ms[TK_N] = {0}, t_cnt[TK_N] = {0}, t_bytes[TK_N] = {0};
+};
+
+namespace {
+
+template <typename T>
+int dalloc(bddc_ctx *c, T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T));
+    if (e != hipSuccess) return fail(BDDC_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    c->allocs.push_back(q);
+    c->dev_bytes += count * sizeof(T);
+    *p = (T *)q;
+    return 0;
+}
+
+template <typename T>
+int dupload(bddc_ctx *c, T **p, const std::vector<T> &v) {
+    int rc = dalloc(c, p, v.size());
+    if (rc) return rc;
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return 0;
+}
+
+void dfree(bddc_ctx *c, void *p) {
+    if (!p) return;
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+    if (it != c->allocs.end()) c->allocs.erase(it);
+    hipFree(p);
+}
+
+// CSR from (target, source) pairs; stable in insertion order
+void build_csr(int64_t ntarget, const std::vector<std::pair<int64_t, int32_t>> &pairs, std::vector<int32_t> &ptr,
+               std::vector<int32_t> &idx) {
+    ptr.assign(ntarget + 1, 0);
+    for (auto &p : pairs) ptr[p.first + 1]++;
+    for (int64_t t = 0; t < ntarget; ++t) ptr[t + 1] += ptr[t];
+    idx.resize(pairs.size());
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (auto &p : pairs) idx[fill[p.first]++] = p.second;
+}
+
+int64_t ntiles_of(int n, int nc) {
+    const int64_t nt = (n + TILE - 1) / TILE, ntc = (nc + TILE - 1) / TILE;
+    return nt * (nt + 1) / 2 + nt * ntc;
+}
+
+// -------------------------------------------------------------------- timing
+hipEvent_t get_event(bddc_ctx *c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    hipEventCreate(&e);
+    return e;
+}
+struct TScope {
+    bddc_ctx *c;
+    int k;
+    hipEvent_t a = nullptr;
+    TScope(bddc_ctx *c_, int k_) : c(c_), k(k_) {
+        if (c->timing) { a = get_event(c); hipEventRecord(a, c->stream); }
+    }
+    ~TScope() {
+        if (c->timing) {
+            hipEvent_t b = get_event(c);
+            hipEventRecord(b, c->stream);
+            c->pending.push_back({k, {a, b}});
+        }
+    }
+};
+void flush_timing(bddc_ctx *c) {
+    for (auto &p : c->pending) {
+        float ms = 0;
+        hipEventElapsedTime(&ms, p.second.first, p.second.second);
+        c->t_ms[p.first] += ms;
+        c->t_cnt[p.first] += 1;
+        c->ev_pool.push_back(p.second.first);
+        c->ev_pool.push_back(p.second.second);
+    }
+    c->pending.clear();
+}
+
+// ------------------------------------------------------------- sub-steps
+int sync_ctl(bddc_ctx *c) {
+    HIPCHK(hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int set_done(bddc_ctx *c, int v) {
+    int32_t val = v;
+    HIPCHK(hipMemcpyAsync(&c->d_ctl->done, &val, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+SymvArgs schur_args(bddc_ctx *c, const double *x, int mode) {
+    SymvArgs a{};
+    a.tiles = c->d_S; a.t_off = c->d_s_off;
+    a.nB = c->d_nB; a.b_off = c->d_b_off; a.gB = c->d_gB;
+    a.nc = nullptr; a.c_off = nullptr;
+    a.x = x; a.y = c->d_locq; a.c = nullptr;
+    a.partial = mode == 1 ? c->d_partial : nullptr;
+    a.ctl = c->d_ctl; a.mode = mode; a.gated = mode == 1;
+    a.d_hist = c->d_dhist; a.a_hist = c->d_ahist; a.hist_cap = c->hist_cap;
+    return a;
+}
+
+void run_schur(bddc_ctx *c, const double *x, int mode) {
+    TScope ts(c, TK_SCHUR);
+    launch_symv(schur_args(c, x, mode), 64, c->n_sub, c->smem_S, c->stream);
+}
+
+// z = M^{-1} r into c->d_z (or out); with reductions when `reduce`
+void run_precond(bddc_ctx *c, const double *r, double *zout, bool reduce, bool first, bool gated) {
+    {
+        TScope ts(c, TK_PREC);
+        SymvArgs a{};
+        a.tiles = c->d_N; a.t_off = c->d_n_off;
+        a.nB = c->d_nB; a.b_off = c->d_b_off; a.gB = c->d_gB;
+        a.nc = c->d_nc; a.c_off = c->d_c_off;
+        a.x = r; a.y = c->d_locu; a.c = c->d_locc;
+        a.partial = nullptr; a.ctl = c->d_ctl; a.mode = 0; a.gated = gated ? 1 : 0;
+        launch_symv(a, c->prec, c->n_sub, c->smem_N, c->stream);
+    }
+    {
+        TScope ts(c, TK_COARSE);
+        ProlArgs p{};
+        p.ctl = c->d_ctl;
+        p.nB = c->d_nB; p.b_off = c->d_b_off; p.nc = c->d_nc; p.c_off = c->d_c_off; p.cidx = c->d_cidx; p.cL = c->d_cL;
+        p.tiles = c->d_N; p.t_off = c->d_n_off;
+        p.locu = c->d_locu;
+        if (c->three) {
+            L2Args l{};
+            l.ctl = c->d_ctl;
+            l.nL = c->d_nL; l.nI2 = c->d_nI2; l.L_off = c->d_L_off; l.L = c->d_L; l.I2_off = c->d_I2_off;
+            l.B2_off = c->d_B2_off; l.g2 = c->d_g2; l.cptr = c->d_casm_ptr; l.cidx_asm = c->d_casm_idx;
+            l.locc = c->d_locc; l.K2_off = c->d_K2_off; l.K2 = c->d_K2; l.vI2 = c->d_vI2; l.t2 = c->d_t2;
+            l.rB2 = c->d_rB2; l.asm2_ptr = c->d_asm2_ptr; l.asm2_idx = c->d_asm2_idx; l.N2_off = c->d_N2_off;
+            l.N2 = c->d_N2; l.P2_off = c->d_P2_off; l.Phi2 = c->d_Phi2; l.nc3 = c->d_nc3; l.C3_off = c->d_C3_off;
+            l.u2 = c->d_u2; l.c3loc = c->d_c3loc;
+            launch_l2_a(l, c->nsr, c->max_nL, c->stream);
+            launch_l2_b(l, c->nsr, c->max_nL, c->stream);
+            CoarseArgs ca{};
+            ca.ctl = c->d_ctl; ca.n = c->n3; ca.ptr = c->d_asm3_ptr; ca.idx = c->d_asm3_idx; ca.loc = c->d_c3loc;
+            ca.Kneg = c->d_K3inv; ca.u = c->d_u3;
+            if (c->n3 > 0) launch_coarse_solve(ca, c->stream);
+            p.three = 1;
+            p.sr_of_sub = c->d_sr_of_sub; p.nL = c->d_nL; p.nI2 = c->d_nI2; p.I2_off = c->d_I2_off;
+            p.B2_off = c->d_B2_off; p.g2 = c->d_g2; p.asm2_ptr = c->d_asm2_ptr; p.asm2_idx = c->d_asm2_idx;
+            p.pos_sr = c->d_pos_sr; p.nc3 = c->d_nc3; p.C3_off = c->d_C3_off; p.c3 = c->d_c3;
+            p.K2_off = c->d_K2_off; p.P2_off = c->d_P2_off; p.K2 = c->d_K2; p.Phi2 = c->d_Phi2;
+            p.u2 = c->d_u2; p.u3 = c->d_u3; p.vI2 = c->d_vI2;
+        } else {
+            CoarseArgs ca{};
+            ca.ctl = c->d_ctl; ca.n = c->nC; ca.ptr = c->d_casm_ptr; ca.idx = c->d_casm_idx; ca.loc = c->d_locc;
+            ca.Kneg = c->d_KCinv; ca.u = c->d_uC;
+            if (c->nC > 0) launch_coarse_solve(ca, c->stream);
+            p.three = 0;
+            p.uCg = c->d_uC;
+        }
+        launch_prolong(p, c->prec, c->n_sub, c->smem_prol, c->stream);
+    }
+    {
+        TScope ts(c, TK_VEC);
+        ZasmArgs z{};
+        z.n = c->n_gamma; z.ptr = c->d_asm_ptr; z.idx = c->d_asm_idx; z.loc = c->d_locu; z.r = r;
+        z.z = zout; z.AW = c->d_AW; z.ld = c->ld; z.Lc = c->d_Lc;
+        z.partial = reduce ? c->d_partial : nullptr;
+        z.ctl = c->d_ctl; z.first = first ? 1 : 0; z.gated = gated ? 1 : 0;
+        z.rho_hist = c->d_rhohist; z.b_hist = c->d_bhist; z.mu_hist = c->d_muhist; z.hist_cap = c->hist_cap;
+        launch_zasm(z, c->stream);
+    }
+}
+
+void run_pupd(bddc_ctx *c) {
+    TScope ts(c, TK_VEC);
+    PupdArgs a{};
+    a.n = c->n_gamma; a.z = c->d_z; a.p = c->d_p; a.W = c->d_W; a.ld = c->ld;
+    a.P = c->d_P; a.cap = c->save_cap; a.ctl = c->d_ctl;
+    launch_pupd(a, c->stream);
+}
+
+void run_update(bddc_ctx *c) {
+    TScope ts(c, TK_VEC);
+    UpdArgs a{};
+    a.n = c->n_gamma; a.ptr = c->d_asm_ptr; a.idx = c->d_asm_idx; a.loc = c->d_locq; a.p = c->d_p;
+    a.x = c->d_x; a.r = c->d_r; a.AP = c->d_AP; a.ld = c->ld; a.cap = c->save_cap;
+    a.partial = c->d_partial; a.ctl = c->d_ctl; a.res_hist = c->d_reshist; a.hist_cap = c->hist_cap;
+    a.max_it = c->opts.max_it;
+    launch_update(a, c->stream);
+}
+
+void run_resid(bddc_ctx *c, int mode, double *out) {
+    TScope ts(c, TK_VEC);
+    ResidArgs a{};
+    a.n = c->n_gamma; a.mode = mode; a.stop_rule = c->opts.stop_rule;
+    a.ptr = c->d_asm_ptr; a.idx = c->d_asm_idx; a.loc = c->d_locq; a.b = c->d_b; a.out = out;
+    a.W = c->d_W; a.ld = c->ld; a.Lc = c->d_Lc; a.partial = c->d_partial; a.ctl = c->d_ctl;
+    launch_resid(a, c->stream);
+}
+
+void run_condense(bddc_ctx *c, const double *F) {
+    TScope ts(c, TK_COND);
+    CondArgs a{};
+    a.nI = c->d_nI; a.nB = c->d_nB; a.i_off = c->d_i_off; a.b_off = c->d_b_off; a.nodesI = c->d_nodesI;
+    a.k_off = c->d_k_off; a.K = c->d_K; a.F = F; a.yI = c->d_yI; a.t = c->d_locq;
+    launch_cond_local(a, c->n_sub, c->max_nI, c->stream);
+    CondAsmArgs b{};
+    b.n = c->n_gamma; b.gamma = c->d_gamma; b.ptr = c->d_asm_ptr; b.idx = c->d_asm_idx; b.F = F; b.loc = c->d_locq;
+    b.b = c->d_b; b.partial = c->d_partial; b.ctl = c->d_ctl;
+    launch_cond_asm(b, c->stream);
+}
+
+int run_recover(bddc_ctx *c, double *u) {
+    TScope ts(c, TK_COND);
+    HIPCHK(hipMemsetAsync(u, 0, c->n_nodes * sizeof(double), c->stream));
+    RecArgs a{};
+    a.nI = c->d_nI; a.nB = c->d_nB; a.i_off = c->d_i_off; a.b_off = c->d_b_off; a.nodesI = c->d_nodesI;
+    a.gB = c->d_gB; a.k_off = c->d_k_off; a.K = c->d_K; a.x = c->d_x; a.yI = c->d_yI; a.u = u;
+    launch_recover(a, c->n_sub, c->max_nB, c->stream);
+    launch_scatter_gamma(c->n_gamma, c->d_gamma, c->d_x, u, c->stream);
+    return 0;
+}
+
+int upload_ctl(bddc_ctx *c, double rtol, bool record) {
+    Ctl h{};
+    h.rtol2 = rtol * rtol;
+    h.k = c->k;
+    h.record = record ? 1 : 0;
+    *c->h_ctl = h;
+    HIPCHK(hipMemcpyAsync(c->d_ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+// One right-hand side: condense, Algorithm 1 from x_prev, recover.
+int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle, int *iters, double *relres) {
+    const bool record = recycle && c->R > 0 && !c->frozen;
+    int rc = upload_ctl(c, rtol, record);
+    if (rc) return rc;
+    run_condense(c, F);
+    if (c->opts.init_guess == 1) HIPCHK(hipMemsetAsync(c->d_x, 0, c->n_gamma * sizeof(double), c->stream));
+    run_schur(c, c->d_x, 0);                 // r = b - A x_{-1}
+    run_resid(c, 0, c->d_r);
+    if (c->k > 0) {                          // Alg. 1 lines 3-4
+        TScope ts(c, TK_VEC);
+        DeflArgs d{};
+        d.n = c->n_gamma; d.stop_rule = c->opts.stop_rule; d.x = c->d_x; d.r = c->d_r; d.W = c->d_W;
+        d.AW = c->d_AW; d.ld = c->ld; d.partial = c->d_partial; d.ctl = c->d_ctl;
+        launch_defl_init(d, c->stream);
+    }
+    if ((rc = sync_ctl(c))) return rc;
+    int restarts = 0;
+    while (true) {
+        if (!c->h_ctl->done) {
+            run_precond(c, c->d_r, c->d_z, true, true, true);   // lines 5-6
+            run_pupd(c);                                        // line 7
+            for (;;) {
+                run_schur(c, c->d_p, 1);                        // line 9 (A p, alpha)
+                run_update(c);                                  // lines 10-11, stopping test
+                run_precond(c, c->d_r, c->d_z, true, false, true);  // lines 13-15
+                run_pupd(c);                                    // line 16
+                if ((rc = sync_ctl(c))) return rc;
+                if (c->h_ctl->done) break;
+            }
+        }
+        // true residual of the interface problem in float64
+        run_schur(c, c->d_x, 0);
+        run_resid(c, 1, c->d_tmp);
+        if ((rc = sync_ctl(c))) return rc;
+        const Ctl &h = *c->h_ctl;
+        if (h.status != 0) break;
+        if (h.true_rr < h.rtol2 * h.denom2 || h.bb == 0.0 || h.iter >= c->opts.max_it) break;
+        // residual replacement and restart (counted iterations continue)
+        ++restarts;
+        launch_copy(c->n_gamma, c->d_tmp, c->d_r, c->stream);
+        if ((rc = set_done(c, 0))) return rc;
+        if ((rc = sync_ctl(c))) return rc;
+    }
+    const Ctl h = *c->h_ctl;
+    c->last_iters = h.iter;
+    c->last_restarts = restarts;
+    c->last_status = h.status;
+    c->have_solve = true;
+    if (iters) *iters = h.iter;
+    if (relres) *relres = h.bb > 0 ? std::sqrt(h.true_rr / h.bb) : 0.0;
+    // z_l = M^{-1} r_l for the harmonic-Ritz matrices (Section 4.2)
+    const int strat = c->opts.recycle_strategy;
+    if (record && h.status == 0 && restarts == 0 && (strat == 3 || strat == 4)) {
+        if ((rc = set_done(c, 0))) return rc;
+        run_precond(c, c->d_r, c->d_tmp, true, false, false);
+    }
+    if ((rc = run_recover(c, u))) return rc;
+    if (h.status == BDDC_EBREAKDOWN) return fail(BDDC_EBREAKDOWN, "PCG breakdown (r^T z <= 0, p^T A p <= 0 or NaN)");
+    if (h.status == BDDC_ENOTCONV) return fail(BDDC_ENOTCONV, "max_it reached");
+    return 0;
+}
+
+int refresh_waw(bddc_ctx *c, double *W, double *AW, int k, std::vector<double> &waw) {
+    if (k == 0) { waw.clear(); return 0; }
+    GramArgs g{};
+    g.n = c->n_gamma; g.k = k; g.ld = c->ld; g.X = W; g.Y = AW; g.partial = c->d_partial; g.out = c->d_G;
+    g.ctl = c->d_ctl;
+    const int nb = std::max(1, std::min(256, (c->n_gamma + 1023) / 1024));
+    launch_gram(g, nb, c->stream);
+    waw.resize((size_t)k * k);
+    HIPCHK(hipMemcpyAsync(waw.data(), c->d_G, (size_t)k * k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < k; ++i)
+        for (int j = i + 1; j < k; ++j) waw[i * k + j] = waw[j * k + i] = 0.5 * (waw[i * k + j] + waw[j * k + i]);
+    return 0;
+}
+
+// W_new = [W, P] Y, AW_new = [AW, AP] Y; commit only if W_new^T A W_new is SPD
+int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol) {
+    const int ldy = (ncol + 7) / 8 * 8;
+    std::vector<double> Yp((size_t)m * ldy, 0.0);
+    for (int q = 0; q < m; ++q)
+        for (int j = 0; j < ncol; ++j) Yp[(size_t)q * ldy + j] = Y[(size_t)q * ncol + j];
+    HIPCHK(hipMemcpyAsync(c->d_Y, Yp.data(), Yp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    const int l = m - c->k;
+    GemmArgs g{};
+    g.n = c->n_gamma; g.ld = c->ld; g.Y = c->d_Y; g.ncol = ncol; g.ldy = ldy;
+    g.V1 = c->d_W; g.k1 = c->k; g.V2 = c->d_P; g.k2 = l; g.out = c->d_Wn;
+    launch_recycle_gemm(g, c->stream);
+    g.V1 = c->d_AW; g.V2 = c->d_AP; g.out = c->d_AWn;
+    launch_recycle_gemm(g, c->stream);
+    std::vector<double> waw;
+    int rc = refresh_waw(c, c->d_Wn, c->d_AWn, ncol, waw);
+    if (rc) return rc;
+    std::vector<double> L = waw;
+    if (!cholesky(L, ncol)) return fail(BDDC_ESINGULAR, "new W^T A W is not positive definite; basis kept");
+    std::swap(c->d_W, c->d_Wn);
+    std::swap(c->d_AW, c->d_AWn);
+    c->k = ncol;
+    c->WAW = waw;
+    HIPCHK(hipMemcpyAsync(c->d_Lc, L.data(), L.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int do_recycle(bddc_ctx *c) {
+    if (c->R == 0 || c->frozen || !c->have_solve) return 0;
+    c->have_solve = false;
+    if (c->last_status != 0 || c->last_restarts > 0) return 0;
+    const int strat = c->opts.recycle_strategy;
+    const int l = std::min(c->last_iters, c->save_cap);
+    const int k = c->k, m = k + l;
+    c->n_updates++;
+    if (strat == 1 || strat == 2) {
+        // B1: first R search directions; B2: sliding window of the last R
+        int ncol;
+        std::vector<int> cols;
+        if (strat == 1) {
+            if (k >= c->R) return 0;
+            for (int q = 0; q < std::min(m, c->R); ++q) cols.push_back(q);
+        } else {
+            for (int q = std::max(0, m - c->R); q < m; ++q) cols.push_back(q);
+        }
+        ncol = (int)cols.size();
+        if (ncol == 0) return 0;
+        std::vector<double> Y((size_t)m * ncol, 0.0);
+        for (int j = 0; j < ncol; ++j) Y[(size_t)cols[j] * ncol + j] = 1.0;
+        return apply_basis(c, Y, m, ncol);
+    }
+    if (m == 0) return 0;
+    // scalars of the last solve
+    std::vector<double> al(l), dd(l), rho(l + 1), mu((size_t)(l + 1) * RMAX);
+    if (l > 0) {
+        HIPCHK(hipMemcpyAsync(al.data(), c->d_ahist, l * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(dd.data(), c->d_dhist, l * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(rho.data(), c->d_rhohist, (l + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(mu.data(), c->d_muhist, (size_t)(l + 1) * RMAX * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    // F = V^T A V = blockdiag(W^T A W, diag(d)) and G = V^T A M^{-1} A V from the
+    // recurrences of Algorithm 1: M^{-1} A p_j = (z_j - z_{j+1}) / alpha_j
+    std::vector<double> F((size_t)m * m, 0.0), G((size_t)m * m, 0.0);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+            F[(size_t)i * m + j] = c->WAW[(size_t)i * k + j];
+            G[(size_t)i * m + j] = c->GWW[(size_t)i * k + j];
+        }
+    for (int j = 0; j < l; ++j) {
+        const double beta = rho[j + 1] / rho[j];
+        F[(size_t)(k + j) * m + k + j] = dd[j];
+        G[(size_t)(k + j) * m + k + j] = dd[j] * (1.0 + beta) / al[j];
+        if (j > 0) {
+            const double off = -dd[j - 1] * dd[j] / rho[j - 1];
+            G[(size_t)(k + j - 1) * m + k + j] = off;
+            G[(size_t)(k + j) * m + k + j - 1] = off;
+        }
+        for (int i = 0; i < k; ++i) {
+            double s = 0.0;
+            for (int q = 0; q < k; ++q)
+                s += c->WAW[(size_t)i * k + q] * (mu[(size_t)j * RMAX + q] - mu[(size_t)(j + 1) * RMAX + q]);
+            s /= al[j];
+            G[(size_t)i * m + k + j] = s;
+            G[(size_t)(k + j) * m + i] = s;
+        }
+    }
+    // generalized eigenproblem G y = theta F y (eq. harmonicRitz)
+    std::vector<double> lam, U;
+    jacobi_eig(F, m, lam, U);
+    const double lmax = *std::max_element(lam.begin(), lam.end());
+    std::vector<int> keep;
+    for (int i = 0; i < m; ++i)
+        if (lam[i] > 1e-12 * lmax) keep.push_back(i);
+    const int mk = (int)keep.size();
+    if (mk == 0) return 0;
+    std::vector<double> T((size_t)m * mk);
+    for (int q = 0; q < m; ++q)
+        for (int j = 0; j < mk; ++j) T[(size_t)q * mk + j] = U[(size_t)q * m + keep[j]] / std::sqrt(lam[keep[j]]);
+    std::vector<double> GT((size_t)m * mk, 0.0), H((size_t)mk * mk, 0.0);
+    for (int q = 0; q < m; ++q)
+        for (int j = 0; j < mk; ++j) {
+            double s = 0.0;
+            for (int t = 0; t < m; ++t) s += G[(size_t)q * m + t] * T[(size_t)t * mk + j];
+            GT[(size_t)q * mk + j] = s;
+        }
+    for (int i = 0; i < mk; ++i)
+        for (int j = 0; j < mk; ++j) {
+            double s = 0.0;
+            for (int q = 0; q < m; ++q) s += T[(size_t)q * mk + i] * GT[(size_t)q * mk + j];
+            H[(size_t)i * mk + j] = s;
+        }
+    for (int i = 0; i < mk; ++i)
+        for (int j = i + 1; j < mk; ++j) H[(size_t)i * mk + j] = H[(size_t)j * mk + i] = 0.5 * (H[(size_t)i * mk + j] + H[(size_t)j * mk + i]);
+    std::vector<double> th, Z;
+    jacobi_eig(H, mk, th, Z);
+    std::vector<int> ord(mk);
+    std::iota(ord.begin(), ord.end(), 0);
+    if (strat == 4) std::reverse(ord.begin(), ord.end());   // descending for B4
+    const int ncol = std::min(c->R, mk);
+    std::vector<double> Y((size_t)m * ncol, 0.0), thsel(ncol);
+    for (int j = 0; j < ncol; ++j) {
+        thsel[j] = th[ord[j]];
+        for (int q = 0; q < m; ++q) {
+            double s = 0.0;
+            for (int t = 0; t < mk; ++t) s += T[(size_t)q * mk + t] * Z[(size_t)t * mk + ord[j]];
+            Y[(size_t)q * ncol + j] = s;
+        }
+    }
+    // G_WW of the new basis: Y^T G Y
+    std::vector<double> gww((size_t)ncol * ncol, 0.0);
+    for (int i = 0; i < ncol; ++i)
+        for (int j = 0; j < ncol; ++j) {
+            double s = 0.0;
+            for (int q = 0; q < m; ++q) {
+                double t = 0.0;
+                for (int r = 0; r < m; ++r) t += G[(size_t)q * m + r] * Y[(size_t)r * ncol + j];
+                s += Y[(size_t)q * ncol + i] * t;
+            }
+            gww[(size_t)i * ncol + j] = s;
+        }
+    int rc = apply_basis(c, Y, m, ncol);
+    if (rc) return rc;
+    c->GWW = gww;
+    // freeze test (eq. harmritzstopcrit) on the sorted selected values
+    if ((int)c->theta.size() == c->R && ncol == c->R) {
+        double num = 0.0, den = 0.0;
+        for (int j = 0; j < ncol; ++j) {
+            num += (thsel[j] - c->theta[j]) * (thsel[j] - c->theta[j]);
+            den += thsel[j] * thsel[j];
+        }
+        if (std::sqrt(num) <= c->opts.ritz_freeze_tol * std::sqrt(den)) {
+            c->frozen = true;
+            c->freeze_step = c->n_updates;
+        }
+    }
+    c->theta = thsel;
+    return 0;
+}
+
+}  // namespace
+
+// ======================================================================== ABI
+extern "C" {
+
+void bddc_default_opts(bddc_opts *o) {
+    std::memset(o, 0, sizeof(*o));
+    o->constraints = BDDC_CORNERS | BDDC_FACES;
+    o->weights = 1;
+    o->local_prec = 64;
+    o->recycle_R = 0;
+    o->recycle_strategy = 4;
+    o->ritz_freeze_tol = 1e-5;
+    o->stop_rule = 0;
+    o->init_guess = 0;
+    o->max_it = 1000;
+    o->save_cap = 256;
+    o->use_graph = 0;
+}
+
+const char *bddc_last_error(void) { return g_err.c_str(); }
+
+static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, const double *coef) {
+    Structure &st = c->st;
+    std::string err;
+    int rc = build_structure(mesh, part, coef, &c->opts, st, err);
+    if (rc) return fail(rc, err);
+    hipStream_t s = c->stream;
+    c->n_sub = st.n_sub;
+    c->n_gamma = (int)st.gamma.size();
+    c->nC = (int)st.coarse.size();
+    c->n_nodes = st.n_nodes;
+    c->prec = c->opts.local_prec;
+    const int nsub = c->n_sub;
+
+    // -------------------------------------------------- level-1 metadata
+    std::vector<int32_t> nI(nsub), nB(nsub), nc(nsub), i_off(nsub + 1, 0), b_off(nsub + 1, 0), c_off(nsub + 1, 0);
+    std::vector<int64_t> k_off(nsub + 1, 0), s_off(nsub + 1, 0), n_off(nsub + 1, 0), kc_off(nsub + 1, 0),
+        m_off(nsub + 1, 0), x_off(nsub + 1, 0);
+    std::vector<int32_t> gB, nodesI, cidx;
+    int max_nt = 0, max_ntc = 0, max_sad = 0, max_nloc = 0;
+    for (int i = 0; i < nsub; ++i) {
+        const SubHost &sh = st.sub[i];
+        nI[i] = sh.nI; nB[i] = sh.nB; nc[i] = (int)sh.cidx.size();
+        if (sh.nB == 0) return fail(BDDC_EINVAL, "subdomain " + std::to_string(i) + " has no interface");
+        i_off[i + 1] = i_off[i] + sh.nI;
+        b_off[i + 1] = b_off[i] + sh.nB;
+        c_off[i + 1] = c_off[i] + nc[i];
+        k_off[i + 1] = k_off[i] + (int64_t)sh.nloc * sh.nloc;
+        s_off[i + 1] = s_off[i] + ntiles_of(sh.nB, 0) * 256;
+        n_off[i + 1] = n_off[i] + ntiles_of(sh.nB, nc[i]) * 256;
+        kc_off[i + 1] = kc_off[i] + (int64_t)nc[i] * nc[i];
+        m_off[i + 1] = m_off[i] + (int64_t)(sh.nB + nc[i]) * (sh.nB + nc[i]);
+        x_off[i + 1] = x_off[i] + (int64_t)sh.nB * nc[i];
+        gB.insert(gB.end(), sh.gB.begin(), sh.gB.end());
+        nodesI.insert(nodesI.end(), sh.nodes.begin(), sh.nodes.begin() + sh.nI);
+        cidx.insert(cidx.end(), sh.cidx.begin(), sh.cidx.end());
+        c->max_nI = std::max(c->max_nI, sh.nI);
+        c->max_nB = std::max(c->max_nB, sh.nB);
+        c->max_nc = std::max(c->max_nc, nc[i]);
+        max_nt = std::max(max_nt, (sh.nB + TILE - 1) / TILE);
+        max_ntc = std::max(max_ntc, (nc[i] + TILE - 1) / TILE);
+        max_sad = std::max(max_sad, sh.nB + nc[i]);
+        max_nloc = std::max(max_nloc, sh.nloc);
+    }
+    if ((rc = dupload(c, &c->d_nI, nI)) || (rc = dupload(c, &c->d_nB, nB)) || (rc = dupload(c, &c->d_nc, nc)) ||
+        (rc = dupload(c, &c->d_i_off, i_off)) || (rc = dupload(c, &c->d_b_off, b_off)) ||
+        (rc = dupload(c, &c->d_c_off, c_off)) || (rc = dupload(c, &c->d_k_off, k_off)) ||
+        (rc = dupload(c, &c->d_s_off, s_off)) || (rc = dupload(c, &c->d_n_off, n_off)) ||
+        (rc = dupload(c, &c->d_gB, gB)) || (rc = dupload(c, &c->d_nodesI, nodesI)) ||
+        (rc = dupload(c, &c->d_cidx, cidx)) || (rc = dupload(c, &c->d_gamma, st.gamma)))
+        return rc;
+    // interface assembly lists (owner-computes, ordered by subdomain)
+    {
+        std::vector<std::pair<int64_t, int32_t>> pr;
+        for (int i = 0; i < nsub; ++i)
+            for (int k = 0; k < nB[i]; ++k) pr.push_back({st.sub[i].gB[k], b_off[i] + k});
+        std::vector<int32_t> ptr, idx;
+        build_csr(c->n_gamma, pr, ptr, idx);
+        if ((rc = dupload(c, &c->d_asm_ptr, ptr)) || (rc = dupload(c, &c->d_asm_idx, idx))) return rc;
+        pr.clear();
+        for (int i = 0; i < nsub; ++i)
+            for (int q = 0; q < nc[i]; ++q) pr.push_back({st.sub[i].cidx[q], c_off[i] + q});
+        build_csr(c->nC, pr, ptr, idx);
+        if ((rc = dupload(c, &c->d_casm_ptr, ptr)) || (rc = dupload(c, &c->d_casm_idx, idx))) return rc;
+    }
+
+    // -------------------------------------------------- local assembly
+    std::vector<int32_t> eloc, incp, ince, incv;
+    std::vector<double> ec;
+    std::vector<int64_t> e_off(nsub + 1, 0), ip_off(nsub + 1, 0), ie_off(nsub + 1, 0);
+    for (int i = 0; i < nsub; ++i) {
+        const SubHost &sh = st.sub[i];
+        e_off[i + 1] = e_off[i] + (int64_t)sh.elem.size();
+        ip_off[i + 1] = ip_off[i] + sh.nloc + 1;
+        ie_off[i + 1] = ie_off[i] + (int64_t)sh.inc_e.size();
+        eloc.insert(eloc.end(), sh.elem_loc.begin(), sh.elem_loc.end());
+        ec.insert(ec.end(), sh.elem_c.begin(), sh.elem_c.end());
+        incp.insert(incp.end(), sh.inc_ptr.begin(), sh.inc_ptr.end());
+        ince.insert(ince.end(), sh.inc_e.begin(), sh.inc_e.end());
+        incv.insert(incv.end(), sh.inc_v.begin(), sh.inc_v.end());
+    }
+    int32_t *d_eloc, *d_incp, *d_ince, *d_incv;
+    double *d_ec;
+    if ((rc = dupload(c, &d_eloc, eloc)) || (rc = dupload(c, &d_ec, ec)) || (rc = dupload(c, &d_incp, incp)) ||
+        (rc = dupload(c, &d_ince, ince)) || (rc = dupload(c, &d_incv, incv)))
+        return rc;
+    if ((rc = dalloc(c, &c->d_K, (size_t)k_off[nsub]))) return rc;
+    if ((rc = dalloc(c, &c->d_status, 1))) return rc;
+    HIPCHK(hipMemsetAsync(c->d_status, 0, sizeof(int32_t), s));
+    {
+        std::vector<AsmDesc> ad(nsub);
+        for (int i = 0; i < nsub; ++i) {
+            ad[i].elem_loc = d_eloc + e_off[i] * 8;
+            ad[i].elem_c = d_ec + e_off[i];
+            ad[i].inc_ptr = d_incp + ip_off[i];
+            ad[i].inc_e = d_ince + ie_off[i];
+            ad[i].inc_v = d_incv + ie_off[i];
+            ad[i].nloc = st.sub[i].nloc;
+            ad[i].K = c->d_K + k_off[i];
+        }
+        AsmDesc *dd;
+        if ((rc = dupload(c, &dd, ad))) return rc;
+        launch_assemble(dd, nsub, s);
+        // interior elimination: sweep the interior pivots of every K_i
+        std::vector<SweepDesc> sd(nsub);
+        for (int i = 0; i < nsub; ++i)
+            sd[i] = SweepDesc{c->d_K + k_off[i], st.sub[i].nloc, st.sub[i].nloc, 0, nI[i], st.sub[i].nloc};
+        SweepDesc *dsd;
+        if ((rc = dupload(c, &dsd, sd))) return rc;
+        set_sweep_smem_limit((size_t)std::max({max_nloc, 1}) * 8);
+        launch_sweep(dsd, nsub, max_nloc, c->d_status, s);
+        HIPCHK(hipStreamSynchronize(s));
+        dfree(c, dd); dfree(c, dsd);
+    }
+    dfree(c, d_eloc); dfree(c, d_incp); dfree(c, d_ince); dfree(c, d_incv);
+
+    // -------------------------------------------------- constrained Neumann operators
+    std::vector<int32_t> cptr, ccol;
+    std::vector<double> cval, wB;
+    std::vector<int64_t> cp_off(nsub + 1, 0), cc_off(nsub + 1, 0);
+    for (int i = 0; i < nsub; ++i) {
+        const SubHost &sh = st.sub[i];
+        cp_off[i + 1] = cp_off[i] + (int64_t)sh.c_ptr.size();
+        cc_off[i + 1] = cc_off[i] + (int64_t)sh.c_col.size();
+        cptr.insert(cptr.end(), sh.c_ptr.begin(), sh.c_ptr.end());
+        ccol.insert(ccol.end(), sh.c_col.begin(), sh.c_col.end());
+        cval.insert(cval.end(), sh.c_val.begin(), sh.c_val.end());
+        wB.insert(wB.end(), sh.wB.begin(), sh.wB.end());
+    }
+    int32_t *d_cptr, *d_ccol;
+    double *d_cval, *d_wB, *d_M, *d_X;
+    if ((rc = dupload(c, &d_cptr, cptr)) || (rc = dupload(c, &d_ccol, ccol)) || (rc = dupload(c, &d_cval, cval)) ||
+        (rc = dupload(c, &d_wB, wB)) || (rc = dalloc(c, &d_M, (size_t)m_off[nsub])) ||
+        (rc = dalloc(c, &d_X, (size_t)x_off[nsub])))
+        return rc;
+    {
+        std::vector<SaddleDesc> sd(nsub);
+        std::vector<SweepDesc> wd(nsub);
+        for (int i = 0; i < nsub; ++i) {
+            const int nl = st.sub[i].nloc, N = nB[i] + nc[i];
+            sd[i] = SaddleDesc{c->d_K + k_off[i] + (int64_t)nI[i] * nl + nI[i], nl, nB[i], nc[i],
+                               d_cptr + cp_off[i], d_ccol + cc_off[i], d_cval + cc_off[i], d_M + m_off[i], N};
+            wd[i] = SweepDesc{d_M + m_off[i], N, N, 0, N, nB[i]};
+        }
+        SaddleDesc *dsd;
+        SweepDesc *dwd;
+        if ((rc = dupload(c, &dsd, sd)) || (rc = dupload(c, &dwd, wd))) return rc;
+        launch_build_saddle(dsd, nsub, s);
+        launch_sweep(dwd, nsub, max_sad, c->d_status, s);
+        // tiles: S_i (float64) and D N_i D with D Phi_i (local precision)
+        c->bytes_S = (size_t)s_off[nsub] * 8;
+        c->bytes_N = (size_t)n_off[nsub] * (c->prec / 8);
+        if ((rc = dalloc(c, &c->d_S, (size_t)s_off[nsub]))) return rc;
+        if ((rc = dalloc(c, (char **)&c->d_N, c->bytes_N))) return rc;
+        std::vector<PackDesc> ps(nsub), pn(nsub);
+        std::vector<PtspDesc> pt(nsub);
+        for (int i = 0; i < nsub; ++i) {
+            const int nl = st.sub[i].nloc, N = nB[i] + nc[i];
+            const double *Sblk = c->d_K + k_off[i] + (int64_t)nI[i] * nl + nI[i];
+            ps[i] = PackDesc{Sblk, nl, nB[i], 1.0, nullptr, nullptr, 0, 0, s_off[i]};
+            pn[i] = PackDesc{d_M + m_off[i], N, nB[i], -1.0, d_wB + b_off[i], d_M + m_off[i] + nB[i], N, nc[i], n_off[i]};
+            pt[i] = PtspDesc{Sblk, nl, d_M + m_off[i] + nB[i], N, -1.0, nB[i], nc[i], d_X + x_off[i], nullptr};
+        }
+        if ((rc = dalloc(c, &c->d_KC, (size_t)kc_off[nsub]))) return rc;
+        for (int i = 0; i < nsub; ++i) pt[i].out = c->d_KC + kc_off[i];
+        PackDesc *dps, *dpn;
+        PtspDesc *dpt;
+        if ((rc = dupload(c, &dps, ps)) || (rc = dupload(c, &dpn, pn)) || (rc = dupload(c, &dpt, pt))) return rc;
+        launch_pack(dps, nsub, 64, c->d_S, s);
+        launch_pack(dpn, nsub, c->prec, c->d_N, s);
+        launch_ptsp(dpt, nsub, s);
+        HIPCHK(hipStreamSynchronize(s));
+        dfree(c, dsd); dfree(c, dwd); dfree(c, dps); dfree(c, dpn); dfree(c, dpt);
+    }
+    dfree(c, d_M); dfree(c, d_X); dfree(c, d_cptr); dfree(c, d_ccol); dfree(c, d_cval); dfree(c, d_wB);
+    {
+        int32_t st_h = 0;
+        HIPCHK(hipMemcpy(&st_h, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (st_h) return fail(BDDC_ESINGULAR, "non-positive pivot in a local elimination (floating subdomain without constraints?)");
+    }
+    c->smem_S = symv_smem(64, max_nt, 0);
+    c->smem_N = symv_smem(c->prec, max_nt, max_ntc);
+    set_symv_smem_limit(std::max(c->smem_S, c->smem_N));
+
+    // -------------------------------------------------- coarse levels
+    c->three = st.three;
+    if (!c->three) {
+        const int n = c->nC;
+        std::vector<std::pair<int64_t, int32_t>> pr;
+        for (int i = 0; i < nsub; ++i)
+            for (int a = 0; a < nc[i]; ++a)
+                for (int b = 0; b < nc[i]; ++b)
+                    pr.push_back({(int64_t)st.sub[i].cidx[a] * n + st.sub[i].cidx[b], (int32_t)(kc_off[i] + a * nc[i] + b)});
+        std::vector<int32_t> ptr, idx;
+        build_csr((int64_t)n * n, pr, ptr, idx);
+        int32_t *dp, *di;
+        if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) || (rc = dalloc(c, &c->d_KCinv, (size_t)n * n)) ||
+            (rc = dalloc(c, &c->d_uC, (size_t)n)))
+            return rc;
+        launch_gather_sum((int64_t)n * n, dp, di, c->d_KC, c->d_KCinv, s);
+        std::vector<SweepDesc> sd{SweepDesc{c->d_KCinv, n, n, 0, n, n}};
+        SweepDesc *dsd;
+        if ((rc = dupload(c, &dsd, sd))) return rc;
+        if (n > 0) launch_sweep(dsd, 1, n, c->d_status, s);
+        HIPCHK(hipStreamSynchronize(s));
+        dfree(c, dp); dfree(c, di); dfree(c, dsd);
+        c->smem_prol = (size_t)(c->max_nc + 1) * 8;
+        std::vector<int32_t> cL(c_off[nsub], 0);
+        if ((rc = dupload(c, &c->d_cL, cL))) return rc;
+    } else {
+        const int nsr = st.n_sr;
+        c->nsr = nsr;
+        c->n3 = st.n3;
+        std::vector<int32_t> nL(nsr), nI2(nsr), nc3(nsr), L_off(nsr + 1, 0), I2_off(nsr + 1, 0), B2_off(nsr + 1, 0),
+            C3_off(nsr + 1, 0), Lall, g2all, c3all, pos_sr, sr_of_sub(nsub);
+        std::vector<int64_t> K2_off(nsr + 1, 0), N2_off(nsr + 1, 0), P2_off(nsr + 1, 0), M2_off(nsr + 1, 0),
+            K3_off(nsr + 1, 0);
+        std::vector<double> w2all;
+        int max_sad2 = 0;
+        for (int j = 0; j < nsr; ++j) {
+            const SubregionHost &r = st.sr[j];
+            nL[j] = (int)r.L.size(); nI2[j] = r.nI; nc3[j] = (int)r.c3.size();
+            L_off[j + 1] = L_off[j] + nL[j];
+            I2_off[j + 1] = I2_off[j] + r.nI;
+            B2_off[j + 1] = B2_off[j] + r.nB;
+            C3_off[j + 1] = C3_off[j] + nc3[j];
+            K2_off[j + 1] = K2_off[j] + (int64_t)nL[j] * nL[j];
+            N2_off[j + 1] = N2_off[j] + (int64_t)r.nB * r.nB;
+            P2_off[j + 1] = P2_off[j] + (int64_t)r.nB * nc3[j];
+            M2_off[j + 1] = M2_off[j] + (int64_t)(r.nB + nc3[j]) * (r.nB + nc3[j]);
+            K3_off[j + 1] = K3_off[j] + (int64_t)nc3[j] * nc3[j];
+            Lall.insert(Lall.end(), r.L.begin(), r.L.end());
+            g2all.insert(g2all.end(), r.g2.begin(), r.g2.end());
+            c3all.insert(c3all.end(), r.c3.begin(), r.c3.end());
+            w2all.insert(w2all.end(), r.w.begin(), r.w.end());
+            for (int k = 0; k < r.nB; ++k) pos_sr.push_back(j);
+            for (int32_t i : r.subs) sr_of_sub[i] = j;
+            c->max_nL = std::max(c->max_nL, nL[j]);
+            max_sad2 = std::max(max_sad2, r.nB + nc3[j]);
+        }
+        // cL: position of each level-1 coarse DOF of subdomain i inside L of its subregion
+        std::vector<int32_t> cL(c_off[nsub]);
+        {
+            std::vector<int32_t> pos(c->nC, -1);
+            for (int j = 0; j < nsr; ++j) {
+                const auto &L = st.sr[j].L;
+                for (size_t a = 0; a < L.size(); ++a) pos[L[a]] = (int32_t)a;
+                for (int32_t i : st.sr[j].subs)
+                    for (int q = 0; q < nc[i]; ++q) cL[c_off[i] + q] = pos[st.sub[i].cidx[q]];
+                for (size_t a = 0; a < L.size(); ++a) pos[L[a]] = -1;
+            }
+        }
+        if ((rc = dupload(c, &c->d_nL, nL)) || (rc = dupload(c, &c->d_nI2, nI2)) || (rc = dupload(c, &c->d_nc3, nc3)) ||
+            (rc = dupload(c, &c->d_L_off, L_off)) || (rc = dupload(c, &c->d_I2_off, I2_off)) ||
+            (rc = dupload(c, &c->d_B2_off, B2_off)) || (rc = dupload(c, &c->d_C3_off, C3_off)) ||
+            (rc = dupload(c, &c->d_L, Lall)) || (rc = dupload(c, &c->d_g2, g2all)) || (rc = dupload(c, &c->d_c3, c3all)) ||
+            (rc = dupload(c, &c->d_pos_sr, pos_sr)) || (rc = dupload(c, &c->d_sr_of_sub, sr_of_sub)) ||
+            (rc = dupload(c, &c->d_K2_off, K2_off)) || (rc = dupload(c, &c->d_N2_off, N2_off)) ||
+            (rc = dupload(c, &c->d_P2_off, P2_off)) || (rc = dupload(c, &c->d_cL, cL)))
+            return rc;
+        // level-2 interface assembly lists and level-3 lists
+        {
+            std::vector<std::pair<int64_t, int32_t>> pr;
+            for (int j = 0; j < nsr; ++j)
+                for (int k = 0; k < st.sr[j].nB; ++k) pr.push_back({st.sr[j].g2[k], B2_off[j] + k});
+            std::vector<int32_t> ptr, idx;
+            build_csr((int64_t)st.gamma2.size(), pr, ptr, idx);
+            if ((rc = dupload(c, &c->d_asm2_ptr, ptr)) || (rc = dupload(c, &c->d_asm2_idx, idx))) return rc;
+            pr.clear();
+            for (int j = 0; j < nsr; ++j)
+                for (int q = 0; q < nc3[j]; ++q) pr.push_back({st.sr[j].c3[q], C3_off[j] + q});
+            build_csr(c->n3, pr, ptr, idx);
+            if ((rc = dupload(c, &c->d_asm3_ptr, ptr)) || (rc = dupload(c, &c->d_asm3_idx, idx))) return rc;
+        }
+        // K2_j = sum over member subdomains of K_Ci (subdomains as elements)
+        {
+            std::vector<std::pair<int64_t, int32_t>> pr;
+            std::vector<int32_t> pos(c->nC, -1);
+            for (int j = 0; j < nsr; ++j) {
+                const auto &L = st.sr[j].L;
+                for (size_t a = 0; a < L.size(); ++a) pos[L[a]] = (int32_t)a;
+                for (int32_t i : st.sr[j].subs)
+                    for (int qa = 0; qa < nc[i]; ++qa)
+                        for (int qb = 0; qb < nc[i]; ++qb)
+                            pr.push_back({K2_off[j] + (int64_t)pos[st.sub[i].cidx[qa]] * nL[j] + pos[st.sub[i].cidx[qb]],
+                                          (int32_t)(kc_off[i] + qa * nc[i] + qb)});
+                for (size_t a = 0; a < L.size(); ++a) pos[L[a]] = -1;
+            }
+            std::vector<int32_t> ptr, idx;
+            build_csr(K2_off[nsr], pr, ptr, idx);
+            int32_t *dp, *di;
+            if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) || (rc = dalloc(c, &c->d_K2, (size_t)K2_off[nsr])))
+                return rc;
+            launch_gather_sum(K2_off[nsr], dp, di, c->d_KC, c->d_K2, s);
+            HIPCHK(hipStreamSynchronize(s));
+            dfree(c, dp); dfree(c, di);
+        }
+        // sweep the level-2 interior pivots, then the level-2 saddle problems
+        std::vector<int32_t> cptr2, ccol2;
+        std::vector<double> cval2;
+        std::vector<int64_t> cp2(nsr + 1, 0), cc2(nsr + 1, 0);
+        for (int j = 0; j < nsr; ++j) {
+            const SubregionHost &r = st.sr[j];
+            cp2[j + 1] = cp2[j] + (int64_t)r.c_ptr.size();
+            cc2[j + 1] = cc2[j] + (int64_t)r.c_col.size();
+            cptr2.insert(cptr2.end(), r.c_ptr.begin(), r.c_ptr.end());
+            ccol2.insert(ccol2.end(), r.c_col.begin(), r.c_col.end());
+            cval2.insert(cval2.end(), r.c_val.begin(), r.c_val.end());
+        }
+        int32_t *d_cptr2, *d_ccol2;
+        double *d_cval2, *d_w2, *d_M2, *d_X2, *d_K3loc;
+        if ((rc = dupload(c, &d_cptr2, cptr2)) || (rc = dupload(c, &d_ccol2, ccol2)) || (rc = dupload(c, &d_cval2, cval2)) ||
+            (rc = dupload(c, &d_w2, w2all)) || (rc = dalloc(c, &d_M2, (size_t)M2_off[nsr])) ||
+            (rc = dalloc(c, &d_X2, (size_t)P2_off[nsr])) || (rc = dalloc(c, &d_K3loc, (size_t)K3_off[nsr])) ||
+            (rc = dalloc(c, &c->d_N2, (size_t)N2_off[nsr])) || (rc = dalloc(c, &c->d_Phi2, (size_t)P2_off[nsr])))
+            return rc;
+        {
+            std::vector<SweepDesc> s1(nsr), s2(nsr);
+            std::vector<SaddleDesc> sd(nsr);
+            std::vector<DenseCopyDesc> cn(nsr), cp(nsr);
+            std::vector<PtspDesc> pt(nsr);
+            for (int j = 0; j < nsr; ++j) {
+                const int n = nL[j], i2 = nI2[j], b = n - i2, N = b + nc3[j];
+                double *Kj = c->d_K2 + K2_off[j];
+                const double *Sj = Kj + (int64_t)i2 * n + i2;
+                s1[j] = SweepDesc{Kj, n, n, 0, i2, n};
+                sd[j] = SaddleDesc{Sj, n, b, nc3[j], d_cptr2 + cp2[j], d_ccol2 + cc2[j], d_cval2 + cc2[j], d_M2 + M2_off[j], N};
+                s2[j] = SweepDesc{d_M2 + M2_off[j], N, N, 0, N, b};
+                cn[j] = DenseCopyDesc{d_M2 + M2_off[j], N, b, b, -1.0, d_w2 + B2_off[j], d_w2 + B2_off[j], c->d_N2 + N2_off[j], b};
+                cp[j] = DenseCopyDesc{d_M2 + M2_off[j] + b, N, b, nc3[j], -1.0, d_w2 + B2_off[j], nullptr, c->d_Phi2 + P2_off[j], nc3[j]};
+                pt[j] = PtspDesc{Sj, n, d_M2 + M2_off[j] + b, N, -1.0, b, nc3[j], d_X2 + P2_off[j], d_K3loc + K3_off[j]};
+            }
+            SweepDesc *ds1, *ds2;
+            SaddleDesc *dsd;
+            DenseCopyDesc *dcn, *dcp;
+            PtspDesc *dpt;
+            if ((rc = dupload(c, &ds1, s1)) || (rc = dupload(c, &ds2, s2)) || (rc = dupload(c, &dsd, sd)) ||
+                (rc = dupload(c, &dcn, cn)) || (rc = dupload(c, &dcp, cp)) || (rc = dupload(c, &dpt, pt)))
+                return rc;
+            launch_sweep(ds1, nsr, c->max_nL, c->d_status, s);
+            launch_build_saddle(dsd, nsr, s);
+            launch_sweep(ds2, nsr, max_sad2, c->d_status, s);
+            launch_dense_copy(dcn, nsr, s);
+            launch_dense_copy(dcp, nsr, s);
+            launch_ptsp(dpt, nsr, s);
+            HIPCHK(hipStreamSynchronize(s));
+            dfree(c, ds1); dfree(c, ds2); dfree(c, dsd); dfree(c, dcn); dfree(c, dcp); dfree(c, dpt);
+        }
+        // level 3: assemble and invert (dense)
+        {
+            const int n = c->n3;
+            std::vector<std::pair<int64_t, int32_t>> pr;
+            for (int j = 0; j < nsr; ++j)
+                for (int a = 0; a < nc3[j]; ++a)
+                    for (int b = 0; b < nc3[j]; ++b)
+                        pr.push_back({(int64_t)st.sr[j].c3[a] * n + st.sr[j].c3[b], (int32_t)(K3_off[j] + a * nc3[j] + b)});
+            std::vector<int32_t> ptr, idx;
+            build_csr((int64_t)n * n, pr, ptr, idx);
+            int32_t *dp, *di;
+            if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) || (rc = dalloc(c, &c->d_K3inv, (size_t)n * n)))
+                return rc;
+            launch_gather_sum((int64_t)n * n, dp, di, d_K3loc, c->d_K3inv, s);
+            std::vector<SweepDesc> sd{SweepDesc{c->d_K3inv, n, n, 0, n, n}};
+            SweepDesc *dsd;
+            if ((rc = dupload(c, &dsd, sd))) return rc;
+            if (n > 0) launch_sweep(dsd, 1, n, c->d_status, s);
+            HIPCHK(hipStreamSynchronize(s));
+            dfree(c, dp); dfree(c, di); dfree(c, dsd);
+        }
+        dfree(c, d_cptr2); dfree(c, d_ccol2); dfree(c, d_cval2); dfree(c, d_w2); dfree(c, d_M2); dfree(c, d_X2);
+        dfree(c, d_K3loc);
+        if ((rc = dalloc(c, &c->d_vI2, (size_t)I2_off[nsr])) || (rc = dalloc(c, &c->d_t2, (size_t)B2_off[nsr])) ||
+            (rc = dalloc(c, &c->d_rB2, (size_t)B2_off[nsr])) || (rc = dalloc(c, &c->d_u2, (size_t)B2_off[nsr])) ||
+            (rc = dalloc(c, &c->d_c3loc, (size_t)C3_off[nsr])) || (rc = dalloc(c, &c->d_u3, (size_t)std::max(1, c->n3))))
+            return rc;
+        c->smem_prol = (size_t)(c->max_nc + c->max_nL + 1) * 8;
+    }
+    {
+        int32_t st_h = 0;
+        HIPCHK(hipMemcpy(&st_h, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (st_h) return fail(BDDC_ESINGULAR, "non-positive pivot in a coarse-level elimination");
+    }
+
+    // -------------------------------------------------- iteration storage
+    const int ng = c->n_gamma;
+    c->ld = ng;
+    c->R = c->opts.recycle_R;
+    c->save_cap = c->R > 0 ? c->opts.save_cap : 0;
+    c->hist_cap = c->opts.max_it + 2;
+    const size_t nblk = (size_t)(ng + 255) / 256;
+    const size_t npart = std::max({nblk * (RMAX + 1), (size_t)nsub + 1, (size_t)256 * RMAX * RMAX});
+    if ((rc = dalloc(c, &c->d_b, ng)) || (rc = dalloc(c, &c->d_x, ng)) || (rc = dalloc(c, &c->d_r, ng)) ||
+        (rc = dalloc(c, &c->d_z, ng)) || (rc = dalloc(c, &c->d_p, ng)) || (rc = dalloc(c, &c->d_tmp, ng)) ||
+        (rc = dalloc(c, &c->d_locq, (size_t)b_off[nsub])) || (rc = dalloc(c, &c->d_locu, (size_t)b_off[nsub])) ||
+        (rc = dalloc(c, &c->d_locc, (size_t)std::max<int64_t>(1, c_off[nsub]))) ||
+        (rc = dalloc(c, &c->d_yI, (size_t)std::max<int64_t>(1, i_off[nsub]))) || (rc = dalloc(c, &c->d_partial, npart)) ||
+        (rc = dalloc(c, &c->d_ctl, 1)) || (rc = dalloc(c, &c->d_ahist, c->hist_cap)) ||
+        (rc = dalloc(c, &c->d_dhist, c->hist_cap)) || (rc = dalloc(c, &c->d_rhohist, c->hist_cap)) ||
+        (rc = dalloc(c, &c->d_bhist, c->hist_cap)) || (rc = dalloc(c, &c->d_reshist, c->hist_cap)) ||
+        (rc = dalloc(c, &c->d_muhist, (size_t)c->hist_cap * RMAX)) || (rc = dalloc(c, &c->d_Lc, RMAX * RMAX)) ||
+        (rc = dalloc(c, &c->d_G, RMAX * RMAX)))
+        return rc;
+    HIPCHK(hipMemsetAsync(c->d_x, 0, ng * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(c->d_p, 0, ng * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(c->d_ctl, 0, sizeof(Ctl), s));
+    HIPCHK(hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
+    if (c->R > 0) {
+        const size_t cols = (size_t)c->R;
+        const int ymax = (c->R + c->save_cap) * ((c->R + 7) / 8 * 8);
+        if ((rc = dalloc(c, &c->d_W, cols * ng)) || (rc = dalloc(c, &c->d_AW, cols * ng)) ||
+            (rc = dalloc(c, &c->d_Wn, cols * ng)) || (rc = dalloc(c, &c->d_AWn, cols * ng)) ||
+            (rc = dalloc(c, &c->d_P, (size_t)c->save_cap * ng)) || (rc = dalloc(c, &c->d_AP, (size_t)c->save_cap * ng)) ||
+            (rc = dalloc(c, &c->d_Y, (size_t)ymax)))
+            return rc;
+    }
+    // element data for the adjoint gradient
+    {
+        std::vector<double> ch(st.n_elem, 0.0);
+        std::vector<uint8_t> keep(st.n_elem, 1);
+        for (int64_t e = 0; e < st.n_elem; ++e) {
+            ch[e] = coef[e] * st.h;
+            if (mesh->elem_keep) keep[e] = mesh->elem_keep[e] ? 1 : 0;
+        }
+        if ((rc = dupload(c, &c->d_coefh, ch)) || (rc = dupload(c, &c->d_keep, keep)) ||
+            (rc = dupload(c, &c->d_free, st.free_node)))
+            return rc;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return 0;
+}
+
+int bddc_setup(const bddc_mesh *mesh, const bddc_partition *part, const double *coef, const bddc_opts *opts,
+               void *hip_stream, bddc_ctx **out) {
+    if (!mesh || !part || !coef || !out) return fail(BDDC_EINVAL, "null argument");
+    *out = nullptr;
+    bddc_ctx *c = new bddc_ctx();
+    c->stream = (hipStream_t)hip_stream;
+    if (opts) c->opts = *opts;
+    else bddc_default_opts(&c->opts);
+    const bddc_opts &o = c->opts;
+    if (o.local_prec != 64 && o.local_prec != 32 && o.local_prec != 16) { delete c; return fail(BDDC_EINVAL, "local_prec must be 64, 32 or 16"); }
+    if (o.recycle_R < 0 || o.recycle_R > RMAX) { delete c; return fail(BDDC_EINVAL, "recycle_R out of range [0, 64]"); }
+    if (o.recycle_strategy < 1 || o.recycle_strategy > 4) { delete c; return fail(BDDC_EINVAL, "recycle_strategy must be 1..4"); }
+    if (o.max_it <= 0 || o.save_cap < 0 || o.save_cap > 4096) { delete c; return fail(BDDC_EINVAL, "bad max_it or save_cap"); }
+    if (!(o.constraints & (BDDC_CORNERS | BDDC_FACES | BDDC_EDGES))) { delete c; return fail(BDDC_EINVAL, "no constraints"); }
+    int rc = setup_impl(c, mesh, part, coef);
+    if (rc) {
+        std::string keep = g_err;
+        bddc_destroy(c);
+        g_err = keep;
+        return rc;
+    }
+    *out = c;
+    return 0;
+}
+
+int dpcg_solve(bddc_ctx *c, const double *rhs_seq, int32_t n_rhs, double rtol, double *x_seq, int32_t *iters,
+               double *true_relres) {
+    if (!c || (!rhs_seq && n_rhs > 0) || (!x_seq && n_rhs > 0) || n_rhs < 0 || !(rtol > 0))
+        return fail(BDDC_EINVAL, "bad dpcg_solve argument");
+    for (int k = 0; k < n_rhs; ++k) {
+        int it = 0;
+        double rr = 0.0;
+        int rc = solve_one(c, rhs_seq + (size_t)k * c->n_nodes, x_seq + (size_t)k * c->n_nodes, rtol, true, &it, &rr);
+        if (iters) iters[k] = it;
+        if (true_relres) true_relres[k] = rr;
+        if (rc) { if (c->timing) flush_timing(c); return rc; }
+        {
+            TScope ts(c, TK_REC);
+            rc = do_recycle(c);
+        }
+        if (rc) { if (c->timing) flush_timing(c); return rc; }
+    }
+    if (c->timing) {
+        hipStreamSynchronize(c->stream);
+        flush_timing(c);
+    }
+    return 0;
+}
+
+int recycle_update(bddc_ctx *c) {
+    if (!c) return fail(BDDC_EINVAL, "null context");
+    return do_recycle(c);
+}
+
+int bddc_reset_recycle(bddc_ctx *c) {
+    if (!c) return fail(BDDC_EINVAL, "null context");
+    c->k = 0;
+    c->WAW.clear();
+    c->GWW.clear();
+    c->theta.clear();
+    c->frozen = false;
+    c->freeze_step = -1;
+    c->n_updates = 0;
+    c->have_solve = false;
+    HIPCHK(hipMemsetAsync(c->d_x, 0, c->n_gamma * sizeof(double), c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int bddc_adjoint_grad(bddc_ctx *c, const double *dLdu_seq, int32_t n_rhs, const double *u_seq, double rtol,
+                      double *grad_logcoef, double *grad_rhs_seq) {
+    if (!c || !dLdu_seq || !u_seq || !grad_logcoef || !grad_rhs_seq || n_rhs < 0 || !(rtol > 0))
+        return fail(BDDC_EINVAL, "bad bddc_adjoint_grad argument");
+    // the forward sequence keeps its own previous solution
+    double *xsave = nullptr;
+    int rc = dalloc(c, &xsave, c->n_gamma);
+    if (rc) return rc;
+    launch_copy(c->n_gamma, c->d_x, xsave, c->stream);
+    HIPCHK(hipMemsetAsync(c->d_x, 0, c->n_gamma * sizeof(double), c->stream));
+    for (int k = 0; k < n_rhs && rc == 0; ++k)
+        rc = solve_one(c, dLdu_seq + (size_t)k * c->n_nodes, grad_rhs_seq + (size_t)k * c->n_nodes, rtol, false, nullptr, nullptr);
+    c->have_solve = false;
+    launch_copy(c->n_gamma, xsave, c->d_x, c->stream);
+    if (rc == 0) {
+        GradArgs g{};
+        g.n_elem = c->st.n_elem; g.n_nodes = c->n_nodes; g.nx = c->st.nx; g.ny = c->st.ny; g.nz = c->st.nz;
+        g.n_rhs = n_rhs; g.keep = c->d_keep; g.free_node = c->d_free; g.coefh = c->d_coefh;
+        g.lam = grad_rhs_seq; g.u = u_seq; g.grad = grad_logcoef;
+        launch_elem_grad(g, c->stream);
+    }
+    hipStreamSynchronize(c->stream);
+    dfree(c, xsave);
+    return rc;
+}
+
+int bddc_apply_schur(bddc_ctx *c, const double *p, double *q) {
+    if (!c || !p || !q) return fail(BDDC_EINVAL, "null argument");
+    run_schur(c, p, 0);
+    launch_gather_sum(c->n_gamma, c->d_asm_ptr, c->d_asm_idx, c->d_locq, q, c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int bddc_apply_precond(bddc_ctx *c, const double *r, double *z) {
+    if (!c || !r || !z) return fail(BDDC_EINVAL, "null argument");
+    int rc = set_done(c, 0);
+    if (rc) return rc;
+    run_precond(c, r, z, false, true, false);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int bddc_condense(bddc_ctx *c, const double *F, double *b) {
+    if (!c || !F || !b) return fail(BDDC_EINVAL, "null argument");
+    run_condense(c, F);
+    launch_copy(c->n_gamma, c->d_b, b, c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int bddc_info(const bddc_ctx *c, int64_t *info) {
+    if (!c || !info) return fail(BDDC_EINVAL, "null argument");
+    info[0] = c->n_nodes;
+    info[1] = c->n_gamma;
+    info[2] = c->n_sub;
+    info[3] = c->nC;
+    info[4] = c->st.n_corner;
+    info[5] = c->st.n_face;
+    info[6] = c->st.n_edge;
+    info[7] = c->three ? (int64_t)c->st.gamma2.size() : 0;
+    info[8] = c->three ? (int64_t)(c->nC - c->st.gamma2.size()) : 0;
+    info[9] = c->three ? c->n3 : c->nC;
+    info[10] = c->k;
+    info[11] = c->frozen ? 1 : 0;
+    info[12] = (int64_t)c->bytes_S;
+    info[13] = (int64_t)c->bytes_N;
+    info[14] = c->max_nB;
+    info[15] = (int64_t)c->dev_bytes;
+    return 0;
+}
+
+int bddc_interface_nodes(const bddc_ctx *c, int64_t *out) {
+    if (!c || !out) return fail(BDDC_EINVAL, "null argument");
+    for (int g = 0; g < c->n_gamma; ++g) out[g] = c->st.gamma[g];
+    return 0;
+}
+
+int bddc_enable_timing(bddc_ctx *c, int32_t enable) {
+    if (!c) return fail(BDDC_EINVAL, "null context");
+    c->timing = enable != 0;
+    for (int k = 0; k < TK_N; ++k) c->t_ms[k] = c->t_cnt[k] = 0;
+    return 0;
+}
+
+int bddc_stats(const bddc_ctx *c, double *out, int32_t n) {
+    if (!c || !out) return fail(BDDC_EINVAL, "null argument");
+    for (int k = 0; k < n && k < TK_N; ++k) {
+        out[3 * k] = c->t_ms[k];
+        out[3 * k + 1] = c->t_cnt[k];
+        out[3 * k + 2] = c->t_bytes[k];
+    }
+    return 0;
+}
+
+int bddc_ritz_values(const bddc_ctx *c, double *theta, int32_t cap, int32_t *count) {
+    if (!c || !count) return fail(BDDC_EINVAL, "null argument");
+    *count = (int32_t)c->theta.size();
+    for (int i = 0; i < *count && i < cap && theta; ++i) theta[i] = c->theta[i];
+    return 0;
+}
+
+void bddc_destroy(bddc_ctx *c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    for (void *p : c->allocs) hipFree(p);
+    c->allocs.clear();
+    if (c->h_ctl) hipHostFree(c->h_ctl);
+    for (auto &p : c->pending) { hipEventDestroy(p.second.first); hipEventDestroy(p.second.second); }
+    for (auto e : c->ev_pool) hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Internal declarations of the BDDC / deflated-PCG library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bddc.h"
+
+namespace bddc {
+
+constexpr int TILE = 16;          // symmetric operators are stored as 16x16 tiles
+constexpr int RMAX = 64;          // largest deflation basis supported
+constexpr int NPART_MAX = 4096;   // largest grid of a reduction kernel
+
+// ---------------------------------------------------------------------------
+// host-side structure built from mesh + partition (partition.cpp)
+// ---------------------------------------------------------------------------
+struct CoarseDof {
+    int kind;                      // 0 corner, 1 face, 2 edge
+    std::vector<int64_t> nodes;    // free nodes (sorted)
+    std::vector<int32_t> subs;     // subdomains sharing it (sorted)
+};
+
+struct SubHost {
+    int nI = 0, nB = 0, nloc = 0;
+    std::vector<int32_t> nodes;     // local free nodes: interior (sorted) then interface (sorted)
+    std::vector<int32_t> gB;        // interface local k -> global interface index
+    std::vector<int32_t> elem;      // element ids
+    std::vector<int32_t> elem_loc;  // 8 local indices per element (-1: not a free node)
+    std::vector<double> elem_c;     // coefficient * h per element
+    std::vector<int32_t> inc_ptr, inc_e, inc_v;  // local node -> (element slot, vertex)
+    std::vector<double> wB;         // interface weights D_i
+    std::vector<int32_t> cidx;      // global coarse DOFs of this subdomain (ascending)
+    std::vector<int32_t> c_ptr, c_col;  // constraint rows over interface-local indices
+    std::vector<double> c_val;
+};
+
+struct SubregionHost {
+    std::vector<int32_t> subs;      // member subdomains
+    std::vector<int32_t> L;         // level-1 coarse DOFs: interior then interface
+    int nI = 0, nB = 0;
+    std::vector<int32_t> g2;        // interface local -> level-2 interface index
+    std::vector<double> w;          // card weights on the interface
+    std::vector<int32_t> c3;        // level-3 DOFs (ascending)
+    std::vector<int32_t> c_ptr, c_col;
+    std::vector<double> c_val;
+};
+
+struct Structure {
+    int nx = 0, ny = 0, nz = 0;
+    double h = 0;
+    int64_t n_nodes = 0, n_elem = 0;
+    std::vector<uint8_t> free_node;
+    std::vector<int32_t> gamma;        // interface node ids (ascending)
+    int n_sub = 0;
+    std::vector<SubHost> sub;
+    std::vector<CoarseDof> coarse;
+    int n_corner = 0, n_face = 0, n_edge = 0;
+    // level 2 (three-level BDDC)
+    bool three = false;
+    int n_sr = 0;
+    std::vector<SubregionHost> sr;
+    std::vector<int32_t> gamma2;       // level-1 coarse ids on the level-2 interface
+    std::vector<std::vector<int32_t>> dof3_members;  // level-3 DOF -> level-1 coarse ids
+    std::vector<std::vector<int32_t>> dof3_subs;     // level-3 DOF -> subregions
+    int n3 = 0, n3_corner = 0, n3_face = 0;
+};
+
+int build_structure(const bddc_mesh *m, const bddc_partition *p, const double *coef,
+                    const bddc_opts *o, Structure &st, std::string &err);
+
+// host dense helpers (hostla.cpp)
+bool cholesky(std::vector<double> &a, int n);                       // in place, lower
+void chol_solve(const std::vector<double> &l, int n, double *x);
+void jacobi_eig(std::vector<double> a, int n, std::vector<double> &w, std::vector<double> &v);
+
+// ---------------------------------------------------------------------------
+// device-side descriptors
+// ---------------------------------------------------------------------------
+struct SweepDesc {
+    double *A;     // row-major symmetric matrix
+    int n, ld;
+    int p0, p1;    // pivots [p0, p1) are swept
+    int pos_end;   // pivots < pos_end must be > 0, others < 0
+};
+
+struct SaddleDesc {
+    const double *S; int ldS;      // nB x nB block
+    int nB, nc;
+    const int32_t *cptr, *ccol; const double *cval;  // constraint CSR (nc rows)
+    double *M; int ldM;            // (nB+nc)^2 output
+};
+
+struct PackDesc {
+    const double *src; int ld;     // n x n symmetric block
+    int n;
+    double sign;
+    const double *D;               // nullable row/col scaling
+    const double *phi; int ldphi;  // nullable n x nc block (scaled by D rows)
+    int nc;
+    int64_t dst;                   // element offset of the first tile
+};
+
+struct PtspDesc {                  // K_C = Phi^T S Phi
+    const double *S; int ldS;
+    const double *Phi; int ldPhi;  // Phi stored in rows of a swept saddle matrix
+    double phisign;
+    int n, nc;
+    double *X;                     // scratch n x nc
+    double *out;                   // nc x nc
+};
+
+struct DenseCopyDesc {             // out[r][c] = sign * D[r] * src[r][c] (* D[c] when sym)
+    const double *src; int ld;
+    int rows, cols;
+    double sign;
+    const double *Drow, *Dcol;
+    double *dst; int ldd;
+};
+
+// reduction/control block living in device memory
+struct Ctl {
+    double rho, pAp, alpha, beta;
+    double rr, bb, r0r0, true_rr;
+    double denom2;          // squared denominator of the stopping test
+    double rtol2;
+    int done, iter, status, restarts;
+    int j;                  // index of the current direction
+    int k;                  // deflation columns in use
+    int record;             // store P / AP / scalar histories
+    int pad;
+    double mu[RMAX];        // current mu (or gamma) vector
+    unsigned int cnt[16];   // last-block counters
+};
+
+// counters (index into Ctl::cnt)
+enum { CNT_SYMV = 0, CNT_UPD, CNT_ZASM, CNT_COND, CNT_RES, CNT_DEFL, CNT_TRUE, CNT_GRAM, CNT_PREC };
+
+}  // namespace bddc
