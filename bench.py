@@ -1,0 +1,160 @@
+#!/usr/bin/env python
+"""Throughput of the deflated-PCG / three-level BDDC sequence solve on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (synthetic, seeded): Q1 Poisson on the unit cube, 64^3 elements
+(274,625 nodes), Dirichlet u = 0 on x = 1, unit coefficient, 8^3 = 512 cube
+subdomains of 8^3 elements, three-level BDDC (subregions of 2x2x2
+subdomains, corners + face averages, diag weights), deflated PCG with a
+20-vector basis recycled by B4 harmonic Ritz vectors, previous-solution
+initial guess, ||r||/||b|| < 1e-8, a 50-step drifting-Gaussian right-hand-side
+sequence.  One step = one 50-RHS sequence from an empty basis (setup
+excluded); value = right-hand sides solved per second in float64.  The same
+line reports the mixed form (float32 local Neumann operators) on the same
+sequence, the roofline of the dominant kernel and the oracle on the host CPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h", "internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2412_17543_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def its_fmt(its):
+    return "%d-%d(%.1f)" % (min(its), max(its), sum(its) / len(its))
+
+
+def run_form(torch, Solver, s, F, rtol, steps, warmup, local_prec, timing):
+    t0 = time.perf_counter()
+    g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"],
+               R=s["R"], local_prec=local_prec)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        g.reset_recycle()
+        g.solve_sequence(F, rtol)
+    torch.cuda.synchronize()
+    if timing:
+        g.enable_timing(True, ("schur", "precond_local"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.reset_recycle()
+        U, its, rr = g.solve_sequence(F, rtol)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = g.stats() if timing else None
+    info = g.info()
+    return dict(g=g, U=U, its=its, rr=rr, elapsed=el, setup_s=setup_s, stats=st, info=info)
+
+
+def cpu_baseline(s, F_np, n_sample):
+    from threadpoolctl import threadpool_limits
+
+    from oracle.sequence import OracleSolver
+    with threadpool_limits(1):
+        o = OracleSolver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"], R=s["R"])
+        t0 = time.perf_counter()
+        for k in range(n_sample):
+            o.solve(F_np[k], 1e-8)
+        el = time.perf_counter() - t0
+    return dict(value=n_sample / el, unit="solves/s", cores=1, kind="oracle",
+                sample="first %d right-hand sides of the same 64^3 sequence (oracle setup excluded, "
+                       "as on the GPU), float64 NumPy/SciPy, one thread" % n_sample)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures the single-GPU path only (one process, one MI355X); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workload
+    from paper_2412_17543_amd.solver import Solver
+
+    s = workload.workload("c64")
+    F_np = workload.rhs_sequence(s["nx"], s["n_rhs"])
+    F = torch.tensor(F_np, device="cuda")       # inputs resident in HBM before timing
+    torch.cuda.synchronize()
+    n_rhs = F.shape[0]
+
+    f64 = run_form(torch, Solver, s, F, args.rtol, args.steps, args.warmup, 64, True)
+    value = n_rhs * args.steps / f64["elapsed"]
+    st = f64["stats"]
+    dom = max(("schur", "precond_local"), key=lambda k: st[k]["ms"])
+    avg_ms = st[dom]["ms"] / max(st[dom]["count"], 1)
+    achieved = st[dom]["bytes"] / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "traffic_c64.json")
+    if os.path.exists(tf):
+        t = json.load(open(tf))
+        if t.get("kernel_hash") == kernel_hash() and dom in t.get("kernels", {}):
+            traffic = t["kernels"][dom]["bytes_per_launch"]
+    line = {
+        "metric": "solves/s to FP64 rtol 1e-8 + HBM GB/s, mixed vs FP64 BDDC-DPCG, 1 GPU",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * f64["elapsed"] / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Q1 Poisson 64^3 elements (274,625 nodes), 512 subdomains of 8^3, "
+                               "three-level BDDC (64 subregions), deflated PCG B4 R=20, 50 drifting-Gaussian "
+                               "right-hand sides, rtol 1e-8",
+                   "n_rhs": n_rhs, "n_gamma": f64["info"]["n_gamma"], "rtol": args.rtol},
+        "iters": its_fmt(f64["its"].tolist()),
+        "max_true_relres": float(f64["rr"].max()),
+        "s_per_sequence": round(f64["elapsed"] / args.steps, 4),
+        "setup_s": round(f64["setup_s"], 3),
+        "roofline": {"bound": "hbm", "kernel": "k_symv<double> (" + ("Schur S_i" if dom == "schur" else "Neumann N_i") + ")",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": st[dom]["bytes"]},
+        "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in st.items() if v["count"]},
+    }
+    if not args.no_mixed:
+        mx = run_form(torch, Solver, s, F, args.rtol, args.steps, args.warmup, 32, False)
+        ud = f64["U"]
+        err = max(float(((mx["U"][k] - ud[k]).abs().max() / ud[k].abs().max()).item()) for k in range(n_rhs))
+        mv = n_rhs * args.steps / mx["elapsed"]
+        line["mixed_fp32"] = {"value": round(mv, 3), "unit": "solves/s", "iters": its_fmt(mx["its"].tolist()),
+                              "max_true_relres": float(mx["rr"].max()), "max_rel_diff_vs_fp64": err,
+                              "speedup_vs_fp64": round(mv / value, 3)}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(s, F_np, args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -193,8 +193,11 @@ int bddc_interface_nodes(const bddc_ctx *ctx, int64_t *out);
 
 /*
  * bddc_stats -- per-kernel device time accumulated with HIP events while
- * enabled (bddc_enable_timing).  out (host float64[3*n]) receives, for kernel
- * class k: total milliseconds, launch count, algorithmic bytes per launch.
+ * enabled (bddc_enable_timing: 0 off, 1 every class, otherwise a bit mask of
+ * the classes to time, bit k = class k).  out (host float64[3*n]) receives,
+ * for kernel class k: total milliseconds, launch count, algorithmic bytes per
+ * launch (packed upper triangle of the symmetric operators + coarse bases +
+ * gathered input, its index and the output).
  * Classes: 0 Schur product, 1 preconditioner local product, 2 coarse levels,
  * 3 vector updates/reductions, 4 condensation/recovery, 5 recycle.
  */

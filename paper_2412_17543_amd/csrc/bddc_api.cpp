@@ -89,6 +89,7 @@ struct bddc_ctx {
     uint8_t *d_keep = nullptr, *d_free = nullptr;
     // timing
     bool timing = false;
+    int timing_mask = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::vector<hipEvent_t> ev_pool;
     double t_ms[TK_N] = {0}, t_cnt[TK_N] = {0}, t_bytes[TK_N] = {0};
@@ -155,11 +156,12 @@ struct TScope {
     bddc_ctx *c;
     int k;
     hipEvent_t a = nullptr;
-    TScope(bddc_ctx *c_, int k_) : c(c_), k(k_) {
-        if (c->timing) { a = get_event(c); hipEventRecord(a, c->stream); }
+    bool on;
+    TScope(bddc_ctx *c_, int k_) : c(c_), k(k_), on(c_->timing && ((c_->timing_mask >> k_) & 1)) {
+        if (on) { a = get_event(c); hipEventRecord(a, c->stream); }
     }
     ~TScope() {
-        if (c->timing) {
+        if (on) {
             hipEvent_t b = get_event(c);
             hipEventRecord(b, c->stream);
             c->pending.push_back({k, {a, b}});
@@ -772,6 +774,20 @@ static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *
         HIPCHK(hipMemcpy(&st_h, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost));
         if (st_h) return fail(BDDC_ESINGULAR, "non-positive pivot in a local elimination (floating subdomain without constraints?)");
     }
+    // algorithmic bytes per launch: the packed upper triangle of each symmetric
+    // operator (+ the n x nc coarse basis), the gathered input, its index and
+    // the written output
+    {
+        double bs = 0.0, bn = 0.0;
+        const double bN = c->prec / 8.0;
+        for (int i = 0; i < nsub; ++i) {
+            const double n = nB[i], m = nc[i];
+            bs += n * (n + 1) / 2 * 8 + n * (8 + 4 + 8);
+            bn += (n * (n + 1) / 2 + n * m) * bN + n * (8 + 4 + 8) + m * 8;
+        }
+        c->t_bytes[TK_SCHUR] = bs;
+        c->t_bytes[TK_PREC] = bn;
+    }
     c->smem_S = symv_smem(64, max_nt, 0);
     c->smem_N = symv_smem(c->prec, max_nt, max_ntc);
     set_symv_smem_limit(std::max(c->smem_S, c->smem_N));
@@ -1172,7 +1188,9 @@ int bddc_interface_nodes(const bddc_ctx *c, int64_t *out) {
 
 int bddc_enable_timing(bddc_ctx *c, int32_t enable) {
     if (!c) return fail(BDDC_EINVAL, "null context");
+    // enable: bit k times kernel class k (1 = all classes)
     c->timing = enable != 0;
+    c->timing_mask = enable == 1 ? 0x3f : (enable & 0x3f);
     for (int k = 0; k < TK_N; ++k) c->t_ms[k] = c->t_cnt[k] = 0;
     return 0;
 }

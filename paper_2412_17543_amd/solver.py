@@ -105,8 +105,11 @@ class Solver:
         check(self.lib.bddc_ritz_values(self.ctx, buf, 64, ctypes.byref(cnt)))
         return np.frombuffer(buf, dtype=np.float64)[: cnt.value].copy()
 
-    def enable_timing(self, on=True):
-        check(self.lib.bddc_enable_timing(self.ctx, 1 if on else 0))
+    def enable_timing(self, on=True, classes=None):
+        """Time kernel classes with HIP events (classes: iterable of STAT_KEYS)."""
+        mask = 0 if not on else (1 if classes is None else
+                                 sum(1 << self.STAT_KEYS.index(k) for k in classes) | 64)
+        check(self.lib.bddc_enable_timing(self.ctx, mask))
 
     STAT_KEYS = ("schur", "precond_local", "coarse", "vector", "condense_recover", "recycle")
 
@@ -114,7 +117,8 @@ class Solver:
         a = (ctypes.c_double * 18)()
         check(self.lib.bddc_stats(self.ctx, a, 6))
         v = np.frombuffer(a, dtype=np.float64)
-        return {k: dict(ms=v[3 * i], count=int(v[3 * i + 1])) for i, k in enumerate(self.STAT_KEYS)}
+        return {k: dict(ms=v[3 * i], count=int(v[3 * i + 1]), bytes=v[3 * i + 2])
+                for i, k in enumerate(self.STAT_KEYS)}
 
     # --------------------------------------------------------------- solving
     def _dev(self, x, shape=None) -> torch.Tensor:
