@@ -91,14 +91,16 @@ typedef struct {
     int32_t init_guess;      /* 0: previous solution (default), 1: zero                 */
     int32_t max_it;          /* per right-hand side, e.g. 1000                          */
     int32_t save_cap;        /* max search directions stored per solve for recycling   */
-    int32_t use_graph;       /* 1: capture the iteration as a hipGraph and poll the
-                                device convergence flag asynchronously                 */
+    int32_t use_graph;       /* 1 (default): the iteration is captured once as a
+                                hipGraph and replayed, the convergence flag polled
+                                asynchronously; 0: kernels launched one by one with
+                                a host check after every iteration                     */
     int32_t reserved[4];
 } bddc_opts;
 
 /* Fills *o with the defaults: corners+faces, diag weights, float64 local
  * operators, R = 0, B4, freeze 1e-5, ||r||/||b||, previous-solution guess,
- * max_it 1000, save_cap 256, no graph. */
+ * max_it 1000, save_cap 256, graph-captured iteration. */
 void bddc_default_opts(bddc_opts *o);
 
 /*
@@ -194,7 +196,9 @@ int bddc_interface_nodes(const bddc_ctx *ctx, int64_t *out);
 /*
  * bddc_stats -- per-kernel device time accumulated with HIP events while
  * enabled (bddc_enable_timing: 0 off, 1 every class, otherwise a bit mask of
- * the classes to time, bit k = class k).  out (host float64[3*n]) receives,
+ * the classes to time, bit k = class k).  While timing is enabled the
+ * iteration is launched kernel by kernel (no graph) so that every launch can
+ * be bracketed by events.  out (host float64[3*n]) receives,
  * for kernel class k: total milliseconds, launch count, algorithmic bytes per
  * launch (packed upper triangle of the symmetric operators + coarse bases +
  * gathered input, its index and the output).

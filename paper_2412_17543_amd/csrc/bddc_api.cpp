@@ -30,10 +30,28 @@ int fail(int code, const std::string &msg) {
 
 enum { TK_SCHUR = 0, TK_PREC, TK_COARSE, TK_VEC, TK_COND, TK_REC, TK_N };
 
+constexpr int GRAPH_ITERS = 2;     // iterations per captured graph
+constexpr int GRAPH_INFLIGHT = 2;  // graphs queued ahead of the convergence poll
+
+// Host view of one batch of operators and its work list.
+struct OpHost {
+    OpDev dev{};
+    int prec = 64;
+    SymvCfg cfg{4, 2};
+    size_t smem = 0;
+    int64_t n_tiles = 0;
+    double bytes = 0;               // algorithmic bytes of one product
+    std::vector<int32_t> nchunk;    // per subdomain
+    int32_t *d_items = nullptr, *d_nchunk = nullptr, *d_pb = nullptr, *d_cb = nullptr;
+    double *d_ypart = nullptr, *d_cpart = nullptr;
+    int64_t ypart_len = 0, cpart_len = 0;
+};
+
 }  // namespace
 
 struct bddc_ctx {
     hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
     bddc_opts opts{};
     Structure st;
     int prec = 64;
@@ -42,20 +60,24 @@ struct bddc_ctx {
     std::vector<void *> allocs;
     size_t dev_bytes = 0;
     size_t bytes_S = 0, bytes_N = 0;
+    int n_cu = 256;
 
     // level 1
     int32_t *d_nB = nullptr, *d_nI = nullptr, *d_b_off = nullptr, *d_i_off = nullptr, *d_nc = nullptr,
-            *d_c_off = nullptr, *d_gB = nullptr, *d_nodesI = nullptr, *d_cidx = nullptr, *d_cL = nullptr,
-            *d_gamma = nullptr;
-    int64_t *d_k_off = nullptr, *d_s_off = nullptr, *d_n_off = nullptr;
+            *d_c_off = nullptr, *d_gB = nullptr, *d_nodesI = nullptr, *d_cidx = nullptr, *d_gamma = nullptr,
+            *d_pos_sub = nullptr, *d_cpos_sub = nullptr;
+    int64_t *d_k_off = nullptr, *d_s_off = nullptr, *d_n_off = nullptr, *d_phr_off = nullptr;
     double *d_K = nullptr, *d_S = nullptr, *d_KC = nullptr;
-    void *d_N = nullptr;
+    void *d_N = nullptr, *d_phir = nullptr;
     int32_t *d_asm_ptr = nullptr, *d_asm_idx = nullptr, *d_casm_ptr = nullptr, *d_casm_idx = nullptr;
-    int max_nI = 0, max_nB = 0, max_nc = 0;
-    size_t smem_S = 0, smem_N = 0, smem_prol = 0;
+    int max_nI = 0, max_nB = 0, max_nc = 0, max_nt = 0, max_ntc = 0;
+    std::vector<int32_t> h_nB, h_nc, h_b_off, h_c_off;
+    OpHost opS, opN;
     // iteration vectors
+    int vgrid = 1;
     double *d_b = nullptr, *d_x = nullptr, *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_tmp = nullptr;
-    double *d_locq = nullptr, *d_locu = nullptr, *d_locc = nullptr, *d_yI = nullptr, *d_partial = nullptr;
+    double *d_locq = nullptr, *d_yI = nullptr;
+    double *d_rr = nullptr, *d_bbp = nullptr, *d_zp = nullptr, *d_wp = nullptr, *d_dotS = nullptr, *d_gp = nullptr;
     // coarse
     bool three = false;
     double *d_KCinv = nullptr, *d_uC = nullptr;
@@ -63,15 +85,16 @@ struct bddc_ctx {
     int32_t *d_nL = nullptr, *d_nI2 = nullptr, *d_L_off = nullptr, *d_L = nullptr, *d_I2_off = nullptr,
             *d_B2_off = nullptr, *d_g2 = nullptr, *d_asm2_ptr = nullptr, *d_asm2_idx = nullptr,
             *d_pos_sr = nullptr, *d_nc3 = nullptr, *d_C3_off = nullptr, *d_c3 = nullptr,
-            *d_sr_of_sub = nullptr, *d_asm3_ptr = nullptr, *d_asm3_idx = nullptr;
+            *d_asm3_ptr = nullptr, *d_asm3_idx = nullptr;
+    uint8_t *d_own2 = nullptr;
     int64_t *d_K2_off = nullptr, *d_N2_off = nullptr, *d_P2_off = nullptr;
     double *d_K2 = nullptr, *d_N2 = nullptr, *d_Phi2 = nullptr, *d_K3inv = nullptr, *d_vI2 = nullptr,
            *d_t2 = nullptr, *d_rB2 = nullptr, *d_u2 = nullptr, *d_c3loc = nullptr, *d_u3 = nullptr;
     // deflation / recycling
-    int R = 0, k = 0, save_cap = 0;
+    int R = 0, k = 0, save_cap = 0, kmax = 0;
     int64_t ld = 0;
     double *d_W = nullptr, *d_AW = nullptr, *d_Wn = nullptr, *d_AWn = nullptr, *d_P = nullptr, *d_AP = nullptr;
-    double *d_Lc = nullptr, *d_Y = nullptr, *d_G = nullptr;
+    double *d_WAWinv = nullptr, *d_Y = nullptr;
     std::vector<double> WAW, GWW, theta;
     bool frozen = false;
     int freeze_step = -1, n_updates = 0;
@@ -80,10 +103,15 @@ struct bddc_ctx {
     double *d_ahist = nullptr, *d_dhist = nullptr, *d_rhohist = nullptr, *d_bhist = nullptr, *d_muhist = nullptr,
            *d_reshist = nullptr;
     // control
-    Ctl *d_ctl = nullptr, *h_ctl = nullptr;
+    Ctl *d_ctl = nullptr, *h_ctl = nullptr, *h_ctl_init = nullptr;
+    int32_t *h_flags = nullptr, *h_zero = nullptr;
     int32_t *d_status = nullptr;
     bool have_solve = false;
     int last_iters = 0, last_restarts = 0, last_status = 0;
+    // graph of GRAPH_ITERS iterations
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t gev[GRAPH_INFLIGHT + 1] = {};
     // element data for the adjoint gradient
     double *d_coefh = nullptr;
     uint8_t *d_keep = nullptr, *d_free = nullptr;
@@ -122,7 +150,7 @@ void dfree(bddc_ctx *c, void *p) {
     if (!p) return;
     auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
     if (it != c->allocs.end()) c->allocs.erase(it);
-    hipFree(p);
+    (void)hipFree(p);
 }
 
 // CSR from (target, source) pairs; stable in insertion order
@@ -148,8 +176,8 @@ hipEvent_t get_event(bddc_ctx *c) {
         c->ev_pool.pop_back();
         return e;
     }
-    hipEvent_t e;
-    hipEventCreate(&e);
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
     return e;
 }
 struct TScope {
@@ -158,12 +186,12 @@ struct TScope {
     hipEvent_t a = nullptr;
     bool on;
     TScope(bddc_ctx *c_, int k_) : c(c_), k(k_), on(c_->timing && ((c_->timing_mask >> k_) & 1)) {
-        if (on) { a = get_event(c); hipEventRecord(a, c->stream); }
+        if (on) { a = get_event(c); (void)hipEventRecord(a, c->stream); }
     }
     ~TScope() {
         if (on) {
             hipEvent_t b = get_event(c);
-            hipEventRecord(b, c->stream);
+            (void)hipEventRecord(b, c->stream);
             c->pending.push_back({k, {a, b}});
         }
     }
@@ -171,13 +199,61 @@ struct TScope {
 void flush_timing(bddc_ctx *c) {
     for (auto &p : c->pending) {
         float ms = 0;
-        hipEventElapsedTime(&ms, p.second.first, p.second.second);
+        (void)hipEventElapsedTime(&ms, p.second.first, p.second.second);
         c->t_ms[p.first] += ms;
         c->t_cnt[p.first] += 1;
         c->ev_pool.push_back(p.second.first);
         c->ev_pool.push_back(p.second.second);
     }
     c->pending.clear();
+}
+
+// ------------------------------------------------------------- work lists
+// Split every subdomain's packed tile sequence into items of about `target`
+// tiles (at least one item per subdomain) and lay out the partial buffers.
+int build_worklist(bddc_ctx *c, OpHost &op, int64_t target) {
+    const int nsub = c->n_sub;
+    std::vector<SymvItem> items;
+    std::vector<int32_t> nch(nsub), pb(nsub), cb(nsub);
+    int64_t ylen = 0, clen = 0;
+    for (int i = 0; i < nsub; ++i) {
+        const int nci = op.dev.nc ? c->h_nc[i] : 0;
+        const int64_t nt = ntiles_of(c->h_nB[i], nci);
+        int C = (int)std::max<int64_t>(1, (nt + target / 2) / std::max<int64_t>(target, 1));
+        C = (int)std::min<int64_t>(C, nt);
+        nch[i] = C;
+        pb[i] = (int32_t)ylen;
+        cb[i] = (int32_t)clen;
+        ylen += (int64_t)C * c->h_nB[i];
+        clen += (int64_t)C * nci;
+        for (int q = 0; q < C; ++q)
+            items.push_back(SymvItem{i, (int32_t)(nt * q / C), (int32_t)(nt * (q + 1) / C), q});
+    }
+    if (ylen > INT32_MAX || clen > INT32_MAX) return fail(BDDC_EINVAL, "operator partial buffers exceed int32 indexing");
+    dfree(c, op.d_items); dfree(c, op.d_nchunk); dfree(c, op.d_pb); dfree(c, op.d_cb);
+    std::vector<int32_t> raw(items.size() * 4);
+    std::memcpy(raw.data(), items.data(), items.size() * sizeof(SymvItem));
+    int rc;
+    if ((rc = dupload(c, &op.d_items, raw)) || (rc = dupload(c, &op.d_nchunk, nch)) || (rc = dupload(c, &op.d_pb, pb)) ||
+        (rc = dupload(c, &op.d_cb, cb)))
+        return rc;
+    if (ylen > op.ypart_len) {
+        dfree(c, op.d_ypart);
+        if ((rc = dalloc(c, &op.d_ypart, (size_t)ylen))) return rc;
+        op.ypart_len = ylen;
+    }
+    if (clen > op.cpart_len) {
+        dfree(c, op.d_cpart);
+        if ((rc = dalloc(c, &op.d_cpart, (size_t)std::max<int64_t>(1, clen)))) return rc;
+        op.cpart_len = clen;
+    }
+    op.nchunk = nch;
+    op.dev.items = reinterpret_cast<const SymvItem *>(op.d_items);
+    op.dev.n_items = (int)items.size();
+    op.dev.nchunk = op.d_nchunk;
+    op.dev.pb = op.d_pb;
+    op.dev.cb = op.d_cb;
+    return 0;
 }
 
 // ------------------------------------------------------------- sub-steps
@@ -188,116 +264,228 @@ int sync_ctl(bddc_ctx *c) {
 }
 
 int set_done(bddc_ctx *c, int v) {
-    int32_t val = v;
-    HIPCHK(hipMemcpyAsync(&c->d_ctl->done, &val, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *c->h_zero = v;
+    HIPCHK(hipMemcpyAsync(&c->d_ctl->done, c->h_zero, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return 0;
 }
 
-SymvArgs schur_args(bddc_ctx *c, const double *x, int mode) {
-    SymvArgs a{};
-    a.tiles = c->d_S; a.t_off = c->d_s_off;
-    a.nB = c->d_nB; a.b_off = c->d_b_off; a.gB = c->d_gB;
-    a.nc = nullptr; a.c_off = nullptr;
-    a.x = x; a.y = c->d_locq; a.c = nullptr;
-    a.partial = mode == 1 ? c->d_partial : nullptr;
-    a.ctl = c->d_ctl; a.mode = mode; a.gated = mode == 1;
-    a.d_hist = c->d_dhist; a.a_hist = c->d_ahist; a.hist_cap = c->hist_cap;
-    return a;
+Gather gather_of(const bddc_ctx *c, const OpHost &op, bool coarse) {
+    Gather g{};
+    if (coarse) {
+        g.ptr = c->d_casm_ptr; g.idx = c->d_casm_idx; g.pos_sub = c->d_cpos_sub; g.off = c->d_c_off; g.len = c->d_nc;
+        g.base = op.d_cb; g.part = op.d_cpart;
+    } else {
+        g.ptr = c->d_asm_ptr; g.idx = c->d_asm_idx; g.pos_sub = c->d_pos_sub; g.off = c->d_b_off; g.len = c->d_nB;
+        g.base = op.d_pb; g.part = op.d_ypart;
+    }
+    g.nchunk = op.d_nchunk;
+    return g;
 }
 
-void run_schur(bddc_ctx *c, const double *x, int mode) {
+// Schur products y_i = S_i x_i of every subdomain (partials in opS); with
+// `dot`, per-item x_i^T y_i partials for p^T A p.
+void run_schur(bddc_ctx *c, const double *x, bool gated, bool dot) {
     TScope ts(c, TK_SCHUR);
-    launch_symv(schur_args(c, x, mode), 64, c->n_sub, c->smem_S, c->stream);
+    SymvArgs a{};
+    a.op = c->opS.dev;
+    a.x = x;
+    a.ypart = c->opS.d_ypart;
+    a.dot = dot ? c->d_dotS : nullptr;
+    a.ctl = c->d_ctl;
+    a.gated = gated ? 1 : 0;
+    launch_symv(a, 64, c->opS.cfg, c->opS.smem, c->stream);
 }
 
-// z = M^{-1} r into c->d_z (or out); with reductions when `reduce`
-void run_precond(bddc_ctx *c, const double *r, double *zout, bool reduce, bool first, bool gated) {
+// One BDDC application on r: local constrained-Neumann products and coarse
+// residuals, the coarse problem, assembly of z with the coarse prolongation
+// and the (r^T z, (AW)^T z) partials.  test: stopping test at the start
+// (0 none, 1 in the loop, 2 first test of a solve).
+void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, bool advance, bool reduce) {
     {
         TScope ts(c, TK_PREC);
         SymvArgs a{};
-        a.tiles = c->d_N; a.t_off = c->d_n_off;
-        a.nB = c->d_nB; a.b_off = c->d_b_off; a.gB = c->d_gB;
-        a.nc = c->d_nc; a.c_off = c->d_c_off;
-        a.x = r; a.y = c->d_locu; a.c = c->d_locc;
-        a.partial = nullptr; a.ctl = c->d_ctl; a.mode = 0; a.gated = gated ? 1 : 0;
-        launch_symv(a, c->prec, c->n_sub, c->smem_N, c->stream);
+        a.op = c->opN.dev;
+        a.x = r;
+        a.ypart = c->opN.d_ypart;
+        a.cpart = c->opN.d_cpart;
+        a.ctl = c->d_ctl;
+        a.gated = gated ? 1 : 0;
+        a.test = test;
+        a.stop_rule = c->opts.stop_rule;
+        a.max_it = c->opts.max_it;
+        a.rr_part = c->d_rr; a.rr_n = c->vgrid;
+        a.bb_part = c->d_bbp; a.bb_n = c->vgrid;
+        a.res_hist = c->d_reshist; a.hist_cap = c->hist_cap;
+        launch_symv(a, c->prec, c->opN.cfg, c->opN.smem, c->stream);
     }
-    {
+    if (c->nC > 0) {
         TScope ts(c, TK_COARSE);
-        ProlArgs p{};
-        p.ctl = c->d_ctl;
-        p.nB = c->d_nB; p.b_off = c->d_b_off; p.nc = c->d_nc; p.c_off = c->d_c_off; p.cidx = c->d_cidx; p.cL = c->d_cL;
-        p.tiles = c->d_N; p.t_off = c->d_n_off;
-        p.locu = c->d_locu;
+        const Gather rc = gather_of(c, c->opN, true);
         if (c->three) {
             L2Args l{};
             l.ctl = c->d_ctl;
+            l.rc = rc;
             l.nL = c->d_nL; l.nI2 = c->d_nI2; l.L_off = c->d_L_off; l.L = c->d_L; l.I2_off = c->d_I2_off;
-            l.B2_off = c->d_B2_off; l.g2 = c->d_g2; l.cptr = c->d_casm_ptr; l.cidx_asm = c->d_casm_idx;
-            l.locc = c->d_locc; l.K2_off = c->d_K2_off; l.K2 = c->d_K2; l.vI2 = c->d_vI2; l.t2 = c->d_t2;
-            l.rB2 = c->d_rB2; l.asm2_ptr = c->d_asm2_ptr; l.asm2_idx = c->d_asm2_idx; l.N2_off = c->d_N2_off;
-            l.N2 = c->d_N2; l.P2_off = c->d_P2_off; l.Phi2 = c->d_Phi2; l.nc3 = c->d_nc3; l.C3_off = c->d_C3_off;
-            l.u2 = c->d_u2; l.c3loc = c->d_c3loc;
+            l.B2_off = c->d_B2_off; l.g2 = c->d_g2;
+            l.K2_off = c->d_K2_off; l.K2 = c->d_K2; l.vI2 = c->d_vI2; l.t2 = c->d_t2; l.rB2 = c->d_rB2;
+            l.asm2_ptr = c->d_asm2_ptr; l.asm2_idx = c->d_asm2_idx; l.N2_off = c->d_N2_off; l.N2 = c->d_N2;
+            l.P2_off = c->d_P2_off; l.Phi2 = c->d_Phi2; l.nc3 = c->d_nc3; l.C3_off = c->d_C3_off; l.c3 = c->d_c3;
+            l.u2 = c->d_u2; l.c3loc = c->d_c3loc; l.pos_sr = c->d_pos_sr; l.own2 = c->d_own2; l.u3 = c->d_u3;
+            l.uC = c->d_uC;
             launch_l2_a(l, c->nsr, c->max_nL, c->stream);
             launch_l2_b(l, c->nsr, c->max_nL, c->stream);
-            CoarseArgs ca{};
-            ca.ctl = c->d_ctl; ca.n = c->n3; ca.ptr = c->d_asm3_ptr; ca.idx = c->d_asm3_idx; ca.loc = c->d_c3loc;
-            ca.Kneg = c->d_K3inv; ca.u = c->d_u3;
-            if (c->n3 > 0) launch_coarse_solve(ca, c->stream);
-            p.three = 1;
-            p.sr_of_sub = c->d_sr_of_sub; p.nL = c->d_nL; p.nI2 = c->d_nI2; p.I2_off = c->d_I2_off;
-            p.B2_off = c->d_B2_off; p.g2 = c->d_g2; p.asm2_ptr = c->d_asm2_ptr; p.asm2_idx = c->d_asm2_idx;
-            p.pos_sr = c->d_pos_sr; p.nc3 = c->d_nc3; p.C3_off = c->d_C3_off; p.c3 = c->d_c3;
-            p.K2_off = c->d_K2_off; p.P2_off = c->d_P2_off; p.K2 = c->d_K2; p.Phi2 = c->d_Phi2;
-            p.u2 = c->d_u2; p.u3 = c->d_u3; p.vI2 = c->d_vI2;
+            L3Args l3{};
+            l3.ctl = c->d_ctl; l3.n = c->n3; l3.ptr = c->d_asm3_ptr; l3.idx = c->d_asm3_idx; l3.loc = c->d_c3loc;
+            l3.Kneg = c->d_K3inv; l3.u = c->d_u3;
+            launch_l3(l3, c->stream);
+            launch_l2_d(l, c->nsr, c->max_nL, c->stream);
         } else {
-            CoarseArgs ca{};
-            ca.ctl = c->d_ctl; ca.n = c->nC; ca.ptr = c->d_casm_ptr; ca.idx = c->d_casm_idx; ca.loc = c->d_locc;
-            ca.Kneg = c->d_KCinv; ca.u = c->d_uC;
-            if (c->nC > 0) launch_coarse_solve(ca, c->stream);
-            p.three = 0;
-            p.uCg = c->d_uC;
+            Coarse2Args ca{};
+            ca.ctl = c->d_ctl; ca.n = c->nC; ca.rc = rc; ca.Kneg = c->d_KCinv; ca.u = c->d_uC;
+            launch_coarse2(ca, c->stream);
         }
-        launch_prolong(p, c->prec, c->n_sub, c->smem_prol, c->stream);
     }
     {
         TScope ts(c, TK_VEC);
-        ZasmArgs z{};
-        z.n = c->n_gamma; z.ptr = c->d_asm_ptr; z.idx = c->d_asm_idx; z.loc = c->d_locu; z.r = r;
-        z.z = zout; z.AW = c->d_AW; z.ld = c->ld; z.Lc = c->d_Lc;
-        z.partial = reduce ? c->d_partial : nullptr;
-        z.ctl = c->d_ctl; z.first = first ? 1 : 0; z.gated = gated ? 1 : 0;
-        z.rho_hist = c->d_rhohist; z.b_hist = c->d_bhist; z.mu_hist = c->d_muhist; z.hist_cap = c->hist_cap;
-        launch_zasm(z, c->stream);
+        ZasmArgs a{};
+        a.n = c->n_gamma;
+        a.u = gather_of(c, c->opN, false);
+        a.b_off = c->d_b_off; a.nB = c->d_nB;
+        a.phir = c->d_phir; a.phr_off = c->d_phr_off;
+        a.nc = c->d_nc; a.c_off = c->d_c_off; a.cidx = c->d_cidx;
+        a.uC = c->nC > 0 ? c->d_uC : nullptr;
+        a.r = r; a.z = z;
+        a.AW = c->d_AW; a.ld = c->ld;
+        a.part = reduce ? c->d_zp : nullptr;
+        a.ctl = c->d_ctl;
+        a.gated = gated ? 1 : 0;
+        a.advance = advance ? 1 : 0;
+        launch_zasm(a, c->prec, c->kmax, c->vgrid, c->stream);
     }
 }
 
-void run_pupd(bddc_ctx *c) {
+void run_pupd(bddc_ctx *c, bool first, bool hist_only, bool gated) {
     TScope ts(c, TK_VEC);
     PupdArgs a{};
     a.n = c->n_gamma; a.z = c->d_z; a.p = c->d_p; a.W = c->d_W; a.ld = c->ld;
-    a.P = c->d_P; a.cap = c->save_cap; a.ctl = c->d_ctl;
-    launch_pupd(a, c->stream);
+    a.P = c->d_P; a.cap = c->save_cap;
+    a.zpart = c->d_zp; a.zpart_n = c->vgrid;
+    a.WAWinv = c->d_WAWinv;
+    a.ctl = c->d_ctl;
+    a.first = first ? 1 : 0; a.hist_only = hist_only ? 1 : 0; a.gated = gated ? 1 : 0;
+    a.rho_hist = c->d_rhohist; a.b_hist = c->d_bhist; a.mu_hist = c->d_muhist; a.hist_cap = c->hist_cap;
+    launch_pupd(a, c->vgrid, c->stream);
 }
 
 void run_update(bddc_ctx *c) {
     TScope ts(c, TK_VEC);
     UpdArgs a{};
-    a.n = c->n_gamma; a.ptr = c->d_asm_ptr; a.idx = c->d_asm_idx; a.loc = c->d_locq; a.p = c->d_p;
-    a.x = c->d_x; a.r = c->d_r; a.AP = c->d_AP; a.ld = c->ld; a.cap = c->save_cap;
-    a.partial = c->d_partial; a.ctl = c->d_ctl; a.res_hist = c->d_reshist; a.hist_cap = c->hist_cap;
-    a.max_it = c->opts.max_it;
-    launch_update(a, c->stream);
+    a.n = c->n_gamma;
+    a.q = gather_of(c, c->opS, false);
+    a.p = c->d_p; a.x = c->d_x; a.r = c->d_r;
+    a.AP = c->d_AP; a.ld = c->ld; a.cap = c->save_cap;
+    a.dot = c->d_dotS; a.dot_n = c->opS.dev.n_items;
+    a.rr_part = c->d_rr;
+    a.ctl = c->d_ctl;
+    a.d_hist = c->d_dhist; a.a_hist = c->d_ahist; a.rho_hist = c->d_rhohist; a.hist_cap = c->hist_cap;
+    launch_update(a, c->vgrid, c->stream);
 }
 
-void run_resid(bddc_ctx *c, int mode, double *out) {
+// out = b - (sum of the Schur partials); per-block ||out||^2 into d_rr and,
+// with want_wtr, (||out||^2, W^T out) into d_wp.
+void run_resid(bddc_ctx *c, double *out, bool want_wtr) {
     TScope ts(c, TK_VEC);
     ResidArgs a{};
-    a.n = c->n_gamma; a.mode = mode; a.stop_rule = c->opts.stop_rule;
-    a.ptr = c->d_asm_ptr; a.idx = c->d_asm_idx; a.loc = c->d_locq; a.b = c->d_b; a.out = out;
-    a.W = c->d_W; a.ld = c->ld; a.Lc = c->d_Lc; a.partial = c->d_partial; a.ctl = c->d_ctl;
-    launch_resid(a, c->stream);
+    a.n = c->n_gamma; a.want_wtr = want_wtr ? 1 : 0;
+    a.q = gather_of(c, c->opS, false);
+    a.b = c->d_b; a.out = out;
+    a.W = c->d_W; a.ld = c->ld;
+    a.ctl = c->d_ctl;
+    a.part = c->d_wp;
+    launch_resid(a, want_wtr ? c->kmax : 0, c->vgrid, c->stream);
+}
+
+// One iteration of Algorithm 1 (lines 9-16), every kernel gated by ctl->done.
+void enqueue_iteration(bddc_ctx *c) {
+    run_schur(c, c->d_p, true, true);                    // line 9: A p_j, p_j^T A p_j
+    run_update(c);                                       // lines 9-11
+    run_precond(c, c->d_r, c->d_z, 1, true, true, true); // stopping test, line 13
+    run_pupd(c, false, false, true);                     // lines 14-16
+}
+
+int capture_graph(bddc_ctx *c) {
+    if (c->gexec) return 0;
+    hipStream_t keep = c->stream;
+    const bool tkeep = c->timing;
+    c->timing = false;
+    c->stream = c->cap_stream;
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        for (int it = 0; it < GRAPH_ITERS; ++it) enqueue_iteration(c);
+        e = hipStreamEndCapture(c->stream, &c->graph);
+    }
+    c->stream = keep;
+    c->timing = tkeep;
+    if (e != hipSuccess) return fail(BDDC_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    HIPCHK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    return 0;
+}
+
+// Iterate until ctl->done: graph replays with the convergence flag polled
+// through pinned memory a few graphs behind (use_graph), or eagerly launched
+// iterations with a host check after each one (plain form).
+int run_loop(bddc_ctx *c) {
+    const int max_launch = c->opts.max_it + 2;
+    if (c->opts.use_graph && !c->timing) {
+        int rc = capture_graph(c);
+        if (rc) return rc;
+        int launched = 0, polled = 0;
+        const int cap = max_launch / GRAPH_ITERS + GRAPH_INFLIGHT + 1;
+        while (true) {
+            const int slot = launched % (GRAPH_INFLIGHT + 1);
+            HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+            HIPCHK(hipMemcpyAsync(&c->h_flags[slot], &c->d_ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipEventRecord(c->gev[slot], c->stream));
+            ++launched;
+            if (launched - polled >= GRAPH_INFLIGHT || launched >= cap) {
+                const int ps = polled % (GRAPH_INFLIGHT + 1);
+                HIPCHK(hipEventSynchronize(c->gev[ps]));
+                ++polled;
+                if (c->h_flags[ps]) break;
+                if (launched >= cap) {
+                    // every kernel stops at max_it; drain what is queued
+                    while (polled < launched) {
+                        const int q = polled % (GRAPH_INFLIGHT + 1);
+                        HIPCHK(hipEventSynchronize(c->gev[q]));
+                        ++polled;
+                        if (c->h_flags[q]) break;
+                    }
+                    break;
+                }
+            }
+        }
+        return 0;
+    }
+    for (int it = 0; it < max_launch; ++it) {
+        enqueue_iteration(c);
+        int rc = sync_ctl(c);
+        if (rc) return rc;
+        if (c->h_ctl->done) break;
+    }
+    return 0;
+}
+
+int upload_ctl(bddc_ctx *c, double rtol, bool record) {
+    HIPCHK(hipStreamSynchronize(c->stream));   // the pinned staging copy may still be read
+    Ctl h{};
+    h.rtol2 = rtol * rtol;
+    h.k = c->k;
+    h.record = record ? 1 : 0;
+    *c->h_ctl_init = h;
+    HIPCHK(hipMemcpyAsync(c->d_ctl, c->h_ctl_init, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+    return 0;
 }
 
 void run_condense(bddc_ctx *c, const double *F) {
@@ -308,13 +496,13 @@ void run_condense(bddc_ctx *c, const double *F) {
     launch_cond_local(a, c->n_sub, c->max_nI, c->stream);
     CondAsmArgs b{};
     b.n = c->n_gamma; b.gamma = c->d_gamma; b.ptr = c->d_asm_ptr; b.idx = c->d_asm_idx; b.F = F; b.loc = c->d_locq;
-    b.b = c->d_b; b.partial = c->d_partial; b.ctl = c->d_ctl;
-    launch_cond_asm(b, c->stream);
+    b.b = c->d_b; b.part = c->d_bbp;
+    launch_cond_asm(b, c->vgrid, c->stream);
 }
 
 int run_recover(bddc_ctx *c, double *u) {
     TScope ts(c, TK_COND);
-    HIPCHK(hipMemsetAsync(u, 0, c->n_nodes * sizeof(double), c->stream));
+    launch_fill(c->n_nodes, 0.0, u, c->stream);
     RecArgs a{};
     a.nI = c->d_nI; a.nB = c->d_nB; a.i_off = c->d_i_off; a.b_off = c->d_b_off; a.nodesI = c->d_nodesI;
     a.gB = c->d_gB; a.k_off = c->d_k_off; a.K = c->d_K; a.x = c->d_x; a.yI = c->d_yI; a.u = u;
@@ -323,15 +511,13 @@ int run_recover(bddc_ctx *c, double *u) {
     return 0;
 }
 
-int upload_ctl(bddc_ctx *c, double rtol, bool record) {
-    Ctl h{};
-    h.rtol2 = rtol * rtol;
-    h.k = c->k;
-    h.record = record ? 1 : 0;
-    *c->h_ctl = h;
-    HIPCHK(hipMemcpyAsync(c->d_ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    return 0;
+// ||b - A x||^2 of the interface problem into ctl->true_rr (and out = b - A x)
+void run_true_residual(bddc_ctx *c, double *out) {
+    run_schur(c, c->d_x, false, false);
+    run_resid(c, out, false);
+    ReduceArgs r{};
+    r.part = c->d_wp; r.n = c->vgrid; r.st = RMAX + 1; r.ncol = 1; r.out = &c->d_ctl->true_rr;
+    launch_reduce(r, c->stream);
 }
 
 // One right-hand side: condense, Algorithm 1 from x_prev, recover.
@@ -339,44 +525,36 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     const bool record = recycle && c->R > 0 && !c->frozen;
     int rc = upload_ctl(c, rtol, record);
     if (rc) return rc;
-    run_condense(c, F);
-    if (c->opts.init_guess == 1) HIPCHK(hipMemsetAsync(c->d_x, 0, c->n_gamma * sizeof(double), c->stream));
-    run_schur(c, c->d_x, 0);                 // r = b - A x_{-1}
-    run_resid(c, 0, c->d_r);
-    if (c->k > 0) {                          // Alg. 1 lines 3-4
+    run_condense(c, F);                                  // b, ||b||^2 partials
+    if (c->opts.init_guess == 1) launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
+    run_schur(c, c->d_x, false, false);                  // r = b - A x_{-1}
+    run_resid(c, c->d_r, c->k > 0);
+    {
         TScope ts(c, TK_VEC);
-        DeflArgs d{};
-        d.n = c->n_gamma; d.stop_rule = c->opts.stop_rule; d.x = c->d_x; d.r = c->d_r; d.W = c->d_W;
-        d.AW = c->d_AW; d.ld = c->ld; d.partial = c->d_partial; d.ctl = c->d_ctl;
-        launch_defl_init(d, c->stream);
+        DeflArgs d{};                                     // Alg. 1 lines 3-4 (k = 0: ||r||^2 only)
+        d.n = c->n_gamma; d.x = c->d_x; d.r = c->d_r; d.W = c->d_W; d.AW = c->d_AW; d.ld = c->ld;
+        d.wpart = c->d_wp; d.wpart_n = c->vgrid; d.WAWinv = c->d_WAWinv; d.rr_part = c->d_rr; d.ctl = c->d_ctl;
+        launch_defl_init(d, c->vgrid, c->stream);
     }
-    if ((rc = sync_ctl(c))) return rc;
+    run_precond(c, c->d_r, c->d_z, 2, false, false, true);  // first test, lines 5-6
+    run_pupd(c, true, false, true);                         // line 7
     int restarts = 0;
     while (true) {
-        if (!c->h_ctl->done) {
-            run_precond(c, c->d_r, c->d_z, true, true, true);   // lines 5-6
-            run_pupd(c);                                        // line 7
-            for (;;) {
-                run_schur(c, c->d_p, 1);                        // line 9 (A p, alpha)
-                run_update(c);                                  // lines 10-11, stopping test
-                run_precond(c, c->d_r, c->d_z, true, false, true);  // lines 13-15
-                run_pupd(c);                                    // line 16
-                if ((rc = sync_ctl(c))) return rc;
-                if (c->h_ctl->done) break;
-            }
-        }
+        if ((rc = run_loop(c))) return rc;
+        if ((rc = sync_ctl(c))) return rc;
+        if (c->h_ctl->zero_rhs) launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
         // true residual of the interface problem in float64
-        run_schur(c, c->d_x, 0);
-        run_resid(c, 1, c->d_tmp);
+        run_true_residual(c, c->d_tmp);
         if ((rc = sync_ctl(c))) return rc;
         const Ctl &h = *c->h_ctl;
-        if (h.status != 0) break;
-        if (h.true_rr < h.rtol2 * h.denom2 || h.bb == 0.0 || h.iter >= c->opts.max_it) break;
-        // residual replacement and restart (counted iterations continue)
+        if (h.status != 0 || h.zero_rhs) break;
+        if (h.true_rr < h.rtol2 * h.denom2 || h.iter >= c->opts.max_it) break;
+        // residual replacement, then continue from line 5 (iterations keep counting)
         ++restarts;
         launch_copy(c->n_gamma, c->d_tmp, c->d_r, c->stream);
         if ((rc = set_done(c, 0))) return rc;
-        if ((rc = sync_ctl(c))) return rc;
+        run_precond(c, c->d_r, c->d_z, 0, false, true, true);
+        run_pupd(c, true, false, true);
     }
     const Ctl h = *c->h_ctl;
     c->last_iters = h.iter;
@@ -385,11 +563,12 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     c->have_solve = true;
     if (iters) *iters = h.iter;
     if (relres) *relres = h.bb > 0 ? std::sqrt(h.true_rr / h.bb) : 0.0;
-    // z_l = M^{-1} r_l for the harmonic-Ritz matrices (Section 4.2)
+    // z_l = M^{-1} r_l for the harmonic-Ritz matrices (Section 4.2): rho_l, mu_l
     const int strat = c->opts.recycle_strategy;
-    if (record && h.status == 0 && restarts == 0 && (strat == 3 || strat == 4)) {
+    if (record && h.status == 0 && restarts == 0 && h.iter > 0 && (strat == 3 || strat == 4)) {
         if ((rc = set_done(c, 0))) return rc;
-        run_precond(c, c->d_r, c->d_tmp, true, false, false);
+        run_precond(c, c->d_r, c->d_z, 0, false, true, true);
+        run_pupd(c, false, true, false);
     }
     if ((rc = run_recover(c, u))) return rc;
     if (h.status == BDDC_EBREAKDOWN) return fail(BDDC_EBREAKDOWN, "PCG breakdown (r^T z <= 0, p^T A p <= 0 or NaN)");
@@ -397,22 +576,26 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     return 0;
 }
 
-int refresh_waw(bddc_ctx *c, double *W, double *AW, int k, std::vector<double> &waw) {
+int refresh_waw(bddc_ctx *c, const double *W, const double *AW, int k, std::vector<double> &waw) {
     if (k == 0) { waw.clear(); return 0; }
-    GramArgs g{};
-    g.n = c->n_gamma; g.k = k; g.ld = c->ld; g.X = W; g.Y = AW; g.partial = c->d_partial; g.out = c->d_G;
-    g.ctl = c->d_ctl;
     const int nb = std::max(1, std::min(256, (c->n_gamma + 1023) / 1024));
+    GramArgs g{};
+    g.n = c->n_gamma; g.k = k; g.ld = c->ld; g.X = W; g.Y = AW; g.part = c->d_gp;
     launch_gram(g, nb, c->stream);
+    ReduceArgs r{};
+    r.part = c->d_gp; r.n = nb; r.st = k * k; r.ncol = k * k; r.out = c->d_Y;
+    launch_reduce(r, c->stream);
     waw.resize((size_t)k * k);
-    HIPCHK(hipMemcpyAsync(waw.data(), c->d_G, (size_t)k * k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(waw.data(), c->d_Y, (size_t)k * k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     for (int i = 0; i < k; ++i)
         for (int j = i + 1; j < k; ++j) waw[i * k + j] = waw[j * k + i] = 0.5 * (waw[i * k + j] + waw[j * k + i]);
     return 0;
 }
 
-// W_new = [W, P] Y, AW_new = [AW, AP] Y; commit only if W_new^T A W_new is SPD
+// W_new = [W, P] Y, AW_new = [AW, AP] Y; commit only if W_new^T A W_new is SPD.
+// The new basis is copied into the fixed W, AW buffers (captured graphs keep
+// their pointers).
 int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol) {
     const int ldy = (ncol + 7) / 8 * 8;
     std::vector<double> Yp((size_t)m * ldy, 0.0);
@@ -426,16 +609,28 @@ int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol) {
     launch_recycle_gemm(g, c->stream);
     g.V1 = c->d_AW; g.V2 = c->d_AP; g.out = c->d_AWn;
     launch_recycle_gemm(g, c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));   // d_Y is reused by the Gram reduction
     std::vector<double> waw;
     int rc = refresh_waw(c, c->d_Wn, c->d_AWn, ncol, waw);
     if (rc) return rc;
     std::vector<double> L = waw;
     if (!cholesky(L, ncol)) return fail(BDDC_ESINGULAR, "new W^T A W is not positive definite; basis kept");
-    std::swap(c->d_W, c->d_Wn);
-    std::swap(c->d_AW, c->d_AWn);
+    // explicit inverse of W^T A W from its Cholesky factor (k x k, row-major)
+    std::vector<double> inv((size_t)ncol * ncol, 0.0), e(ncol);
+    for (int j = 0; j < ncol; ++j) {
+        std::fill(e.begin(), e.end(), 0.0);
+        e[j] = 1.0;
+        chol_solve(L, ncol, e.data());
+        for (int i = 0; i < ncol; ++i) inv[(size_t)i * ncol + j] = e[i];
+    }
+    for (int i = 0; i < ncol; ++i)
+        for (int j = i + 1; j < ncol; ++j) inv[(size_t)i * ncol + j] = inv[(size_t)j * ncol + i] =
+            0.5 * (inv[(size_t)i * ncol + j] + inv[(size_t)j * ncol + i]);
+    launch_copy((int64_t)ncol * c->ld, c->d_Wn, c->d_W, c->stream);
+    launch_copy((int64_t)ncol * c->ld, c->d_AWn, c->d_AW, c->stream);
     c->k = ncol;
     c->WAW = waw;
-    HIPCHK(hipMemcpyAsync(c->d_Lc, L.data(), L.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_WAWinv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return 0;
 }
@@ -590,30 +785,87 @@ void bddc_default_opts(bddc_opts *o) {
     o->init_guess = 0;
     o->max_it = 1000;
     o->save_cap = 256;
-    o->use_graph = 0;
+    o->use_graph = 1;
 }
 
 const char *bddc_last_error(void) { return g_err.c_str(); }
 
-static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, const double *coef) {
+}  // extern "C"
+
+namespace {
+
+// Work-list granularity: about `items_per_cu` items per compute unit, each
+// at least 32 tiles.
+int64_t item_target(const bddc_ctx *c, int64_t total_tiles, int items_per_cu) {
+    const int64_t want = (int64_t)c->n_cu * items_per_cu;
+    return std::max<int64_t>(32, (total_tiles + want - 1) / want);
+}
+
+int setup_operators(bddc_ctx *c) {
+    const int nsub = c->n_sub;
+    OpHost *ops[2] = {&c->opS, &c->opN};
+    for (int w = 0; w < 2; ++w) {
+        OpHost &op = *ops[w];
+        const bool isN = w == 1;
+        op.prec = isN ? c->prec : 64;
+        op.dev.tiles = isN ? c->d_N : (const void *)c->d_S;
+        op.dev.t_off = isN ? c->d_n_off : c->d_s_off;
+        op.dev.nB = c->d_nB;
+        op.dev.b_off = c->d_b_off;
+        op.dev.gB = c->d_gB;
+        op.dev.nc = isN ? c->d_nc : nullptr;
+        op.n_tiles = 0;
+        double bytes = 0.0;
+        const double eb = op.prec / 8.0;
+        for (int i = 0; i < nsub; ++i) {
+            const int nci = isN ? c->h_nc[i] : 0;
+            op.n_tiles += ntiles_of(c->h_nB[i], nci);
+            const double n = c->h_nB[i];
+            // packed upper triangle (+ coarse basis), gathered input and its
+            // index, output (+ coarse output)
+            bytes += (n * (n + 1) / 2 + n * nci) * eb + n * (8 + 4 + 8) + nci * 8;
+        }
+        op.bytes = bytes;
+        op.cfg = SymvCfg{4, 2};
+        op.smem = symv_smem(op.prec, op.cfg.nw, c->max_nt, isN ? c->max_ntc : 0);
+        int rc = build_worklist(c, op, item_target(c, op.n_tiles, 6));
+        if (rc) return rc;
+    }
+    const size_t lim = std::max(symv_smem(64, 8, c->max_nt, 0), symv_smem(c->prec, 8, c->max_nt, c->max_ntc));
+    if (lim > 160 * 1024) return fail(BDDC_EINVAL, "a subdomain interface is too large for the LDS-staged products");
+    if (set_symv_smem_limit(lim)) return fail(BDDC_EHIP, "hipFuncSetAttribute (dynamic LDS) failed");
+    c->t_bytes[TK_SCHUR] = c->opS.bytes;
+    c->t_bytes[TK_PREC] = c->opN.bytes;
+    return 0;
+}
+
+int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, const double *coef) {
     Structure &st = c->st;
     std::string err;
     int rc = build_structure(mesh, part, coef, &c->opts, st, err);
     if (rc) return fail(rc, err);
     hipStream_t s = c->stream;
+    {
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        int ncu = 0;
+        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        c->n_cu = std::max(1, ncu);
+    }
     c->n_sub = st.n_sub;
     c->n_gamma = (int)st.gamma.size();
     c->nC = (int)st.coarse.size();
     c->n_nodes = st.n_nodes;
     c->prec = c->opts.local_prec;
     const int nsub = c->n_sub;
+    const int eN = c->prec / 8;   // bytes per element of the local Neumann operators
 
     // -------------------------------------------------- level-1 metadata
     std::vector<int32_t> nI(nsub), nB(nsub), nc(nsub), i_off(nsub + 1, 0), b_off(nsub + 1, 0), c_off(nsub + 1, 0);
     std::vector<int64_t> k_off(nsub + 1, 0), s_off(nsub + 1, 0), n_off(nsub + 1, 0), kc_off(nsub + 1, 0),
-        m_off(nsub + 1, 0), x_off(nsub + 1, 0);
-    std::vector<int32_t> gB, nodesI, cidx;
-    int max_nt = 0, max_ntc = 0, max_sad = 0, max_nloc = 0;
+        m_off(nsub + 1, 0), x_off(nsub + 1, 0), phr_off(nsub + 1, 0);
+    std::vector<int32_t> gB, nodesI, cidx, pos_sub, cpos_sub;
+    int max_sad = 0, max_nloc = 0;
     for (int i = 0; i < nsub; ++i) {
         const SubHost &sh = st.sub[i];
         nI[i] = sh.nI; nB[i] = sh.nB; nc[i] = (int)sh.cidx.size();
@@ -627,23 +879,32 @@ static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *
         kc_off[i + 1] = kc_off[i] + (int64_t)nc[i] * nc[i];
         m_off[i + 1] = m_off[i] + (int64_t)(sh.nB + nc[i]) * (sh.nB + nc[i]);
         x_off[i + 1] = x_off[i] + (int64_t)sh.nB * nc[i];
+        phr_off[i + 1] = phr_off[i] + (int64_t)sh.nB * nc[i];
         gB.insert(gB.end(), sh.gB.begin(), sh.gB.end());
         nodesI.insert(nodesI.end(), sh.nodes.begin(), sh.nodes.begin() + sh.nI);
         cidx.insert(cidx.end(), sh.cidx.begin(), sh.cidx.end());
+        pos_sub.insert(pos_sub.end(), sh.nB, i);
+        cpos_sub.insert(cpos_sub.end(), nc[i], i);
         c->max_nI = std::max(c->max_nI, sh.nI);
         c->max_nB = std::max(c->max_nB, sh.nB);
         c->max_nc = std::max(c->max_nc, nc[i]);
-        max_nt = std::max(max_nt, (sh.nB + TILE - 1) / TILE);
-        max_ntc = std::max(max_ntc, (nc[i] + TILE - 1) / TILE);
+        c->max_nt = std::max(c->max_nt, (sh.nB + TILE - 1) / TILE);
+        c->max_ntc = std::max(c->max_ntc, (nc[i] + TILE - 1) / TILE);
         max_sad = std::max(max_sad, sh.nB + nc[i]);
         max_nloc = std::max(max_nloc, sh.nloc);
     }
+    if (b_off[nsub] > INT32_MAX / 2) return fail(BDDC_EINVAL, "too many local interface entries");
+    c->h_nB = nB; c->h_nc = nc;
+    c->h_b_off.assign(b_off.begin(), b_off.end() - 1);
+    c->h_c_off.assign(c_off.begin(), c_off.end() - 1);
     if ((rc = dupload(c, &c->d_nI, nI)) || (rc = dupload(c, &c->d_nB, nB)) || (rc = dupload(c, &c->d_nc, nc)) ||
         (rc = dupload(c, &c->d_i_off, i_off)) || (rc = dupload(c, &c->d_b_off, b_off)) ||
         (rc = dupload(c, &c->d_c_off, c_off)) || (rc = dupload(c, &c->d_k_off, k_off)) ||
         (rc = dupload(c, &c->d_s_off, s_off)) || (rc = dupload(c, &c->d_n_off, n_off)) ||
-        (rc = dupload(c, &c->d_gB, gB)) || (rc = dupload(c, &c->d_nodesI, nodesI)) ||
-        (rc = dupload(c, &c->d_cidx, cidx)) || (rc = dupload(c, &c->d_gamma, st.gamma)))
+        (rc = dupload(c, &c->d_phr_off, phr_off)) || (rc = dupload(c, &c->d_gB, gB)) ||
+        (rc = dupload(c, &c->d_nodesI, nodesI)) || (rc = dupload(c, &c->d_cidx, cidx)) ||
+        (rc = dupload(c, &c->d_gamma, st.gamma)) || (rc = dupload(c, &c->d_pos_sub, pos_sub)) ||
+        (rc = dupload(c, &c->d_cpos_sub, cpos_sub)))
         return rc;
     // interface assembly lists (owner-computes, ordered by subdomain)
     {
@@ -703,7 +964,7 @@ static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *
             sd[i] = SweepDesc{c->d_K + k_off[i], st.sub[i].nloc, st.sub[i].nloc, 0, nI[i], st.sub[i].nloc};
         SweepDesc *dsd;
         if ((rc = dupload(c, &dsd, sd))) return rc;
-        set_sweep_smem_limit((size_t)std::max({max_nloc, 1}) * 8);
+        set_sweep_smem_limit((size_t)std::max({max_nloc, max_sad, 1}) * 8);
         launch_sweep(dsd, nsub, max_nloc, c->d_status, s);
         HIPCHK(hipStreamSynchronize(s));
         dfree(c, dd); dfree(c, dsd);
@@ -743,27 +1004,30 @@ static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *
         if ((rc = dupload(c, &dsd, sd)) || (rc = dupload(c, &dwd, wd))) return rc;
         launch_build_saddle(dsd, nsub, s);
         launch_sweep(dwd, nsub, max_sad, c->d_status, s);
-        // tiles: S_i (float64) and D N_i D with D Phi_i (local precision)
+        // tiles: S_i (float64) and D N_i D with D Phi_i (local precision), plus
+        // the row-major D Phi_i for the prolongation
         c->bytes_S = (size_t)s_off[nsub] * 8;
-        c->bytes_N = (size_t)n_off[nsub] * (c->prec / 8);
+        c->bytes_N = (size_t)n_off[nsub] * eN;
         if ((rc = dalloc(c, &c->d_S, (size_t)s_off[nsub]))) return rc;
         if ((rc = dalloc(c, (char **)&c->d_N, c->bytes_N))) return rc;
+        if ((rc = dalloc(c, (char **)&c->d_phir, (size_t)std::max<int64_t>(1, phr_off[nsub]) * eN))) return rc;
         std::vector<PackDesc> ps(nsub), pn(nsub);
         std::vector<PtspDesc> pt(nsub);
         for (int i = 0; i < nsub; ++i) {
             const int nl = st.sub[i].nloc, N = nB[i] + nc[i];
             const double *Sblk = c->d_K + k_off[i] + (int64_t)nI[i] * nl + nI[i];
-            ps[i] = PackDesc{Sblk, nl, nB[i], 1.0, nullptr, nullptr, 0, 0, s_off[i]};
-            pn[i] = PackDesc{d_M + m_off[i], N, nB[i], -1.0, d_wB + b_off[i], d_M + m_off[i] + nB[i], N, nc[i], n_off[i]};
+            ps[i] = PackDesc{Sblk, nl, nB[i], 1.0, nullptr, nullptr, 0, 0, s_off[i], -1};
+            pn[i] = PackDesc{d_M + m_off[i], N, nB[i], -1.0, d_wB + b_off[i], d_M + m_off[i] + nB[i], N, nc[i], n_off[i],
+                             phr_off[i]};
             pt[i] = PtspDesc{Sblk, nl, d_M + m_off[i] + nB[i], N, -1.0, nB[i], nc[i], d_X + x_off[i], nullptr};
         }
-        if ((rc = dalloc(c, &c->d_KC, (size_t)kc_off[nsub]))) return rc;
+        if ((rc = dalloc(c, &c->d_KC, (size_t)std::max<int64_t>(1, kc_off[nsub])))) return rc;
         for (int i = 0; i < nsub; ++i) pt[i].out = c->d_KC + kc_off[i];
         PackDesc *dps, *dpn;
         PtspDesc *dpt;
         if ((rc = dupload(c, &dps, ps)) || (rc = dupload(c, &dpn, pn)) || (rc = dupload(c, &dpt, pt))) return rc;
-        launch_pack(dps, nsub, 64, c->d_S, s);
-        launch_pack(dpn, nsub, c->prec, c->d_N, s);
+        launch_pack(dps, nsub, 64, c->d_S, nullptr, s);
+        launch_pack(dpn, nsub, c->prec, c->d_N, c->d_phir, s);
         launch_ptsp(dpt, nsub, s);
         HIPCHK(hipStreamSynchronize(s));
         dfree(c, dsd); dfree(c, dwd); dfree(c, dps); dfree(c, dpn); dfree(c, dpt);
@@ -774,28 +1038,15 @@ static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *
         HIPCHK(hipMemcpy(&st_h, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost));
         if (st_h) return fail(BDDC_ESINGULAR, "non-positive pivot in a local elimination (floating subdomain without constraints?)");
     }
-    // algorithmic bytes per launch: the packed upper triangle of each symmetric
-    // operator (+ the n x nc coarse basis), the gathered input, its index and
-    // the written output
-    {
-        double bs = 0.0, bn = 0.0;
-        const double bN = c->prec / 8.0;
-        for (int i = 0; i < nsub; ++i) {
-            const double n = nB[i], m = nc[i];
-            bs += n * (n + 1) / 2 * 8 + n * (8 + 4 + 8);
-            bn += (n * (n + 1) / 2 + n * m) * bN + n * (8 + 4 + 8) + m * 8;
-        }
-        c->t_bytes[TK_SCHUR] = bs;
-        c->t_bytes[TK_PREC] = bn;
-    }
-    c->smem_S = symv_smem(64, max_nt, 0);
-    c->smem_N = symv_smem(c->prec, max_nt, max_ntc);
-    set_symv_smem_limit(std::max(c->smem_S, c->smem_N));
+    if ((rc = setup_operators(c))) return rc;
 
     // -------------------------------------------------- coarse levels
     c->three = st.three;
+    if ((rc = dalloc(c, &c->d_uC, (size_t)std::max(1, c->nC)))) return rc;
     if (!c->three) {
         const int n = c->nC;
+        if ((size_t)n * 8 > 160 * 1024) return fail(BDDC_EINVAL, "two-level coarse problem too large for the dense solve; use subregions");
+        if ((size_t)n * 8 > 65536) return fail(BDDC_EINVAL, "two-level coarse problem above 8192 DOFs; use subregions");
         std::vector<std::pair<int64_t, int32_t>> pr;
         for (int i = 0; i < nsub; ++i)
             for (int a = 0; a < nc[i]; ++a)
@@ -804,25 +1055,25 @@ static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *
         std::vector<int32_t> ptr, idx;
         build_csr((int64_t)n * n, pr, ptr, idx);
         int32_t *dp, *di;
-        if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) || (rc = dalloc(c, &c->d_KCinv, (size_t)n * n)) ||
-            (rc = dalloc(c, &c->d_uC, (size_t)n)))
+        if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) || (rc = dalloc(c, &c->d_KCinv, (size_t)std::max(1, n * n))))
             return rc;
         launch_gather_sum((int64_t)n * n, dp, di, c->d_KC, c->d_KCinv, s);
         std::vector<SweepDesc> sd{SweepDesc{c->d_KCinv, n, n, 0, n, n}};
         SweepDesc *dsd;
         if ((rc = dupload(c, &dsd, sd))) return rc;
-        if (n > 0) launch_sweep(dsd, 1, n, c->d_status, s);
+        if (n > 0) {
+            set_sweep_smem_limit((size_t)std::max({max_nloc, max_sad, n, 1}) * 8);
+            launch_sweep(dsd, 1, n, c->d_status, s);
+        }
         HIPCHK(hipStreamSynchronize(s));
         dfree(c, dp); dfree(c, di); dfree(c, dsd);
-        c->smem_prol = (size_t)(c->max_nc + 1) * 8;
-        std::vector<int32_t> cL(c_off[nsub], 0);
-        if ((rc = dupload(c, &c->d_cL, cL))) return rc;
     } else {
         const int nsr = st.n_sr;
         c->nsr = nsr;
         c->n3 = st.n3;
+        if ((size_t)c->n3 * 8 > 65536) return fail(BDDC_EINVAL, "level-3 coarse problem above 8192 DOFs");
         std::vector<int32_t> nL(nsr), nI2(nsr), nc3(nsr), L_off(nsr + 1, 0), I2_off(nsr + 1, 0), B2_off(nsr + 1, 0),
-            C3_off(nsr + 1, 0), Lall, g2all, c3all, pos_sr, sr_of_sub(nsub);
+            C3_off(nsr + 1, 0), Lall, g2all, c3all, pos_sr;
         std::vector<int64_t> K2_off(nsr + 1, 0), N2_off(nsr + 1, 0), P2_off(nsr + 1, 0), M2_off(nsr + 1, 0),
             K3_off(nsr + 1, 0);
         std::vector<double> w2all;
@@ -844,38 +1095,30 @@ static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *
             c3all.insert(c3all.end(), r.c3.begin(), r.c3.end());
             w2all.insert(w2all.end(), r.w.begin(), r.w.end());
             for (int k = 0; k < r.nB; ++k) pos_sr.push_back(j);
-            for (int32_t i : r.subs) sr_of_sub[i] = j;
             c->max_nL = std::max(c->max_nL, nL[j]);
             max_sad2 = std::max(max_sad2, r.nB + nc3[j]);
         }
-        // cL: position of each level-1 coarse DOF of subdomain i inside L of its subregion
-        std::vector<int32_t> cL(c_off[nsub]);
-        {
-            std::vector<int32_t> pos(c->nC, -1);
-            for (int j = 0; j < nsr; ++j) {
-                const auto &L = st.sr[j].L;
-                for (size_t a = 0; a < L.size(); ++a) pos[L[a]] = (int32_t)a;
-                for (int32_t i : st.sr[j].subs)
-                    for (int q = 0; q < nc[i]; ++q) cL[c_off[i] + q] = pos[st.sub[i].cidx[q]];
-                for (size_t a = 0; a < L.size(); ++a) pos[L[a]] = -1;
-            }
-        }
+        if ((size_t)c->max_nL * 8 > 65536) return fail(BDDC_EINVAL, "a subregion has too many coarse DOFs");
         if ((rc = dupload(c, &c->d_nL, nL)) || (rc = dupload(c, &c->d_nI2, nI2)) || (rc = dupload(c, &c->d_nc3, nc3)) ||
             (rc = dupload(c, &c->d_L_off, L_off)) || (rc = dupload(c, &c->d_I2_off, I2_off)) ||
             (rc = dupload(c, &c->d_B2_off, B2_off)) || (rc = dupload(c, &c->d_C3_off, C3_off)) ||
             (rc = dupload(c, &c->d_L, Lall)) || (rc = dupload(c, &c->d_g2, g2all)) || (rc = dupload(c, &c->d_c3, c3all)) ||
-            (rc = dupload(c, &c->d_pos_sr, pos_sr)) || (rc = dupload(c, &c->d_sr_of_sub, sr_of_sub)) ||
-            (rc = dupload(c, &c->d_K2_off, K2_off)) || (rc = dupload(c, &c->d_N2_off, N2_off)) ||
-            (rc = dupload(c, &c->d_P2_off, P2_off)) || (rc = dupload(c, &c->d_cL, cL)))
+            (rc = dupload(c, &c->d_pos_sr, pos_sr)) || (rc = dupload(c, &c->d_K2_off, K2_off)) ||
+            (rc = dupload(c, &c->d_N2_off, N2_off)) || (rc = dupload(c, &c->d_P2_off, P2_off)))
             return rc;
-        // level-2 interface assembly lists and level-3 lists
+        // level-2 interface assembly lists, owners, level-3 lists
         {
             std::vector<std::pair<int64_t, int32_t>> pr;
             for (int j = 0; j < nsr; ++j)
                 for (int k = 0; k < st.sr[j].nB; ++k) pr.push_back({st.sr[j].g2[k], B2_off[j] + k});
             std::vector<int32_t> ptr, idx;
             build_csr((int64_t)st.gamma2.size(), pr, ptr, idx);
-            if ((rc = dupload(c, &c->d_asm2_ptr, ptr)) || (rc = dupload(c, &c->d_asm2_idx, idx))) return rc;
+            std::vector<uint8_t> own2(B2_off[nsr], 0);
+            for (size_t gi = 0; gi + 1 < ptr.size(); ++gi)
+                if (ptr[gi + 1] > ptr[gi]) own2[idx[ptr[gi]]] = 1;
+            if ((rc = dupload(c, &c->d_asm2_ptr, ptr)) || (rc = dupload(c, &c->d_asm2_idx, idx)) ||
+                (rc = dupload(c, &c->d_own2, own2)))
+                return rc;
             pr.clear();
             for (int j = 0; j < nsr; ++j)
                 for (int q = 0; q < nc3[j]; ++q) pr.push_back({st.sr[j].c3[q], C3_off[j] + q});
@@ -947,6 +1190,7 @@ static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *
             if ((rc = dupload(c, &ds1, s1)) || (rc = dupload(c, &ds2, s2)) || (rc = dupload(c, &dsd, sd)) ||
                 (rc = dupload(c, &dcn, cn)) || (rc = dupload(c, &dcp, cp)) || (rc = dupload(c, &dpt, pt)))
                 return rc;
+            set_sweep_smem_limit((size_t)std::max({max_nloc, max_sad, c->max_nL, max_sad2, c->n3, 1}) * 8);
             launch_sweep(ds1, nsr, c->max_nL, c->d_status, s);
             launch_build_saddle(dsd, nsr, s);
             launch_sweep(ds2, nsr, max_sad2, c->d_status, s);
@@ -967,7 +1211,8 @@ static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *
             std::vector<int32_t> ptr, idx;
             build_csr((int64_t)n * n, pr, ptr, idx);
             int32_t *dp, *di;
-            if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) || (rc = dalloc(c, &c->d_K3inv, (size_t)n * n)))
+            if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) ||
+                (rc = dalloc(c, &c->d_K3inv, (size_t)std::max(1, n * n))))
                 return rc;
             launch_gather_sum((int64_t)n * n, dp, di, d_K3loc, c->d_K3inv, s);
             std::vector<SweepDesc> sd{SweepDesc{c->d_K3inv, n, n, 0, n, n}};
@@ -983,7 +1228,6 @@ static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *
             (rc = dalloc(c, &c->d_rB2, (size_t)B2_off[nsr])) || (rc = dalloc(c, &c->d_u2, (size_t)B2_off[nsr])) ||
             (rc = dalloc(c, &c->d_c3loc, (size_t)C3_off[nsr])) || (rc = dalloc(c, &c->d_u3, (size_t)std::max(1, c->n3))))
             return rc;
-        c->smem_prol = (size_t)(c->max_nc + c->max_nL + 1) * 8;
     }
     {
         int32_t st_h = 0;
@@ -995,41 +1239,55 @@ static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *
     const int ng = c->n_gamma;
     c->ld = ng;
     c->R = c->opts.recycle_R;
+    c->kmax = kmax_bucket(c->R);
     c->save_cap = c->R > 0 ? c->opts.save_cap : 0;
     c->hist_cap = c->opts.max_it + 2;
-    const size_t nblk = (size_t)(ng + 255) / 256;
-    const size_t npart = std::max({nblk * (RMAX + 1), (size_t)nsub + 1, (size_t)256 * RMAX * RMAX});
+    c->vgrid = std::max(1, std::min(VGRID, (ng + 255) / 256));
+    const int gram_nb = std::max(1, std::min(256, (ng + 1023) / 1024));
     if ((rc = dalloc(c, &c->d_b, ng)) || (rc = dalloc(c, &c->d_x, ng)) || (rc = dalloc(c, &c->d_r, ng)) ||
         (rc = dalloc(c, &c->d_z, ng)) || (rc = dalloc(c, &c->d_p, ng)) || (rc = dalloc(c, &c->d_tmp, ng)) ||
-        (rc = dalloc(c, &c->d_locq, (size_t)b_off[nsub])) || (rc = dalloc(c, &c->d_locu, (size_t)b_off[nsub])) ||
-        (rc = dalloc(c, &c->d_locc, (size_t)std::max<int64_t>(1, c_off[nsub]))) ||
-        (rc = dalloc(c, &c->d_yI, (size_t)std::max<int64_t>(1, i_off[nsub]))) || (rc = dalloc(c, &c->d_partial, npart)) ||
+        (rc = dalloc(c, &c->d_locq, (size_t)b_off[nsub])) ||
+        (rc = dalloc(c, &c->d_yI, (size_t)std::max<int64_t>(1, i_off[nsub]))) ||
+        (rc = dalloc(c, &c->d_rr, (size_t)c->vgrid)) || (rc = dalloc(c, &c->d_bbp, (size_t)c->vgrid)) ||
+        (rc = dalloc(c, &c->d_zp, (size_t)c->vgrid * (RMAX + 1))) ||
+        (rc = dalloc(c, &c->d_wp, (size_t)c->vgrid * (RMAX + 1))) ||
+        (rc = dalloc(c, &c->d_dotS, (size_t)c->opS.dev.n_items)) ||
+        (rc = dalloc(c, &c->d_gp, (size_t)gram_nb * RMAX * RMAX)) ||
         (rc = dalloc(c, &c->d_ctl, 1)) || (rc = dalloc(c, &c->d_ahist, c->hist_cap)) ||
         (rc = dalloc(c, &c->d_dhist, c->hist_cap)) || (rc = dalloc(c, &c->d_rhohist, c->hist_cap)) ||
         (rc = dalloc(c, &c->d_bhist, c->hist_cap)) || (rc = dalloc(c, &c->d_reshist, c->hist_cap)) ||
-        (rc = dalloc(c, &c->d_muhist, (size_t)c->hist_cap * RMAX)) || (rc = dalloc(c, &c->d_Lc, RMAX * RMAX)) ||
-        (rc = dalloc(c, &c->d_G, RMAX * RMAX)))
+        (rc = dalloc(c, &c->d_muhist, (size_t)c->hist_cap * RMAX)) || (rc = dalloc(c, &c->d_WAWinv, RMAX * RMAX)))
         return rc;
     HIPCHK(hipMemsetAsync(c->d_x, 0, ng * sizeof(double), s));
     HIPCHK(hipMemsetAsync(c->d_p, 0, ng * sizeof(double), s));
     HIPCHK(hipMemsetAsync(c->d_ctl, 0, sizeof(Ctl), s));
     HIPCHK(hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
-    if (c->R > 0) {
-        const size_t cols = (size_t)c->R;
-        const int ymax = (c->R + c->save_cap) * ((c->R + 7) / 8 * 8);
+    HIPCHK(hipHostMalloc((void **)&c->h_ctl_init, sizeof(Ctl), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c->h_flags, sizeof(int32_t) * (GRAPH_INFLIGHT + 2), hipHostMallocDefault));
+    c->h_zero = c->h_flags + GRAPH_INFLIGHT + 1;
+    {
+        // W, AW always exist (k = 0 columns are never read); the recycling
+        // buffers only with R > 0
+        const size_t cols = (size_t)std::max(1, c->R);
+        const int ymax = std::max((c->R + c->save_cap) * ((c->R + 7) / 8 * 8), RMAX * RMAX);
         if ((rc = dalloc(c, &c->d_W, cols * ng)) || (rc = dalloc(c, &c->d_AW, cols * ng)) ||
-            (rc = dalloc(c, &c->d_Wn, cols * ng)) || (rc = dalloc(c, &c->d_AWn, cols * ng)) ||
-            (rc = dalloc(c, &c->d_P, (size_t)c->save_cap * ng)) || (rc = dalloc(c, &c->d_AP, (size_t)c->save_cap * ng)) ||
             (rc = dalloc(c, &c->d_Y, (size_t)ymax)))
             return rc;
+        if (c->R > 0 && ((rc = dalloc(c, &c->d_Wn, cols * ng)) || (rc = dalloc(c, &c->d_AWn, cols * ng)) ||
+                         (rc = dalloc(c, &c->d_P, (size_t)std::max(1, c->save_cap) * ng)) ||
+                         (rc = dalloc(c, &c->d_AP, (size_t)std::max(1, c->save_cap) * ng))))
+            return rc;
     }
+    HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    for (auto &e : c->gev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // element data for the adjoint gradient
     {
         std::vector<double> ch(st.n_elem, 0.0);
         std::vector<uint8_t> keep(st.n_elem, 1);
         for (int64_t e = 0; e < st.n_elem; ++e) {
-            ch[e] = coef[e] * st.h;
-            if (mesh->elem_keep) keep[e] = mesh->elem_keep[e] ? 1 : 0;
+            const bool kept = !mesh->elem_keep || mesh->elem_keep[e];
+            ch[e] = kept ? coef[e] * st.h : 0.0;
+            keep[e] = kept ? 1 : 0;
         }
         if ((rc = dupload(c, &c->d_coefh, ch)) || (rc = dupload(c, &c->d_keep, keep)) ||
             (rc = dupload(c, &c->d_free, st.free_node)))
@@ -1038,6 +1296,10 @@ static int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *
     HIPCHK(hipStreamSynchronize(s));
     return 0;
 }
+
+}  // namespace
+
+extern "C" {
 
 int bddc_setup(const bddc_mesh *mesh, const bddc_partition *part, const double *coef, const bddc_opts *opts,
                void *hip_stream, bddc_ctx **out) {
@@ -1051,7 +1313,7 @@ int bddc_setup(const bddc_mesh *mesh, const bddc_partition *part, const double *
     if (o.local_prec != 64 && o.local_prec != 32 && o.local_prec != 16) { delete c; return fail(BDDC_EINVAL, "local_prec must be 64, 32 or 16"); }
     if (o.recycle_R < 0 || o.recycle_R > RMAX) { delete c; return fail(BDDC_EINVAL, "recycle_R out of range [0, 64]"); }
     if (o.recycle_strategy < 1 || o.recycle_strategy > 4) { delete c; return fail(BDDC_EINVAL, "recycle_strategy must be 1..4"); }
-    if (o.max_it <= 0 || o.save_cap < 0 || o.save_cap > 4096) { delete c; return fail(BDDC_EINVAL, "bad max_it or save_cap"); }
+    if (o.max_it <= 0 || o.max_it > 100000 || o.save_cap < 0 || o.save_cap > 4096) { delete c; return fail(BDDC_EINVAL, "bad max_it or save_cap"); }
     if (!(o.constraints & (BDDC_CORNERS | BDDC_FACES | BDDC_EDGES))) { delete c; return fail(BDDC_EINVAL, "no constraints"); }
     int rc = setup_impl(c, mesh, part, coef);
     if (rc) {
@@ -1074,17 +1336,15 @@ int dpcg_solve(bddc_ctx *c, const double *rhs_seq, int32_t n_rhs, double rtol, d
         int rc = solve_one(c, rhs_seq + (size_t)k * c->n_nodes, x_seq + (size_t)k * c->n_nodes, rtol, true, &it, &rr);
         if (iters) iters[k] = it;
         if (true_relres) true_relres[k] = rr;
-        if (rc) { if (c->timing) flush_timing(c); return rc; }
+        if (rc) { if (c->timing) { (void)hipStreamSynchronize(c->stream); flush_timing(c); } return rc; }
         {
             TScope ts(c, TK_REC);
             rc = do_recycle(c);
         }
-        if (rc) { if (c->timing) flush_timing(c); return rc; }
+        if (rc) { if (c->timing) { (void)hipStreamSynchronize(c->stream); flush_timing(c); } return rc; }
     }
-    if (c->timing) {
-        hipStreamSynchronize(c->stream);
-        flush_timing(c);
-    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->timing) flush_timing(c);
     return 0;
 }
 
@@ -1117,7 +1377,7 @@ int bddc_adjoint_grad(bddc_ctx *c, const double *dLdu_seq, int32_t n_rhs, const 
     int rc = dalloc(c, &xsave, c->n_gamma);
     if (rc) return rc;
     launch_copy(c->n_gamma, c->d_x, xsave, c->stream);
-    HIPCHK(hipMemsetAsync(c->d_x, 0, c->n_gamma * sizeof(double), c->stream));
+    launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
     for (int k = 0; k < n_rhs && rc == 0; ++k)
         rc = solve_one(c, dLdu_seq + (size_t)k * c->n_nodes, grad_rhs_seq + (size_t)k * c->n_nodes, rtol, false, nullptr, nullptr);
     c->have_solve = false;
@@ -1129,15 +1389,18 @@ int bddc_adjoint_grad(bddc_ctx *c, const double *dLdu_seq, int32_t n_rhs, const 
         g.lam = grad_rhs_seq; g.u = u_seq; g.grad = grad_logcoef;
         launch_elem_grad(g, c->stream);
     }
-    hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     dfree(c, xsave);
     return rc;
 }
 
 int bddc_apply_schur(bddc_ctx *c, const double *p, double *q) {
     if (!c || !p || !q) return fail(BDDC_EINVAL, "null argument");
-    run_schur(c, p, 0);
-    launch_gather_sum(c->n_gamma, c->d_asm_ptr, c->d_asm_idx, c->d_locq, q, c->stream);
+    run_schur(c, p, false, false);
+    ResidArgs a{};
+    a.n = c->n_gamma; a.want_wtr = 0; a.q = gather_of(c, c->opS, false); a.b = nullptr; a.out = q;
+    a.W = c->d_W; a.ld = c->ld; a.ctl = c->d_ctl; a.part = c->d_wp;
+    launch_resid(a, 0, c->vgrid, c->stream);
     HIPCHK(hipStreamSynchronize(c->stream));
     return 0;
 }
@@ -1146,7 +1409,7 @@ int bddc_apply_precond(bddc_ctx *c, const double *r, double *z) {
     if (!c || !r || !z) return fail(BDDC_EINVAL, "null argument");
     int rc = set_done(c, 0);
     if (rc) return rc;
-    run_precond(c, r, z, false, true, false);
+    run_precond(c, r, z, 0, false, false, false);
     HIPCHK(hipStreamSynchronize(c->stream));
     return 0;
 }
@@ -1214,13 +1477,20 @@ int bddc_ritz_values(const bddc_ctx *c, double *theta, int32_t cap, int32_t *cou
 
 void bddc_destroy(bddc_ctx *c) {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
-    else hipDeviceSynchronize();
-    for (void *p : c->allocs) hipFree(p);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (auto &e : c->gev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
-    if (c->h_ctl) hipHostFree(c->h_ctl);
-    for (auto &p : c->pending) { hipEventDestroy(p.second.first); hipEventDestroy(p.second.second); }
-    for (auto e : c->ev_pool) hipEventDestroy(e);
+    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+    if (c->h_ctl_init) (void)hipHostFree(c->h_ctl_init);
+    if (c->h_flags) (void)hipHostFree(c->h_flags);
+    for (auto &p : c->pending) { (void)hipEventDestroy(p.second.first); (void)hipEventDestroy(p.second.second); }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
 

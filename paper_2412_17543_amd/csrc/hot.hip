@@ -1,0 +1,769 @@
+// gfx950 kernels of one deflated-PCG iteration (Algorithm 1) preconditioned
+// by two- or three-level BDDC (Section 3.2), on the interface problem of
+// Section 3.1.
+//
+// One iteration is a fixed chain of kernels that can be captured once as a
+// graph and replayed:
+//   k_symv (S)   q_i = S_i p_i                      Alg. 1 line 9 (A p)
+//   k_update     alpha, x += alpha p, r -= alpha q  lines 9-11
+//   k_symv (N)   stopping test (Section 5); u_i = D N_i D r_i, c_i = (D Phi_i)^T r_i
+//   coarse       two levels: k_coarse2; three levels: k_l2_a, k_l2_b, k_l3, k_l2_d
+//   k_zasm       z = sum_i R_i^T (u_i + D Phi_i u_C), r^T z, (AW)^T z   line 13
+//   k_pupd       beta, mu, p = z + beta p - W mu    lines 14-16
+// A converged or failed solve sets ctl->done; every later kernel returns at
+// once, so replaying more iterations than needed is harmless.
+//
+// Reductions never cross blocks inside a kernel: a producer writes one
+// partial per block (or per work item) and every block of the consuming
+// kernel sums them in index order, so all blocks see bitwise the same
+// scalars and every run gives the same result.
+#include <hip/hip_runtime.h>
+
+#include "devutil.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace bddc {
+
+using dev::block_sum;
+using dev::wave_sum;
+using dev::wave_sum_strided;
+
+namespace {
+
+template <typename T>
+struct Acc {
+    using type = double;
+};
+template <>
+struct Acc<float> {
+    using type = float;
+};
+template <>
+struct Acc<uint16_t> {
+    using type = float;
+};
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef unsigned int uvec2 __attribute__((ext_vector_type(2)));
+
+// The four values lane l holds of a 16x16 tile: rows 4*(l/16)+i, column l%16
+// (element order of tile_index).
+template <typename T>
+struct Frag;
+template <>
+struct Frag<double> {
+    dvec2 a, b;
+    __device__ __forceinline__ void load(const double *t, int l) {
+        a = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(t) + l);
+        b = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(t) + 64 + l);
+    }
+    __device__ __forceinline__ void get(double v[4]) const { v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; }
+};
+template <>
+struct Frag<float> {
+    fvec4 a;
+    __device__ __forceinline__ void load(const float *t, int l) {
+        a = __builtin_nontemporal_load(reinterpret_cast<const fvec4 *>(t) + l);
+    }
+    __device__ __forceinline__ void get(float v[4]) const { v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; }
+};
+template <>
+struct Frag<uint16_t> {
+    uvec2 a;
+    __device__ __forceinline__ void load(const uint16_t *t, int l) {
+        a = __builtin_nontemporal_load(reinterpret_cast<const uvec2 *>(t) + l);
+    }
+    __device__ __forceinline__ void get(float v[4]) const {
+        v[0] = dev::bf16_to_f32(a.x & 0xffffu);
+        v[1] = dev::bf16_to_f32(a.x >> 16);
+        v[2] = dev::bf16_to_f32(a.y & 0xffffu);
+        v[3] = dev::bf16_to_f32(a.y >> 16);
+    }
+};
+
+__device__ __forceinline__ double to_d(double v) { return v; }
+__device__ __forceinline__ double to_d(float v) { return (double)v; }
+__device__ __forceinline__ double to_d(uint16_t v) { return (double)dev::bf16_to_f32(v); }
+
+// Sum over the owners of assembled entry t of all partial products of each
+// owner (fixed order: owners as listed, items in increasing order).
+__device__ __forceinline__ double gather_sum(const Gather &G, int64_t t) {
+    double s = 0.0;
+    for (int e = G.ptr[t]; e < G.ptr[t + 1]; ++e) {
+        const int pos = G.idx[e];
+        const int i = G.pos_sub[pos];
+        const int k = pos - G.off[i];
+        const int n = G.len[i], C = G.nchunk[i];
+        const double *p = G.part + G.base[i] + k;
+        for (int c = 0; c < C; ++c) s += p[(int64_t)c * n];
+    }
+    return s;
+}
+
+// Stopping test of Section 5 (eq. stopping_rhs, or eq. stopping_residual with
+// stop_rule 1) on the residual whose per-block ||r||^2 partials are in
+// a.rr_part.  test 2: the first test of a solve, on r_0 (zero iterations
+// allowed); test 1: after the residual update of direction j.  Every block
+// evaluates it identically; block 0 records the outcome.
+__device__ bool stop_test(const SymvArgs &a) {
+    __shared__ int s_stop;
+    Ctl *c = a.ctl;
+    if (threadIdx.x < 64) {
+        const double rr = wave_sum_strided(a.rr_part, a.rr_n, 1);
+        const bool first = a.test == 2;
+        double bb = 0.0, denom2;
+        if (first) {
+            bb = wave_sum_strided(a.bb_part, a.bb_n, 1);
+            denom2 = a.stop_rule == 0 ? bb : rr;
+        } else {
+            denom2 = c->denom2;
+        }
+        const int iter = first ? 0 : c->j + 1;
+        const bool conv = (first && bb == 0.0) || rr < c->rtol2 * denom2;
+        const bool bad = !isfinite(rr);
+        const bool maxed = !first && iter >= a.max_it;
+        const bool stop = conv || bad || maxed;
+        if (threadIdx.x == 0) {
+            s_stop = stop ? 1 : 0;
+            if (blockIdx.x == 0) {
+                c->rr = rr;
+                if (first) {
+                    c->bb = bb;
+                    c->r0r0 = rr;
+                    c->denom2 = denom2;
+                    if (bb == 0.0) c->zero_rhs = 1;
+                } else {
+                    c->iter = iter;
+                }
+                if (a.res_hist && iter < a.hist_cap) a.res_hist[iter] = rr;
+                if (bad) c->status = BDDC_EBREAKDOWN;
+                else if (!conv && maxed) c->status = BDDC_ENOTCONV;
+                if (stop) c->done = 1;
+            }
+        }
+    }
+    __syncthreads();
+    return s_stop != 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batched symmetric product over a work list (one item per block):
+//   y_i = Op_i x_i with x_i = x[gB_i]    (Op packed upper triangle)
+//   c_i = Phi_i^T x_i                    (coarse-basis tiles, when present)
+// Each item covers a contiguous tile range of one subdomain, split evenly
+// over the block's waves.  Lane l of a wave holds column l%16 and rows
+// 4(l/16)..+3 of a tile: the direct product y_I += T x_J accumulates in
+// registers along the tile row, the transposed product y_J += T^T x_I needs
+// one two-step butterfly per tile.  Every wave accumulates in its own LDS
+// vector; the block sums them in wave order and writes the item's partial
+// vector (all nB entries) and, optionally, the partial x_i^T y_i.
+// ---------------------------------------------------------------------------
+template <typename T, int NW, int U>
+__global__ void __launch_bounds__(NW * 64) k_symv(SymvArgs a) {
+    using ACC = typename Acc<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[16];
+    if (a.gated && a.ctl->done) return;
+    if (a.test && stop_test(a)) return;
+    const SymvItem it = a.op.items[blockIdx.x];
+    const int sub = it.sub;
+    const int n = a.op.nB[sub];
+    const int nt = (n + TILE - 1) / TILE;
+    const int ncs = a.op.nc ? a.op.nc[sub] : 0;
+    const int ntc = (ncs + TILE - 1) / TILE;
+    const int npad = nt * TILE;
+    ACC *xs = reinterpret_cast<ACC *>(smem_raw);
+    ACC *yw = xs + npad;
+    ACC *cw = yw + NW * npad;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g4 = 4 * (l >> 4), cl = l & 15;
+    const int boff = a.op.b_off[sub];
+    for (int k = tid; k < npad; k += NW * 64) xs[k] = k < n ? (ACC)a.x[a.op.gB[boff + k]] : (ACC)0;
+    for (int k = tid; k < NW * npad; k += NW * 64) yw[k] = (ACC)0;
+    for (int k = tid; k < NW * ntc * TILE; k += NW * 64) cw[k] = (ACC)0;
+    __syncthreads();
+
+    const T *tb = reinterpret_cast<const T *>(a.op.tiles) + a.op.t_off[sub];
+    const int span = it.t1 - it.t0;
+    const int w0 = it.t0 + (int)((int64_t)span * w / NW);
+    const int w1 = it.t0 + (int)((int64_t)span * (w + 1) / NW);
+    ACC *myy = yw + w * npad;
+    ACC *myc = cw + w * ntc * TILE;
+    if (w0 < w1) {
+        int I = 0, rs = 0;
+        while (rs + (nt - I + ntc) <= w0) { rs += nt - I + ntc; ++I; }
+        int J = I + (w0 - rs);
+        ACC xi[4], ra[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { xi[q] = xs[I * TILE + g4 + q]; ra[q] = (ACC)0; }
+        for (int t = w0; t < w1; t += U) {
+            Frag<T> f[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (t + u < w1) f[u].load(tb + (int64_t)(t + u) * 256, l);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (t + u >= w1) break;
+                ACC v[4];
+                f[u].get(v);
+                if (J < nt) {
+                    const ACC xj = xs[J * TILE + cl];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) ra[q] += v[q] * xj;
+                }
+                if (J != I) {
+                    ACC s = v[0] * xi[0] + v[1] * xi[1] + v[2] * xi[2] + v[3] * xi[3];
+                    s += __shfl_xor(s, 16);
+                    s += __shfl_xor(s, 32);
+                    if (l < 16) {
+                        ACC *dst = (J < nt) ? (myy + J * TILE) : (myc + (J - nt) * TILE);
+                        dst[cl] += s;
+                    }
+                }
+                if (++J == nt + ntc) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        ACC s = ra[q];
+                        s += __shfl_xor(s, 1);
+                        s += __shfl_xor(s, 2);
+                        s += __shfl_xor(s, 4);
+                        s += __shfl_xor(s, 8);
+                        if (cl == 0) myy[I * TILE + g4 + q] += s;
+                        ra[q] = (ACC)0;
+                    }
+                    ++I;
+                    J = I;
+                    if (I < nt) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) xi[q] = xs[I * TILE + g4 + q];
+                    }
+                }
+            }
+        }
+        if (J != I) {   // flush a partly processed tile row
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ACC s = ra[q];
+                s += __shfl_xor(s, 1);
+                s += __shfl_xor(s, 2);
+                s += __shfl_xor(s, 4);
+                s += __shfl_xor(s, 8);
+                if (cl == 0) myy[I * TILE + g4 + q] += s;
+            }
+        }
+    }
+    __syncthreads();
+
+    double dot = 0.0;
+    double *yp = a.ypart + a.op.pb[sub] + (int64_t)it.c * n;
+    for (int k = tid; k < n; k += NW * 64) {
+        ACC s = (ACC)0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) s += yw[q * npad + k];
+        const double y = (double)s;
+        yp[k] = y;
+        dot += (double)xs[k] * y;
+    }
+    if (ncs) {
+        double *cp = a.cpart + a.op.cb[sub] + (int64_t)it.c * ncs;
+        for (int k = tid; k < ncs; k += NW * 64) {
+            ACC s = (ACC)0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) s += cw[q * ntc * TILE + k];
+            cp[k] = (double)s;
+        }
+    }
+    if (a.dot) {
+        dot = block_sum(dot, red);
+        if (tid == 0) a.dot[blockIdx.x] = dot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 1 lines 9-11: alpha = rho_j / p^T A p (every block sums the partials
+// of the Schur product), q = sum_i R_i^T q_i, x += alpha p, r -= alpha q;
+// per-block ||r||^2; the product is kept as AP_j for recycling.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_update(UpdArgs a) {
+    __shared__ double red[16];
+    __shared__ double s_alpha;
+    __shared__ int s_bad;
+    Ctl *c = a.ctl;
+    if (c->done) return;
+    const int j = c->j;
+    if (threadIdx.x < 64) {
+        const double pAp = wave_sum_strided(a.dot, a.dot_n, 1);
+        if (threadIdx.x == 0) {
+            const double alpha = (j < a.hist_cap ? a.rho_hist[j] : 0.0) / pAp;
+            const bool bad = !(pAp > 0.0) || !isfinite(alpha) || j >= a.hist_cap;
+            s_alpha = alpha;
+            s_bad = bad ? 1 : 0;
+            if (blockIdx.x == 0) {
+                c->pAp = pAp;
+                c->alpha = alpha;
+                if (j < a.hist_cap) { a.d_hist[j] = pAp; a.a_hist[j] = alpha; }
+                if (bad) { c->status = BDDC_EBREAKDOWN; c->done = 1; }
+            }
+        }
+    }
+    __syncthreads();
+    if (s_bad) return;
+    const double alpha = s_alpha;
+    const bool rec = a.AP && c->record && j < a.cap;
+    double rr = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
+        const double q = gather_sum(a.q, g);
+        const double xi = a.x[g] + alpha * a.p[g];
+        const double ri = a.r[g] - alpha * q;
+        a.x[g] = xi;
+        a.r[g] = ri;
+        rr += ri * ri;
+        if (rec) a.AP[(int64_t)j * a.ld + g] = q;
+    }
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) a.rr_part[blockIdx.x] = rr;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 1 line 13, assembly: z = sum_i R_i^T D_i (u_i + Phi_i u_C) (eq.
+// averaging_subdomain_solves; D is folded into the stored N_i and Phi_i),
+// with the coarse prolongation done per owner entry from the row-major
+// coarse-basis copy.  Per-block partials of r^T z and (AW)^T z (line 15).
+// With `advance`, block 0 moves the direction index to j + 1 (no block of this
+// kernel reads it).
+// ---------------------------------------------------------------------------
+template <typename T, int KM>
+__global__ void __launch_bounds__(256) k_zasm(ZasmArgs a) {
+    __shared__ double wacc[4][KM + 1];
+    Ctl *c = a.ctl;
+    if (a.gated && c->done) return;
+    if (a.advance && blockIdx.x == 0 && threadIdx.x == 0) c->j = c->j + 1;
+    const int k = a.part ? c->k : 0;
+    const T *phir = reinterpret_cast<const T *>(a.phir);
+    double acc[KM + 1];
+#pragma unroll
+    for (int q = 0; q <= KM; ++q) acc[q] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
+        double z = 0.0;
+        const Gather &G = a.u;
+        for (int e = G.ptr[g]; e < G.ptr[g + 1]; ++e) {
+            const int pos = G.idx[e];
+            const int i = G.pos_sub[pos];
+            const int kk = pos - a.b_off[i];
+            const int n = a.nB[i], C = G.nchunk[i];
+            const double *p = G.part + G.base[i] + kk;
+            double u = 0.0;
+            for (int cc = 0; cc < C; ++cc) u += p[(int64_t)cc * n];
+            if (a.uC) {
+                const int nci = a.nc[i];
+                const T *ph = phir + a.phr_off[i] + (int64_t)kk * nci;
+                const int32_t *ci = a.cidx + a.c_off[i];
+                for (int q = 0; q < nci; ++q) u += to_d(ph[q]) * a.uC[ci[q]];
+            }
+            z += u;
+        }
+        a.z[g] = z;
+        if (a.part) {
+            acc[0] += a.r[g] * z;
+#pragma unroll
+            for (int q = 0; q < KM; ++q)
+                if (q < k) acc[1 + q] += a.AW[(int64_t)q * a.ld + g] * z;
+        }
+    }
+    if (!a.part) return;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q <= KM; ++q) {
+        if (q <= k) {
+            const double v = wave_sum(acc[q]);
+            if (l == 0) wacc[w][q] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x <= k) {
+        double s = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += wacc[q][threadIdx.x];
+        a.part[(int64_t)blockIdx.x * (RMAX + 1) + threadIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 1 lines 14-16 (line 7 when `first`): every block sums the k_zasm
+// partials into rho = r^T z and t = (AW)^T z, mu = (W^T A W)^{-1} t,
+// beta = rho / rho_prev; p = z + beta p - W mu.  Block 0 records rho, beta,
+// mu for the recycling step.  `hist_only` records without updating p (the
+// extra preconditioner application after convergence).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
+    __shared__ double tv[RMAX + 1];
+    __shared__ double mu[RMAX];
+    __shared__ double s_beta;
+    __shared__ int s_bad;
+    Ctl *c = a.ctl;
+    if (a.gated && c->done) return;
+    const int k = c->k, j = c->j;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int col = w; col <= k; col += nw) {
+        const double s = wave_sum_strided(a.zpart + col, a.zpart_n, RMAX + 1);
+        if (l == 0) tv[col] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double s = 0.0;
+        for (int q = 0; q < k; ++q) s += a.WAWinv[threadIdx.x * k + q] * tv[1 + q];
+        mu[threadIdx.x] = s;
+    }
+    if (threadIdx.x == 0) {
+        const double rho = tv[0];
+        const double beta = a.first ? 0.0 : rho / a.rho_hist[j - 1];
+        const bool bad = !(rho > 0.0) || !isfinite(rho) || !isfinite(beta);
+        s_beta = beta;
+        s_bad = bad ? 1 : 0;
+        if (blockIdx.x == 0) {
+            if (j < a.hist_cap) a.rho_hist[j] = rho;
+            if (!a.first && j >= 1 && j - 1 < a.hist_cap) a.b_hist[j - 1] = beta;
+            if (bad && !a.hist_only) { c->status = BDDC_EBREAKDOWN; c->done = 1; }
+        }
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x < k && j < a.hist_cap) a.mu_hist[(int64_t)j * RMAX + threadIdx.x] = mu[threadIdx.x];
+    if (a.hist_only || s_bad) return;
+    const double beta = s_beta;
+    const bool rec = a.P && c->record && j < a.cap;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
+        double p = a.z[g] + beta * a.p[g];
+        for (int q = 0; q < k; ++q) p -= a.W[(int64_t)q * a.ld + g] * mu[q];
+        a.p[g] = p;
+        if (rec) a.P[(int64_t)j * a.ld + g] = p;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// out = b - sum_i R_i^T q_i (initial or true residual; out = the assembled
+// product when b is null); per-block partials of ||out||^2 and, with
+// want_wtr, of W^T out (Alg. 1 line 3).
+// ---------------------------------------------------------------------------
+template <int KM>
+__global__ void __launch_bounds__(256) k_resid(ResidArgs a) {
+    __shared__ double wacc[4][KM + 1];
+    const int k = a.want_wtr ? a.ctl->k : 0;
+    double acc[KM + 1];
+#pragma unroll
+    for (int q = 0; q <= KM; ++q) acc[q] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
+        const double q = gather_sum(a.q, g);
+        const double r = a.b ? a.b[g] - q : q;
+        a.out[g] = r;
+        acc[0] += r * r;
+#pragma unroll
+        for (int q = 0; q < KM; ++q)
+            if (q < k) acc[1 + q] += a.W[(int64_t)q * a.ld + g] * r;
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q <= KM; ++q) {
+        if (q <= k) {
+            const double v = wave_sum(acc[q]);
+            if (l == 0) wacc[w][q] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x <= k) {
+        double s = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += wacc[q][threadIdx.x];
+        a.part[(int64_t)blockIdx.x * (RMAX + 1) + threadIdx.x] = s;
+    }
+}
+
+// Alg. 1 lines 3-4: gamma = (W^T A W)^{-1} W^T r (every block, from the
+// k_resid partials); x += W gamma; r -= AW gamma (= b - A x_0); ||r||^2.
+__global__ void __launch_bounds__(256) k_defl_init(DeflArgs a) {
+    __shared__ double tv[RMAX + 1];
+    __shared__ double gam[RMAX];
+    __shared__ double red[16];
+    const int k = a.ctl->k;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int col = 1 + w; col <= k; col += nw) {
+        const double s = wave_sum_strided(a.wpart + col, a.wpart_n, RMAX + 1);
+        if (l == 0) tv[col] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double s = 0.0;
+        for (int q = 0; q < k; ++q) s += a.WAWinv[threadIdx.x * k + q] * tv[1 + q];
+        gam[threadIdx.x] = s;
+    }
+    __syncthreads();
+    double rr = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
+        double x = a.x[g], r = a.r[g];
+        for (int q = 0; q < k; ++q) {
+            x += a.W[(int64_t)q * a.ld + g] * gam[q];
+            r -= a.AW[(int64_t)q * a.ld + g] * gam[q];
+        }
+        a.x[g] = x;
+        a.r[g] = r;
+        rr += r * r;
+    }
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) a.rr_part[blockIdx.x] = rr;
+}
+
+__global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
+    for (int c = threadIdx.x; c < a.ncol; c += blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < a.n; ++b) s += a.part[(int64_t)b * a.st + c];
+        a.out[c] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coarse problem (eq. coarse_problem); three levels: the multilevel paragraph
+// of Section 3.2, subdomains acting as the elements of subregions
+// ---------------------------------------------------------------------------
+// Two levels: r_C = sum_i R_Ci^T c_i, u_C = K_C^{-1} r_C with the dense
+// inverse (stored negated by the sweep).  Block b computes rows
+// [64b, 64b + 64), each wave a quarter of the columns.
+__global__ void __launch_bounds__(256) k_coarse2(Coarse2Args a) {
+    extern __shared__ double rs[];
+    __shared__ double part[4][64];
+    if (a.ctl->done) return;
+    for (int q = threadIdx.x; q < a.n; q += blockDim.x) rs[q] = gather_sum(a.rc, q);
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int r = blockIdx.x * 64 + l;
+    const int q0 = (int)((int64_t)a.n * w / 4), q1 = (int)((int64_t)a.n * (w + 1) / 4);
+    double s = 0.0;
+    if (r < a.n)
+        for (int q = q0; q < q1; ++q) s += a.Kneg[(int64_t)q * a.n + r] * rs[q];
+    part[w][l] = s;
+    __syncthreads();
+    if (w == 0 && r < a.n) a.u[r] = -(part[0][l] + part[1][l] + part[2][l] + part[3][l]);
+}
+
+// Level 2, phase A (one block per subregion): the subregion's coarse
+// residual r_L, interior pre-solve v_I = K_II^{-1} r_I and its interface
+// coupling t = K_BI K_II^{-1} r_I (from the swept subregion matrix).
+__global__ void __launch_bounds__(256) k_l2_a(L2Args a) {
+    extern __shared__ double rL[];
+    if (a.ctl->done) return;
+    const int j = blockIdx.x;
+    const int nL = a.nL[j], nI = a.nI2[j];
+    const int loff = a.L_off[j];
+    for (int q = threadIdx.x; q < nL; q += blockDim.x) rL[q] = gather_sum(a.rc, a.L[loff + q]);
+    __syncthreads();
+    const double *K = a.K2 + a.K2_off[j];
+    const int i2 = a.I2_off[j], b2 = a.B2_off[j];
+    for (int q = threadIdx.x; q < nL; q += blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < nI; ++b) s += K[(int64_t)q * nL + b] * rL[b];
+        if (q < nI) a.vI2[i2 + q] = -s;
+        else { a.t2[b2 + q - nI] = s; a.rB2[b2 + q - nI] = rL[q]; }
+    }
+}
+
+// Level 2, phase B (one block per subregion): level-2 interface residual
+// g = r_G - sum_j R_j^T t_j, then u = (D N D) g and c3 = (D Phi)^T g.
+__global__ void __launch_bounds__(256) k_l2_b(L2Args a) {
+    extern __shared__ double gs[];
+    if (a.ctl->done) return;
+    const int j = blockIdx.x;
+    const int nB = a.nL[j] - a.nI2[j];
+    const int b2 = a.B2_off[j];
+    for (int k = threadIdx.x; k < nB; k += blockDim.x) {
+        const int gi = a.g2[b2 + k];
+        double s = a.rB2[b2 + k];
+        for (int t = a.asm2_ptr[gi]; t < a.asm2_ptr[gi + 1]; ++t) s -= a.t2[a.asm2_idx[t]];
+        gs[k] = s;
+    }
+    __syncthreads();
+    const double *N = a.N2 + a.N2_off[j];
+    for (int k = threadIdx.x; k < nB; k += blockDim.x) {
+        double s = 0.0;
+        for (int q = 0; q < nB; ++q) s += N[(int64_t)k * nB + q] * gs[q];
+        a.u2[b2 + k] = s;
+    }
+    const int nc3 = a.nc3[j], c3o = a.C3_off[j];
+    const double *Ph = a.Phi2 + a.P2_off[j];
+    for (int q = threadIdx.x; q < nc3; q += blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < nB; ++k) s += Ph[(int64_t)k * nc3 + q] * gs[k];
+        a.c3loc[c3o + q] = s;
+    }
+}
+
+// Level 3: r3 = sum of the subregion contributions, u3 = K3^{-1} r3 (dense
+// inverse stored negated).  Same row/column split as k_coarse2.
+__global__ void __launch_bounds__(256) k_l3(L3Args a) {
+    extern __shared__ double rs[];
+    __shared__ double part[4][64];
+    if (a.ctl->done) return;
+    for (int q = threadIdx.x; q < a.n; q += blockDim.x) {
+        double s = 0.0;
+        for (int k = a.ptr[q]; k < a.ptr[q + 1]; ++k) s += a.loc[a.idx[k]];
+        rs[q] = s;
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int r = blockIdx.x * 64 + l;
+    const int q0 = (int)((int64_t)a.n * w / 4), q1 = (int)((int64_t)a.n * (w + 1) / 4);
+    double s = 0.0;
+    if (r < a.n)
+        for (int q = q0; q < q1; ++q) s += a.Kneg[(int64_t)q * a.n + r] * rs[q];
+    part[w][l] = s;
+    __syncthreads();
+    if (w == 0 && r < a.n) a.u[r] = -(part[0][l] + part[1][l] + part[2][l] + part[3][l]);
+}
+
+// Level 2, phase D (one block per subregion): level-2 interface solution
+// x_G = sum_j R_j^T (u_j + (D Phi_j) u3) on the subregion's interface, interior
+// post-correction x_I = v_I - T^T x_G; both written to the level-1 coarse
+// solution u_C (an interface DOF by its first-listed subregion only; every
+// subregion computes the same value in the same order).
+__global__ void __launch_bounds__(256) k_l2_d(L2Args a) {
+    extern __shared__ double xg[];
+    if (a.ctl->done) return;
+    const int j = blockIdx.x;
+    const int nL = a.nL[j], nI = a.nI2[j], nB = nL - nI;
+    const int b2 = a.B2_off[j], loff = a.L_off[j];
+    for (int k = threadIdx.x; k < nB; k += blockDim.x) {
+        const int gi = a.g2[b2 + k];
+        double s = 0.0;
+        for (int t = a.asm2_ptr[gi]; t < a.asm2_ptr[gi + 1]; ++t) {
+            const int pos = a.asm2_idx[t];
+            const int jj = a.pos_sr[pos];
+            const int kk = pos - a.B2_off[jj];
+            const int n3j = a.nc3[jj];
+            const double *ph = a.Phi2 + a.P2_off[jj] + (int64_t)kk * n3j;
+            const int32_t *c3 = a.c3 + a.C3_off[jj];
+            double v = a.u2[pos];
+            for (int q = 0; q < n3j; ++q) v += ph[q] * a.u3[c3[q]];
+            s += v;
+        }
+        xg[k] = s;
+        if (a.own2[b2 + k]) a.uC[a.L[loff + nI + k]] = s;
+    }
+    __syncthreads();
+    const double *K = a.K2 + a.K2_off[j];
+    const int i2 = a.I2_off[j];
+    for (int q = threadIdx.x; q < nI; q += blockDim.x) {
+        double s = a.vI2[i2 + q];
+        for (int k = 0; k < nB; ++k) s -= K[(int64_t)(nI + k) * nL + q] * xg[k];
+        a.uC[a.L[loff + q]] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+size_t symv_smem(int prec, int nw, int max_nt, int max_ntc) {
+    const size_t acc = prec == 64 ? 8 : 4;
+    return acc * ((size_t)max_nt * TILE * (1 + nw) + (size_t)nw * max_ntc * TILE);
+}
+
+template <typename T>
+static int set_limit_t(size_t bytes) {
+    const void *f[4] = {(const void *)k_symv<T, 4, 2>, (const void *)k_symv<T, 4, 4>,
+                        (const void *)k_symv<T, 8, 2>, (const void *)k_symv<T, 8, 4>};
+    for (const void *p : f)
+        if (hipFuncSetAttribute(p, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+    return 0;
+}
+
+int set_symv_smem_limit(size_t bytes) {
+    if (set_limit_t<double>(bytes) || set_limit_t<float>(bytes) || set_limit_t<uint16_t>(bytes)) return -1;
+    return 0;
+}
+
+template <typename T>
+static void launch_symv_t(const SymvArgs &a, SymvCfg cfg, size_t smem, hipStream_t s) {
+    const dim3 grid(a.op.n_items);
+    if (cfg.nw == 8) {
+        if (cfg.unroll == 4) hipLaunchKernelGGL((k_symv<T, 8, 4>), grid, dim3(512), smem, s, a);
+        else hipLaunchKernelGGL((k_symv<T, 8, 2>), grid, dim3(512), smem, s, a);
+    } else {
+        if (cfg.unroll == 4) hipLaunchKernelGGL((k_symv<T, 4, 4>), grid, dim3(256), smem, s, a);
+        else hipLaunchKernelGGL((k_symv<T, 4, 2>), grid, dim3(256), smem, s, a);
+    }
+}
+
+void launch_symv(const SymvArgs &a, int prec, SymvCfg cfg, size_t smem, hipStream_t s) {
+    if (a.op.n_items <= 0) return;
+    if (prec == 64) launch_symv_t<double>(a, cfg, smem, s);
+    else if (prec == 32) launch_symv_t<float>(a, cfg, smem, s);
+    else launch_symv_t<uint16_t>(a, cfg, smem, s);
+}
+
+void launch_update(const UpdArgs &a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_update, dim3(grid), dim3(256), 0, s, a);
+}
+
+int kmax_bucket(int k) { return k == 0 ? 0 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
+
+template <typename T>
+static void launch_zasm_t(const ZasmArgs &a, int kmax, int grid, hipStream_t s) {
+    switch (kmax) {
+        case 0: hipLaunchKernelGGL((k_zasm<T, 0>), dim3(grid), dim3(256), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_zasm<T, 8>), dim3(grid), dim3(256), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((k_zasm<T, 16>), dim3(grid), dim3(256), 0, s, a); break;
+        case 32: hipLaunchKernelGGL((k_zasm<T, 32>), dim3(grid), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_zasm<T, 64>), dim3(grid), dim3(256), 0, s, a); break;
+    }
+}
+
+void launch_zasm(const ZasmArgs &a, int prec, int kmax, int grid, hipStream_t s) {
+    if (prec == 64) launch_zasm_t<double>(a, kmax, grid, s);
+    else if (prec == 32) launch_zasm_t<float>(a, kmax, grid, s);
+    else launch_zasm_t<uint16_t>(a, kmax, grid, s);
+}
+
+void launch_pupd(const PupdArgs &a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_pupd, dim3(grid), dim3(256), 0, s, a);
+}
+
+void launch_resid(const ResidArgs &a, int kmax, int grid, hipStream_t s) {
+    switch (kmax) {
+        case 0: hipLaunchKernelGGL(k_resid<0>, dim3(grid), dim3(256), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(k_resid<8>, dim3(grid), dim3(256), 0, s, a); break;
+        case 16: hipLaunchKernelGGL(k_resid<16>, dim3(grid), dim3(256), 0, s, a); break;
+        case 32: hipLaunchKernelGGL(k_resid<32>, dim3(grid), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_resid<64>, dim3(grid), dim3(256), 0, s, a); break;
+    }
+}
+
+void launch_defl_init(const DeflArgs &a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_defl_init, dim3(grid), dim3(256), 0, s, a);
+}
+
+void launch_reduce(const ReduceArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, a);
+}
+
+void launch_coarse2(const Coarse2Args &a, hipStream_t s) {
+    if (a.n <= 0) return;
+    hipLaunchKernelGGL(k_coarse2, dim3((a.n + 63) / 64), dim3(256), (size_t)a.n * 8, s, a);
+}
+
+void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
+    hipLaunchKernelGGL(k_l2_a, dim3(nsr), dim3(256), (size_t)max_nL * 8, s, a);
+}
+void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
+    hipLaunchKernelGGL(k_l2_b, dim3(nsr), dim3(256), (size_t)max_nL * 8, s, a);
+}
+void launch_l3(const L3Args &a, hipStream_t s) {
+    if (a.n <= 0) return;
+    hipLaunchKernelGGL(k_l3, dim3((a.n + 63) / 64), dim3(256), (size_t)a.n * 8, s, a);
+}
+void launch_l2_d(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
+    hipLaunchKernelGGL(k_l2_d, dim3(nsr), dim3(256), (size_t)max_nL * 8, s, a);
+}
+
+}  // namespace bddc

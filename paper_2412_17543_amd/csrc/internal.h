@@ -13,7 +13,7 @@ namespace bddc {
 
 constexpr int TILE = 16;          // symmetric operators are stored as 16x16 tiles
 constexpr int RMAX = 64;          // largest deflation basis supported
-constexpr int NPART_MAX = 4096;   // largest grid of a reduction kernel
+constexpr int VGRID = 512;        // blocks of the grid-stride vector kernels (max)
 
 // ---------------------------------------------------------------------------
 // host-side structure built from mesh + partition (partition.cpp)
@@ -102,6 +102,8 @@ struct PackDesc {
     const double *phi; int ldphi;  // nullable n x nc block (scaled by D rows)
     int nc;
     int64_t dst;                   // element offset of the first tile
+    int64_t phr;                   // element offset of the row-major copy of
+                                   // the (D-scaled) coarse-basis rows, or -1
 };
 
 struct PtspDesc {                  // K_C = Phi^T S Phi
@@ -121,22 +123,36 @@ struct DenseCopyDesc {             // out[r][c] = sign * D[r] * src[r][c] (* D[c
     double *dst; int ldd;
 };
 
-// reduction/control block living in device memory
+// Control block of one solve, in device memory.  Every kernel of the
+// iteration reads it at its start; a field is written (by block 0) only by a
+// kernel none of whose other blocks read that field, so no block ever sees a
+// half-updated control state.
 struct Ctl {
-    double rho, pAp, alpha, beta;
-    double rr, bb, r0r0, true_rr;
+    double rr;              // ||r_j||^2 of the last stopping test
+    double bb;              // ||b||^2 of the condensed right-hand side
+    double r0r0;            // ||r_0||^2
     double denom2;          // squared denominator of the stopping test
-    double rtol2;
-    int done, iter, status, restarts;
-    int j;                  // index of the current direction
-    int k;                  // deflation columns in use
-    int record;             // store P / AP / scalar histories
-    int pad;
-    double mu[RMAX];        // current mu (or gamma) vector
-    unsigned int cnt[16];   // last-block counters
+    double rtol2;           // squared relative tolerance
+    double true_rr;         // ||b - A x||^2 after the loop
+    double pAp, alpha;      // last p^T A p and alpha (diagnostics)
+    int32_t done;           // 1: converged or failed; later kernels return at once
+    int32_t iter;           // loop passes done (products with A inside the loop)
+    int32_t status;         // 0 or BDDC_ENOTCONV / BDDC_EBREAKDOWN
+    int32_t j;              // index of the current search direction p_j
+    int32_t k;              // deflation columns in use
+    int32_t record;         // store P, AP for recycling
+    int32_t zero_rhs;       // b == 0: the solution is x = 0
+    int32_t pad;
 };
 
-// counters (index into Ctl::cnt)
-enum { CNT_SYMV = 0, CNT_UPD, CNT_ZASM, CNT_COND, CNT_RES, CNT_DEFL, CNT_TRUE, CNT_GRAM, CNT_PREC };
+// Element index of entry (r, c) inside a 16x16 operator tile.  Lane
+// l = 16 (r / 4) + c of a wave holds rows 4 (l / 16) .. + 3 of column l % 16;
+// float64 tiles are stored as two 1 KB halves (rows i = 0,1 then 2,3 of every
+// lane), float32 and bfloat16 tiles as 4 consecutive values per lane, so each
+// wave-wide load is one contiguous, fully used block.
+__host__ __device__ inline int tile_index(int r, int c, int elem_bytes) {
+    const int l = 16 * (r >> 2) + c, i = r & 3;
+    return elem_bytes == 8 ? ((i >> 1) * 128 + l * 2 + (i & 1)) : (l * 4 + i);
+}
 
 }  // namespace bddc

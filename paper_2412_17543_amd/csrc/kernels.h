@@ -1,10 +1,12 @@
-// Kernel argument structs and launchers (kernels.hip).
+// Kernel argument structs and launchers (kernels.hip: setup and per-solve
+// kernels; hot.hip: the kernels of one deflated-PCG iteration).
 #pragma once
 
 #include "internal.h"
 
 namespace bddc {
 
+// ============================================================ setup kernels
 struct AsmDesc {
     const int32_t *elem_loc; const double *elem_c;
     const int32_t *inc_ptr, *inc_e, *inc_v;
@@ -12,74 +14,161 @@ struct AsmDesc {
     double *K;
 };
 
-struct SymvArgs {
+// ======================================================== operator products
+// One work item of a batched symmetric product: tiles [t0, t1) of the packed
+// tile sequence of subdomain `sub`; `c` numbers the items of that subdomain.
+struct SymvItem {
+    int32_t sub, t0, t1, c;
+};
+
+// A batch of packed symmetric operators.  Tile row I of subdomain i holds the
+// tiles (I, I..nt-1) of the upper triangle and, when `nc` is set, ntc extra
+// tiles of the coarse basis rows (I, nt..nt+ntc-1).  Item c of subdomain i
+// writes its partial products to ypart[pb[i] + c * nB[i] + k] and, with a
+// coarse basis, cpart[cb[i] + c * nc[i] + q].
+struct OpDev {
     const void *tiles;
     const int64_t *t_off;
     const int32_t *nB, *b_off, *gB;
-    const int32_t *nc, *c_off;     // nullable: coarse-basis tile columns
-    const double *x;
-    double *y, *c;
-    double *partial;               // nullable: no reduction
+    const int32_t *nc;              // nullable
+    const SymvItem *items;
+    int n_items;
+    const int32_t *nchunk, *pb, *cb;
+};
+
+// Sum of the partial products of the owners of one assembled entry:
+// entries `pos` index local interface (b_off-based) or coarse (c_off-based)
+// positions, pos_sub maps them back to their subdomain.
+struct Gather {
+    const int32_t *ptr, *idx;       // assembled entry -> positions
+    const int32_t *pos_sub;         // position -> subdomain
+    const int32_t *off;             // per subdomain: b_off (or c_off)
+    const int32_t *len;             // per subdomain: nB (or nc)
+    const int32_t *nchunk, *base;   // per subdomain: item count, partial base
+    const double *part;
+};
+
+struct SymvArgs {
+    OpDev op;
+    const double *x;                // global interface vector
+    double *ypart, *cpart;
+    double *dot;                    // nullable: per-item x_i^T y_i partials
     Ctl *ctl;
-    int mode;                      // 1: alpha = rho / pAp
-    int gated;                     // skip when ctl->done
+    int gated;                      // return when ctl->done
+    // stopping test made at the start (Section 5), on the residual whose
+    // per-block ||r||^2 partials the previous kernel wrote
+    int test;                       // 0 none, 1 in the loop, 2 on r_0 (first)
+    int stop_rule, max_it;
+    const double *rr_part; int rr_n;
+    const double *bb_part; int bb_n;
+    double *res_hist; int hist_cap;
+};
+
+struct UpdArgs {                    // Alg. 1, lines 9-11
+    int n;
+    Gather q;                       // q = A p from the Schur partials
+    const double *p;
+    double *x, *r;
+    double *AP; int64_t ld; int cap;
+    const double *dot; int dot_n;   // p^T A p partials
+    double *rr_part;
+    Ctl *ctl;
     double *d_hist, *a_hist;
+    const double *rho_hist;
     int hist_cap;
 };
 
-struct UpdArgs {
+struct ZasmArgs {                   // z = sum_i R_i^T D_i (u_i + Phi_i u_C), rho, (AW)^T z
     int n;
-    const int32_t *ptr, *idx;
-    const double *loc, *p;
-    double *x, *r;
-    double *AP; int64_t ld; int cap;
-    double *partial;
-    Ctl *ctl;
-    double *res_hist; int hist_cap;
-    int max_it;
-};
-
-struct ZasmArgs {
-    int n;
-    const int32_t *ptr, *idx;
-    const double *loc, *r;
+    Gather u;                       // local Neumann products (D N D r_i)
+    const int32_t *b_off, *nB;
+    const void *phir;               // D Phi_i rows, local precision
+    const int64_t *phr_off;
+    const int32_t *nc, *c_off, *cidx;
+    const double *uC;               // level-1 coarse solution (nullable: no coarse space)
+    const double *r;
     double *z;
     const double *AW; int64_t ld;
-    const double *Lc;
-    double *partial;
+    double *part;                   // nullable: per-block (r^T z, (AW)^T z)
     Ctl *ctl;
-    int first, gated;
-    double *rho_hist, *b_hist, *mu_hist; int hist_cap;
+    int gated, advance;
 };
 
-struct PupdArgs {
+struct PupdArgs {                   // Alg. 1, lines 14-16 (line 7 when first)
     int n;
     const double *z;
     double *p;
     const double *W; int64_t ld;
     double *P; int cap;
+    const double *zpart; int zpart_n;
+    const double *WAWinv;
     Ctl *ctl;
+    int first, hist_only, gated;
+    double *rho_hist, *b_hist, *mu_hist; int hist_cap;
 };
 
-struct ResidArgs {
-    int n, mode, stop_rule;
-    const int32_t *ptr, *idx;
-    const double *loc, *b;
+struct ResidArgs {                  // out = b - sum of the Schur partials
+    int n, want_wtr;
+    Gather q;
+    const double *b;
     double *out;
     const double *W; int64_t ld;
-    const double *Lc;
-    double *partial;
     Ctl *ctl;
+    double *part;                   // per-block (||out||^2, W^T out)
 };
 
-struct DeflArgs {
-    int n, stop_rule;
+struct DeflArgs {                   // Alg. 1, lines 3-4
+    int n;
     double *x, *r;
     const double *W, *AW; int64_t ld;
-    double *partial;
+    const double *wpart; int wpart_n;
+    const double *WAWinv;
+    double *rr_part;
     Ctl *ctl;
 };
 
+struct ReduceArgs {                 // one block: out[c] = sum_b part[b * st + c]
+    const double *part;
+    int n, st, ncol;
+    double *out;
+};
+
+// ============================================================ coarse levels
+struct Coarse2Args {                // two levels: u_C = K_C^{-1} r_C (dense)
+    Ctl *ctl;
+    int n;
+    Gather rc;
+    const double *Kneg;             // -K_C^{-1}
+    double *u;
+};
+
+struct L2Args {
+    Ctl *ctl;
+    Gather rc;                      // level-1 coarse residual from the coarse partials
+    const int32_t *nL, *nI2, *L_off, *L, *I2_off, *B2_off, *g2;
+    const int64_t *K2_off; const double *K2;   // swept subregion matrices
+    double *vI2, *t2, *rB2;
+    const int32_t *asm2_ptr, *asm2_idx;        // level-2 interface DOF -> B2 positions
+    const int64_t *N2_off; const double *N2;
+    const int64_t *P2_off; const double *Phi2;
+    const int32_t *nc3, *C3_off, *c3;
+    double *u2, *c3loc;
+    const int32_t *pos_sr;
+    const uint8_t *own2;
+    const double *u3;
+    double *uC;
+};
+
+struct L3Args {                     // level 3: u3 = K3^{-1} r3 (dense)
+    Ctl *ctl;
+    int n;
+    const int32_t *ptr, *idx;
+    const double *loc;
+    const double *Kneg;
+    double *u;
+};
+
+// ====================================================== per-solve kernels
 struct CondArgs {
     const int32_t *nI, *nB, *i_off, *b_off, *nodesI;
     const int64_t *k_off;
@@ -91,8 +180,7 @@ struct CondAsmArgs {
     int n;
     const int32_t *gamma, *ptr, *idx;
     const double *F, *loc;
-    double *b, *partial;
-    Ctl *ctl;
+    double *b, *part;
 };
 
 struct RecArgs {
@@ -100,43 +188,6 @@ struct RecArgs {
     const int64_t *k_off;
     const double *K, *x, *yI;
     double *u;
-};
-
-struct L2Args {
-    Ctl *ctl;
-    const int32_t *nL, *nI2, *L_off, *L, *I2_off, *B2_off, *g2;
-    const int32_t *cptr, *cidx_asm;      // level-1 coarse DOF -> positions in locc
-    const double *locc;
-    const int64_t *K2_off; const double *K2;   // swept subregion matrices
-    double *vI2, *t2, *rB2;
-    const int32_t *asm2_ptr, *asm2_idx;  // level-2 interface DOF -> positions in the B2 arrays
-    const int64_t *N2_off; const double *N2;
-    const int64_t *P2_off; const double *Phi2;
-    const int32_t *nc3, *C3_off;
-    double *u2, *c3loc;
-};
-
-struct CoarseArgs {
-    Ctl *ctl;
-    int n;
-    const int32_t *ptr, *idx;
-    const double *loc;
-    const double *Kneg;
-    double *u;
-};
-
-struct ProlArgs {
-    Ctl *ctl;
-    int three;
-    const int32_t *nB, *b_off, *nc, *c_off, *cidx, *cL;
-    const void *tiles; const int64_t *t_off;
-    const double *uCg;
-    // three-level data
-    const int32_t *sr_of_sub, *nL, *nI2, *I2_off, *B2_off, *g2, *asm2_ptr, *asm2_idx, *pos_sr;
-    const int32_t *nc3, *C3_off, *c3;
-    const int64_t *K2_off, *P2_off;
-    const double *K2, *Phi2, *u2, *u3, *vI2;
-    double *locu;
 };
 
 struct GemmArgs {
@@ -152,8 +203,7 @@ struct GramArgs {
     int n, k;
     int64_t ld;
     const double *X, *Y;
-    double *partial, *out;
-    Ctl *ctl;
+    double *part;
 };
 
 struct GradArgs {
@@ -164,33 +214,45 @@ struct GradArgs {
     double *grad;
 };
 
+// setup (kernels.hip)
 void launch_assemble(const AsmDesc *d, int n, hipStream_t s);
 void launch_sweep(const SweepDesc *d, int n, int maxn, int *status, hipStream_t s);
 void set_sweep_smem_limit(size_t bytes);
 void launch_build_saddle(const SaddleDesc *d, int n, hipStream_t s);
-void launch_pack(const PackDesc *d, int n, int prec, void *dst, hipStream_t s);
+void launch_pack(const PackDesc *d, int n, int prec, void *dst, void *phir, hipStream_t s);
 void launch_ptsp(const PtspDesc *d, int n, hipStream_t s);
 void launch_dense_copy(const DenseCopyDesc *d, int n, hipStream_t s);
 void launch_gather_sum(int64_t n, const int32_t *ptr, const int32_t *idx, const double *src, double *out, hipStream_t s);
-size_t symv_smem(int prec, int max_nt, int max_ntc);
-void set_symv_smem_limit(size_t bytes);
-void launch_symv(const SymvArgs &a, int prec, int nsub, size_t smem, hipStream_t s);
-void launch_update(const UpdArgs &a, hipStream_t s);
-void launch_zasm(const ZasmArgs &a, hipStream_t s);
-void launch_pupd(const PupdArgs &a, hipStream_t s);
-void launch_resid(const ResidArgs &a, hipStream_t s);
-void launch_defl_init(const DeflArgs &a, hipStream_t s);
+// per solve (kernels.hip)
 void launch_cond_local(const CondArgs &a, int nsub, int max_nI, hipStream_t s);
-void launch_cond_asm(const CondAsmArgs &a, hipStream_t s);
+void launch_cond_asm(const CondAsmArgs &a, int grid, hipStream_t s);
 void launch_recover(const RecArgs &a, int nsub, int max_nB, hipStream_t s);
 void launch_scatter_gamma(int n, const int32_t *gamma, const double *x, double *u, hipStream_t s);
-void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s);
-void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s);
-void launch_coarse_solve(const CoarseArgs &a, hipStream_t s);
-void launch_prolong(const ProlArgs &a, int prec, int nsub, size_t smem, hipStream_t s);
 void launch_recycle_gemm(const GemmArgs &a, hipStream_t s);
 void launch_gram(const GramArgs &a, int nblocks, hipStream_t s);
 void launch_elem_grad(const GradArgs &a, hipStream_t s);
 void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s);
+void launch_fill(int64_t n, double v, double *dst, hipStream_t s);
+// iteration (hot.hip)
+struct SymvCfg {
+    int nw;                         // waves per block: 4 or 8
+    int unroll;                     // tiles in flight per wave: 2 or 4
+};
+size_t symv_smem(int prec, int nw, int max_nt, int max_ntc);
+int set_symv_smem_limit(size_t bytes);
+void launch_symv(const SymvArgs &a, int prec, SymvCfg cfg, size_t smem, hipStream_t s);
+void launch_update(const UpdArgs &a, int grid, hipStream_t s);
+void launch_zasm(const ZasmArgs &a, int prec, int kmax, int grid, hipStream_t s);
+void launch_pupd(const PupdArgs &a, int grid, hipStream_t s);
+void launch_resid(const ResidArgs &a, int kmax, int grid, hipStream_t s);
+void launch_defl_init(const DeflArgs &a, int grid, hipStream_t s);
+void launch_reduce(const ReduceArgs &a, hipStream_t s);
+void launch_coarse2(const Coarse2Args &a, hipStream_t s);
+void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s);
+void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s);
+void launch_l3(const L3Args &a, hipStream_t s);
+void launch_l2_d(const L2Args &a, int nsr, int max_nL, hipStream_t s);
+// deflation-column bucket of the templated reductions (0, 8, 16, 32, 64)
+int kmax_bucket(int k);
 
 }  // namespace bddc

@@ -33,7 +33,7 @@ class Solver:
                  node_dirichlet=None, ny=None, nz=None, R=0, strategy="B4", local_prec=64,
                  weights="diag", constraints=("corners", "faces"), stop_rule="rhs",
                  init_guess="prev", max_it=1000, save_cap=256, freeze_tol=1e-5,
-                 device="cuda", stream=None):
+                 use_graph=True, device="cuda", stream=None):
         lib = _lib.load()
         self.lib = lib
         self.device = torch.device(device)
@@ -75,6 +75,7 @@ class Solver:
         o.init_guess = {"prev": 0, "zero": 1}[init_guess]
         o.max_it = max_it
         o.save_cap = save_cap
+        o.use_graph = 1 if use_graph else 0
         self.opts = o
         torch.cuda.set_device(self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
