@@ -45,6 +45,8 @@ struct OpHost {
     int32_t *d_items = nullptr, *d_nchunk = nullptr, *d_pb = nullptr, *d_cb = nullptr;
     double *d_ypart = nullptr, *d_cpart = nullptr;
     int64_t ypart_len = 0, cpart_len = 0;
+    // flat gather lists: interface node -> y partials, coarse DOF -> c partials
+    int32_t *d_yptr = nullptr, *d_yidx = nullptr, *d_cptr = nullptr, *d_cidx = nullptr;
 };
 
 }  // namespace
@@ -71,12 +73,13 @@ struct bddc_ctx {
     void *d_N = nullptr, *d_phir = nullptr;
     int32_t *d_asm_ptr = nullptr, *d_asm_idx = nullptr, *d_casm_ptr = nullptr, *d_casm_idx = nullptr;
     int max_nI = 0, max_nB = 0, max_nc = 0, max_nt = 0, max_ntc = 0;
-    std::vector<int32_t> h_nB, h_nc, h_b_off, h_c_off;
+    std::vector<int32_t> h_nB, h_nc, h_b_off, h_c_off, h_pos_sub, h_cpos_sub;
+    std::vector<int32_t> h_asm_ptr, h_asm_idx, h_casm_ptr, h_casm_idx;
     OpHost opS, opN;
     // iteration vectors
     int vgrid = 1;
     double *d_b = nullptr, *d_x = nullptr, *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_tmp = nullptr;
-    double *d_locq = nullptr, *d_yI = nullptr;
+    double *d_locq = nullptr, *d_yI = nullptr, *d_wloc = nullptr;
     double *d_rr = nullptr, *d_bbp = nullptr, *d_zp = nullptr, *d_wp = nullptr, *d_dotS = nullptr, *d_gp = nullptr;
     // coarse
     bool three = false;
@@ -253,6 +256,36 @@ int build_worklist(bddc_ctx *c, OpHost &op, int64_t target) {
     op.dev.nchunk = op.d_nchunk;
     op.dev.pb = op.d_pb;
     op.dev.cb = op.d_cb;
+    // flat gather lists, owners in assembly order, items in increasing order
+    {
+        std::vector<int32_t> ptr(c->n_gamma + 1, 0), idx;
+        idx.reserve(ylen);
+        for (int g = 0; g < c->n_gamma; ++g) {
+            for (int e = c->h_asm_ptr[g]; e < c->h_asm_ptr[g + 1]; ++e) {
+                const int pos = c->h_asm_idx[e];
+                const int i = c->h_pos_sub[pos];
+                const int k = pos - c->h_b_off[i];
+                for (int q = 0; q < nch[i]; ++q) idx.push_back(pb[i] + q * c->h_nB[i] + k);
+            }
+            ptr[g + 1] = (int32_t)idx.size();
+        }
+        dfree(c, op.d_yptr); dfree(c, op.d_yidx);
+        if ((rc = dupload(c, &op.d_yptr, ptr)) || (rc = dupload(c, &op.d_yidx, idx))) return rc;
+    }
+    if (op.dev.nc) {
+        std::vector<int32_t> ptr(c->nC + 1, 0), idx;
+        for (int t = 0; t < c->nC; ++t) {
+            for (int e = c->h_casm_ptr[t]; e < c->h_casm_ptr[t + 1]; ++e) {
+                const int pos = c->h_casm_idx[e];
+                const int i = c->h_cpos_sub[pos];
+                const int q = pos - c->h_c_off[i];
+                for (int cc = 0; cc < nch[i]; ++cc) idx.push_back(cb[i] + cc * c->h_nc[i] + q);
+            }
+            ptr[t + 1] = (int32_t)idx.size();
+        }
+        dfree(c, op.d_cptr); dfree(c, op.d_cidx);
+        if ((rc = dupload(c, &op.d_cptr, ptr)) || (rc = dupload(c, &op.d_cidx, idx))) return rc;
+    }
     return 0;
 }
 
@@ -271,16 +304,10 @@ int set_done(bddc_ctx *c, int v) {
     return 0;
 }
 
-Gather gather_of(const bddc_ctx *c, const OpHost &op, bool coarse) {
+Gather gather_of(const OpHost &op, bool coarse) {
     Gather g{};
-    if (coarse) {
-        g.ptr = c->d_casm_ptr; g.idx = c->d_casm_idx; g.pos_sub = c->d_cpos_sub; g.off = c->d_c_off; g.len = c->d_nc;
-        g.base = op.d_cb; g.part = op.d_cpart;
-    } else {
-        g.ptr = c->d_asm_ptr; g.idx = c->d_asm_idx; g.pos_sub = c->d_pos_sub; g.off = c->d_b_off; g.len = c->d_nB;
-        g.base = op.d_pb; g.part = op.d_ypart;
-    }
-    g.nchunk = op.d_nchunk;
+    if (coarse) { g.ptr = op.d_cptr; g.idx = op.d_cidx; g.part = op.d_cpart; }
+    else { g.ptr = op.d_yptr; g.idx = op.d_yidx; g.part = op.d_ypart; }
     return g;
 }
 
@@ -322,7 +349,7 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
     }
     if (c->nC > 0) {
         TScope ts(c, TK_COARSE);
-        const Gather rc = gather_of(c, c->opN, true);
+        const Gather rc = gather_of(c->opN, true);
         if (c->three) {
             L2Args l{};
             l.ctl = c->d_ctl;
@@ -349,20 +376,24 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
     }
     {
         TScope ts(c, TK_VEC);
+        ProlArgs pa{};
+        pa.ctl = c->d_ctl; pa.gated = gated ? 1 : 0;
+        pa.nB = c->d_nB; pa.b_off = c->d_b_off; pa.nc = c->d_nc; pa.c_off = c->d_c_off; pa.cidx = c->d_cidx;
+        pa.nchunk = c->opN.d_nchunk; pa.pb = c->opN.d_pb; pa.upart = c->opN.d_ypart;
+        pa.phir = c->d_phir; pa.phr_off = c->d_phr_off;
+        pa.uC = c->nC > 0 ? c->d_uC : nullptr;
+        pa.wloc = c->d_wloc;
+        launch_prolong(pa, c->prec, c->n_sub, c->max_nc, c->stream);
         ZasmArgs a{};
         a.n = c->n_gamma;
-        a.u = gather_of(c, c->opN, false);
-        a.b_off = c->d_b_off; a.nB = c->d_nB;
-        a.phir = c->d_phir; a.phr_off = c->d_phr_off;
-        a.nc = c->d_nc; a.c_off = c->d_c_off; a.cidx = c->d_cidx;
-        a.uC = c->nC > 0 ? c->d_uC : nullptr;
+        a.w.ptr = c->d_asm_ptr; a.w.idx = c->d_asm_idx; a.w.part = c->d_wloc;
         a.r = r; a.z = z;
         a.AW = c->d_AW; a.ld = c->ld;
         a.part = reduce ? c->d_zp : nullptr;
         a.ctl = c->d_ctl;
         a.gated = gated ? 1 : 0;
         a.advance = advance ? 1 : 0;
-        launch_zasm(a, c->prec, c->kmax, c->vgrid, c->stream);
+        launch_zasm(a, c->kmax, c->vgrid, c->stream);
     }
 }
 
@@ -383,7 +414,7 @@ void run_update(bddc_ctx *c) {
     TScope ts(c, TK_VEC);
     UpdArgs a{};
     a.n = c->n_gamma;
-    a.q = gather_of(c, c->opS, false);
+    a.q = gather_of(c->opS, false);
     a.p = c->d_p; a.x = c->d_x; a.r = c->d_r;
     a.AP = c->d_AP; a.ld = c->ld; a.cap = c->save_cap;
     a.dot = c->d_dotS; a.dot_n = c->opS.dev.n_items;
@@ -399,7 +430,7 @@ void run_resid(bddc_ctx *c, double *out, bool want_wtr) {
     TScope ts(c, TK_VEC);
     ResidArgs a{};
     a.n = c->n_gamma; a.want_wtr = want_wtr ? 1 : 0;
-    a.q = gather_of(c, c->opS, false);
+    a.q = gather_of(c->opS, false);
     a.b = c->d_b; a.out = out;
     a.W = c->d_W; a.ld = c->ld;
     a.ctl = c->d_ctl;
@@ -516,7 +547,7 @@ void run_true_residual(bddc_ctx *c, double *out) {
     run_schur(c, c->d_x, false, false);
     run_resid(c, out, false);
     ReduceArgs r{};
-    r.part = c->d_wp; r.n = c->vgrid; r.st = RMAX + 1; r.ncol = 1; r.out = &c->d_ctl->true_rr;
+    r.part = c->d_wp; r.n = c->vgrid; r.ncol = 1; r.out = &c->d_ctl->true_rr;
     launch_reduce(r, c->stream);
 }
 
@@ -583,7 +614,7 @@ int refresh_waw(bddc_ctx *c, const double *W, const double *AW, int k, std::vect
     g.n = c->n_gamma; g.k = k; g.ld = c->ld; g.X = W; g.Y = AW; g.part = c->d_gp;
     launch_gram(g, nb, c->stream);
     ReduceArgs r{};
-    r.part = c->d_gp; r.n = nb; r.st = k * k; r.ncol = k * k; r.out = c->d_Y;
+    r.part = c->d_gp; r.n = nb; r.ncol = k * k; r.out = c->d_Y;
     launch_reduce(r, c->stream);
     waw.resize((size_t)k * k);
     HIPCHK(hipMemcpyAsync(waw.data(), c->d_Y, (size_t)k * k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -894,7 +925,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         max_nloc = std::max(max_nloc, sh.nloc);
     }
     if (b_off[nsub] > INT32_MAX / 2) return fail(BDDC_EINVAL, "too many local interface entries");
-    c->h_nB = nB; c->h_nc = nc;
+    c->h_nB = nB; c->h_nc = nc; c->h_pos_sub = pos_sub; c->h_cpos_sub = cpos_sub;
     c->h_b_off.assign(b_off.begin(), b_off.end() - 1);
     c->h_c_off.assign(c_off.begin(), c_off.end() - 1);
     if ((rc = dupload(c, &c->d_nI, nI)) || (rc = dupload(c, &c->d_nB, nB)) || (rc = dupload(c, &c->d_nc, nc)) ||
@@ -914,11 +945,13 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         std::vector<int32_t> ptr, idx;
         build_csr(c->n_gamma, pr, ptr, idx);
         if ((rc = dupload(c, &c->d_asm_ptr, ptr)) || (rc = dupload(c, &c->d_asm_idx, idx))) return rc;
+        c->h_asm_ptr = ptr; c->h_asm_idx = idx;
         pr.clear();
         for (int i = 0; i < nsub; ++i)
             for (int q = 0; q < nc[i]; ++q) pr.push_back({st.sub[i].cidx[q], c_off[i] + q});
         build_csr(c->nC, pr, ptr, idx);
         if ((rc = dupload(c, &c->d_casm_ptr, ptr)) || (rc = dupload(c, &c->d_casm_idx, idx))) return rc;
+        c->h_casm_ptr = ptr; c->h_casm_idx = idx;
     }
 
     // -------------------------------------------------- local assembly
@@ -1246,7 +1279,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
     const int gram_nb = std::max(1, std::min(256, (ng + 1023) / 1024));
     if ((rc = dalloc(c, &c->d_b, ng)) || (rc = dalloc(c, &c->d_x, ng)) || (rc = dalloc(c, &c->d_r, ng)) ||
         (rc = dalloc(c, &c->d_z, ng)) || (rc = dalloc(c, &c->d_p, ng)) || (rc = dalloc(c, &c->d_tmp, ng)) ||
-        (rc = dalloc(c, &c->d_locq, (size_t)b_off[nsub])) ||
+        (rc = dalloc(c, &c->d_locq, (size_t)b_off[nsub])) || (rc = dalloc(c, &c->d_wloc, (size_t)b_off[nsub])) ||
         (rc = dalloc(c, &c->d_yI, (size_t)std::max<int64_t>(1, i_off[nsub]))) ||
         (rc = dalloc(c, &c->d_rr, (size_t)c->vgrid)) || (rc = dalloc(c, &c->d_bbp, (size_t)c->vgrid)) ||
         (rc = dalloc(c, &c->d_zp, (size_t)c->vgrid * (RMAX + 1))) ||
@@ -1398,7 +1431,7 @@ int bddc_apply_schur(bddc_ctx *c, const double *p, double *q) {
     if (!c || !p || !q) return fail(BDDC_EINVAL, "null argument");
     run_schur(c, p, false, false);
     ResidArgs a{};
-    a.n = c->n_gamma; a.want_wtr = 0; a.q = gather_of(c, c->opS, false); a.b = nullptr; a.out = q;
+    a.n = c->n_gamma; a.want_wtr = 0; a.q = gather_of(c->opS, false); a.b = nullptr; a.out = q;
     a.W = c->d_W; a.ld = c->ld; a.ctl = c->d_ctl; a.part = c->d_wp;
     launch_resid(a, 0, c->vgrid, c->stream);
     HIPCHK(hipStreamSynchronize(c->stream));

@@ -33,13 +33,30 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return t;
 }
 
-// Sum of p[i * st], i < n, by one wave in a fixed order (lane-strided partial
-// sums, then a butterfly): every wave that calls it gets the same value.
-__device__ __forceinline__ double wave_sum_strided(const double *p, int n, int st) {
-    const int l = threadIdx.x & 63;
-    double s = 0.0;
-    for (int i = l; i < n; i += 64) s += p[(size_t)i * st];
-    return wave_sum(s);
+// Per-thread part of a contiguous sum: element i goes to thread i % nthr,
+// four independent accumulators so that the loads are issued together.
+__device__ __forceinline__ double strided_part(const double *p, int n, int t, int nthr) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = t;
+    for (; i + 3 * nthr < n; i += 4 * nthr) {
+        s0 += p[i];
+        s1 += p[i + nthr];
+        s2 += p[i + 2 * nthr];
+        s3 += p[i + 3 * nthr];
+    }
+    for (; i < n; i += nthr) s0 += p[i];
+    return (s0 + s1) + (s2 + s3);
+}
+
+// Sum of p[0..n) by one wave in a fixed order: every wave that calls it gets
+// the same value.
+__device__ __forceinline__ double wave_sum_contig(const double *p, int n) {
+    return wave_sum(strided_part(p, n, threadIdx.x & 63, 64));
+}
+
+// Sum of p[0..n) by the whole block in a fixed order (every thread gets it).
+__device__ __forceinline__ double block_sum_contig(const double *p, int n, double *sh) {
+    return block_sum(strided_part(p, n, threadIdx.x, blockDim.x), sh);
 }
 
 __device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }

@@ -8,15 +8,16 @@
 //   k_update     alpha, x += alpha p, r -= alpha q  lines 9-11
 //   k_symv (N)   stopping test (Section 5); u_i = D N_i D r_i, c_i = (D Phi_i)^T r_i
 //   coarse       two levels: k_coarse2; three levels: k_l2_a, k_l2_b, k_l3, k_l2_d
-//   k_zasm       z = sum_i R_i^T (u_i + D Phi_i u_C), r^T z, (AW)^T z   line 13
+//   k_prolong    w_i = u_i + D Phi_i u_C            eq. averaging_subdomain_solves
+//   k_zasm       z = sum_i R_i^T w_i, r^T z, (AW)^T z   line 13
 //   k_pupd       beta, mu, p = z + beta p - W mu    lines 14-16
 // A converged or failed solve sets ctl->done; every later kernel returns at
 // once, so replaying more iterations than needed is harmless.
 //
 // Reductions never cross blocks inside a kernel: a producer writes one
-// partial per block (or per work item) and every block of the consuming
-// kernel sums them in index order, so all blocks see bitwise the same
-// scalars and every run gives the same result.
+// partial per block (or per work item), column by column, and every block of
+// the consuming kernel sums them in index order, so all blocks see bitwise
+// the same scalars and every run gives the same result.
 #include <hip/hip_runtime.h>
 
 #include "devutil.h"
@@ -26,8 +27,9 @@
 namespace bddc {
 
 using dev::block_sum;
+using dev::block_sum_contig;
 using dev::wave_sum;
-using dev::wave_sum_strided;
+using dev::wave_sum_contig;
 
 namespace {
 
@@ -87,18 +89,17 @@ __device__ __forceinline__ double to_d(double v) { return v; }
 __device__ __forceinline__ double to_d(float v) { return (double)v; }
 __device__ __forceinline__ double to_d(uint16_t v) { return (double)dev::bf16_to_f32(v); }
 
-// Sum over the owners of assembled entry t of all partial products of each
-// owner (fixed order: owners as listed, items in increasing order).
+// Sum of the partial products listed for assembled entry t (fixed order).
 __device__ __forceinline__ double gather_sum(const Gather &G, int64_t t) {
+    const int e0 = G.ptr[t], e1 = G.ptr[t + 1];
     double s = 0.0;
-    for (int e = G.ptr[t]; e < G.ptr[t + 1]; ++e) {
-        const int pos = G.idx[e];
-        const int i = G.pos_sub[pos];
-        const int k = pos - G.off[i];
-        const int n = G.len[i], C = G.nchunk[i];
-        const double *p = G.part + G.base[i] + k;
-        for (int c = 0; c < C; ++c) s += p[(int64_t)c * n];
+    int e = e0;
+    for (; e + 3 < e1; e += 4) {
+        const double a0 = G.part[G.idx[e]], a1 = G.part[G.idx[e + 1]];
+        const double a2 = G.part[G.idx[e + 2]], a3 = G.part[G.idx[e + 3]];
+        s += a0; s += a1; s += a2; s += a3;
     }
+    for (; e < e1; ++e) s += G.part[G.idx[e]];
     return s;
 }
 
@@ -111,11 +112,11 @@ __device__ bool stop_test(const SymvArgs &a) {
     __shared__ int s_stop;
     Ctl *c = a.ctl;
     if (threadIdx.x < 64) {
-        const double rr = wave_sum_strided(a.rr_part, a.rr_n, 1);
+        const double rr = wave_sum_contig(a.rr_part, a.rr_n);
         const bool first = a.test == 2;
         double bb = 0.0, denom2;
         if (first) {
-            bb = wave_sum_strided(a.bb_part, a.bb_n, 1);
+            bb = wave_sum_contig(a.bb_part, a.bb_n);
             denom2 = a.stop_rule == 0 ? bb : rr;
         } else {
             denom2 = c->denom2;
@@ -148,20 +149,37 @@ __device__ bool stop_test(const SymvArgs &a) {
     return s_stop != 0;
 }
 
+// y_r = sum_{q < ncol} M[q * ldm + r] x[q] for r in [r0, r1) (M read column
+// by column, i.e. the transposed access of a row-major symmetric matrix, so
+// consecutive lanes read consecutive addresses).  The NW waves of the block
+// split the columns; lanes take the rows; partial sums are added in wave
+// order by wave 0, which calls store(r, y_r).  x is in LDS.
+template <int NW, typename F>
+__device__ __forceinline__ void cm_matvec(const double *M, int64_t ldm, int r0, int r1, int ncol, const double *x,
+                                          double (*part)[64], F store) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int q0 = (int)((int64_t)ncol * w / NW), q1 = (int)((int64_t)ncol * (w + 1) / NW);
+    for (int rb = r0; rb < r1; rb += 64) {
+        const int r = rb + l;
+        double s = 0.0;
+        if (r < r1) {
+#pragma unroll 8
+            for (int q = q0; q < q1; ++q) s += M[(int64_t)q * ldm + r] * x[q];
+        }
+        part[w][l] = s;
+        __syncthreads();
+        if (w == 0 && r < r1) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) t += part[q][l];
+            store(r, t);
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// Batched symmetric product over a work list (one item per block):
-//   y_i = Op_i x_i with x_i = x[gB_i]    (Op packed upper triangle)
-//   c_i = Phi_i^T x_i                    (coarse-basis tiles, when present)
-// Each item covers a contiguous tile range of one subdomain, split evenly
-// over the block's waves.  Lane l of a wave holds column l%16 and rows
-// 4(l/16)..+3 of a tile: the direct product y_I += T x_J accumulates in
-// registers along the tile row, the transposed product y_J += T^T x_I needs
-// one two-step butterfly per tile.  Every wave accumulates in its own LDS
-// vector; the block sums them in wave order and writes the item's partial
-// vector (all nB entries) and, optionally, the partial x_i^T y_i.
-// ---------------------------------------------------------------------------
 template <typename T, int NW, int U>
 __global__ void __launch_bounds__(NW * 64) k_symv(SymvArgs a) {
     using ACC = typename Acc<T>::type;
@@ -283,35 +301,25 @@ __global__ void __launch_bounds__(NW * 64) k_symv(SymvArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Alg. 1 lines 9-11: alpha = rho_j / p^T A p (every block sums the partials
-// of the Schur product), q = sum_i R_i^T q_i, x += alpha p, r -= alpha q;
-// per-block ||r||^2; the product is kept as AP_j for recycling.
+// Alg. 1 lines 9-11: alpha = rho_j / p^T A p (every block sums the per-item
+// partials of the Schur product), q = sum_i R_i^T q_i, x += alpha p,
+// r -= alpha q; per-block ||r||^2; the product is kept as AP_j for recycling.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_update(UpdArgs a) {
     __shared__ double red[16];
-    __shared__ double s_alpha;
-    __shared__ int s_bad;
     Ctl *c = a.ctl;
     if (c->done) return;
     const int j = c->j;
-    if (threadIdx.x < 64) {
-        const double pAp = wave_sum_strided(a.dot, a.dot_n, 1);
-        if (threadIdx.x == 0) {
-            const double alpha = (j < a.hist_cap ? a.rho_hist[j] : 0.0) / pAp;
-            const bool bad = !(pAp > 0.0) || !isfinite(alpha) || j >= a.hist_cap;
-            s_alpha = alpha;
-            s_bad = bad ? 1 : 0;
-            if (blockIdx.x == 0) {
-                c->pAp = pAp;
-                c->alpha = alpha;
-                if (j < a.hist_cap) { a.d_hist[j] = pAp; a.a_hist[j] = alpha; }
-                if (bad) { c->status = BDDC_EBREAKDOWN; c->done = 1; }
-            }
-        }
+    const double pAp = block_sum_contig(a.dot, a.dot_n, red);
+    const double alpha = (j < a.hist_cap ? a.rho_hist[j] : 0.0) / pAp;
+    const bool bad = !(pAp > 0.0) || !isfinite(alpha) || j >= a.hist_cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->pAp = pAp;
+        c->alpha = alpha;
+        if (j < a.hist_cap) { a.d_hist[j] = pAp; a.a_hist[j] = alpha; }
+        if (bad) { c->status = BDDC_EBREAKDOWN; c->done = 1; }
     }
-    __syncthreads();
-    if (s_bad) return;
-    const double alpha = s_alpha;
+    if (bad) return;
     const bool rec = a.AP && c->record && j < a.cap;
     double rr = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -329,44 +337,52 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Alg. 1 line 13, assembly: z = sum_i R_i^T D_i (u_i + Phi_i u_C) (eq.
-// averaging_subdomain_solves; D is folded into the stored N_i and Phi_i),
-// with the coarse prolongation done per owner entry from the row-major
-// coarse-basis copy.  Per-block partials of r^T z and (AW)^T z (line 15).
-// With `advance`, block 0 moves the direction index to j + 1 (no block of this
-// kernel reads it).
+// Coarse prolongation (eq. averaging_subdomain_solves), one block per
+// subdomain: w_i = u_i + (D Phi_i) u_C|_i, u_i summed from the partial
+// products of the Neumann operator's work items.
 // ---------------------------------------------------------------------------
-template <typename T, int KM>
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong(ProlArgs a) {
+    extern __shared__ double uCl[];
+    if (a.gated && a.ctl->done) return;
+    const int i = blockIdx.x;
+    const int n = a.nB[i], C = a.nchunk[i];
+    const int nci = a.uC ? a.nc[i] : 0;
+    const int32_t *ci = a.cidx + a.c_off[i];
+    for (int q = threadIdx.x; q < nci; q += blockDim.x) uCl[q] = a.uC[ci[q]];
+    __syncthreads();
+    const T *ph = reinterpret_cast<const T *>(a.phir) + a.phr_off[i];
+    const double *up = a.upart + a.pb[i];
+    double *wl = a.wloc + a.b_off[i];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        double w = 0.0;
+        for (int cc = 0; cc < C; ++cc) w += up[(int64_t)cc * n + k];
+        const T *row = ph + (int64_t)k * nci;
+#pragma unroll 8
+        for (int q = 0; q < nci; ++q) w += to_d(row[q]) * uCl[q];
+        wl[k] = w;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 1 line 13, assembly: z = sum_i R_i^T w_i (weights folded into the
+// stored operators).  Per-block partials of r^T z and (AW)^T z (line 15),
+// column-major.  With `advance`, block 0 moves the direction index to j + 1
+// (no block of this kernel reads it).
+// ---------------------------------------------------------------------------
+template <int KM>
 __global__ void __launch_bounds__(256) k_zasm(ZasmArgs a) {
     __shared__ double wacc[4][KM + 1];
     Ctl *c = a.ctl;
     if (a.gated && c->done) return;
     if (a.advance && blockIdx.x == 0 && threadIdx.x == 0) c->j = c->j + 1;
     const int k = a.part ? c->k : 0;
-    const T *phir = reinterpret_cast<const T *>(a.phir);
     double acc[KM + 1];
 #pragma unroll
     for (int q = 0; q <= KM; ++q) acc[q] = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
-        double z = 0.0;
-        const Gather &G = a.u;
-        for (int e = G.ptr[g]; e < G.ptr[g + 1]; ++e) {
-            const int pos = G.idx[e];
-            const int i = G.pos_sub[pos];
-            const int kk = pos - a.b_off[i];
-            const int n = a.nB[i], C = G.nchunk[i];
-            const double *p = G.part + G.base[i] + kk;
-            double u = 0.0;
-            for (int cc = 0; cc < C; ++cc) u += p[(int64_t)cc * n];
-            if (a.uC) {
-                const int nci = a.nc[i];
-                const T *ph = phir + a.phr_off[i] + (int64_t)kk * nci;
-                const int32_t *ci = a.cidx + a.c_off[i];
-                for (int q = 0; q < nci; ++q) u += to_d(ph[q]) * a.uC[ci[q]];
-            }
-            z += u;
-        }
+        const double z = gather_sum(a.w, g);
         a.z[g] = z;
         if (a.part) {
             acc[0] += a.r[g] * z;
@@ -388,7 +404,7 @@ __global__ void __launch_bounds__(256) k_zasm(ZasmArgs a) {
     if (threadIdx.x <= k) {
         double s = 0.0;
         for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += wacc[q][threadIdx.x];
-        a.part[(int64_t)blockIdx.x * (RMAX + 1) + threadIdx.x] = s;
+        a.part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
     }
 }
 
@@ -402,14 +418,12 @@ __global__ void __launch_bounds__(256) k_zasm(ZasmArgs a) {
 __global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
     __shared__ double tv[RMAX + 1];
     __shared__ double mu[RMAX];
-    __shared__ double s_beta;
-    __shared__ int s_bad;
     Ctl *c = a.ctl;
     if (a.gated && c->done) return;
     const int k = c->k, j = c->j;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
     for (int col = w; col <= k; col += nw) {
-        const double s = wave_sum_strided(a.zpart + col, a.zpart_n, RMAX + 1);
+        const double s = wave_sum_contig(a.zpart + (int64_t)col * a.zpart_n, a.zpart_n);
         if (l == 0) tv[col] = s;
     }
     __syncthreads();
@@ -418,22 +432,19 @@ __global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
         for (int q = 0; q < k; ++q) s += a.WAWinv[threadIdx.x * k + q] * tv[1 + q];
         mu[threadIdx.x] = s;
     }
-    if (threadIdx.x == 0) {
-        const double rho = tv[0];
-        const double beta = a.first ? 0.0 : rho / a.rho_hist[j - 1];
-        const bool bad = !(rho > 0.0) || !isfinite(rho) || !isfinite(beta);
-        s_beta = beta;
-        s_bad = bad ? 1 : 0;
-        if (blockIdx.x == 0) {
+    __syncthreads();
+    const double rho = tv[0];
+    const double beta = a.first ? 0.0 : rho / a.rho_hist[j - 1];
+    const bool bad = !(rho > 0.0) || !isfinite(rho) || !isfinite(beta);
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
             if (j < a.hist_cap) a.rho_hist[j] = rho;
             if (!a.first && j >= 1 && j - 1 < a.hist_cap) a.b_hist[j - 1] = beta;
             if (bad && !a.hist_only) { c->status = BDDC_EBREAKDOWN; c->done = 1; }
         }
+        if (threadIdx.x < k && j < a.hist_cap) a.mu_hist[(int64_t)j * RMAX + threadIdx.x] = mu[threadIdx.x];
     }
-    __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x < k && j < a.hist_cap) a.mu_hist[(int64_t)j * RMAX + threadIdx.x] = mu[threadIdx.x];
-    if (a.hist_only || s_bad) return;
-    const double beta = s_beta;
+    if (a.hist_only || bad) return;
     const bool rec = a.P && c->record && j < a.cap;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
@@ -446,8 +457,8 @@ __global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
 
 // ---------------------------------------------------------------------------
 // out = b - sum_i R_i^T q_i (initial or true residual; out = the assembled
-// product when b is null); per-block partials of ||out||^2 and, with
-// want_wtr, of W^T out (Alg. 1 line 3).
+// product when b is null); per-block partials (column-major) of ||out||^2
+// and, with want_wtr, of W^T out (Alg. 1 line 3).
 // ---------------------------------------------------------------------------
 template <int KM>
 __global__ void __launch_bounds__(256) k_resid(ResidArgs a) {
@@ -463,8 +474,8 @@ __global__ void __launch_bounds__(256) k_resid(ResidArgs a) {
         a.out[g] = r;
         acc[0] += r * r;
 #pragma unroll
-        for (int q = 0; q < KM; ++q)
-            if (q < k) acc[1 + q] += a.W[(int64_t)q * a.ld + g] * r;
+        for (int q2 = 0; q2 < KM; ++q2)
+            if (q2 < k) acc[1 + q2] += a.W[(int64_t)q2 * a.ld + g] * r;
     }
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
@@ -478,7 +489,7 @@ __global__ void __launch_bounds__(256) k_resid(ResidArgs a) {
     if (threadIdx.x <= k) {
         double s = 0.0;
         for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += wacc[q][threadIdx.x];
-        a.part[(int64_t)blockIdx.x * (RMAX + 1) + threadIdx.x] = s;
+        a.part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
     }
 }
 
@@ -491,7 +502,7 @@ __global__ void __launch_bounds__(256) k_defl_init(DeflArgs a) {
     const int k = a.ctl->k;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
     for (int col = 1 + w; col <= k; col += nw) {
-        const double s = wave_sum_strided(a.wpart + col, a.wpart_n, RMAX + 1);
+        const double s = wave_sum_contig(a.wpart + (int64_t)col * a.wpart_n, a.wpart_n);
         if (l == 0) tv[col] = s;
     }
     __syncthreads();
@@ -517,36 +528,30 @@ __global__ void __launch_bounds__(256) k_defl_init(DeflArgs a) {
     if (threadIdx.x == 0) a.rr_part[blockIdx.x] = rr;
 }
 
+// out[c] = sum_b part[c * n + b] (column-major partials), one block per column
 __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
-    for (int c = threadIdx.x; c < a.ncol; c += blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < a.n; ++b) s += a.part[(int64_t)b * a.st + c];
-        a.out[c] = s;
-    }
+    __shared__ double red[16];
+    const int c = blockIdx.x;
+    const double s = block_sum_contig(a.part + (int64_t)c * a.n, a.n, red);
+    if (threadIdx.x == 0) a.out[c] = s;
 }
 
 // ---------------------------------------------------------------------------
 // coarse problem (eq. coarse_problem); three levels: the multilevel paragraph
-// of Section 3.2, subdomains acting as the elements of subregions
+// of Section 3.2, subdomains acting as the elements of subregions.  Every
+// matrix here is symmetric and row-major; products read it column by column.
 // ---------------------------------------------------------------------------
 // Two levels: r_C = sum_i R_Ci^T c_i, u_C = K_C^{-1} r_C with the dense
-// inverse (stored negated by the sweep).  Block b computes rows
-// [64b, 64b + 64), each wave a quarter of the columns.
-__global__ void __launch_bounds__(256) k_coarse2(Coarse2Args a) {
+// inverse (stored negated by the sweep); block b computes rows [64b, 64b+64).
+__global__ void __launch_bounds__(1024) k_coarse2(Coarse2Args a) {
     extern __shared__ double rs[];
-    __shared__ double part[4][64];
+    __shared__ double part[16][64];
     if (a.ctl->done) return;
     for (int q = threadIdx.x; q < a.n; q += blockDim.x) rs[q] = gather_sum(a.rc, q);
     __syncthreads();
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int r = blockIdx.x * 64 + l;
-    const int q0 = (int)((int64_t)a.n * w / 4), q1 = (int)((int64_t)a.n * (w + 1) / 4);
-    double s = 0.0;
-    if (r < a.n)
-        for (int q = q0; q < q1; ++q) s += a.Kneg[(int64_t)q * a.n + r] * rs[q];
-    part[w][l] = s;
-    __syncthreads();
-    if (w == 0 && r < a.n) a.u[r] = -(part[0][l] + part[1][l] + part[2][l] + part[3][l]);
+    const int r0 = blockIdx.x * 64, r1 = min(a.n, r0 + 64);
+    double *u = a.u;
+    cm_matvec<16>(a.Kneg, a.n, r0, r1, a.n, rs, part, [&](int r, double y) { u[r] = -y; });
 }
 
 // Level 2, phase A (one block per subregion): the subregion's coarse
@@ -554,26 +559,25 @@ __global__ void __launch_bounds__(256) k_coarse2(Coarse2Args a) {
 // coupling t = K_BI K_II^{-1} r_I (from the swept subregion matrix).
 __global__ void __launch_bounds__(256) k_l2_a(L2Args a) {
     extern __shared__ double rL[];
+    __shared__ double part[4][64];
     if (a.ctl->done) return;
     const int j = blockIdx.x;
     const int nL = a.nL[j], nI = a.nI2[j];
     const int loff = a.L_off[j];
     for (int q = threadIdx.x; q < nL; q += blockDim.x) rL[q] = gather_sum(a.rc, a.L[loff + q]);
     __syncthreads();
-    const double *K = a.K2 + a.K2_off[j];
-    const int i2 = a.I2_off[j], b2 = a.B2_off[j];
-    for (int q = threadIdx.x; q < nL; q += blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < nI; ++b) s += K[(int64_t)q * nL + b] * rL[b];
-        if (q < nI) a.vI2[i2 + q] = -s;
-        else { a.t2[b2 + q - nI] = s; a.rB2[b2 + q - nI] = rL[q]; }
-    }
+    double *vI2 = a.vI2 + a.I2_off[j], *t2 = a.t2 + a.B2_off[j], *rB2 = a.rB2 + a.B2_off[j];
+    cm_matvec<4>(a.K2 + a.K2_off[j], nL, 0, nL, nI, rL, part, [&](int q, double y) {
+        if (q < nI) vI2[q] = -y;
+        else { t2[q - nI] = y; rB2[q - nI] = rL[q]; }
+    });
 }
 
 // Level 2, phase B (one block per subregion): level-2 interface residual
 // g = r_G - sum_j R_j^T t_j, then u = (D N D) g and c3 = (D Phi)^T g.
 __global__ void __launch_bounds__(256) k_l2_b(L2Args a) {
     extern __shared__ double gs[];
+    __shared__ double part[4][64];
     if (a.ctl->done) return;
     const int j = blockIdx.x;
     const int nB = a.nL[j] - a.nI2[j];
@@ -585,26 +589,16 @@ __global__ void __launch_bounds__(256) k_l2_b(L2Args a) {
         gs[k] = s;
     }
     __syncthreads();
-    const double *N = a.N2 + a.N2_off[j];
-    for (int k = threadIdx.x; k < nB; k += blockDim.x) {
-        double s = 0.0;
-        for (int q = 0; q < nB; ++q) s += N[(int64_t)k * nB + q] * gs[q];
-        a.u2[b2 + k] = s;
-    }
-    const int nc3 = a.nc3[j], c3o = a.C3_off[j];
-    const double *Ph = a.Phi2 + a.P2_off[j];
-    for (int q = threadIdx.x; q < nc3; q += blockDim.x) {
-        double s = 0.0;
-        for (int k = 0; k < nB; ++k) s += Ph[(int64_t)k * nc3 + q] * gs[k];
-        a.c3loc[c3o + q] = s;
-    }
+    double *u2 = a.u2 + b2, *c3 = a.c3loc + a.C3_off[j];
+    cm_matvec<4>(a.N2 + a.N2_off[j], nB, 0, nB, nB, gs, part, [&](int k, double y) { u2[k] = y; });
+    cm_matvec<4>(a.Phi2 + a.P2_off[j], a.nc3[j], 0, a.nc3[j], nB, gs, part, [&](int q, double y) { c3[q] = y; });
 }
 
 // Level 3: r3 = sum of the subregion contributions, u3 = K3^{-1} r3 (dense
-// inverse stored negated).  Same row/column split as k_coarse2.
-__global__ void __launch_bounds__(256) k_l3(L3Args a) {
+// inverse stored negated); block b computes rows [64b, 64b + 64).
+__global__ void __launch_bounds__(1024) k_l3(L3Args a) {
     extern __shared__ double rs[];
-    __shared__ double part[4][64];
+    __shared__ double part[16][64];
     if (a.ctl->done) return;
     for (int q = threadIdx.x; q < a.n; q += blockDim.x) {
         double s = 0.0;
@@ -612,15 +606,9 @@ __global__ void __launch_bounds__(256) k_l3(L3Args a) {
         rs[q] = s;
     }
     __syncthreads();
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int r = blockIdx.x * 64 + l;
-    const int q0 = (int)((int64_t)a.n * w / 4), q1 = (int)((int64_t)a.n * (w + 1) / 4);
-    double s = 0.0;
-    if (r < a.n)
-        for (int q = q0; q < q1; ++q) s += a.Kneg[(int64_t)q * a.n + r] * rs[q];
-    part[w][l] = s;
-    __syncthreads();
-    if (w == 0 && r < a.n) a.u[r] = -(part[0][l] + part[1][l] + part[2][l] + part[3][l]);
+    const int r0 = blockIdx.x * 64, r1 = min(a.n, r0 + 64);
+    double *u = a.u;
+    cm_matvec<16>(a.Kneg, a.n, r0, r1, a.n, rs, part, [&](int r, double y) { u[r] = -y; });
 }
 
 // Level 2, phase D (one block per subregion): level-2 interface solution
@@ -630,6 +618,7 @@ __global__ void __launch_bounds__(256) k_l3(L3Args a) {
 // subregion computes the same value in the same order).
 __global__ void __launch_bounds__(256) k_l2_d(L2Args a) {
     extern __shared__ double xg[];
+    __shared__ double part[4][64];
     if (a.ctl->done) return;
     const int j = blockIdx.x;
     const int nL = a.nL[j], nI = a.nI2[j], nB = nL - nI;
@@ -645,6 +634,7 @@ __global__ void __launch_bounds__(256) k_l2_d(L2Args a) {
             const double *ph = a.Phi2 + a.P2_off[jj] + (int64_t)kk * n3j;
             const int32_t *c3 = a.c3 + a.C3_off[jj];
             double v = a.u2[pos];
+#pragma unroll 8
             for (int q = 0; q < n3j; ++q) v += ph[q] * a.u3[c3[q]];
             s += v;
         }
@@ -652,13 +642,12 @@ __global__ void __launch_bounds__(256) k_l2_d(L2Args a) {
         if (a.own2[b2 + k]) a.uC[a.L[loff + nI + k]] = s;
     }
     __syncthreads();
-    const double *K = a.K2 + a.K2_off[j];
     const int i2 = a.I2_off[j];
-    for (int q = threadIdx.x; q < nI; q += blockDim.x) {
-        double s = a.vI2[i2 + q];
-        for (int k = 0; k < nB; ++k) s -= K[(int64_t)(nI + k) * nL + q] * xg[k];
-        a.uC[a.L[loff + q]] = s;
-    }
+    const double *vI2 = a.vI2 + i2;
+    const int32_t *L = a.L + loff;
+    double *uC = a.uC;
+    cm_matvec<4>(a.K2 + a.K2_off[j] + (int64_t)nI * nL, nL, 0, nI, nB, xg, part,
+                 [&](int q, double y) { uC[L[q]] = vI2[q] - y; });
 }
 
 // ---------------------------------------------------------------------------
@@ -706,23 +695,23 @@ void launch_update(const UpdArgs &a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_update, dim3(grid), dim3(256), 0, s, a);
 }
 
-int kmax_bucket(int k) { return k == 0 ? 0 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
-
-template <typename T>
-static void launch_zasm_t(const ZasmArgs &a, int kmax, int grid, hipStream_t s) {
-    switch (kmax) {
-        case 0: hipLaunchKernelGGL((k_zasm<T, 0>), dim3(grid), dim3(256), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((k_zasm<T, 8>), dim3(grid), dim3(256), 0, s, a); break;
-        case 16: hipLaunchKernelGGL((k_zasm<T, 16>), dim3(grid), dim3(256), 0, s, a); break;
-        case 32: hipLaunchKernelGGL((k_zasm<T, 32>), dim3(grid), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_zasm<T, 64>), dim3(grid), dim3(256), 0, s, a); break;
-    }
+void launch_prolong(const ProlArgs &a, int prec, int nsub, int max_nc, hipStream_t s) {
+    const size_t smem = (size_t)std::max(1, max_nc) * 8;
+    if (prec == 64) hipLaunchKernelGGL(k_prolong<double>, dim3(nsub), dim3(256), smem, s, a);
+    else if (prec == 32) hipLaunchKernelGGL(k_prolong<float>, dim3(nsub), dim3(256), smem, s, a);
+    else hipLaunchKernelGGL(k_prolong<uint16_t>, dim3(nsub), dim3(256), smem, s, a);
 }
 
-void launch_zasm(const ZasmArgs &a, int prec, int kmax, int grid, hipStream_t s) {
-    if (prec == 64) launch_zasm_t<double>(a, kmax, grid, s);
-    else if (prec == 32) launch_zasm_t<float>(a, kmax, grid, s);
-    else launch_zasm_t<uint16_t>(a, kmax, grid, s);
+int kmax_bucket(int k) { return k == 0 ? 0 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
+
+void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s) {
+    switch (kmax) {
+        case 0: hipLaunchKernelGGL(k_zasm<0>, dim3(grid), dim3(256), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(k_zasm<8>, dim3(grid), dim3(256), 0, s, a); break;
+        case 16: hipLaunchKernelGGL(k_zasm<16>, dim3(grid), dim3(256), 0, s, a); break;
+        case 32: hipLaunchKernelGGL(k_zasm<32>, dim3(grid), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_zasm<64>, dim3(grid), dim3(256), 0, s, a); break;
+    }
 }
 
 void launch_pupd(const PupdArgs &a, int grid, hipStream_t s) {
@@ -744,12 +733,12 @@ void launch_defl_init(const DeflArgs &a, int grid, hipStream_t s) {
 }
 
 void launch_reduce(const ReduceArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, a);
+    if (a.ncol > 0) hipLaunchKernelGGL(k_reduce, dim3(a.ncol), dim3(256), 0, s, a);
 }
 
 void launch_coarse2(const Coarse2Args &a, hipStream_t s) {
     if (a.n <= 0) return;
-    hipLaunchKernelGGL(k_coarse2, dim3((a.n + 63) / 64), dim3(256), (size_t)a.n * 8, s, a);
+    hipLaunchKernelGGL(k_coarse2, dim3((a.n + 63) / 64), dim3(1024), (size_t)a.n * 8, s, a);
 }
 
 void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
@@ -760,7 +749,7 @@ void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
 }
 void launch_l3(const L3Args &a, hipStream_t s) {
     if (a.n <= 0) return;
-    hipLaunchKernelGGL(k_l3, dim3((a.n + 63) / 64), dim3(256), (size_t)a.n * 8, s, a);
+    hipLaunchKernelGGL(k_l3, dim3((a.n + 63) / 64), dim3(1024), (size_t)a.n * 8, s, a);
 }
 void launch_l2_d(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
     hipLaunchKernelGGL(k_l2_d, dim3(nsr), dim3(256), (size_t)max_nL * 8, s, a);

@@ -36,15 +36,10 @@ struct OpDev {
     const int32_t *nchunk, *pb, *cb;
 };
 
-// Sum of the partial products of the owners of one assembled entry:
-// entries `pos` index local interface (b_off-based) or coarse (c_off-based)
-// positions, pos_sub maps them back to their subdomain.
+// Assembled entry t is the sum of part[idx[e]] for e in [ptr[t], ptr[t+1]):
+// the partial products of all work items of all owners, in a fixed order.
 struct Gather {
-    const int32_t *ptr, *idx;       // assembled entry -> positions
-    const int32_t *pos_sub;         // position -> subdomain
-    const int32_t *off;             // per subdomain: b_off (or c_off)
-    const int32_t *len;             // per subdomain: nB (or nc)
-    const int32_t *nchunk, *base;   // per subdomain: item count, partial base
+    const int32_t *ptr, *idx;
     const double *part;
 };
 
@@ -78,18 +73,25 @@ struct UpdArgs {                    // Alg. 1, lines 9-11
     int hist_cap;
 };
 
-struct ZasmArgs {                   // z = sum_i R_i^T D_i (u_i + Phi_i u_C), rho, (AW)^T z
-    int n;
-    Gather u;                       // local Neumann products (D N D r_i)
-    const int32_t *b_off, *nB;
+struct ProlArgs {                   // w_i = u_i + D Phi_i u_C (eq. averaging_subdomain_solves)
+    Ctl *ctl;
+    int gated;
+    const int32_t *nB, *b_off, *nc, *c_off, *cidx;
+    const int32_t *nchunk, *pb;     // Neumann work items per subdomain, partial bases
+    const double *upart;
     const void *phir;               // D Phi_i rows, local precision
     const int64_t *phr_off;
-    const int32_t *nc, *c_off, *cidx;
     const double *uC;               // level-1 coarse solution (nullable: no coarse space)
+    double *wloc;
+};
+
+struct ZasmArgs {                   // z = sum_i R_i^T w_i, rho, (AW)^T z
+    int n;
+    Gather w;
     const double *r;
     double *z;
     const double *AW; int64_t ld;
-    double *part;                   // nullable: per-block (r^T z, (AW)^T z)
+    double *part;                   // nullable: (r^T z, (AW)^T z) per block, column-major
     Ctl *ctl;
     int gated, advance;
 };
@@ -114,7 +116,7 @@ struct ResidArgs {                  // out = b - sum of the Schur partials
     double *out;
     const double *W; int64_t ld;
     Ctl *ctl;
-    double *part;                   // per-block (||out||^2, W^T out)
+    double *part;                   // (||out||^2, W^T out) per block, column-major
 };
 
 struct DeflArgs {                   // Alg. 1, lines 3-4
@@ -127,9 +129,9 @@ struct DeflArgs {                   // Alg. 1, lines 3-4
     Ctl *ctl;
 };
 
-struct ReduceArgs {                 // one block: out[c] = sum_b part[b * st + c]
+struct ReduceArgs {                 // out[c] = sum_b part[c * n + b]
     const double *part;
-    int n, st, ncol;
+    int n, ncol;
     double *out;
 };
 
@@ -242,7 +244,8 @@ size_t symv_smem(int prec, int nw, int max_nt, int max_ntc);
 int set_symv_smem_limit(size_t bytes);
 void launch_symv(const SymvArgs &a, int prec, SymvCfg cfg, size_t smem, hipStream_t s);
 void launch_update(const UpdArgs &a, int grid, hipStream_t s);
-void launch_zasm(const ZasmArgs &a, int prec, int kmax, int grid, hipStream_t s);
+void launch_prolong(const ProlArgs &a, int prec, int nsub, int max_nc, hipStream_t s);
+void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s);
 void launch_pupd(const PupdArgs &a, int grid, hipStream_t s);
 void launch_resid(const ResidArgs &a, int kmax, int grid, hipStream_t s);
 void launch_defl_init(const DeflArgs &a, int grid, hipStream_t s);

@@ -286,8 +286,8 @@ __global__ void __launch_bounds__(256) k_recycle_gemm(GemmArgs a) {
 }
 
 // Gram partials: block b sums X^T Y (k x k, X and Y column-major n x k) over
-// its row range, 32-row slabs staged in LDS; part[b][p*k+q].  A one-block
-// reduction finishes the (deterministic) sum.
+// its row range, 32-row slabs staged in LDS; part[(p*k+q) * nblocks + b].  A
+// column reduction finishes the (deterministic) sum.
 __global__ void __launch_bounds__(256) k_gram(GramArgs a) {
     __shared__ double xs[32][RMAX + 1];
     __shared__ double ys[32][RMAX + 1];
@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(256) k_gram(GramArgs a) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         const int pq = threadIdx.x + u * blockDim.x;
-        if (pq < npair) a.part[(int64_t)blockIdx.x * npair + pq] = acc[u];
+        if (pq < npair) a.part[(int64_t)pq * gridDim.x + blockIdx.x] = acc[u];
     }
 }
 
