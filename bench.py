@@ -65,7 +65,7 @@ def run_form(torch, Solver, s, F, rtol, steps, warmup, local_prec, timing, use_g
         st = g.stats()
         g.enable_timing(False)
     info = g.info()
-    return dict(g=g, U=U, its=its, rr=rr, elapsed=el, setup_s=setup_s, stats=st, info=info)
+    return dict(g=g, U=U, its=its, rr=rr, elapsed=el, setup_s=setup_s, stats=st, info=info, tuning=g.tuning())
 
 
 def cpu_baseline(s, F_np, n_sample):
@@ -148,6 +148,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": st[dom]["bytes"]},
         "kernel_ms_per_sequence_eager": {k: round(v["ms"], 3) for k, v in st.items() if v["count"]},
+        "tuning": f64["tuning"],
     }
     if not args.no_mixed:
         mx = run_form(torch, Solver, s, F, args.rtol, args.steps, args.warmup, 32, False)

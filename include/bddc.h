@@ -95,12 +95,15 @@ typedef struct {
                                 hipGraph and replayed, the convergence flag polled
                                 asynchronously; 0: kernels launched one by one with
                                 a host check after every iteration                     */
-    int32_t reserved[4];
+    int32_t autotune;        /* 1 (default): time a few work-list sizes, waves per
+                                block and tiles in flight of the two batched operator
+                                products at setup and keep the fastest; 0: fixed     */
+    int32_t reserved[3];
 } bddc_opts;
 
 /* Fills *o with the defaults: corners+faces, diag weights, float64 local
  * operators, R = 0, B4, freeze 1e-5, ||r||/||b||, previous-solution guess,
- * max_it 1000, save_cap 256, graph-captured iteration. */
+ * max_it 1000, save_cap 256, graph-captured iteration, autotuned products. */
 void bddc_default_opts(bddc_opts *o);
 
 /*
@@ -207,6 +210,14 @@ int bddc_interface_nodes(const bddc_ctx *ctx, int64_t *out);
  */
 int bddc_enable_timing(bddc_ctx *ctx, int32_t enable);
 int bddc_stats(const bddc_ctx *ctx, double *out, int32_t n);
+
+/*
+ * bddc_tuning -- configuration of the two batched operator products (host
+ * float64[12]): for the Schur operators then the Neumann operators, work
+ * items, items per compute unit, waves per block, tiles in flight per wave,
+ * fastest tuning launch in microseconds (0 without autotuning), tiles.
+ */
+int bddc_tuning(const bddc_ctx *ctx, double *out);
 
 /* Theta (selected harmonic Ritz values, host float64[R]) of the last update. */
 int bddc_ritz_values(const bddc_ctx *ctx, double *theta, int32_t cap, int32_t *count);

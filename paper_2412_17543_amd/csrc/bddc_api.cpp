@@ -38,6 +38,8 @@ struct OpHost {
     OpDev dev{};
     int prec = 64;
     SymvCfg cfg{4, 2};
+    int ipc = 6;                    // work items per compute unit
+    float tuned_us = 0.f;           // fastest tuning launch
     size_t smem = 0;
     int64_t n_tiles = 0;
     double bytes = 0;               // algorithmic bytes of one product
@@ -47,6 +49,21 @@ struct OpHost {
     int64_t ypart_len = 0, cpart_len = 0;
     // flat gather lists: interface node -> y partials, coarse DOF -> c partials
     int32_t *d_yptr = nullptr, *d_yidx = nullptr, *d_cptr = nullptr, *d_cidx = nullptr;
+};
+
+// Pinned host block filled by the per-solve synchronisation.
+struct SyncBuf {
+    Ctl ctl;
+    RecState rs;
+    double waw[RMAX * RMAX];
+};
+
+// Basis update enqueued but not yet confirmed by the device.
+struct Pending {
+    bool active = false;
+    int k = 0;
+    bool freeze = false;
+    std::vector<double> GWW, theta;
 };
 
 }  // namespace
@@ -63,6 +80,7 @@ struct bddc_ctx {
     size_t dev_bytes = 0;
     size_t bytes_S = 0, bytes_N = 0;
     int n_cu = 256;
+    bool allow8 = true;             // 8-wave product blocks fit in LDS
 
     // level 1
     int32_t *d_nB = nullptr, *d_nI = nullptr, *d_b_off = nullptr, *d_i_off = nullptr, *d_nc = nullptr,
@@ -97,19 +115,26 @@ struct bddc_ctx {
     int R = 0, k = 0, save_cap = 0, kmax = 0;
     int64_t ld = 0;
     double *d_W = nullptr, *d_AW = nullptr, *d_Wn = nullptr, *d_AWn = nullptr, *d_P = nullptr, *d_AP = nullptr;
-    double *d_WAWinv = nullptr, *d_Y = nullptr;
+    double *d_WAWinv = nullptr, *d_Y = nullptr, *d_WAWnew = nullptr, *d_WAWsym = nullptr, *d_invnew = nullptr;
+    RecState *d_state = nullptr;
     std::vector<double> WAW, GWW, theta;
     bool frozen = false;
-    int freeze_step = -1, n_updates = 0;
+    int freeze_step = -1, n_updates = 0, update_refused = 0, gram_nb = 1;
+    Pending pend;
     // histories of the last solve
     int hist_cap = 0;
     double *d_ahist = nullptr, *d_dhist = nullptr, *d_rhohist = nullptr, *d_bhist = nullptr, *d_muhist = nullptr,
            *d_reshist = nullptr;
     // control
-    Ctl *d_ctl = nullptr, *h_ctl = nullptr, *h_ctl_init = nullptr;
-    int32_t *h_flags = nullptr, *h_zero = nullptr;
+    Ctl *d_ctl = nullptr, *h_ctl = nullptr;
+    SyncBuf *h_sync = nullptr;      // pinned
+    double *h_hist = nullptr;       // pinned: alpha, d, rho (hcopy each), mu (hcopy x RMAX)
+    double *h_Y = nullptr;          // pinned staging of the recycling coefficients
+    int hcopy = 0;
+    int32_t *h_flags = nullptr;     // pinned, device-mapped: [0] convergence word
+    int32_t *d_hflag = nullptr;     // device address of h_flags[0]
     int32_t *d_status = nullptr;
-    bool have_solve = false;
+    bool have_solve = false, have_hist = false;
     int last_iters = 0, last_restarts = 0, last_status = 0;
     // graph of GRAPH_ITERS iterations
     hipGraph_t graph = nullptr;
@@ -296,14 +321,6 @@ int sync_ctl(bddc_ctx *c) {
     return 0;
 }
 
-int set_done(bddc_ctx *c, int v) {
-    HIPCHK(hipStreamSynchronize(c->stream));
-    *c->h_zero = v;
-    HIPCHK(hipMemcpyAsync(&c->d_ctl->done, c->h_zero, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    return 0;
-}
-
 Gather gather_of(const OpHost &op, bool coarse) {
     Gather g{};
     if (coarse) { g.ptr = op.d_cptr; g.idx = op.d_cidx; g.part = op.d_cpart; }
@@ -407,7 +424,7 @@ void run_pupd(bddc_ctx *c, bool first, bool hist_only, bool gated) {
     a.ctl = c->d_ctl;
     a.first = first ? 1 : 0; a.hist_only = hist_only ? 1 : 0; a.gated = gated ? 1 : 0;
     a.rho_hist = c->d_rhohist; a.b_hist = c->d_bhist; a.mu_hist = c->d_muhist; a.hist_cap = c->hist_cap;
-    launch_pupd(a, c->vgrid, c->stream);
+    launch_pupd(a, c->kmax, c->vgrid, c->stream);
 }
 
 void run_update(bddc_ctx *c) {
@@ -464,37 +481,29 @@ int capture_graph(bddc_ctx *c) {
     return 0;
 }
 
-// Iterate until ctl->done: graph replays with the convergence flag polled
-// through pinned memory a few graphs behind (use_graph), or eagerly launched
-// iterations with a host check after each one (plain form).
+// Iterate until ctl->done: graph replays, GRAPH_INFLIGHT graphs queued ahead
+// of the convergence check, which reads the pinned word the kernels set
+// together with ctl->done (use_graph); or eagerly launched iterations with a
+// host check after each one (plain form).
 int run_loop(bddc_ctx *c) {
     const int max_launch = c->opts.max_it + 2;
     if (c->opts.use_graph && !c->timing) {
         int rc = capture_graph(c);
         if (rc) return rc;
+        volatile int32_t *flag = c->h_flags;
         int launched = 0, polled = 0;
         const int cap = max_launch / GRAPH_ITERS + GRAPH_INFLIGHT + 1;
         while (true) {
             const int slot = launched % (GRAPH_INFLIGHT + 1);
             HIPCHK(hipGraphLaunch(c->gexec, c->stream));
-            HIPCHK(hipMemcpyAsync(&c->h_flags[slot], &c->d_ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipEventRecord(c->gev[slot], c->stream));
             ++launched;
             if (launched - polled >= GRAPH_INFLIGHT || launched >= cap) {
                 const int ps = polled % (GRAPH_INFLIGHT + 1);
                 HIPCHK(hipEventSynchronize(c->gev[ps]));
                 ++polled;
-                if (c->h_flags[ps]) break;
-                if (launched >= cap) {
-                    // every kernel stops at max_it; drain what is queued
-                    while (polled < launched) {
-                        const int q = polled % (GRAPH_INFLIGHT + 1);
-                        HIPCHK(hipEventSynchronize(c->gev[q]));
-                        ++polled;
-                        if (c->h_flags[q]) break;
-                    }
-                    break;
-                }
+                if (*flag) break;
+                if (launched >= cap) break;   // every kernel stops at max_it by itself
             }
         }
         return 0;
@@ -505,17 +514,6 @@ int run_loop(bddc_ctx *c) {
         if (rc) return rc;
         if (c->h_ctl->done) break;
     }
-    return 0;
-}
-
-int upload_ctl(bddc_ctx *c, double rtol, bool record) {
-    HIPCHK(hipStreamSynchronize(c->stream));   // the pinned staging copy may still be read
-    Ctl h{};
-    h.rtol2 = rtol * rtol;
-    h.k = c->k;
-    h.record = record ? 1 : 0;
-    *c->h_ctl_init = h;
-    HIPCHK(hipMemcpyAsync(c->d_ctl, c->h_ctl_init, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
     return 0;
 }
 
@@ -551,88 +549,122 @@ void run_true_residual(bddc_ctx *c, double *out) {
     launch_reduce(r, c->stream);
 }
 
-// One right-hand side: condense, Algorithm 1 from x_prev, recover.
-int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle, int *iters, double *relres) {
+// A basis update was enqueued after the previous solve; the device committed
+// it only if the new W^T A W was positive definite.  Adopt its outcome.
+void resolve_pending(bddc_ctx *c) {
+    if (!c->pend.active) return;
+    c->pend.active = false;
+    const SyncBuf &h = *c->h_sync;
+    if (h.rs.ok) {
+        const int k = c->pend.k;
+        c->k = k;
+        c->WAW.assign(h.waw, h.waw + (size_t)k * k);
+        c->GWW = c->pend.GWW;
+        c->theta = c->pend.theta;
+        if (c->pend.freeze) {
+            c->frozen = true;
+            c->freeze_step = c->n_updates;
+        }
+    } else {
+        c->update_refused++;   // W^T A W not positive definite: the old basis stays
+    }
+}
+
+// The one host synchronisation of a solve: control block, deflation state
+// and, when recording, the scalar histories of the solve.
+int end_sync(bddc_ctx *c, bool hist) {
+    HIPCHK(hipMemcpyAsync(&c->h_sync->ctl, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    if (c->R > 0) {
+        HIPCHK(hipMemcpyAsync(&c->h_sync->rs, c->d_state, sizeof(RecState), hipMemcpyDeviceToHost, c->stream));
+        if (c->pend.active)
+            HIPCHK(hipMemcpyAsync(c->h_sync->waw, c->d_WAWsym, (size_t)c->pend.k * c->pend.k * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream));
+    }
+    if (hist) {
+        const size_t n = (size_t)c->hcopy;
+        HIPCHK(hipMemcpyAsync(c->h_hist, c->d_ahist, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_hist + n, c->d_dhist, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_hist + 2 * n, c->d_rhohist, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_hist + 3 * n, c->d_muhist, n * RMAX * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *c->h_ctl = c->h_sync->ctl;
+    resolve_pending(c);
+    return 0;
+}
+
+// One right-hand side: condense (unless already done), Algorithm 1 from
+// x_prev, recover.  The stream is synchronised once, after the loop.
+int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle, bool condensed, int *iters,
+              double *relres) {
     const bool record = recycle && c->R > 0 && !c->frozen;
-    int rc = upload_ctl(c, rtol, record);
-    if (rc) return rc;
-    run_condense(c, F);                                  // b, ||b||^2 partials
+    const int strat = c->opts.recycle_strategy;
+    const bool want_hist = record && (strat == 3 || strat == 4);
+    *c->h_flags = 0;
+    launch_ctl_init(c->d_ctl, rtol * rtol, record ? 1 : 0, c->R > 0 ? c->d_state : nullptr, c->d_hflag, c->stream);
+    if (!condensed) run_condense(c, F);                  // b, ||b||^2 partials
     if (c->opts.init_guess == 1) launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
     run_schur(c, c->d_x, false, false);                  // r = b - A x_{-1}
-    run_resid(c, c->d_r, c->k > 0);
+    run_resid(c, c->d_r, c->R > 0);
     {
         TScope ts(c, TK_VEC);
         DeflArgs d{};                                     // Alg. 1 lines 3-4 (k = 0: ||r||^2 only)
         d.n = c->n_gamma; d.x = c->d_x; d.r = c->d_r; d.W = c->d_W; d.AW = c->d_AW; d.ld = c->ld;
         d.wpart = c->d_wp; d.wpart_n = c->vgrid; d.WAWinv = c->d_WAWinv; d.rr_part = c->d_rr; d.ctl = c->d_ctl;
-        launch_defl_init(d, c->vgrid, c->stream);
+        launch_defl_init(d, c->kmax, c->vgrid, c->stream);
     }
     run_precond(c, c->d_r, c->d_z, 2, false, false, true);  // first test, lines 5-6
     run_pupd(c, true, false, true);                         // line 7
-    int restarts = 0;
+    int restarts = 0, rc;
     while (true) {
         if ((rc = run_loop(c))) return rc;
-        if ((rc = sync_ctl(c))) return rc;
-        if (c->h_ctl->zero_rhs) launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
-        // true residual of the interface problem in float64
-        run_true_residual(c, c->d_tmp);
-        if ((rc = sync_ctl(c))) return rc;
+        run_true_residual(c, c->d_tmp);                  // float64 ||b - A x||
+        // z_l = M^{-1} r_l for the harmonic-Ritz matrices (Section 4.2):
+        // rho_l, mu_l recorded, direction index advanced
+        const bool extra = want_hist && restarts == 0;
+        if (extra) {
+            launch_set_done(c->d_ctl, 0, c->stream);
+            run_precond(c, c->d_r, c->d_z, 0, false, true, true);
+            run_pupd(c, false, true, false);
+        }
+        if ((rc = end_sync(c, extra))) return rc;
         const Ctl &h = *c->h_ctl;
+        if (h.zero_rhs) launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
         if (h.status != 0 || h.zero_rhs) break;
         if (h.true_rr < h.rtol2 * h.denom2 || h.iter >= c->opts.max_it) break;
         // residual replacement, then continue from line 5 (iterations keep counting)
         ++restarts;
         launch_copy(c->n_gamma, c->d_tmp, c->d_r, c->stream);
-        if ((rc = set_done(c, 0))) return rc;
-        run_precond(c, c->d_r, c->d_z, 0, false, true, true);
+        launch_set_done(c->d_ctl, 0, c->stream);
+        run_precond(c, c->d_r, c->d_z, 0, false, !extra, true);
         run_pupd(c, true, false, true);
+        *c->h_flags = 0;
     }
     const Ctl h = *c->h_ctl;
     c->last_iters = h.iter;
     c->last_restarts = restarts;
     c->last_status = h.status;
     c->have_solve = true;
+    c->have_hist = want_hist && restarts == 0;
     if (iters) *iters = h.iter;
-    if (relres) *relres = h.bb > 0 ? std::sqrt(h.true_rr / h.bb) : 0.0;
-    // z_l = M^{-1} r_l for the harmonic-Ritz matrices (Section 4.2): rho_l, mu_l
-    const int strat = c->opts.recycle_strategy;
-    if (record && h.status == 0 && restarts == 0 && h.iter > 0 && (strat == 3 || strat == 4)) {
-        if ((rc = set_done(c, 0))) return rc;
-        run_precond(c, c->d_r, c->d_z, 0, false, true, true);
-        run_pupd(c, false, true, false);
-    }
+    if (relres) *relres = (h.bb > 0 && !h.zero_rhs) ? std::sqrt(h.true_rr / h.bb) : 0.0;
     if ((rc = run_recover(c, u))) return rc;
     if (h.status == BDDC_EBREAKDOWN) return fail(BDDC_EBREAKDOWN, "PCG breakdown (r^T z <= 0, p^T A p <= 0 or NaN)");
     if (h.status == BDDC_ENOTCONV) return fail(BDDC_ENOTCONV, "max_it reached");
     return 0;
 }
 
-int refresh_waw(bddc_ctx *c, const double *W, const double *AW, int k, std::vector<double> &waw) {
-    if (k == 0) { waw.clear(); return 0; }
-    const int nb = std::max(1, std::min(256, (c->n_gamma + 1023) / 1024));
-    GramArgs g{};
-    g.n = c->n_gamma; g.k = k; g.ld = c->ld; g.X = W; g.Y = AW; g.part = c->d_gp;
-    launch_gram(g, nb, c->stream);
-    ReduceArgs r{};
-    r.part = c->d_gp; r.n = nb; r.ncol = k * k; r.out = c->d_Y;
-    launch_reduce(r, c->stream);
-    waw.resize((size_t)k * k);
-    HIPCHK(hipMemcpyAsync(waw.data(), c->d_Y, (size_t)k * k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    for (int i = 0; i < k; ++i)
-        for (int j = i + 1; j < k; ++j) waw[i * k + j] = waw[j * k + i] = 0.5 * (waw[i * k + j] + waw[j * k + i]);
-    return 0;
-}
-
-// W_new = [W, P] Y, AW_new = [AW, AP] Y; commit only if W_new^T A W_new is SPD.
-// The new basis is copied into the fixed W, AW buffers (captured graphs keep
-// their pointers).
-int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol) {
+// W_new = [W, P] Y, AW_new = [AW, AP] Y, then on the device: Gram W_new^T A W_new,
+// Cholesky and inverse, and the commit of W, AW and the inverse when it is
+// positive definite.  Nothing here waits for the device; the outcome is
+// adopted at the next synchronisation (resolve_pending).
+int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol, const std::vector<double> &gww,
+                const std::vector<double> &theta, bool freeze) {
     const int ldy = (ncol + 7) / 8 * 8;
-    std::vector<double> Yp((size_t)m * ldy, 0.0);
+    std::memset(c->h_Y, 0, (size_t)m * ldy * sizeof(double));
     for (int q = 0; q < m; ++q)
-        for (int j = 0; j < ncol; ++j) Yp[(size_t)q * ldy + j] = Y[(size_t)q * ncol + j];
-    HIPCHK(hipMemcpyAsync(c->d_Y, Yp.data(), Yp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        for (int j = 0; j < ncol; ++j) c->h_Y[(size_t)q * ldy + j] = Y[(size_t)q * ncol + j];
+    HIPCHK(hipMemcpyAsync(c->d_Y, c->h_Y, (size_t)m * ldy * sizeof(double), hipMemcpyHostToDevice, c->stream));
     const int l = m - c->k;
     GemmArgs g{};
     g.n = c->n_gamma; g.ld = c->ld; g.Y = c->d_Y; g.ncol = ncol; g.ldy = ldy;
@@ -640,32 +672,34 @@ int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol) {
     launch_recycle_gemm(g, c->stream);
     g.V1 = c->d_AW; g.V2 = c->d_AP; g.out = c->d_AWn;
     launch_recycle_gemm(g, c->stream);
-    HIPCHK(hipStreamSynchronize(c->stream));   // d_Y is reused by the Gram reduction
-    std::vector<double> waw;
-    int rc = refresh_waw(c, c->d_Wn, c->d_AWn, ncol, waw);
-    if (rc) return rc;
-    std::vector<double> L = waw;
-    if (!cholesky(L, ncol)) return fail(BDDC_ESINGULAR, "new W^T A W is not positive definite; basis kept");
-    // explicit inverse of W^T A W from its Cholesky factor (k x k, row-major)
-    std::vector<double> inv((size_t)ncol * ncol, 0.0), e(ncol);
-    for (int j = 0; j < ncol; ++j) {
-        std::fill(e.begin(), e.end(), 0.0);
-        e[j] = 1.0;
-        chol_solve(L, ncol, e.data());
-        for (int i = 0; i < ncol; ++i) inv[(size_t)i * ncol + j] = e[i];
-    }
-    for (int i = 0; i < ncol; ++i)
-        for (int j = i + 1; j < ncol; ++j) inv[(size_t)i * ncol + j] = inv[(size_t)j * ncol + i] =
-            0.5 * (inv[(size_t)i * ncol + j] + inv[(size_t)j * ncol + i]);
-    launch_copy((int64_t)ncol * c->ld, c->d_Wn, c->d_W, c->stream);
-    launch_copy((int64_t)ncol * c->ld, c->d_AWn, c->d_AW, c->stream);
-    c->k = ncol;
-    c->WAW = waw;
-    HIPCHK(hipMemcpyAsync(c->d_WAWinv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    const int nb = c->gram_nb;
+    GramArgs gr{};
+    gr.n = c->n_gamma; gr.k = ncol; gr.ld = c->ld; gr.X = c->d_Wn; gr.Y = c->d_AWn; gr.part = c->d_gp;
+    launch_gram(gr, nb, c->stream);
+    ReduceArgs r{};
+    r.part = c->d_gp; r.n = nb; r.ncol = ncol * ncol; r.out = c->d_WAWnew;
+    launch_reduce(r, c->stream);
+    CholArgs ch{};
+    ch.k = ncol; ch.waw = c->d_WAWnew; ch.waw_sym = c->d_WAWsym; ch.inv = c->d_invnew; ch.state = c->d_state;
+    launch_chol_inv(ch, c->stream);
+    CommitArgs cm{};
+    cm.n = (int64_t)ncol * c->ld; cm.ncol = ncol;
+    cm.Wn = c->d_Wn; cm.AWn = c->d_AWn; cm.inv_new = c->d_invnew;
+    cm.W = c->d_W; cm.AW = c->d_AW; cm.inv = c->d_WAWinv; cm.state = c->d_state;
+    launch_commit(cm, c->stream);
+    c->pend.active = true;
+    c->pend.k = ncol;
+    c->pend.GWW = gww;
+    c->pend.theta = theta;
+    c->pend.freeze = freeze;
     return 0;
 }
 
+// Recycling step after a solve (Section 4.2): B1/B2 select stored search
+// directions; B3/B4 solve the harmonic-Ritz problem (eq. harmonicRitz) on
+// V = [W, P] with the small matrices formed from the solve's own scalars,
+// keep the R smallest (B3) or largest (B4) values, and test eq.
+// harmritzstopcrit for freezing the basis.
 int do_recycle(bddc_ctx *c) {
     if (c->R == 0 || c->frozen || !c->have_solve) return 0;
     c->have_solve = false;
@@ -676,7 +710,6 @@ int do_recycle(bddc_ctx *c) {
     c->n_updates++;
     if (strat == 1 || strat == 2) {
         // B1: first R search directions; B2: sliding window of the last R
-        int ncol;
         std::vector<int> cols;
         if (strat == 1) {
             if (k >= c->R) return 0;
@@ -684,22 +717,16 @@ int do_recycle(bddc_ctx *c) {
         } else {
             for (int q = std::max(0, m - c->R); q < m; ++q) cols.push_back(q);
         }
-        ncol = (int)cols.size();
+        const int ncol = (int)cols.size();
         if (ncol == 0) return 0;
         std::vector<double> Y((size_t)m * ncol, 0.0);
         for (int j = 0; j < ncol; ++j) Y[(size_t)cols[j] * ncol + j] = 1.0;
-        return apply_basis(c, Y, m, ncol);
+        return apply_basis(c, Y, m, ncol, std::vector<double>(), std::vector<double>(), false);
     }
-    if (m == 0) return 0;
+    if (m == 0 || !c->have_hist) return 0;
     // scalars of the last solve
-    std::vector<double> al(l), dd(l), rho(l + 1), mu((size_t)(l + 1) * RMAX);
-    if (l > 0) {
-        HIPCHK(hipMemcpyAsync(al.data(), c->d_ahist, l * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipMemcpyAsync(dd.data(), c->d_dhist, l * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipMemcpyAsync(rho.data(), c->d_rhohist, (l + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipMemcpyAsync(mu.data(), c->d_muhist, (size_t)(l + 1) * RMAX * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-    }
+    const size_t hn = (size_t)c->hcopy;
+    const double *al = c->h_hist, *dd = c->h_hist + hn, *rho = c->h_hist + 2 * hn, *mu = c->h_hist + 3 * hn;
     // F = V^T A V = blockdiag(W^T A W, diag(d)) and G = V^T A M^{-1} A V from the
     // recurrences of Algorithm 1: M^{-1} A p_j = (z_j - z_{j+1}) / alpha_j
     std::vector<double> F((size_t)m * m, 0.0), G((size_t)m * m, 0.0);
@@ -726,7 +753,10 @@ int do_recycle(bddc_ctx *c) {
             G[(size_t)(k + j) * m + i] = s;
         }
     }
-    // generalized eigenproblem G y = theta F y (eq. harmonicRitz)
+    for (size_t e = 0; e < G.size(); ++e)
+        if (!std::isfinite(G[e]) || !std::isfinite(F[e])) return 0;   // keep the basis
+    // generalized eigenproblem G y = theta F y: F = U diag(lam) U^T, directions
+    // with lam < 1e-12 max dropped, T = U lam^{-1/2}, H = T^T G T
     std::vector<double> lam, U;
     jacobi_eig(F, m, lam, U);
     const double lmax = *std::max_element(lam.begin(), lam.end());
@@ -780,26 +810,33 @@ int do_recycle(bddc_ctx *c) {
             }
             gww[(size_t)i * ncol + j] = s;
         }
-    int rc = apply_basis(c, Y, m, ncol);
-    if (rc) return rc;
-    c->GWW = gww;
     // freeze test (eq. harmritzstopcrit) on the sorted selected values
+    bool freeze = false;
     if ((int)c->theta.size() == c->R && ncol == c->R) {
         double num = 0.0, den = 0.0;
         for (int j = 0; j < ncol; ++j) {
             num += (thsel[j] - c->theta[j]) * (thsel[j] - c->theta[j]);
             den += thsel[j] * thsel[j];
         }
-        if (std::sqrt(num) <= c->opts.ritz_freeze_tol * std::sqrt(den)) {
-            c->frozen = true;
-            c->freeze_step = c->n_updates;
-        }
+        freeze = std::sqrt(num) <= c->opts.ritz_freeze_tol * std::sqrt(den);
     }
-    c->theta = thsel;
+    return apply_basis(c, Y, m, ncol, gww, thsel, freeze);
+}
+
+// Wait for the device and adopt a pending basis update (end of a sequence).
+int settle(bddc_ctx *c) {
+    if (c->R > 0 && c->pend.active) {
+        HIPCHK(hipMemcpyAsync(&c->h_sync->rs, c->d_state, sizeof(RecState), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_sync->waw, c->d_WAWsym, (size_t)c->pend.k * c->pend.k * sizeof(double),
+                              hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    resolve_pending(c);
     return 0;
 }
 
 }  // namespace
+
 
 // ======================================================================== ABI
 extern "C" {
@@ -817,6 +854,7 @@ void bddc_default_opts(bddc_opts *o) {
     o->max_it = 1000;
     o->save_cap = 256;
     o->use_graph = 1;
+    o->autotune = 1;
 }
 
 const char *bddc_last_error(void) { return g_err.c_str(); }
@@ -862,12 +900,61 @@ int setup_operators(bddc_ctx *c) {
         int rc = build_worklist(c, op, item_target(c, op.n_tiles, 6));
         if (rc) return rc;
     }
-    const size_t lim = std::max(symv_smem(64, 8, c->max_nt, 0), symv_smem(c->prec, 8, c->max_nt, c->max_ntc));
-    if (lim > 160 * 1024) return fail(BDDC_EINVAL, "a subdomain interface is too large for the LDS-staged products");
-    if (set_symv_smem_limit(lim)) return fail(BDDC_EHIP, "hipFuncSetAttribute (dynamic LDS) failed");
+    const size_t need4 = std::max(symv_smem(64, 4, c->max_nt, 0), symv_smem(c->prec, 4, c->max_nt, c->max_ntc));
+    const size_t need8 = std::max(symv_smem(64, 8, c->max_nt, 0), symv_smem(c->prec, 8, c->max_nt, c->max_ntc));
+    if (need4 > 160 * 1024) return fail(BDDC_EINVAL, "a subdomain interface is too large for the LDS-staged products");
+    c->allow8 = need8 <= 160 * 1024;
+    if (set_symv_smem_limit(c->allow8 ? need8 : need4)) return fail(BDDC_EHIP, "hipFuncSetAttribute (dynamic LDS) failed");
     c->t_bytes[TK_SCHUR] = c->opS.bytes;
     c->t_bytes[TK_PREC] = c->opN.bytes;
     return 0;
+}
+
+// Tile-level autotuning of the two batched products on the operators just
+// built: work-list granularity (items per compute unit), waves per block and
+// tiles in flight per wave; the fastest of a few timed launches is kept.
+int tune_operators(bddc_ctx *c) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int rc = 0;
+    const int ipcs[4] = {2, 4, 8, 16};
+    OpHost *ops[2] = {&c->opS, &c->opN};
+    for (int w = 0; w < 2 && rc == 0; ++w) {
+        OpHost &op = *ops[w];
+        const int ntc = op.dev.nc ? c->max_ntc : 0;
+        float best = 1e30f;
+        int best_ipc = 6;
+        SymvCfg best_cfg{4, 2};
+        for (int ipc : ipcs) {
+            if ((rc = build_worklist(c, op, item_target(c, op.n_tiles, ipc)))) break;
+            for (int nw : {4, 8}) {
+                if (nw == 8 && !c->allow8) continue;
+                for (int u : {2, 4}) {
+                    const SymvCfg cfg{nw, u};
+                    const size_t smem = symv_smem(op.prec, nw, c->max_nt, ntc);
+                    SymvArgs a{};
+                    a.op = op.dev; a.x = c->d_x; a.ypart = op.d_ypart; a.cpart = op.d_cpart; a.ctl = c->d_ctl;
+                    for (int r = 0; r < 2; ++r) launch_symv(a, op.prec, cfg, smem, c->stream);
+                    HIPCHK(hipEventRecord(e0, c->stream));
+                    for (int r = 0; r < 4; ++r) launch_symv(a, op.prec, cfg, smem, c->stream);
+                    HIPCHK(hipEventRecord(e1, c->stream));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) { best = ms; best_ipc = ipc; best_cfg = cfg; }
+                }
+            }
+        }
+        if (rc == 0) rc = build_worklist(c, op, item_target(c, op.n_tiles, best_ipc));
+        op.cfg = best_cfg;
+        op.ipc = best_ipc;
+        op.smem = symv_smem(op.prec, best_cfg.nw, c->max_nt, ntc);
+        op.tuned_us = best * 1e3f / 4;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, const double *coef) {
@@ -1277,6 +1364,8 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
     c->hist_cap = c->opts.max_it + 2;
     c->vgrid = std::max(1, std::min(VGRID, (ng + 255) / 256));
     const int gram_nb = std::max(1, std::min(256, (ng + 1023) / 1024));
+    c->gram_nb = gram_nb;
+    c->hcopy = std::min(c->hist_cap, c->save_cap + 2);
     if ((rc = dalloc(c, &c->d_b, ng)) || (rc = dalloc(c, &c->d_x, ng)) || (rc = dalloc(c, &c->d_r, ng)) ||
         (rc = dalloc(c, &c->d_z, ng)) || (rc = dalloc(c, &c->d_p, ng)) || (rc = dalloc(c, &c->d_tmp, ng)) ||
         (rc = dalloc(c, &c->d_locq, (size_t)b_off[nsub])) || (rc = dalloc(c, &c->d_wloc, (size_t)b_off[nsub])) ||
@@ -1284,20 +1373,24 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         (rc = dalloc(c, &c->d_rr, (size_t)c->vgrid)) || (rc = dalloc(c, &c->d_bbp, (size_t)c->vgrid)) ||
         (rc = dalloc(c, &c->d_zp, (size_t)c->vgrid * (RMAX + 1))) ||
         (rc = dalloc(c, &c->d_wp, (size_t)c->vgrid * (RMAX + 1))) ||
-        (rc = dalloc(c, &c->d_dotS, (size_t)c->opS.dev.n_items)) ||
         (rc = dalloc(c, &c->d_gp, (size_t)gram_nb * RMAX * RMAX)) ||
         (rc = dalloc(c, &c->d_ctl, 1)) || (rc = dalloc(c, &c->d_ahist, c->hist_cap)) ||
         (rc = dalloc(c, &c->d_dhist, c->hist_cap)) || (rc = dalloc(c, &c->d_rhohist, c->hist_cap)) ||
         (rc = dalloc(c, &c->d_bhist, c->hist_cap)) || (rc = dalloc(c, &c->d_reshist, c->hist_cap)) ||
-        (rc = dalloc(c, &c->d_muhist, (size_t)c->hist_cap * RMAX)) || (rc = dalloc(c, &c->d_WAWinv, RMAX * RMAX)))
+        (rc = dalloc(c, &c->d_muhist, (size_t)c->hist_cap * RMAX)) || (rc = dalloc(c, &c->d_WAWinv, RMAX * RMAX)) ||
+        (rc = dalloc(c, &c->d_WAWnew, RMAX * RMAX)) || (rc = dalloc(c, &c->d_WAWsym, RMAX * RMAX)) ||
+        (rc = dalloc(c, &c->d_invnew, RMAX * RMAX)) || (rc = dalloc(c, &c->d_state, 1)))
         return rc;
     HIPCHK(hipMemsetAsync(c->d_x, 0, ng * sizeof(double), s));
     HIPCHK(hipMemsetAsync(c->d_p, 0, ng * sizeof(double), s));
     HIPCHK(hipMemsetAsync(c->d_ctl, 0, sizeof(Ctl), s));
+    HIPCHK(hipMemsetAsync(c->d_state, 0, sizeof(RecState), s));
     HIPCHK(hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void **)&c->h_ctl_init, sizeof(Ctl), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void **)&c->h_flags, sizeof(int32_t) * (GRAPH_INFLIGHT + 2), hipHostMallocDefault));
-    c->h_zero = c->h_flags + GRAPH_INFLIGHT + 1;
+    HIPCHK(hipHostMalloc((void **)&c->h_sync, sizeof(SyncBuf), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c->h_hist, sizeof(double) * (size_t)c->hcopy * (3 + RMAX), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c->h_flags, sizeof(int32_t) * 4, hipHostMallocMapped));
+    HIPCHK(hipHostGetDevicePointer((void **)&c->d_hflag, c->h_flags, 0));
+    c->h_flags[0] = 0;
     {
         // W, AW always exist (k = 0 columns are never read); the recycling
         // buffers only with R > 0
@@ -1306,11 +1399,14 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         if ((rc = dalloc(c, &c->d_W, cols * ng)) || (rc = dalloc(c, &c->d_AW, cols * ng)) ||
             (rc = dalloc(c, &c->d_Y, (size_t)ymax)))
             return rc;
+        HIPCHK(hipHostMalloc((void **)&c->h_Y, sizeof(double) * (size_t)ymax, hipHostMallocDefault));
         if (c->R > 0 && ((rc = dalloc(c, &c->d_Wn, cols * ng)) || (rc = dalloc(c, &c->d_AWn, cols * ng)) ||
                          (rc = dalloc(c, &c->d_P, (size_t)std::max(1, c->save_cap) * ng)) ||
                          (rc = dalloc(c, &c->d_AP, (size_t)std::max(1, c->save_cap) * ng))))
             return rc;
     }
+    if (c->opts.autotune && (rc = tune_operators(c))) return rc;
+    if ((rc = dalloc(c, &c->d_dotS, (size_t)c->opS.dev.n_items))) return rc;
     HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     for (auto &e : c->gev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // element data for the adjoint gradient
@@ -1363,27 +1459,35 @@ int dpcg_solve(bddc_ctx *c, const double *rhs_seq, int32_t n_rhs, double rtol, d
                double *true_relres) {
     if (!c || (!rhs_seq && n_rhs > 0) || (!x_seq && n_rhs > 0) || n_rhs < 0 || !(rtol > 0))
         return fail(BDDC_EINVAL, "bad dpcg_solve argument");
+    bool condensed = false;
     for (int k = 0; k < n_rhs; ++k) {
         int it = 0;
         double rr = 0.0;
-        int rc = solve_one(c, rhs_seq + (size_t)k * c->n_nodes, x_seq + (size_t)k * c->n_nodes, rtol, true, &it, &rr);
+        int rc = solve_one(c, rhs_seq + (size_t)k * c->n_nodes, x_seq + (size_t)k * c->n_nodes, rtol, true, condensed,
+                           &it, &rr);
         if (iters) iters[k] = it;
         if (true_relres) true_relres[k] = rr;
-        if (rc) { if (c->timing) { (void)hipStreamSynchronize(c->stream); flush_timing(c); } return rc; }
+        if (rc) { (void)settle(c); if (c->timing) flush_timing(c); return rc; }
+        // the next right-hand side is condensed while the host solves the
+        // small recycling eigenproblem
+        condensed = k + 1 < n_rhs;
+        if (condensed) run_condense(c, rhs_seq + (size_t)(k + 1) * c->n_nodes);
         {
             TScope ts(c, TK_REC);
             rc = do_recycle(c);
         }
-        if (rc) { if (c->timing) { (void)hipStreamSynchronize(c->stream); flush_timing(c); } return rc; }
+        if (rc) { (void)settle(c); if (c->timing) flush_timing(c); return rc; }
     }
-    HIPCHK(hipStreamSynchronize(c->stream));
+    int rc = settle(c);
     if (c->timing) flush_timing(c);
-    return 0;
+    return rc;
 }
 
 int recycle_update(bddc_ctx *c) {
     if (!c) return fail(BDDC_EINVAL, "null context");
-    return do_recycle(c);
+    int rc = do_recycle(c);
+    if (rc) return rc;
+    return settle(c);
 }
 
 int bddc_reset_recycle(bddc_ctx *c) {
@@ -1395,8 +1499,11 @@ int bddc_reset_recycle(bddc_ctx *c) {
     c->frozen = false;
     c->freeze_step = -1;
     c->n_updates = 0;
+    c->update_refused = 0;
     c->have_solve = false;
-    HIPCHK(hipMemsetAsync(c->d_x, 0, c->n_gamma * sizeof(double), c->stream));
+    c->pend = Pending();
+    launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
+    if (c->d_state) launch_set_state(c->d_state, 0, 1, c->stream);
     HIPCHK(hipStreamSynchronize(c->stream));
     return 0;
 }
@@ -1412,7 +1519,8 @@ int bddc_adjoint_grad(bddc_ctx *c, const double *dLdu_seq, int32_t n_rhs, const 
     launch_copy(c->n_gamma, c->d_x, xsave, c->stream);
     launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
     for (int k = 0; k < n_rhs && rc == 0; ++k)
-        rc = solve_one(c, dLdu_seq + (size_t)k * c->n_nodes, grad_rhs_seq + (size_t)k * c->n_nodes, rtol, false, nullptr, nullptr);
+        rc = solve_one(c, dLdu_seq + (size_t)k * c->n_nodes, grad_rhs_seq + (size_t)k * c->n_nodes, rtol, false, false,
+                       nullptr, nullptr);
     c->have_solve = false;
     launch_copy(c->n_gamma, xsave, c->d_x, c->stream);
     if (rc == 0) {
@@ -1440,8 +1548,7 @@ int bddc_apply_schur(bddc_ctx *c, const double *p, double *q) {
 
 int bddc_apply_precond(bddc_ctx *c, const double *r, double *z) {
     if (!c || !r || !z) return fail(BDDC_EINVAL, "null argument");
-    int rc = set_done(c, 0);
-    if (rc) return rc;
+    launch_set_done(c->d_ctl, 0, c->stream);
     run_precond(c, r, z, 0, false, false, false);
     HIPCHK(hipStreamSynchronize(c->stream));
     return 0;
@@ -1501,6 +1608,20 @@ int bddc_stats(const bddc_ctx *c, double *out, int32_t n) {
     return 0;
 }
 
+int bddc_tuning(const bddc_ctx *c, double *out) {
+    if (!c || !out) return fail(BDDC_EINVAL, "null argument");
+    const OpHost *ops[2] = {&c->opS, &c->opN};
+    for (int w = 0; w < 2; ++w) {
+        out[6 * w + 0] = ops[w]->dev.n_items;
+        out[6 * w + 1] = ops[w]->ipc;
+        out[6 * w + 2] = ops[w]->cfg.nw;
+        out[6 * w + 3] = ops[w]->cfg.unroll;
+        out[6 * w + 4] = ops[w]->tuned_us;
+        out[6 * w + 5] = (double)ops[w]->n_tiles;
+    }
+    return 0;
+}
+
 int bddc_ritz_values(const bddc_ctx *c, double *theta, int32_t cap, int32_t *count) {
     if (!c || !count) return fail(BDDC_EINVAL, "null argument");
     *count = (int32_t)c->theta.size();
@@ -1520,7 +1641,9 @@ void bddc_destroy(bddc_ctx *c) {
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->h_ctl) (void)hipHostFree(c->h_ctl);
-    if (c->h_ctl_init) (void)hipHostFree(c->h_ctl_init);
+    if (c->h_sync) (void)hipHostFree(c->h_sync);
+    if (c->h_hist) (void)hipHostFree(c->h_hist);
+    if (c->h_Y) (void)hipHostFree(c->h_Y);
     if (c->h_flags) (void)hipHostFree(c->h_flags);
     for (auto &p : c->pending) { (void)hipEventDestroy(p.second.first); (void)hipEventDestroy(p.second.second); }
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);

@@ -59,6 +59,35 @@ __device__ __forceinline__ double block_sum_contig(const double *p, int n, doubl
     return block_sum(strided_part(p, n, threadIdx.x, blockDim.x), sh);
 }
 
+// Block-wide sums of the per-thread values acc[0..ncol) (ncol <= NC, a block
+// of exactly 256 threads): 16 columns at a time are transposed through LDS
+// (lds: 16 * 256 doubles), thread (u, j) adds the entries j, j + 16, ... of
+// column u (consecutive lanes read consecutive words) and a four-step
+// butterfly finishes; res[q] (LDS, NC doubles) receives column q.  Fixed
+// order; every thread may read res after the call.
+template <int NC>
+__device__ __forceinline__ void block_sum_cols(const double (&acc)[NC], int ncol, double *lds, double *res) {
+    const int t = threadIdx.x, u = t >> 4, j = t & 15;
+#pragma unroll
+    for (int q0 = 0; q0 < NC; q0 += 16) {
+        if (q0 < ncol) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                if (q0 + v < NC) lds[v * 256 + t] = acc[q0 + v < NC ? q0 + v : 0];
+            __syncthreads();
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) s += lds[u * 256 + i * 16 + j];
+            s += __shfl_xor(s, 8);
+            s += __shfl_xor(s, 4);
+            s += __shfl_xor(s, 2);
+            s += __shfl_xor(s, 1);
+            if (j == 0 && q0 + u < ncol) res[q0 + u] = s;
+            __syncthreads();
+        }
+    }
+}
+
 __device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
 
 // Q1 reference stiffness on the unit cube: 1/3 on the diagonal, 0 between

@@ -27,6 +27,7 @@
 namespace bddc {
 
 using dev::block_sum;
+using dev::block_sum_cols;
 using dev::block_sum_contig;
 using dev::wave_sum;
 using dev::wave_sum_contig;
@@ -141,7 +142,7 @@ __device__ bool stop_test(const SymvArgs &a) {
                 if (a.res_hist && iter < a.hist_cap) a.res_hist[iter] = rr;
                 if (bad) c->status = BDDC_EBREAKDOWN;
                 else if (!conv && maxed) c->status = BDDC_ENOTCONV;
-                if (stop) c->done = 1;
+                if (stop) ctl_finish(c);
             }
         }
     }
@@ -317,7 +318,7 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs a) {
         c->pAp = pAp;
         c->alpha = alpha;
         if (j < a.hist_cap) { a.d_hist[j] = pAp; a.a_hist[j] = alpha; }
-        if (bad) { c->status = BDDC_EBREAKDOWN; c->done = 1; }
+        if (bad) { c->status = BDDC_EBREAKDOWN; ctl_finish(c); }
     }
     if (bad) return;
     const bool rec = a.AP && c->record && j < a.cap;
@@ -372,7 +373,8 @@ __global__ void __launch_bounds__(256) k_prolong(ProlArgs a) {
 // ---------------------------------------------------------------------------
 template <int KM>
 __global__ void __launch_bounds__(256) k_zasm(ZasmArgs a) {
-    __shared__ double wacc[4][KM + 1];
+    __shared__ double lds[16 * 256];
+    __shared__ double res[KM + 1];
     Ctl *c = a.ctl;
     if (a.gated && c->done) return;
     if (a.advance && blockIdx.x == 0 && threadIdx.x == 0) c->j = c->j + 1;
@@ -392,20 +394,8 @@ __global__ void __launch_bounds__(256) k_zasm(ZasmArgs a) {
         }
     }
     if (!a.part) return;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-#pragma unroll
-    for (int q = 0; q <= KM; ++q) {
-        if (q <= k) {
-            const double v = wave_sum(acc[q]);
-            if (l == 0) wacc[w][q] = v;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x <= k) {
-        double s = 0.0;
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += wacc[q][threadIdx.x];
-        a.part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
-    }
+    block_sum_cols<KM + 1>(acc, k + 1, lds, res);
+    if (threadIdx.x <= k) a.part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = res[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -415,18 +405,25 @@ __global__ void __launch_bounds__(256) k_zasm(ZasmArgs a) {
 // mu for the recycling step.  `hist_only` records without updating p (the
 // extra preconditioner application after convergence).
 // ---------------------------------------------------------------------------
+template <int KM>
 __global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
-    __shared__ double tv[RMAX + 1];
+    __shared__ double lds[16 * 256];
+    __shared__ double tv[KM + 1];
     __shared__ double mu[RMAX];
     Ctl *c = a.ctl;
     if (a.gated && c->done) return;
     const int k = c->k, j = c->j;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
-    for (int col = w; col <= k; col += nw) {
-        const double s = wave_sum_contig(a.zpart + (int64_t)col * a.zpart_n, a.zpart_n);
-        if (l == 0) tv[col] = s;
+    {
+        double acc[KM + 1];
+#pragma unroll
+        for (int q = 0; q <= KM; ++q) acc[q] = 0.0;
+        for (int b = threadIdx.x; b < a.zpart_n; b += blockDim.x) {
+#pragma unroll
+            for (int q = 0; q <= KM; ++q)
+                if (q <= k) acc[q] += a.zpart[(int64_t)q * a.zpart_n + b];
+        }
+        block_sum_cols<KM + 1>(acc, k + 1, lds, tv);
     }
-    __syncthreads();
     if (threadIdx.x < k) {
         double s = 0.0;
         for (int q = 0; q < k; ++q) s += a.WAWinv[threadIdx.x * k + q] * tv[1 + q];
@@ -440,7 +437,7 @@ __global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
         if (threadIdx.x == 0) {
             if (j < a.hist_cap) a.rho_hist[j] = rho;
             if (!a.first && j >= 1 && j - 1 < a.hist_cap) a.b_hist[j - 1] = beta;
-            if (bad && !a.hist_only) { c->status = BDDC_EBREAKDOWN; c->done = 1; }
+            if (bad && !a.hist_only) { c->status = BDDC_EBREAKDOWN; ctl_finish(c); }
         }
         if (threadIdx.x < k && j < a.hist_cap) a.mu_hist[(int64_t)j * RMAX + threadIdx.x] = mu[threadIdx.x];
     }
@@ -462,7 +459,8 @@ __global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
 // ---------------------------------------------------------------------------
 template <int KM>
 __global__ void __launch_bounds__(256) k_resid(ResidArgs a) {
-    __shared__ double wacc[4][KM + 1];
+    __shared__ double lds[16 * 256];
+    __shared__ double res[KM + 1];
     const int k = a.want_wtr ? a.ctl->k : 0;
     double acc[KM + 1];
 #pragma unroll
@@ -477,35 +475,30 @@ __global__ void __launch_bounds__(256) k_resid(ResidArgs a) {
         for (int q2 = 0; q2 < KM; ++q2)
             if (q2 < k) acc[1 + q2] += a.W[(int64_t)q2 * a.ld + g] * r;
     }
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-#pragma unroll
-    for (int q = 0; q <= KM; ++q) {
-        if (q <= k) {
-            const double v = wave_sum(acc[q]);
-            if (l == 0) wacc[w][q] = v;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x <= k) {
-        double s = 0.0;
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += wacc[q][threadIdx.x];
-        a.part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
-    }
+    block_sum_cols<KM + 1>(acc, k + 1, lds, res);
+    if (threadIdx.x <= k) a.part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = res[threadIdx.x];
 }
 
 // Alg. 1 lines 3-4: gamma = (W^T A W)^{-1} W^T r (every block, from the
 // k_resid partials); x += W gamma; r -= AW gamma (= b - A x_0); ||r||^2.
+template <int KM>
 __global__ void __launch_bounds__(256) k_defl_init(DeflArgs a) {
-    __shared__ double tv[RMAX + 1];
+    __shared__ double lds[16 * 256];
+    __shared__ double tv[KM + 1];
     __shared__ double gam[RMAX];
     __shared__ double red[16];
     const int k = a.ctl->k;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
-    for (int col = 1 + w; col <= k; col += nw) {
-        const double s = wave_sum_contig(a.wpart + (int64_t)col * a.wpart_n, a.wpart_n);
-        if (l == 0) tv[col] = s;
+    {
+        double acc[KM + 1];
+#pragma unroll
+        for (int q = 0; q <= KM; ++q) acc[q] = 0.0;
+        for (int b = threadIdx.x; b < a.wpart_n; b += blockDim.x) {
+#pragma unroll
+            for (int q = 0; q <= KM; ++q)
+                if (q <= k) acc[q] += a.wpart[(int64_t)q * a.wpart_n + b];
+        }
+        block_sum_cols<KM + 1>(acc, k + 1, lds, tv);
     }
-    __syncthreads();
     if (threadIdx.x < k) {
         double s = 0.0;
         for (int q = 0; q < k; ++q) s += a.WAWinv[threadIdx.x * k + q] * tv[1 + q];
@@ -714,8 +707,14 @@ void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s) {
     }
 }
 
-void launch_pupd(const PupdArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_pupd, dim3(grid), dim3(256), 0, s, a);
+void launch_pupd(const PupdArgs &a, int kmax, int grid, hipStream_t s) {
+    switch (kmax) {
+        case 0: hipLaunchKernelGGL(k_pupd<0>, dim3(grid), dim3(256), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(k_pupd<8>, dim3(grid), dim3(256), 0, s, a); break;
+        case 16: hipLaunchKernelGGL(k_pupd<16>, dim3(grid), dim3(256), 0, s, a); break;
+        case 32: hipLaunchKernelGGL(k_pupd<32>, dim3(grid), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_pupd<64>, dim3(grid), dim3(256), 0, s, a); break;
+    }
 }
 
 void launch_resid(const ResidArgs &a, int kmax, int grid, hipStream_t s) {
@@ -728,8 +727,14 @@ void launch_resid(const ResidArgs &a, int kmax, int grid, hipStream_t s) {
     }
 }
 
-void launch_defl_init(const DeflArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_defl_init, dim3(grid), dim3(256), 0, s, a);
+void launch_defl_init(const DeflArgs &a, int kmax, int grid, hipStream_t s) {
+    switch (kmax) {
+        case 0: hipLaunchKernelGGL(k_defl_init<0>, dim3(grid), dim3(256), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(k_defl_init<8>, dim3(grid), dim3(256), 0, s, a); break;
+        case 16: hipLaunchKernelGGL(k_defl_init<16>, dim3(grid), dim3(256), 0, s, a); break;
+        case 32: hipLaunchKernelGGL(k_defl_init<32>, dim3(grid), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_defl_init<64>, dim3(grid), dim3(256), 0, s, a); break;
+    }
 }
 
 void launch_reduce(const ReduceArgs &a, hipStream_t s) {

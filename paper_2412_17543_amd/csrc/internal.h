@@ -143,7 +143,20 @@ struct Ctl {
     int32_t record;         // store P, AP for recycling
     int32_t zero_rhs;       // b == 0: the solution is x = 0
     int32_t pad;
+    int32_t *hflag;         // pinned host word set to 1 together with `done`
 };
+
+// Deflation-basis state kept on the device between solves: the columns in
+// use and the outcome of the last basis update (1: committed).
+struct RecState {
+    int32_t k, ok;
+};
+
+// Marks the solve finished; the host polls hflag instead of copying ctl.
+__device__ inline void ctl_finish(Ctl *c) {
+    c->done = 1;
+    if (c->hflag) *reinterpret_cast<volatile int32_t *>(c->hflag) = 1;
+}
 
 // Element index of entry (r, c) inside a 16x16 operator tile.  Lane
 // l = 16 (r / 4) + c of a wave holds rows 4 (l / 16) .. + 3 of column l % 16;

@@ -208,6 +208,22 @@ struct GramArgs {
     double *part;
 };
 
+struct CholArgs {                   // new W^T A W: Cholesky, inverse, commit flag
+    int k;
+    const double *waw;              // k x k Gram product (row-major)
+    double *waw_sym;                // symmetrised copy for the host
+    double *inv;                    // k x k inverse (written when SPD)
+    RecState *state;
+};
+
+struct CommitArgs {                 // W, AW <- Wn, AWn and the inverse, when state->ok
+    int64_t n;                      // ncol * ld elements
+    int ncol;
+    const double *Wn, *AWn, *inv_new;
+    double *W, *AW, *inv;
+    RecState *state;
+};
+
 struct GradArgs {
     int64_t n_elem, n_nodes;
     int nx, ny, nz, n_rhs;
@@ -235,6 +251,11 @@ void launch_gram(const GramArgs &a, int nblocks, hipStream_t s);
 void launch_elem_grad(const GradArgs &a, hipStream_t s);
 void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s);
 void launch_fill(int64_t n, double v, double *dst, hipStream_t s);
+void launch_ctl_init(Ctl *ctl, double rtol2, int record, const RecState *state, int32_t *hflag, hipStream_t s);
+void launch_set_done(Ctl *ctl, int v, hipStream_t s);
+void launch_set_state(RecState *state, int k, int ok, hipStream_t s);
+void launch_chol_inv(const CholArgs &a, hipStream_t s);
+void launch_commit(const CommitArgs &a, hipStream_t s);
 // iteration (hot.hip)
 struct SymvCfg {
     int nw;                         // waves per block: 4 or 8
@@ -246,9 +267,9 @@ void launch_symv(const SymvArgs &a, int prec, SymvCfg cfg, size_t smem, hipStrea
 void launch_update(const UpdArgs &a, int grid, hipStream_t s);
 void launch_prolong(const ProlArgs &a, int prec, int nsub, int max_nc, hipStream_t s);
 void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s);
-void launch_pupd(const PupdArgs &a, int grid, hipStream_t s);
+void launch_pupd(const PupdArgs &a, int kmax, int grid, hipStream_t s);
 void launch_resid(const ResidArgs &a, int kmax, int grid, hipStream_t s);
-void launch_defl_init(const DeflArgs &a, int grid, hipStream_t s);
+void launch_defl_init(const DeflArgs &a, int kmax, int grid, hipStream_t s);
 void launch_reduce(const ReduceArgs &a, hipStream_t s);
 void launch_coarse2(const Coarse2Args &a, hipStream_t s);
 void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s);

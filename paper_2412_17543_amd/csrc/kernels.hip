@@ -9,6 +9,8 @@
 // hot.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "devutil.h"
 #include "internal.h"
 #include "kernels.h"
@@ -366,6 +368,97 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, double v, double *dst) 
 }
 
 // ---------------------------------------------------------------------------
+// control block and deflation-basis bookkeeping on the device
+// ---------------------------------------------------------------------------
+__global__ void k_ctl_init(Ctl *c, double rtol2, int record, const RecState *st, int32_t *hflag) {
+    if (threadIdx.x != 0) return;
+    Ctl h{};
+    h.rtol2 = rtol2;
+    h.record = record;
+    h.k = st ? st->k : 0;
+    h.hflag = hflag;
+    *c = h;
+}
+
+__global__ void k_set_done(Ctl *c, int v) {
+    if (threadIdx.x == 0) c->done = v;
+}
+
+__global__ void k_set_state(RecState *st, int k, int ok) {
+    if (threadIdx.x == 0) { st->k = k; st->ok = ok; }
+}
+
+// One block: symmetrise the new W^T A W, Cholesky factor in LDS, explicit
+// inverse by forward/backward substitution (one column per thread),
+// symmetrised.  state->ok = 1 when positive definite (Section 4.1: W^T A W
+// must be invertible for the projection of eq. projectionQ).
+__global__ void __launch_bounds__(256) k_chol_inv(CholArgs a) {
+    __shared__ double L[RMAX][RMAX];
+    __shared__ double X[RMAX][RMAX];
+    const int k = a.k, t = threadIdx.x;
+    for (int e = t; e < k * k; e += blockDim.x) {
+        const int i = e / k, j = e - i * k;
+        const double v = 0.5 * (a.waw[i * k + j] + a.waw[j * k + i]);
+        L[i][j] = v;
+        a.waw_sym[i * k + j] = v;
+    }
+    __syncthreads();
+    bool bad = false;
+    for (int j = 0; j < k; ++j) {
+        if (t == 0) {
+            // a non-positive pivot leaves 0 on the diagonal, seen by every thread
+            const double d = L[j][j];
+            L[j][j] = (d > 0.0 && isfinite(d)) ? sqrt(d) : 0.0;
+        }
+        __syncthreads();
+        if (!(L[j][j] > 0.0)) { bad = true; break; }
+        for (int i = j + 1 + t; i < k; i += blockDim.x) L[i][j] /= L[j][j];
+        __syncthreads();
+        for (int e = t; e < (k - j - 1) * (k - j - 1); e += blockDim.x) {
+            const int i = j + 1 + e / (k - j - 1), q = j + 1 + e % (k - j - 1);
+            if (q <= i) L[i][q] -= L[i][j] * L[q][j];
+        }
+        __syncthreads();
+    }
+    if (bad) {
+        if (t == 0) a.state->ok = 0;
+        return;
+    }
+    if (t < k) {
+        // column t of (L L^T)^{-1}: L y = e_t, then L^T x = y
+        for (int i = 0; i < k; ++i) {
+            double s = (i == t) ? 1.0 : 0.0;
+            for (int q = 0; q < i; ++q) s -= L[i][q] * X[q][t];
+            X[i][t] = s / L[i][i];
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double s = X[i][t];
+            for (int q = i + 1; q < k; ++q) s -= L[q][i] * X[q][t];
+            X[i][t] = s / L[i][i];
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < k * k; e += blockDim.x) {
+        const int i = e / k, j = e - i * k;
+        a.inv[i * k + j] = 0.5 * (X[i][j] + X[j][i]);
+    }
+    if (t == 0) a.state->ok = 1;
+}
+
+__global__ void __launch_bounds__(256) k_commit(CommitArgs a) {
+    if (!a.state->ok) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
+        a.W[g] = a.Wn[g];
+        a.AW[g] = a.AWn[g];
+    }
+    if (blockIdx.x == 0) {
+        for (int e = threadIdx.x; e < a.ncol * a.ncol; e += blockDim.x) a.inv[e] = a.inv_new[e];
+        if (threadIdx.x == 0) a.state->k = a.ncol;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -423,6 +516,23 @@ void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s) {
 }
 void launch_fill(int64_t n, double v, double *dst, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256)), dim3(256), 0, s, n, v, dst);
+}
+
+void launch_ctl_init(Ctl *ctl, double rtol2, int record, const RecState *state, int32_t *hflag, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl, rtol2, record, state, hflag);
+}
+void launch_set_done(Ctl *ctl, int v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, s, ctl, v);
+}
+void launch_set_state(RecState *state, int k, int ok, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, state, k, ok);
+}
+void launch_chol_inv(const CholArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, s, a);
+}
+void launch_commit(const CommitArgs &a, hipStream_t s) {
+    const int64_t nb = std::min<int64_t>(1024, std::max<int64_t>(1, (a.n + 255) / 256));
+    hipLaunchKernelGGL(k_commit, dim3((unsigned)nb), dim3(256), 0, s, a);
 }
 
 }  // namespace bddc

@@ -33,7 +33,7 @@ class Solver:
                  node_dirichlet=None, ny=None, nz=None, R=0, strategy="B4", local_prec=64,
                  weights="diag", constraints=("corners", "faces"), stop_rule="rhs",
                  init_guess="prev", max_it=1000, save_cap=256, freeze_tol=1e-5,
-                 use_graph=True, device="cuda", stream=None):
+                 use_graph=True, autotune=True, device="cuda", stream=None):
         lib = _lib.load()
         self.lib = lib
         self.device = torch.device(device)
@@ -76,6 +76,7 @@ class Solver:
         o.max_it = max_it
         o.save_cap = save_cap
         o.use_graph = 1 if use_graph else 0
+        o.autotune = 1 if autotune else 0
         self.opts = o
         torch.cuda.set_device(self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -105,6 +106,15 @@ class Solver:
         cnt = ctypes.c_int32()
         check(self.lib.bddc_ritz_values(self.ctx, buf, 64, ctypes.byref(cnt)))
         return np.frombuffer(buf, dtype=np.float64)[: cnt.value].copy()
+
+    TUNING_KEYS = ("items", "items_per_cu", "waves", "unroll", "best_us", "tiles")
+
+    def tuning(self) -> dict:
+        """Configuration chosen for the Schur and Neumann products."""
+        a = (ctypes.c_double * 12)()
+        check(self.lib.bddc_tuning(self.ctx, a))
+        v = list(a)
+        return {"schur": dict(zip(self.TUNING_KEYS, v[:6])), "neumann": dict(zip(self.TUNING_KEYS, v[6:]))}
 
     def enable_timing(self, on=True, classes=None):
         """Time kernel classes with HIP events (classes: iterable of STAT_KEYS)."""
