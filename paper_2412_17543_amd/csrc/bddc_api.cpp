@@ -43,6 +43,7 @@ struct OpHost {
     size_t smem = 0;
     int64_t n_tiles = 0;
     double bytes = 0;               // algorithmic bytes of one product
+    bool interior = false;          // interior operators (sizes nI, no gather lists)
     std::vector<int32_t> nchunk;    // per subdomain
     int32_t *d_items = nullptr, *d_nchunk = nullptr, *d_pb = nullptr, *d_cb = nullptr;
     double *d_ypart = nullptr, *d_cpart = nullptr;
@@ -90,14 +91,18 @@ struct bddc_ctx {
     double *d_K = nullptr, *d_S = nullptr, *d_KC = nullptr;
     void *d_N = nullptr, *d_phir = nullptr;
     int32_t *d_asm_ptr = nullptr, *d_asm_idx = nullptr, *d_casm_ptr = nullptr, *d_casm_idx = nullptr;
-    int max_nI = 0, max_nB = 0, max_nc = 0, max_nt = 0, max_ntc = 0;
-    std::vector<int32_t> h_nB, h_nc, h_b_off, h_c_off, h_pos_sub, h_cpos_sub;
+    int max_nI = 0, max_nB = 0, max_nc = 0, max_nt = 0, max_ntc = 0, max_ntI = 0;
+    std::vector<int32_t> h_nB, h_nI, h_nc, h_b_off, h_c_off, h_pos_sub, h_cpos_sub;
     std::vector<int32_t> h_asm_ptr, h_asm_idx, h_casm_ptr, h_casm_idx;
-    OpHost opS, opN;
+    OpHost opS, opN, opI;           // Schur, Neumann, interior inverse K_II^{-1}
+    int64_t *d_ki_off = nullptr;
+    double *d_KI = nullptr;         // packed K_II^{-1} tiles
+    int32_t *d_kib_ptr = nullptr, *d_kib_col = nullptr, *d_kbi_ptr = nullptr, *d_kbi_col = nullptr;
+    double *d_kib_val = nullptr, *d_kbi_val = nullptr, *d_tmpN = nullptr;
     // iteration vectors
     int vgrid = 1;
     double *d_b = nullptr, *d_x = nullptr, *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_tmp = nullptr;
-    double *d_locq = nullptr, *d_yI = nullptr, *d_wloc = nullptr;
+    double *d_locq = nullptr, *d_wloc = nullptr;
     double *d_rr = nullptr, *d_bbp = nullptr, *d_zp = nullptr, *d_wp = nullptr, *d_dotS = nullptr, *d_gp = nullptr;
     // coarse
     bool three = false;
@@ -108,6 +113,10 @@ struct bddc_ctx {
             *d_pos_sr = nullptr, *d_nc3 = nullptr, *d_C3_off = nullptr, *d_c3 = nullptr,
             *d_asm3_ptr = nullptr, *d_asm3_idx = nullptr;
     uint8_t *d_own2 = nullptr;
+    int64_t *d_ph_off2 = nullptr;
+    int32_t *d_c3o = nullptr, *d_n3p = nullptr, *d_sr_ptr = nullptr, *d_sr_sub = nullptr, *d_cL = nullptr;
+    size_t smem_l2d = 0;
+    bool fuse_prolong = false;      // three levels with enough subregions to fill the GPU
     int64_t *d_K2_off = nullptr, *d_N2_off = nullptr, *d_P2_off = nullptr;
     double *d_K2 = nullptr, *d_N2 = nullptr, *d_Phi2 = nullptr, *d_K3inv = nullptr, *d_vI2 = nullptr,
            *d_t2 = nullptr, *d_rB2 = nullptr, *d_u2 = nullptr, *d_c3loc = nullptr, *d_u3 = nullptr;
@@ -244,15 +253,16 @@ int build_worklist(bddc_ctx *c, OpHost &op, int64_t target) {
     std::vector<SymvItem> items;
     std::vector<int32_t> nch(nsub), pb(nsub), cb(nsub);
     int64_t ylen = 0, clen = 0;
+    const std::vector<int32_t> &sizes = op.interior ? c->h_nI : c->h_nB;
     for (int i = 0; i < nsub; ++i) {
         const int nci = op.dev.nc ? c->h_nc[i] : 0;
-        const int64_t nt = ntiles_of(c->h_nB[i], nci);
+        const int64_t nt = ntiles_of(sizes[i], nci);
         int C = (int)std::max<int64_t>(1, (nt + target / 2) / std::max<int64_t>(target, 1));
         C = (int)std::min<int64_t>(C, nt);
         nch[i] = C;
         pb[i] = (int32_t)ylen;
         cb[i] = (int32_t)clen;
-        ylen += (int64_t)C * c->h_nB[i];
+        ylen += (int64_t)C * sizes[i];
         clen += (int64_t)C * nci;
         for (int q = 0; q < C; ++q)
             items.push_back(SymvItem{i, (int32_t)(nt * q / C), (int32_t)(nt * (q + 1) / C), q});
@@ -281,6 +291,7 @@ int build_worklist(bddc_ctx *c, OpHost &op, int64_t target) {
     op.dev.nchunk = op.d_nchunk;
     op.dev.pb = op.d_pb;
     op.dev.cb = op.d_cb;
+    if (op.interior) return 0;      // interior entries have one owner: no lists
     // flat gather lists, owners in assembly order, items in increasing order
     {
         std::vector<int32_t> ptr(c->n_gamma + 1, 0), idx;
@@ -378,13 +389,18 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
             l.P2_off = c->d_P2_off; l.Phi2 = c->d_Phi2; l.nc3 = c->d_nc3; l.C3_off = c->d_C3_off; l.c3 = c->d_c3;
             l.u2 = c->d_u2; l.c3loc = c->d_c3loc; l.pos_sr = c->d_pos_sr; l.own2 = c->d_own2; l.u3 = c->d_u3;
             l.uC = c->d_uC;
+            l.ph_off = c->d_ph_off2; l.c3o = c->d_c3o; l.n3p = c->d_n3p; l.n3 = c->n3; l.max_nL = c->max_nL;
+            l.sr_ptr = c->d_sr_ptr; l.sr_sub = c->d_sr_sub; l.cL = c->d_cL;
+            l.nB = c->d_nB; l.b_off = c->d_b_off; l.nc = c->d_nc; l.c_off = c->d_c_off;
+            l.nchunk = c->opN.d_nchunk; l.pb = c->opN.d_pb; l.upart = c->opN.d_ypart;
+            l.phir = c->d_phir; l.phr_off = c->d_phr_off; l.wloc = c->fuse_prolong ? c->d_wloc : nullptr;
             launch_l2_a(l, c->nsr, c->max_nL, c->stream);
             launch_l2_b(l, c->nsr, c->max_nL, c->stream);
             L3Args l3{};
             l3.ctl = c->d_ctl; l3.n = c->n3; l3.ptr = c->d_asm3_ptr; l3.idx = c->d_asm3_idx; l3.loc = c->d_c3loc;
             l3.Kneg = c->d_K3inv; l3.u = c->d_u3;
             launch_l3(l3, c->stream);
-            launch_l2_d(l, c->nsr, c->max_nL, c->stream);
+            launch_l2_d(l, c->prec, c->nsr, c->smem_l2d, c->stream);   // with the prolongation
         } else {
             Coarse2Args ca{};
             ca.ctl = c->d_ctl; ca.n = c->nC; ca.rc = rc; ca.Kneg = c->d_KCinv; ca.u = c->d_uC;
@@ -394,13 +410,14 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
     {
         TScope ts(c, TK_VEC);
         ProlArgs pa{};
+        const bool prolonged = c->fuse_prolong;        // done by k_l2_d
         pa.ctl = c->d_ctl; pa.gated = gated ? 1 : 0;
         pa.nB = c->d_nB; pa.b_off = c->d_b_off; pa.nc = c->d_nc; pa.c_off = c->d_c_off; pa.cidx = c->d_cidx;
         pa.nchunk = c->opN.d_nchunk; pa.pb = c->opN.d_pb; pa.upart = c->opN.d_ypart;
         pa.phir = c->d_phir; pa.phr_off = c->d_phr_off;
         pa.uC = c->nC > 0 ? c->d_uC : nullptr;
         pa.wloc = c->d_wloc;
-        launch_prolong(pa, c->prec, c->n_sub, c->max_nc, c->stream);
+        if (!prolonged) launch_prolong(pa, c->prec, c->n_sub, c->max_nc, c->stream);
         ZasmArgs a{};
         a.n = c->n_gamma;
         a.w.ptr = c->d_asm_ptr; a.w.idx = c->d_asm_idx; a.w.part = c->d_wloc;
@@ -517,11 +534,26 @@ int run_loop(bddc_ctx *c) {
     return 0;
 }
 
+// y_I = K_II^{-1} v_I for every subdomain, v gathered from the nodal vector
+// at the interior nodes (partial products in opI)
+void run_interior(bddc_ctx *c, const double *v) {
+    SymvArgs a{};
+    a.op = c->opI.dev;
+    a.x = v;
+    a.ypart = c->opI.d_ypart;
+    a.ctl = c->d_ctl;
+    launch_symv(a, 64, c->opI.cfg, c->opI.smem, c->stream);
+}
+
+// Condensation (Section 3.1): y_I = K_II^{-1} F_I, t_i = K_BI y_I,
+// b = F_G - sum_i R_i^T t_i, per-block ||b||^2 partials.
 void run_condense(bddc_ctx *c, const double *F) {
     TScope ts(c, TK_COND);
+    run_interior(c, F);
     CondArgs a{};
-    a.nI = c->d_nI; a.nB = c->d_nB; a.i_off = c->d_i_off; a.b_off = c->d_b_off; a.nodesI = c->d_nodesI;
-    a.k_off = c->d_k_off; a.K = c->d_K; a.F = F; a.yI = c->d_yI; a.t = c->d_locq;
+    a.nI = c->d_nI; a.nB = c->d_nB; a.i_off = c->d_i_off; a.b_off = c->d_b_off;
+    a.nchunk = c->opI.d_nchunk; a.pb = c->opI.d_pb; a.ypart = c->opI.d_ypart;
+    a.kbi_ptr = c->d_kbi_ptr; a.kbi_col = c->d_kbi_col; a.kbi_val = c->d_kbi_val; a.t = c->d_locq;
     launch_cond_local(a, c->n_sub, c->max_nI, c->stream);
     CondAsmArgs b{};
     b.n = c->n_gamma; b.gamma = c->d_gamma; b.ptr = c->d_asm_ptr; b.idx = c->d_asm_idx; b.F = F; b.loc = c->d_locq;
@@ -529,13 +561,18 @@ void run_condense(bddc_ctx *c, const double *F) {
     launch_cond_asm(b, c->vgrid, c->stream);
 }
 
-int run_recover(bddc_ctx *c, double *u) {
+// Interior recovery (Section 3.1): x_I = K_II^{-1} (F_I - K_IB x_B), u = (x_I, x_G).
+int run_recover(bddc_ctx *c, const double *F, double *u) {
     TScope ts(c, TK_COND);
-    launch_fill(c->n_nodes, 0.0, u, c->stream);
     RecArgs a{};
     a.nI = c->d_nI; a.nB = c->d_nB; a.i_off = c->d_i_off; a.b_off = c->d_b_off; a.nodesI = c->d_nodesI;
-    a.gB = c->d_gB; a.k_off = c->d_k_off; a.K = c->d_K; a.x = c->d_x; a.yI = c->d_yI; a.u = u;
-    launch_recover(a, c->n_sub, c->max_nB, c->stream);
+    a.gB = c->d_gB; a.x = c->d_x; a.F = F;
+    a.kib_ptr = c->d_kib_ptr; a.kib_col = c->d_kib_col; a.kib_val = c->d_kib_val; a.out = c->d_tmpN;
+    a.nchunk = c->opI.d_nchunk; a.pb = c->opI.d_pb; a.ypart = c->opI.d_ypart; a.u = u;
+    launch_rec_rhs(a, c->n_sub, c->max_nB, c->stream);
+    run_interior(c, c->d_tmpN);
+    launch_fill(c->n_nodes, 0.0, u, c->stream);
+    launch_rec_out(a, c->n_sub, c->stream);
     launch_scatter_gamma(c->n_gamma, c->d_gamma, c->d_x, u, c->stream);
     return 0;
 }
@@ -648,7 +685,7 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     c->have_hist = want_hist && restarts == 0;
     if (iters) *iters = h.iter;
     if (relres) *relres = (h.bb > 0 && !h.zero_rhs) ? std::sqrt(h.true_rr / h.bb) : 0.0;
-    if ((rc = run_recover(c, u))) return rc;
+    if ((rc = run_recover(c, F, u))) return rc;
     if (h.status == BDDC_EBREAKDOWN) return fail(BDDC_EBREAKDOWN, "PCG breakdown (r^T z <= 0, p^T A p <= 0 or NaN)");
     if (h.status == BDDC_ENOTCONV) return fail(BDDC_ENOTCONV, "max_it reached");
     return 0;
@@ -910,6 +947,92 @@ int setup_operators(bddc_ctx *c) {
     return 0;
 }
 
+// Interior inverses K_II^{-1} packed like the other symmetric operators, and
+// the sparse couplings K_IB (interior rows) and K_BI (interface rows) from
+// the element matrices c_e h Kref (Section 2), for condensation and recovery.
+int setup_interior(bddc_ctx *c, const std::vector<int64_t> &k_off) {
+    const int nsub = c->n_sub;
+    const Structure &st = c->st;
+    std::vector<int64_t> ki_off(nsub + 1, 0);
+    for (int i = 0; i < nsub; ++i) ki_off[i + 1] = ki_off[i] + ntiles_of(c->h_nI[i], 0) * 256;
+    int rc;
+    if ((rc = dupload(c, &c->d_ki_off, ki_off)) || (rc = dalloc(c, &c->d_KI, (size_t)std::max<int64_t>(1, ki_off[nsub]))))
+        return rc;
+    std::vector<PackDesc> pk;
+    for (int i = 0; i < nsub; ++i) {
+        if (c->h_nI[i] == 0) continue;
+        const int nl = st.sub[i].nloc;
+        pk.push_back(PackDesc{c->d_K + k_off[i], nl, c->h_nI[i], -1.0, nullptr, nullptr, 0, 0, ki_off[i], -1});
+    }
+    if (!pk.empty()) {
+        PackDesc *dpk;
+        if ((rc = dupload(c, &dpk, pk))) return rc;
+        launch_pack(dpk, (int)pk.size(), 64, c->d_KI, nullptr, c->stream);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        dfree(c, dpk);
+    }
+    // K_IB from the element matrices; Kref: 1/3 on the diagonal, 0 between
+    // vertices differing in one coordinate, -1/12 otherwise
+    std::vector<int32_t> ib_ptr(1, 0), ib_col, bi_ptr(1, 0), bi_col;
+    std::vector<double> ib_val, bi_val;
+    for (int i = 0; i < nsub; ++i) {
+        const SubHost &sh = st.sub[i];
+        const int nI = sh.nI, nB = sh.nB;
+        std::vector<std::map<int, double>> rows(nI), cols(nB);
+        for (size_t t = 0; t < sh.elem.size(); ++t) {
+            for (int v = 0; v < 8; ++v) {
+                const int a = sh.elem_loc[t * 8 + v];
+                if (a < 0 || a >= nI) continue;
+                for (int w = 0; w < 8; ++w) {
+                    const int b = sh.elem_loc[t * 8 + w];
+                    if (b < nI) continue;
+                    const int nd = __builtin_popcount(v ^ w);
+                    if (nd == 1) continue;
+                    const double kv = sh.elem_c[t] * (nd == 0 ? 1.0 / 3.0 : -1.0 / 12.0);
+                    rows[a][b - nI] += kv;
+                    cols[b - nI][a] += kv;
+                }
+            }
+        }
+        for (int a = 0; a < nI; ++a) {
+            for (auto &e : rows[a]) { ib_col.push_back(e.first); ib_val.push_back(e.second); }
+            ib_ptr.push_back((int32_t)ib_col.size());
+        }
+        for (int k = 0; k < nB; ++k) {
+            for (auto &e : cols[k]) { bi_col.push_back(e.first); bi_val.push_back(e.second); }
+            bi_ptr.push_back((int32_t)bi_col.size());
+        }
+    }
+    if ((rc = dupload(c, &c->d_kib_ptr, ib_ptr)) || (rc = dupload(c, &c->d_kib_col, ib_col)) ||
+        (rc = dupload(c, &c->d_kib_val, ib_val)) || (rc = dupload(c, &c->d_kbi_ptr, bi_ptr)) ||
+        (rc = dupload(c, &c->d_kbi_col, bi_col)) || (rc = dupload(c, &c->d_kbi_val, bi_val)) ||
+        (rc = dalloc(c, &c->d_tmpN, (size_t)c->n_nodes)))
+        return rc;
+    OpHost &op = c->opI;
+    op.interior = true;
+    op.prec = 64;
+    op.dev.tiles = c->d_KI;
+    op.dev.t_off = c->d_ki_off;
+    op.dev.nB = c->d_nI;
+    op.dev.b_off = c->d_i_off;
+    op.dev.gB = c->d_nodesI;
+    op.dev.nc = nullptr;
+    op.n_tiles = ki_off[nsub] / 256;
+    op.cfg = SymvCfg{4, 2};
+    int max_ntI = 0;
+    for (int i = 0; i < nsub; ++i) max_ntI = std::max(max_ntI, (c->h_nI[i] + TILE - 1) / TILE);
+    if (symv_smem(64, 4, max_ntI, 0) > 160 * 1024) return fail(BDDC_EINVAL, "a subdomain interior is too large for the LDS-staged products");
+    c->max_ntI = max_ntI;
+    op.smem = symv_smem(64, 4, max_ntI, 0);
+    if (c->allow8 && symv_smem(64, 8, max_ntI, 0) > 160 * 1024) c->allow8 = false;
+    const int nwmax = c->allow8 ? 8 : 4;
+    const size_t lim = std::max(symv_smem(64, nwmax, std::max(c->max_nt, max_ntI), 0),
+                                symv_smem(c->prec, nwmax, c->max_nt, c->max_ntc));
+    if (set_symv_smem_limit(lim)) return fail(BDDC_EHIP, "hipFuncSetAttribute (dynamic LDS) failed");
+    HIPCHK(hipMemsetAsync(c->d_tmpN, 0, (size_t)c->n_nodes * sizeof(double), c->stream));
+    return build_worklist(c, op, item_target(c, op.n_tiles, 6));
+}
+
 // Tile-level autotuning of the two batched products on the operators just
 // built: work-list granularity (items per compute unit), waves per block and
 // tiles in flight per wave; the fastest of a few timed launches is kept.
@@ -919,10 +1042,12 @@ int tune_operators(bddc_ctx *c) {
     HIPCHK(hipEventCreate(&e1));
     int rc = 0;
     const int ipcs[4] = {2, 4, 8, 16};
-    OpHost *ops[2] = {&c->opS, &c->opN};
-    for (int w = 0; w < 2 && rc == 0; ++w) {
+    OpHost *ops[3] = {&c->opS, &c->opN, &c->opI};
+    for (int w = 0; w < 3 && rc == 0; ++w) {
         OpHost &op = *ops[w];
+        if (op.dev.n_items == 0) continue;
         const int ntc = op.dev.nc ? c->max_ntc : 0;
+        const int mnt = op.interior ? c->max_ntI : c->max_nt;
         float best = 1e30f;
         int best_ipc = 6;
         SymvCfg best_cfg{4, 2};
@@ -932,9 +1057,10 @@ int tune_operators(bddc_ctx *c) {
                 if (nw == 8 && !c->allow8) continue;
                 for (int u : {2, 4}) {
                     const SymvCfg cfg{nw, u};
-                    const size_t smem = symv_smem(op.prec, nw, c->max_nt, ntc);
+                    const size_t smem = symv_smem(op.prec, nw, mnt, ntc);
                     SymvArgs a{};
-                    a.op = op.dev; a.x = c->d_x; a.ypart = op.d_ypart; a.cpart = op.d_cpart; a.ctl = c->d_ctl;
+                    a.op = op.dev; a.x = op.interior ? c->d_tmpN : c->d_x; a.ypart = op.d_ypart; a.cpart = op.d_cpart;
+                    a.ctl = c->d_ctl;
                     for (int r = 0; r < 2; ++r) launch_symv(a, op.prec, cfg, smem, c->stream);
                     HIPCHK(hipEventRecord(e0, c->stream));
                     for (int r = 0; r < 4; ++r) launch_symv(a, op.prec, cfg, smem, c->stream);
@@ -949,7 +1075,7 @@ int tune_operators(bddc_ctx *c) {
         if (rc == 0) rc = build_worklist(c, op, item_target(c, op.n_tiles, best_ipc));
         op.cfg = best_cfg;
         op.ipc = best_ipc;
-        op.smem = symv_smem(op.prec, best_cfg.nw, c->max_nt, ntc);
+        op.smem = symv_smem(op.prec, best_cfg.nw, mnt, ntc);
         op.tuned_us = best * 1e3f / 4;
     }
     (void)hipEventDestroy(e0);
@@ -1012,7 +1138,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         max_nloc = std::max(max_nloc, sh.nloc);
     }
     if (b_off[nsub] > INT32_MAX / 2) return fail(BDDC_EINVAL, "too many local interface entries");
-    c->h_nB = nB; c->h_nc = nc; c->h_pos_sub = pos_sub; c->h_cpos_sub = cpos_sub;
+    c->h_nB = nB; c->h_nI = nI; c->h_nc = nc; c->h_pos_sub = pos_sub; c->h_cpos_sub = cpos_sub;
     c->h_b_off.assign(b_off.begin(), b_off.end() - 1);
     c->h_c_off.assign(c_off.begin(), c_off.end() - 1);
     if ((rc = dupload(c, &c->d_nI, nI)) || (rc = dupload(c, &c->d_nB, nB)) || (rc = dupload(c, &c->d_nc, nc)) ||
@@ -1159,6 +1285,9 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         if (st_h) return fail(BDDC_ESINGULAR, "non-positive pivot in a local elimination (floating subdomain without constraints?)");
     }
     if ((rc = setup_operators(c))) return rc;
+    if ((rc = setup_interior(c, k_off))) return rc;
+    dfree(c, c->d_K);   // the swept local matrices are not used after setup
+    c->d_K = nullptr;
 
     // -------------------------------------------------- coarse levels
     c->three = st.three;
@@ -1219,6 +1348,39 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
             max_sad2 = std::max(max_sad2, r.nB + nc3[j]);
         }
         if ((size_t)c->max_nL * 8 > 65536) return fail(BDDC_EINVAL, "a subregion has too many coarse DOFs");
+        {
+            // per level-2 interface position: its D Phi row and level-3 DOF list
+            std::vector<int64_t> ph_off2(B2_off[nsr]);
+            std::vector<int32_t> c3o(B2_off[nsr]), n3p(B2_off[nsr]), sr_ptr(nsr + 1, 0), sr_sub;
+            for (int j = 0; j < nsr; ++j) {
+                for (int k = 0; k < st.sr[j].nB; ++k) {
+                    ph_off2[B2_off[j] + k] = P2_off[j] + (int64_t)k * nc3[j];
+                    c3o[B2_off[j] + k] = C3_off[j];
+                    n3p[B2_off[j] + k] = nc3[j];
+                }
+                sr_sub.insert(sr_sub.end(), st.sr[j].subs.begin(), st.sr[j].subs.end());
+                sr_ptr[j + 1] = (int32_t)sr_sub.size();
+            }
+            // position of each coarse DOF of subdomain i in L of its subregion
+            std::vector<int32_t> cL(std::max<int64_t>(1, c_off[nsub]), 0), pos(c->nC, -1);
+            for (int j = 0; j < nsr; ++j) {
+                const auto &L = st.sr[j].L;
+                for (size_t q = 0; q < L.size(); ++q) pos[L[q]] = (int32_t)q;
+                for (int32_t i : st.sr[j].subs)
+                    for (int q = 0; q < nc[i]; ++q) cL[c_off[i] + q] = pos[st.sub[i].cidx[q]];
+                for (size_t q = 0; q < L.size(); ++q) pos[L[q]] = -1;
+            }
+            if ((rc = dupload(c, &c->d_ph_off2, ph_off2)) || (rc = dupload(c, &c->d_c3o, c3o)) ||
+                (rc = dupload(c, &c->d_n3p, n3p)) || (rc = dupload(c, &c->d_sr_ptr, sr_ptr)) ||
+                (rc = dupload(c, &c->d_sr_sub, sr_sub)) || (rc = dupload(c, &c->d_cL, cL)))
+                return rc;
+            // the level-2 post-correction kernel (one block per subregion) also
+            // prolongates to its subdomains when there are enough subregions
+            c->fuse_prolong = nsr >= 2 * c->n_cu;
+            c->smem_l2d = l2_d_smem(c->max_nL, c->n3);
+            if (c->smem_l2d > 160 * 1024) return fail(BDDC_EINVAL, "level-3 problem too large for the staged level-2 kernel");
+            if (set_l2_d_smem_limit(c->smem_l2d)) return fail(BDDC_EHIP, "hipFuncSetAttribute (dynamic LDS) failed");
+        }
         if ((rc = dupload(c, &c->d_nL, nL)) || (rc = dupload(c, &c->d_nI2, nI2)) || (rc = dupload(c, &c->d_nc3, nc3)) ||
             (rc = dupload(c, &c->d_L_off, L_off)) || (rc = dupload(c, &c->d_I2_off, I2_off)) ||
             (rc = dupload(c, &c->d_B2_off, B2_off)) || (rc = dupload(c, &c->d_C3_off, C3_off)) ||
@@ -1369,7 +1531,6 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
     if ((rc = dalloc(c, &c->d_b, ng)) || (rc = dalloc(c, &c->d_x, ng)) || (rc = dalloc(c, &c->d_r, ng)) ||
         (rc = dalloc(c, &c->d_z, ng)) || (rc = dalloc(c, &c->d_p, ng)) || (rc = dalloc(c, &c->d_tmp, ng)) ||
         (rc = dalloc(c, &c->d_locq, (size_t)b_off[nsub])) || (rc = dalloc(c, &c->d_wloc, (size_t)b_off[nsub])) ||
-        (rc = dalloc(c, &c->d_yI, (size_t)std::max<int64_t>(1, i_off[nsub]))) ||
         (rc = dalloc(c, &c->d_rr, (size_t)c->vgrid)) || (rc = dalloc(c, &c->d_bbp, (size_t)c->vgrid)) ||
         (rc = dalloc(c, &c->d_zp, (size_t)c->vgrid * (RMAX + 1))) ||
         (rc = dalloc(c, &c->d_wp, (size_t)c->vgrid * (RMAX + 1))) ||

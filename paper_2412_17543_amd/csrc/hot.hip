@@ -424,9 +424,11 @@ __global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
         }
         block_sum_cols<KM + 1>(acc, k + 1, lds, tv);
     }
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) lds[e] = a.WAWinv[e];
+    __syncthreads();
     if (threadIdx.x < k) {
         double s = 0.0;
-        for (int q = 0; q < k; ++q) s += a.WAWinv[threadIdx.x * k + q] * tv[1 + q];
+        for (int q = 0; q < k; ++q) s += lds[threadIdx.x * k + q] * tv[1 + q];
         mu[threadIdx.x] = s;
     }
     __syncthreads();
@@ -499,9 +501,11 @@ __global__ void __launch_bounds__(256) k_defl_init(DeflArgs a) {
         }
         block_sum_cols<KM + 1>(acc, k + 1, lds, tv);
     }
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) lds[e] = a.WAWinv[e];
+    __syncthreads();
     if (threadIdx.x < k) {
         double s = 0.0;
-        for (int q = 0; q < k; ++q) s += a.WAWinv[threadIdx.x * k + q] * tv[1 + q];
+        for (int q = 0; q < k; ++q) s += lds[threadIdx.x * k + q] * tv[1 + q];
         gam[threadIdx.x] = s;
     }
     __syncthreads();
@@ -605,42 +609,69 @@ __global__ void __launch_bounds__(1024) k_l3(L3Args a) {
 }
 
 // Level 2, phase D (one block per subregion): level-2 interface solution
-// x_G = sum_j R_j^T (u_j + (D Phi_j) u3) on the subregion's interface, interior
-// post-correction x_I = v_I - T^T x_G; both written to the level-1 coarse
-// solution u_C (an interface DOF by its first-listed subregion only; every
-// subregion computes the same value in the same order).
+// x_G = sum_j R_j^T (u_j + (D Phi_j) u3) on the subregion's interface and the
+// interior post-correction x_I = v_I - T^T x_G give the level-1 coarse
+// solution u_C on all coarse DOFs of the subregion (kept in LDS; every
+// subregion sharing an interface DOF computes the same value in the same
+// order).  The block then prolongates to its member subdomains:
+// w_i = u_i + (D Phi_i) u_C|_i (eq. averaging_subdomain_solves), u_i summed
+// from the Neumann product's work items.  Without wloc the block only
+// publishes u_C for k_prolong.
+template <typename T>
 __global__ void __launch_bounds__(256) k_l2_d(L2Args a) {
-    extern __shared__ double xg[];
+    extern __shared__ double sm[];
     __shared__ double part[4][64];
     if (a.ctl->done) return;
+    double *uCL = sm;                 // nL: x_I then x_G
+    double *u3s = sm + a.max_nL;      // n3
     const int j = blockIdx.x;
     const int nL = a.nL[j], nI = a.nI2[j], nB = nL - nI;
-    const int b2 = a.B2_off[j], loff = a.L_off[j];
+    const int b2 = a.B2_off[j];
+    for (int q = threadIdx.x; q < a.n3; q += blockDim.x) u3s[q] = a.u3[q];
+    __syncthreads();
     for (int k = threadIdx.x; k < nB; k += blockDim.x) {
         const int gi = a.g2[b2 + k];
         double s = 0.0;
         for (int t = a.asm2_ptr[gi]; t < a.asm2_ptr[gi + 1]; ++t) {
             const int pos = a.asm2_idx[t];
-            const int jj = a.pos_sr[pos];
-            const int kk = pos - a.B2_off[jj];
-            const int n3j = a.nc3[jj];
-            const double *ph = a.Phi2 + a.P2_off[jj] + (int64_t)kk * n3j;
-            const int32_t *c3 = a.c3 + a.C3_off[jj];
+            const double *ph = a.Phi2 + a.ph_off[pos];
+            const int32_t *c3 = a.c3 + a.c3o[pos];
+            const int n3j = a.n3p[pos];
             double v = a.u2[pos];
 #pragma unroll 8
-            for (int q = 0; q < n3j; ++q) v += ph[q] * a.u3[c3[q]];
+            for (int q = 0; q < n3j; ++q) v += ph[q] * u3s[c3[q]];
             s += v;
         }
-        xg[k] = s;
-        if (a.own2[b2 + k]) a.uC[a.L[loff + nI + k]] = s;
+        uCL[nI + k] = s;
     }
     __syncthreads();
-    const int i2 = a.I2_off[j];
-    const double *vI2 = a.vI2 + i2;
-    const int32_t *L = a.L + loff;
-    double *uC = a.uC;
-    cm_matvec<4>(a.K2 + a.K2_off[j] + (int64_t)nI * nL, nL, 0, nI, nB, xg, part,
-                 [&](int q, double y) { uC[L[q]] = vI2[q] - y; });
+    const double *vI2 = a.vI2 + a.I2_off[j];
+    cm_matvec<4>(a.K2 + a.K2_off[j] + (int64_t)nI * nL, nL, 0, nI, nB, uCL + nI, part,
+                 [&](int q, double y) { uCL[q] = vI2[q] - y; });
+    // cm_matvec ends with a barrier: uCL is complete
+    if (!a.wloc) {
+        // prolongation left to k_prolong: publish u_C
+        for (int q = threadIdx.x; q < nL; q += blockDim.x)
+            if (q < nI || a.own2[b2 + q - nI]) a.uC[a.L[a.L_off[j] + q]] = uCL[q];
+        return;
+    }
+    const T *phir = reinterpret_cast<const T *>(a.phir);
+    for (int m = a.sr_ptr[j]; m < a.sr_ptr[j + 1]; ++m) {
+        const int i = a.sr_sub[m];
+        const int n = a.nB[i], C = a.nchunk[i], nci = a.nc[i];
+        const int32_t *cl = a.cL + a.c_off[i];
+        const T *ph = phir + a.phr_off[i];
+        const double *up = a.upart + a.pb[i];
+        double *wl = a.wloc + a.b_off[i];
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            double w = 0.0;
+            for (int cc = 0; cc < C; ++cc) w += up[(int64_t)cc * n + k];
+            const T *row = ph + (int64_t)k * nci;
+#pragma unroll 8
+            for (int q = 0; q < nci; ++q) w += to_d(row[q]) * uCL[cl[q]];
+            wl[k] = w;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -756,8 +787,20 @@ void launch_l3(const L3Args &a, hipStream_t s) {
     if (a.n <= 0) return;
     hipLaunchKernelGGL(k_l3, dim3((a.n + 63) / 64), dim3(1024), (size_t)a.n * 8, s, a);
 }
-void launch_l2_d(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
-    hipLaunchKernelGGL(k_l2_d, dim3(nsr), dim3(256), (size_t)max_nL * 8, s, a);
+size_t l2_d_smem(int max_nL, int n3) { return (size_t)(std::max(1, max_nL) + std::max(1, n3)) * 8; }
+
+int set_l2_d_smem_limit(size_t bytes) {
+    if (bytes <= 65536) return 0;
+    const void *f[3] = {(const void *)k_l2_d<double>, (const void *)k_l2_d<float>, (const void *)k_l2_d<uint16_t>};
+    for (const void *p : f)
+        if (hipFuncSetAttribute(p, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+    return 0;
+}
+
+void launch_l2_d(const L2Args &a, int prec, int nsr, size_t smem, hipStream_t s) {
+    if (prec == 64) hipLaunchKernelGGL(k_l2_d<double>, dim3(nsr), dim3(256), smem, s, a);
+    else if (prec == 32) hipLaunchKernelGGL(k_l2_d<float>, dim3(nsr), dim3(256), smem, s, a);
+    else hipLaunchKernelGGL(k_l2_d<uint16_t>, dim3(nsr), dim3(256), smem, s, a);
 }
 
 }  // namespace bddc

@@ -159,6 +159,19 @@ struct L2Args {
     const uint8_t *own2;
     const double *u3;
     double *uC;
+    // level-2 interface positions: offset of the position's D Phi row and
+    // of its subregion's level-3 DOF list, level-3 DOFs of that subregion
+    const int64_t *ph_off;
+    const int32_t *c3o, *n3p;
+    int n3, max_nL;
+    // prolongation of the member subdomains (eq. averaging_subdomain_solves)
+    const int32_t *sr_ptr, *sr_sub;     // subregion -> member subdomains
+    const int32_t *cL;                  // coarse DOF q of subdomain i -> position in L of its subregion
+    const int32_t *nB, *b_off, *nc, *c_off, *nchunk, *pb;
+    const double *upart;
+    const void *phir;
+    const int64_t *phr_off;
+    double *wloc;
 };
 
 struct L3Args {                     // level 3: u3 = K3^{-1} r3 (dense)
@@ -171,11 +184,13 @@ struct L3Args {                     // level 3: u3 = K3^{-1} r3 (dense)
 };
 
 // ====================================================== per-solve kernels
-struct CondArgs {
-    const int32_t *nI, *nB, *i_off, *b_off, *nodesI;
-    const int64_t *k_off;
-    const double *K, *F;
-    double *yI, *t;
+struct CondArgs {                   // t_i = K_BI y_I, y_I from the interior-product partials
+    const int32_t *nI, *nB, *i_off, *b_off;
+    const int32_t *nchunk, *pb;
+    const double *ypart;
+    const int32_t *kbi_ptr, *kbi_col;   // interface rows (b_off based), interior columns
+    const double *kbi_val;
+    double *t;
 };
 
 struct CondAsmArgs {
@@ -185,10 +200,14 @@ struct CondAsmArgs {
     double *b, *part;
 };
 
-struct RecArgs {
+struct RecArgs {                    // out[nodesI] = F_I - K_IB x_B; then u[nodesI] = y_I
     const int32_t *nI, *nB, *i_off, *b_off, *nodesI, *gB;
-    const int64_t *k_off;
-    const double *K, *x, *yI;
+    const double *x, *F;
+    const int32_t *kib_ptr, *kib_col;   // interior rows (i_off based), interface columns
+    const double *kib_val;
+    double *out;
+    const int32_t *nchunk, *pb;
+    const double *ypart;
     double *u;
 };
 
@@ -244,7 +263,8 @@ void launch_gather_sum(int64_t n, const int32_t *ptr, const int32_t *idx, const 
 // per solve (kernels.hip)
 void launch_cond_local(const CondArgs &a, int nsub, int max_nI, hipStream_t s);
 void launch_cond_asm(const CondAsmArgs &a, int grid, hipStream_t s);
-void launch_recover(const RecArgs &a, int nsub, int max_nB, hipStream_t s);
+void launch_rec_rhs(const RecArgs &a, int nsub, int max_nB, hipStream_t s);
+void launch_rec_out(const RecArgs &a, int nsub, hipStream_t s);
 void launch_scatter_gamma(int n, const int32_t *gamma, const double *x, double *u, hipStream_t s);
 void launch_recycle_gemm(const GemmArgs &a, hipStream_t s);
 void launch_gram(const GramArgs &a, int nblocks, hipStream_t s);
@@ -275,7 +295,9 @@ void launch_coarse2(const Coarse2Args &a, hipStream_t s);
 void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s);
 void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s);
 void launch_l3(const L3Args &a, hipStream_t s);
-void launch_l2_d(const L2Args &a, int nsr, int max_nL, hipStream_t s);
+size_t l2_d_smem(int max_nL, int n3);
+int set_l2_d_smem_limit(size_t bytes);
+void launch_l2_d(const L2Args &a, int prec, int nsr, size_t smem, hipStream_t s);
 // deflation-column bucket of the templated reductions (0, 8, 16, 32, 64)
 int kmax_bucket(int k);
 

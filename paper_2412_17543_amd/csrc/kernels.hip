@@ -212,22 +212,27 @@ __global__ void __launch_bounds__(256) k_gather_sum(int64_t n, const int32_t *pt
 
 
 // ---------------------------------------------------------------------------
-// condensation b = F_G - sum_i R_i^T T_i F_I and interior recovery (Section 3.1)
-// on the swept local matrices [-K_II^{-1}, T_i^T; T_i, S_i]
+// condensation and interior recovery (Section 3.1) with the packed interior
+// inverses (products in hot.hip's k_symv) and the sparse couplings K_IB, K_BI
 // ---------------------------------------------------------------------------
+// One block per subdomain: y_I summed from its work items into LDS, then
+// t_k = sum_a K_BI[k][a] y_I[a] for the interface rows.
 __global__ void __launch_bounds__(256) k_cond_local(CondArgs a) {
-    extern __shared__ double fI[];
+    extern __shared__ double yI[];
     const int i = blockIdx.x;
-    const int nI = a.nI[i], nloc = nI + a.nB[i];
-    const double *K = a.K + a.k_off[i];
-    const int ioff = a.i_off[i];
-    for (int k = threadIdx.x; k < nI; k += blockDim.x) fI[k] = a.F[a.nodesI[ioff + k]];
-    __syncthreads();
-    for (int r = threadIdx.x; r < nloc; r += blockDim.x) {
+    const int nI = a.nI[i], nB = a.nB[i], C = a.nchunk[i];
+    const double *yp = a.ypart + a.pb[i];
+    for (int k = threadIdx.x; k < nI; k += blockDim.x) {
         double s = 0.0;
-        for (int k = 0; k < nI; ++k) s += K[(size_t)k * nloc + r] * fI[k];
-        if (r < nI) a.yI[ioff + r] = -s;
-        else a.t[a.b_off[i] + r - nI] = s;
+        for (int q = 0; q < C; ++q) s += yp[(int64_t)q * nI + k];
+        yI[k] = s;
+    }
+    __syncthreads();
+    const int boff = a.b_off[i];
+    for (int k = threadIdx.x; k < nB; k += blockDim.x) {
+        double s = 0.0;
+        for (int e = a.kbi_ptr[boff + k]; e < a.kbi_ptr[boff + k + 1]; ++e) s += a.kbi_val[e] * yI[a.kbi_col[e]];
+        a.t[boff + k] = s;
     }
 }
 
@@ -246,17 +251,31 @@ __global__ void __launch_bounds__(256) k_cond_asm(CondAsmArgs a) {
     if (threadIdx.x == 0) a.part[blockIdx.x] = bb;
 }
 
-__global__ void __launch_bounds__(256) k_recover(RecArgs a) {
+// One block per subdomain: out[nodesI] = F_I - K_IB x_B (the interior
+// right-hand side of the recovery, written at the subdomain's own nodes).
+__global__ void __launch_bounds__(256) k_rec_rhs(RecArgs a) {
     extern __shared__ double xB[];
     const int i = blockIdx.x;
-    const int nI = a.nI[i], nB = a.nB[i], nloc = nI + nB;
-    const double *K = a.K + a.k_off[i];
+    const int nI = a.nI[i], nB = a.nB[i];
     const int boff = a.b_off[i], ioff = a.i_off[i];
     for (int k = threadIdx.x; k < nB; k += blockDim.x) xB[k] = a.x[a.gB[boff + k]];
     __syncthreads();
     for (int r = threadIdx.x; r < nI; r += blockDim.x) {
-        double s = a.yI[ioff + r];
-        for (int k = 0; k < nB; ++k) s -= K[(size_t)(nI + k) * nloc + r] * xB[k];
+        const int node = a.nodesI[ioff + r];
+        double s = a.F[node];
+        for (int e = a.kib_ptr[ioff + r]; e < a.kib_ptr[ioff + r + 1]; ++e) s -= a.kib_val[e] * xB[a.kib_col[e]];
+        a.out[node] = s;
+    }
+}
+
+// u[nodesI] = x_I summed from the interior product's work items.
+__global__ void __launch_bounds__(256) k_rec_out(RecArgs a) {
+    const int i = blockIdx.x;
+    const int nI = a.nI[i], C = a.nchunk[i], ioff = a.i_off[i];
+    const double *yp = a.ypart + a.pb[i];
+    for (int r = threadIdx.x; r < nI; r += blockDim.x) {
+        double s = 0.0;
+        for (int q = 0; q < C; ++q) s += yp[(int64_t)q * nI + r];
         a.u[a.nodesI[ioff + r]] = s;
     }
 }
@@ -491,13 +510,16 @@ void launch_gather_sum(int64_t n, const int32_t *ptr, const int32_t *idx, const 
     if (n > 0) hipLaunchKernelGGL(k_gather_sum, dim3(nblk(n, 256)), dim3(256), 0, s, n, ptr, idx, src, out);
 }
 void launch_cond_local(const CondArgs &a, int nsub, int max_nI, hipStream_t s) {
-    hipLaunchKernelGGL(k_cond_local, dim3(nsub), dim3(256), (size_t)max_nI * 8, s, a);
+    hipLaunchKernelGGL(k_cond_local, dim3(nsub), dim3(256), (size_t)std::max(1, max_nI) * 8, s, a);
 }
 void launch_cond_asm(const CondAsmArgs &a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_cond_asm, dim3(grid), dim3(256), 0, s, a);
 }
-void launch_recover(const RecArgs &a, int nsub, int max_nB, hipStream_t s) {
-    hipLaunchKernelGGL(k_recover, dim3(nsub), dim3(256), (size_t)max_nB * 8, s, a);
+void launch_rec_rhs(const RecArgs &a, int nsub, int max_nB, hipStream_t s) {
+    hipLaunchKernelGGL(k_rec_rhs, dim3(nsub), dim3(256), (size_t)std::max(1, max_nB) * 8, s, a);
+}
+void launch_rec_out(const RecArgs &a, int nsub, hipStream_t s) {
+    hipLaunchKernelGGL(k_rec_out, dim3(nsub), dim3(256), 0, s, a);
 }
 void launch_scatter_gamma(int n, const int32_t *gamma, const double *x, double *u, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_scatter_gamma, dim3(nblk(n, 256)), dim3(256), 0, s, n, gamma, x, u);
