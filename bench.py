@@ -25,6 +25,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+WORKLOADS = {
+    "c64": "Q1 Poisson 64^3 elements (274,625 nodes), 512 subdomains of 8^3, three-level BDDC (64 subregions), "
+           "deflated PCG B4 R=20, 50 drifting-Gaussian right-hand sides, rtol 1e-8",
+    "c3": "Q1 Poisson 64^3 elements minus a sphere of radius 0.15, 400 jittered-RCB subdomains of uneven size, "
+          "log-normal coefficients (sigma 0.5), three-level BDDC (50 subregions), deflated PCG B4 R=20, "
+          "50 drifting-Gaussian right-hand sides, rtol 1e-8",
+}
 
 
 def kernel_hash():
@@ -41,7 +48,7 @@ def its_fmt(its):
 def run_form(torch, Solver, s, F, rtol, steps, warmup, local_prec, timing, use_graph=True):
     t0 = time.perf_counter()
     g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"],
-               R=s["R"], local_prec=local_prec, use_graph=use_graph)
+               elem_keep=s["elem_keep"], R=s["R"], local_prec=local_prec, use_graph=use_graph)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     for _ in range(warmup):
@@ -73,13 +80,14 @@ def cpu_baseline(s, F_np, n_sample):
 
     from oracle.sequence import OracleSolver
     with threadpool_limits(1):
-        o = OracleSolver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"], R=s["R"])
+        o = OracleSolver(s["nx"], s["elem_to_sub"], s["coef"], elem_keep=s["elem_keep"],
+                         sub_to_subregion=s["sub_to_subregion"], R=s["R"])
         t0 = time.perf_counter()
         for k in range(n_sample):
             o.solve(F_np[k], 1e-8)
         el = time.perf_counter() - t0
     return dict(value=n_sample / el, unit="solves/s", cores=1, kind="oracle",
-                sample="first %d right-hand sides of the same 64^3 sequence (oracle setup excluded, "
+                sample="first %d right-hand sides of the same sequence (oracle setup excluded, "
                        "as on the GPU), float64 NumPy/SciPy, one thread" % n_sample)
 
 
@@ -92,6 +100,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2)
+    ap.add_argument("--workload", default="c64", choices=("c64", "c3"),
+                    help="c64: 64^3 cube lattice (the headline configuration); c3: 64^3 with a spherical "
+                         "hole, 400 uneven RCB subdomains, log-normal coefficients")
+    ap.add_argument("--bf16", action="store_true", help="also run the bfloat16 Neumann-operator form")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures the single-GPU path only (one process, one MI355X); "
@@ -104,8 +116,8 @@ def main():
     import workload
     from paper_2412_17543_amd.solver import Solver
 
-    s = workload.workload("c64")
-    F_np = workload.rhs_sequence(s["nx"], s["n_rhs"])
+    s = workload.workload(args.workload)
+    F_np = workload.rhs_sequence(s["nx"], s["n_rhs"], s["elem_keep"])
     F = torch.tensor(F_np, device="cuda")       # inputs resident in HBM before timing
     torch.cuda.synchronize()
     n_rhs = F.shape[0]
@@ -135,9 +147,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "Q1 Poisson 64^3 elements (274,625 nodes), 512 subdomains of 8^3, "
-                               "three-level BDDC (64 subregions), deflated PCG B4 R=20, 50 drifting-Gaussian "
-                               "right-hand sides, rtol 1e-8",
+        "config": {"workload": WORKLOADS[args.workload],
                    "n_rhs": n_rhs, "n_gamma": f64["info"]["n_gamma"], "rtol": args.rtol},
         "iters": its_fmt(f64["its"].tolist()),
         "max_true_relres": float(f64["rr"].max()),
@@ -158,6 +168,14 @@ def main():
         line["mixed_fp32"] = {"value": round(mv, 3), "unit": "solves/s", "iters": its_fmt(mx["its"].tolist()),
                               "max_true_relres": float(mx["rr"].max()), "max_rel_diff_vs_fp64": err,
                               "speedup_vs_fp64": round(mv / value, 3)}
+    if args.bf16:
+        bf = run_form(torch, Solver, s, F, args.rtol, args.steps, args.warmup, 16, False)
+        ud = f64["U"]
+        err = max(float(((bf["U"][k] - ud[k]).abs().max() / ud[k].abs().max()).item()) for k in range(n_rhs))
+        bv = n_rhs * args.steps / bf["elapsed"]
+        line["mixed_bf16"] = {"value": round(bv, 3), "unit": "solves/s", "iters": its_fmt(bf["its"].tolist()),
+                              "max_true_relres": float(bf["rr"].max()), "max_rel_diff_vs_fp64": err,
+                              "speedup_vs_fp64": round(bv / value, 3)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(s, F_np, args.cpu_sample)
     print(json.dumps(line), flush=True)

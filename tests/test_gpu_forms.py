@@ -205,3 +205,32 @@ def test_adjoint_gradient_central_differences_through_gpu_solves():
     err = np.abs(g[idx] - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(g).max())
     print("[gpu] FD rel err", err, flush=True)
     assert err.max() < 1e-5
+
+
+def _hole_solver(name, **kw):
+    from paper_2412_17543_amd.solver import Solver
+    s = workload.workload(name)
+    print("[gpu] setup %s %s" % (name, sorted(kw)), flush=True)
+    return Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"],
+                  elem_keep=s["elem_keep"], **kw)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_uneven_partition_with_hole_matches_oracle(prec):
+    # jittered RCB subdomains of very different sizes around a spherical hole,
+    # log-normal coefficients, three levels, recycling
+    torch = _torch()
+    from oracle.sequence import OracleSolver
+    s = workload.workload("c3s")
+    F = workload.rhs_sequence(s["nx"], 3, s["elem_keep"])
+    rtol = 1e-10 if prec == 64 else 1e-8
+    U, its, rr = _hole_solver("c3s", R=6, local_prec=prec).solve_sequence(torch.tensor(F, device="cuda"), rtol)
+    o = OracleSolver(s["nx"], s["elem_to_sub"], s["coef"], elem_keep=s["elem_keep"],
+                     sub_to_subregion=s["sub_to_subregion"], R=6)
+    uo, ito, _ = o.solve_sequence(F, 1e-10 if prec == 64 else 1e-12)
+    print("[gpu] c3s fp%d iters gpu %s oracle %s" % (prec, its.tolist(), ito.tolist()), flush=True)
+    assert np.all(rr < rtol)
+    if prec == 64:
+        assert np.all(np.abs(its - ito) <= 1)
+    for k in range(len(F)):
+        assert _rel(U[k].cpu().numpy(), uo[k]) <= (1e-9 if prec == 64 else 1e-7)

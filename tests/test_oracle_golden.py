@@ -38,3 +38,16 @@ def test_c64_golden_counts():
     assert g["faces"] == 3 * (m - 1) * m * m
     assert g["n_gamma"] == 78652
     assert g["level3"] == (4 - 1) ** 3 + 5 * (4 - 1) ** 2 + 3 * (4 - 1) * 4 * 4
+
+
+def test_rcb_workload_is_face_connected_and_grouped():
+    # the uneven-batching inputs: every subdomain one face-connected piece of
+    # kept elements, subregions of equal count, removed elements excluded
+    import numpy as np
+    s = workload.workload("c3s")
+    keep, part = s["elem_keep"], s["elem_to_sub"]
+    assert s["n_sub"] == 24 and (keep == 0).sum() > 0
+    lab = workload._face_components(24, part.astype(np.int64), keep)
+    assert int(lab.max()) + 1 == 24
+    assert np.all(np.bincount(s["sub_to_subregion"]) == 8)
+    assert np.all(np.bincount(part[keep.astype(bool)], minlength=24) > 0)

@@ -114,6 +114,138 @@ def sphere_hole_keep(nx: int, centre=(0.5, 0.5, 0.5), radius: float = 0.15) -> n
     return (d2 > radius * radius).astype(np.uint8)
 
 
+def _rcb_split(points: np.ndarray, ids: np.ndarray, k: int, g: np.random.Generator, lo: float, hi: float,
+               out: np.ndarray, first: int) -> int:
+    """Assign parts first..first+k-1 to ids by recursive coordinate bisection:
+    cut along the longest extent, a fraction f ~ U[lo, hi] of the points to
+    the first floor(k/2) parts (f = 1/2 when lo == hi == 0.5)."""
+    if k == 1:
+        out[ids] = first
+        return first + 1
+    p = points[ids]
+    axis = int(np.argmax(p.max(axis=0) - p.min(axis=0)))
+    order = np.argsort(p[:, axis], kind="stable")
+    k1 = k // 2
+    f = g.uniform(lo, hi) if hi > lo else lo
+    if lo == hi == 0.5:
+        f = k1 / k
+    cut = min(max(int(round(f * len(ids))), 1), len(ids) - 1)
+    nxt = _rcb_split(points, ids[order[:cut]], k1, g, lo, hi, out, first)
+    return _rcb_split(points, ids[order[cut:]], k - k1, g, lo, hi, out, nxt)
+
+
+def _face_components(nx: int, part: np.ndarray, keep: np.ndarray) -> np.ndarray:
+    """Label connected components (through shared element faces) of each part;
+    returns a new part id per element (removed elements: -1)."""
+    n = nx ** 3
+    par = np.arange(n)
+
+    def find(a):
+        while par[a] != a:
+            par[a] = par[par[a]]
+            a = par[a]
+        return a
+
+    e = np.arange(n)
+    ex, ey, ez = e % nx, (e // nx) % nx, e // (nx * nx)
+    for d, ok in ((1, ex < nx - 1), (nx, ey < nx - 1), (nx * nx, ez < nx - 1)):
+        a = e[ok]
+        b = a + d
+        same = keep[a].astype(bool) & keep[b].astype(bool) & (part[a] == part[b])
+        for u, v in zip(a[same], b[same]):
+            ru, rv = find(u), find(v)
+            if ru != rv:
+                par[max(ru, rv)] = min(ru, rv)
+    roots = np.array([find(x) for x in range(n)])
+    lab = np.full(n, -1, dtype=np.int64)
+    kept = keep.astype(bool)
+    _, inv = np.unique(roots[kept], return_inverse=True)
+    lab[kept] = inv
+    return lab
+
+
+def interior_counts(nx: int, part: np.ndarray, keep: np.ndarray) -> np.ndarray:
+    """Interior free nodes per part: nodes touched by elements of that part
+    only, excluding the Dirichlet face x = 1."""
+    en = element_nodes(nx)[keep.astype(bool)]
+    pe = part[keep.astype(bool)]
+    nn = n_nodes(nx)
+    first = np.full(nn, -1, dtype=np.int64)
+    multi = np.zeros(nn, dtype=bool)
+    for v in range(8):
+        nd = en[:, v]
+        unset = first[nd] < 0
+        first[nd[unset]] = pe[unset]
+        multi[nd[(~unset) & (first[nd] != pe)]] = True
+    # a second pass catches nodes first set by a later element of another part
+    for v in range(8):
+        nd = en[:, v]
+        multi[nd[first[nd] != pe]] = True
+    dirichlet = (np.arange(nn) % (nx + 1)) == nx
+    ok = (first >= 0) & ~multi & ~dirichlet
+    return np.bincount(first[ok], minlength=int(part.max()) + 1)
+
+
+def rcb_partition(nx: int, n_parts: int, keep: np.ndarray | None = None, lo: float = 0.3, hi: float = 0.7,
+                  min_interior: int = 0, sub: int = 0) -> np.ndarray:
+    """Seeded jittered recursive coordinate bisection of the kept elements into
+    n_parts face-connected subdomains (removed elements get part 0).
+
+    Cuts take a fraction f ~ U[lo, hi] of the points; disconnected pieces are
+    split into their own parts, then the part with the fewest interior free
+    nodes is merged into the face neighbour sharing most faces with it until
+    n_parts remain and every part has at least min_interior interior nodes
+    (or no merge is possible)."""
+    keep = np.ones(nx ** 3, dtype=np.uint8) if keep is None else keep
+    kept = np.nonzero(keep)[0]
+    out = np.zeros(nx ** 3, dtype=np.int64)
+    _rcb_split(element_centroids(nx), kept, n_parts, rng("partition", sub), lo, hi, out, 0)
+    part = _face_components(nx, out, keep)
+    e = np.arange(nx ** 3)
+    ex, ey, ez = e % nx, (e // nx) % nx, e // (nx * nx)
+    pairs = []
+    for d, ok in ((1, ex < nx - 1), (nx, ey < nx - 1), (nx * nx, ez < nx - 1)):
+        a = e[ok]
+        b = a + d
+        m = keep[a].astype(bool) & keep[b].astype(bool)
+        pairs.append((a[m], b[m]))
+    while True:
+        npart = int(part.max()) + 1
+        cnt = interior_counts(nx, part, keep)
+        if npart <= n_parts and cnt.min() >= min_interior:
+            break
+        if npart <= 1:
+            break
+        small = int(np.argmin(cnt))
+        shared = np.zeros(npart, dtype=np.int64)
+        for a, b in pairs:
+            pa, pb = part[a], part[b]
+            m = (pa == small) & (pb != small)
+            np.add.at(shared, pb[m], 1)
+            m = (pb == small) & (pa != small)
+            np.add.at(shared, pa[m], 1)
+        if shared.max() == 0:
+            break
+        tgt = int(np.argmax(shared))
+        part[part == small] = tgt
+        part[part > small] -= 1
+    part[~keep.astype(bool)] = 0
+    return part.astype(np.int32)
+
+
+def rcb_subregions(nx: int, part: np.ndarray, keep: np.ndarray, n_groups: int) -> np.ndarray:
+    """Group subdomains into n_groups subregions of (nearly) equal count by
+    recursive coordinate bisection of the subdomain centroids."""
+    c = element_centroids(nx)[keep.astype(bool)]
+    p = part[keep.astype(bool)]
+    n = int(p.max()) + 1
+    cen = np.stack([np.bincount(p, weights=c[:, d], minlength=n) for d in range(3)], axis=1)
+    cen /= np.bincount(p, minlength=n)[:, None]
+    out = np.zeros(n, dtype=np.int64)
+    _rcb_split(cen, np.arange(n), n_groups, rng("partition", 99), 0.5, 0.5, out, 0)
+    return out.astype(np.int32)
+
+
 def lognormal_coef(n_elem: int, sigma: float, purpose: str = "coef", sub: int = 0) -> np.ndarray:
     """Per-element coefficient exp(sigma * xi), xi ~ N(0, 1)."""
     g = rng(purpose, sub)
@@ -191,6 +323,12 @@ def workload(name: str) -> dict:
     * ``c96``: 96^3 elements, 12^3 subdomains, three-level, 20 RHS (adjoint form).
     * ``c192``: 192^3 elements, 24^3 subdomains, three-level, 40-vector basis.
     * ``tiny``: 8^3 elements, 2x2x2 subdomains of 4^3 (tests).
+    * ``c3``: 64^3 box with a spherical hole (radius 0.15, centre 0.5), seeded
+      jittered RCB into 400 face-connected subdomains of uneven size, 50
+      subregions of 8 by RCB, log-normal coefficients (sigma 0.5), R = 20,
+      50 right-hand sides.
+    * ``c3s``: the same construction at 24^3 with 24 subdomains in 3
+      subregions (parity-test size).
     """
     specs = {
         "tiny": dict(nx=8, sub=4, group=0, R=0, n_rhs=3),
@@ -200,6 +338,8 @@ def workload(name: str) -> dict:
         "c96": dict(nx=96, sub=8, group=2, R=20, n_rhs=20),
         "c192": dict(nx=192, sub=8, group=2, R=40, n_rhs=200),
     }
+    if name in ("c3", "c3s"):
+        return _hole_workload(name)
     s = dict(specs[name])
     nx, sub, group = s["nx"], s["sub"], s["group"]
     m = nx // sub
@@ -214,4 +354,20 @@ def workload(name: str) -> dict:
     s["coef"] = np.ones(nx ** 3)
     s["elem_keep"] = None
     s["name"] = name
+    return s
+
+
+def _hole_workload(name: str) -> dict:
+    """Uneven-batching workload: hole, jittered RCB partition, log-normal coefficients."""
+    if name == "c3":
+        nx, n_sub, n_sr, min_int, n_rhs = 64, 400, 50, 0, 50
+    else:
+        nx, n_sub, n_sr, min_int, n_rhs = 24, 24, 3, 0, 3
+    keep = sphere_hole_keep(nx)
+    part = rcb_partition(nx, n_sub, keep, 0.3, 0.7, min_int)
+    s = dict(nx=nx, R=20, n_rhs=n_rhs, name=name, elem_keep=keep, elem_to_sub=part)
+    s["n_sub"] = int(part[keep.astype(bool)].max()) + 1
+    s["sub_to_subregion"] = rcb_subregions(nx, part, keep, n_sr)
+    s["n_subregion"] = n_sr
+    s["coef"] = lognormal_coef(nx ** 3, 0.5)
     return s
