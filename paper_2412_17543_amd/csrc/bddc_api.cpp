@@ -175,6 +175,17 @@ int dalloc(bddc_ctx *c, T **p, size_t count) {
     return 0;
 }
 
+// A packed tile array of `count` elements followed by TILE_TAIL_BYTES zeroed
+// bytes.
+template <typename T>
+int dalloc_tiles(bddc_ctx *c, T **p, size_t count) {
+    const size_t tail = (TILE_TAIL_BYTES + sizeof(T) - 1) / sizeof(T);
+    int rc = dalloc(c, p, count + tail);
+    if (rc) return rc;
+    if (hipMemset(*p + count, 0, tail * sizeof(T)) != hipSuccess) return fail(BDDC_EHIP, "hipMemset failed");
+    return 0;
+}
+
 template <typename T>
 int dupload(bddc_ctx *c, T **p, const std::vector<T> &v) {
     int rc = dalloc(c, p, v.size());
@@ -956,7 +967,7 @@ int setup_interior(bddc_ctx *c, const std::vector<int64_t> &k_off) {
     std::vector<int64_t> ki_off(nsub + 1, 0);
     for (int i = 0; i < nsub; ++i) ki_off[i + 1] = ki_off[i] + ntiles_of(c->h_nI[i], 0) * 256;
     int rc;
-    if ((rc = dupload(c, &c->d_ki_off, ki_off)) || (rc = dalloc(c, &c->d_KI, (size_t)std::max<int64_t>(1, ki_off[nsub]))))
+    if ((rc = dupload(c, &c->d_ki_off, ki_off)) || (rc = dalloc_tiles(c, &c->d_KI, (size_t)std::max<int64_t>(1, ki_off[nsub]))))
         return rc;
     std::vector<PackDesc> pk;
     for (int i = 0; i < nsub; ++i) {
@@ -1254,8 +1265,8 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         // the row-major D Phi_i for the prolongation
         c->bytes_S = (size_t)s_off[nsub] * 8;
         c->bytes_N = (size_t)n_off[nsub] * eN;
-        if ((rc = dalloc(c, &c->d_S, (size_t)s_off[nsub]))) return rc;
-        if ((rc = dalloc(c, (char **)&c->d_N, c->bytes_N))) return rc;
+        if ((rc = dalloc_tiles(c, &c->d_S, (size_t)s_off[nsub]))) return rc;
+        if ((rc = dalloc_tiles(c, (char **)&c->d_N, c->bytes_N))) return rc;
         if ((rc = dalloc(c, (char **)&c->d_phir, (size_t)std::max<int64_t>(1, phr_off[nsub]) * eN))) return rc;
         std::vector<PackDesc> ps(nsub), pn(nsub);
         std::vector<PtspDesc> pt(nsub);

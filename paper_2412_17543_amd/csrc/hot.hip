@@ -47,37 +47,56 @@ struct Acc<uint16_t> {
     using type = float;
 };
 
-typedef double dvec2 __attribute__((ext_vector_type(2)));
-typedef float fvec4 __attribute__((ext_vector_type(4)));
 typedef unsigned int uvec2 __attribute__((ext_vector_type(2)));
 
+typedef unsigned int uvec4 __attribute__((ext_vector_type(4)));
+
+// Buffer resource over `bytes` bytes from p (raw, unswizzled): loads past the
+// end return zero without a memory access.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void *p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, bytes, 0x00020000);
+}
+constexpr int LOAD_NT = 2;          // non-temporal: each tile is read once per product
+
 // The four values lane l holds of a 16x16 tile: rows 4*(l/16)+i, column l%16
-// (element order of tile_index).
+// (element order of tile_index); tile t of the resource (the whole offset is
+// in the vector operand, which is what the range check sees).  settle() waits for
+// a fragment that is not going to be used (a loop exit), so that no path
+// reaches the loop head with its load outstanding.
 template <typename T>
 struct Frag;
 template <>
 struct Frag<double> {
-    dvec2 a, b;
-    __device__ __forceinline__ void load(const double *t, int l) {
-        a = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(t) + l);
-        b = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(t) + 64 + l);
+    uvec4 a, b;
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, int t, int l) {
+        a = __builtin_amdgcn_raw_buffer_load_b128(r, t * 2048 + l * 16, 0, LOAD_NT);
+        b = __builtin_amdgcn_raw_buffer_load_b128(r, t * 2048 + 1024 + l * 16, 0, LOAD_NT);
     }
-    __device__ __forceinline__ void get(double v[4]) const { v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; }
+    __device__ __forceinline__ void settle() const { asm volatile("" ::"v"(a), "v"(b)); }
+    __device__ __forceinline__ void get(double v[4]) const {
+        v[0] = __hiloint2double(a.y, a.x); v[1] = __hiloint2double(a.w, a.z);
+        v[2] = __hiloint2double(b.y, b.x); v[3] = __hiloint2double(b.w, b.z);
+    }
 };
 template <>
 struct Frag<float> {
-    fvec4 a;
-    __device__ __forceinline__ void load(const float *t, int l) {
-        a = __builtin_nontemporal_load(reinterpret_cast<const fvec4 *>(t) + l);
+    uvec4 a;
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, int t, int l) {
+        a = __builtin_amdgcn_raw_buffer_load_b128(r, t * 1024 + l * 16, 0, LOAD_NT);
     }
-    __device__ __forceinline__ void get(float v[4]) const { v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; }
+    __device__ __forceinline__ void settle() const { asm volatile("" ::"v"(a)); }
+    __device__ __forceinline__ void get(float v[4]) const {
+        v[0] = __uint_as_float(a.x); v[1] = __uint_as_float(a.y);
+        v[2] = __uint_as_float(a.z); v[3] = __uint_as_float(a.w);
+    }
 };
 template <>
 struct Frag<uint16_t> {
     uvec2 a;
-    __device__ __forceinline__ void load(const uint16_t *t, int l) {
-        a = __builtin_nontemporal_load(reinterpret_cast<const uvec2 *>(t) + l);
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, int t, int l) {
+        a = __builtin_amdgcn_raw_buffer_load_b64(r, t * 512 + l * 8, 0, LOAD_NT);
     }
+    __device__ __forceinline__ void settle() const { asm volatile("" ::"v"(a)); }
     __device__ __forceinline__ void get(float v[4]) const {
         v[0] = dev::bf16_to_f32(a.x & 0xffffu);
         v[1] = dev::bf16_to_f32(a.x >> 16);
@@ -85,6 +104,58 @@ struct Frag<uint16_t> {
         v[3] = dev::bf16_to_f32(a.y >> 16);
     }
 };
+
+// Cross-lane moves without LDS: DPP within rows of 16 lanes, and the gfx950
+// row-swap permutes across rows.  Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+constexpr int DPP_XOR1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> i ^ 7 within 8 lanes
+constexpr int DPP_ROR8 = 0x128;     // lane i <-> i ^ 8 within 16 lanes
+
+// v + v[l ^ 16] and then + [l ^ 32]: the sum over the four lanes l % 16 + 16 g.
+__device__ __forceinline__ float col_sum4(float v) {
+    auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+__device__ __forceinline__ double col_sum4(double v) {
+    auto pl = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    auto ph = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    v = __hiloint2double(ph[0], pl[0]) + __hiloint2double(ph[1], pl[1]);
+    auto ql = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    auto qh = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double(qh[0], ql[0]) + __hiloint2double(qh[1], ql[1]);
+}
+
+// Sums of ra[0..3] over the 16 lanes of a row of the wave, by exchange:
+// lanes with bit 3 set keep rows 2, 3 and pass rows 0, 1 to lane ^ 8 (and
+// the converse), then bit 2 halves again against the mirrored lane, and two
+// quad swaps finish.  Returns, in every lane, the full sum of ra[cl >> 2].
+template <typename A>
+__device__ __forceinline__ A row_sum4(const A (&ra)[4], int cl) {
+    const bool b3 = (cl & 8) != 0, b2 = (cl & 4) != 0;
+    A k0 = b3 ? ra[2] : ra[0], k1 = b3 ? ra[3] : ra[1];
+    const A s0 = b3 ? ra[0] : ra[2], s1 = b3 ? ra[1] : ra[3];
+    k0 += dpp<DPP_ROR8>(s0);
+    k1 += dpp<DPP_ROR8>(s1);
+    A m = b2 ? k1 : k0;
+    const A sd = b2 ? k0 : k1;
+    m += dpp<DPP_HALF_MIRROR>(sd);
+    m += dpp<DPP_XOR1>(m);
+    m += dpp<DPP_XOR2>(m);
+    return m;
+}
 
 __device__ __forceinline__ double to_d(double v) { return v; }
 __device__ __forceinline__ double to_d(float v) { return (double)v; }
@@ -207,10 +278,11 @@ __global__ void __launch_bounds__(NW * 64) k_symv(SymvArgs a) {
 
     const T *tb = reinterpret_cast<const T *>(a.op.tiles) + a.op.t_off[sub];
     const int span = it.t1 - it.t0;
-    const int w0 = it.t0 + (int)((int64_t)span * w / NW);
-    const int w1 = it.t0 + (int)((int64_t)span * (w + 1) / NW);
-    ACC *myy = yw + w * npad;
-    ACC *myc = cw + w * ntc * TILE;
+    const int wu = __builtin_amdgcn_readfirstlane(w);     // wave-uniform control flow
+    const int w0 = it.t0 + (int)((int64_t)span * wu / NW);
+    const int w1 = it.t0 + (int)((int64_t)span * (wu + 1) / NW);
+    ACC *myy = yw + wu * npad;
+    ACC *myc = cw + wu * ntc * TILE;
     if (w0 < w1) {
         int I = 0, rs = 0;
         while (rs + (nt - I + ntc) <= w0) { rs += nt - I + ntc; ++I; }
@@ -218,41 +290,37 @@ __global__ void __launch_bounds__(NW * 64) k_symv(SymvArgs a) {
         ACC xi[4], ra[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) { xi[q] = xs[I * TILE + g4 + q]; ra[q] = (ACC)0; }
-        for (int t = w0; t < w1; t += U) {
-            Frag<T> f[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (t + u < w1) f[u].load(tb + (int64_t)(t + u) * 256, l);
+        // tiles past w1 read as zero without a memory access, so the loads of
+        // the next U tiles are issued unconditionally while the current U are
+        // used (two register sets in turn: no copy waits for a load)
+        // resource over tiles [t, w1) for a stage starting at tile t
+        auto stage = [&](int t) {
+            return tile_rsrc(tb + (int64_t)t * 256, max(w1 - t, 0) * 256 * (int)sizeof(T));
+        };
+        // Every fragment is used arithmetically on every path (a tile past
+        // w1 reads as zero and only its bookkeeping is skipped), so no path
+        // leaves a load outstanding when its registers are loaded again.
+        auto use = [&](const Frag<T> (&f)[U], int t) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (t + u >= w1) break;
+                const bool live = t + u < w1;
                 ACC v[4];
                 f[u].get(v);
-                if (J < nt) {
-                    const ACC xj = xs[J * TILE + cl];
+                // no direct part in coarse columns, nor past the range
+                const ACC xj = (live && J < nt) ? xs[J * TILE + cl] : (ACC)0;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) ra[q] += v[q] * xj;
-                }
-                if (J != I) {
-                    ACC s = v[0] * xi[0] + v[1] * xi[1] + v[2] * xi[2] + v[3] * xi[3];
-                    s += __shfl_xor(s, 16);
-                    s += __shfl_xor(s, 32);
-                    if (l < 16) {
-                        ACC *dst = (J < nt) ? (myy + J * TILE) : (myc + (J - nt) * TILE);
-                        dst[cl] += s;
-                    }
+                for (int q = 0; q < 4; ++q) ra[q] += v[q] * xj;
+                const ACC s = col_sum4(v[0] * xi[0] + v[1] * xi[1] + v[2] * xi[2] + v[3] * xi[3]);
+                if (!live) continue;
+                if (J != I && l < 16) {
+                    ACC *dst = (J < nt) ? (myy + J * TILE) : (myc + (J - nt) * TILE);
+                    dst[cl] += s;
                 }
                 if (++J == nt + ntc) {
+                    const ACC m = row_sum4(ra, cl);
+                    if ((cl & 3) == 0) myy[I * TILE + g4 + (cl >> 2)] += m;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        ACC s = ra[q];
-                        s += __shfl_xor(s, 1);
-                        s += __shfl_xor(s, 2);
-                        s += __shfl_xor(s, 4);
-                        s += __shfl_xor(s, 8);
-                        if (cl == 0) myy[I * TILE + g4 + q] += s;
-                        ra[q] = (ACC)0;
-                    }
+                    for (int q = 0; q < 4; ++q) ra[q] = (ACC)0;
                     ++I;
                     J = I;
                     if (I < nt) {
@@ -261,17 +329,33 @@ __global__ void __launch_bounds__(NW * 64) k_symv(SymvArgs a) {
                     }
                 }
             }
+        };
+        Frag<T> fa[U], fb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) fa[u].load(stage(w0), u, l);
+        for (int t = w0;;) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) fb[u].load(stage(t + U), u, l);
+            use(fa, t);
+            t += U;
+            if (t >= w1) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) fb[u].settle();
+                break;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) fa[u].load(stage(t + U), u, l);
+            use(fb, t);
+            t += U;
+            if (t >= w1) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) fa[u].settle();
+                break;
+            }
         }
         if (J != I) {   // flush a partly processed tile row
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                ACC s = ra[q];
-                s += __shfl_xor(s, 1);
-                s += __shfl_xor(s, 2);
-                s += __shfl_xor(s, 4);
-                s += __shfl_xor(s, 8);
-                if (cl == 0) myy[I * TILE + g4 + q] += s;
-            }
+            const ACC m = row_sum4(ra, cl);
+            if ((cl & 3) == 0) myy[I * TILE + g4 + (cl >> 2)] += m;
         }
     }
     __syncthreads();

@@ -12,6 +12,9 @@
 namespace bddc {
 
 constexpr int TILE = 16;          // symmetric operators are stored as 16x16 tiles
+// zeroed bytes after every packed tile array: the product kernel's prefetch
+// of up to 8 tiles past a work range stays inside the allocation
+constexpr int64_t TILE_TAIL_BYTES = 8 * 256 * 8;
 constexpr int RMAX = 64;          // largest deflation basis supported
 constexpr int VGRID = 512;        // blocks of the grid-stride vector kernels (max)
 
