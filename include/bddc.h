@@ -98,12 +98,21 @@ typedef struct {
     int32_t autotune;        /* 1 (default): time a few work-list sizes, waves per
                                 block and tiles in flight of the two batched operator
                                 products at setup and keep the fastest; 0: fixed     */
-    int32_t reserved[3];
+    int32_t coarse_form;     /* three levels only: how the level-2 BDDC approximation
+                                of K_C^{-1} is applied.  1: the subregion chain of
+                                Section 3.2 (level-2 solves, level-3 coarse solve,
+                                level-2 correction) at every application; 2: that
+                                same linear operator assembled once at setup, column
+                                by column through the chain, into a dense nC x nC
+                                matrix applied as one product (nC <= 8192, else
+                                EINVAL); 0 (default): 2 when nC <= 4096, else 1     */
+    int32_t reserved[2];
 } bddc_opts;
 
 /* Fills *o with the defaults: corners+faces, diag weights, float64 local
  * operators, R = 0, B4, freeze 1e-5, ||r||/||b||, previous-solution guess,
- * max_it 1000, save_cap 256, graph-captured iteration, autotuned products. */
+ * max_it 1000, save_cap 256, graph-captured iteration, autotuned products,
+ * automatic coarse form. */
 void bddc_default_opts(bddc_opts *o);
 
 /*

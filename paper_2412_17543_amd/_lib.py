@@ -31,7 +31,7 @@ class Opts(ctypes.Structure):
                 ("recycle_R", c_int32), ("recycle_strategy", c_int32), ("ritz_freeze_tol", c_double),
                 ("stop_rule", c_int32), ("init_guess", c_int32), ("max_it", c_int32),
                 ("save_cap", c_int32), ("use_graph", c_int32), ("autotune", c_int32),
-                ("reserved", c_int32 * 3)]
+                ("coarse_form", c_int32), ("reserved", c_int32 * 2)]
 
 
 class BddcError(RuntimeError):

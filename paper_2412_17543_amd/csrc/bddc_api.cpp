@@ -117,6 +117,11 @@ struct bddc_ctx {
     int32_t *d_c3o = nullptr, *d_n3p = nullptr, *d_sr_ptr = nullptr, *d_sr_sub = nullptr, *d_cL = nullptr;
     size_t smem_l2d = 0;
     bool fuse_prolong = false;      // three levels with enough subregions to fill the GPU
+    bool coarse_dense = false;      // u_C from one dense product (two levels, or explicit form)
+    // dense coarse operator, row-major nC x nC with rows of ldm (even)
+    // entries: -K_C^{-1} (two levels) or the explicit level-2 BDDC operator
+    double *d_Mc = nullptr, *d_rC = nullptr;
+    int64_t ldm = 0;
     int64_t *d_K2_off = nullptr, *d_N2_off = nullptr, *d_P2_off = nullptr;
     double *d_K2 = nullptr, *d_N2 = nullptr, *d_Phi2 = nullptr, *d_K3inv = nullptr, *d_vI2 = nullptr,
            *d_t2 = nullptr, *d_rB2 = nullptr, *d_u2 = nullptr, *d_c3loc = nullptr, *d_u3 = nullptr;
@@ -364,6 +369,40 @@ void run_schur(bddc_ctx *c, const double *x, bool gated, bool dot) {
     launch_symv(a, 64, c->opS.cfg, c->opS.smem, c->stream);
 }
 
+// Arguments of the level-2/3 kernels with the level-1 coarse residual taken
+// from `rc` (no prolongation).
+L2Args l2_args(const bddc_ctx *c, const Gather &rc) {
+    L2Args l{};
+    l.ctl = c->d_ctl;
+    l.rc = rc;
+    l.nL = c->d_nL; l.nI2 = c->d_nI2; l.L_off = c->d_L_off; l.L = c->d_L; l.I2_off = c->d_I2_off;
+    l.B2_off = c->d_B2_off; l.g2 = c->d_g2;
+    l.K2_off = c->d_K2_off; l.K2 = c->d_K2; l.vI2 = c->d_vI2; l.t2 = c->d_t2; l.rB2 = c->d_rB2;
+    l.asm2_ptr = c->d_asm2_ptr; l.asm2_idx = c->d_asm2_idx; l.N2_off = c->d_N2_off; l.N2 = c->d_N2;
+    l.P2_off = c->d_P2_off; l.Phi2 = c->d_Phi2; l.nc3 = c->d_nc3; l.C3_off = c->d_C3_off; l.c3 = c->d_c3;
+    l.u2 = c->d_u2; l.c3loc = c->d_c3loc; l.pos_sr = c->d_pos_sr; l.own2 = c->d_own2; l.u3 = c->d_u3;
+    l.uC = c->d_uC;
+    l.ph_off = c->d_ph_off2; l.c3o = c->d_c3o; l.n3p = c->d_n3p; l.n3 = c->n3; l.max_nL = c->max_nL;
+    l.sr_ptr = c->d_sr_ptr; l.sr_sub = c->d_sr_sub; l.cL = c->d_cL;
+    l.nB = c->d_nB; l.b_off = c->d_b_off; l.nc = c->d_nc; l.c_off = c->d_c_off;
+    l.nchunk = c->opN.d_nchunk; l.pb = c->opN.d_pb; l.upart = c->opN.d_ypart;
+    l.phir = c->d_phir; l.phr_off = c->d_phr_off; l.wloc = nullptr;
+    return l;
+}
+
+// Level-2 BDDC applied to the level-1 coarse residual (Section 3.2,
+// multilevel paragraph): subregion pre-solves, level-2 interface residual
+// and local solves, level-3 coarse solve, level-2 correction into u_C.
+void run_l2_chain(const bddc_ctx *c, const L2Args &l, hipStream_t st) {
+    launch_l2_a(l, c->nsr, c->max_nL, st);
+    launch_l2_b(l, c->nsr, c->max_nL, st);
+    L3Args l3{};
+    l3.ctl = c->d_ctl; l3.n = c->n3; l3.ptr = c->d_asm3_ptr; l3.idx = c->d_asm3_idx; l3.loc = c->d_c3loc;
+    l3.Kneg = c->d_K3inv; l3.u = c->d_u3;
+    launch_l3(l3, st);
+    launch_l2_d(l, c->prec, c->nsr, c->smem_l2d, st);
+}
+
 // One BDDC application on r: local constrained-Neumann products and coarse
 // residuals, the coarse problem, assembly of z with the coarse prolongation
 // and the (r^T z, (AW)^T z) partials.  test: stopping test at the start
@@ -389,39 +428,23 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
     if (c->nC > 0) {
         TScope ts(c, TK_COARSE);
         const Gather rc = gather_of(c->opN, true);
-        if (c->three) {
-            L2Args l{};
-            l.ctl = c->d_ctl;
-            l.rc = rc;
-            l.nL = c->d_nL; l.nI2 = c->d_nI2; l.L_off = c->d_L_off; l.L = c->d_L; l.I2_off = c->d_I2_off;
-            l.B2_off = c->d_B2_off; l.g2 = c->d_g2;
-            l.K2_off = c->d_K2_off; l.K2 = c->d_K2; l.vI2 = c->d_vI2; l.t2 = c->d_t2; l.rB2 = c->d_rB2;
-            l.asm2_ptr = c->d_asm2_ptr; l.asm2_idx = c->d_asm2_idx; l.N2_off = c->d_N2_off; l.N2 = c->d_N2;
-            l.P2_off = c->d_P2_off; l.Phi2 = c->d_Phi2; l.nc3 = c->d_nc3; l.C3_off = c->d_C3_off; l.c3 = c->d_c3;
-            l.u2 = c->d_u2; l.c3loc = c->d_c3loc; l.pos_sr = c->d_pos_sr; l.own2 = c->d_own2; l.u3 = c->d_u3;
-            l.uC = c->d_uC;
-            l.ph_off = c->d_ph_off2; l.c3o = c->d_c3o; l.n3p = c->d_n3p; l.n3 = c->n3; l.max_nL = c->max_nL;
-            l.sr_ptr = c->d_sr_ptr; l.sr_sub = c->d_sr_sub; l.cL = c->d_cL;
-            l.nB = c->d_nB; l.b_off = c->d_b_off; l.nc = c->d_nc; l.c_off = c->d_c_off;
-            l.nchunk = c->opN.d_nchunk; l.pb = c->opN.d_pb; l.upart = c->opN.d_ypart;
-            l.phir = c->d_phir; l.phr_off = c->d_phr_off; l.wloc = c->fuse_prolong ? c->d_wloc : nullptr;
-            launch_l2_a(l, c->nsr, c->max_nL, c->stream);
-            launch_l2_b(l, c->nsr, c->max_nL, c->stream);
-            L3Args l3{};
-            l3.ctl = c->d_ctl; l3.n = c->n3; l3.ptr = c->d_asm3_ptr; l3.idx = c->d_asm3_idx; l3.loc = c->d_c3loc;
-            l3.Kneg = c->d_K3inv; l3.u = c->d_u3;
-            launch_l3(l3, c->stream);
-            launch_l2_d(l, c->prec, c->nsr, c->smem_l2d, c->stream);   // with the prolongation
+        if (c->coarse_dense) {
+            CoarseDenseArgs ca{};
+            ca.ctl = c->d_ctl; ca.n = c->nC; ca.rc = rc; ca.r = c->d_rC;
+            ca.M = c->d_Mc; ca.ldm = c->ldm;
+            ca.sign = c->three ? 1.0 : -1.0;
+            ca.u = c->d_uC;
+            launch_coarse_dense(ca, c->stream);
         } else {
-            Coarse2Args ca{};
-            ca.ctl = c->d_ctl; ca.n = c->nC; ca.rc = rc; ca.Kneg = c->d_KCinv; ca.u = c->d_uC;
-            launch_coarse2(ca, c->stream);
+            L2Args l = l2_args(c, rc);
+            l.wloc = c->fuse_prolong ? c->d_wloc : nullptr;
+            run_l2_chain(c, l, c->stream);   // with the prolongation when fused
         }
     }
     {
         TScope ts(c, TK_VEC);
         ProlArgs pa{};
-        const bool prolonged = c->fuse_prolong;        // done by k_l2_d
+        const bool prolonged = !c->coarse_dense && c->fuse_prolong;   // done by k_l2_d
         pa.ctl = c->d_ctl; pa.gated = gated ? 1 : 0;
         pa.nB = c->d_nB; pa.b_off = c->d_b_off; pa.nc = c->d_nc; pa.c_off = c->d_c_off; pa.cidx = c->d_cidx;
         pa.nchunk = c->opN.d_nchunk; pa.pb = c->opN.d_pb; pa.upart = c->opN.d_ypart;
@@ -903,6 +926,7 @@ void bddc_default_opts(bddc_opts *o) {
     o->save_cap = 256;
     o->use_graph = 1;
     o->autotune = 1;
+    o->coarse_form = 0;
 }
 
 const char *bddc_last_error(void) { return g_err.c_str(); }
@@ -1092,6 +1116,51 @@ int tune_operators(bddc_ctx *c) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+// Row-major copy of an nC x nC matrix (given column-major when `transpose`)
+// with rows padded to an even length, and the r_C buffer of the dense product.
+int upload_dense_coarse(bddc_ctx *c, const std::vector<double> &h, bool transpose) {
+    const int n = c->nC;
+    c->ldm = (n + 1) & ~1;
+    std::vector<double> t((size_t)n * c->ldm, 0.0);
+    for (int r = 0; r < n; ++r)
+        for (int q = 0; q < n; ++q)
+            t[(size_t)r * c->ldm + q] = transpose ? h[(size_t)q * n + r] : h[(size_t)r * n + q];
+    int rc;
+    if ((rc = dupload(c, &c->d_Mc, t)) || (rc = dalloc(c, &c->d_rC, (size_t)std::max(1, n)))) return rc;
+    return 0;
+}
+
+// The level-2 BDDC approximation of K_C^{-1} is a fixed linear operator: its
+// columns are the level-2/3 chain applied to the unit vectors e_q (rc reads
+// the coarse residual from one dense vector), stored row-major.
+int build_explicit_coarse(bddc_ctx *c) {
+    const int n = c->nC;
+    hipStream_t s = c->stream;
+    std::vector<int32_t> ptr(n + 1), idx(n);
+    for (int q = 0; q <= n; ++q) ptr[q] = q;
+    for (int q = 0; q < n; ++q) idx[q] = q;
+    int32_t *dp, *di;
+    double *de, *dcol;
+    int rc;
+    if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) || (rc = dalloc(c, &de, (size_t)n)) ||
+        (rc = dalloc(c, &dcol, (size_t)n * n)))
+        return rc;
+    launch_fill(n, 0.0, de, s);
+    launch_set_done(c->d_ctl, 0, s);
+    const L2Args l = l2_args(c, Gather{dp, di, de});
+    for (int q = 0; q < n; ++q) {
+        launch_fill(1, 1.0, de + q, s);
+        run_l2_chain(c, l, s);
+        launch_copy(n, c->d_uC, dcol + (int64_t)q * n, s);
+        launch_fill(1, 0.0, de + q, s);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<double> h((size_t)n * n);
+    HIPCHK(hipMemcpy(h.data(), dcol, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    dfree(c, dp); dfree(c, di); dfree(c, de); dfree(c, dcol);
+    return upload_dense_coarse(c, h, true);
 }
 
 int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, const double *coef) {
@@ -1327,6 +1396,13 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         }
         HIPCHK(hipStreamSynchronize(s));
         dfree(c, dp); dfree(c, di); dfree(c, dsd);
+        if (n > 0) {
+            std::vector<double> h((size_t)n * n);
+            HIPCHK(hipMemcpy(h.data(), c->d_KCinv, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+            if ((rc = upload_dense_coarse(c, h, false))) return rc;
+        }
+        dfree(c, c->d_KCinv);
+        c->d_KCinv = nullptr;
     } else {
         const int nsr = st.n_sr;
         c->nsr = nsr;
@@ -1576,6 +1652,18 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
                          (rc = dalloc(c, &c->d_P, (size_t)std::max(1, c->save_cap) * ng)) ||
                          (rc = dalloc(c, &c->d_AP, (size_t)std::max(1, c->save_cap) * ng))))
             return rc;
+    }
+    // coarse form: one dense product for two levels; for three levels the
+    // explicit operator when the coarse space is small enough (option)
+    c->coarse_dense = !c->three;
+    if (c->three && c->nC > 0) {
+        const int form = c->opts.coarse_form;
+        if (form < 0 || form > 2) return fail(BDDC_EINVAL, "coarse_form must be 0, 1 or 2");
+        if (form == 2 && c->nC > 8192) return fail(BDDC_EINVAL, "explicit coarse operator above 8192 DOFs");
+        if (form == 2 || (form == 0 && c->nC <= 4096)) {
+            if ((rc = build_explicit_coarse(c))) return rc;
+            c->coarse_dense = true;
+        }
     }
     if (c->opts.autotune && (rc = tune_operators(c))) return rc;
     if ((rc = dalloc(c, &c->d_dotS, (size_t)c->opS.dev.n_items))) return rc;

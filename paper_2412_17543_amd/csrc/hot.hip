@@ -7,7 +7,8 @@
 //   k_symv (S)   q_i = S_i p_i                      Alg. 1 line 9 (A p)
 //   k_update     alpha, x += alpha p, r -= alpha q  lines 9-11
 //   k_symv (N)   stopping test (Section 5); u_i = D N_i D r_i, c_i = (D Phi_i)^T r_i
-//   coarse       two levels: k_coarse2; three levels: k_l2_a, k_l2_b, k_l3, k_l2_d
+//   coarse       k_coarse_dense (two levels, or three levels in explicit form);
+//                three levels as a chain: k_l2_a, k_l2_b, k_l3, k_l2_d
 //   k_prolong    w_i = u_i + D Phi_i u_C            eq. averaging_subdomain_solves
 //   k_zasm       z = sum_i R_i^T w_i, r^T z, (AW)^T z   line 13
 //   k_pupd       beta, mu, p = z + beta p - W mu    lines 14-16
@@ -270,33 +271,43 @@ __global__ void __launch_bounds__(NW * 64) k_symv(SymvArgs a) {
     ACC *yw = xs + npad;
     ACC *cw = yw + NW * npad;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g4 = 4 * (l >> 4), cl = l & 15;
-    const int boff = a.op.b_off[sub];
-    for (int k = tid; k < npad; k += NW * 64) xs[k] = k < n ? (ACC)a.x[a.op.gB[boff + k]] : (ACC)0;
-    for (int k = tid; k < NW * npad; k += NW * 64) yw[k] = (ACC)0;
-    for (int k = tid; k < NW * ntc * TILE; k += NW * 64) cw[k] = (ACC)0;
-    __syncthreads();
-
     const T *tb = reinterpret_cast<const T *>(a.op.tiles) + a.op.t_off[sub];
     const int span = it.t1 - it.t0;
     const int wu = __builtin_amdgcn_readfirstlane(w);     // wave-uniform control flow
     const int w0 = it.t0 + (int)((int64_t)span * wu / NW);
     const int w1 = it.t0 + (int)((int64_t)span * (wu + 1) / NW);
+    // Tiles past w1 read as zero without a memory access (resource over
+    // tiles [t, w1) for the stage starting at tile t), so the loads of the
+    // next U tiles are issued unconditionally while the current U are used;
+    // two register sets in turn, so that no copy waits for a load.  The first
+    // stage is in flight while the block gathers its input.
+    auto stage = [&](int t) {
+        return tile_rsrc(tb + (int64_t)t * 256, max(w1 - t, 0) * 256 * (int)sizeof(T));
+    };
+    const int32_t *gb = a.op.gB + a.op.b_off[sub];
+    const int g0 = gb[min(tid, n - 1)];                   // first gather index, ahead of the tiles
+    asm volatile("" ::: "memory");                        // (keeps that load first)
+    Frag<T> fa[U], fb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) fa[u].load(stage(w0), u, l);
+
+    for (int k = tid; k < npad; k += NW * 64) xs[k] = k < n ? (ACC)a.x[k == tid ? g0 : gb[k]] : (ACC)0;
+    for (int k = tid; k < NW * npad; k += NW * 64) yw[k] = (ACC)0;
+    for (int k = tid; k < NW * ntc * TILE; k += NW * 64) cw[k] = (ACC)0;
+    __syncthreads();
+
     ACC *myy = yw + wu * npad;
     ACC *myc = cw + wu * ntc * TILE;
-    if (w0 < w1) {
+    if (w0 >= w1) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) fa[u].settle();
+    } else {
         int I = 0, rs = 0;
         while (rs + (nt - I + ntc) <= w0) { rs += nt - I + ntc; ++I; }
         int J = I + (w0 - rs);
         ACC xi[4], ra[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) { xi[q] = xs[I * TILE + g4 + q]; ra[q] = (ACC)0; }
-        // tiles past w1 read as zero without a memory access, so the loads of
-        // the next U tiles are issued unconditionally while the current U are
-        // used (two register sets in turn: no copy waits for a load)
-        // resource over tiles [t, w1) for a stage starting at tile t
-        auto stage = [&](int t) {
-            return tile_rsrc(tb + (int64_t)t * 256, max(w1 - t, 0) * 256 * (int)sizeof(T));
-        };
         // Every fragment is used arithmetically on every path (a tile past
         // w1 reads as zero and only its bookkeeping is skipped), so no path
         // leaves a load outstanding when its registers are loaded again.
@@ -330,9 +341,6 @@ __global__ void __launch_bounds__(NW * 64) k_symv(SymvArgs a) {
                 }
             }
         };
-        Frag<T> fa[U], fb[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) fa[u].load(stage(w0), u, l);
         for (int t = w0;;) {
 #pragma unroll
             for (int u = 0; u < U; ++u) fb[u].load(stage(t + U), u, l);
@@ -624,15 +632,42 @@ __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
 // ---------------------------------------------------------------------------
 // Two levels: r_C = sum_i R_Ci^T c_i, u_C = K_C^{-1} r_C with the dense
 // inverse (stored negated by the sweep); block b computes rows [64b, 64b+64).
-__global__ void __launch_bounds__(1024) k_coarse2(Coarse2Args a) {
-    extern __shared__ double rs[];
-    __shared__ double part[16][64];
+// r_C assembled once from the coarse partials (fixed order).
+__global__ void __launch_bounds__(256) k_coarse_rhs(CoarseDenseArgs a) {
     if (a.ctl->done) return;
-    for (int q = threadIdx.x; q < a.n; q += blockDim.x) rs[q] = gather_sum(a.rc, q);
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < a.n) a.r[q] = gather_sum(a.rc, q);
+}
+
+// Dense coarse product u_C = sign * M r_C (row-major M): every block stages
+// r_C in LDS; each wave takes one row of the block's CD_ROWS, lanes striding
+// over the columns in 16-byte pieces, four pieces in flight per lane.
+constexpr int CD_ROWS = 4;          // rows per block (one per wave)
+__global__ void __launch_bounds__(256) k_coarse_dense(CoarseDenseArgs a) {
+    extern __shared__ double rs[];
+    if (a.ctl->done) return;
+    const int n = a.n;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) rs[q] = a.r[q];
     __syncthreads();
-    const int r0 = blockIdx.x * 64, r1 = min(a.n, r0 + 64);
-    double *u = a.u;
-    cm_matvec<16>(a.Kneg, a.n, r0, r1, a.n, rs, part, [&](int r, double y) { u[r] = -y; });
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int row = blockIdx.x * CD_ROWS + w;
+    if (row >= n) return;
+    const double *m = a.M + (int64_t)row * a.ldm;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int col = 2 * l;
+    for (; col + 3 * 128 + 1 < n; col += 4 * 128) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double2 v = *reinterpret_cast<const double2 *>(m + col + u * 128);
+            s[u] += v.x * rs[col + u * 128] + v.y * rs[col + u * 128 + 1];
+        }
+    }
+    for (; col < n; col += 128) {
+        s[0] += m[col] * rs[col];
+        if (col + 1 < n) s[1] += m[col + 1] * rs[col + 1];
+    }
+    const double t = wave_sum((s[0] + s[1]) + (s[2] + s[3]));
+    if (l == 0) a.u[row] = a.sign * t;
 }
 
 // Level 2, phase A (one block per subregion): the subregion's coarse
@@ -856,9 +891,10 @@ void launch_reduce(const ReduceArgs &a, hipStream_t s) {
     if (a.ncol > 0) hipLaunchKernelGGL(k_reduce, dim3(a.ncol), dim3(256), 0, s, a);
 }
 
-void launch_coarse2(const Coarse2Args &a, hipStream_t s) {
+void launch_coarse_dense(const CoarseDenseArgs &a, hipStream_t s) {
     if (a.n <= 0) return;
-    hipLaunchKernelGGL(k_coarse2, dim3((a.n + 63) / 64), dim3(1024), (size_t)a.n * 8, s, a);
+    hipLaunchKernelGGL(k_coarse_rhs, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_coarse_dense, dim3((a.n + CD_ROWS - 1) / CD_ROWS), dim3(256), (size_t)a.n * 8, s, a);
 }
 
 void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s) {

@@ -136,11 +136,17 @@ struct ReduceArgs {                 // out[c] = sum_b part[c * n + b]
 };
 
 // ============================================================ coarse levels
-struct Coarse2Args {                // two levels: u_C = K_C^{-1} r_C (dense)
+// u_C = sign * M r_C with a dense row-major n x n matrix M (r_C assembled by
+// a first kernel, the product by a second): two levels,
+// M = -K_C^{-1} (sign -1); three levels in explicit form, M = the level-2
+// BDDC operator assembled at setup (sign +1).
+struct CoarseDenseArgs {
     Ctl *ctl;
     int n;
-    Gather rc;
-    const double *Kneg;             // -K_C^{-1}
+    Gather rc;                      // r_C from the coarse partials
+    double *r;                      // assembled r_C (n)
+    const double *M; int64_t ldm;   // rows padded to an even length (16-byte aligned)
+    double sign;
     double *u;
 };
 
@@ -291,7 +297,7 @@ void launch_pupd(const PupdArgs &a, int kmax, int grid, hipStream_t s);
 void launch_resid(const ResidArgs &a, int kmax, int grid, hipStream_t s);
 void launch_defl_init(const DeflArgs &a, int kmax, int grid, hipStream_t s);
 void launch_reduce(const ReduceArgs &a, hipStream_t s);
-void launch_coarse2(const Coarse2Args &a, hipStream_t s);
+void launch_coarse_dense(const CoarseDenseArgs &a, hipStream_t s);
 void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s);
 void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s);
 void launch_l3(const L3Args &a, hipStream_t s);

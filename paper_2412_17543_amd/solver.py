@@ -33,7 +33,7 @@ class Solver:
                  node_dirichlet=None, ny=None, nz=None, R=0, strategy="B4", local_prec=64,
                  weights="diag", constraints=("corners", "faces"), stop_rule="rhs",
                  init_guess="prev", max_it=1000, save_cap=256, freeze_tol=1e-5,
-                 use_graph=True, autotune=True, device="cuda", stream=None):
+                 use_graph=True, autotune=True, coarse_form="auto", device="cuda", stream=None):
         lib = _lib.load()
         self.lib = lib
         self.device = torch.device(device)
@@ -77,6 +77,7 @@ class Solver:
         o.save_cap = save_cap
         o.use_graph = 1 if use_graph else 0
         o.autotune = 1 if autotune else 0
+        o.coarse_form = {"auto": 0, "chain": 1, "explicit": 2}[coarse_form]
         self.opts = o
         torch.cuda.set_device(self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)

@@ -51,7 +51,7 @@ def test_default_opts(lib):
     lib.bddc_default_opts(ctypes.byref(o))
     assert o.constraints == 3 and o.weights == 1 and o.local_prec == 64
     assert o.recycle_strategy == 4 and o.ritz_freeze_tol == 1e-5 and o.max_it == 1000
-    assert o.use_graph == 1 and o.autotune == 1 and o.save_cap == 256
+    assert o.use_graph == 1 and o.autotune == 1 and o.save_cap == 256 and o.coarse_form == 0
 
 
 def _setup(lib, nx=4, e2s=None, coef=None, **ov):

@@ -11,7 +11,10 @@ Tolerances (same reasoning as test_gpu_parity.py):
     1e-7 of the converged oracle solution;
   * adjoint gradient: solves at rtol 1e-12, gradient within 1e-8 of the
     oracle's direct-solve gradient (which the oracle tests pin to central
-    differences), plus a direct finite-difference check through GPU solves.
+    differences), plus a direct finite-difference check through GPU solves;
+  * three-level coarse operator applied through the subregion chain or as the
+    explicit matrix assembled from it: the same linear operator up to
+    rounding (1e-12 relative on M r, both within 1e-9 of the oracle).
 """
 import numpy as np
 import pytest
@@ -234,3 +237,30 @@ def test_uneven_partition_with_hole_matches_oracle(prec):
         assert np.all(np.abs(its - ito) <= 1)
     for k in range(len(F)):
         assert _rel(U[k].cpu().numpy(), uo[k]) <= (1e-9 if prec == 64 else 1e-7)
+
+
+@pytest.mark.parametrize("name", ["tiny3", "c3s"])
+def test_explicit_three_level_operator_matches_subregion_chain(name):
+    torch = _torch()
+    from oracle.sequence import OracleSolver
+    s = workload.workload(name)
+    mk = _hole_solver if name == "c3s" else _solver
+    gc = mk(name, coarse_form="chain")
+    ge = mk(name, coarse_form="explicit")
+    o = OracleSolver(s["nx"], s["elem_to_sub"], s["coef"], elem_keep=s["elem_keep"],
+                     sub_to_subregion=s["sub_to_subregion"])
+    rng = np.random.default_rng(11)
+    for _ in range(2):
+        r = rng.standard_normal(o.ss.n_gamma)
+        zc = gc.apply_precond(torch.tensor(r, device="cuda")).cpu().numpy()
+        ze = ge.apply_precond(torch.tensor(r, device="cuda")).cpu().numpy()
+        zo = o.M.apply(r)
+        assert _rel(ze, zc) < 1e-12
+        assert _rel(zc, zo) < 1e-9 and _rel(ze, zo) < 1e-9
+    F = workload.rhs_sequence(s["nx"], 2, s["elem_keep"])
+    Ft = torch.tensor(F, device="cuda")
+    Uc, itc, _ = gc.solve_sequence(Ft, 1e-10)
+    Ue, ite, _ = ge.solve_sequence(Ft, 1e-10)
+    assert np.all(np.abs(itc - ite) <= 1)
+    for k in range(len(F)):
+        assert _rel(Ue[k].cpu().numpy(), Uc[k].cpu().numpy()) <= 1e-9
