@@ -829,7 +829,7 @@ int do_recycle(bddc_ctx *c) {
     // generalized eigenproblem G y = theta F y: F = U diag(lam) U^T, directions
     // with lam < 1e-12 max dropped, T = U lam^{-1/2}, H = T^T G T
     std::vector<double> lam, U;
-    jacobi_eig(F, m, lam, U);
+    sym_eig(F, m, lam, U);
     const double lmax = *std::max_element(lam.begin(), lam.end());
     std::vector<int> keep;
     for (int i = 0; i < m; ++i)
@@ -855,7 +855,7 @@ int do_recycle(bddc_ctx *c) {
     for (int i = 0; i < mk; ++i)
         for (int j = i + 1; j < mk; ++j) H[(size_t)i * mk + j] = H[(size_t)j * mk + i] = 0.5 * (H[(size_t)i * mk + j] + H[(size_t)j * mk + i]);
     std::vector<double> th, Z;
-    jacobi_eig(H, mk, th, Z);
+    sym_eig(H, mk, th, Z);
     std::vector<int> ord(mk);
     std::iota(ord.begin(), ord.end(), 0);
     if (strat == 4) std::reverse(ord.begin(), ord.end());   // descending for B4
@@ -1076,7 +1076,7 @@ int tune_operators(bddc_ctx *c) {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     int rc = 0;
-    const int ipcs[4] = {2, 4, 8, 16};
+    const int ipcs[6] = {2, 3, 4, 6, 8, 16};
     OpHost *ops[3] = {&c->opS, &c->opN, &c->opI};
     for (int w = 0; w < 3 && rc == 0; ++w) {
         OpHost &op = *ops[w];
@@ -1612,7 +1612,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
     c->save_cap = c->R > 0 ? c->opts.save_cap : 0;
     c->hist_cap = c->opts.max_it + 2;
     c->vgrid = std::max(1, std::min(VGRID, (ng + 255) / 256));
-    const int gram_nb = std::max(1, std::min(256, (ng + 1023) / 1024));
+    const int gram_nb = std::max(1, std::min(512, (ng + 127) / 128));
     c->gram_nb = gram_nb;
     c->hcopy = std::min(c->hist_cap, c->save_cap + 2);
     if ((rc = dalloc(c, &c->d_b, ng)) || (rc = dalloc(c, &c->d_x, ng)) || (rc = dalloc(c, &c->d_r, ng)) ||

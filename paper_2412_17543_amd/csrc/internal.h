@@ -78,7 +78,7 @@ int build_structure(const bddc_mesh *m, const bddc_partition *p, const double *c
 // host dense helpers (hostla.cpp)
 bool cholesky(std::vector<double> &a, int n);                       // in place, lower
 void chol_solve(const std::vector<double> &l, int n, double *x);
-void jacobi_eig(std::vector<double> a, int n, std::vector<double> &w, std::vector<double> &v);
+void sym_eig(std::vector<double> a, int n, std::vector<double> &w, std::vector<double> &v);
 
 // ---------------------------------------------------------------------------
 // device-side descriptors
@@ -145,7 +145,7 @@ struct Ctl {
     int32_t k;              // deflation columns in use
     int32_t record;         // store P, AP for recycling
     int32_t zero_rhs;       // b == 0: the solution is x = 0
-    int32_t pad;
+    int32_t pfirst;         // 1: the next search direction starts a cycle (beta = 0)
     int32_t *hflag;         // pinned host word set to 1 together with `done`
 };
 

@@ -287,63 +287,98 @@ __global__ void __launch_bounds__(256) k_scatter_gamma(int n, const int32_t *gam
 
 // ---------------------------------------------------------------------------
 // recycling: out[:, c] = sum_q V[:, q] Y[q][c] for two blocks [W, P] (and
-// [AW, AP]), column-major with leading dimension ld
+// [AW, AP]), column-major with leading dimension ld.  One row per thread,
+// all NC output columns in registers; Y staged in LDS 64 rows at a time and
+// read by broadcast, so every entry of V is read once.
 // ---------------------------------------------------------------------------
+template <int NC>
 __global__ void __launch_bounds__(256) k_recycle_gemm(GemmArgs a) {
+    __shared__ double ys[64][NC];
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.n) return;
-    for (int c0 = 0; c0 < a.ncol; c0 += 8) {
-        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int q = 0; q < a.k1 + a.k2; ++q) {
-            const double v = q < a.k1 ? a.V1[(size_t)q * a.ld + g] : a.V2[(size_t)(q - a.k1) * a.ld + g];
-            const double *y = a.Y + (size_t)q * a.ldy + c0;
+    const int m = a.k1 + a.k2;
+    double acc[NC];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) acc[c] += v * y[c];
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (int q0 = 0; q0 < m; q0 += 64) {
+        const int qn = min(64, m - q0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * NC; e += blockDim.x) {
+            const int q = e / NC, cc = e - q * NC;
+            ys[q][cc] = (q < qn && cc < a.ncol) ? a.Y[(size_t)(q0 + q) * a.ldy + cc] : 0.0;
         }
+        __syncthreads();
+        if (g < a.n) {
+#pragma unroll 4
+            for (int q = 0; q < qn; ++q) {
+                const int qq = q0 + q;
+                const double v = qq < a.k1 ? a.V1[(size_t)qq * a.ld + g] : a.V2[(size_t)(qq - a.k1) * a.ld + g];
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-            if (c0 + c < a.ncol) a.out[(size_t)(c0 + c) * a.ld + g] = acc[c];
+                for (int c = 0; c < NC; ++c) acc[c] += v * ys[q][c];
+            }
+        }
+    }
+    if (g < a.n) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < a.ncol) a.out[(size_t)c * a.ld + g] = acc[c];
     }
 }
 
 // Gram partials: block b sums X^T Y (k x k, X and Y column-major n x k) over
-// its row range, 32-row slabs staged in LDS; part[(p*k+q) * nblocks + b].  A
-// column reduction finishes the (deterministic) sum.
+// its row range in slabs of GRAM_ROWS rows staged in LDS (padded rows, no
+// bank conflicts).  The pairs are taken in 2 x 2 blocks (kb = ceil(k/2) per
+// side), block t -> p in {2 (t/kb), +1}, q in {2 (t%kb), +1}, at most four
+// per thread.  part[(p*k+q) * nblocks + b]; a column reduction finishes the
+// (deterministic) sum.
+constexpr int GRAM_ROWS = 64;
 __global__ void __launch_bounds__(256) k_gram(GramArgs a) {
-    __shared__ double xs[32][RMAX + 1];
-    __shared__ double ys[32][RMAX + 1];
-    const int k = a.k;
-    const int64_t per = ((a.n + gridDim.x - 1) / gridDim.x + 31) / 32 * 32;
+    __shared__ double xs[RMAX][GRAM_ROWS + 1];
+    __shared__ double ys[RMAX][GRAM_ROWS + 1];
+    const int k = a.k, kb = (k + 1) / 2;
+    const int64_t per = (a.n + gridDim.x - 1) / gridDim.x;
     const int64_t g0 = (int64_t)blockIdx.x * per, g1 = min((int64_t)a.n, g0 + per);
-    const int npair = k * k;
-    double acc[16];
+    constexpr int NB = (RMAX / 2) * (RMAX / 2) / 256;     // pair blocks per thread
+    double acc[NB][4];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-    for (int64_t s0 = g0; s0 < g1; s0 += 32) {
+    for (int u = 0; u < NB; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int64_t s0 = g0; s0 < g1; s0 += GRAM_ROWS) {
+        const int nr = (int)min((int64_t)GRAM_ROWS, g1 - s0);
         __syncthreads();
-        for (int t = threadIdx.x; t < 32 * k; t += blockDim.x) {
-            const int rr = t & 31, c = t >> 5;
-            const int64_t g = s0 + rr;
-            const bool ok = g < g1;
-            xs[rr][c] = ok ? a.X[(int64_t)c * a.ld + g] : 0.0;
-            ys[rr][c] = ok ? a.Y[(int64_t)c * a.ld + g] : 0.0;
+        for (int t = threadIdx.x; t < GRAM_ROWS * k; t += blockDim.x) {
+            const int rr = t % GRAM_ROWS, c = t / GRAM_ROWS;
+            const bool ok = rr < nr;
+            xs[c][rr] = ok ? a.X[(int64_t)c * a.ld + s0 + rr] : 0.0;
+            ys[c][rr] = ok ? a.Y[(int64_t)c * a.ld + s0 + rr] : 0.0;
         }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int pq = threadIdx.x + u * blockDim.x;
-            if (pq < npair) {
-                const int p = pq / k, q = pq - p * k;
-                double s = 0.0;
-                for (int rr = 0; rr < 32; ++rr) s += xs[rr][p] * ys[rr][q];
-                acc[u] += s;
+        for (int u = 0; u < NB; ++u) {
+            const int b = threadIdx.x + u * 256;
+            if (b < kb * kb) {
+                const int p0 = 2 * (b / kb), q0 = 2 * (b % kb);
+                const int p1 = min(p0 + 1, k - 1), q1 = min(q0 + 1, k - 1);
+                for (int rr = 0; rr < nr; ++rr) {
+                    const double x0 = xs[p0][rr], x1 = xs[p1][rr], y0 = ys[q0][rr], y1 = ys[q1][rr];
+                    acc[u][0] += x0 * y0;
+                    acc[u][1] += x0 * y1;
+                    acc[u][2] += x1 * y0;
+                    acc[u][3] += x1 * y1;
+                }
             }
         }
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int pq = threadIdx.x + u * blockDim.x;
-        if (pq < npair) a.part[(int64_t)pq * gridDim.x + blockIdx.x] = acc[u];
+    for (int u = 0; u < NB; ++u) {
+        const int b = threadIdx.x + u * 256;
+        if (b >= kb * kb) continue;
+        const int p0 = 2 * (b / kb), q0 = 2 * (b % kb);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int p = p0 + (v >> 1), q = q0 + (v & 1);
+            if (p < k && q < k) a.part[(int64_t)(p * k + q) * gridDim.x + blockIdx.x] = acc[u][v];
+        }
     }
 }
 
@@ -525,7 +560,10 @@ void launch_scatter_gamma(int n, const int32_t *gamma, const double *x, double *
     if (n > 0) hipLaunchKernelGGL(k_scatter_gamma, dim3(nblk(n, 256)), dim3(256), 0, s, n, gamma, x, u);
 }
 void launch_recycle_gemm(const GemmArgs &a, hipStream_t s) {
-    if (a.n > 0) hipLaunchKernelGGL(k_recycle_gemm, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
+    if (a.n <= 0) return;
+    if (a.ncol <= 16) hipLaunchKernelGGL(k_recycle_gemm<16>, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
+    else if (a.ncol <= 32) hipLaunchKernelGGL(k_recycle_gemm<32>, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_recycle_gemm<64>, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
 }
 void launch_gram(const GramArgs &a, int nblocks, hipStream_t s) {
     hipLaunchKernelGGL(k_gram, dim3(nblocks), dim3(256), 0, s, a);
