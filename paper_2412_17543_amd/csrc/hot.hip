@@ -59,6 +59,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void *p, int b
 }
 constexpr int LOAD_NT = 2;          // non-temporal: each tile is read once per product
 
+// Element i of a float64 array through a buffer resource of `n` elements:
+// zero past the end, without a memory access.  A fixed-count loop of such
+// loads needs no per-element condition, so the loads are all issued before
+// the first wait.  Byte offsets below 2^31.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const double *p, int64_t n) {
+    return tile_rsrc(p, (int)(n * 8));
+}
+__device__ __forceinline__ double ld_rc(__amdgpu_buffer_rsrc_t r, int64_t i) {
+    const uvec2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(i * 8), 0, 0);
+    return __hiloint2double(v.y, v.x);
+}
+
 // The four values lane l holds of a 16x16 tile: rows 4*(l/16)+i, column l%16
 // (element order of tile_index); tile t of the resource (the whole offset is
 // in the vector operand, which is what the range check sees).  settle() waits for
@@ -403,6 +415,16 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs a) {
     Ctl *c = a.ctl;
     if (c->done) return;
     const int j = c->j;
+    // the operands of this thread's first node do not depend on alpha: their
+    // loads are issued before the reduction
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double q0 = 0.0, x0 = 0.0, p0 = 0.0, r0 = 0.0;
+    if (g0 < a.n) {
+        q0 = gather_sum(a.q, g0);
+        x0 = a.x[g0];
+        p0 = a.p[g0];
+        r0 = a.r[g0];
+    }
     const double pAp = block_sum_contig(a.dot, a.dot_n, red);
     const double alpha = (j < a.hist_cap ? a.rho_hist[j] : 0.0) / pAp;
     const bool bad = !(pAp > 0.0) || !isfinite(alpha) || j >= a.hist_cap;
@@ -416,10 +438,11 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs a) {
     const bool rec = a.AP && c->record && j < a.cap;
     double rr = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
-        const double q = gather_sum(a.q, g);
-        const double xi = a.x[g] + alpha * a.p[g];
-        const double ri = a.r[g] - alpha * q;
+    for (int64_t g = g0; g < a.n; g += stride) {
+        const bool first = g == g0;
+        const double q = first ? q0 : gather_sum(a.q, g);
+        const double xi = (first ? x0 : a.x[g]) + alpha * (first ? p0 : a.p[g]);
+        const double ri = (first ? r0 : a.r[g]) - alpha * q;
         a.x[g] = xi;
         a.r[g] = ri;
         rr += ri * ri;
@@ -480,9 +503,9 @@ __global__ void __launch_bounds__(256) k_zasm(ZasmArgs a) {
         a.z[g] = z;
         if (a.part) {
             acc[0] += a.r[g] * z;
+            const __amdgpu_buffer_rsrc_t awr = vec_rsrc(a.AW, (int64_t)k * a.ld);
 #pragma unroll
-            for (int q = 0; q < KM; ++q)
-                if (q < k) acc[1 + q] += a.AW[(int64_t)q * a.ld + g] * z;
+            for (int q = 0; q < KM; ++q) acc[1 + q] += ld_rc(awr, (int64_t)q * a.ld + g) * z;
         }
     }
     if (!a.part) return;
@@ -502,25 +525,38 @@ __global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
     __shared__ double lds[16 * 256];
     __shared__ double tv[KM + 1];
     __shared__ double mu[RMAX];
+    __shared__ double wawi[KM > 0 ? KM * KM : 1];
     Ctl *c = a.ctl;
     if (a.gated && c->done) return;
     const int k = c->k, j = c->j;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double z0 = 0.0, p0 = 0.0, w0[KM > 0 ? KM : 1];
     {
         double acc[KM + 1];
 #pragma unroll
         for (int q = 0; q <= KM; ++q) acc[q] = 0.0;
+        const __amdgpu_buffer_rsrc_t zr = vec_rsrc(a.zpart, (int64_t)(k + 1) * a.zpart_n);
         for (int b = threadIdx.x; b < a.zpart_n; b += blockDim.x) {
 #pragma unroll
-            for (int q = 0; q <= KM; ++q)
-                if (q <= k) acc[q] += a.zpart[(int64_t)q * a.zpart_n + b];
+            for (int q = 0; q <= KM; ++q) acc[q] += ld_rc(zr, (int64_t)q * a.zpart_n + b);
         }
+        // the operands of this thread's first node do not depend on beta and
+        // mu: their loads overlap the reductions (columns q >= k read as zero
+        // through the range check, so every load is unconditional)
+        if (!a.hist_only && g0 < a.n) {
+            z0 = a.z[g0];
+            p0 = a.p[g0];
+            const __amdgpu_buffer_rsrc_t wr = vec_rsrc(a.W, (int64_t)k * a.ld);
+#pragma unroll
+            for (int q = 0; q < KM; ++q) w0[q] = ld_rc(wr, (int64_t)q * a.ld + g0);
+        }
+        for (int e = threadIdx.x; e < k * k; e += blockDim.x) wawi[e] = a.WAWinv[e];
         block_sum_cols<KM + 1>(acc, k + 1, lds, tv);
     }
-    for (int e = threadIdx.x; e < k * k; e += blockDim.x) lds[e] = a.WAWinv[e];
-    __syncthreads();
+    // (block_sum_cols ends with a barrier: wawi is complete)
     if (threadIdx.x < k) {
         double s = 0.0;
-        for (int q = 0; q < k; ++q) s += lds[threadIdx.x * k + q] * tv[1 + q];
+        for (int q = 0; q < k; ++q) s += wawi[threadIdx.x * k + q] * tv[1 + q];
         mu[threadIdx.x] = s;
     }
     __syncthreads();
@@ -538,7 +574,15 @@ __global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
     if (a.hist_only || bad) return;
     const bool rec = a.P && c->record && j < a.cap;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
+    if (g0 < a.n) {
+        double p = z0 + beta * p0;
+#pragma unroll
+        for (int q = 0; q < KM; ++q)
+            if (q < k) p -= w0[q] * mu[q];
+        a.p[g0] = p;
+        if (rec) a.P[(int64_t)j * a.ld + g0] = p;
+    }
+    for (int64_t g = g0 + stride; g < a.n; g += stride) {
         double p = a.z[g] + beta * a.p[g];
         for (int q = 0; q < k; ++q) p -= a.W[(int64_t)q * a.ld + g] * mu[q];
         a.p[g] = p;
@@ -565,9 +609,9 @@ __global__ void __launch_bounds__(256) k_resid(ResidArgs a) {
         const double r = a.b ? a.b[g] - q : q;
         a.out[g] = r;
         acc[0] += r * r;
+        const __amdgpu_buffer_rsrc_t wr = vec_rsrc(a.W, (int64_t)k * a.ld);
 #pragma unroll
-        for (int q2 = 0; q2 < KM; ++q2)
-            if (q2 < k) acc[1 + q2] += a.W[(int64_t)q2 * a.ld + g] * r;
+        for (int q2 = 0; q2 < KM; ++q2) acc[1 + q2] += ld_rc(wr, (int64_t)q2 * a.ld + g) * r;
     }
     block_sum_cols<KM + 1>(acc, k + 1, lds, res);
     if (threadIdx.x <= k) a.part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = res[threadIdx.x];
@@ -586,10 +630,10 @@ __global__ void __launch_bounds__(256) k_defl_init(DeflArgs a) {
         double acc[KM + 1];
 #pragma unroll
         for (int q = 0; q <= KM; ++q) acc[q] = 0.0;
+        const __amdgpu_buffer_rsrc_t wr = vec_rsrc(a.wpart, (int64_t)(k + 1) * a.wpart_n);
         for (int b = threadIdx.x; b < a.wpart_n; b += blockDim.x) {
 #pragma unroll
-            for (int q = 0; q <= KM; ++q)
-                if (q <= k) acc[q] += a.wpart[(int64_t)q * a.wpart_n + b];
+            for (int q = 0; q <= KM; ++q) acc[q] += ld_rc(wr, (int64_t)q * a.wpart_n + b);
         }
         block_sum_cols<KM + 1>(acc, k + 1, lds, tv);
     }
