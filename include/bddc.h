@@ -222,9 +222,11 @@ int bddc_stats(const bddc_ctx *ctx, double *out, int32_t n);
 
 /*
  * bddc_tuning -- configuration of the two batched operator products (host
- * float64[12]): for the Schur operators then the Neumann operators, work
- * items, items per compute unit, waves per block, tiles in flight per wave,
- * fastest tuning launch in microseconds (0 without autotuning), tiles.
+ * float64[14]): for the Schur operators then the Neumann operators, kernel
+ * blocks, blocks per compute unit requested, work split (1: every block
+ * inside one subdomain, 0: equal ranges of the whole tile sequence), waves
+ * per block, tiles in flight per wave, fastest tuning launch in
+ * microseconds (0 without autotuning), tiles.
  */
 int bddc_tuning(const bddc_ctx *ctx, double *out);
 

@@ -38,14 +38,15 @@ struct OpHost {
     OpDev dev{};
     int prec = 64;
     SymvCfg cfg{4, 2};
-    int ipc = 6;                    // work items per compute unit
+    int bpc = 6;                    // product blocks per compute unit
+    bool per_sub = true;            // blocks inside single subdomains (else balanced ranges)
     float tuned_us = 0.f;           // fastest tuning launch
     size_t smem = 0;
     int64_t n_tiles = 0;
     double bytes = 0;               // algorithmic bytes of one product
     bool interior = false;          // interior operators (sizes nI, no gather lists)
     std::vector<int32_t> nchunk;    // per subdomain
-    int32_t *d_items = nullptr, *d_nchunk = nullptr, *d_pb = nullptr, *d_cb = nullptr;
+    int32_t *d_items = nullptr, *d_nchunk = nullptr, *d_pb = nullptr, *d_cb = nullptr, *d_seg = nullptr;
     double *d_ypart = nullptr, *d_cpart = nullptr;
     int64_t ypart_len = 0, cpart_len = 0;
     // flat gather lists: interface node -> y partials, coarse DOF -> c partials
@@ -262,34 +263,61 @@ void flush_timing(bddc_ctx *c) {
 }
 
 // ------------------------------------------------------------- work lists
-// Split every subdomain's packed tile sequence into items of about `target`
-// tiles (at least one item per subdomain) and lay out the partial buffers.
-int build_worklist(bddc_ctx *c, OpHost &op, int64_t target) {
+// Split the work of a batched product over `nblocks` blocks and lay out the
+// partial buffers (one partial vector per segment).  Balanced: the
+// concatenated tile sequence of all subdomains is cut into nblocks equal
+// ranges, each range into segments inside single subdomains (a block may
+// span subdomains).  Per subdomain: every subdomain is cut into about
+// tiles / (total / nblocks) equal segments, one block each (a block never
+// spans subdomains; the block count follows the rounding).
+int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
     const int nsub = c->n_sub;
     std::vector<SymvItem> items;
-    std::vector<int32_t> nch(nsub), pb(nsub), cb(nsub);
+    std::vector<int32_t> nch(nsub, 0), pb(nsub), cb(nsub), seg_ptr(nblocks + 1, 0);
     int64_t ylen = 0, clen = 0;
     const std::vector<int32_t> &sizes = op.interior ? c->h_nI : c->h_nB;
-    for (int i = 0; i < nsub; ++i) {
-        const int nci = op.dev.nc ? c->h_nc[i] : 0;
-        const int64_t nt = ntiles_of(sizes[i], nci);
-        int C = (int)std::max<int64_t>(1, (nt + target / 2) / std::max<int64_t>(target, 1));
-        C = (int)std::min<int64_t>(C, nt);
-        nch[i] = C;
-        pb[i] = (int32_t)ylen;
-        cb[i] = (int32_t)clen;
-        ylen += (int64_t)C * sizes[i];
-        clen += (int64_t)C * nci;
-        for (int q = 0; q < C; ++q)
-            items.push_back(SymvItem{i, (int32_t)(nt * q / C), (int32_t)(nt * (q + 1) / C), q});
+    std::vector<int64_t> start(nsub + 1, 0);
+    for (int i = 0; i < nsub; ++i) start[i + 1] = start[i] + ntiles_of(sizes[i], op.dev.nc ? c->h_nc[i] : 0);
+    const int64_t total = start[nsub];
+    if (per_sub) {
+        const int64_t target = std::max<int64_t>(1, (total + nblocks - 1) / nblocks);
+        for (int k = 0; k < nsub; ++k) {
+            const int64_t nt = start[k + 1] - start[k];
+            if (nt == 0) continue;
+            const int C = (int)std::min<int64_t>(nt, std::max<int64_t>(1, (nt + target / 2) / target));
+            for (int q = 0; q < C; ++q)
+                items.push_back(SymvItem{k, (int32_t)(nt * q / C), (int32_t)(nt * (q + 1) / C), nch[k]++});
+        }
+        nblocks = (int)items.size();
+        seg_ptr.assign(nblocks + 1, 0);
+        for (int b = 0; b <= nblocks; ++b) seg_ptr[b] = b;
+    } else {
+        int i = 0;
+        for (int b = 0; b < nblocks; ++b) {
+            const int64_t g0 = total * b / nblocks, g1 = total * (b + 1) / nblocks;
+            seg_ptr[b] = (int32_t)items.size();
+            while (i < nsub && start[i + 1] <= g0) ++i;
+            for (int k = i; k < nsub && start[k] < g1; ++k) {
+                const int64_t t0 = std::max(g0, start[k]) - start[k], t1 = std::min(g1, start[k + 1]) - start[k];
+                if (t1 > t0) items.push_back(SymvItem{k, (int32_t)t0, (int32_t)t1, nch[k]++});
+            }
+        }
+        seg_ptr[nblocks] = (int32_t)items.size();
+    }
+    for (int k = 0; k < nsub; ++k) {
+        const int nci = op.dev.nc ? c->h_nc[k] : 0;
+        pb[k] = (int32_t)ylen;
+        cb[k] = (int32_t)clen;
+        ylen += (int64_t)nch[k] * sizes[k];
+        clen += (int64_t)nch[k] * nci;
     }
     if (ylen > INT32_MAX || clen > INT32_MAX) return fail(BDDC_EINVAL, "operator partial buffers exceed int32 indexing");
-    dfree(c, op.d_items); dfree(c, op.d_nchunk); dfree(c, op.d_pb); dfree(c, op.d_cb);
-    std::vector<int32_t> raw(items.size() * 4);
+    dfree(c, op.d_items); dfree(c, op.d_nchunk); dfree(c, op.d_pb); dfree(c, op.d_cb); dfree(c, op.d_seg);
+    std::vector<int32_t> raw(std::max<size_t>(1, items.size()) * 4, 0);
     std::memcpy(raw.data(), items.data(), items.size() * sizeof(SymvItem));
     int rc;
     if ((rc = dupload(c, &op.d_items, raw)) || (rc = dupload(c, &op.d_nchunk, nch)) || (rc = dupload(c, &op.d_pb, pb)) ||
-        (rc = dupload(c, &op.d_cb, cb)))
+        (rc = dupload(c, &op.d_cb, cb)) || (rc = dupload(c, &op.d_seg, seg_ptr)))
         return rc;
     if (ylen > op.ypart_len) {
         dfree(c, op.d_ypart);
@@ -304,6 +332,8 @@ int build_worklist(bddc_ctx *c, OpHost &op, int64_t target) {
     op.nchunk = nch;
     op.dev.items = reinterpret_cast<const SymvItem *>(op.d_items);
     op.dev.n_items = (int)items.size();
+    op.dev.seg_ptr = op.d_seg;
+    op.dev.n_blocks = total > 0 ? nblocks : 0;
     op.dev.nchunk = op.d_nchunk;
     op.dev.pb = op.d_pb;
     op.dev.cb = op.d_cb;
@@ -485,7 +515,7 @@ void run_update(bddc_ctx *c) {
     a.q = gather_of(c->opS, false);
     a.p = c->d_p; a.x = c->d_x; a.r = c->d_r;
     a.AP = c->d_AP; a.ld = c->ld; a.cap = c->save_cap;
-    a.dot = c->d_dotS; a.dot_n = c->opS.dev.n_items;
+    a.dot = c->d_dotS; a.dot_n = c->opS.dev.n_blocks;
     a.rr_part = c->d_rr;
     a.ctl = c->d_ctl;
     a.d_hist = c->d_dhist; a.a_hist = c->d_ahist; a.rho_hist = c->d_rhohist; a.hist_cap = c->hist_cap;
@@ -935,11 +965,10 @@ const char *bddc_last_error(void) { return g_err.c_str(); }
 
 namespace {
 
-// Work-list granularity: about `items_per_cu` items per compute unit, each
-// at least 32 tiles.
-int64_t item_target(const bddc_ctx *c, int64_t total_tiles, int items_per_cu) {
-    const int64_t want = (int64_t)c->n_cu * items_per_cu;
-    return std::max<int64_t>(32, (total_tiles + want - 1) / want);
+// Product blocks for `per_cu` blocks per compute unit, at most one per 16
+// tiles.
+int product_blocks(const bddc_ctx *c, int64_t total_tiles, int per_cu) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * per_cu, (total_tiles + 15) / 16));
 }
 
 int setup_operators(bddc_ctx *c) {
@@ -969,7 +998,7 @@ int setup_operators(bddc_ctx *c) {
         op.bytes = bytes;
         op.cfg = SymvCfg{4, 2};
         op.smem = symv_smem(op.prec, op.cfg.nw, c->max_nt, isN ? c->max_ntc : 0);
-        int rc = build_worklist(c, op, item_target(c, op.n_tiles, 6));
+        int rc = build_worklist(c, op, product_blocks(c, op.n_tiles, op.bpc), op.per_sub);
         if (rc) return rc;
     }
     const size_t need4 = std::max(symv_smem(64, 4, c->max_nt, 0), symv_smem(c->prec, 4, c->max_nt, c->max_ntc));
@@ -1065,7 +1094,7 @@ int setup_interior(bddc_ctx *c, const std::vector<int64_t> &k_off) {
                                 symv_smem(c->prec, nwmax, c->max_nt, c->max_ntc));
     if (set_symv_smem_limit(lim)) return fail(BDDC_EHIP, "hipFuncSetAttribute (dynamic LDS) failed");
     HIPCHK(hipMemsetAsync(c->d_tmpN, 0, (size_t)c->n_nodes * sizeof(double), c->stream));
-    return build_worklist(c, op, item_target(c, op.n_tiles, 6));
+    return build_worklist(c, op, product_blocks(c, op.n_tiles, op.bpc), op.per_sub);
 }
 
 // Tile-level autotuning of the two batched products on the operators just
@@ -1076,18 +1105,21 @@ int tune_operators(bddc_ctx *c) {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     int rc = 0;
-    const int ipcs[6] = {2, 3, 4, 6, 8, 16};
+    const int bpcs[7] = {1, 2, 3, 4, 5, 6, 8};
     OpHost *ops[3] = {&c->opS, &c->opN, &c->opI};
     for (int w = 0; w < 3 && rc == 0; ++w) {
         OpHost &op = *ops[w];
-        if (op.dev.n_items == 0) continue;
+        if (op.dev.n_blocks == 0) continue;
         const int ntc = op.dev.nc ? c->max_ntc : 0;
         const int mnt = op.interior ? c->max_ntI : c->max_nt;
         float best = 1e30f;
-        int best_ipc = 6;
+        int best_bpc = op.bpc;
+        bool best_ps = op.per_sub;
         SymvCfg best_cfg{4, 2};
-        for (int ipc : ipcs) {
-            if ((rc = build_worklist(c, op, item_target(c, op.n_tiles, ipc)))) break;
+        for (int trial = 0; trial < 14 && rc == 0; ++trial) {
+            const bool ps = trial >= 7;
+            const int bpc = bpcs[trial % 7];
+            if ((rc = build_worklist(c, op, product_blocks(c, op.n_tiles, bpc), ps))) break;
             for (int nw : {4, 8}) {
                 if (nw == 8 && !c->allow8) continue;
                 for (int u : {2, 4}) {
@@ -1103,13 +1135,14 @@ int tune_operators(bddc_ctx *c) {
                     HIPCHK(hipEventSynchronize(e1));
                     float ms = 0.f;
                     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                    if (ms < best) { best = ms; best_ipc = ipc; best_cfg = cfg; }
+                    if (ms < best) { best = ms; best_bpc = bpc; best_ps = ps; best_cfg = cfg; }
                 }
             }
         }
-        if (rc == 0) rc = build_worklist(c, op, item_target(c, op.n_tiles, best_ipc));
+        if (rc == 0) rc = build_worklist(c, op, product_blocks(c, op.n_tiles, best_bpc), best_ps);
         op.cfg = best_cfg;
-        op.ipc = best_ipc;
+        op.bpc = best_bpc;
+        op.per_sub = best_ps;
         op.smem = symv_smem(op.prec, best_cfg.nw, mnt, ntc);
         op.tuned_us = best * 1e3f / 4;
     }
@@ -1666,7 +1699,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         }
     }
     if (c->opts.autotune && (rc = tune_operators(c))) return rc;
-    if ((rc = dalloc(c, &c->d_dotS, (size_t)c->opS.dev.n_items))) return rc;
+    if ((rc = dalloc(c, &c->d_dotS, (size_t)std::max(1, c->opS.dev.n_blocks)))) return rc;
     HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     for (auto &e : c->gev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // element data for the adjoint gradient
@@ -1872,12 +1905,14 @@ int bddc_tuning(const bddc_ctx *c, double *out) {
     if (!c || !out) return fail(BDDC_EINVAL, "null argument");
     const OpHost *ops[2] = {&c->opS, &c->opN};
     for (int w = 0; w < 2; ++w) {
-        out[6 * w + 0] = ops[w]->dev.n_items;
-        out[6 * w + 1] = ops[w]->ipc;
-        out[6 * w + 2] = ops[w]->cfg.nw;
-        out[6 * w + 3] = ops[w]->cfg.unroll;
-        out[6 * w + 4] = ops[w]->tuned_us;
-        out[6 * w + 5] = (double)ops[w]->n_tiles;
+        double *o = out + 7 * w;
+        o[0] = ops[w]->dev.n_blocks;
+        o[1] = ops[w]->bpc;
+        o[2] = ops[w]->per_sub ? 1.0 : 0.0;
+        o[3] = ops[w]->cfg.nw;
+        o[4] = ops[w]->cfg.unroll;
+        o[5] = ops[w]->tuned_us;
+        o[6] = (double)ops[w]->n_tiles;
     }
     return 0;
 }

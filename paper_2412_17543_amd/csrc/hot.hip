@@ -234,6 +234,15 @@ __device__ bool stop_test(const SymvArgs &a) {
     return s_stop != 0;
 }
 
+// ctl->done read once per block (a block of the kernel that sets it may be
+// running meanwhile): every thread gets the same answer.
+__device__ bool block_done(const Ctl *c) {
+    __shared__ int s_done;
+    if (threadIdx.x == 0) s_done = c->done;
+    __syncthreads();
+    return s_done != 0;
+}
+
 // y_r = sum_{q < ncol} M[q * ldm + r] x[q] for r in [r0, r1) (M read column
 // by column, i.e. the transposed access of a row-major symmetric matrix, so
 // consecutive lanes read consecutive addresses).  The NW waves of the block
@@ -265,143 +274,153 @@ __device__ __forceinline__ void cm_matvec(const double *M, int64_t ldm, int r0, 
 
 }  // namespace
 
+// registers for at least 6 waves per SIMD (4 with four float64 tiles in flight)
+template <typename T, int U>
+constexpr int symv_waves_per_simd() { return (sizeof(T) == 8 && U == 4) ? 4 : 6; }
+
 template <typename T, int NW, int U>
-__global__ void __launch_bounds__(NW * 64) k_symv(SymvArgs a) {
+__global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv(SymvArgs a) {
     using ACC = typename Acc<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[16];
-    if (a.gated && a.ctl->done) return;
+    if (a.gated && block_done(a.ctl)) return;
     if (a.test && stop_test(a)) return;
-    const SymvItem it = a.op.items[blockIdx.x];
-    const int sub = it.sub;
-    const int n = a.op.nB[sub];
-    const int nt = (n + TILE - 1) / TILE;
-    const int ncs = a.op.nc ? a.op.nc[sub] : 0;
-    const int ntc = (ncs + TILE - 1) / TILE;
-    const int npad = nt * TILE;
-    ACC *xs = reinterpret_cast<ACC *>(smem_raw);
-    ACC *yw = xs + npad;
-    ACC *cw = yw + NW * npad;
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g4 = 4 * (l >> 4), cl = l & 15;
-    const T *tb = reinterpret_cast<const T *>(a.op.tiles) + a.op.t_off[sub];
-    const int span = it.t1 - it.t0;
-    const int wu = __builtin_amdgcn_readfirstlane(w);     // wave-uniform control flow
-    const int w0 = it.t0 + (int)((int64_t)span * wu / NW);
-    const int w1 = it.t0 + (int)((int64_t)span * (wu + 1) / NW);
-    // Tiles past w1 read as zero without a memory access (resource over
-    // tiles [t, w1) for the stage starting at tile t), so the loads of the
-    // next U tiles are issued unconditionally while the current U are used;
-    // two register sets in turn, so that no copy waits for a load.  The first
-    // stage is in flight while the block gathers its input.
-    auto stage = [&](int t) {
-        return tile_rsrc(tb + (int64_t)t * 256, max(w1 - t, 0) * 256 * (int)sizeof(T));
-    };
-    const int32_t *gb = a.op.gB + a.op.b_off[sub];
-    const int g0 = gb[min(tid, n - 1)];                   // first gather index, ahead of the tiles
-    asm volatile("" ::: "memory");                        // (keeps that load first)
-    Frag<T> fa[U], fb[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) fa[u].load(stage(w0), u, l);
+    // the block's segments (consecutive pieces of the global tile sequence,
+    // each inside one subdomain), one after the other
+    double dot = 0.0;
+    const int seg1 = a.op.seg_ptr[blockIdx.x + 1];
+    for (int seg = a.op.seg_ptr[blockIdx.x]; seg < seg1; ++seg) {
+        const SymvItem it = a.op.items[seg];
+        const int sub = it.sub;
+        const int n = a.op.nB[sub];
+        const int nt = (n + TILE - 1) / TILE;
+        const int ncs = a.op.nc ? a.op.nc[sub] : 0;
+        const int ntc = (ncs + TILE - 1) / TILE;
+        const int npad = nt * TILE;
+        ACC *xs = reinterpret_cast<ACC *>(smem_raw);
+        ACC *yw = xs + npad;
+        ACC *cw = yw + NW * npad;
+        const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g4 = 4 * (l >> 4), cl = l & 15;
+        const T *tb = reinterpret_cast<const T *>(a.op.tiles) + a.op.t_off[sub];
+        const int span = it.t1 - it.t0;
+        const int wu = __builtin_amdgcn_readfirstlane(w);     // wave-uniform control flow
+        const int w0 = it.t0 + (int)((int64_t)span * wu / NW);
+        const int w1 = it.t0 + (int)((int64_t)span * (wu + 1) / NW);
+        // Tiles past w1 read as zero without a memory access (resource over
+        // tiles [t, w1) for the stage starting at tile t), so the loads of the
+        // next U tiles are issued unconditionally while the current U are used;
+        // two register sets in turn, so that no copy waits for a load.  The first
+        // stage is in flight while the block gathers its input.
+        auto stage = [&](int t) {
+            return tile_rsrc(tb + (int64_t)t * 256, max(w1 - t, 0) * 256 * (int)sizeof(T));
+        };
+        const int32_t *gb = a.op.gB + a.op.b_off[sub];
+        const int g0 = gb[min(tid, n - 1)];                   // first gather index, ahead of the tiles
+        asm volatile("" ::: "memory");                        // (keeps that load first)
+        Frag<T> fa[U], fb[U];
+    #pragma unroll
+        for (int u = 0; u < U; ++u) fa[u].load(stage(w0), u, l);
 
-    for (int k = tid; k < npad; k += NW * 64) xs[k] = k < n ? (ACC)a.x[k == tid ? g0 : gb[k]] : (ACC)0;
-    for (int k = tid; k < NW * npad; k += NW * 64) yw[k] = (ACC)0;
-    for (int k = tid; k < NW * ntc * TILE; k += NW * 64) cw[k] = (ACC)0;
-    __syncthreads();
+        for (int k = tid; k < npad; k += NW * 64) xs[k] = k < n ? (ACC)a.x[k == tid ? g0 : gb[k]] : (ACC)0;
+        for (int k = tid; k < NW * npad; k += NW * 64) yw[k] = (ACC)0;
+        for (int k = tid; k < NW * ntc * TILE; k += NW * 64) cw[k] = (ACC)0;
+        __syncthreads();
 
-    ACC *myy = yw + wu * npad;
-    ACC *myc = cw + wu * ntc * TILE;
-    if (w0 >= w1) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) fa[u].settle();
-    } else {
-        int I = 0, rs = 0;
-        while (rs + (nt - I + ntc) <= w0) { rs += nt - I + ntc; ++I; }
-        int J = I + (w0 - rs);
-        ACC xi[4], ra[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) { xi[q] = xs[I * TILE + g4 + q]; ra[q] = (ACC)0; }
-        // Every fragment is used arithmetically on every path (a tile past
-        // w1 reads as zero and only its bookkeeping is skipped), so no path
-        // leaves a load outstanding when its registers are loaded again.
-        auto use = [&](const Frag<T> (&f)[U], int t) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool live = t + u < w1;
-                ACC v[4];
-                f[u].get(v);
-                // no direct part in coarse columns, nor past the range
-                const ACC xj = (live && J < nt) ? xs[J * TILE + cl] : (ACC)0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) ra[q] += v[q] * xj;
-                const ACC s = col_sum4(v[0] * xi[0] + v[1] * xi[1] + v[2] * xi[2] + v[3] * xi[3]);
-                if (!live) continue;
-                if (J != I && l < 16) {
-                    ACC *dst = (J < nt) ? (myy + J * TILE) : (myc + (J - nt) * TILE);
-                    dst[cl] += s;
-                }
-                if (++J == nt + ntc) {
-                    const ACC m = row_sum4(ra, cl);
-                    if ((cl & 3) == 0) myy[I * TILE + g4 + (cl >> 2)] += m;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) ra[q] = (ACC)0;
-                    ++I;
-                    J = I;
-                    if (I < nt) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) xi[q] = xs[I * TILE + g4 + q];
+        ACC *myy = yw + wu * npad;
+        ACC *myc = cw + wu * ntc * TILE;
+        if (w0 >= w1) {
+    #pragma unroll
+            for (int u = 0; u < U; ++u) fa[u].settle();
+        } else {
+            int I = 0, rs = 0;
+            while (rs + (nt - I + ntc) <= w0) { rs += nt - I + ntc; ++I; }
+            int J = I + (w0 - rs);
+            ACC xi[4], ra[4];
+    #pragma unroll
+            for (int q = 0; q < 4; ++q) { xi[q] = xs[I * TILE + g4 + q]; ra[q] = (ACC)0; }
+            // Every fragment is used arithmetically on every path (a tile past
+            // w1 reads as zero and only its bookkeeping is skipped), so no path
+            // leaves a load outstanding when its registers are loaded again.
+            auto use = [&](const Frag<T> (&f)[U], int t) {
+    #pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool live = t + u < w1;
+                    ACC v[4];
+                    f[u].get(v);
+                    // no direct part in coarse columns, nor past the range
+                    const ACC xj = (live && J < nt) ? xs[J * TILE + cl] : (ACC)0;
+    #pragma unroll
+                    for (int q = 0; q < 4; ++q) ra[q] += v[q] * xj;
+                    const ACC s = col_sum4(v[0] * xi[0] + v[1] * xi[1] + v[2] * xi[2] + v[3] * xi[3]);
+                    if (!live) continue;
+                    if (J != I && l < 16) {
+                        ACC *dst = (J < nt) ? (myy + J * TILE) : (myc + (J - nt) * TILE);
+                        dst[cl] += s;
+                    }
+                    if (++J == nt + ntc) {
+                        const ACC m = row_sum4(ra, cl);
+                        if ((cl & 3) == 0) myy[I * TILE + g4 + (cl >> 2)] += m;
+    #pragma unroll
+                        for (int q = 0; q < 4; ++q) ra[q] = (ACC)0;
+                        ++I;
+                        J = I;
+                        if (I < nt) {
+    #pragma unroll
+                            for (int q = 0; q < 4; ++q) xi[q] = xs[I * TILE + g4 + q];
+                        }
                     }
                 }
+            };
+            for (int t = w0;;) {
+    #pragma unroll
+                for (int u = 0; u < U; ++u) fb[u].load(stage(t + U), u, l);
+                use(fa, t);
+                t += U;
+                if (t >= w1) {
+    #pragma unroll
+                    for (int u = 0; u < U; ++u) fb[u].settle();
+                    break;
+                }
+    #pragma unroll
+                for (int u = 0; u < U; ++u) fa[u].load(stage(t + U), u, l);
+                use(fb, t);
+                t += U;
+                if (t >= w1) {
+    #pragma unroll
+                    for (int u = 0; u < U; ++u) fa[u].settle();
+                    break;
+                }
             }
-        };
-        for (int t = w0;;) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) fb[u].load(stage(t + U), u, l);
-            use(fa, t);
-            t += U;
-            if (t >= w1) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) fb[u].settle();
-                break;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) fa[u].load(stage(t + U), u, l);
-            use(fb, t);
-            t += U;
-            if (t >= w1) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) fa[u].settle();
-                break;
+            if (J != I) {   // flush a partly processed tile row
+                const ACC m = row_sum4(ra, cl);
+                if ((cl & 3) == 0) myy[I * TILE + g4 + (cl >> 2)] += m;
             }
         }
-        if (J != I) {   // flush a partly processed tile row
-            const ACC m = row_sum4(ra, cl);
-            if ((cl & 3) == 0) myy[I * TILE + g4 + (cl >> 2)] += m;
-        }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    double dot = 0.0;
-    double *yp = a.ypart + a.op.pb[sub] + (int64_t)it.c * n;
-    for (int k = tid; k < n; k += NW * 64) {
-        ACC s = (ACC)0;
-#pragma unroll
-        for (int q = 0; q < NW; ++q) s += yw[q * npad + k];
-        const double y = (double)s;
-        yp[k] = y;
-        dot += (double)xs[k] * y;
-    }
-    if (ncs) {
-        double *cp = a.cpart + a.op.cb[sub] + (int64_t)it.c * ncs;
-        for (int k = tid; k < ncs; k += NW * 64) {
+        double *yp = a.ypart + a.op.pb[sub] + (int64_t)it.c * n;
+        for (int k = tid; k < n; k += NW * 64) {
             ACC s = (ACC)0;
-#pragma unroll
-            for (int q = 0; q < NW; ++q) s += cw[q * ntc * TILE + k];
-            cp[k] = (double)s;
+    #pragma unroll
+            for (int q = 0; q < NW; ++q) s += yw[q * npad + k];
+            const double y = (double)s;
+            yp[k] = y;
+            dot += (double)xs[k] * y;
         }
+        if (ncs) {
+            double *cp = a.cpart + a.op.cb[sub] + (int64_t)it.c * ncs;
+            for (int k = tid; k < ncs; k += NW * 64) {
+                ACC s = (ACC)0;
+    #pragma unroll
+                for (int q = 0; q < NW; ++q) s += cw[q * ntc * TILE + k];
+                cp[k] = (double)s;
+            }
+        }
+        __syncthreads();   // LDS is reused by the next segment
     }
     if (a.dot) {
         dot = block_sum(dot, red);
-        if (tid == 0) a.dot[blockIdx.x] = dot;
+        if (threadIdx.x == 0) a.dot[blockIdx.x] = dot;
     }
 }
 
@@ -861,7 +880,7 @@ int set_symv_smem_limit(size_t bytes) {
 
 template <typename T>
 static void launch_symv_t(const SymvArgs &a, SymvCfg cfg, size_t smem, hipStream_t s) {
-    const dim3 grid(a.op.n_items);
+    const dim3 grid(a.op.n_blocks);
     if (cfg.nw == 8) {
         if (cfg.unroll == 4) hipLaunchKernelGGL((k_symv<T, 8, 4>), grid, dim3(512), smem, s, a);
         else hipLaunchKernelGGL((k_symv<T, 8, 2>), grid, dim3(512), smem, s, a);
@@ -872,7 +891,7 @@ static void launch_symv_t(const SymvArgs &a, SymvCfg cfg, size_t smem, hipStream
 }
 
 void launch_symv(const SymvArgs &a, int prec, SymvCfg cfg, size_t smem, hipStream_t s) {
-    if (a.op.n_items <= 0) return;
+    if (a.op.n_blocks <= 0) return;
     if (prec == 64) launch_symv_t<double>(a, cfg, smem, s);
     else if (prec == 32) launch_symv_t<float>(a, cfg, smem, s);
     else launch_symv_t<uint16_t>(a, cfg, smem, s);

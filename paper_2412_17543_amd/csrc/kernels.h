@@ -15,24 +15,30 @@ struct AsmDesc {
 };
 
 // ======================================================== operator products
-// One work item of a batched symmetric product: tiles [t0, t1) of the packed
-// tile sequence of subdomain `sub`; `c` numbers the items of that subdomain.
+// One segment of a batched symmetric product: tiles [t0, t1) of the packed
+// tile sequence of subdomain `sub`; `c` numbers the segments of that
+// subdomain.
 struct SymvItem {
     int32_t sub, t0, t1, c;
 };
 
 // A batch of packed symmetric operators.  Tile row I of subdomain i holds the
 // tiles (I, I..nt-1) of the upper triangle and, when `nc` is set, ntc extra
-// tiles of the coarse basis rows (I, nt..nt+ntc-1).  Item c of subdomain i
-// writes its partial products to ypart[pb[i] + c * nB[i] + k] and, with a
-// coarse basis, cpart[cb[i] + c * nc[i] + q].
+// tiles of the coarse basis rows (I, nt..nt+ntc-1).  The concatenated tile
+// sequence of all subdomains is cut into n_blocks equal ranges, one per
+// block; block b processes segments [seg_ptr[b], seg_ptr[b+1]), the pieces of
+// its range inside single subdomains.  Segment c of subdomain i writes its
+// partial products to ypart[pb[i] + c * nB[i] + k] and, with a coarse basis,
+// cpart[cb[i] + c * nc[i] + q].
 struct OpDev {
     const void *tiles;
     const int64_t *t_off;
     const int32_t *nB, *b_off, *gB;
     const int32_t *nc;              // nullable
-    const SymvItem *items;
+    const SymvItem *items;          // segments
     int n_items;
+    const int32_t *seg_ptr;         // n_blocks + 1
+    int n_blocks;
     const int32_t *nchunk, *pb, *cb;
 };
 

@@ -108,14 +108,14 @@ class Solver:
         check(self.lib.bddc_ritz_values(self.ctx, buf, 64, ctypes.byref(cnt)))
         return np.frombuffer(buf, dtype=np.float64)[: cnt.value].copy()
 
-    TUNING_KEYS = ("items", "items_per_cu", "waves", "unroll", "best_us", "tiles")
+    TUNING_KEYS = ("blocks", "blocks_per_cu", "per_subdomain", "waves", "unroll", "best_us", "tiles")
 
     def tuning(self) -> dict:
         """Configuration chosen for the Schur and Neumann products."""
-        a = (ctypes.c_double * 12)()
+        a = (ctypes.c_double * 14)()
         check(self.lib.bddc_tuning(self.ctx, a))
         v = list(a)
-        return {"schur": dict(zip(self.TUNING_KEYS, v[:6])), "neumann": dict(zip(self.TUNING_KEYS, v[6:]))}
+        return {"schur": dict(zip(self.TUNING_KEYS, v[:7])), "neumann": dict(zip(self.TUNING_KEYS, v[7:]))}
 
     def enable_timing(self, on=True, classes=None):
         """Time kernel classes with HIP events (classes: iterable of STAT_KEYS)."""
