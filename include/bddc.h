@@ -106,6 +106,13 @@ typedef struct {
                                 by column through the chain, into a dense nC x nC
                                 matrix applied as one product (nC <= 8192, else
                                 EINVAL); 0 (default): 2 when nC <= 4096, else 1     */
+    int32_t product_cfg[8];  /* optional fixed configuration of the two batched
+                                products, Schur then Neumann: blocks per compute
+                                unit, work split (1: blocks inside one subdomain,
+                                0: equal ranges of the tile sequence), waves per
+                                block (4 or 8), tiles in flight per wave (2 or 4).
+                                A product whose first entry is 0 is autotuned (or
+                                takes the default without autotuning).         */
     int32_t reserved[2];
 } bddc_opts;
 
@@ -229,6 +236,17 @@ int bddc_stats(const bddc_ctx *ctx, double *out, int32_t n);
  * microseconds (0 without autotuning), tiles.
  */
 int bddc_tuning(const bddc_ctx *ctx, double *out);
+
+/*
+ * bddc_time_products -- measurement helper: `reps` back-to-back launches of
+ * the batched Schur product and then of the batched Neumann product (the
+ * configuration the solve uses, input x = the current interface iterate),
+ * timed with HIP events on the context's stream.  out (host float64[4]):
+ * Schur microseconds per launch, Schur algorithmic bytes per launch,
+ * Neumann microseconds per launch, Neumann algorithmic bytes per launch.
+ * Overwrites the products' partial buffers only.  Errors: EINVAL, EHIP.
+ */
+int bddc_time_products(bddc_ctx *ctx, int32_t reps, double *out);
 
 /* Theta (selected harmonic Ritz values, host float64[R]) of the last update. */
 int bddc_ritz_values(const bddc_ctx *ctx, double *theta, int32_t cap, int32_t *count);

@@ -31,7 +31,7 @@ class Opts(ctypes.Structure):
                 ("recycle_R", c_int32), ("recycle_strategy", c_int32), ("ritz_freeze_tol", c_double),
                 ("stop_rule", c_int32), ("init_guess", c_int32), ("max_it", c_int32),
                 ("save_cap", c_int32), ("use_graph", c_int32), ("autotune", c_int32),
-                ("coarse_form", c_int32), ("reserved", c_int32 * 2)]
+                ("coarse_form", c_int32), ("product_cfg", c_int32 * 8), ("reserved", c_int32 * 2)]
 
 
 class BddcError(RuntimeError):
@@ -56,6 +56,7 @@ SIGNATURES = {
     "bddc_stats": (c_int32, [c_void_p, POINTER(c_double), c_int32]),
     "bddc_ritz_values": (c_int32, [c_void_p, POINTER(c_double), c_int32, POINTER(c_int32)]),
     "bddc_tuning": (c_int32, [c_void_p, POINTER(c_double)]),
+    "bddc_time_products": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "bddc_destroy": (None, [c_void_p]),
     "bddc_last_error": (c_char_p, []),
 }

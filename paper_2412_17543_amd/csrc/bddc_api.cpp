@@ -1699,6 +1699,22 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         }
     }
     if (c->opts.autotune && (rc = tune_operators(c))) return rc;
+    {   // pinned configurations
+        OpHost *ops[2] = {&c->opS, &c->opN};
+        for (int w = 0; w < 2; ++w) {
+            const int32_t *pc = c->opts.product_cfg + 4 * w;
+            if (pc[0] <= 0) continue;
+            if ((pc[2] != 4 && pc[2] != 8) || (pc[3] != 2 && pc[3] != 4) || (pc[2] == 8 && !c->allow8))
+                return fail(BDDC_EINVAL, "product_cfg: waves must be 4 or 8 (8 when it fits), tiles in flight 2 or 4");
+            OpHost &op = *ops[w];
+            op.bpc = pc[0];
+            op.per_sub = pc[1] != 0;
+            op.cfg = SymvCfg{pc[2], pc[3]};
+            op.smem = symv_smem(op.prec, op.cfg.nw, c->max_nt, w == 1 ? c->max_ntc : 0);
+            op.tuned_us = 0.f;
+            if ((rc = build_worklist(c, op, product_blocks(c, op.n_tiles, op.bpc), op.per_sub))) return rc;
+        }
+    }
     if ((rc = dalloc(c, &c->d_dotS, (size_t)std::max(1, c->opS.dev.n_blocks)))) return rc;
     HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     for (auto &e : c->gev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -1899,6 +1915,33 @@ int bddc_stats(const bddc_ctx *c, double *out, int32_t n) {
         out[3 * k + 2] = c->t_bytes[k];
     }
     return 0;
+}
+
+int bddc_time_products(bddc_ctx *c, int32_t reps, double *out) {
+    if (!c || !out || reps <= 0) return fail(BDDC_EINVAL, "null argument or reps <= 0");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const OpHost *ops[2] = {&c->opS, &c->opN};
+    int rc = 0;
+    for (int w = 0; w < 2 && rc == 0; ++w) {
+        const OpHost &op = *ops[w];
+        SymvArgs a{};
+        a.op = op.dev; a.x = c->d_x; a.ypart = op.d_ypart; a.cpart = op.d_cpart; a.ctl = c->d_ctl;
+        launch_symv(a, op.prec, op.cfg, op.smem, c->stream);   // warm
+        hipError_t e = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) launch_symv(a, op.prec, op.cfg, op.smem, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) rc = fail(BDDC_EHIP, std::string("timing: ") + hipGetErrorString(e));
+        out[2 * w] = 1e3 * ms / reps;
+        out[2 * w + 1] = op.bytes;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int bddc_tuning(const bddc_ctx *c, double *out) {

@@ -33,7 +33,8 @@ class Solver:
                  node_dirichlet=None, ny=None, nz=None, R=0, strategy="B4", local_prec=64,
                  weights="diag", constraints=("corners", "faces"), stop_rule="rhs",
                  init_guess="prev", max_it=1000, save_cap=256, freeze_tol=1e-5,
-                 use_graph=True, autotune=True, coarse_form="auto", device="cuda", stream=None):
+                 use_graph=True, autotune=True, coarse_form="auto", product_cfg=None, device="cuda",
+                 stream=None):
         lib = _lib.load()
         self.lib = lib
         self.device = torch.device(device)
@@ -78,6 +79,10 @@ class Solver:
         o.use_graph = 1 if use_graph else 0
         o.autotune = 1 if autotune else 0
         o.coarse_form = {"auto": 0, "chain": 1, "explicit": 2}[coarse_form]
+        if product_cfg is not None:
+            assert len(product_cfg) == 8
+            for i, v in enumerate(product_cfg):
+                o.product_cfg[i] = int(v)
         self.opts = o
         torch.cuda.set_device(self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -116,6 +121,13 @@ class Solver:
         check(self.lib.bddc_tuning(self.ctx, a))
         v = list(a)
         return {"schur": dict(zip(self.TUNING_KEYS, v[:7])), "neumann": dict(zip(self.TUNING_KEYS, v[7:]))}
+
+    def time_products(self, reps=20) -> dict:
+        """Back-to-back launches of the Schur and Neumann products timed with
+        HIP events: microseconds and algorithmic bytes per launch."""
+        a = (ctypes.c_double * 4)()
+        check(self.lib.bddc_time_products(self.ctx, reps, a))
+        return {"schur": {"us": a[0], "bytes": a[1]}, "neumann": {"us": a[2], "bytes": a[3]}}
 
     def enable_timing(self, on=True, classes=None):
         """Time kernel classes with HIP events (classes: iterable of STAT_KEYS)."""

@@ -264,3 +264,21 @@ def test_explicit_three_level_operator_matches_subregion_chain(name):
     assert np.all(np.abs(itc - ite) <= 1)
     for k in range(len(F)):
         assert _rel(Ue[k].cpu().numpy(), Uc[k].cpu().numpy()) <= 1e-9
+
+
+def test_pinned_product_configuration():
+    torch = _torch()
+    from paper_2412_17543_amd._lib import BddcError
+    pin = [3, 0, 4, 2, 2, 1, 4, 4]       # Schur: balanced ranges; Neumann: per-subdomain
+    g = _solver("tiny3", R=4, product_cfg=pin)
+    t = g.tuning()
+    assert (t["schur"]["blocks_per_cu"], t["schur"]["per_subdomain"], t["schur"]["waves"], t["schur"]["unroll"]) == (3, 0, 4, 2)
+    assert (t["neumann"]["per_subdomain"], t["neumann"]["waves"], t["neumann"]["unroll"]) == (1, 4, 4)
+    F = workload.rhs_sequence(16, 3)
+    U, its, _ = g.solve_sequence(torch.tensor(F, device="cuda"), 1e-10)
+    uo, ito, _ = _oracle("tiny3", R=4).solve_sequence(F, 1e-10)
+    assert np.all(np.abs(its - ito) <= 1)
+    for k in range(len(F)):
+        assert _rel(U[k].cpu().numpy(), uo[k]) <= 1e-9
+    with pytest.raises(BddcError):
+        _solver("tiny3", product_cfg=[2, 1, 5, 2, 0, 0, 0, 0])
