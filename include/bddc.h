@@ -113,7 +113,9 @@ typedef struct {
                                 block (4 or 8), tiles in flight per wave (2 or 4).
                                 A product whose first entry is 0 is autotuned (or
                                 takes the default without autotuning).         */
-    int32_t reserved[2];
+    int32_t reorth;          /* 1: after every residual update, r -= W (W^T W)^{-1} W^T r
+                                (Alg. 1, optional re-orthogonalisation); 0: off  */
+    int32_t reserved[1];
 } bddc_opts;
 
 /* Fills *o with the defaults: corners+faces, diag weights, float64 local

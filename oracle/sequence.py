@@ -18,12 +18,13 @@ from .substructure import Substructuring
 class OracleSolver:
     def __init__(self, nx, elem_to_sub, coef, elem_keep=None, sub_to_subregion=None,
                  weight_kind="diag", constraints=("corners", "faces"), R=0, strategy="B4",
-                 freeze_tol=1e-5, stop="rhs", init_guess="prev", all_corners=False):
+                 freeze_tol=1e-5, stop="rhs", init_guess="prev", all_corners=False, reorth=False):
         self.ss = Substructuring(nx, elem_to_sub, coef, elem_keep)
         self.M = BDDC(self.ss, weight_kind, constraints, sub_to_subregion, all_corners)
         self.rec = Recycler(R, strategy, freeze_tol)
         self.stop = stop
         self.init_guess = init_guess
+        self.reorth = reorth
         self.x_prev = np.zeros(self.ss.n_gamma)
 
     def reset(self):
@@ -35,7 +36,7 @@ class OracleSolver:
         b = ss.condense(F)
         W = self.rec.basis(ss.n_gamma)
         x0 = self.x_prev if self.init_guess == "prev" else np.zeros(ss.n_gamma)
-        res = dpcg(ss.apply_A, self.M.apply, b, x0, W, rtol, max_it, self.stop)
+        res = dpcg(ss.apply_A, self.M.apply, b, x0, W, rtol, max_it, self.stop, reorth=self.reorth)
         self.x_prev = res["x"]
         if update:
             P = np.column_stack(res["P"]) if res["P"] else np.zeros((ss.n_gamma, 0))

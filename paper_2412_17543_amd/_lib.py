@@ -31,7 +31,8 @@ class Opts(ctypes.Structure):
                 ("recycle_R", c_int32), ("recycle_strategy", c_int32), ("ritz_freeze_tol", c_double),
                 ("stop_rule", c_int32), ("init_guess", c_int32), ("max_it", c_int32),
                 ("save_cap", c_int32), ("use_graph", c_int32), ("autotune", c_int32),
-                ("coarse_form", c_int32), ("product_cfg", c_int32 * 8), ("reserved", c_int32 * 2)]
+                ("coarse_form", c_int32), ("product_cfg", c_int32 * 8),
+                ("reorth", c_int32), ("reserved", c_int32 * 1)]
 
 
 class BddcError(RuntimeError):

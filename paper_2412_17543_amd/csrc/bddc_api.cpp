@@ -131,6 +131,10 @@ struct bddc_ctx {
     int64_t ld = 0;
     double *d_W = nullptr, *d_AW = nullptr, *d_Wn = nullptr, *d_AWn = nullptr, *d_P = nullptr, *d_AP = nullptr;
     double *d_WAWinv = nullptr, *d_Y = nullptr, *d_WAWnew = nullptr, *d_WAWsym = nullptr, *d_invnew = nullptr;
+    // re-orthogonalisation: (W^T W)^{-1} of the basis in use and of the new one,
+    // W^T r partials, a scratch state for the Cholesky of W^T W
+    double *d_WWinv = nullptr, *d_WWnew = nullptr, *d_WWsym = nullptr, *d_WWinvnew = nullptr, *d_rop = nullptr;
+    RecState *d_state2 = nullptr;
     RecState *d_state = nullptr;
     std::vector<double> WAW, GWW, theta;
     bool frozen = false;
@@ -508,6 +512,15 @@ void run_pupd(bddc_ctx *c, bool first, bool hist_only, bool gated) {
     launch_pupd(a, c->kmax, c->vgrid, c->stream);
 }
 
+// Alg. 1, optional re-orthogonalisation of the updated residual.
+void run_reorth(bddc_ctx *c) {
+    TScope ts(c, TK_VEC);
+    ReorthArgs a{};
+    a.n = c->n_gamma; a.r = c->d_r; a.W = c->d_W; a.ld = c->ld; a.WWinv = c->d_WWinv;
+    a.part = c->d_rop; a.rr_part = c->d_rr; a.ctl = c->d_ctl;
+    launch_reorth(a, c->kmax, c->vgrid, c->stream);
+}
+
 void run_update(bddc_ctx *c) {
     TScope ts(c, TK_VEC);
     UpdArgs a{};
@@ -540,6 +553,7 @@ void run_resid(bddc_ctx *c, double *out, bool want_wtr) {
 void enqueue_iteration(bddc_ctx *c) {
     run_schur(c, c->d_p, true, true);                    // line 9: A p_j, p_j^T A p_j
     run_update(c);                                       // lines 9-11
+    if (c->opts.reorth && c->R > 0) run_reorth(c);       // optional line
     run_precond(c, c->d_r, c->d_z, 1, true, true, true); // stopping test, line 13
     run_pupd(c, false, false, true);                     // lines 14-16
 }
@@ -783,10 +797,22 @@ int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol, cons
     CholArgs ch{};
     ch.k = ncol; ch.waw = c->d_WAWnew; ch.waw_sym = c->d_WAWsym; ch.inv = c->d_invnew; ch.state = c->d_state;
     launch_chol_inv(ch, c->stream);
+    if (c->opts.reorth) {   // (W^T W)^{-1} of the new basis
+        GramArgs gw{};
+        gw.n = c->n_gamma; gw.k = ncol; gw.ld = c->ld; gw.X = c->d_Wn; gw.Y = c->d_Wn; gw.part = c->d_gp;
+        launch_gram(gw, nb, c->stream);
+        ReduceArgs rw{};
+        rw.part = c->d_gp; rw.n = nb; rw.ncol = ncol * ncol; rw.out = c->d_WWnew;
+        launch_reduce(rw, c->stream);
+        CholArgs cw{};
+        cw.k = ncol; cw.waw = c->d_WWnew; cw.waw_sym = c->d_WWsym; cw.inv = c->d_WWinvnew; cw.state = c->d_state2;
+        launch_chol_inv(cw, c->stream);
+    }
     CommitArgs cm{};
     cm.n = (int64_t)ncol * c->ld; cm.ncol = ncol;
     cm.Wn = c->d_Wn; cm.AWn = c->d_AWn; cm.inv_new = c->d_invnew;
     cm.W = c->d_W; cm.AW = c->d_AW; cm.inv = c->d_WAWinv; cm.state = c->d_state;
+    if (c->opts.reorth) { cm.ww_new = c->d_WWinvnew; cm.ww = c->d_WWinv; }
     launch_commit(cm, c->stream);
     c->pend.active = true;
     c->pend.k = ncol;
@@ -1660,7 +1686,10 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         (rc = dalloc(c, &c->d_bhist, c->hist_cap)) || (rc = dalloc(c, &c->d_reshist, c->hist_cap)) ||
         (rc = dalloc(c, &c->d_muhist, (size_t)c->hist_cap * RMAX)) || (rc = dalloc(c, &c->d_WAWinv, RMAX * RMAX)) ||
         (rc = dalloc(c, &c->d_WAWnew, RMAX * RMAX)) || (rc = dalloc(c, &c->d_WAWsym, RMAX * RMAX)) ||
-        (rc = dalloc(c, &c->d_invnew, RMAX * RMAX)) || (rc = dalloc(c, &c->d_state, 1)))
+        (rc = dalloc(c, &c->d_invnew, RMAX * RMAX)) || (rc = dalloc(c, &c->d_state, 1)) ||
+        (rc = dalloc(c, &c->d_WWinv, RMAX * RMAX)) || (rc = dalloc(c, &c->d_WWnew, RMAX * RMAX)) ||
+        (rc = dalloc(c, &c->d_WWsym, RMAX * RMAX)) || (rc = dalloc(c, &c->d_WWinvnew, RMAX * RMAX)) ||
+        (rc = dalloc(c, &c->d_rop, (size_t)RMAX * VGRID)) || (rc = dalloc(c, &c->d_state2, 1)))
         return rc;
     HIPCHK(hipMemsetAsync(c->d_x, 0, ng * sizeof(double), s));
     HIPCHK(hipMemsetAsync(c->d_p, 0, ng * sizeof(double), s));

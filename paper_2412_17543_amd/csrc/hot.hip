@@ -681,6 +681,68 @@ __global__ void __launch_bounds__(256) k_defl_init(DeflArgs a) {
 }
 
 // out[c] = sum_b part[c * n + b] (column-major partials), one block per column
+// Re-orthogonalisation (Alg. 1, optional line after the residual update):
+// k_wtr writes per-block W^T r partials; k_reorth sums them in every block
+// (fixed order), gamma = (W^T W)^{-1} W^T r, r -= W gamma and per-block
+// ||r||^2 partials that replace the update's for the stopping test.
+template <int KM>
+__global__ void __launch_bounds__(256) k_wtr(ReorthArgs a) {
+    __shared__ double lds[16 * 256];
+    __shared__ double res[KM > 0 ? KM : 1];
+    if (a.ctl->done) return;
+    const int k = a.ctl->k;
+    if (k == 0) return;
+    double acc[KM > 0 ? KM : 1];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) acc[q] = 0.0;
+    const __amdgpu_buffer_rsrc_t wr = vec_rsrc(a.W, (int64_t)k * a.ld);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
+        const double r = a.r[g];
+#pragma unroll
+        for (int q = 0; q < KM; ++q) acc[q] += ld_rc(wr, (int64_t)q * a.ld + g) * r;
+    }
+    block_sum_cols<KM>(acc, k, lds, res);
+    if (threadIdx.x < k) a.part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = res[threadIdx.x];
+}
+
+template <int KM>
+__global__ void __launch_bounds__(256) k_reorth(ReorthArgs a) {
+    __shared__ double lds[16 * 256];
+    __shared__ double tv[KM > 0 ? KM : 1], gam[KM > 0 ? KM : 1];
+    __shared__ double red[16];
+    if (a.ctl->done) return;
+    const int k = a.ctl->k;
+    if (k == 0) return;
+    {
+        double acc[KM > 0 ? KM : 1];
+#pragma unroll
+        for (int q = 0; q < KM; ++q) acc[q] = 0.0;
+        const __amdgpu_buffer_rsrc_t pr = vec_rsrc(a.part, (int64_t)k * gridDim.x);
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+#pragma unroll
+            for (int q = 0; q < KM; ++q) acc[q] += ld_rc(pr, (int64_t)q * gridDim.x + b);
+        }
+        block_sum_cols<KM>(acc, k, lds, tv);
+    }
+    if (threadIdx.x < k) {
+        double s = 0.0;
+        for (int q = 0; q < k; ++q) s += a.WWinv[threadIdx.x * k + q] * tv[q];
+        gam[threadIdx.x] = s;
+    }
+    __syncthreads();
+    double rr = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
+        double r = a.r[g];
+        for (int q = 0; q < k; ++q) r -= a.W[(int64_t)q * a.ld + g] * gam[q];
+        a.r[g] = r;
+        rr += r * r;
+    }
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) a.rr_part[blockIdx.x] = rr;
+}
+
 __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
     __shared__ double red[16];
     const int c = blockIdx.x;
@@ -947,6 +1009,28 @@ void launch_defl_init(const DeflArgs &a, int kmax, int grid, hipStream_t s) {
         case 16: hipLaunchKernelGGL(k_defl_init<16>, dim3(grid), dim3(256), 0, s, a); break;
         case 32: hipLaunchKernelGGL(k_defl_init<32>, dim3(grid), dim3(256), 0, s, a); break;
         default: hipLaunchKernelGGL(k_defl_init<64>, dim3(grid), dim3(256), 0, s, a); break;
+    }
+}
+
+void launch_reorth(const ReorthArgs &a, int kmax, int grid, hipStream_t s) {
+    switch (kmax) {
+        case 0: break;
+        case 8:
+            hipLaunchKernelGGL(k_wtr<8>, dim3(grid), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(k_reorth<8>, dim3(grid), dim3(256), 0, s, a);
+            break;
+        case 16:
+            hipLaunchKernelGGL(k_wtr<16>, dim3(grid), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(k_reorth<16>, dim3(grid), dim3(256), 0, s, a);
+            break;
+        case 32:
+            hipLaunchKernelGGL(k_wtr<32>, dim3(grid), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(k_reorth<32>, dim3(grid), dim3(256), 0, s, a);
+            break;
+        default:
+            hipLaunchKernelGGL(k_wtr<64>, dim3(grid), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(k_reorth<64>, dim3(grid), dim3(256), 0, s, a);
+            break;
     }
 }
 

@@ -135,6 +135,16 @@ struct DeflArgs {                   // Alg. 1, lines 3-4
     Ctl *ctl;
 };
 
+struct ReorthArgs {                 // Alg. 1 optional line: r -= W (W^T W)^{-1} W^T r
+    int n;
+    double *r;
+    const double *W; int64_t ld;
+    const double *WWinv;            // (W^T W)^{-1}, k x k
+    double *part;                   // W^T r per block, column-major (k columns x grid)
+    double *rr_part;                // ||r||^2 per block after the projection
+    Ctl *ctl;
+};
+
 struct ReduceArgs {                 // out[c] = sum_b part[c * n + b]
     const double *part;
     int n, ncol;
@@ -252,6 +262,8 @@ struct CommitArgs {                 // W, AW <- Wn, AWn and the inverse, when st
     int ncol;
     const double *Wn, *AWn, *inv_new;
     double *W, *AW, *inv;
+    const double *ww_new;           // nullable: (W^T W)^{-1} of the new basis
+    double *ww;
     RecState *state;
 };
 
@@ -303,6 +315,7 @@ void launch_pupd(const PupdArgs &a, int kmax, int grid, hipStream_t s);
 void launch_resid(const ResidArgs &a, int kmax, int grid, hipStream_t s);
 void launch_defl_init(const DeflArgs &a, int kmax, int grid, hipStream_t s);
 void launch_reduce(const ReduceArgs &a, hipStream_t s);
+void launch_reorth(const ReorthArgs &a, int kmax, int grid, hipStream_t s);
 void launch_coarse_dense(const CoarseDenseArgs &a, hipStream_t s);
 void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s);
 void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s);

@@ -507,7 +507,10 @@ __global__ void __launch_bounds__(256) k_commit(CommitArgs a) {
         a.AW[g] = a.AWn[g];
     }
     if (blockIdx.x == 0) {
-        for (int e = threadIdx.x; e < a.ncol * a.ncol; e += blockDim.x) a.inv[e] = a.inv_new[e];
+        for (int e = threadIdx.x; e < a.ncol * a.ncol; e += blockDim.x) {
+            a.inv[e] = a.inv_new[e];
+            if (a.ww_new) a.ww[e] = a.ww_new[e];
+        }
         if (threadIdx.x == 0) a.state->k = a.ncol;
     }
 }

@@ -33,8 +33,8 @@ class Solver:
                  node_dirichlet=None, ny=None, nz=None, R=0, strategy="B4", local_prec=64,
                  weights="diag", constraints=("corners", "faces"), stop_rule="rhs",
                  init_guess="prev", max_it=1000, save_cap=256, freeze_tol=1e-5,
-                 use_graph=True, autotune=True, coarse_form="auto", product_cfg=None, device="cuda",
-                 stream=None):
+                 use_graph=True, autotune=True, coarse_form="auto", product_cfg=None, reorth=False,
+                 device="cuda", stream=None):
         lib = _lib.load()
         self.lib = lib
         self.device = torch.device(device)
@@ -79,6 +79,7 @@ class Solver:
         o.use_graph = 1 if use_graph else 0
         o.autotune = 1 if autotune else 0
         o.coarse_form = {"auto": 0, "chain": 1, "explicit": 2}[coarse_form]
+        o.reorth = 1 if reorth else 0
         if product_cfg is not None:
             assert len(product_cfg) == 8
             for i, v in enumerate(product_cfg):

@@ -282,3 +282,15 @@ def test_pinned_product_configuration():
         assert _rel(U[k].cpu().numpy(), uo[k]) <= 1e-9
     with pytest.raises(BddcError):
         _solver("tiny3", product_cfg=[2, 1, 5, 2, 0, 0, 0, 0])
+
+
+def test_reorthogonalisation_matches_oracle():
+    torch = _torch()
+    F = workload.rhs_sequence(16, 5)
+    U, its, rr = _solver("tiny3", R=6, reorth=True).solve_sequence(torch.tensor(F, device="cuda"), 1e-10)
+    uo, ito, _ = _oracle("tiny3", R=6, reorth=True).solve_sequence(F, 1e-10)
+    print("[gpu] reorth iters gpu %s oracle %s" % (its.tolist(), ito.tolist()), flush=True)
+    assert np.all(np.abs(its - ito) <= 1)
+    assert np.all(rr < 1e-10)
+    for k in range(len(F)):
+        assert _rel(U[k].cpu().numpy(), uo[k]) <= 1e-9

@@ -76,6 +76,28 @@ def test_deflation_invariants(c16):
     assert np.abs(off).max() < 1e-6 * np.abs(np.diag(G)).max()
 
 
+def test_reorthogonalisation_projects_residual(c16):
+    # optional line of Alg. 1: after r -= W (W^T W)^{-1} W^T r the residual is
+    # orthogonal to range(W) to rounding at every step (the recurrence alone
+    # only keeps W^T r small), and the iteration still converges to A^{-1} b
+    ss, M, F = c16
+    g = np.random.default_rng(7)
+    W = g.standard_normal((ss.n_gamma, 5))
+    b = ss.condense(F[1])
+    plain = dpcg(ss.apply_A, M.apply, b, W=W, rtol=1e-10)
+    ro = dpcg(ss.apply_A, M.apply, b, W=W, rtol=1e-10, reorth=True)
+    assert max(ro["wtr"]) < 1e-14
+    assert max(ro["wtr"]) <= max(plain["wtr"])
+    assert abs(ro["iters"] - plain["iters"]) <= 1
+    np.testing.assert_allclose(ro["x"], plain["x"], atol=1e-8 * np.abs(plain["x"]).max())
+    n = 60
+    A = _spd(n, cond=1e6, seed=3)
+    Wd = g.standard_normal((n, 6))
+    bd = g.standard_normal(n)
+    rd = dpcg(lambda v: A @ v, lambda v: v, bd, W=Wd, rtol=1e-11, reorth=True)
+    np.testing.assert_allclose(rd["x"], np.linalg.solve(A, bd), rtol=1e-7)
+
+
 def test_w_empty_is_plain_pcg(c16):
     ss, M, F = c16
     b = ss.condense(F[1])
