@@ -31,6 +31,8 @@ WORKLOADS = {
     "c3": "Q1 Poisson 64^3 elements minus a sphere of radius 0.15, 400 jittered-RCB subdomains of uneven size, "
           "log-normal coefficients (sigma 0.5), three-level BDDC (50 subregions), deflated PCG B4 R=20, "
           "50 drifting-Gaussian right-hand sides, rtol 1e-8",
+    "c96": "Q1 Poisson 96^3 elements (912,673 nodes), 1,728 subdomains of 8^3, three-level BDDC (216 subregions), "
+           "deflated PCG B4 R=20, 20 drifting-Gaussian right-hand sides, rtol 1e-8 (adjoint: 20 more solves)",
 }
 
 
@@ -113,10 +115,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2)
-    ap.add_argument("--workload", default="c64", choices=("c64", "c3"),
+    ap.add_argument("--workload", default="c64", choices=("c64", "c3", "c96"),
                     help="c64: 64^3 cube lattice (the headline configuration); c3: 64^3 with a spherical "
                          "hole, 400 uneven RCB subdomains, log-normal coefficients")
     ap.add_argument("--bf16", action="store_true", help="also run the bfloat16 Neumann-operator form")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time the adjoint gradient of L = sum_k ||u_k - t_k||^2 (t_k = 0.9 u_k): one adjoint "
+                         "solve per right-hand side with the recycled basis, and the element gradient")
     ap.add_argument("--pin", default=None,
                     help="fixed product configuration of the float64 form: 8 comma-separated integers "
                          "(Schur then Neumann: blocks per CU, per-subdomain split, waves, tiles in flight)")
@@ -227,6 +232,20 @@ def main():
         line["mixed_bf16"] = {"value": round(bv, 3), "unit": "solves/s", "iters": its_fmt(bf["its"].tolist()),
                               "max_true_relres": float(bf["rr"].max()), "max_rel_diff_vs_fp64": err,
                               "speedup_vs_fp64": round(bv / value, 3)}
+    if args.adjoint:
+        g = f64["g"]
+        U = f64["U"]
+        dLdu = 2.0 * (U - 0.9 * U)
+        g.adjoint_grad(dLdu, U, args.rtol)          # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            grad, gF = g.adjoint_grad(dLdu, U, args.rtol)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        line["adjoint"] = {"value": round(n_rhs * args.steps / el, 3), "unit": "adjoint solves/s",
+                           "s_per_sequence": round(el / args.steps, 4),
+                           "grad_norm": float(grad.norm().item())}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(s, F_np, args.cpu_sample)
     print(json.dumps(line), flush=True)
