@@ -58,10 +58,11 @@ def pin_of(tuning):
     return out
 
 
-def run_form(torch, Solver, s, F, rtol, steps, warmup, local_prec, timing, use_graph=True, pin=None):
+def run_form(torch, Solver, s, F, rtol, steps, warmup, local_prec, timing, use_graph=True, pin=None, autotune=True):
     t0 = time.perf_counter()
     g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"],
-               elem_keep=s["elem_keep"], R=s["R"], local_prec=local_prec, use_graph=use_graph, product_cfg=pin)
+               elem_keep=s["elem_keep"], R=s["R"], local_prec=local_prec, use_graph=use_graph, product_cfg=pin,
+               autotune=autotune)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     for _ in range(warmup):
@@ -114,6 +115,7 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain (kernel-by-kernel) FP64 form")
     ap.add_argument("--cpu-sample", type=int, default=2)
     ap.add_argument("--workload", default="c64", choices=("c64", "c3", "c96"),
                     help="c64: 64^3 cube lattice (the headline configuration); c3: 64^3 with a spherical "
@@ -216,6 +218,15 @@ def main():
         "pin": ",".join(str(v) for v in pin_of(f64["tuning"])),
         "pin_source": pin_source,
     }
+    plain_value = None
+    if not args.no_plain:
+        # the plain FP64 GPU form: kernels launched one by one with a host check
+        # after every iteration, default product configuration (no autotuning)
+        pl = run_form(torch, Solver, s, F, args.rtol, args.steps, args.warmup, 64, False, use_graph=False,
+                      autotune=False)
+        plain_value = n_rhs * args.steps / pl["elapsed"]
+        line["fp64_plain"] = {"value": round(plain_value, 3), "unit": "solves/s", "iters": its_fmt(pl["its"].tolist()),
+                              "max_true_relres": float(pl["rr"].max())}
     if not args.no_mixed:
         mx = run_form(torch, Solver, s, F, args.rtol, args.steps, args.warmup, 32, False)
         ud = f64["U"]
@@ -224,6 +235,8 @@ def main():
         line["mixed_fp32"] = {"value": round(mv, 3), "unit": "solves/s", "iters": its_fmt(mx["its"].tolist()),
                               "max_true_relres": float(mx["rr"].max()), "max_rel_diff_vs_fp64": err,
                               "speedup_vs_fp64": round(mv / value, 3)}
+        if plain_value:
+            line["mixed_fp32"]["speedup_vs_plain_fp64"] = round(mv / plain_value, 3)
     if args.bf16:
         bf = run_form(torch, Solver, s, F, args.rtol, args.steps, args.warmup, 16, False)
         ud = f64["U"]
@@ -232,6 +245,8 @@ def main():
         line["mixed_bf16"] = {"value": round(bv, 3), "unit": "solves/s", "iters": its_fmt(bf["its"].tolist()),
                               "max_true_relres": float(bf["rr"].max()), "max_rel_diff_vs_fp64": err,
                               "speedup_vs_fp64": round(bv / value, 3)}
+        if plain_value:
+            line["mixed_bf16"]["speedup_vs_plain_fp64"] = round(bv / plain_value, 3)
     if args.adjoint:
         g = f64["g"]
         U = f64["U"]

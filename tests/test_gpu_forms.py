@@ -167,12 +167,12 @@ def _adjoint_problem(nx=16, n_rhs=3):
     return F, T, theta
 
 
-def _gpu_loss_and_grad(torch, theta, F, T, R=4):
+def _gpu_loss_and_grad(torch, theta, F, T, R=4, rtol=1e-12):
     from paper_2412_17543_amd.solver import DPCGSolveFn
     s = workload.workload("c16")
     th = torch.tensor(theta, device="cuda", requires_grad=True)
     Ft = torch.tensor(F, device="cuda", requires_grad=True)
-    spec = dict(nx=16, elem_to_sub=s["elem_to_sub"], R=R, rtol=1e-12)
+    spec = dict(nx=16, elem_to_sub=s["elem_to_sub"], R=R, rtol=rtol, autotune=False)
     U = DPCGSolveFn.apply(th, Ft, spec)
     L = ((U - torch.tensor(T, device="cuda")) ** 2).sum()
     L.backward()
@@ -208,6 +208,33 @@ def test_adjoint_gradient_central_differences_through_gpu_solves():
     err = np.abs(g[idx] - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(g).max())
     print("[gpu] FD rel err", err, flush=True)
     assert err.max() < 1e-5
+
+
+def test_adjoint_gradient_50_random_directions():
+    # directional central differences, step 1e-6, along 50 seeded random
+    # directions in the space of element log-coefficients (16^3)
+    # (solves at rtol 1e-14: a step of 1e-6 turns a relative solve error e into
+    # an error of about e / 1e-6 in the difference quotient)
+    torch = _torch()
+    F, T, theta = _adjoint_problem()
+    L, g, _ = _gpu_loss_and_grad(torch, theta, F, T, R=0, rtol=1e-14)
+    eps = 1e-6
+    rng = np.random.default_rng(8)
+    fd, gv = [], []
+    for _ in range(50):
+        v = rng.standard_normal(theta.size)
+        v /= np.linalg.norm(v)
+        Lp = _gpu_loss_and_grad(torch, theta + eps * v, F, T, R=0, rtol=1e-14)[0]
+        Lm = _gpu_loss_and_grad(torch, theta - eps * v, F, T, R=0, rtol=1e-14)[0]
+        fd.append((Lp - Lm) / (2 * eps))
+        gv.append(g @ v)
+    fd, gv = np.array(fd), np.array(gv)
+    rel = np.linalg.norm(fd - gv) / np.linalg.norm(fd)
+    worst = np.max(np.abs(fd - gv) / np.maximum(np.abs(fd), 1e-3 * np.linalg.norm(g)))
+    print("[gpu] directional FD: relative error %.2e over the 50 directions, worst single %.2e" % (rel, worst),
+          flush=True)
+    assert rel < 1e-5
+    assert worst < 1e-4
 
 
 def _hole_solver(name, **kw):
