@@ -2,6 +2,7 @@
 // Krylov subspace recycling, adjoint gradient (see include/bddc.h).
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -46,7 +47,7 @@ struct OpHost {
     double bytes = 0;               // algorithmic bytes of one product
     bool interior = false;          // interior operators (sizes nI, no gather lists)
     std::vector<int32_t> nchunk;    // per subdomain
-    int32_t *d_items = nullptr, *d_nchunk = nullptr, *d_pb = nullptr, *d_cb = nullptr, *d_seg = nullptr;
+    int32_t *d_items = nullptr, *d_nchunk = nullptr, *d_pb = nullptr, *d_cb = nullptr;
     double *d_ypart = nullptr, *d_cpart = nullptr;
     int64_t ypart_len = 0, cpart_len = 0;
     // flat gather lists: interface node -> y partials, coarse DOF -> c partials
@@ -147,7 +148,10 @@ struct bddc_ctx {
     // control
     Ctl *d_ctl = nullptr, *h_ctl = nullptr;
     SyncBuf *h_sync = nullptr;      // pinned
-    double *h_hist = nullptr;       // pinned: alpha, d, rho (hcopy each), mu (hcopy x RMAX)
+    double *h_hist = nullptr;       // pinned: alpha, d, rho (hist_cap each), mu (hist_cap x RMAX)
+    SyncBuf *d_sync = nullptr;      // device image of SyncBuf (holds d_ctl, d_state, d_WAWsym)
+    bool pre_schur = false;         // A x of the next solve's initial residual already enqueued
+    double *d_hblk = nullptr;       // device image of h_hist (holds the four histories)
     double *h_Y = nullptr;          // pinned staging of the recycling coefficients
     int hcopy = 0;
     int32_t *h_flags = nullptr;     // pinned, device-mapped: [0] convergence word
@@ -159,6 +163,7 @@ struct bddc_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipEvent_t gev[GRAPH_INFLIGHT + 1] = {};
+    hipEvent_t sync_ev = nullptr;   // recorded after the copies of a solve's synchronisation
     // element data for the adjoint gradient
     double *d_coefh = nullptr;
     uint8_t *d_keep = nullptr, *d_free = nullptr;
@@ -276,37 +281,38 @@ void flush_timing(bddc_ctx *c) {
 // spans subdomains; the block count follows the rounding).
 int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
     const int nsub = c->n_sub;
-    std::vector<SymvItem> items;
-    std::vector<int32_t> nch(nsub, 0), pb(nsub), cb(nsub), seg_ptr(nblocks + 1, 0);
+    struct Seg { int k; int64_t t0, t1; int32_t c; };
+    std::vector<std::vector<Seg>> blk;   // segments of every block, in order
+    std::vector<int32_t> nch(nsub, 0), pb(nsub), cb(nsub), xoff(nsub + 1, 0);
     int64_t ylen = 0, clen = 0;
     const std::vector<int32_t> &sizes = op.interior ? c->h_nI : c->h_nB;
     std::vector<int64_t> start(nsub + 1, 0);
-    for (int i = 0; i < nsub; ++i) start[i + 1] = start[i] + ntiles_of(sizes[i], op.dev.nc ? c->h_nc[i] : 0);
+    for (int i = 0; i < nsub; ++i) {
+        start[i + 1] = start[i] + ntiles_of(sizes[i], op.dev.nc ? c->h_nc[i] : 0);
+        xoff[i + 1] = xoff[i] + sizes[i];
+    }
     const int64_t total = start[nsub];
+    if (total > INT32_MAX) return fail(BDDC_EINVAL, "operator tile count exceeds int32 indexing");
     if (per_sub) {
         const int64_t target = std::max<int64_t>(1, (total + nblocks - 1) / nblocks);
         for (int k = 0; k < nsub; ++k) {
             const int64_t nt = start[k + 1] - start[k];
             if (nt == 0) continue;
             const int C = (int)std::min<int64_t>(nt, std::max<int64_t>(1, (nt + target / 2) / target));
-            for (int q = 0; q < C; ++q)
-                items.push_back(SymvItem{k, (int32_t)(nt * q / C), (int32_t)(nt * (q + 1) / C), nch[k]++});
+            for (int q = 0; q < C; ++q) blk.push_back({Seg{k, nt * q / C, nt * (q + 1) / C, nch[k]++}});
         }
-        nblocks = (int)items.size();
-        seg_ptr.assign(nblocks + 1, 0);
-        for (int b = 0; b <= nblocks; ++b) seg_ptr[b] = b;
+        nblocks = (int)blk.size();
     } else {
+        blk.resize(nblocks);
         int i = 0;
         for (int b = 0; b < nblocks; ++b) {
             const int64_t g0 = total * b / nblocks, g1 = total * (b + 1) / nblocks;
-            seg_ptr[b] = (int32_t)items.size();
             while (i < nsub && start[i + 1] <= g0) ++i;
             for (int k = i; k < nsub && start[k] < g1; ++k) {
                 const int64_t t0 = std::max(g0, start[k]) - start[k], t1 = std::min(g1, start[k + 1]) - start[k];
-                if (t1 > t0) items.push_back(SymvItem{k, (int32_t)t0, (int32_t)t1, nch[k]++});
+                if (t1 > t0) blk[b].push_back(Seg{k, t0, t1, nch[k]++});
             }
         }
-        seg_ptr[nblocks] = (int32_t)items.size();
     }
     for (int k = 0; k < nsub; ++k) {
         const int nci = op.dev.nc ? c->h_nc[k] : 0;
@@ -316,12 +322,31 @@ int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
         clen += (int64_t)nch[k] * nci;
     }
     if (ylen > INT32_MAX || clen > INT32_MAX) return fail(BDDC_EINVAL, "operator partial buffers exceed int32 indexing");
-    dfree(c, op.d_items); dfree(c, op.d_nchunk); dfree(c, op.d_pb); dfree(c, op.d_cb); dfree(c, op.d_seg);
-    std::vector<int32_t> raw(std::max<size_t>(1, items.size()) * 4, 0);
+    // block b's first segment at index b, its others appended and chained
+    std::vector<SymvItem> items(std::max(nblocks, 1), SymvItem{0, 0, 0, 0, 0, 0, 0, 0, -1, 0, 0, 0});
+    auto record = [&](const Seg &g) {
+        const int nci = op.dev.nc ? c->h_nc[g.k] : 0;
+        return SymvItem{(int32_t)start[g.k], (int32_t)g.t0, (int32_t)g.t1, sizes[g.k], nci, xoff[g.k],
+                        pb[g.k] + g.c * sizes[g.k], cb[g.k] + g.c * nci, -1, 0, 0, 0};
+    };
+    for (int b = 0; b < nblocks; ++b) {
+        int prev = b;
+        for (size_t q = 0; q < blk[b].size(); ++q) {
+            if (q == 0) {
+                items[b] = record(blk[b][0]);
+            } else {
+                items[prev].next = (int32_t)items.size();
+                prev = (int)items.size();
+                items.push_back(record(blk[b][q]));
+            }
+        }
+    }
+    dfree(c, op.d_items); dfree(c, op.d_nchunk); dfree(c, op.d_pb); dfree(c, op.d_cb);
+    std::vector<int32_t> raw(items.size() * (sizeof(SymvItem) / 4));
     std::memcpy(raw.data(), items.data(), items.size() * sizeof(SymvItem));
     int rc;
     if ((rc = dupload(c, &op.d_items, raw)) || (rc = dupload(c, &op.d_nchunk, nch)) || (rc = dupload(c, &op.d_pb, pb)) ||
-        (rc = dupload(c, &op.d_cb, cb)) || (rc = dupload(c, &op.d_seg, seg_ptr)))
+        (rc = dupload(c, &op.d_cb, cb)))
         return rc;
     if (ylen > op.ypart_len) {
         dfree(c, op.d_ypart);
@@ -335,8 +360,6 @@ int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
     }
     op.nchunk = nch;
     op.dev.items = reinterpret_cast<const SymvItem *>(op.d_items);
-    op.dev.n_items = (int)items.size();
-    op.dev.seg_ptr = op.d_seg;
     op.dev.n_blocks = total > 0 ? nblocks : 0;
     op.dev.nchunk = op.d_nchunk;
     op.dev.pb = op.d_pb;
@@ -686,23 +709,24 @@ void resolve_pending(bddc_ctx *c) {
 }
 
 // The one host synchronisation of a solve: control block, deflation state
-// and, when recording, the scalar histories of the solve.
-int end_sync(bddc_ctx *c, bool hist) {
-    HIPCHK(hipMemcpyAsync(&c->h_sync->ctl, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
-    if (c->R > 0) {
-        HIPCHK(hipMemcpyAsync(&c->h_sync->rs, c->d_state, sizeof(RecState), hipMemcpyDeviceToHost, c->stream));
-        if (c->pend.active)
-            HIPCHK(hipMemcpyAsync(c->h_sync->waw, c->d_WAWsym, (size_t)c->pend.k * c->pend.k * sizeof(double),
-                                  hipMemcpyDeviceToHost, c->stream));
+// and, when recording, the scalar histories of the solve.  end_sync_issue
+// enqueues the copies and an event after them; work enqueued after that
+// keeps the device busy while end_sync_wait waits for the event only.
+int end_sync_issue(bddc_ctx *c, bool hist) {
+    const size_t waw = c->pend.active ? (size_t)c->pend.k * c->pend.k * sizeof(double) : 0;
+    HIPCHK(hipMemcpyAsync(c->h_sync, c->d_sync, offsetof(SyncBuf, waw) + waw, hipMemcpyDeviceToHost, c->stream));
+    if (hist) {   // alpha, d and rho (the first hcopy of each), then mu
+        const size_t n = (size_t)c->hcopy, cap = (size_t)c->hist_cap;
+        HIPCHK(hipMemcpyAsync(c->h_hist, c->d_hblk, (2 * cap + n) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_hist + 3 * cap, c->d_muhist, n * RMAX * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
     }
-    if (hist) {
-        const size_t n = (size_t)c->hcopy;
-        HIPCHK(hipMemcpyAsync(c->h_hist, c->d_ahist, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipMemcpyAsync(c->h_hist + n, c->d_dhist, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipMemcpyAsync(c->h_hist + 2 * n, c->d_rhohist, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipMemcpyAsync(c->h_hist + 3 * n, c->d_muhist, n * RMAX * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    }
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipEventRecord(c->sync_ev, c->stream));
+    return 0;
+}
+
+int end_sync_wait(bddc_ctx *c) {
+    HIPCHK(hipEventSynchronize(c->sync_ev));
     *c->h_ctl = c->h_sync->ctl;
     resolve_pending(c);
     return 0;
@@ -718,8 +742,11 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     *c->h_flags = 0;
     launch_ctl_init(c->d_ctl, rtol * rtol, record ? 1 : 0, c->R > 0 ? c->d_state : nullptr, c->d_hflag, c->stream);
     if (!condensed) run_condense(c, F);                  // b, ||b||^2 partials
-    if (c->opts.init_guess == 1) launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
-    run_schur(c, c->d_x, false, false);                  // r = b - A x_{-1}
+    if (!c->pre_schur) {
+        if (c->opts.init_guess == 1) launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
+        run_schur(c, c->d_x, false, false);              // r = b - A x_{-1}
+    }
+    c->pre_schur = false;
     run_resid(c, c->d_r, c->R > 0);
     {
         TScope ts(c, TK_VEC);
@@ -731,6 +758,7 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     run_precond(c, c->d_r, c->d_z, 2, false, false, true);  // first test, lines 5-6
     run_pupd(c, true, false, true);                         // line 7
     int restarts = 0, rc;
+    bool recovered = false;
     while (true) {
         if ((rc = run_loop(c))) return rc;
         run_true_residual(c, c->d_tmp);                  // float64 ||b - A x||
@@ -742,13 +770,23 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
             run_precond(c, c->d_r, c->d_z, 0, false, true, true);
             run_pupd(c, false, true, false);
         }
-        if ((rc = end_sync(c, extra))) return rc;
+        // interior recovery from this x, enqueued behind the synchronisation's
+        // copies so that the device works while the host waits (done again if
+        // the solve goes on or x is reset)
+        if ((rc = end_sync_issue(c, extra))) return rc;
+        if ((rc = run_recover(c, F, u))) return rc;
+        recovered = true;
+        if ((rc = end_sync_wait(c))) return rc;
         const Ctl &h = *c->h_ctl;
-        if (h.zero_rhs) launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
+        if (h.zero_rhs) {
+            launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
+            recovered = false;
+        }
         if (h.status != 0 || h.zero_rhs) break;
         if (h.true_rr < h.rtol2 * h.denom2 || h.iter >= c->opts.max_it) break;
         // residual replacement, then continue from line 5 (iterations keep counting)
         ++restarts;
+        recovered = false;
         launch_copy(c->n_gamma, c->d_tmp, c->d_r, c->stream);
         launch_set_done(c->d_ctl, 0, c->stream);
         run_precond(c, c->d_r, c->d_z, 0, false, !extra, true);
@@ -763,7 +801,7 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     c->have_hist = want_hist && restarts == 0;
     if (iters) *iters = h.iter;
     if (relres) *relres = (h.bb > 0 && !h.zero_rhs) ? std::sqrt(h.true_rr / h.bb) : 0.0;
-    if ((rc = run_recover(c, F, u))) return rc;
+    if (!recovered && (rc = run_recover(c, F, u))) return rc;
     if (h.status == BDDC_EBREAKDOWN) return fail(BDDC_EBREAKDOWN, "PCG breakdown (r^T z <= 0, p^T A p <= 0 or NaN)");
     if (h.status == BDDC_ENOTCONV) return fail(BDDC_ENOTCONV, "max_it reached");
     return 0;
@@ -783,9 +821,9 @@ int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol, cons
     const int l = m - c->k;
     GemmArgs g{};
     g.n = c->n_gamma; g.ld = c->ld; g.Y = c->d_Y; g.ncol = ncol; g.ldy = ldy;
-    g.V1 = c->d_W; g.k1 = c->k; g.V2 = c->d_P; g.k2 = l; g.out = c->d_Wn;
-    launch_recycle_gemm(g, c->stream);
-    g.V1 = c->d_AW; g.V2 = c->d_AP; g.out = c->d_AWn;
+    g.k1 = c->k; g.k2 = l;
+    g.V1[0] = c->d_W; g.V2[0] = c->d_P; g.out[0] = c->d_Wn;
+    g.V1[1] = c->d_AW; g.V2[1] = c->d_AP; g.out[1] = c->d_AWn;
     launch_recycle_gemm(g, c->stream);
     const int nb = c->gram_nb;
     GramArgs gr{};
@@ -852,7 +890,7 @@ int do_recycle(bddc_ctx *c) {
     }
     if (m == 0 || !c->have_hist) return 0;
     // scalars of the last solve
-    const size_t hn = (size_t)c->hcopy;
+    const size_t hn = (size_t)c->hist_cap;
     const double *al = c->h_hist, *dd = c->h_hist + hn, *rho = c->h_hist + 2 * hn, *mu = c->h_hist + 3 * hn;
     // F = V^T A V = blockdiag(W^T A W, diag(d)) and G = V^T A M^{-1} A V from the
     // recurrences of Algorithm 1: M^{-1} A p_j = (z_j - z_{j+1}) / alpha_j
@@ -883,9 +921,24 @@ int do_recycle(bddc_ctx *c) {
     for (size_t e = 0; e < G.size(); ++e)
         if (!std::isfinite(G[e]) || !std::isfinite(F[e])) return 0;   // keep the basis
     // generalized eigenproblem G y = theta F y: F = U diag(lam) U^T, directions
-    // with lam < 1e-12 max dropped, T = U lam^{-1/2}, H = T^T G T
-    std::vector<double> lam, U;
-    sym_eig(F, m, lam, U);
+    // with lam < 1e-12 max dropped, T = U lam^{-1/2}, H = T^T G T.  F is block
+    // diagonal (W^T A W, then diag(d)): its eigenpairs are those of W^T A W
+    // and (d_j, unit vectors).
+    std::vector<double> lam(m, 0.0), U((size_t)m * m, 0.0);
+    if (k > 0) {
+        std::vector<double> Fw((size_t)k * k), lw, Uw;
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) Fw[(size_t)i * k + j] = F[(size_t)i * m + j];
+        sym_eig(Fw, k, lw, Uw);
+        for (int j = 0; j < k; ++j) {
+            lam[j] = lw[j];
+            for (int i = 0; i < k; ++i) U[(size_t)i * m + j] = Uw[(size_t)i * k + j];
+        }
+    }
+    for (int j = k; j < m; ++j) {
+        lam[j] = F[(size_t)j * m + j];
+        U[(size_t)j * m + j] = 1.0;
+    }
     const double lmax = *std::max_element(lam.begin(), lam.end());
     std::vector<int> keep;
     for (int i = 0; i < m; ++i)
@@ -925,17 +978,17 @@ int do_recycle(bddc_ctx *c) {
             Y[(size_t)q * ncol + j] = s;
         }
     }
-    // G_WW of the new basis: Y^T G Y
-    std::vector<double> gww((size_t)ncol * ncol, 0.0);
-    for (int i = 0; i < ncol; ++i)
-        for (int j = 0; j < ncol; ++j) {
-            double s = 0.0;
-            for (int q = 0; q < m; ++q) {
-                double t = 0.0;
-                for (int r = 0; r < m; ++r) t += G[(size_t)q * m + r] * Y[(size_t)r * ncol + j];
-                s += Y[(size_t)q * ncol + i] * t;
-            }
-            gww[(size_t)i * ncol + j] = s;
+    // G_WW of the new basis: Y^T (G Y)
+    std::vector<double> GY((size_t)m * ncol, 0.0), gww((size_t)ncol * ncol, 0.0);
+    for (int q = 0; q < m; ++q)
+        for (int r = 0; r < m; ++r) {
+            const double g = G[(size_t)q * m + r];
+            for (int j = 0; j < ncol; ++j) GY[(size_t)q * ncol + j] += g * Y[(size_t)r * ncol + j];
+        }
+    for (int q = 0; q < m; ++q)
+        for (int i = 0; i < ncol; ++i) {
+            const double y = Y[(size_t)q * ncol + i];
+            for (int j = 0; j < ncol; ++j) gww[(size_t)i * ncol + j] += y * GY[(size_t)q * ncol + j];
         }
     // freeze test (eq. harmritzstopcrit) on the sorted selected values
     bool freeze = false;
@@ -952,11 +1005,9 @@ int do_recycle(bddc_ctx *c) {
 
 // Wait for the device and adopt a pending basis update (end of a sequence).
 int settle(bddc_ctx *c) {
-    if (c->R > 0 && c->pend.active) {
-        HIPCHK(hipMemcpyAsync(&c->h_sync->rs, c->d_state, sizeof(RecState), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipMemcpyAsync(c->h_sync->waw, c->d_WAWsym, (size_t)c->pend.k * c->pend.k * sizeof(double),
+    if (c->R > 0 && c->pend.active)
+        HIPCHK(hipMemcpyAsync(c->h_sync, c->d_sync, offsetof(SyncBuf, waw) + (size_t)c->pend.k * c->pend.k * sizeof(double),
                               hipMemcpyDeviceToHost, c->stream));
-    }
     HIPCHK(hipStreamSynchronize(c->stream));
     resolve_pending(c);
     return 0;
@@ -1681,23 +1732,31 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         (rc = dalloc(c, &c->d_zp, (size_t)c->vgrid * (RMAX + 1))) ||
         (rc = dalloc(c, &c->d_wp, (size_t)c->vgrid * (RMAX + 1))) ||
         (rc = dalloc(c, &c->d_gp, (size_t)gram_nb * RMAX * RMAX)) ||
-        (rc = dalloc(c, &c->d_ctl, 1)) || (rc = dalloc(c, &c->d_ahist, c->hist_cap)) ||
-        (rc = dalloc(c, &c->d_dhist, c->hist_cap)) || (rc = dalloc(c, &c->d_rhohist, c->hist_cap)) ||
+        (rc = dalloc(c, &c->d_sync, 1)) || (rc = dalloc(c, &c->d_hblk, (size_t)c->hist_cap * (3 + RMAX))) ||
         (rc = dalloc(c, &c->d_bhist, c->hist_cap)) || (rc = dalloc(c, &c->d_reshist, c->hist_cap)) ||
-        (rc = dalloc(c, &c->d_muhist, (size_t)c->hist_cap * RMAX)) || (rc = dalloc(c, &c->d_WAWinv, RMAX * RMAX)) ||
-        (rc = dalloc(c, &c->d_WAWnew, RMAX * RMAX)) || (rc = dalloc(c, &c->d_WAWsym, RMAX * RMAX)) ||
-        (rc = dalloc(c, &c->d_invnew, RMAX * RMAX)) || (rc = dalloc(c, &c->d_state, 1)) ||
+        (rc = dalloc(c, &c->d_WAWinv, RMAX * RMAX)) || (rc = dalloc(c, &c->d_WAWnew, RMAX * RMAX)) ||
+        (rc = dalloc(c, &c->d_invnew, RMAX * RMAX)) ||
         (rc = dalloc(c, &c->d_WWinv, RMAX * RMAX)) || (rc = dalloc(c, &c->d_WWnew, RMAX * RMAX)) ||
         (rc = dalloc(c, &c->d_WWsym, RMAX * RMAX)) || (rc = dalloc(c, &c->d_WWinvnew, RMAX * RMAX)) ||
         (rc = dalloc(c, &c->d_rop, (size_t)RMAX * VGRID)) || (rc = dalloc(c, &c->d_state2, 1)))
         return rc;
+    // control block, deflation state and W^T A W of a pending update side by
+    // side (the layout of the pinned SyncBuf: one copy per synchronisation);
+    // alpha, d, rho and mu histories in one block of the pinned h_hist layout
+    c->d_ctl = &c->d_sync->ctl;
+    c->d_state = &c->d_sync->rs;
+    c->d_WAWsym = c->d_sync->waw;
+    c->d_ahist = c->d_hblk;
+    c->d_dhist = c->d_hblk + c->hist_cap;
+    c->d_rhohist = c->d_hblk + 2 * (size_t)c->hist_cap;
+    c->d_muhist = c->d_hblk + 3 * (size_t)c->hist_cap;
     HIPCHK(hipMemsetAsync(c->d_x, 0, ng * sizeof(double), s));
     HIPCHK(hipMemsetAsync(c->d_p, 0, ng * sizeof(double), s));
     HIPCHK(hipMemsetAsync(c->d_ctl, 0, sizeof(Ctl), s));
     HIPCHK(hipMemsetAsync(c->d_state, 0, sizeof(RecState), s));
     HIPCHK(hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&c->h_sync, sizeof(SyncBuf), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void **)&c->h_hist, sizeof(double) * (size_t)c->hcopy * (3 + RMAX), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c->h_hist, sizeof(double) * (size_t)c->hist_cap * (3 + RMAX), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&c->h_flags, sizeof(int32_t) * 4, hipHostMallocMapped));
     HIPCHK(hipHostGetDevicePointer((void **)&c->d_hflag, c->h_flags, 0));
     c->h_flags[0] = 0;
@@ -1705,7 +1764,8 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         // W, AW always exist (k = 0 columns are never read); the recycling
         // buffers only with R > 0
         const size_t cols = (size_t)std::max(1, c->R);
-        const int ymax = std::max((c->R + c->save_cap) * ((c->R + 7) / 8 * 8), RMAX * RMAX);
+        // (+ RMAX: the recycling product reads up to 64 entries past a row)
+        const int ymax = std::max((c->R + c->save_cap) * ((c->R + 7) / 8 * 8), RMAX * RMAX) + RMAX;
         if ((rc = dalloc(c, &c->d_W, cols * ng)) || (rc = dalloc(c, &c->d_AW, cols * ng)) ||
             (rc = dalloc(c, &c->d_Y, (size_t)ymax)))
             return rc;
@@ -1747,6 +1807,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
     if ((rc = dalloc(c, &c->d_dotS, (size_t)std::max(1, c->opS.dev.n_blocks)))) return rc;
     HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     for (auto &e : c->gev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->sync_ev, hipEventDisableTiming));
     // element data for the adjoint gradient
     {
         std::vector<double> ch(st.n_elem, 0.0);
@@ -1798,6 +1859,7 @@ int dpcg_solve(bddc_ctx *c, const double *rhs_seq, int32_t n_rhs, double rtol, d
     if (!c || (!rhs_seq && n_rhs > 0) || (!x_seq && n_rhs > 0) || n_rhs < 0 || !(rtol > 0))
         return fail(BDDC_EINVAL, "bad dpcg_solve argument");
     bool condensed = false;
+    c->pre_schur = false;
     for (int k = 0; k < n_rhs; ++k) {
         int it = 0;
         double rr = 0.0;
@@ -1809,13 +1871,21 @@ int dpcg_solve(bddc_ctx *c, const double *rhs_seq, int32_t n_rhs, double rtol, d
         // the next right-hand side is condensed while the host solves the
         // small recycling eigenproblem
         condensed = k + 1 < n_rhs;
-        if (condensed) run_condense(c, rhs_seq + (size_t)(k + 1) * c->n_nodes);
+        if (condensed) {
+            run_condense(c, rhs_seq + (size_t)(k + 1) * c->n_nodes);
+            // A x_{-1} of the next initial residual does not depend on the
+            // deflation basis: it runs ahead of the basis update as well
+            if (c->opts.init_guess == 1) launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
+            run_schur(c, c->d_x, false, false);
+            c->pre_schur = true;
+        }
         {
             TScope ts(c, TK_REC);
             rc = do_recycle(c);
         }
-        if (rc) { (void)settle(c); if (c->timing) flush_timing(c); return rc; }
+        if (rc) { c->pre_schur = false; (void)settle(c); if (c->timing) flush_timing(c); return rc; }
     }
+    c->pre_schur = false;
     int rc = settle(c);
     if (c->timing) flush_timing(c);
     return rc;
@@ -2004,6 +2074,7 @@ void bddc_destroy(bddc_ctx *c) {
     if (c->graph) (void)hipGraphDestroy(c->graph);
     for (auto &e : c->gev)
         if (e) (void)hipEventDestroy(e);
+    if (c->sync_ev) (void)hipEventDestroy(c->sync_ev);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();

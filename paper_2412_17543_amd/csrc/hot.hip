@@ -275,6 +275,14 @@ __device__ __forceinline__ void cm_matvec(const double *M, int64_t ldm, int r0, 
 }  // namespace
 
 // registers for at least 6 waves per SIMD (4 with four float64 tiles in flight)
+// A segment record, read through the constant address space: the index is
+// block-uniform, so these become scalar loads.
+__device__ __forceinline__ SymvItem load_item(const SymvItem *items, int i) {
+    typedef const __attribute__((address_space(4))) int32_t CInt;
+    CInt *q = (CInt *)(items + i);
+    return SymvItem{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], 0, 0, 0};
+}
+
 template <typename T, int U>
 constexpr int symv_waves_per_simd() { return (sizeof(T) == 8 && U == 4) ? 4 : 6; }
 
@@ -283,54 +291,74 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
     using ACC = typename Acc<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[16];
+    constexpr int NT = NW * 64;
+    constexpr int GATHER_PER_THREAD = NT >= 512 ? 1 : 512 / NT;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g4 = 4 * (l >> 4), cl = l & 15;
+    const int wu = __builtin_amdgcn_readfirstlane(w);     // wave-uniform control flow
+    // Segment records are block-uniform: read through the constant address
+    // space (scalar loads).  The first one is in flight during the control
+    // check; the gather indices and first tile stage of a segment are issued
+    // as soon as its record is there (before the stopping test for the first
+    // segment), then gathered values, then the second stage, in this order,
+    // so that waiting for the values never waits for the second stage (loads
+    // complete in issue order).  Three round trips before the first tile is
+    // used.
+    SymvItem it = load_item(a.op.items, blockIdx.x);
     if (a.gated && block_done(a.ctl)) return;
-    if (a.test && stop_test(a)) return;
+
+    // Tiles past w1 read as zero without a memory access (resource over tiles
+    // [t, w1) for the stage starting at tile t), so the loads of the next U
+    // tiles are issued unconditionally while the current U are used; two
+    // register sets in turn, so that no copy waits for a load.
+    double dot = 0.0;
     // the block's segments (consecutive pieces of the global tile sequence,
     // each inside one subdomain), one after the other
-    double dot = 0.0;
-    const int seg1 = a.op.seg_ptr[blockIdx.x + 1];
-    for (int seg = a.op.seg_ptr[blockIdx.x]; seg < seg1; ++seg) {
-        const SymvItem it = a.op.items[seg];
-        const int sub = it.sub;
-        const int n = a.op.nB[sub];
+    for (bool first = true;; first = false) {
+        const int n = it.n;
+        const T *tb = reinterpret_cast<const T *>(a.op.tiles) + (int64_t)it.tile * 256;
+        const int32_t *gb = a.op.gB + it.x_off;
+        const int span = it.t1 - it.t0;
+        const int w0 = it.t0 + (int)((int64_t)span * wu / NW);
+        const int w1 = it.t0 + (int)((int64_t)span * (wu + 1) / NW);
+        auto stage = [&](int t) {
+            return tile_rsrc(tb + (int64_t)t * 256, max(w1 - t, 0) * 256 * (int)sizeof(T));
+        };
+        int gi[GATHER_PER_THREAD];
+    #pragma unroll
+        for (int j = 0; j < GATHER_PER_THREAD; ++j) gi[j] = gb[min(tid + j * NT, max(n - 1, 0))];
+        asm volatile("" ::: "memory");                        // (keeps those loads first)
+        Frag<T> fa[U], fb[U];
+    #pragma unroll
+        for (int u = 0; u < U; ++u) fa[u].load(stage(w0), u, l);
+        if (first && a.test && stop_test(a)) return;
         const int nt = (n + TILE - 1) / TILE;
-        const int ncs = a.op.nc ? a.op.nc[sub] : 0;
+        const int ncs = it.nc;
         const int ntc = (ncs + TILE - 1) / TILE;
         const int npad = nt * TILE;
         ACC *xs = reinterpret_cast<ACC *>(smem_raw);
         ACC *yw = xs + npad;
         ACC *cw = yw + NW * npad;
-        const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g4 = 4 * (l >> 4), cl = l & 15;
-        const T *tb = reinterpret_cast<const T *>(a.op.tiles) + a.op.t_off[sub];
-        const int span = it.t1 - it.t0;
-        const int wu = __builtin_amdgcn_readfirstlane(w);     // wave-uniform control flow
-        const int w0 = it.t0 + (int)((int64_t)span * wu / NW);
-        const int w1 = it.t0 + (int)((int64_t)span * (wu + 1) / NW);
-        // Tiles past w1 read as zero without a memory access (resource over
-        // tiles [t, w1) for the stage starting at tile t), so the loads of the
-        // next U tiles are issued unconditionally while the current U are used;
-        // two register sets in turn, so that no copy waits for a load.  The first
-        // stage is in flight while the block gathers its input.
-        auto stage = [&](int t) {
-            return tile_rsrc(tb + (int64_t)t * 256, max(w1 - t, 0) * 256 * (int)sizeof(T));
-        };
-        const int32_t *gb = a.op.gB + a.op.b_off[sub];
-        const int g0 = gb[min(tid, n - 1)];                   // first gather index, ahead of the tiles
-        asm volatile("" ::: "memory");                        // (keeps that load first)
-        Frag<T> fa[U], fb[U];
+        double xv[GATHER_PER_THREAD];
     #pragma unroll
-        for (int u = 0; u < U; ++u) fa[u].load(stage(w0), u, l);
-
-        for (int k = tid; k < npad; k += NW * 64) xs[k] = k < n ? (ACC)a.x[k == tid ? g0 : gb[k]] : (ACC)0;
-        for (int k = tid; k < NW * npad; k += NW * 64) yw[k] = (ACC)0;
-        for (int k = tid; k < NW * ntc * TILE; k += NW * 64) cw[k] = (ACC)0;
+        for (int j = 0; j < GATHER_PER_THREAD; ++j) xv[j] = a.x[gi[j]];
+        asm volatile("" ::: "memory");                        // (the gathered values before fb)
+    #pragma unroll
+        for (int u = 0; u < U; ++u) fb[u].load(stage(w0 + U), u, l);
+    #pragma unroll
+        for (int j = 0; j < GATHER_PER_THREAD; ++j) {
+            const int k = tid + j * NT;
+            if (k < npad) xs[k] = k < n ? (ACC)xv[j] : (ACC)0;
+        }
+        for (int k = tid + GATHER_PER_THREAD * NT; k < npad; k += NT) xs[k] = k < n ? (ACC)a.x[gb[k]] : (ACC)0;
+        for (int k = tid; k < NW * npad; k += NT) yw[k] = (ACC)0;
+        for (int k = tid; k < NW * ntc * TILE; k += NT) cw[k] = (ACC)0;
         __syncthreads();
 
         ACC *myy = yw + wu * npad;
         ACC *myc = cw + wu * ntc * TILE;
         if (w0 >= w1) {
     #pragma unroll
-            for (int u = 0; u < U; ++u) fa[u].settle();
+            for (int u = 0; u < U; ++u) { fa[u].settle(); fb[u].settle(); }
         } else {
             int I = 0, rs = 0;
             while (rs + (nt - I + ntc) <= w0) { rs += nt - I + ntc; ++I; }
@@ -371,9 +399,8 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
                     }
                 }
             };
+            // fa holds tiles [t, t + U), fb the next U (both issued above)
             for (int t = w0;;) {
-    #pragma unroll
-                for (int u = 0; u < U; ++u) fb[u].load(stage(t + U), u, l);
                 use(fa, t);
                 t += U;
                 if (t >= w1) {
@@ -390,6 +417,8 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
                     for (int u = 0; u < U; ++u) fa[u].settle();
                     break;
                 }
+    #pragma unroll
+                for (int u = 0; u < U; ++u) fb[u].load(stage(t + U), u, l);
             }
             if (J != I) {   // flush a partly processed tile row
                 const ACC m = row_sum4(ra, cl);
@@ -398,7 +427,7 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
         }
         __syncthreads();
 
-        double *yp = a.ypart + a.op.pb[sub] + (int64_t)it.c * n;
+        double *yp = a.ypart + it.yoff;
         for (int k = tid; k < n; k += NW * 64) {
             ACC s = (ACC)0;
     #pragma unroll
@@ -408,7 +437,7 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
             dot += (double)xs[k] * y;
         }
         if (ncs) {
-            double *cp = a.cpart + a.op.cb[sub] + (int64_t)it.c * ncs;
+            double *cp = a.cpart + it.coff;
             for (int k = tid; k < ncs; k += NW * 64) {
                 ACC s = (ACC)0;
     #pragma unroll
@@ -417,6 +446,8 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
             }
         }
         __syncthreads();   // LDS is reused by the next segment
+        if (it.next < 0) break;
+        it = load_item(a.op.items, it.next);
     }
     if (a.dot) {
         dot = block_sum(dot, red);

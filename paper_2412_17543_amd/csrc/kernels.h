@@ -16,28 +16,32 @@ struct AsmDesc {
 
 // ======================================================== operator products
 // One segment of a batched symmetric product: tiles [t0, t1) of the packed
-// tile sequence of subdomain `sub`; `c` numbers the segments of that
-// subdomain.
+// tile sequence of one subdomain, whose tiles start at tile `tile` of the
+// operator array; the subdomain has n rows and nc coarse columns, and its
+// input entries are x[gB[x_off + k]], k < n.  The segment writes its partial
+// products to ypart[yoff + k] and cpart[coff + q].  Item b is the first
+// segment of block b, `next` the index of the block's next one (-1: none);
+// an empty item (t0 == t1, n == 0) does nothing.  All that a block needs to
+// start a segment is in this one record.
 struct SymvItem {
-    int32_t sub, t0, t1, c;
+    int32_t tile, t0, t1, n;
+    int32_t nc, x_off, yoff, coff;
+    int32_t next, pad0, pad1, pad2;
 };
 
 // A batch of packed symmetric operators.  Tile row I of subdomain i holds the
 // tiles (I, I..nt-1) of the upper triangle and, when `nc` is set, ntc extra
 // tiles of the coarse basis rows (I, nt..nt+ntc-1).  The concatenated tile
-// sequence of all subdomains is cut into n_blocks equal ranges, one per
-// block; block b processes segments [seg_ptr[b], seg_ptr[b+1]), the pieces of
-// its range inside single subdomains.  Segment c of subdomain i writes its
-// partial products to ypart[pb[i] + c * nB[i] + k] and, with a coarse basis,
-// cpart[cb[i] + c * nc[i] + q].
+// sequence of all subdomains is cut into n_blocks ranges, one per block, and
+// each range into segments inside single subdomains.  Segment c of
+// subdomain i writes its partial products to ypart[pb[i] + c * nB[i] + k]
+// and, with a coarse basis, cpart[cb[i] + c * nc[i] + q].
 struct OpDev {
     const void *tiles;
     const int64_t *t_off;
     const int32_t *nB, *b_off, *gB;
     const int32_t *nc;              // nullable
-    const SymvItem *items;          // segments
-    int n_items;
-    const int32_t *seg_ptr;         // n_blocks + 1
+    const SymvItem *items;          // n_blocks first segments, then the others
     int n_blocks;
     const int32_t *nchunk, *pb, *cb;
 };
@@ -233,13 +237,14 @@ struct RecArgs {                    // out[nodesI] = F_I - K_IB x_B; then u[node
     double *u;
 };
 
+// Two products of the same shape (blockIdx.y picks one): out[y] = [V1[y], V2[y]] Y.
 struct GemmArgs {
     int n;
     int64_t ld;
-    const double *V1; int k1;
-    const double *V2; int k2;
+    const double *V1[2]; int k1;
+    const double *V2[2]; int k2;
     const double *Y; int ncol, ldy;
-    double *out;
+    double *out[2];
 };
 
 struct GramArgs {

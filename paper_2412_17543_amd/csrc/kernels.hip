@@ -286,41 +286,52 @@ __global__ void __launch_bounds__(256) k_scatter_gamma(int n, const int32_t *gam
 }
 
 // ---------------------------------------------------------------------------
-// recycling: out[:, c] = sum_q V[:, q] Y[q][c] for two blocks [W, P] (and
-// [AW, AP]), column-major with leading dimension ld.  One row per thread,
-// all NC output columns in registers; Y staged in LDS 64 rows at a time and
-// read by broadcast, so every entry of V is read once.
+// recycling: out[:, c] = sum_q V[:, q] Y[q][c] with V = [V1, V2] column-major
+// (leading dimension ld); blockIdx.y selects [W, P] or [AW, AP].  One row per
+// thread, all NC output columns in registers.  Y is the same for every lane:
+// it is read through the constant address space (scalar loads, operands of
+// the FMAs straight from scalar registers), and every entry of V is read
+// once.  The loads of GEMM_CHUNK columns of V are issued together, so that a
+// wave has that many in flight.  Y rows hold ldy >= ncol entries and the
+// buffer has NC entries of slack past row m-1 (columns >= ncol are read but
+// not stored).
 // ---------------------------------------------------------------------------
+constexpr int GEMM_CHUNK = 16;
 template <int NC>
 __global__ void __launch_bounds__(256) k_recycle_gemm(GemmArgs a) {
-    __shared__ double ys[64][NC];
+    typedef const __attribute__((address_space(4))) double CD;
+    CD *Y = (CD *)a.Y;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const double *V1 = a.V1[y], *V2 = a.V2[y];
     const int m = a.k1 + a.k2;
+    const int gc = min(g, a.n - 1);          // rows past n load row n-1 and store nothing
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    for (int q0 = 0; q0 < m; q0 += 64) {
-        const int qn = min(64, m - q0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < 64 * NC; e += blockDim.x) {
-            const int q = e / NC, cc = e - q * NC;
-            ys[q][cc] = (q < qn && cc < a.ncol) ? a.Y[(size_t)(q0 + q) * a.ldy + cc] : 0.0;
-        }
-        __syncthreads();
-        if (g < a.n) {
-#pragma unroll 4
-            for (int q = 0; q < qn; ++q) {
-                const int qq = q0 + q;
-                const double v = qq < a.k1 ? a.V1[(size_t)qq * a.ld + g] : a.V2[(size_t)(qq - a.k1) * a.ld + g];
+    for (int q = 0; q < m; q += GEMM_CHUNK) {
+        double v[GEMM_CHUNK];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) acc[c] += v * ys[q][c];
+        for (int u = 0; u < GEMM_CHUNK; ++u) {
+            const int qq = min(q + u, m - 1);   // past m: a valid column, weight 0
+            const double *col = qq < a.k1 ? V1 + (size_t)qq * a.ld : V2 + (size_t)(qq - a.k1) * a.ld;
+            v[u] = col[gc];
+        }
+#pragma unroll
+        for (int u = 0; u < GEMM_CHUNK; ++u) {
+            const int qq = min(q + u, m - 1);
+            const bool live = q + u < m;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double yv = Y[(size_t)qq * a.ldy + c];
+                acc[c] += v[u] * (live ? yv : 0.0);
             }
         }
     }
     if (g < a.n) {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (c < a.ncol) a.out[(size_t)c * a.ld + g] = acc[c];
+            if (c < a.ncol) a.out[y][(size_t)c * a.ld + g] = acc[c];
     }
 }
 
@@ -564,9 +575,10 @@ void launch_scatter_gamma(int n, const int32_t *gamma, const double *x, double *
 }
 void launch_recycle_gemm(const GemmArgs &a, hipStream_t s) {
     if (a.n <= 0) return;
-    if (a.ncol <= 16) hipLaunchKernelGGL(k_recycle_gemm<16>, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
-    else if (a.ncol <= 32) hipLaunchKernelGGL(k_recycle_gemm<32>, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_recycle_gemm<64>, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
+    const dim3 grid(nblk(a.n, 256), 2);
+    if (a.ncol <= 16) hipLaunchKernelGGL(k_recycle_gemm<16>, grid, dim3(256), 0, s, a);
+    else if (a.ncol <= 32) hipLaunchKernelGGL(k_recycle_gemm<32>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_recycle_gemm<64>, grid, dim3(256), 0, s, a);
 }
 void launch_gram(const GramArgs &a, int nblocks, hipStream_t s) {
     hipLaunchKernelGGL(k_gram, dim3(nblocks), dim3(256), 0, s, a);
