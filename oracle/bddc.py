@@ -357,11 +357,19 @@ class BDDC:
     """M^{-1} of Section 3.2 on the interface problem of a ``Substructuring``."""
 
     def __init__(self, ss, weight_kind="diag", constraints=("corners", "faces"),
-                 sub_to_subregion=None, all_corners=False):
+                 sub_to_subregion=None, all_corners=False, adaptive=None):
         self.ss = ss
         self.dofs = coarse_dofs(ss, constraints, all_corners)
-        self.nC = len(self.dofs)
         self.D = weights(ss, weight_kind)
+        self.adapt_info = []
+        if adaptive is not None:
+            # Section 3.3: face DOFs from eq. eig-matrix, appended after the
+            # initial ones (adaptive = (tau, at most this many per face))
+            from .adaptive import adaptive_dofs
+            tau, per_face = adaptive
+            new, self.adapt_info = adaptive_dofs(ss, self.D, self.dofs, tau, per_face)
+            self.dofs = self.dofs + new
+        self.nC = len(self.dofs)
         # per-subdomain constraints and local saddle problems (eq. localCorr)
         self.cidx = []
         self.loc = []
@@ -411,4 +419,5 @@ class BDDC:
 
     def counts(self):
         kinds = [d["kind"] for d in self.dofs]
-        return dict(corners=kinds.count("corner"), faces=kinds.count("face"), edges=kinds.count("edge"))
+        return dict(corners=kinds.count("corner"), faces=kinds.count("face"), edges=kinds.count("edge"),
+                    adaptive=kinds.count("adaptive"))

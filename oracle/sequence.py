@@ -18,9 +18,10 @@ from .substructure import Substructuring
 class OracleSolver:
     def __init__(self, nx, elem_to_sub, coef, elem_keep=None, sub_to_subregion=None,
                  weight_kind="diag", constraints=("corners", "faces"), R=0, strategy="B4",
-                 freeze_tol=1e-5, stop="rhs", init_guess="prev", all_corners=False, reorth=False):
+                 freeze_tol=1e-5, stop="rhs", init_guess="prev", all_corners=False, reorth=False,
+                 adaptive=None):
         self.ss = Substructuring(nx, elem_to_sub, coef, elem_keep)
-        self.M = BDDC(self.ss, weight_kind, constraints, sub_to_subregion, all_corners)
+        self.M = BDDC(self.ss, weight_kind, constraints, sub_to_subregion, all_corners, adaptive)
         self.rec = Recycler(R, strategy, freeze_tol)
         self.stop = stop
         self.init_guess = init_guess

@@ -6,7 +6,8 @@ catch it is re-run and must raise.
 import numpy as np
 import pytest
 
-from oracle import bddc, q1
+from oracle import adaptive, bddc, q1
+from tests import test_oracle_adaptive as ta
 from tests import test_oracle_bddc as tb
 from tests import test_oracle_q1 as tq
 
@@ -55,3 +56,29 @@ def test_dropped_interior_correction_is_caught(monkeypatch):
     monkeypatch.setattr(Substructuring, "apply_S_local", lambda self, i, xb: self.sub[i]["KBB"] @ xb)
     with pytest.raises(AssertionError):
         tb.test_schur_equals_global_elimination()
+
+
+def test_unweighted_pair_average_is_caught(monkeypatch):
+    # E_st with plain (1/2, 1/2) averaging instead of the D weights
+    orig = adaptive.averaging_matrix
+    monkeypatch.setattr(adaptive, "averaging_matrix",
+                        lambda ss, D, s, t: orig(ss, [np.ones_like(d) for d in D], s, t))
+    with pytest.raises(AssertionError):
+        ta.test_two_subdomain_face_eigenvalue_is_the_condition_number()
+
+
+def test_missing_projection_is_caught(monkeypatch):
+    # Pi left out of the pencil (shared coarse DOFs not enforced)
+    monkeypatch.setattr(adaptive, "shared_constraints",
+                        lambda ss, dofs, s, t: np.zeros((0, ss.sub[s]["nodes_B"].size + ss.sub[t]["nodes_B"].size)))
+    with pytest.raises(AssertionError):
+        ta.test_two_subdomain_face_eigenvalue_is_the_condition_number()
+
+
+def test_wrong_side_of_the_pencil_is_caught(monkeypatch):
+    # E in place of I - E on the left-hand side of eq. eig-matrix
+    orig = adaptive.averaging_matrix
+    monkeypatch.setattr(adaptive, "averaging_matrix",
+                        lambda ss, D, s, t: np.eye(orig(ss, D, s, t).shape[0]) - orig(ss, D, s, t))
+    with pytest.raises(AssertionError):
+        ta.test_two_subdomain_face_bound(2.0)
