@@ -115,7 +115,12 @@ typedef struct {
                                 takes the default without autotuning).         */
     int32_t reorth;          /* 1: after every residual update, r -= W (W^T W)^{-1} W^T r
                                 (Alg. 1, optional re-orthogonalisation); 0: off  */
-    int32_t reserved[1];
+    int32_t adapt_max_per_face; /* adaptive coarse space (Section 3.3): at most this
+                                many new rows per face (paper: 10)                */
+    double  adapt_tau;       /* > 0: enrich every level-1 face with the eigenvectors
+                                of eq. eig-matrix whose eigenvalue exceeds tau
+                                (rows from eq. c-def restricted to the face);
+                                <= 0: off (default)                              */
 } bddc_opts;
 
 /* Fills *o with the defaults: corners+faces, diag weights, float64 local
@@ -210,6 +215,32 @@ int bddc_condense(bddc_ctx *ctx, const double *F, double *b);
  *  [14] max nB [15] total device bytes held
  */
 int bddc_info(const bddc_ctx *ctx, int64_t *info);
+
+/*
+ * bddc_adaptive_stats -- outcome of the adaptive face selection at setup,
+ * host float64 out[4]: faces examined, rows added (coarse DOFs of kind
+ * "adaptive"), largest face eigenvalue of eq. eig-matrix before enrichment,
+ * seconds spent.  All zero when adapt_tau <= 0.
+ */
+int bddc_adaptive_stats(const bddc_ctx *ctx, double *out);
+
+/*
+ * bddc_face_constraints -- one face problem of the adaptive selection in the
+ * jump space of its m shared nodes (host float64; no device work; exported so
+ * the computation can be checked on its own).  Row-major m x m inputs in the
+ * order of the shared nodes: Hs, Ht the Schur complements of S_s, S_t onto
+ * them, Ks, Kt the blocks S_s, S_t on them; Ds, Dt the interface weights;
+ * floating_s/t: subdomain without Dirichlet nodes; B (nb x m) the rows of the
+ * coarse DOFs s and t share; fpos (nf) the face's own nodes among the shared
+ * ones.  Out: lam (capacity m) the eigenvalues of eq. eig-matrix, descending,
+ * and n_lam of them; rows (capacity max_rows x nf) the new rows (orthonormal,
+ * against the face average too) of the eigenvalues above tau, n_rows of them.
+ * Errors: EINVAL (sizes), ESINGULAR (no Cholesky of H_s + H_t).
+ */
+int bddc_face_constraints(int32_t m, const double *Hs, const double *Ht, const double *Ks, const double *Kt,
+                          const double *Ds, const double *Dt, int32_t floating_s, int32_t floating_t, int32_t nb,
+                          const double *B, int32_t nf, const int32_t *fpos, double tau, int32_t max_rows,
+                          double *lam, int32_t *n_lam, double *rows, int32_t *n_rows);
 
 /* Interface node ids (host int64 out[n_gamma]) in interface-vector order. */
 int bddc_interface_nodes(const bddc_ctx *ctx, int64_t *out);

@@ -32,7 +32,7 @@ class Opts(ctypes.Structure):
                 ("stop_rule", c_int32), ("init_guess", c_int32), ("max_it", c_int32),
                 ("save_cap", c_int32), ("use_graph", c_int32), ("autotune", c_int32),
                 ("coarse_form", c_int32), ("product_cfg", c_int32 * 8),
-                ("reorth", c_int32), ("reserved", c_int32 * 1)]
+                ("reorth", c_int32), ("adapt_max_per_face", c_int32), ("adapt_tau", c_double)]
 
 
 class BddcError(RuntimeError):
@@ -58,6 +58,10 @@ SIGNATURES = {
     "bddc_ritz_values": (c_int32, [c_void_p, POINTER(c_double), c_int32, POINTER(c_int32)]),
     "bddc_tuning": (c_int32, [c_void_p, POINTER(c_double)]),
     "bddc_time_products": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
+    "bddc_adaptive_stats": (c_int32, [c_void_p, POINTER(c_double)]),
+    "bddc_face_constraints": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_double,
+                                        c_int32, c_void_p, POINTER(c_int32), c_void_p, POINTER(c_int32)]),
     "bddc_destroy": (None, [c_void_p]),
     "bddc_last_error": (c_char_p, []),
 }

@@ -9,6 +9,7 @@
 #include <numeric>
 
 #include "internal.h"
+#include "adaptive.h"
 #include "kernels.h"
 
 using namespace bddc;
@@ -151,6 +152,7 @@ struct bddc_ctx {
     double *h_hist = nullptr;       // pinned: alpha, d, rho (hist_cap each), mu (hist_cap x RMAX)
     SyncBuf *d_sync = nullptr;      // device image of SyncBuf (holds d_ctl, d_state, d_WAWsym)
     bool pre_schur = false;         // A x of the next solve's initial residual already enqueued
+    AdaptStats adapt;               // adaptive face selection at setup
     double *d_hblk = nullptr;       // device image of h_hist (holds the four histories)
     double *h_Y = nullptr;          // pinned staging of the recycling coefficients
     int hcopy = 0;
@@ -1034,6 +1036,8 @@ void bddc_default_opts(bddc_opts *o) {
     o->use_graph = 1;
     o->autotune = 1;
     o->coarse_form = 0;
+    o->adapt_max_per_face = 10;
+    o->adapt_tau = 0.0;
 }
 
 const char *bddc_last_error(void) { return g_err.c_str(); }
@@ -1286,6 +1290,81 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         c->n_cu = std::max(1, ncu);
     }
+    {
+        const int nsub = st.n_sub;
+        std::vector<int64_t> k_off(nsub + 1, 0);
+        std::vector<int32_t> nI(nsub);
+        int max_nloc = 0;
+        for (int i = 0; i < nsub; ++i) {
+            const SubHost &sh = st.sub[i];
+            nI[i] = sh.nI;
+            k_off[i + 1] = k_off[i] + (int64_t)sh.nloc * sh.nloc;
+            max_nloc = std::max(max_nloc, sh.nloc);
+        }
+        // -------------------------------------------------- local assembly
+        // K_i from the element matrices, then the interior elimination that
+        // leaves S_i in the interface block (before the coarse DOFs are final:
+        // adaptive face rows need S_i)
+        std::vector<int32_t> eloc, incp, ince, incv;
+        std::vector<double> ec;
+        std::vector<int64_t> e_off(nsub + 1, 0), ip_off(nsub + 1, 0), ie_off(nsub + 1, 0);
+        for (int i = 0; i < nsub; ++i) {
+            const SubHost &sh = st.sub[i];
+            e_off[i + 1] = e_off[i] + (int64_t)sh.elem.size();
+            ip_off[i + 1] = ip_off[i] + sh.nloc + 1;
+            ie_off[i + 1] = ie_off[i] + (int64_t)sh.inc_e.size();
+            eloc.insert(eloc.end(), sh.elem_loc.begin(), sh.elem_loc.end());
+            ec.insert(ec.end(), sh.elem_c.begin(), sh.elem_c.end());
+            incp.insert(incp.end(), sh.inc_ptr.begin(), sh.inc_ptr.end());
+            ince.insert(ince.end(), sh.inc_e.begin(), sh.inc_e.end());
+            incv.insert(incv.end(), sh.inc_v.begin(), sh.inc_v.end());
+        }
+        int32_t *d_eloc, *d_incp, *d_ince, *d_incv;
+        double *d_ec;
+        if ((rc = dupload(c, &d_eloc, eloc)) || (rc = dupload(c, &d_ec, ec)) || (rc = dupload(c, &d_incp, incp)) ||
+            (rc = dupload(c, &d_ince, ince)) || (rc = dupload(c, &d_incv, incv)))
+            return rc;
+        if ((rc = dalloc(c, &c->d_K, (size_t)k_off[nsub]))) return rc;
+        if ((rc = dalloc(c, &c->d_status, 1))) return rc;
+        HIPCHK(hipMemsetAsync(c->d_status, 0, sizeof(int32_t), s));
+        {
+            std::vector<AsmDesc> ad(nsub);
+            for (int i = 0; i < nsub; ++i) {
+                ad[i].elem_loc = d_eloc + e_off[i] * 8;
+                ad[i].elem_c = d_ec + e_off[i];
+                ad[i].inc_ptr = d_incp + ip_off[i];
+                ad[i].inc_e = d_ince + ie_off[i];
+                ad[i].inc_v = d_incv + ie_off[i];
+                ad[i].nloc = st.sub[i].nloc;
+                ad[i].K = c->d_K + k_off[i];
+            }
+            AsmDesc *dd;
+            if ((rc = dupload(c, &dd, ad))) return rc;
+            launch_assemble(dd, nsub, s);
+            // interior elimination: sweep the interior pivots of every K_i
+            std::vector<SweepDesc> sd(nsub);
+            for (int i = 0; i < nsub; ++i)
+                sd[i] = SweepDesc{c->d_K + k_off[i], st.sub[i].nloc, st.sub[i].nloc, 0, nI[i], st.sub[i].nloc};
+            SweepDesc *dsd;
+            if ((rc = dupload(c, &dsd, sd))) return rc;
+            set_sweep_smem_limit((size_t)std::max(max_nloc, 1) * 8);
+            launch_sweep(dsd, nsub, max_nloc, c->d_status, s);
+            HIPCHK(hipStreamSynchronize(s));
+            dfree(c, dd); dfree(c, dsd);
+        }
+        dfree(c, d_eloc); dfree(c, d_incp); dfree(c, d_ince); dfree(c, d_incv);
+        if (c->opts.adapt_tau > 0) {
+            // Section 3.3: enrich the level-1 faces, then every later step
+            // works with the enlarged coarse space
+            std::vector<CoarseDof> extra;
+            AdaptStats as;
+            if ((rc = adaptive_faces(st, c->d_K, k_off, c->opts.adapt_tau, std::max(0, c->opts.adapt_max_per_face),
+                                     c->d_status, s, extra, as, err)))
+                return fail(rc, err);
+            if ((rc = add_coarse_dofs(st, part, extra, err))) return fail(rc, err);
+            c->adapt = as;
+        }
+    }
     c->n_sub = st.n_sub;
     c->n_gamma = (int)st.gamma.size();
     c->nC = (int)st.coarse.size();
@@ -1357,56 +1436,6 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         c->h_casm_ptr = ptr; c->h_casm_idx = idx;
     }
 
-    // -------------------------------------------------- local assembly
-    std::vector<int32_t> eloc, incp, ince, incv;
-    std::vector<double> ec;
-    std::vector<int64_t> e_off(nsub + 1, 0), ip_off(nsub + 1, 0), ie_off(nsub + 1, 0);
-    for (int i = 0; i < nsub; ++i) {
-        const SubHost &sh = st.sub[i];
-        e_off[i + 1] = e_off[i] + (int64_t)sh.elem.size();
-        ip_off[i + 1] = ip_off[i] + sh.nloc + 1;
-        ie_off[i + 1] = ie_off[i] + (int64_t)sh.inc_e.size();
-        eloc.insert(eloc.end(), sh.elem_loc.begin(), sh.elem_loc.end());
-        ec.insert(ec.end(), sh.elem_c.begin(), sh.elem_c.end());
-        incp.insert(incp.end(), sh.inc_ptr.begin(), sh.inc_ptr.end());
-        ince.insert(ince.end(), sh.inc_e.begin(), sh.inc_e.end());
-        incv.insert(incv.end(), sh.inc_v.begin(), sh.inc_v.end());
-    }
-    int32_t *d_eloc, *d_incp, *d_ince, *d_incv;
-    double *d_ec;
-    if ((rc = dupload(c, &d_eloc, eloc)) || (rc = dupload(c, &d_ec, ec)) || (rc = dupload(c, &d_incp, incp)) ||
-        (rc = dupload(c, &d_ince, ince)) || (rc = dupload(c, &d_incv, incv)))
-        return rc;
-    if ((rc = dalloc(c, &c->d_K, (size_t)k_off[nsub]))) return rc;
-    if ((rc = dalloc(c, &c->d_status, 1))) return rc;
-    HIPCHK(hipMemsetAsync(c->d_status, 0, sizeof(int32_t), s));
-    {
-        std::vector<AsmDesc> ad(nsub);
-        for (int i = 0; i < nsub; ++i) {
-            ad[i].elem_loc = d_eloc + e_off[i] * 8;
-            ad[i].elem_c = d_ec + e_off[i];
-            ad[i].inc_ptr = d_incp + ip_off[i];
-            ad[i].inc_e = d_ince + ie_off[i];
-            ad[i].inc_v = d_incv + ie_off[i];
-            ad[i].nloc = st.sub[i].nloc;
-            ad[i].K = c->d_K + k_off[i];
-        }
-        AsmDesc *dd;
-        if ((rc = dupload(c, &dd, ad))) return rc;
-        launch_assemble(dd, nsub, s);
-        // interior elimination: sweep the interior pivots of every K_i
-        std::vector<SweepDesc> sd(nsub);
-        for (int i = 0; i < nsub; ++i)
-            sd[i] = SweepDesc{c->d_K + k_off[i], st.sub[i].nloc, st.sub[i].nloc, 0, nI[i], st.sub[i].nloc};
-        SweepDesc *dsd;
-        if ((rc = dupload(c, &dsd, sd))) return rc;
-        set_sweep_smem_limit((size_t)std::max({max_nloc, max_sad, 1}) * 8);
-        launch_sweep(dsd, nsub, max_nloc, c->d_status, s);
-        HIPCHK(hipStreamSynchronize(s));
-        dfree(c, dd); dfree(c, dsd);
-    }
-    dfree(c, d_eloc); dfree(c, d_incp); dfree(c, d_ince); dfree(c, d_incv);
-
     // -------------------------------------------------- constrained Neumann operators
     std::vector<int32_t> cptr, ccol;
     std::vector<double> cval, wB;
@@ -1439,6 +1468,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         SweepDesc *dwd;
         if ((rc = dupload(c, &dsd, sd)) || (rc = dupload(c, &dwd, wd))) return rc;
         launch_build_saddle(dsd, nsub, s);
+        set_sweep_smem_limit((size_t)std::max(max_sad, 1) * 8);
         launch_sweep(dwd, nsub, max_sad, c->d_status, s);
         // tiles: S_i (float64) and D N_i D with D Phi_i (local precision), plus
         // the row-major D Phi_i for the prolongation
@@ -1988,6 +2018,36 @@ int bddc_info(const bddc_ctx *c, int64_t *info) {
     info[13] = (int64_t)c->bytes_N;
     info[14] = c->max_nB;
     info[15] = (int64_t)c->dev_bytes;
+    return 0;
+}
+
+int bddc_adaptive_stats(const bddc_ctx *c, double *out) {
+    if (!c || !out) return fail(BDDC_EINVAL, "null argument");
+    out[0] = c->adapt.faces;
+    out[1] = c->adapt.added;
+    out[2] = c->adapt.lam_max;
+    out[3] = c->adapt.seconds;
+    return 0;
+}
+
+int bddc_face_constraints(int32_t m, const double *Hs, const double *Ht, const double *Ks, const double *Kt,
+                          const double *Ds, const double *Dt, int32_t floating_s, int32_t floating_t, int32_t nb,
+                          const double *B, int32_t nf, const int32_t *fpos, double tau, int32_t max_rows,
+                          double *lam, int32_t *n_lam, double *rows, int32_t *n_rows) {
+    if (m < 0 || nb < 0 || nf < 0 || max_rows < 0 || !n_lam || !n_rows || (m > 0 && (!Hs || !Ht || !Ks || !Kt || !Ds || !Dt || !lam)) ||
+        (nb > 0 && !B) || (nf > 0 && !fpos) || (max_rows > 0 && nf > 0 && !rows))
+        return fail(BDDC_EINVAL, "bad bddc_face_constraints argument");
+    for (int q = 0; q < nf; ++q)
+        if (fpos[q] < 0 || fpos[q] >= m) return fail(BDDC_EINVAL, "face position out of range");
+    FaceInput in{m, Hs, Ht, Ks, Kt, Ds, Dt, floating_s != 0, floating_t != 0, nb, B, nf, fpos};
+    FaceOutput out;
+    int rc = face_rows(in, tau, max_rows, out);
+    if (rc) return fail(rc, "face problem: no Cholesky factor of H_s + H_t");
+    *n_lam = (int32_t)out.lam.size();
+    for (size_t i = 0; i < out.lam.size(); ++i) lam[i] = out.lam[i];
+    *n_rows = (int32_t)out.rows.size();
+    for (size_t r = 0; r < out.rows.size(); ++r)
+        for (int q = 0; q < nf; ++q) rows[r * nf + q] = out.rows[r][q];
     return 0;
 }
 

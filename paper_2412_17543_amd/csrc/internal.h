@@ -22,9 +22,10 @@ constexpr int VGRID = 512;        // blocks of the grid-stride vector kernels (m
 // host-side structure built from mesh + partition (partition.cpp)
 // ---------------------------------------------------------------------------
 struct CoarseDof {
-    int kind;                      // 0 corner, 1 face, 2 edge
+    int kind;                      // 0 corner, 1 face, 2 edge, 3 adaptive face row
     std::vector<int64_t> nodes;    // free nodes (sorted)
     std::vector<int32_t> subs;     // subdomains sharing it (sorted)
+    std::vector<double> wts;       // row over `nodes`; empty: the average 1/|nodes|
 };
 
 struct SubHost {
@@ -61,7 +62,7 @@ struct Structure {
     int n_sub = 0;
     std::vector<SubHost> sub;
     std::vector<CoarseDof> coarse;
-    int n_corner = 0, n_face = 0, n_edge = 0;
+    int n_corner = 0, n_face = 0, n_edge = 0, n_adaptive = 0;
     // level 2 (three-level BDDC)
     bool three = false;
     int n_sr = 0;
@@ -74,6 +75,9 @@ struct Structure {
 
 int build_structure(const bddc_mesh *m, const bddc_partition *p, const double *coef,
                     const bddc_opts *o, Structure &st, std::string &err);
+int constraint_rows(Structure &st, std::string &err);
+int build_level2(Structure &st, const bddc_partition *p, std::string &err);
+int add_coarse_dofs(Structure &st, const bddc_partition *p, const std::vector<CoarseDof> &extra, std::string &err);
 
 // host dense helpers (hostla.cpp)
 bool cholesky(std::vector<double> &a, int n);                       // in place, lower

@@ -7,6 +7,17 @@
 namespace bddc {
 
 // ============================================================ setup kernels
+// Schur complement of one subdomain's interface Schur complement S onto a
+// subset of its interface entries (adaptive face selection, Section 3.3):
+// W = S(perm, perm) with the p entries to eliminate first; keep = W(p:, p:)
+// before and hat = W(p:, p:) after eliminating them (m = n - p).
+struct FaceSchurDesc {
+    const double *S; int ld;
+    const int32_t *perm; int n, p;
+    double *work;                  // n x n scratch
+    double *hat, *keep;            // m x m each, row-major
+};
+
 struct AsmDesc {
     const int32_t *elem_loc; const double *elem_c;
     const int32_t *inc_ptr, *inc_e, *inc_v;
@@ -283,6 +294,7 @@ struct GradArgs {
 // setup (kernels.hip)
 void launch_assemble(const AsmDesc *d, int n, hipStream_t s);
 void launch_sweep(const SweepDesc *d, int n, int maxn, int *status, hipStream_t s);
+void launch_face_schur(const FaceSchurDesc *d, int n, int maxn, int *status, hipStream_t s);
 void set_sweep_smem_limit(size_t bytes);
 void launch_build_saddle(const SaddleDesc *d, int n, hipStream_t s);
 void launch_pack(const PackDesc *d, int n, int prec, void *dst, void *phir, hipStream_t s);

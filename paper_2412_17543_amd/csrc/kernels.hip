@@ -79,6 +79,43 @@ __global__ void __launch_bounds__(1024) k_sweep(const SweepDesc *descs, int *sta
 }
 
 // ---------------------------------------------------------------------------
+// setup: Schur complement onto the last m = n - p entries of a permuted copy
+// of S (symmetric positive semi-definite, positive definite on the p leading
+// entries): symmetric Gaussian elimination of the leading p pivots, each
+// updating only the trailing rows and columns.  One block per descriptor.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_face_schur(const FaceSchurDesc *descs, int *status) {
+    extern __shared__ double row[];
+    const FaceSchurDesc d = descs[blockIdx.x];
+    const int n = d.n, p = d.p, m = n - p;
+    double *W = d.work;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int i = w; i < n; i += nw) {
+        const double *src = d.S + (size_t)d.perm[i] * d.ld;
+        for (int j = l; j < n; j += 64) W[(size_t)i * n + j] = src[d.perm[j]];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) d.keep[e] = W[(size_t)(p + e / m) * n + p + e % m];
+    for (int k = 0; k < p; ++k) {
+        for (int j = k + threadIdx.x; j < n; j += blockDim.x) row[j] = W[(size_t)k * n + j];
+        __syncthreads();
+        const double piv = row[k];
+        if (!(piv > 0.0 && isfinite(piv))) {
+            if (threadIdx.x == 0) atomicMax(status, 2);
+            return;
+        }
+        const double inv = 1.0 / piv;
+        for (int i = k + 1 + w; i < n; i += nw) {
+            double *Wi = W + (size_t)i * n;
+            const double f = row[i] * inv;         // W(i, k) = W(k, i) by symmetry
+            for (int j = k + 1 + l; j < n; j += 64) Wi[j] -= f * row[j];
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) d.hat[e] = W[(size_t)(p + e / m) * n + p + e % m];
+}
+
+// ---------------------------------------------------------------------------
 // setup: saddle matrix [S + C^T Om C, C^T; C, 0] of eq. localCorr in Schur form.
 // The augmentation C^T Om C does not change the (1,1) and (1,2) blocks of the
 // inverse on the constrained subspace and makes the leading block SPD for
@@ -536,6 +573,13 @@ void launch_assemble(const AsmDesc *d, int n, hipStream_t s) {
 }
 void launch_sweep(const SweepDesc *d, int n, int maxn, int *status, hipStream_t s) {
     hipLaunchKernelGGL(k_sweep, dim3(n), dim3(1024), (size_t)maxn * sizeof(double), s, d, status);
+}
+void launch_face_schur(const FaceSchurDesc *d, int n, int maxn, int *status, hipStream_t s) {
+    if (n <= 0) return;
+    if ((size_t)maxn * sizeof(double) > 65536)
+        (void)hipFuncSetAttribute((const void *)k_face_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(maxn * sizeof(double)));
+    hipLaunchKernelGGL(k_face_schur, dim3(n), dim3(1024), (size_t)maxn * sizeof(double), s, d, status);
 }
 void set_sweep_smem_limit(size_t bytes) {
     if (bytes > 65536)

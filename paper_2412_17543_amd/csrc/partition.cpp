@@ -256,27 +256,57 @@ int build_structure(const bddc_mesh *m, const bddc_partition *p, const double *c
         }
         for (int32_t n : sh.nodes) pos[n] = -1;
     }
-    // coarse DOFs per subdomain and constraint rows
+    (void)nC;
+    int rc = constraint_rows(st, err);
+    if (rc) return rc;
+    return build_level2(st, p, err);
+}
+
+
+// Coarse DOFs of every subdomain (ascending) and its constraint rows over
+// interface-local indices: the DOF's weights, or 1/|nodes| for an average
+// (one node: a corner value).
+int constraint_rows(Structure &st, std::string &err) {
+    const int nC = (int)st.coarse.size();
+    std::vector<int32_t> pos(st.n_nodes, -1);
+    for (auto &sh : st.sub) {
+        sh.cidx.clear();
+        sh.c_ptr.clear();
+        sh.c_col.clear();
+        sh.c_val.clear();
+    }
     for (int c = 0; c < nC; ++c)
         for (int32_t s : st.coarse[c].subs) st.sub[s].cidx.push_back(c);
-    for (int i = 0; i < nsub; ++i) {
+    for (int i = 0; i < st.n_sub; ++i) {
         SubHost &sh = st.sub[i];
         for (int k = 0; k < sh.nB; ++k) pos[sh.nodes[sh.nI + k]] = k;
         sh.c_ptr.assign(1, 0);
         for (int32_t c : sh.cidx) {
             const CoarseDof &d = st.coarse[c];
-            double w = 1.0 / (double)d.nodes.size();
-            for (int64_t n : d.nodes) {
+            const double w = 1.0 / (double)d.nodes.size();
+            for (size_t q = 0; q < d.nodes.size(); ++q) {
+                const int64_t n = d.nodes[q];
                 if (pos[n] < 0) { err = "coarse DOF outside its subdomain interface"; return BDDC_EINVAL; }
                 sh.c_col.push_back(pos[n]);
-                sh.c_val.push_back(w);
+                sh.c_val.push_back(d.wts.empty() ? w : d.wts[q]);
             }
             sh.c_ptr.push_back((int32_t)sh.c_col.size());
         }
         for (int k = 0; k < sh.nB; ++k) pos[sh.nodes[sh.nI + k]] = -1;
     }
+    return BDDC_OK;
+}
 
-    // ---------------------------------------------------------------- level 2
+// Level-2 structure (three levels): subregion DOF lists, level-2 interface,
+// globs, corners and face averages (the level-3 unknowns), constraint rows.
+int build_level2(Structure &st, const bddc_partition *p, std::string &err) {
+    const int nC = (int)st.coarse.size();
+    const int nsub = st.n_sub;
+    st.sr.clear();
+    st.gamma2.clear();
+    st.dof3_members.clear();
+    st.dof3_subs.clear();
+    st.n3 = st.n3_corner = st.n3_face = 0;
     st.three = p->n_subregion > 0;
     if (!st.three) return BDDC_OK;
     const int nsr = p->n_subregion;
@@ -369,6 +399,17 @@ int build_structure(const bddc_mesh *m, const bddc_partition *p, const double *c
         for (int k = 0; k < r.nB; ++k) posL[r.L[r.nI + k]] = -1;
     }
     return BDDC_OK;
+}
+
+// Appends coarse DOFs (adaptive face rows, Section 3.3) and rebuilds every
+// subdomain's constraint rows and the level-2 structure.
+int add_coarse_dofs(Structure &st, const bddc_partition *p, const std::vector<CoarseDof> &extra, std::string &err) {
+    if (extra.empty()) return BDDC_OK;
+    st.coarse.insert(st.coarse.end(), extra.begin(), extra.end());
+    st.n_adaptive += (int)extra.size();
+    int rc = constraint_rows(st, err);
+    if (rc) return rc;
+    return build_level2(st, p, err);
 }
 
 }  // namespace bddc

@@ -34,7 +34,7 @@ class Solver:
                  weights="diag", constraints=("corners", "faces"), stop_rule="rhs",
                  init_guess="prev", max_it=1000, save_cap=256, freeze_tol=1e-5,
                  use_graph=True, autotune=True, coarse_form="auto", product_cfg=None, reorth=False,
-                 device="cuda", stream=None):
+                 adapt_tau=0.0, adapt_max_per_face=10, device="cuda", stream=None):
         lib = _lib.load()
         self.lib = lib
         self.device = torch.device(device)
@@ -80,6 +80,8 @@ class Solver:
         o.autotune = 1 if autotune else 0
         o.coarse_form = {"auto": 0, "chain": 1, "explicit": 2}[coarse_form]
         o.reorth = 1 if reorth else 0
+        o.adapt_tau = float(adapt_tau)
+        o.adapt_max_per_face = int(adapt_max_per_face)
         if product_cfg is not None:
             assert len(product_cfg) == 8
             for i, v in enumerate(product_cfg):
@@ -102,6 +104,13 @@ class Solver:
         a = (ctypes.c_int64 * 16)()
         check(self.lib.bddc_info(self.ctx, a))
         return dict(zip(self.INFO_KEYS, list(a)))
+
+    def adaptive_stats(self) -> dict:
+        """Adaptive face selection at setup (Section 3.3): faces examined, rows
+        added, largest face eigenvalue before enrichment, seconds."""
+        a = (ctypes.c_double * 4)()
+        check(self.lib.bddc_adaptive_stats(self.ctx, a))
+        return dict(faces=int(a[0]), added=int(a[1]), lam_max=float(a[2]), seconds=float(a[3]))
 
     def interface_nodes(self) -> np.ndarray:
         a = (ctypes.c_int64 * self.n_gamma)()

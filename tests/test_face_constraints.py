@@ -1,0 +1,112 @@
+"""The library's face problem of adaptive BDDC (Section 3.3, worked in the jump
+space of the shared nodes, host code behind bddc_face_constraints) against
+the oracle's full pair-space pencil of eq. eig-matrix and its rows from
+eq. c-def: same eigenvalues, same spans of new rows.  CPU only (no device work).
+"""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import workload
+from oracle import adaptive as ad
+from oracle.bddc import coarse_dofs, weights
+from oracle.substructure import Substructuring
+from tests.test_oracle_adaptive import channel_problem
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2412_17543_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2412_17543_amd.build import build
+        build()
+    return _lib.load()
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def native_face(lib, ss, D, dofs, face, S, tau, max_rows):
+    s, t = face["subs"]
+    shared, ps, pt = ad.pair_maps(ss, s, t)
+    m = shared.size
+    def schur_onto(i, pos):
+        rest = np.setdiff1d(np.arange(S[i].shape[0]), pos)
+        A = S[i]
+        H = A[np.ix_(pos, pos)]
+        if rest.size:
+            H = H - A[np.ix_(pos, rest)] @ np.linalg.solve(A[np.ix_(rest, rest)], A[np.ix_(rest, pos)])
+        return np.ascontiguousarray(0.5 * (H + H.T)), np.ascontiguousarray(A[np.ix_(pos, pos)])
+    Hs, Ks = schur_onto(s, ps)
+    Ht, Kt = schur_onto(t, pt)
+    Ds, Dt = np.ascontiguousarray(D[s][ps]), np.ascontiguousarray(D[t][pt])
+    rows = []
+    for d in dofs:
+        if s in d["subs"] and t in d["subs"]:
+            r = np.zeros(m)
+            r[np.searchsorted(shared, d["nodes"])] = d["wts"]
+            rows.append(r)
+    B = np.ascontiguousarray(np.array(rows).reshape(len(rows), m))
+    fpos = np.ascontiguousarray(np.searchsorted(shared, face["nodes"]).astype(np.int32))
+    floating = [not ss.dir[ss.en[ss.sub[i]["elems"]]].any() for i in (s, t)]
+    lam = np.zeros(m)
+    out = np.zeros(max(max_rows, 1) * fpos.size)
+    nl, nr = ctypes.c_int32(), ctypes.c_int32()
+    rc = lib.bddc_face_constraints(m, _p(Hs), _p(Ht), _p(Ks), _p(Kt), _p(Ds), _p(Dt), int(floating[0]),
+                                   int(floating[1]), B.shape[0], _p(B), fpos.size, _p(fpos), tau, max_rows,
+                                   _p(lam), ctypes.byref(nl), _p(out), ctypes.byref(nr))
+    assert rc == 0, lib.bddc_last_error()
+    return lam[: nl.value], out[: nr.value * fpos.size].reshape(nr.value, fpos.size)
+
+
+def fpos_size(face):
+    return face["nodes"].size
+
+
+def _check(lib, ss, tau, max_rows=10, faces=None):
+    D = weights(ss, "diag")
+    dofs = coarse_dofs(ss)
+    S = [ss.dense_S(i) for i in range(ss.n_sub)]
+    new, info = ad.adaptive_dofs(ss, D, dofs, tau, max_rows, S_dense=S)
+    fdofs = [d for d in dofs if d["kind"] == "face"]
+    seen = 0
+    for k, face in enumerate(fdofs):
+        if faces is not None and k not in faces:
+            continue
+        lam, rows = native_face(lib, ss, D, dofs, face, S, tau, max_rows)
+        lam_o = info[k]["lam"]
+        # the jump-space spectrum is the pair-space one without its zeros
+        np.testing.assert_allclose(lam, lam_o[: lam.size], rtol=1e-8, atol=1e-9 * lam_o[0])
+        np.testing.assert_allclose(lam_o[lam.size:], 0.0, atol=1e-9 * lam_o[0])
+        ro = np.array([d["wts"] for d in new if d["subs"] == face["subs"]]).reshape(-1, fpos_size(face))
+        assert ro.shape[0] == rows.shape[0] == info[k]["added"]
+        if rows.shape[0]:
+            # equal eigenvalues leave the rows free inside their eigenspace:
+            # compare the spans (both sets orthonormal): all cosines 1
+            sv = np.linalg.svd(rows @ ro.T, compute_uv=False)
+            np.testing.assert_allclose(sv, 1.0, atol=1e-7)
+        seen += rows.shape[0]
+    return seen
+
+
+def test_two_subdomains_channels(lib):
+    assert _check(lib, channel_problem(right=0.1), tau=2.0, max_rows=20) >= 4
+
+
+def test_eight_subdomains_lognormal(lib):
+    s = workload.workload("tiny")
+    coef = np.exp(2.0 * np.random.default_rng(5).standard_normal(s["nx"] ** 3))
+    ss = Substructuring(s["nx"], s["elem_to_sub"], coef)
+    assert _check(lib, ss, tau=2.0) > 0
+
+
+def test_argument_errors(lib):
+    z = np.zeros(4)
+    nl, nr = ctypes.c_int32(), ctypes.c_int32()
+    fpos = np.array([5], dtype=np.int32)
+    rc = lib.bddc_face_constraints(2, _p(z), _p(z), _p(z), _p(z), _p(z), _p(z), 0, 0, 0, None, 1, _p(fpos), 1.0, 1,
+                                   _p(z), ctypes.byref(nl), _p(z), ctypes.byref(nr))
+    assert rc != 0 and b"range" in lib.bddc_last_error()

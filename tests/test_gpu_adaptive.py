@@ -1,0 +1,100 @@
+"""GPU tests of the adaptive coarse space (Section 3.3) through the C ABI,
+against the oracle's pair-space reading of eqs. eig-matrix and c-def.
+
+The new rows are unique only up to their span (equal eigenvalues, signs), but
+BDDC depends on the constraint rows only through the space of functions whose
+coarse DOFs are continuous; so the preconditioners must agree as linear
+operators (1e-9 relative on M r) and the solves as in the other parity tests
+(rtol 1e-10: iterations within +-1, solution within 1e-9).
+"""
+import numpy as np
+import pytest
+
+import workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _pair(name, coef, tau, **kw):
+    from oracle.sequence import OracleSolver
+    from paper_2412_17543_amd.solver import Solver
+    s = workload.workload(name)
+    keep = s.get("elem_keep")
+    print("[gpu] adaptive setup %s tau %g" % (name, tau), flush=True)
+    g = Solver(s["nx"], s["elem_to_sub"], coef, sub_to_subregion=s["sub_to_subregion"], elem_keep=keep,
+               adapt_tau=tau, **kw)
+    o = OracleSolver(s["nx"], s["elem_to_sub"], coef, sub_to_subregion=s["sub_to_subregion"], elem_keep=keep,
+                     adaptive=(tau, 10), R=kw.get("R", 0))
+    return s, g, o
+
+
+def _precond_parity(torch, g, o, n=2):
+    rng = np.random.default_rng(11)
+    for _ in range(n):
+        r = rng.standard_normal(o.ss.n_gamma)
+        z = g.apply_precond(torch.tensor(r, device="cuda")).cpu().numpy()
+        assert _rel(z, o.M.apply(r)) < 1e-9
+
+
+def test_three_level_enriched_faces_match_oracle():
+    torch = _torch()
+    coef = np.exp(2.5 * np.random.default_rng(7).standard_normal(16 ** 3))
+    s, g, o = _pair("tiny3", coef, 10.0)
+    st = g.adaptive_stats()
+    print("[gpu] tiny3 adaptive", st, o.M.counts(), flush=True)
+    assert st["added"] == o.M.counts()["adaptive"] > 0
+    assert st["faces"] == len(o.M.adapt_info)
+    np.testing.assert_allclose(st["lam_max"], max(i["lam"][0] for i in o.M.adapt_info), rtol=1e-8)
+    assert g.info()["n_coarse"] == o.M.nC
+    _precond_parity(torch, g, o)
+
+
+def test_two_level_enriched_sequence_matches_oracle():
+    torch = _torch()
+    coef = np.exp(2.0 * np.random.default_rng(5).standard_normal(8 ** 3))
+    s, g, o = _pair("tiny", coef, 2.0, R=4)
+    assert g.adaptive_stats()["added"] == o.M.counts()["adaptive"] > 0
+    _precond_parity(torch, g, o)
+    F = workload.rhs_sequence(8, 3)
+    U, its, rr = g.solve_sequence(torch.tensor(F, device="cuda"), 1e-10)
+    uo, ito, _ = o.solve_sequence(F, 1e-10)
+    print("[gpu] tiny adaptive iters gpu %s oracle %s" % (its.tolist(), ito.tolist()), flush=True)
+    assert np.all(np.abs(its - ito) <= 1)
+    assert np.all(rr < 1e-10)
+    for k in range(len(F)):
+        assert _rel(U[k].cpu().numpy(), uo[k]) <= 1e-9
+
+
+def test_uneven_partition_with_hole_enriched():
+    torch = _torch()
+    s = workload.workload("c3s")
+    coef = s["coef"] * np.exp(1.5 * np.random.default_rng(3).standard_normal(s["nx"] ** 3))
+    s, g, o = _pair("c3s", coef, 4.0)
+    st = g.adaptive_stats()
+    print("[gpu] c3s adaptive", st, o.M.counts(), flush=True)
+    assert st["added"] == o.M.counts()["adaptive"] > 0
+    _precond_parity(torch, g, o)
+
+
+def test_threshold_above_every_eigenvalue_changes_nothing():
+    torch = _torch()
+    from paper_2412_17543_amd.solver import Solver
+    s = workload.workload("tiny")
+    coef = np.exp(np.random.default_rng(2).standard_normal(8 ** 3))
+    g0 = Solver(s["nx"], s["elem_to_sub"], coef)
+    g1 = Solver(s["nx"], s["elem_to_sub"], coef, adapt_tau=1e12)
+    assert g1.adaptive_stats()["added"] == 0 and g1.adaptive_stats()["faces"] == 12
+    r = torch.tensor(np.random.default_rng(4).standard_normal(g0.n_gamma), device="cuda")
+    assert _rel(g1.apply_precond(r).cpu().numpy(), g0.apply_precond(r).cpu().numpy()) < 1e-14
