@@ -107,6 +107,76 @@ def cpu_baseline(s, F_np, n_sample):
                        "as on the GPU), float64 NumPy/SciPy, one thread" % n_sample)
 
 
+def _rhs_chunk(job):
+    import workload
+    nx, first, n = job
+    return workload.rhs_sequence(nx, n, None, first=first)
+
+
+def run_large(args):
+    """192^3 (13,824 subdomains): the float32-Neumann form with adaptive faces
+    and R = 40, on the leading right-hand sides of the sequence."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    import workload
+    s = workload.workload("c192")
+    n_rhs = args.n_rhs or s["n_rhs"]
+    t0 = time.perf_counter()
+    chunk = max(1, (n_rhs + 15) // 16)
+    jobs = [(s["nx"], k, min(chunk, n_rhs - k)) for k in range(0, n_rhs, chunk)]
+    # worker processes (CPU only) are started before this process touches the GPU
+    with ProcessPoolExecutor(max_workers=min(16, len(jobs))) as ex:
+        parts = list(ex.map(_rhs_chunk, jobs))
+    import torch
+
+    from paper_2412_17543_amd.solver import Solver
+    F = torch.cat([torch.tensor(a, device="cuda") for a in parts])
+    del parts
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    print("[bench] c192: %d right-hand sides generated in %.1f s" % (n_rhs, gen_s), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"], R=s["R"],
+               local_prec=32, adapt_tau=10.0, adapt_max_per_face=10)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print("[bench] c192: setup %.1f s" % setup_s, file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        g.reset_recycle()
+        g.solve_sequence(F, args.rtol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.reset_recycle()
+        U, its, rr = g.solve_sequence(F, args.rtol)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info = g.info()
+    line = {
+        "metric": "solves/s to FP64 rtol 1e-8, BDDC-DPCG with adaptive faces, 1 GPU",
+        "value": round(n_rhs * args.steps / el, 3),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (float32 Neumann operators)", "data": "synthetic",
+        "config": {"workload": "Q1 Poisson 192^3 elements (7,189,057 nodes), 13,824 subdomains of 8^3, three-level "
+                               "BDDC (1,728 subregions), adaptive faces tau 10 (at most 10 per face), float32 N_i "
+                               "and Phi_i, deflated PCG B4 R=40, drifting-Gaussian right-hand sides, rtol 1e-8",
+                   "n_rhs": n_rhs, "n_gamma": info["n_gamma"], "rtol": args.rtol},
+        "iters": its_fmt(its.tolist()),
+        "max_true_relres": float(rr.max()),
+        "s_per_sequence": round(el / args.steps, 4),
+        "setup_s": round(setup_s, 2),
+        "adaptive": g.adaptive_stats(),
+        "coarse": {k: info[k] for k in ("n_coarse", "corners", "faces", "level2_interface", "level3")},
+        "device_gb": round(info["device_bytes"] / 1e9, 2),
+        "rhs_generation_s": round(gen_s, 1),
+        "tuning": g.tuning(),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,9 +187,12 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (kernel-by-kernel) FP64 form")
     ap.add_argument("--cpu-sample", type=int, default=2)
-    ap.add_argument("--workload", default="c64", choices=("c64", "c3", "c96"),
+    ap.add_argument("--workload", default="c64", choices=("c64", "c3", "c96", "c192"),
                     help="c64: 64^3 cube lattice (the headline configuration); c3: 64^3 with a spherical "
-                         "hole, 400 uneven RCB subdomains, log-normal coefficients")
+                         "hole, 400 uneven RCB subdomains, log-normal coefficients; c192: 192^3, 13,824 "
+                         "subdomains, adaptive faces (tau 10), float32 Neumann operators, R = 40 (its own "
+                         "line: the float32 form only)")
+    ap.add_argument("--n-rhs", type=int, default=0, help="use the first N right-hand sides of the sequence")
     ap.add_argument("--bf16", action="store_true", help="also run the bfloat16 Neumann-operator form")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the adjoint gradient of L = sum_k ||u_k - t_k||^2 (t_k = 0.9 u_k): one adjoint "
@@ -135,6 +208,9 @@ def main():
         print("bench.py measures the single-GPU path only (one process, one MI355X); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c192":
+        return run_large(args)
 
     import numpy as np
     import torch
@@ -203,6 +279,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload],
                    "n_rhs": n_rhs, "n_gamma": f64["info"]["n_gamma"], "rtol": args.rtol},
         "iters": its_fmt(f64["its"].tolist()),
+        "basis": {"columns": int(f64["info"]["deflation_cols"]), "frozen": bool(f64["info"]["frozen"])},
         "max_true_relres": float(f64["rr"].max()),
         "s_per_sequence": round(f64["elapsed"] / args.steps, 4),
         "setup_s": round(f64["setup_s"], 3),

@@ -225,7 +225,7 @@ class _LocalSaddle:
 class Level2:
     """M_2^{-1} approximating K_C^{-1}: BDDC with subdomains as elements."""
 
-    def __init__(self, n_coarse, S1, is_corner, KC_loc, cidx, sub_to_subregion):
+    def __init__(self, n_coarse, S1, is_corner, KC_loc, cidx, sub_to_subregion, is_adaptive=None):
         self.nC = n_coarse
         s2r = np.asarray(sub_to_subregion)
         self.n_sr = int(s2r.max()) + 1
@@ -258,10 +258,15 @@ class Level2:
         Adj.setdiag(0)
         Adj.eliminate_zeros()
         self.adj = Adj
+        # adaptive face rows (Section 3.3) stay out of the level-2 globs: each
+        # one on the level-2 interface is a level-3 unknown of its own, so the
+        # operator does not depend on the rows' signs or on their basis
+        adaptive = np.zeros(n_coarse, bool) if is_adaptive is None else np.asarray(is_adaptive, bool)
         keyid = {}
         key = -np.ones(n_coarse, dtype=np.int64)
         for c in self.gamma2:
-            key[c] = keyid.setdefault(S2[c], len(keyid))
+            if not adaptive[c]:
+                key[c] = keyid.setdefault(S2[c], len(keyid))
         Ac = Adj.tocoo()
         m = (key[Ac.row] >= 0) & (key[Ac.row] == key[Ac.col])
         Gg = sp.coo_matrix((np.ones(m.sum()), (Ac.row[m], Ac.col[m])), shape=(n_coarse, n_coarse))
@@ -269,7 +274,8 @@ class Level2:
         glob = np.where(key >= 0, lab, -1)
         members = {}
         for c in self.gamma2:
-            members.setdefault(int(glob[c]), []).append(int(c))
+            if not adaptive[c]:
+                members.setdefault(int(glob[c]), []).append(int(c))
         # level-2 coarse DOFs (level-3 unknowns)
         dofs3 = []
         for c in self.gamma2:
@@ -283,6 +289,9 @@ class Level2:
             if any(set(S2[c]) < set(S2[mm]) for mm in nb):
                 continue
             dofs3.append(dict(kind="corner", dofs=np.array([c]), wts=np.array([1.0]), subs=S2[c]))
+        for c in self.gamma2:
+            if adaptive[c]:
+                dofs3.append(dict(kind="adaptive", dofs=np.array([c]), wts=np.array([1.0]), subs=S2[c]))
         for g, mem in members.items():
             if len(S2[mem[0]]) != 2:
                 continue
@@ -375,6 +384,7 @@ class BDDC:
         self.loc = []
         S1 = [d["subs"] for d in self.dofs]
         is_corner = np.array([d["kind"] == "corner" for d in self.dofs], dtype=bool)
+        is_adaptive = np.array([d["kind"] == "adaptive" for d in self.dofs], dtype=bool)
         for i, d in enumerate(ss.sub):
             posB = {int(v): k for k, v in enumerate(d["nodes_B"])}
             ci = [k for k, cd in enumerate(self.dofs) if i in cd["subs"]]
@@ -387,7 +397,7 @@ class BDDC:
         KC_loc = [s.KC for s in self.loc]
         self.three_level = sub_to_subregion is not None
         if self.three_level:
-            self.level2 = Level2(self.nC, S1, is_corner, KC_loc, self.cidx, sub_to_subregion)
+            self.level2 = Level2(self.nC, S1, is_corner, KC_loc, self.cidx, sub_to_subregion, is_adaptive)
         else:
             KC = np.zeros((self.nC, self.nC))
             for i, s in enumerate(self.loc):

@@ -477,6 +477,7 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
         a.ctl = c->d_ctl;
         a.gated = gated ? 1 : 0;
         a.test = test;
+        a.defer = test ? 1 : 0;          // k_pupd tests instead while the basis records
         a.stop_rule = c->opts.stop_rule;
         a.max_it = c->opts.max_it;
         a.rr_part = c->d_rr; a.rr_n = c->vgrid;
@@ -524,7 +525,7 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
     }
 }
 
-void run_pupd(bddc_ctx *c, bool first, bool hist_only, bool gated) {
+void run_pupd(bddc_ctx *c, bool first, bool hist_only, bool gated, int test) {
     TScope ts(c, TK_VEC);
     PupdArgs a{};
     a.n = c->n_gamma; a.z = c->d_z; a.p = c->d_p; a.W = c->d_W; a.ld = c->ld;
@@ -534,6 +535,9 @@ void run_pupd(bddc_ctx *c, bool first, bool hist_only, bool gated) {
     a.ctl = c->d_ctl;
     a.first = first ? 1 : 0; a.hist_only = hist_only ? 1 : 0; a.gated = gated ? 1 : 0;
     a.rho_hist = c->d_rhohist; a.b_hist = c->d_bhist; a.mu_hist = c->d_muhist; a.hist_cap = c->hist_cap;
+    a.test = test; a.stop_rule = c->opts.stop_rule; a.max_it = c->opts.max_it;
+    a.rr_part = c->d_rr; a.rr_n = c->vgrid; a.bb_part = c->d_bbp; a.bb_n = c->vgrid;
+    a.res_hist = c->d_reshist;
     launch_pupd(a, c->kmax, c->vgrid, c->stream);
 }
 
@@ -580,7 +584,7 @@ void enqueue_iteration(bddc_ctx *c) {
     run_update(c);                                       // lines 9-11
     if (c->opts.reorth && c->R > 0) run_reorth(c);       // optional line
     run_precond(c, c->d_r, c->d_z, 1, true, true, true); // stopping test, line 13
-    run_pupd(c, false, false, true);                     // lines 14-16
+    run_pupd(c, false, false, true, 1);                  // lines 14-16 (the test while recording)
 }
 
 int capture_graph(bddc_ctx *c) {
@@ -758,24 +762,19 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
         launch_defl_init(d, c->kmax, c->vgrid, c->stream);
     }
     run_precond(c, c->d_r, c->d_z, 2, false, false, true);  // first test, lines 5-6
-    run_pupd(c, true, false, true);                         // line 7
+    run_pupd(c, true, false, true, 2);                      // line 7 (the first test while recording)
     int restarts = 0, rc;
     bool recovered = false;
     while (true) {
         if ((rc = run_loop(c))) return rc;
         run_true_residual(c, c->d_tmp);                  // float64 ||b - A x||
-        // z_l = M^{-1} r_l for the harmonic-Ritz matrices (Section 4.2):
-        // rho_l, mu_l recorded, direction index advanced
-        const bool extra = want_hist && restarts == 0;
-        if (extra) {
-            launch_set_done(c->d_ctl, 0, c->stream);
-            run_precond(c, c->d_r, c->d_z, 0, false, true, true);
-            run_pupd(c, false, true, false);
-        }
+        // while recording, the loop's last pass applied M^{-1} to r_l before
+        // its (deferred) stopping test and recorded rho_l, mu_l (Section 4.2)
+        const bool hist = want_hist && restarts == 0;
         // interior recovery from this x, enqueued behind the synchronisation's
         // copies so that the device works while the host waits (done again if
         // the solve goes on or x is reset)
-        if ((rc = end_sync_issue(c, extra))) return rc;
+        if ((rc = end_sync_issue(c, hist))) return rc;
         if ((rc = run_recover(c, F, u))) return rc;
         recovered = true;
         if ((rc = end_sync_wait(c))) return rc;
@@ -791,8 +790,9 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
         recovered = false;
         launch_copy(c->n_gamma, c->d_tmp, c->d_r, c->stream);
         launch_set_done(c->d_ctl, 0, c->stream);
-        run_precond(c, c->d_r, c->d_z, 0, false, !extra, true);
-        run_pupd(c, true, false, true);
+        // (while recording, the loop's last pass has advanced the direction index)
+        run_precond(c, c->d_r, c->d_z, 0, false, !record, true);
+        run_pupd(c, true, false, true, 0);
         *c->h_flags = 0;
     }
     const Ctl h = *c->h_ctl;
@@ -1527,15 +1527,11 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) || (rc = dalloc(c, &c->d_KCinv, (size_t)std::max(1, n * n))))
             return rc;
         launch_gather_sum((int64_t)n * n, dp, di, c->d_KC, c->d_KCinv, s);
-        std::vector<SweepDesc> sd{SweepDesc{c->d_KCinv, n, n, 0, n, n}};
-        SweepDesc *dsd;
-        if ((rc = dupload(c, &dsd, sd))) return rc;
-        if (n > 0) {
-            set_sweep_smem_limit((size_t)std::max({max_nloc, max_sad, n, 1}) * 8);
-            launch_sweep(dsd, 1, n, c->d_status, s);
-        }
+        double *drows;
+        if ((rc = dalloc(c, &drows, (size_t)std::max(1, 2 * n)))) return rc;
+        launch_sweep_large(c->d_KCinv, n, n, n, drows, c->d_status, s);
         HIPCHK(hipStreamSynchronize(s));
-        dfree(c, dp); dfree(c, di); dfree(c, dsd);
+        dfree(c, dp); dfree(c, di); dfree(c, drows);
         if (n > 0) {
             std::vector<double> h((size_t)n * n);
             HIPCHK(hipMemcpy(h.data(), c->d_KCinv, h.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -1724,12 +1720,11 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
                 (rc = dalloc(c, &c->d_K3inv, (size_t)std::max(1, n * n))))
                 return rc;
             launch_gather_sum((int64_t)n * n, dp, di, d_K3loc, c->d_K3inv, s);
-            std::vector<SweepDesc> sd{SweepDesc{c->d_K3inv, n, n, 0, n, n}};
-            SweepDesc *dsd;
-            if ((rc = dupload(c, &dsd, sd))) return rc;
-            if (n > 0) launch_sweep(dsd, 1, n, c->d_status, s);
+            double *drows;
+            if ((rc = dalloc(c, &drows, (size_t)std::max(1, 2 * n)))) return rc;
+            launch_sweep_large(c->d_K3inv, n, n, n, drows, c->d_status, s);
             HIPCHK(hipStreamSynchronize(s));
-            dfree(c, dp); dfree(c, di); dfree(c, dsd);
+            dfree(c, dp); dfree(c, di); dfree(c, drows);
         }
         dfree(c, d_cptr2); dfree(c, d_ccol2); dfree(c, d_cval2); dfree(c, d_w2); dfree(c, d_M2); dfree(c, d_X2);
         dfree(c, d_K3loc);

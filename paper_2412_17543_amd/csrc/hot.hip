@@ -190,26 +190,24 @@ __device__ __forceinline__ double gather_sum(const Gather &G, int64_t t) {
 
 // Stopping test of Section 5 (eq. stopping_rhs, or eq. stopping_residual with
 // stop_rule 1) on the residual whose per-block ||r||^2 partials are in
-// a.rr_part.  test 2: the first test of a solve, on r_0 (zero iterations
-// allowed); test 1: after the residual update of direction j.  Every block
-// evaluates it identically; block 0 records the outcome.
-__device__ bool stop_test(const SymvArgs &a) {
+// rr_part.  first: the first test of a solve, on r_0 (zero iterations
+// allowed); otherwise after the residual update, `iter` loop passes done.
+// Every block evaluates it identically; block 0 records the outcome.
+__device__ bool stop_eval(Ctl *c, const double *rr_part, int rr_n, const double *bb_part, int bb_n, bool first,
+                          int stop_rule, int max_it, int iter, double *res_hist, int hist_cap) {
     __shared__ int s_stop;
-    Ctl *c = a.ctl;
     if (threadIdx.x < 64) {
-        const double rr = wave_sum_contig(a.rr_part, a.rr_n);
-        const bool first = a.test == 2;
+        const double rr = wave_sum_contig(rr_part, rr_n);
         double bb = 0.0, denom2;
         if (first) {
-            bb = wave_sum_contig(a.bb_part, a.bb_n);
-            denom2 = a.stop_rule == 0 ? bb : rr;
+            bb = wave_sum_contig(bb_part, bb_n);
+            denom2 = stop_rule == 0 ? bb : rr;
         } else {
             denom2 = c->denom2;
         }
-        const int iter = first ? 0 : c->j + 1;
         const bool conv = (first && bb == 0.0) || rr < c->rtol2 * denom2;
         const bool bad = !isfinite(rr);
-        const bool maxed = !first && iter >= a.max_it;
+        const bool maxed = !first && iter >= max_it;
         const bool stop = conv || bad || maxed;
         if (threadIdx.x == 0) {
             s_stop = stop ? 1 : 0;
@@ -223,7 +221,7 @@ __device__ bool stop_test(const SymvArgs &a) {
                 } else {
                     c->iter = iter;
                 }
-                if (a.res_hist && iter < a.hist_cap) a.res_hist[iter] = rr;
+                if (res_hist && iter < hist_cap) res_hist[iter] = rr;
                 if (bad) c->status = BDDC_EBREAKDOWN;
                 else if (!conv && maxed) c->status = BDDC_ENOTCONV;
                 if (stop) ctl_finish(c);
@@ -232,6 +230,17 @@ __device__ bool stop_test(const SymvArgs &a) {
     }
     __syncthreads();
     return s_stop != 0;
+}
+
+// The test at the start of the preconditioner's product (direction j not yet
+// advanced).  While the basis is recording and `defer` is set, the test is
+// left to k_pupd instead, so that the last pass also produces z = M^{-1} r,
+// which the harmonic-Ritz matrices need (Section 4.2).
+__device__ bool stop_test(const SymvArgs &a) {
+    Ctl *c = a.ctl;
+    const bool first = a.test == 2;
+    return stop_eval(c, a.rr_part, a.rr_n, a.bb_part, a.bb_n, first, a.stop_rule, a.max_it, first ? 0 : c->j + 1,
+                     a.res_hist, a.hist_cap);
 }
 
 // ctl->done read once per block (a block of the kernel that sets it may be
@@ -305,6 +314,7 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
     // used.
     SymvItem it = load_item(a.op.items, blockIdx.x);
     if (a.gated && block_done(a.ctl)) return;
+    const bool test_here = a.test && !(a.defer && a.ctl->record);
 
     // Tiles past w1 read as zero without a memory access (resource over tiles
     // [t, w1) for the stage starting at tile t), so the loads of the next U
@@ -330,7 +340,7 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
         Frag<T> fa[U], fb[U];
     #pragma unroll
         for (int u = 0; u < U; ++u) fa[u].load(stage(w0), u, l);
-        if (first && a.test && stop_test(a)) return;
+        if (first && test_here && stop_test(a)) return;
         const int nt = (n + TILE - 1) / TILE;
         const int ncs = it.nc;
         const int ntc = (ncs + TILE - 1) / TILE;
@@ -579,6 +589,15 @@ __global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
     Ctl *c = a.ctl;
     if (a.gated && c->done) return;
     const int k = c->k, j = c->j;
+    // the stopping test deferred from the preconditioner's product (while
+    // recording): on a stop, record rho and mu of this z and leave p alone
+    bool hist_only = a.hist_only;
+    if (a.test && c->record) {
+        const bool first = a.test == 2;
+        if (stop_eval(c, a.rr_part, a.rr_n, a.bb_part, a.bb_n, first, a.stop_rule, a.max_it, first ? 0 : j,
+                      a.res_hist, a.hist_cap))
+            hist_only = true;
+    }
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double z0 = 0.0, p0 = 0.0, w0[KM > 0 ? KM : 1];
     {
@@ -593,7 +612,7 @@ __global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
         // the operands of this thread's first node do not depend on beta and
         // mu: their loads overlap the reductions (columns q >= k read as zero
         // through the range check, so every load is unconditional)
-        if (!a.hist_only && g0 < a.n) {
+        if (!hist_only && g0 < a.n) {
             z0 = a.z[g0];
             p0 = a.p[g0];
             const __amdgpu_buffer_rsrc_t wr = vec_rsrc(a.W, (int64_t)k * a.ld);
@@ -617,11 +636,11 @@ __global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
         if (threadIdx.x == 0) {
             if (j < a.hist_cap) a.rho_hist[j] = rho;
             if (!a.first && j >= 1 && j - 1 < a.hist_cap) a.b_hist[j - 1] = beta;
-            if (bad && !a.hist_only) { c->status = BDDC_EBREAKDOWN; ctl_finish(c); }
+            if (bad && !hist_only) { c->status = BDDC_EBREAKDOWN; ctl_finish(c); }
         }
         if (threadIdx.x < k && j < a.hist_cap) a.mu_hist[(int64_t)j * RMAX + threadIdx.x] = mu[threadIdx.x];
     }
-    if (a.hist_only || bad) return;
+    if (hist_only || bad) return;
     const bool rec = a.P && c->record && j < a.cap;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (g0 < a.n) {

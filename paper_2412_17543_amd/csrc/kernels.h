@@ -74,6 +74,7 @@ struct SymvArgs {
     // stopping test made at the start (Section 5), on the residual whose
     // per-block ||r||^2 partials the previous kernel wrote
     int test;                       // 0 none, 1 in the loop, 2 on r_0 (first)
+    int defer;                      // leave the test to k_pupd while ctl->record
     int stop_rule, max_it;
     const double *rr_part; int rr_n;
     const double *bb_part; int bb_n;
@@ -128,6 +129,12 @@ struct PupdArgs {                   // Alg. 1, lines 14-16 (line 7 when first)
     Ctl *ctl;
     int first, hist_only, gated;
     double *rho_hist, *b_hist, *mu_hist; int hist_cap;
+    // stopping test deferred from the preconditioner's product while the
+    // basis is recording (0 none, 1 in the loop, 2 on r_0)
+    int test, stop_rule, max_it;
+    const double *rr_part; int rr_n;
+    const double *bb_part; int bb_n;
+    double *res_hist;
 };
 
 struct ResidArgs {                  // out = b - sum of the Schur partials
@@ -295,6 +302,8 @@ struct GradArgs {
 void launch_assemble(const AsmDesc *d, int n, hipStream_t s);
 void launch_sweep(const SweepDesc *d, int n, int maxn, int *status, hipStream_t s);
 void launch_face_schur(const FaceSchurDesc *d, int n, int maxn, int *status, hipStream_t s);
+// sweep of all pivots of one n x n matrix (rows: 2 n scratch), grid-wide
+void launch_sweep_large(double *A, int n, int ld, int pos_end, double *rows, int *status, hipStream_t s);
 void set_sweep_smem_limit(size_t bytes);
 void launch_build_saddle(const SaddleDesc *d, int n, hipStream_t s);
 void launch_pack(const PackDesc *d, int n, int prec, void *dst, void *phir, hipStream_t s);

@@ -79,6 +79,46 @@ __global__ void __launch_bounds__(1024) k_sweep(const SweepDesc *descs, int *sta
 }
 
 // ---------------------------------------------------------------------------
+// setup: the same sweep for one large matrix (the dense coarse problems), one
+// launch per pivot over the whole grid.  Step k reads the pivot row from
+// rows[k & 1] (written by the previous step) and every block updates its own
+// rows; the block that updates row k + 1 also stores its new values in
+// rows[(k + 1) & 1] for the next step, so no block reads a row another block
+// of the same launch writes.
+// ---------------------------------------------------------------------------
+constexpr int SWEEP_ROWS = 4;       // rows per block, one wave each
+__global__ void __launch_bounds__(256) k_sweep_step(double *A, int n, int ld, int k, int pos_end, double *rows,
+                                                    int *status) {
+    const double *row = rows + (size_t)(k & 1) * n;
+    double *next = rows + (size_t)((k + 1) & 1) * n;
+    const double piv = row[k];
+    if (!((k < pos_end ? piv > 0.0 : piv < 0.0) && isfinite(piv))) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(status, 1);
+        return;
+    }
+    const double inv = 1.0 / piv;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int i = blockIdx.x * SWEEP_ROWS + w;
+    if (i >= n) return;
+    double *Ai = A + (size_t)i * ld;
+    const bool keep_next = (i == k + 1);
+    if (i == k) {
+        for (int j = l; j < n; j += 64) Ai[j] = (j == k) ? -inv : row[j] * inv;
+    } else {
+        const double ri = row[i] * inv;
+        for (int j = l; j < n; j += 64) {
+            const double v = (j == k) ? ri : Ai[j] - ri * row[j];
+            Ai[j] = v;
+            if (keep_next) next[j] = v;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_copy_row(const double *A, int n, double *dst) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) dst[j] = A[j];
+}
+
+// ---------------------------------------------------------------------------
 // setup: Schur complement onto the last m = n - p entries of a permuted copy
 // of S (symmetric positive semi-definite, positive definite on the p leading
 // entries): symmetric Gaussian elimination of the leading p pivots, each
@@ -490,41 +530,38 @@ __global__ void k_set_state(RecState *st, int k, int ok) {
     if (threadIdx.x == 0) { st->k = k; st->ok = ok; }
 }
 
-// One block: symmetrise the new W^T A W, Cholesky factor in LDS, explicit
-// inverse by forward/backward substitution (one column per thread),
-// symmetrised.  state->ok = 1 when positive definite (Section 4.1: W^T A W
-// must be invertible for the projection of eq. projectionQ).
-__global__ void __launch_bounds__(256) k_chol_inv(CholArgs a) {
-    __shared__ double L[RMAX][RMAX];
-    __shared__ double X[RMAX][RMAX];
+// One wave: symmetrise the new W^T A W, Cholesky factor in LDS (lane t owns
+// row t), explicit inverse by forward/backward substitution (lane t solves
+// for column t), symmetrised.  state->ok = 1 when positive definite
+// (Section 4.1: W^T A W must be invertible for the projection of
+// eq. projectionQ).  k <= RMAX = 64.
+__global__ void __launch_bounds__(64) k_chol_inv(CholArgs a) {
+    __shared__ double L[RMAX][RMAX + 1];
+    __shared__ double X[RMAX][RMAX + 1];
     const int k = a.k, t = threadIdx.x;
-    for (int e = t; e < k * k; e += blockDim.x) {
+    for (int e = t; e < k * k; e += 64) {
         const int i = e / k, j = e - i * k;
         const double v = 0.5 * (a.waw[i * k + j] + a.waw[j * k + i]);
         L[i][j] = v;
         a.waw_sym[i * k + j] = v;
     }
     __syncthreads();
-    bool bad = false;
     for (int j = 0; j < k; ++j) {
-        if (t == 0) {
-            // a non-positive pivot leaves 0 on the diagonal, seen by every thread
-            const double d = L[j][j];
-            L[j][j] = (d > 0.0 && isfinite(d)) ? sqrt(d) : 0.0;
+        const double d = L[j][j];
+        if (!(d > 0.0 && isfinite(d))) {     // the same value in every lane
+            if (t == 0) a.state->ok = 0;
+            return;
+        }
+        const double s = sqrt(d);
+        __syncthreads();
+        if (t == j) L[j][j] = s;
+        if (t > j && t < k) L[t][j] /= s;
+        __syncthreads();
+        if (t > j && t < k) {
+            const double ltj = L[t][j];
+            for (int q = j + 1; q <= t; ++q) L[t][q] -= ltj * L[q][j];
         }
         __syncthreads();
-        if (!(L[j][j] > 0.0)) { bad = true; break; }
-        for (int i = j + 1 + t; i < k; i += blockDim.x) L[i][j] /= L[j][j];
-        __syncthreads();
-        for (int e = t; e < (k - j - 1) * (k - j - 1); e += blockDim.x) {
-            const int i = j + 1 + e / (k - j - 1), q = j + 1 + e % (k - j - 1);
-            if (q <= i) L[i][q] -= L[i][j] * L[q][j];
-        }
-        __syncthreads();
-    }
-    if (bad) {
-        if (t == 0) a.state->ok = 0;
-        return;
     }
     if (t < k) {
         // column t of (L L^T)^{-1}: L y = e_t, then L^T x = y
@@ -540,7 +577,7 @@ __global__ void __launch_bounds__(256) k_chol_inv(CholArgs a) {
         }
     }
     __syncthreads();
-    for (int e = t; e < k * k; e += blockDim.x) {
+    for (int e = t; e < k * k; e += 64) {
         const int i = e / k, j = e - i * k;
         a.inv[i * k + j] = 0.5 * (X[i][j] + X[j][i]);
     }
@@ -573,6 +610,13 @@ void launch_assemble(const AsmDesc *d, int n, hipStream_t s) {
 }
 void launch_sweep(const SweepDesc *d, int n, int maxn, int *status, hipStream_t s) {
     hipLaunchKernelGGL(k_sweep, dim3(n), dim3(1024), (size_t)maxn * sizeof(double), s, d, status);
+}
+void launch_sweep_large(double *A, int n, int ld, int pos_end, double *rows, int *status, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_copy_row, dim3(nblk(n, 256)), dim3(256), 0, s, A, n, rows);
+    const unsigned nb = nblk(n, SWEEP_ROWS);
+    for (int k = 0; k < n; ++k)
+        hipLaunchKernelGGL(k_sweep_step, dim3(nb), dim3(256), 0, s, A, n, ld, k, pos_end, rows, status);
 }
 void launch_face_schur(const FaceSchurDesc *d, int n, int maxn, int *status, hipStream_t s) {
     if (n <= 0) return;
@@ -647,7 +691,7 @@ void launch_set_state(RecState *state, int k, int ok, hipStream_t s) {
     hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, state, k, ok);
 }
 void launch_chol_inv(const CholArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), 0, s, a);
 }
 void launch_commit(const CommitArgs &a, hipStream_t s) {
     const int64_t nb = std::min<int64_t>(1024, std::max<int64_t>(1, (a.n + 255) / 256));

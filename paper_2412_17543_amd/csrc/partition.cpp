@@ -348,10 +348,16 @@ int build_level2(Structure &st, const bddc_partition *p, std::string &err) {
         const auto &ci = st.sub[i].cidx;
         for (size_t a = 0; a < ci.size(); ++a)
             for (size_t b = a + 1; b < ci.size(); ++b)
-                if (g2idx[ci[a]] >= 0 && g2idx[ci[b]] >= 0 && S2[ci[a]] == S2[ci[b]]) d2.u(ci[a], ci[b]);
+                if (g2idx[ci[a]] >= 0 && g2idx[ci[b]] >= 0 && S2[ci[a]] == S2[ci[b]] &&
+                    st.coarse[ci[a]].kind != 3 && st.coarse[ci[b]].kind != 3)
+                    d2.u(ci[a], ci[b]);
     }
+    // adaptive face rows (Section 3.3) stay out of the level-2 globs: each one
+    // on the level-2 interface is a level-3 unknown of its own, so the
+    // operator does not depend on the rows' signs or on their basis
     std::map<int64_t, std::vector<int32_t>> gm;
-    for (int32_t c : st.gamma2) gm[d2.f(c)].push_back(c);
+    for (int32_t c : st.gamma2)
+        if (st.coarse[c].kind != 3) gm[d2.f(c)].push_back(c);
     for (int32_t c : st.gamma2) {
         if (st.coarse[c].kind != 0 || S2[c].size() < 3) continue;
         std::vector<int32_t> nbs;
@@ -371,6 +377,11 @@ int build_level2(Structure &st, const bddc_partition *p, std::string &err) {
             st.dof3_subs.push_back(S2[c]);
             st.n3_corner++;
         }
+    }
+    for (int32_t c : st.gamma2) {
+        if (st.coarse[c].kind != 3) continue;
+        st.dof3_members.push_back({c});
+        st.dof3_subs.push_back(S2[c]);
     }
     for (auto &kv : gm) {
         if (S2[kv.second[0]].size() != 2) continue;
