@@ -1899,9 +1899,16 @@ int dpcg_solve(bddc_ctx *c, const double *rhs_seq, int32_t n_rhs, double rtol, d
         if (condensed) {
             run_condense(c, rhs_seq + (size_t)(k + 1) * c->n_nodes);
             // A x_{-1} of the next initial residual does not depend on the
-            // deflation basis: it runs ahead of the basis update as well
-            if (c->opts.init_guess == 1) launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
-            run_schur(c, c->d_x, false, false);
+            // deflation basis.  With the previous solution as x_{-1} it is the
+            // product the true residual just formed, still in the Schur
+            // partials (nothing in between writes them); otherwise it runs
+            // here, ahead of the basis update
+            if (c->opts.init_guess == 1) {
+                launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
+                run_schur(c, c->d_x, false, false);
+            } else if (c->h_ctl->zero_rhs) {
+                run_schur(c, c->d_x, false, false);    // x was reset to 0 after that product
+            }
             c->pre_schur = true;
         }
         {
