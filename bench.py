@@ -193,7 +193,7 @@ def main():
                          "subdomains, adaptive faces (tau 10), float32 Neumann operators, R = 40 (its own "
                          "line: the float32 form only)")
     ap.add_argument("--n-rhs", type=int, default=0, help="use the first N right-hand sides of the sequence")
-    ap.add_argument("--bf16", action="store_true", help="also run the bfloat16 Neumann-operator form")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16 Neumann-operator form")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the adjoint gradient of L = sum_k ||u_k - t_k||^2 (t_k = 0.9 u_k): one adjoint "
                          "solve per right-hand side with the recycled basis, and the element gradient")
@@ -314,7 +314,7 @@ def main():
                               "speedup_vs_fp64": round(mv / value, 3)}
         if plain_value:
             line["mixed_fp32"]["speedup_vs_plain_fp64"] = round(mv / plain_value, 3)
-    if args.bf16:
+    if not args.no_bf16 and not args.no_mixed:
         bf = run_form(torch, Solver, s, F, args.rtol, args.steps, args.warmup, 16, False)
         ud = f64["U"]
         err = max(float(((bf["U"][k] - ud[k]).abs().max() / ud[k].abs().max()).item()) for k in range(n_rhs))

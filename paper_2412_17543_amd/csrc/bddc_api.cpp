@@ -158,6 +158,9 @@ struct bddc_ctx {
     int hcopy = 0;
     int32_t *h_flags = nullptr;     // pinned, device-mapped: [0] convergence word
     int32_t *d_hflag = nullptr;     // device address of h_flags[0]
+    double *h_prog = nullptr;       // pinned, device-mapped: last ||r||^2, its denominator, iteration
+    double *d_hprog = nullptr;      // device address of h_prog
+    double rtol2_run = 0.0;         // squared tolerance of the running solve
     int32_t *d_status = nullptr;
     bool have_solve = false, have_hist = false;
     int last_iters = 0, last_restarts = 0, last_status = 0;
@@ -615,19 +618,42 @@ int run_loop(bddc_ctx *c) {
         int rc = capture_graph(c);
         if (rc) return rc;
         volatile int32_t *flag = c->h_flags;
+        volatile const double *prog = c->h_prog;
         int launched = 0, polled = 0;
         const int cap = max_launch / GRAPH_ITERS + GRAPH_INFLIGHT + 1;
+        double last_rr = -1.0, last_it = -1.0, rate = 0.0;
+        auto wait_one = [&]() -> int {
+            const int ps = polled % (GRAPH_INFLIGHT + 1);
+            HIPCHK(hipEventSynchronize(c->gev[ps]));
+            ++polled;
+            return 0;
+        };
         while (true) {
             const int slot = launched % (GRAPH_INFLIGHT + 1);
             HIPCHK(hipGraphLaunch(c->gexec, c->stream));
             HIPCHK(hipEventRecord(c->gev[slot], c->stream));
             ++launched;
             if (launched - polled >= GRAPH_INFLIGHT || launched >= cap) {
-                const int ps = polled % (GRAPH_INFLIGHT + 1);
-                HIPCHK(hipEventSynchronize(c->gev[ps]));
-                ++polled;
+                if (int rc = wait_one()) return rc;
                 if (*flag) break;
                 if (launched >= cap) break;   // every kernel stops at max_it by itself
+                // The residual after the polled graph and its decay per
+                // iteration predict whether the graphs still queued reach the
+                // tolerance; if so, wait for them before queuing another (a
+                // graph queued past convergence costs its launches for nothing).
+                const double rr = prog[0], den = prog[1], it = prog[2];
+                if (last_it >= 0.0 && it > last_it && rr > 0.0 && last_rr > 0.0 && rr < last_rr)
+                    rate = std::pow(rr / last_rr, 1.0 / (it - last_it));
+                last_rr = rr;
+                last_it = it;
+                if (rate > 0.0 && rate < 1.0 && rr > 0.0 && den > 0.0) {
+                    const double need = std::log(c->rtol2_run * den / rr) / std::log(rate);
+                    if (need <= (double)(launched - polled) * GRAPH_ITERS) {
+                        while (polled < launched && !*flag)
+                            if (int rc = wait_one()) return rc;
+                        if (*flag) break;
+                    }
+                }
             }
         }
         return 0;
@@ -746,7 +772,9 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     const int strat = c->opts.recycle_strategy;
     const bool want_hist = record && (strat == 3 || strat == 4);
     *c->h_flags = 0;
-    launch_ctl_init(c->d_ctl, rtol * rtol, record ? 1 : 0, c->R > 0 ? c->d_state : nullptr, c->d_hflag, c->stream);
+    c->rtol2_run = rtol * rtol;
+    launch_ctl_init(c->d_ctl, rtol * rtol, record ? 1 : 0, c->R > 0 ? c->d_state : nullptr, c->d_hflag, c->d_hprog,
+                    c->stream);
     if (!condensed) run_condense(c, F);                  // b, ||b||^2 partials
     if (!c->pre_schur) {
         if (c->opts.init_guess == 1) launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
@@ -1785,6 +1813,9 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
     HIPCHK(hipHostMalloc((void **)&c->h_flags, sizeof(int32_t) * 4, hipHostMallocMapped));
     HIPCHK(hipHostGetDevicePointer((void **)&c->d_hflag, c->h_flags, 0));
     c->h_flags[0] = 0;
+    HIPCHK(hipHostMalloc((void **)&c->h_prog, sizeof(double) * 4, hipHostMallocMapped));
+    HIPCHK(hipHostGetDevicePointer((void **)&c->d_hprog, c->h_prog, 0));
+    for (int q = 0; q < 4; ++q) c->h_prog[q] = 0.0;
     {
         // W, AW always exist (k = 0 columns are never read); the recycling
         // buffers only with R > 0
@@ -2145,6 +2176,7 @@ void bddc_destroy(bddc_ctx *c) {
     if (c->h_hist) (void)hipHostFree(c->h_hist);
     if (c->h_Y) (void)hipHostFree(c->h_Y);
     if (c->h_flags) (void)hipHostFree(c->h_flags);
+    if (c->h_prog) (void)hipHostFree(c->h_prog);
     for (auto &p : c->pending) { (void)hipEventDestroy(p.second.first); (void)hipEventDestroy(p.second.second); }
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;

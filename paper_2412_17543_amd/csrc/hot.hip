@@ -222,6 +222,12 @@ __device__ bool stop_eval(Ctl *c, const double *rr_part, int rr_n, const double 
                     c->iter = iter;
                 }
                 if (res_hist && iter < hist_cap) res_hist[iter] = rr;
+                if (c->hprog) {
+                    volatile double *hp = c->hprog;
+                    hp[0] = rr;
+                    hp[1] = denom2;
+                    hp[2] = (double)iter;
+                }
                 if (bad) c->status = BDDC_EBREAKDOWN;
                 else if (!conv && maxed) c->status = BDDC_ENOTCONV;
                 if (stop) ctl_finish(c);

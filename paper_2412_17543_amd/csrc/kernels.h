@@ -321,7 +321,8 @@ void launch_gram(const GramArgs &a, int nblocks, hipStream_t s);
 void launch_elem_grad(const GradArgs &a, hipStream_t s);
 void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s);
 void launch_fill(int64_t n, double v, double *dst, hipStream_t s);
-void launch_ctl_init(Ctl *ctl, double rtol2, int record, const RecState *state, int32_t *hflag, hipStream_t s);
+void launch_ctl_init(Ctl *ctl, double rtol2, int record, const RecState *state, int32_t *hflag, double *hprog,
+                     hipStream_t s);
 void launch_set_done(Ctl *ctl, int v, hipStream_t s);
 void launch_set_state(RecState *state, int k, int ok, hipStream_t s);
 void launch_chol_inv(const CholArgs &a, hipStream_t s);

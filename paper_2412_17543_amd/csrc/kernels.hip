@@ -512,13 +512,14 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, double v, double *dst) 
 // ---------------------------------------------------------------------------
 // control block and deflation-basis bookkeeping on the device
 // ---------------------------------------------------------------------------
-__global__ void k_ctl_init(Ctl *c, double rtol2, int record, const RecState *st, int32_t *hflag) {
+__global__ void k_ctl_init(Ctl *c, double rtol2, int record, const RecState *st, int32_t *hflag, double *hprog) {
     if (threadIdx.x != 0) return;
     Ctl h{};
     h.rtol2 = rtol2;
     h.record = record;
     h.k = st ? st->k : 0;
     h.hflag = hflag;
+    h.hprog = hprog;
     *c = h;
 }
 
@@ -530,56 +531,64 @@ __global__ void k_set_state(RecState *st, int k, int ok) {
     if (threadIdx.x == 0) { st->k = k; st->ok = ok; }
 }
 
-// One wave: symmetrise the new W^T A W, Cholesky factor in LDS (lane t owns
-// row t), explicit inverse by forward/backward substitution (lane t solves
-// for column t), symmetrised.  state->ok = 1 when positive definite
+// One wave: symmetrise the new W^T A W and invert it in LDS by a symmetric
+// Gauss-Jordan sweep of all pivots (lane t owns row t; after the sweep the
+// matrix holds -(W^T A W)^{-1}).  Every pivot of a symmetric positive
+// definite matrix is positive (it is a diagonal entry of a Schur
+// complement), so state->ok = 1 exactly when the matrix is positive definite
 // (Section 4.1: W^T A W must be invertible for the projection of
 // eq. projectionQ).  k <= RMAX = 64.
 __global__ void __launch_bounds__(64) k_chol_inv(CholArgs a) {
-    __shared__ double L[RMAX][RMAX + 1];
-    __shared__ double X[RMAX][RMAX + 1];
+    __shared__ double A[RMAX][RMAX + 1];
+    __shared__ double row[RMAX];
     const int k = a.k, t = threadIdx.x;
-    for (int e = t; e < k * k; e += 64) {
-        const int i = e / k, j = e - i * k;
-        const double v = 0.5 * (a.waw[i * k + j] + a.waw[j * k + i]);
-        L[i][j] = v;
-        a.waw_sym[i * k + j] = v;
+    // lane t reads row t (all loads issued before any store), then the
+    // symmetric part is formed in LDS
+    if (t < k) {
+        double v[RMAX];
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) v[j] = j < k ? a.waw[t * k + j] : 0.0;
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) A[t][j] = v[j];
     }
     __syncthreads();
-    for (int j = 0; j < k; ++j) {
-        const double d = L[j][j];
-        if (!(d > 0.0 && isfinite(d))) {     // the same value in every lane
+    {
+        double v[RMAX];
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) v[j] = (t < k) ? 0.5 * (A[t][j] + A[j][t]) : 0.0;
+        __syncthreads();
+        if (t < k) {
+#pragma unroll
+            for (int j = 0; j < RMAX; ++j) A[t][j] = v[j];
+#pragma unroll
+            for (int j = 0; j < RMAX; ++j)
+                if (j < k) a.waw_sym[t * k + j] = v[j];
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < k; ++p) {
+        if (t < k) row[t] = A[p][t];
+        __syncthreads();
+        const double piv = row[p];
+        if (!(piv > 0.0 && isfinite(piv))) {     // the same value in every lane
             if (t == 0) a.state->ok = 0;
             return;
         }
-        const double s = sqrt(d);
-        __syncthreads();
-        if (t == j) L[j][j] = s;
-        if (t > j && t < k) L[t][j] /= s;
-        __syncthreads();
-        if (t > j && t < k) {
-            const double ltj = L[t][j];
-            for (int q = j + 1; q <= t; ++q) L[t][q] -= ltj * L[q][j];
+        const double inv = 1.0 / piv;
+        if (t < k) {
+            if (t == p) {
+                for (int j = 0; j < k; ++j) A[p][j] = (j == p) ? -inv : row[j] * inv;
+            } else {
+                const double f = row[t] * inv;     // A(t, p) = A(p, t) by symmetry
+                for (int j = 0; j < k; ++j) A[t][j] = (j == p) ? f : A[t][j] - f * row[j];
+            }
         }
         __syncthreads();
     }
     if (t < k) {
-        // column t of (L L^T)^{-1}: L y = e_t, then L^T x = y
-        for (int i = 0; i < k; ++i) {
-            double s = (i == t) ? 1.0 : 0.0;
-            for (int q = 0; q < i; ++q) s -= L[i][q] * X[q][t];
-            X[i][t] = s / L[i][i];
-        }
-        for (int i = k - 1; i >= 0; --i) {
-            double s = X[i][t];
-            for (int q = i + 1; q < k; ++q) s -= L[q][i] * X[q][t];
-            X[i][t] = s / L[i][i];
-        }
-    }
-    __syncthreads();
-    for (int e = t; e < k * k; e += 64) {
-        const int i = e / k, j = e - i * k;
-        a.inv[i * k + j] = 0.5 * (X[i][j] + X[j][i]);
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j)
+            if (j < k) a.inv[t * k + j] = -0.5 * (A[t][j] + A[j][t]);
     }
     if (t == 0) a.state->ok = 1;
 }
@@ -681,8 +690,9 @@ void launch_fill(int64_t n, double v, double *dst, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256)), dim3(256), 0, s, n, v, dst);
 }
 
-void launch_ctl_init(Ctl *ctl, double rtol2, int record, const RecState *state, int32_t *hflag, hipStream_t s) {
-    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl, rtol2, record, state, hflag);
+void launch_ctl_init(Ctl *ctl, double rtol2, int record, const RecState *state, int32_t *hflag, double *hprog,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl, rtol2, record, state, hflag, hprog);
 }
 void launch_set_done(Ctl *ctl, int v, hipStream_t s) {
     hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, s, ctl, v);
