@@ -29,7 +29,9 @@ def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def native_face(lib, ss, D, dofs, face, S, tau, max_rows):
+def face_inputs(ss, D, dofs, face, S):
+    """The jump-space inputs of one face problem, formed from the oracle's
+    dense local Schur complements."""
     s, t = face["subs"]
     shared, ps, pt = ad.pair_maps(ss, s, t)
     m = shared.size
@@ -52,6 +54,13 @@ def native_face(lib, ss, D, dofs, face, S, tau, max_rows):
     B = np.ascontiguousarray(np.array(rows).reshape(len(rows), m))
     fpos = np.ascontiguousarray(np.searchsorted(shared, face["nodes"]).astype(np.int32))
     floating = [not ss.dir[ss.en[ss.sub[i]["elems"]]].any() for i in (s, t)]
+    return dict(m=m, Hs=Hs, Ht=Ht, Ks=Ks, Kt=Kt, Ds=Ds, Dt=Dt, floating=floating, B=B, fpos=fpos)
+
+
+def native_face(lib, ss, D, dofs, face, S, tau, max_rows):
+    f = face_inputs(ss, D, dofs, face, S)
+    m, Hs, Ht, Ks, Kt, Ds, Dt, floating, B, fpos = (f[k] for k in ("m", "Hs", "Ht", "Ks", "Kt", "Ds", "Dt",
+                                                                    "floating", "B", "fpos"))
     lam = np.zeros(m)
     out = np.zeros(max(max_rows, 1) * fpos.size)
     nl, nr = ctypes.c_int32(), ctypes.c_int32()
