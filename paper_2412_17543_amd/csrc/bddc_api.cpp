@@ -307,6 +307,11 @@ int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
             for (int q = 0; q < C; ++q) blk.push_back({Seg{k, nt * q / C, nt * (q + 1) / C, nch[k]++}});
         }
         nblocks = (int)blk.size();
+        // longest items first: the blocks that start after the first round
+        // are the short ones, which fill the compute units left idle early
+        std::stable_sort(blk.begin(), blk.end(), [](const std::vector<Seg> &x, const std::vector<Seg> &y) {
+            return x[0].t1 - x[0].t0 > y[0].t1 - y[0].t0;
+        });
     } else {
         blk.resize(nblocks);
         int i = 0;
