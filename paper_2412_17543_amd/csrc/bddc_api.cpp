@@ -117,9 +117,8 @@ struct bddc_ctx {
             *d_asm3_ptr = nullptr, *d_asm3_idx = nullptr;
     uint8_t *d_own2 = nullptr;
     int64_t *d_ph_off2 = nullptr;
-    int32_t *d_c3o = nullptr, *d_n3p = nullptr, *d_sr_ptr = nullptr, *d_sr_sub = nullptr, *d_cL = nullptr;
+    int32_t *d_c3o = nullptr, *d_n3p = nullptr;
     size_t smem_l2d = 0;
-    bool fuse_prolong = false;      // three levels with enough subregions to fill the GPU
     bool coarse_dense = false;      // u_C from one dense product (two levels, or explicit form)
     // dense coarse operator, row-major nC x nC with rows of ldm (even)
     // entries: -K_C^{-1} (two levels) or the explicit level-2 BDDC operator
@@ -437,7 +436,7 @@ void run_schur(bddc_ctx *c, const double *x, bool gated, bool dot) {
 }
 
 // Arguments of the level-2/3 kernels with the level-1 coarse residual taken
-// from `rc` (no prolongation).
+// from `rc`.
 L2Args l2_args(const bddc_ctx *c, const Gather &rc) {
     L2Args l{};
     l.ctl = c->d_ctl;
@@ -450,10 +449,6 @@ L2Args l2_args(const bddc_ctx *c, const Gather &rc) {
     l.u2 = c->d_u2; l.c3loc = c->d_c3loc; l.pos_sr = c->d_pos_sr; l.own2 = c->d_own2; l.u3 = c->d_u3;
     l.uC = c->d_uC;
     l.ph_off = c->d_ph_off2; l.c3o = c->d_c3o; l.n3p = c->d_n3p; l.n3 = c->n3; l.max_nL = c->max_nL;
-    l.sr_ptr = c->d_sr_ptr; l.sr_sub = c->d_sr_sub; l.cL = c->d_cL;
-    l.nB = c->d_nB; l.b_off = c->d_b_off; l.nc = c->d_nc; l.c_off = c->d_c_off;
-    l.nchunk = c->opN.d_nchunk; l.pb = c->opN.d_pb; l.upart = c->opN.d_ypart;
-    l.phir = c->d_phir; l.phr_off = c->d_phr_off; l.wloc = nullptr;
     return l;
 }
 
@@ -467,7 +462,7 @@ void run_l2_chain(const bddc_ctx *c, const L2Args &l, hipStream_t st) {
     l3.ctl = c->d_ctl; l3.n = c->n3; l3.ptr = c->d_asm3_ptr; l3.idx = c->d_asm3_idx; l3.loc = c->d_c3loc;
     l3.Kneg = c->d_K3inv; l3.u = c->d_u3;
     launch_l3(l3, st);
-    launch_l2_d(l, c->prec, c->nsr, c->smem_l2d, st);
+    launch_l2_d(l, c->nsr, c->smem_l2d, st);
 }
 
 // One BDDC application on r: local constrained-Neumann products and coarse
@@ -504,22 +499,19 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
             ca.u = c->d_uC;
             launch_coarse_dense(ca, c->stream);
         } else {
-            L2Args l = l2_args(c, rc);
-            l.wloc = c->fuse_prolong ? c->d_wloc : nullptr;
-            run_l2_chain(c, l, c->stream);   // with the prolongation when fused
+            run_l2_chain(c, l2_args(c, rc), c->stream);
         }
     }
     {
         TScope ts(c, TK_VEC);
         ProlArgs pa{};
-        const bool prolonged = !c->coarse_dense && c->fuse_prolong;   // done by k_l2_d
         pa.ctl = c->d_ctl; pa.gated = gated ? 1 : 0;
         pa.nB = c->d_nB; pa.b_off = c->d_b_off; pa.nc = c->d_nc; pa.c_off = c->d_c_off; pa.cidx = c->d_cidx;
         pa.nchunk = c->opN.d_nchunk; pa.pb = c->opN.d_pb; pa.upart = c->opN.d_ypart;
         pa.phir = c->d_phir; pa.phr_off = c->d_phr_off;
         pa.uC = c->nC > 0 ? c->d_uC : nullptr;
         pa.wloc = c->d_wloc;
-        if (!prolonged) launch_prolong(pa, c->prec, c->n_sub, c->max_nc, c->stream);
+        launch_prolong(pa, c->prec, c->n_sub, c->max_nc, c->stream);
         ZasmArgs a{};
         a.n = c->n_gamma;
         a.w.ptr = c->d_asm_ptr; a.w.idx = c->d_asm_idx; a.w.part = c->d_wloc;
@@ -1607,32 +1599,17 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         {
             // per level-2 interface position: its D Phi row and level-3 DOF list
             std::vector<int64_t> ph_off2(B2_off[nsr]);
-            std::vector<int32_t> c3o(B2_off[nsr]), n3p(B2_off[nsr]), sr_ptr(nsr + 1, 0), sr_sub;
+            std::vector<int32_t> c3o(B2_off[nsr]), n3p(B2_off[nsr]);
             for (int j = 0; j < nsr; ++j) {
                 for (int k = 0; k < st.sr[j].nB; ++k) {
                     ph_off2[B2_off[j] + k] = P2_off[j] + (int64_t)k * nc3[j];
                     c3o[B2_off[j] + k] = C3_off[j];
                     n3p[B2_off[j] + k] = nc3[j];
                 }
-                sr_sub.insert(sr_sub.end(), st.sr[j].subs.begin(), st.sr[j].subs.end());
-                sr_ptr[j + 1] = (int32_t)sr_sub.size();
-            }
-            // position of each coarse DOF of subdomain i in L of its subregion
-            std::vector<int32_t> cL(std::max<int64_t>(1, c_off[nsub]), 0), pos(c->nC, -1);
-            for (int j = 0; j < nsr; ++j) {
-                const auto &L = st.sr[j].L;
-                for (size_t q = 0; q < L.size(); ++q) pos[L[q]] = (int32_t)q;
-                for (int32_t i : st.sr[j].subs)
-                    for (int q = 0; q < nc[i]; ++q) cL[c_off[i] + q] = pos[st.sub[i].cidx[q]];
-                for (size_t q = 0; q < L.size(); ++q) pos[L[q]] = -1;
             }
             if ((rc = dupload(c, &c->d_ph_off2, ph_off2)) || (rc = dupload(c, &c->d_c3o, c3o)) ||
-                (rc = dupload(c, &c->d_n3p, n3p)) || (rc = dupload(c, &c->d_sr_ptr, sr_ptr)) ||
-                (rc = dupload(c, &c->d_sr_sub, sr_sub)) || (rc = dupload(c, &c->d_cL, cL)))
+                (rc = dupload(c, &c->d_n3p, n3p)))
                 return rc;
-            // the level-2 post-correction kernel (one block per subregion) also
-            // prolongates to its subdomains when there are enough subregions
-            c->fuse_prolong = nsr >= 2 * c->n_cu;
             c->smem_l2d = l2_d_smem(c->max_nL, c->n3);
             if (c->smem_l2d > 160 * 1024) return fail(BDDC_EINVAL, "level-3 problem too large for the staged level-2 kernel");
             if (set_l2_d_smem_limit(c->smem_l2d)) return fail(BDDC_EHIP, "hipFuncSetAttribute (dynamic LDS) failed");

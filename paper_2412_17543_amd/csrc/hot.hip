@@ -911,13 +911,9 @@ __global__ void __launch_bounds__(1024) k_l3(L3Args a) {
 // Level 2, phase D (one block per subregion): level-2 interface solution
 // x_G = sum_j R_j^T (u_j + (D Phi_j) u3) on the subregion's interface and the
 // interior post-correction x_I = v_I - T^T x_G give the level-1 coarse
-// solution u_C on all coarse DOFs of the subregion (kept in LDS; every
-// subregion sharing an interface DOF computes the same value in the same
-// order).  The block then prolongates to its member subdomains:
-// w_i = u_i + (D Phi_i) u_C|_i (eq. averaging_subdomain_solves), u_i summed
-// from the Neumann product's work items.  Without wloc the block only
-// publishes u_C for k_prolong.
-template <typename T>
+// solution u_C on the coarse DOFs of the subregion (every subregion sharing
+// an interface DOF computes the same value in the same order; its owner
+// writes it) for the prolongation, k_prolong.
 __global__ void __launch_bounds__(256) k_l2_d(L2Args a) {
     extern __shared__ double sm[];
     __shared__ double part[4][64];
@@ -949,29 +945,8 @@ __global__ void __launch_bounds__(256) k_l2_d(L2Args a) {
     cm_matvec<4>(a.K2 + a.K2_off[j] + (int64_t)nI * nL, nL, 0, nI, nB, uCL + nI, part,
                  [&](int q, double y) { uCL[q] = vI2[q] - y; });
     // cm_matvec ends with a barrier: uCL is complete
-    if (!a.wloc) {
-        // prolongation left to k_prolong: publish u_C
-        for (int q = threadIdx.x; q < nL; q += blockDim.x)
-            if (q < nI || a.own2[b2 + q - nI]) a.uC[a.L[a.L_off[j] + q]] = uCL[q];
-        return;
-    }
-    const T *phir = reinterpret_cast<const T *>(a.phir);
-    for (int m = a.sr_ptr[j]; m < a.sr_ptr[j + 1]; ++m) {
-        const int i = a.sr_sub[m];
-        const int n = a.nB[i], C = a.nchunk[i], nci = a.nc[i];
-        const int32_t *cl = a.cL + a.c_off[i];
-        const T *ph = phir + a.phr_off[i];
-        const double *up = a.upart + a.pb[i];
-        double *wl = a.wloc + a.b_off[i];
-        for (int k = threadIdx.x; k < n; k += blockDim.x) {
-            double w = 0.0;
-            for (int cc = 0; cc < C; ++cc) w += up[(int64_t)cc * n + k];
-            const T *row = ph + (int64_t)k * nci;
-#pragma unroll 8
-            for (int q = 0; q < nci; ++q) w += to_d(row[q]) * uCL[cl[q]];
-            wl[k] = w;
-        }
-    }
+    for (int q = threadIdx.x; q < nL; q += blockDim.x)
+        if (q < nI || a.own2[b2 + q - nI]) a.uC[a.L[a.L_off[j] + q]] = uCL[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -1114,16 +1089,12 @@ size_t l2_d_smem(int max_nL, int n3) { return (size_t)(std::max(1, max_nL) + std
 
 int set_l2_d_smem_limit(size_t bytes) {
     if (bytes <= 65536) return 0;
-    const void *f[3] = {(const void *)k_l2_d<double>, (const void *)k_l2_d<float>, (const void *)k_l2_d<uint16_t>};
-    for (const void *p : f)
-        if (hipFuncSetAttribute(p, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-    return 0;
+    return hipFuncSetAttribute((const void *)k_l2_d, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess
+               ? 0 : -1;
 }
 
-void launch_l2_d(const L2Args &a, int prec, int nsr, size_t smem, hipStream_t s) {
-    if (prec == 64) hipLaunchKernelGGL(k_l2_d<double>, dim3(nsr), dim3(256), smem, s, a);
-    else if (prec == 32) hipLaunchKernelGGL(k_l2_d<float>, dim3(nsr), dim3(256), smem, s, a);
-    else hipLaunchKernelGGL(k_l2_d<uint16_t>, dim3(nsr), dim3(256), smem, s, a);
+void launch_l2_d(const L2Args &a, int nsr, size_t smem, hipStream_t s) {
+    hipLaunchKernelGGL(k_l2_d, dim3(nsr), dim3(256), smem, s, a);
 }
 
 }  // namespace bddc

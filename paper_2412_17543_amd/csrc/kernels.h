@@ -208,14 +208,6 @@ struct L2Args {
     const int64_t *ph_off;
     const int32_t *c3o, *n3p;
     int n3, max_nL;
-    // prolongation of the member subdomains (eq. averaging_subdomain_solves)
-    const int32_t *sr_ptr, *sr_sub;     // subregion -> member subdomains
-    const int32_t *cL;                  // coarse DOF q of subdomain i -> position in L of its subregion
-    const int32_t *nB, *b_off, *nc, *c_off, *nchunk, *pb;
-    const double *upart;
-    const void *phir;
-    const int64_t *phr_off;
-    double *wloc;
 };
 
 struct L3Args {                     // level 3: u3 = K3^{-1} r3 (dense)
@@ -349,7 +341,7 @@ void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s);
 void launch_l3(const L3Args &a, hipStream_t s);
 size_t l2_d_smem(int max_nL, int n3);
 int set_l2_d_smem_limit(size_t bytes);
-void launch_l2_d(const L2Args &a, int prec, int nsr, size_t smem, hipStream_t s);
+void launch_l2_d(const L2Args &a, int nsr, size_t smem, hipStream_t s);
 // deflation-column bucket of the templated reductions (0, 8, 16, 32, 64)
 int kmax_bucket(int k);
 
