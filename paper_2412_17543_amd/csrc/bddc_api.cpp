@@ -110,7 +110,7 @@ struct bddc_ctx {
     // coarse
     bool three = false;
     double *d_KCinv = nullptr, *d_uC = nullptr;
-    int nsr = 0, n3 = 0, max_nL = 0;
+    int nsr = 0, n3 = 0, max_nL = 0, ld3 = 0;
     int32_t *d_nL = nullptr, *d_nI2 = nullptr, *d_L_off = nullptr, *d_L = nullptr, *d_I2_off = nullptr,
             *d_B2_off = nullptr, *d_g2 = nullptr, *d_asm2_ptr = nullptr, *d_asm2_idx = nullptr,
             *d_pos_sr = nullptr, *d_nc3 = nullptr, *d_C3_off = nullptr, *d_c3 = nullptr,
@@ -125,7 +125,7 @@ struct bddc_ctx {
     double *d_Mc = nullptr, *d_rC = nullptr;
     int64_t ldm = 0;
     int64_t *d_K2_off = nullptr, *d_N2_off = nullptr, *d_P2_off = nullptr;
-    double *d_K2 = nullptr, *d_N2 = nullptr, *d_Phi2 = nullptr, *d_K3inv = nullptr, *d_vI2 = nullptr,
+    double *d_K2 = nullptr, *d_N2 = nullptr, *d_Phi2 = nullptr, *d_K3inv = nullptr, *d_r3 = nullptr, *d_vI2 = nullptr,
            *d_t2 = nullptr, *d_rB2 = nullptr, *d_u2 = nullptr, *d_c3loc = nullptr, *d_u3 = nullptr;
     // deflation / recycling
     int R = 0, k = 0, save_cap = 0, kmax = 0;
@@ -458,10 +458,12 @@ L2Args l2_args(const bddc_ctx *c, const Gather &rc) {
 void run_l2_chain(const bddc_ctx *c, const L2Args &l, hipStream_t st) {
     launch_l2_a(l, c->nsr, c->max_nL, st);
     launch_l2_b(l, c->nsr, c->max_nL, st);
-    L3Args l3{};
-    l3.ctl = c->d_ctl; l3.n = c->n3; l3.ptr = c->d_asm3_ptr; l3.idx = c->d_asm3_idx; l3.loc = c->d_c3loc;
-    l3.Kneg = c->d_K3inv; l3.u = c->d_u3;
-    launch_l3(l3, st);
+    // level 3: r3 = sum of the subregion contributions, u3 = K3^{-1} r3 with
+    // the dense inverse (stored negated, rows padded to ld3)
+    CoarseDenseArgs l3{};
+    l3.ctl = c->d_ctl; l3.n = c->n3; l3.rc = Gather{c->d_asm3_ptr, c->d_asm3_idx, c->d_c3loc}; l3.r = c->d_r3;
+    l3.M = c->d_K3inv; l3.ldm = c->ld3; l3.sign = -1.0; l3.u = c->d_u3;
+    launch_coarse_dense(l3, st);
     launch_l2_d(l, c->nsr, c->smem_l2d, st);
 }
 
@@ -1718,21 +1720,23 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         // level 3: assemble and invert (dense)
         {
             const int n = c->n3;
+            const int ld = c->ld3 = (n + 1) & ~1;      // rows padded to an even length (zero)
             std::vector<std::pair<int64_t, int32_t>> pr;
             for (int j = 0; j < nsr; ++j)
                 for (int a = 0; a < nc3[j]; ++a)
                     for (int b = 0; b < nc3[j]; ++b)
-                        pr.push_back({(int64_t)st.sr[j].c3[a] * n + st.sr[j].c3[b], (int32_t)(K3_off[j] + a * nc3[j] + b)});
+                        pr.push_back({(int64_t)st.sr[j].c3[a] * ld + st.sr[j].c3[b], (int32_t)(K3_off[j] + a * nc3[j] + b)});
             std::vector<int32_t> ptr, idx;
-            build_csr((int64_t)n * n, pr, ptr, idx);
+            build_csr((int64_t)n * ld, pr, ptr, idx);
             int32_t *dp, *di;
             if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) ||
-                (rc = dalloc(c, &c->d_K3inv, (size_t)std::max(1, n * n))))
+                (rc = dalloc(c, &c->d_K3inv, (size_t)std::max<int64_t>(1, (int64_t)n * ld))) ||
+                (rc = dalloc(c, &c->d_r3, (size_t)std::max(1, n))))
                 return rc;
-            launch_gather_sum((int64_t)n * n, dp, di, d_K3loc, c->d_K3inv, s);
+            launch_gather_sum((int64_t)n * ld, dp, di, d_K3loc, c->d_K3inv, s);
             double *drows;
             if ((rc = dalloc(c, &drows, (size_t)std::max(1, 2 * n)))) return rc;
-            launch_sweep_large(c->d_K3inv, n, n, n, drows, c->d_status, s);
+            launch_sweep_large(c->d_K3inv, n, ld, n, drows, c->d_status, s);
             HIPCHK(hipStreamSynchronize(s));
             dfree(c, dp); dfree(c, di); dfree(c, drows);
         }

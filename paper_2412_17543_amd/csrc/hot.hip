@@ -8,7 +8,8 @@
 //   k_update     alpha, x += alpha p, r -= alpha q  lines 9-11
 //   k_symv (N)   stopping test (Section 5); u_i = D N_i D r_i, c_i = (D Phi_i)^T r_i
 //   coarse       k_coarse_dense (two levels, or three levels in explicit form);
-//                three levels as a chain: k_l2_a, k_l2_b, k_l3, k_l2_d
+//                three levels as a chain: k_l2_a, k_l2_b, level 3 by the
+//                dense product, k_l2_d
 //   k_prolong    w_i = u_i + D Phi_i u_C            eq. averaging_subdomain_solves
 //   k_zasm       z = sum_i R_i^T w_i, r^T z, (AW)^T z   line 13
 //   k_pupd       beta, mu, p = z + beta p - W mu    lines 14-16
@@ -820,35 +821,64 @@ __global__ void __launch_bounds__(256) k_coarse_rhs(CoarseDenseArgs a) {
     if (q < a.n) a.r[q] = gather_sum(a.rc, q);
 }
 
-// Dense coarse product u_C = sign * M r_C (row-major M): every block stages
-// r_C in LDS; each wave takes one row of the block's CD_ROWS, lanes striding
-// over the columns in 16-byte pieces, four pieces in flight per lane.
+// Dense coarse product u_C = sign * M r_C (row-major M, rows padded with
+// zeros to the even length ldm): each wave takes one row of the block's
+// CD_ROWS, lanes striding over the columns in 16-byte pieces, four pieces per
+// round.  The first CD_PRE rounds of the row do not depend on r_C and are
+// requested before r_C is staged in LDS; the staging issues all of a
+// thread's loads before waiting for any.  Loads past the row read as zero
+// through the buffer range check, and the staged copy is zero past n.
 constexpr int CD_ROWS = 4;          // rows per block (one per wave)
+constexpr int CD_PRE = 4;           // rounds of 512 columns requested up front
+__host__ __device__ inline int coarse_dense_staged(int ldm) {
+    return ((max(ldm, 512 * CD_PRE) + 511) / 512) * 512;
+}
 __global__ void __launch_bounds__(256) k_coarse_dense(CoarseDenseArgs a) {
     extern __shared__ double rs[];
     if (a.ctl->done) return;
-    const int n = a.n;
-    for (int q = threadIdx.x; q < n; q += blockDim.x) rs[q] = a.r[q];
-    __syncthreads();
+    const int n = a.n, ldm = (int)a.ldm;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int row = blockIdx.x * CD_ROWS + w;
-    if (row >= n) return;
-    const double *m = a.M + (int64_t)row * a.ldm;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    int col = 2 * l;
-    for (; col + 3 * 128 + 1 < n; col += 4 * 128) {
+    const bool live = row < n;
+    const __amdgpu_buffer_rsrc_t mr = tile_rsrc(a.M + (int64_t)(live ? row : 0) * ldm, live ? ldm * 8 : 0);
+    uvec4 pre[4 * CD_PRE];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double2 v = *reinterpret_cast<const double2 *>(m + col + u * 128);
-            s[u] += v.x * rs[col + u * 128] + v.y * rs[col + u * 128 + 1];
+    for (int u = 0; u < 4 * CD_PRE; ++u) pre[u] = __builtin_amdgcn_raw_buffer_load_b128(mr, (2 * l + 128 * u) * 8, 0, 0);
+    const int nr = coarse_dense_staged(ldm);
+    const __amdgpu_buffer_rsrc_t rr = vec_rsrc(a.r, n);
+    for (int q0 = 0; q0 < nr; q0 += 8 * 256) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = ld_rc(rr, q0 + u * 256 + (int)threadIdx.x);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * 256 + (int)threadIdx.x;
+            if (q < nr) rs[q] = v[u];
         }
     }
-    for (; col < n; col += 128) {
-        s[0] += m[col] * rs[col];
-        if (col + 1 < n) s[1] += m[col + 1] * rs[col + 1];
+    __syncthreads();
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < CD_PRE; ++i) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int col = 2 * l + 512 * i + 128 * u;
+            const uvec4 v = pre[4 * i + u];
+            s[u] += __hiloint2double(v.y, v.x) * rs[col] + __hiloint2double(v.w, v.z) * rs[col + 1];
+        }
+    }
+    for (int c0 = 512 * CD_PRE; c0 < ldm; c0 += 512) {
+        uvec4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = __builtin_amdgcn_raw_buffer_load_b128(mr, (2 * l + c0 + 128 * u) * 8, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int col = 2 * l + c0 + 128 * u;
+            s[u] += __hiloint2double(v[u].y, v[u].x) * rs[col] + __hiloint2double(v[u].w, v[u].z) * rs[col + 1];
+        }
     }
     const double t = wave_sum((s[0] + s[1]) + (s[2] + s[3]));
-    if (l == 0) a.u[row] = a.sign * t;
+    if (live && l == 0) a.u[row] = a.sign * t;
 }
 
 // Level 2, phase A (one block per subregion): the subregion's coarse
@@ -889,23 +919,6 @@ __global__ void __launch_bounds__(256) k_l2_b(L2Args a) {
     double *u2 = a.u2 + b2, *c3 = a.c3loc + a.C3_off[j];
     cm_matvec<4>(a.N2 + a.N2_off[j], nB, 0, nB, nB, gs, part, [&](int k, double y) { u2[k] = y; });
     cm_matvec<4>(a.Phi2 + a.P2_off[j], a.nc3[j], 0, a.nc3[j], nB, gs, part, [&](int q, double y) { c3[q] = y; });
-}
-
-// Level 3: r3 = sum of the subregion contributions, u3 = K3^{-1} r3 (dense
-// inverse stored negated); block b computes rows [64b, 64b + 64).
-__global__ void __launch_bounds__(1024) k_l3(L3Args a) {
-    extern __shared__ double rs[];
-    __shared__ double part[16][64];
-    if (a.ctl->done) return;
-    for (int q = threadIdx.x; q < a.n; q += blockDim.x) {
-        double s = 0.0;
-        for (int k = a.ptr[q]; k < a.ptr[q + 1]; ++k) s += a.loc[a.idx[k]];
-        rs[q] = s;
-    }
-    __syncthreads();
-    const int r0 = blockIdx.x * 64, r1 = min(a.n, r0 + 64);
-    double *u = a.u;
-    cm_matvec<16>(a.Kneg, a.n, r0, r1, a.n, rs, part, [&](int r, double y) { u[r] = -y; });
 }
 
 // Level 2, phase D (one block per subregion): level-2 interface solution
@@ -1072,7 +1085,8 @@ void launch_reduce(const ReduceArgs &a, hipStream_t s) {
 void launch_coarse_dense(const CoarseDenseArgs &a, hipStream_t s) {
     if (a.n <= 0) return;
     hipLaunchKernelGGL(k_coarse_rhs, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_coarse_dense, dim3((a.n + CD_ROWS - 1) / CD_ROWS), dim3(256), (size_t)a.n * 8, s, a);
+    hipLaunchKernelGGL(k_coarse_dense, dim3((a.n + CD_ROWS - 1) / CD_ROWS), dim3(256),
+                       (size_t)coarse_dense_staged((int)a.ldm) * 8, s, a);
 }
 
 void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
@@ -1080,10 +1094,6 @@ void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
 }
 void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
     hipLaunchKernelGGL(k_l2_b, dim3(nsr), dim3(256), (size_t)max_nL * 8, s, a);
-}
-void launch_l3(const L3Args &a, hipStream_t s) {
-    if (a.n <= 0) return;
-    hipLaunchKernelGGL(k_l3, dim3((a.n + 63) / 64), dim3(1024), (size_t)a.n * 8, s, a);
 }
 size_t l2_d_smem(int max_nL, int n3) { return (size_t)(std::max(1, max_nL) + std::max(1, n3)) * 8; }
 

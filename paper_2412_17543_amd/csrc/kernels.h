@@ -177,7 +177,8 @@ struct ReduceArgs {                 // out[c] = sum_b part[c * n + b]
 // u_C = sign * M r_C with a dense row-major n x n matrix M (r_C assembled by
 // a first kernel, the product by a second): two levels,
 // M = -K_C^{-1} (sign -1); three levels in explicit form, M = the level-2
-// BDDC operator assembled at setup (sign +1).
+// BDDC operator assembled at setup (sign +1); level 3 of the three-level
+// chain, M = -K_3^{-1} (sign -1).
 struct CoarseDenseArgs {
     Ctl *ctl;
     int n;
@@ -210,14 +211,6 @@ struct L2Args {
     int n3, max_nL;
 };
 
-struct L3Args {                     // level 3: u3 = K3^{-1} r3 (dense)
-    Ctl *ctl;
-    int n;
-    const int32_t *ptr, *idx;
-    const double *loc;
-    const double *Kneg;
-    double *u;
-};
 
 // ====================================================== per-solve kernels
 struct CondArgs {                   // t_i = K_BI y_I, y_I from the interior-product partials
@@ -338,7 +331,6 @@ void launch_reorth(const ReorthArgs &a, int kmax, int grid, hipStream_t s);
 void launch_coarse_dense(const CoarseDenseArgs &a, hipStream_t s);
 void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s);
 void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s);
-void launch_l3(const L3Args &a, hipStream_t s);
 size_t l2_d_smem(int max_nL, int n3);
 int set_l2_d_smem_limit(size_t bytes);
 void launch_l2_d(const L2Args &a, int nsr, size_t smem, hipStream_t s);
