@@ -936,7 +936,19 @@ __global__ void __launch_bounds__(256) k_l2_d(L2Args a) {
     const int j = blockIdx.x;
     const int nL = a.nL[j], nI = a.nI2[j], nB = nL - nI;
     const int b2 = a.B2_off[j];
-    for (int q = threadIdx.x; q < a.n3; q += blockDim.x) u3s[q] = a.u3[q];
+    {   // u3 into LDS, eight loads of a thread in flight at a time
+        const __amdgpu_buffer_rsrc_t ur = vec_rsrc(a.u3, a.n3);
+        for (int q0 = 0; q0 < a.n3; q0 += 8 * 256) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = ld_rc(ur, q0 + u * 256 + (int)threadIdx.x);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = q0 + u * 256 + (int)threadIdx.x;
+                if (q < a.n3) u3s[q] = v[u];
+            }
+        }
+    }
     __syncthreads();
     for (int k = threadIdx.x; k < nB; k += blockDim.x) {
         const int gi = a.g2[b2 + k];
