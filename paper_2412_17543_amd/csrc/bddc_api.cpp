@@ -1612,8 +1612,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
             if ((rc = dupload(c, &c->d_ph_off2, ph_off2)) || (rc = dupload(c, &c->d_c3o, c3o)) ||
                 (rc = dupload(c, &c->d_n3p, n3p)))
                 return rc;
-            c->smem_l2d = l2_d_smem(c->max_nL, c->n3);
-            if (c->smem_l2d > 160 * 1024) return fail(BDDC_EINVAL, "level-3 problem too large for the staged level-2 kernel");
+            c->smem_l2d = l2_d_smem(c->max_nL);
             if (set_l2_d_smem_limit(c->smem_l2d)) return fail(BDDC_EHIP, "hipFuncSetAttribute (dynamic LDS) failed");
         }
         if ((rc = dupload(c, &c->d_nL, nL)) || (rc = dupload(c, &c->d_nI2, nI2)) || (rc = dupload(c, &c->d_nc3, nc3)) ||

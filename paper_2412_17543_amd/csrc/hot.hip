@@ -932,24 +932,9 @@ __global__ void __launch_bounds__(256) k_l2_d(L2Args a) {
     __shared__ double part[4][64];
     if (a.ctl->done) return;
     double *uCL = sm;                 // nL: x_I then x_G
-    double *u3s = sm + a.max_nL;      // n3
     const int j = blockIdx.x;
     const int nL = a.nL[j], nI = a.nI2[j], nB = nL - nI;
     const int b2 = a.B2_off[j];
-    {   // u3 into LDS, eight loads of a thread in flight at a time
-        const __amdgpu_buffer_rsrc_t ur = vec_rsrc(a.u3, a.n3);
-        for (int q0 = 0; q0 < a.n3; q0 += 8 * 256) {
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = ld_rc(ur, q0 + u * 256 + (int)threadIdx.x);
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int q = q0 + u * 256 + (int)threadIdx.x;
-                if (q < a.n3) u3s[q] = v[u];
-            }
-        }
-    }
-    __syncthreads();
     for (int k = threadIdx.x; k < nB; k += blockDim.x) {
         const int gi = a.g2[b2 + k];
         double s = 0.0;
@@ -960,7 +945,7 @@ __global__ void __launch_bounds__(256) k_l2_d(L2Args a) {
             const int n3j = a.n3p[pos];
             double v = a.u2[pos];
 #pragma unroll 8
-            for (int q = 0; q < n3j; ++q) v += ph[q] * u3s[c3[q]];
+            for (int q = 0; q < n3j; ++q) v += ph[q] * a.u3[c3[q]];
             s += v;
         }
         uCL[nI + k] = s;
@@ -1107,7 +1092,7 @@ void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
 void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
     hipLaunchKernelGGL(k_l2_b, dim3(nsr), dim3(256), (size_t)max_nL * 8, s, a);
 }
-size_t l2_d_smem(int max_nL, int n3) { return (size_t)(std::max(1, max_nL) + std::max(1, n3)) * 8; }
+size_t l2_d_smem(int max_nL) { return (size_t)std::max(1, max_nL) * 8; }
 
 int set_l2_d_smem_limit(size_t bytes) {
     if (bytes <= 65536) return 0;

@@ -331,7 +331,7 @@ void launch_reorth(const ReorthArgs &a, int kmax, int grid, hipStream_t s);
 void launch_coarse_dense(const CoarseDenseArgs &a, hipStream_t s);
 void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s);
 void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s);
-size_t l2_d_smem(int max_nL, int n3);
+size_t l2_d_smem(int max_nL);
 int set_l2_d_smem_limit(size_t bytes);
 void launch_l2_d(const L2Args &a, int nsr, size_t smem, hipStream_t s);
 // deflation-column bucket of the templated reductions (0, 8, 16, 32, 64)
