@@ -823,22 +823,23 @@ __global__ void __launch_bounds__(256) k_coarse_rhs(CoarseDenseArgs a) {
 
 // Dense coarse product u_C = sign * M r_C (row-major M, rows padded with
 // zeros to the even length ldm): each wave takes one row of the block's
-// CD_ROWS, lanes striding over the columns in 16-byte pieces, four pieces per
-// round.  The first CD_PRE rounds of the row do not depend on r_C and are
+// ROWS, lanes striding over the columns in 16-byte pieces, four pieces per
+// round (8 rows per block above 4096 columns, where the staged r_C limits the
+// blocks per compute unit, else 4).  The first CD_PRE rounds of the row do not depend on r_C and are
 // requested before r_C is staged in LDS; the staging issues all of a
 // thread's loads before waiting for any.  Loads past the row read as zero
 // through the buffer range check, and the staged copy is zero past n.
-constexpr int CD_ROWS = 4;          // rows per block (one per wave)
 constexpr int CD_PRE = 4;           // rounds of 512 columns requested up front
 __host__ __device__ inline int coarse_dense_staged(int ldm) {
     return ((max(ldm, 512 * CD_PRE) + 511) / 512) * 512;
 }
-__global__ void __launch_bounds__(256) k_coarse_dense(CoarseDenseArgs a) {
+template <int ROWS>
+__global__ void __launch_bounds__(ROWS * 64) k_coarse_dense(CoarseDenseArgs a) {
     extern __shared__ double rs[];
     if (a.ctl->done) return;
     const int n = a.n, ldm = (int)a.ldm;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int row = blockIdx.x * CD_ROWS + w;
+    const int row = blockIdx.x * ROWS + w;
     const bool live = row < n;
     const __amdgpu_buffer_rsrc_t mr = tile_rsrc(a.M + (int64_t)(live ? row : 0) * ldm, live ? ldm * 8 : 0);
     uvec4 pre[4 * CD_PRE];
@@ -846,13 +847,14 @@ __global__ void __launch_bounds__(256) k_coarse_dense(CoarseDenseArgs a) {
     for (int u = 0; u < 4 * CD_PRE; ++u) pre[u] = __builtin_amdgcn_raw_buffer_load_b128(mr, (2 * l + 128 * u) * 8, 0, 0);
     const int nr = coarse_dense_staged(ldm);
     const __amdgpu_buffer_rsrc_t rr = vec_rsrc(a.r, n);
-    for (int q0 = 0; q0 < nr; q0 += 8 * 256) {
+    constexpr int NT = ROWS * 64;
+    for (int q0 = 0; q0 < nr; q0 += 8 * NT) {
         double v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = ld_rc(rr, q0 + u * 256 + (int)threadIdx.x);
+        for (int u = 0; u < 8; ++u) v[u] = ld_rc(rr, q0 + u * NT + (int)threadIdx.x);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int q = q0 + u * 256 + (int)threadIdx.x;
+            const int q = q0 + u * NT + (int)threadIdx.x;
             if (q < nr) rs[q] = v[u];
         }
     }
@@ -1082,8 +1084,9 @@ void launch_reduce(const ReduceArgs &a, hipStream_t s) {
 void launch_coarse_dense(const CoarseDenseArgs &a, hipStream_t s) {
     if (a.n <= 0) return;
     hipLaunchKernelGGL(k_coarse_rhs, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_coarse_dense, dim3((a.n + CD_ROWS - 1) / CD_ROWS), dim3(256),
-                       (size_t)coarse_dense_staged((int)a.ldm) * 8, s, a);
+    const size_t smem = (size_t)coarse_dense_staged((int)a.ldm) * 8;
+    if (a.n > 4096) hipLaunchKernelGGL(k_coarse_dense<8>, dim3((a.n + 7) / 8), dim3(512), smem, s, a);
+    else hipLaunchKernelGGL(k_coarse_dense<4>, dim3((a.n + 3) / 4), dim3(256), smem, s, a);
 }
 
 void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
