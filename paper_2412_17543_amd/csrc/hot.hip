@@ -524,25 +524,72 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs a) {
 // subdomain: w_i = u_i + (D Phi_i) u_C|_i, u_i summed from the partial
 // products of the Neumann operator's work items.
 // ---------------------------------------------------------------------------
+// Element i of a T array through a buffer resource (zero past its end).
+template <typename T>
+__device__ __forceinline__ double ld_rc_as(__amdgpu_buffer_rsrc_t r, int i);
+template <>
+__device__ __forceinline__ double ld_rc_as<double>(__amdgpu_buffer_rsrc_t r, int i) { return ld_rc(r, i); }
+template <>
+__device__ __forceinline__ double ld_rc_as<float>(__amdgpu_buffer_rsrc_t r, int i) {
+    return (double)__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, 0));
+}
+template <>
+__device__ __forceinline__ double ld_rc_as<uint16_t>(__amdgpu_buffer_rsrc_t r, int i) {
+    return (double)dev::bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, i * 2, 0, 0));
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong(ProlArgs a) {
     extern __shared__ double uCl[];
+    constexpr int PF = 16, CF = 4;      // basis entries / partials of a row requested early
     if (a.gated && a.ctl->done) return;
     const int i = blockIdx.x;
     const int n = a.nB[i], C = a.nchunk[i];
     const int nci = a.uC ? a.nc[i] : 0;
     const int32_t *ci = a.cidx + a.c_off[i];
-    for (int q = threadIdx.x; q < nci; q += blockDim.x) uCl[q] = a.uC[ci[q]];
-    __syncthreads();
     const T *ph = reinterpret_cast<const T *>(a.phir) + a.phr_off[i];
     const double *up = a.upart + a.pb[i];
     double *wl = a.wloc + a.b_off[i];
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    // The first CF partial sums and PF basis entries of this thread's first
+    // two rows do not depend on u_C: they are requested before its gather,
+    // through range-checked loads (no conditions; entries past the
+    // subdomain's arrays read as zero, other rows' entries are not used).
+    const __amdgpu_buffer_rsrc_t ur = vec_rsrc(up, (int64_t)C * n);
+    const __amdgpu_buffer_rsrc_t pr = tile_rsrc(ph, n * nci * (int)sizeof(T));
+    const int k0 = threadIdx.x, k1 = threadIdx.x + 256;
+    double u0[CF], u1[CF], r0[PF], r1[PF];
+#pragma unroll
+    for (int cc = 0; cc < CF; ++cc) {
+        u0[cc] = ld_rc(ur, cc * n + k0);
+        u1[cc] = ld_rc(ur, cc * n + k1);
+    }
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        r0[q] = ld_rc_as<T>(pr, k0 * nci + q);
+        r1[q] = ld_rc_as<T>(pr, k1 * nci + q);
+    }
+    for (int q = threadIdx.x; q < nci; q += blockDim.x) uCl[q] = a.uC[ci[q]];
+    __syncthreads();
+    // w = sum of the partials, then the basis terms, in column order
+    auto row = [&](int k, const double (&u)[CF], const double (&r)[PF]) {
+        double w = 0.0;
+        for (int cc = 0; cc < C; ++cc) w += cc < CF ? u[cc] : up[(int64_t)cc * n + k];
+        const T *rk = ph + (int64_t)k * nci;
+#pragma unroll
+        for (int q = 0; q < PF; ++q)
+            if (q < nci) w += r[q] * uCl[q];
+#pragma unroll 8
+        for (int q = PF; q < nci; ++q) w += to_d(rk[q]) * uCl[q];
+        wl[k] = w;
+    };
+    if (k0 < n) row(k0, u0, r0);
+    if (k1 < n) row(k1, u1, r1);
+    for (int k = threadIdx.x + 512; k < n; k += blockDim.x) {
         double w = 0.0;
         for (int cc = 0; cc < C; ++cc) w += up[(int64_t)cc * n + k];
-        const T *row = ph + (int64_t)k * nci;
+        const T *rk = ph + (int64_t)k * nci;
 #pragma unroll 8
-        for (int q = 0; q < nci; ++q) w += to_d(row[q]) * uCl[q];
+        for (int q = 0; q < nci; ++q) w += to_d(rk[q]) * uCl[q];
         wl[k] = w;
     }
 }
