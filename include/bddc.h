@@ -91,10 +91,12 @@ typedef struct {
     int32_t init_guess;      /* 0: previous solution (default), 1: zero                 */
     int32_t max_it;          /* per right-hand side, e.g. 1000                          */
     int32_t save_cap;        /* max search directions stored per solve for recycling   */
-    int32_t use_graph;       /* 1 (default): the iteration is captured once as a
-                                hipGraph and replayed, the convergence flag polled
-                                asynchronously; 0: kernels launched one by one with
-                                a host check after every iteration                     */
+    int32_t use_graph;       /* iterations launched in groups of two, queued ahead of
+                                an asynchronous poll of the convergence flag:
+                                2 (default) kernel by kernel into the stream;
+                                1 as replays of a hipGraph captured once;
+                                0: one iteration at a time with a host check after
+                                every iteration (plain form); other values EINVAL    */
     int32_t autotune;        /* 1 (default): time a few work-list sizes, waves per
                                 block and tiles in flight of the two batched operator
                                 products at setup and keep the fastest; 0: fixed     */

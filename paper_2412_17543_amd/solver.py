@@ -26,7 +26,11 @@ class Solver:
 
     Parameters mirror ``bddc_setup``: element partition (and optional
     subdomain->subregion grouping for three levels), element coefficients,
-    optional element keep mask (holes) and Dirichlet node mask.
+    optional element keep mask (holes) and Dirichlet node mask.  ``use_graph``
+    selects how iterations are launched: "queued" (or True, the default:
+    kernels queued ahead of an asynchronous convergence poll), "graph" (the
+    same with replays of a captured hipGraph) or "plain" (or False: a host
+    check after every iteration).
     """
 
     def __init__(self, nx, elem_to_sub, coef, sub_to_subregion=None, elem_keep=None,
@@ -76,7 +80,7 @@ class Solver:
         o.init_guess = {"prev": 0, "zero": 1}[init_guess]
         o.max_it = max_it
         o.save_cap = save_cap
-        o.use_graph = 1 if use_graph else 0
+        o.use_graph = {True: 2, False: 0, "queued": 2, "graph": 1, "plain": 0}[use_graph]
         o.autotune = 1 if autotune else 0
         o.coarse_form = {"auto": 0, "chain": 1, "explicit": 2}[coarse_form]
         o.reorth = 1 if reorth else 0

@@ -52,16 +52,19 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("name,R", [("c16", 6), ("tiny3", 8)])
-def test_graph_form_equals_kernel_by_kernel_form(name, R):
+def test_launch_forms_agree_bitwise(name, R):
+    """Queued stream launches (the default), graph replays and the plain
+    kernel-by-kernel form run the same kernels in the same order."""
     torch = _torch()
     s = workload.workload(name)
     F = torch.tensor(workload.rhs_sequence(s["nx"], 4), device="cuda")
     # fixed work lists: the autotuner may pick different ones per context,
     # which changes the (deterministic) summation order
-    U1, it1, rr1 = _solver(name, R=R, use_graph=True, autotune=False).solve_sequence(F, 1e-10)
-    U2, it2, rr2 = _solver(name, R=R, use_graph=False, autotune=False).solve_sequence(F, 1e-10)
-    np.testing.assert_array_equal(it1, it2)
-    assert torch.equal(U1, U2)
+    U0, it0, _ = _solver(name, R=R, use_graph="plain", autotune=False).solve_sequence(F, 1e-10)
+    for form in ("queued", "graph"):
+        U1, it1, _ = _solver(name, R=R, use_graph=form, autotune=False).solve_sequence(F, 1e-10)
+        np.testing.assert_array_equal(it1, it0)
+        assert torch.equal(U1, U0), form
 
 
 def test_repeated_sequence_is_bitwise_reproducible():
