@@ -78,7 +78,7 @@ def run_form(torch, Solver, s, F, rtol, steps, warmup, local_prec, timing, use_g
     st = None
     if timing:
         # one more sequence, launched kernel by kernel with HIP events around
-        # every operator product (graph replay cannot be bracketed per kernel)
+        # every operator product (queued launches cannot be bracketed per kernel)
         g.enable_timing(True, ("schur", "precond_local"))
         g.reset_recycle()
         g.solve_sequence(F, rtol)

@@ -32,8 +32,8 @@ int fail(int code, const std::string &msg) {
 
 enum { TK_SCHUR = 0, TK_PREC, TK_COARSE, TK_VEC, TK_COND, TK_REC, TK_N };
 
-constexpr int GRAPH_ITERS = 2;     // iterations per captured graph
-constexpr int GRAPH_INFLIGHT = 2;  // graphs queued ahead of the convergence poll
+constexpr int GRAPH_ITERS = 2;     // iterations per queued group (and per captured graph)
+constexpr int GRAPH_INFLIGHT = 2;  // groups queued ahead of the convergence poll
 
 // Host view of one batch of operators and its work list.
 struct OpHost {
@@ -163,7 +163,7 @@ struct bddc_ctx {
     int32_t *d_status = nullptr;
     bool have_solve = false, have_hist = false;
     int last_iters = 0, last_restarts = 0, last_status = 0;
-    // graph of GRAPH_ITERS iterations
+    // graph of GRAPH_ITERS iterations (use_graph 1)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipEvent_t gev[GRAPH_INFLIGHT + 1] = {};
@@ -645,10 +645,10 @@ int run_loop(bddc_ctx *c) {
                 if (int rc = wait_one()) return rc;
                 if (*flag) break;
                 if (launched >= cap) break;   // every kernel stops at max_it by itself
-                // The residual after the polled graph and its decay per
-                // iteration predict whether the graphs still queued reach the
+                // The residual after the polled group and its decay per
+                // iteration predict whether the groups still queued reach the
                 // tolerance; if so, wait for them before queuing another (a
-                // graph queued past convergence costs its launches for nothing).
+                // group queued past convergence costs its launches for nothing).
                 const double rr = prog[0], den = prog[1], it = prog[2];
                 if (last_it >= 0.0 && it > last_it && rr > 0.0 && last_rr > 0.0 && rr < last_rr)
                     rate = std::pow(rr / last_rr, 1.0 / (it - last_it));
