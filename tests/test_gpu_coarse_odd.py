@@ -45,3 +45,23 @@ def test_odd_coarse_dimension_matches_oracle(cons, nc):
     assert np.all(rr < 1e-10)
     for k in range(len(F)):
         assert _rel(U[k].cpu().numpy(), uo[k]) <= 1e-9
+
+
+@pytest.mark.parametrize("cons", [("corners", "faces"), ("corners",)])
+def test_three_level_chain_matches_oracle(cons):
+    """Three levels applied as the subregion chain (level 3 through the same
+    dense product on the padded K_3^{-1}; 3 level-3 DOFs here, an odd count)."""
+    torch = _torch()
+    from oracle.sequence import OracleSolver
+    from paper_2412_17543_amd.solver import Solver
+    s = workload.workload("c3s")
+    g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"],
+               elem_keep=s["elem_keep"], constraints=cons, coarse_form="chain")
+    print("[gpu] c3s three-level chain %s: %s" % (cons, g.info()), flush=True)
+    o = OracleSolver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"],
+                     elem_keep=s["elem_keep"], constraints=cons)
+    rng = np.random.default_rng(6)
+    for _ in range(2):
+        r = rng.standard_normal(o.ss.n_gamma)
+        z = g.apply_precond(torch.tensor(r, device="cuda")).cpu().numpy()
+        assert _rel(z, o.M.apply(r)) < 1e-9
