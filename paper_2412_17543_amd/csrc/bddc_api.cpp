@@ -91,6 +91,8 @@ struct bddc_ctx {
             *d_c_off = nullptr, *d_gB = nullptr, *d_nodesI = nullptr, *d_cidx = nullptr, *d_gamma = nullptr,
             *d_pos_sub = nullptr, *d_cpos_sub = nullptr;
     int64_t *d_k_off = nullptr, *d_s_off = nullptr, *d_n_off = nullptr, *d_phr_off = nullptr;
+    int32_t *d_pch_sub = nullptr, *d_pch_row = nullptr;   // prolongation blocks: subdomain, first row
+    int n_pch = 0;
     double *d_K = nullptr, *d_S = nullptr, *d_KC = nullptr;
     void *d_N = nullptr, *d_phir = nullptr;
     int32_t *d_asm_ptr = nullptr, *d_asm_idx = nullptr, *d_casm_ptr = nullptr, *d_casm_idx = nullptr;
@@ -513,7 +515,8 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
         pa.phir = c->d_phir; pa.phr_off = c->d_phr_off;
         pa.uC = c->nC > 0 ? c->d_uC : nullptr;
         pa.wloc = c->d_wloc;
-        launch_prolong(pa, c->prec, c->n_sub, c->max_nc, c->stream);
+        pa.ch_sub = c->d_pch_sub; pa.ch_row = c->d_pch_row;
+        launch_prolong(pa, c->prec, c->n_pch, c->max_nc, c->stream);
         ZasmArgs a{};
         a.n = c->n_gamma;
         a.w.ptr = c->d_asm_ptr; a.w.idx = c->d_asm_idx; a.w.part = c->d_wloc;
@@ -1443,6 +1446,13 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         max_nloc = std::max(max_nloc, sh.nloc);
     }
     if (b_off[nsub] > INT32_MAX / 2) return fail(BDDC_EINVAL, "too many local interface entries");
+    {   // prolongation blocks: 512 interface rows of one subdomain each
+        std::vector<int32_t> ch_sub, ch_row;
+        for (int i = 0; i < nsub; ++i)
+            for (int r = 0; r == 0 || r < nB[i]; r += 512) { ch_sub.push_back(i); ch_row.push_back(r); }
+        c->n_pch = (int)ch_sub.size();
+        if ((rc = dupload(c, &c->d_pch_sub, ch_sub)) || (rc = dupload(c, &c->d_pch_row, ch_row))) return rc;
+    }
     c->h_nB = nB; c->h_nI = nI; c->h_nc = nc; c->h_pos_sub = pos_sub; c->h_cpos_sub = cpos_sub;
     c->h_b_off.assign(b_off.begin(), b_off.end() - 1);
     c->h_c_off.assign(c_off.begin(), c_off.end() - 1);

@@ -543,7 +543,8 @@ __global__ void __launch_bounds__(256) k_prolong(ProlArgs a) {
     extern __shared__ double uCl[];
     constexpr int PF = 16, CF = 4;      // basis entries / partials of a row requested early
     if (a.gated && a.ctl->done) return;
-    const int i = blockIdx.x;
+    // 512 rows of one subdomain per block (large subdomains take several)
+    const int i = a.ch_sub[blockIdx.x], r0 = a.ch_row[blockIdx.x];
     const int n = a.nB[i], C = a.nchunk[i];
     const int nci = a.uC ? a.nc[i] : 0;
     const int32_t *ci = a.cidx + a.c_off[i];
@@ -556,8 +557,8 @@ __global__ void __launch_bounds__(256) k_prolong(ProlArgs a) {
     // subdomain's arrays read as zero, other rows' entries are not used).
     const __amdgpu_buffer_rsrc_t ur = vec_rsrc(up, (int64_t)C * n);
     const __amdgpu_buffer_rsrc_t pr = tile_rsrc(ph, n * nci * (int)sizeof(T));
-    const int k0 = threadIdx.x, k1 = threadIdx.x + 256;
-    double u0[CF], u1[CF], r0[PF], r1[PF];
+    const int k0 = r0 + threadIdx.x, k1 = r0 + threadIdx.x + 256;
+    double u0[CF], u1[CF], pr0[PF], pr1[PF];
 #pragma unroll
     for (int cc = 0; cc < CF; ++cc) {
         u0[cc] = ld_rc(ur, cc * n + k0);
@@ -565,8 +566,8 @@ __global__ void __launch_bounds__(256) k_prolong(ProlArgs a) {
     }
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
-        r0[q] = ld_rc_as<T>(pr, k0 * nci + q);
-        r1[q] = ld_rc_as<T>(pr, k1 * nci + q);
+        pr0[q] = ld_rc_as<T>(pr, k0 * nci + q);
+        pr1[q] = ld_rc_as<T>(pr, k1 * nci + q);
     }
     for (int q = threadIdx.x; q < nci; q += blockDim.x) uCl[q] = a.uC[ci[q]];
     __syncthreads();
@@ -582,16 +583,8 @@ __global__ void __launch_bounds__(256) k_prolong(ProlArgs a) {
         for (int q = PF; q < nci; ++q) w += to_d(rk[q]) * uCl[q];
         wl[k] = w;
     };
-    if (k0 < n) row(k0, u0, r0);
-    if (k1 < n) row(k1, u1, r1);
-    for (int k = threadIdx.x + 512; k < n; k += blockDim.x) {
-        double w = 0.0;
-        for (int cc = 0; cc < C; ++cc) w += up[(int64_t)cc * n + k];
-        const T *rk = ph + (int64_t)k * nci;
-#pragma unroll 8
-        for (int q = 0; q < nci; ++q) w += to_d(rk[q]) * uCl[q];
-        wl[k] = w;
-    }
+    if (k0 < n) row(k0, u0, pr0);
+    if (k1 < n) row(k1, u1, pr1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1053,11 +1046,11 @@ void launch_update(const UpdArgs &a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_update, dim3(grid), dim3(256), 0, s, a);
 }
 
-void launch_prolong(const ProlArgs &a, int prec, int nsub, int max_nc, hipStream_t s) {
+void launch_prolong(const ProlArgs &a, int prec, int nblocks, int max_nc, hipStream_t s) {
     const size_t smem = (size_t)std::max(1, max_nc) * 8;
-    if (prec == 64) hipLaunchKernelGGL(k_prolong<double>, dim3(nsub), dim3(256), smem, s, a);
-    else if (prec == 32) hipLaunchKernelGGL(k_prolong<float>, dim3(nsub), dim3(256), smem, s, a);
-    else hipLaunchKernelGGL(k_prolong<uint16_t>, dim3(nsub), dim3(256), smem, s, a);
+    if (prec == 64) hipLaunchKernelGGL(k_prolong<double>, dim3(nblocks), dim3(256), smem, s, a);
+    else if (prec == 32) hipLaunchKernelGGL(k_prolong<float>, dim3(nblocks), dim3(256), smem, s, a);
+    else hipLaunchKernelGGL(k_prolong<uint16_t>, dim3(nblocks), dim3(256), smem, s, a);
 }
 
 int kmax_bucket(int k) { return k == 0 ? 0 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }

@@ -105,6 +105,7 @@ struct ProlArgs {                   // w_i = u_i + D Phi_i u_C (eq. averaging_su
     const int64_t *phr_off;
     const double *uC;               // level-1 coarse solution (nullable: no coarse space)
     double *wloc;
+    const int32_t *ch_sub, *ch_row; // block b: subdomain ch_sub[b], rows ch_row[b] .. +511
 };
 
 struct ZasmArgs {                   // z = sum_i R_i^T w_i, rho, (AW)^T z
@@ -321,7 +322,7 @@ size_t symv_smem(int prec, int nw, int max_nt, int max_ntc);
 int set_symv_smem_limit(size_t bytes);
 void launch_symv(const SymvArgs &a, int prec, SymvCfg cfg, size_t smem, hipStream_t s);
 void launch_update(const UpdArgs &a, int grid, hipStream_t s);
-void launch_prolong(const ProlArgs &a, int prec, int nsub, int max_nc, hipStream_t s);
+void launch_prolong(const ProlArgs &a, int prec, int nblocks, int max_nc, hipStream_t s);
 void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s);
 void launch_pupd(const PupdArgs &a, int kmax, int grid, hipStream_t s);
 void launch_resid(const ResidArgs &a, int kmax, int grid, hipStream_t s);
