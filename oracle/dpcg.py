@@ -24,6 +24,17 @@ iteration count is the number of loop passes (= products with A inside the
 loop).  After exit the true residual b - A x is evaluated; if it does not meet
 the tolerance the residual is replaced by it and the iteration continues
 (counted), up to max_it.
+
+Recycling after a residual replacement (a reading: Section 4.2 keeps "some of"
+the search vectors and never meets a replacement): ``seg_start`` is the index of
+the first search direction after the last replacement, so that the directions
+offered for recycling, P[seg_start:], come from one unbroken run of Algorithm 1
+with the same W.
+
+``restart_every`` (not in the paper; 0 = off) ends a run after that many
+passes without convergence: the true residual is then evaluated and, unless it
+meets the tolerance, replaces the recursive one and the iteration restarts
+from line 5, as after a residual replacement.
 """
 from __future__ import annotations
 
@@ -31,7 +42,7 @@ import numpy as np
 
 
 def dpcg(apply_A, apply_M, b, x_init=None, W=None, rtol=1e-8, max_it=1000,
-         stop="rhs", reorth=False, record=True):
+         stop="rhs", reorth=False, record=True, restart_every=0):
     n = b.size
     if W is None:
         W = np.zeros((n, 0))
@@ -44,7 +55,7 @@ def dpcg(apply_A, apply_M, b, x_init=None, W=None, rtol=1e-8, max_it=1000,
         return np.linalg.solve(WAW, v) if k else np.zeros(0)
 
     out = dict(alpha=[], beta=[], rho=[], d=[], mu=[], relres=[], P=[], AP=[],
-               wtr=[], wtap=[], restarts=0)
+               wtr=[], wtap=[], restarts=0, seg_start=0)
     nb = np.linalg.norm(b)
     x = np.zeros(n) if x_init is None else np.asarray(x_init, dtype=np.float64).copy()
     if nb == 0.0:
@@ -76,6 +87,7 @@ def dpcg(apply_A, apply_M, b, x_init=None, W=None, rtol=1e-8, max_it=1000,
             rho = r @ z
             out["rho"].append(rho)
             out["mu"].append(mu)
+            run_start = it
             while it < max_it:
                 Ap = apply_A(p)
                 d = p @ Ap
@@ -95,7 +107,7 @@ def dpcg(apply_A, apply_M, b, x_init=None, W=None, rtol=1e-8, max_it=1000,
                     # rounding in W^T r stays at eps*||r_0||, so normalise by ||r_0||
                     out["wtr"].append(np.linalg.norm(W.T @ r) / (np.linalg.norm(W) * r0n))
                     out["wtap"].append(np.linalg.norm(AW.T @ p) / (np.linalg.norm(AW) * np.linalg.norm(p)))
-                if converged(r):
+                if converged(r) or 0 < restart_every <= it - run_start:
                     break
                 z = apply_M(r)                                    # line 13
                 rho_new = r @ z
@@ -112,6 +124,7 @@ def dpcg(apply_A, apply_M, b, x_init=None, W=None, rtol=1e-8, max_it=1000,
             break
         r = true_r                                                # residual replacement
         out["restarts"] += 1
+        out["seg_start"] = len(out["alpha"])
         done = False
     out.update(x=x, iters=it, true_relres=tr)
     return out

@@ -28,6 +28,22 @@ from __future__ import annotations
 import numpy as np
 
 
+def select(theta, R, strategy):
+    """Indices of the harmonic Ritz values kept (Section 4.2, paragraphs B3 and
+    B4): the R largest for B4, the R smallest for B3, ordered from the kept end
+    of the spectrum (descending for B4, ascending for B3); all of them when
+    there are at most R."""
+    order = np.argsort(-theta, kind="stable") if strategy == "B4" else np.argsort(theta, kind="stable")
+    return order[:R]
+
+
+def ritz_change(theta_new, theta_old):
+    """Left-hand side of eq. harmritzstopcrit: the 2-norm of the change of the
+    selected (sorted) harmonic Ritz values relative to the 2-norm of the new
+    ones."""
+    return np.linalg.norm(theta_new - theta_old) / np.linalg.norm(theta_new)
+
+
 class Recycler:
     def __init__(self, R, strategy="B4", freeze_tol=1e-5, drop_tol=1e-12):
         self.R = int(R)
@@ -79,13 +95,12 @@ class Recycler:
         if V.shape[1] == 0:
             return
         theta, Y, _, _ = self.harmonic_ritz(V, apply_A, apply_M, self.drop_tol)
-        order = np.argsort(-theta) if self.strategy == "B4" else np.argsort(theta)
-        sel = order[: self.R]
+        sel = select(theta, self.R, self.strategy)
         th = theta[sel]
         self.W = V @ Y[:, sel]
         self.history.append(th.copy())
         if self.theta is not None and th.size == self.R and self.theta.size == self.R:
-            if np.linalg.norm(th - self.theta) / np.linalg.norm(th) <= self.freeze_tol:
+            if ritz_change(th, self.theta) <= self.freeze_tol:
                 self.frozen = True
                 self.freeze_step = self.step
         self.theta = th

@@ -19,13 +19,14 @@ class OracleSolver:
     def __init__(self, nx, elem_to_sub, coef, elem_keep=None, sub_to_subregion=None,
                  weight_kind="diag", constraints=("corners", "faces"), R=0, strategy="B4",
                  freeze_tol=1e-5, stop="rhs", init_guess="prev", all_corners=False, reorth=False,
-                 adaptive=None):
+                 adaptive=None, restart_every=0):
         self.ss = Substructuring(nx, elem_to_sub, coef, elem_keep)
         self.M = BDDC(self.ss, weight_kind, constraints, sub_to_subregion, all_corners, adaptive)
         self.rec = Recycler(R, strategy, freeze_tol)
         self.stop = stop
         self.init_guess = init_guess
         self.reorth = reorth
+        self.restart_every = restart_every
         self.x_prev = np.zeros(self.ss.n_gamma)
 
     def reset(self):
@@ -37,10 +38,12 @@ class OracleSolver:
         b = ss.condense(F)
         W = self.rec.basis(ss.n_gamma)
         x0 = self.x_prev if self.init_guess == "prev" else np.zeros(ss.n_gamma)
-        res = dpcg(ss.apply_A, self.M.apply, b, x0, W, rtol, max_it, self.stop, reorth=self.reorth)
+        res = dpcg(ss.apply_A, self.M.apply, b, x0, W, rtol, max_it, self.stop, reorth=self.reorth,
+                   restart_every=self.restart_every)
         self.x_prev = res["x"]
         if update:
-            P = np.column_stack(res["P"]) if res["P"] else np.zeros((ss.n_gamma, 0))
+            Ps = res["P"][res["seg_start"]:]            # the run after the last replacement
+            P = np.column_stack(Ps) if Ps else np.zeros((ss.n_gamma, 0))
             self.rec.update(P, ss.apply_A, self.M.apply)
         res["u"] = ss.recover(res["x"], F)
         res["b"] = b

@@ -82,3 +82,39 @@ def test_wrong_side_of_the_pencil_is_caught(monkeypatch):
                         lambda ss, D, s, t: np.eye(orig(ss, D, s, t).shape[0]) - orig(ss, D, s, t))
     with pytest.raises(AssertionError):
         ta.test_two_subdomain_face_bound(2.0)
+
+
+# ------------------------------------------------ recycling (Section 4.2)
+
+def test_b3_b4_swap_is_caught(monkeypatch):
+    from oracle import recycle
+    from tests import test_oracle_recycle_pins as tr
+    orig = recycle.select
+    monkeypatch.setattr(recycle, "select",
+                        lambda theta, R, strategy: orig(theta, R, "B3" if strategy == "B4" else "B4"))
+    with pytest.raises(AssertionError):
+        tr.test_selection_on_invariant_subspace("B4")
+
+
+def _freeze_pins(tr):
+    tr.test_freeze_threshold_uniform_scaling(1.000005e-5, True)
+    tr.test_freeze_threshold_uniform_scaling(1.00002e-5, False)
+    tr.test_freeze_threshold_uses_two_norms(1.2e-5, True)
+    tr.test_freeze_threshold_uses_two_norms(2.0e-5, False)
+
+
+@pytest.mark.parametrize("mistake", ["old_denominator", "max_norm", "one_norm", "unsorted"])
+def test_freeze_criterion_mistakes_are_caught(monkeypatch, mistake):
+    from oracle import recycle
+    from tests import test_oracle_recycle_pins as tr
+    if mistake == "old_denominator":
+        bad = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    elif mistake == "max_norm":
+        bad = lambda a, b: np.abs(a - b).max() / np.abs(a).max()
+    elif mistake == "one_norm":
+        bad = lambda a, b: np.abs(a - b).sum() / np.abs(a).sum()
+    else:   # new values compared in the opposite order to the stored ones
+        bad = lambda a, b: np.linalg.norm(a[::-1] - b) / np.linalg.norm(a)
+    monkeypatch.setattr(recycle, "ritz_change", bad)
+    with pytest.raises(AssertionError):
+        _freeze_pins(tr)
