@@ -1,23 +1,39 @@
 #!/usr/bin/env python
 """Throughput of the deflated-PCG / three-level BDDC sequence solve on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c192|c64|c3|c96]
 
-Workload (synthetic, seeded): Q1 Poisson on the unit cube, 64^3 elements
-(274,625 nodes), Dirichlet u = 0 on x = 1, unit coefficient, 8^3 = 512 cube
-subdomains of 8^3 elements, three-level BDDC (subregions of 2x2x2
-subdomains, corners + face averages, diag weights), deflated PCG with a
-20-vector basis recycled by B4 harmonic Ritz vectors, previous-solution
-initial guess, ||r||/||b|| < 1e-8, a 50-step drifting-Gaussian right-hand-side
-sequence.  One step = one 50-RHS sequence from an empty basis (setup
-excluded); value = right-hand sides solved per second in float64.  The same
-line reports the mixed form (float32 local Neumann operators) on the same
-sequence, the roofline of the dominant kernel and the oracle on the host CPU.
+Default workload (synthetic, seeded): Q1 Poisson on the unit cube, 192^3
+elements (7,189,057 nodes), Dirichlet u = 0 on x = 1, unit coefficient,
+24^3 = 13,824 cube subdomains of 8^3 elements, three-level BDDC (1,728
+subregions of 2x2x2 subdomains), adaptive face constraints (tau = 10, at most
+10 per face), deflated PCG with a 40-vector basis recycled by B4 harmonic
+Ritz vectors, previous-solution initial guess, ||r||/||b|| < 1e-8, a
+200-step drifting-Gaussian right-hand-side sequence.
+
+One step = 10 consecutive right-hand sides of that sequence, solved with the
+recycling state carried from step to step, so 20 steps are the whole
+200-step sequence from an empty basis (warm-up steps run the sequence's first
+right-hand sides, then the basis is reset).  Setup is excluded; inputs are in
+HBM before timing.  `value` = right-hand sides solved per second in the
+configuration's own form: float32 local Neumann operators (N_i, Phi_i),
+everything else float64.  The same line reports the float64 form, the
+bfloat16 form and the plain float64 form (kernel by kernel, host check after
+every iteration, untuned products) on the same operators and sequence, the
+roofline of the dominant kernel and of the preconditioner application, and
+the oracle on the host CPU.
+
+Other workloads (their own lines): c64 (64^3, 512 subdomains, R = 20, 50 RHS,
+float64), c3 (64^3 with a spherical hole, 400 uneven subdomains, log-normal
+coefficients, float32 Neumann operators), c96 (96^3, 1,728 subdomains, 20 RHS,
+float64; --adjoint times the adjoint gradient too).  For these a step is the
+whole sequence.
 """
 import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -25,15 +41,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+METRIC = "solves/s to FP64 rtol 1e-8 + HBM GB/s, mixed vs FP64 BDDC-DPCG, 1 GPU"
 WORKLOADS = {
-    "c64": "Q1 Poisson 64^3 elements (274,625 nodes), 512 subdomains of 8^3, three-level BDDC (64 subregions), "
-           "deflated PCG B4 R=20, 50 drifting-Gaussian right-hand sides, rtol 1e-8",
-    "c3": "Q1 Poisson 64^3 elements minus a sphere of radius 0.15, 400 jittered-RCB subdomains of uneven size, "
-          "log-normal coefficients (sigma 0.5), three-level BDDC (50 subregions), deflated PCG B4 R=20, "
-          "50 drifting-Gaussian right-hand sides, rtol 1e-8",
-    "c96": "Q1 Poisson 96^3 elements (912,673 nodes), 1,728 subdomains of 8^3, three-level BDDC (216 subregions), "
-           "deflated PCG B4 R=20, 20 drifting-Gaussian right-hand sides, rtol 1e-8 (adjoint: 20 more solves)",
+    "c192": dict(desc="Q1 Poisson 192^3 elements (7,189,057 nodes), 13,824 subdomains of 8^3, three-level BDDC "
+                      "(1,728 subregions), adaptive faces tau 10 (at most 10 per face), deflated PCG B4 R=40, "
+                      "200 drifting-Gaussian right-hand sides, rtol 1e-8",
+                 prec=32, step_rhs=10, adapt=True),
+    "c64": dict(desc="Q1 Poisson 64^3 elements (274,625 nodes), 512 subdomains of 8^3, three-level BDDC "
+                     "(64 subregions), deflated PCG B4 R=20, 50 drifting-Gaussian right-hand sides, rtol 1e-8",
+                prec=64, step_rhs=0, adapt=False),
+    "c3": dict(desc="Q1 Poisson 64^3 elements minus a sphere of radius 0.15, 400 jittered-RCB subdomains of uneven "
+                    "size, log-normal coefficients (sigma 0.5), three-level BDDC (50 subregions), deflated PCG B4 "
+                    "R=20, 50 drifting-Gaussian right-hand sides, rtol 1e-8",
+               prec=32, step_rhs=0, adapt=False),
+    "c96": dict(desc="Q1 Poisson 96^3 elements (912,673 nodes), 1,728 subdomains of 8^3, three-level BDDC "
+                     "(216 subregions), deflated PCG B4 R=20, 20 drifting-Gaussian right-hand sides, rtol 1e-8",
+                prec=64, step_rhs=0, adapt=False),
 }
+PREC_NAME = {64: "f64", 32: "f32", 16: "bf16"}
+# the oracle sample standing in for the 192^3 problem: a 32^3 block of the
+# same 8^3 subdomains (64 of them, 8 subregions), same options
+CPU_SAMPLE_NX = 32
 
 
 def kernel_hash():
@@ -49,297 +77,309 @@ def its_fmt(its):
     return "%d-%d(%.1f)" % (min(its), max(its), sum(its) / len(its))
 
 
-def pin_of(tuning):
-    """The 8-entry product configuration of a tuning report."""
-    out = []
-    for k in ("schur", "neumann"):
-        t = tuning[k]
-        out += [int(t["blocks_per_cu"]), int(t["per_subdomain"]), int(t["waves"]), int(t["unroll"])]
-    return out
-
-
-def run_form(torch, Solver, s, F, rtol, steps, warmup, local_prec, timing, use_graph=True, pin=None, autotune=True):
-    t0 = time.perf_counter()
-    g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"],
-               elem_keep=s["elem_keep"], R=s["R"], local_prec=local_prec, use_graph=use_graph, product_cfg=pin,
-               autotune=autotune)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    for _ in range(warmup):
-        g.reset_recycle()
-        g.solve_sequence(F, rtol)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        g.reset_recycle()
-        U, its, rr = g.solve_sequence(F, rtol)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    st = None
-    if timing:
-        # one more sequence, launched kernel by kernel with HIP events around
-        # every operator product (queued launches cannot be bracketed per kernel)
-        g.enable_timing(True, ("schur", "precond_local"))
-        g.reset_recycle()
-        g.solve_sequence(F, rtol)
-        torch.cuda.synchronize()
-        st = g.stats()
-        g.enable_timing(False)
-    info = g.info()
-    prod = g.time_products(20) if timing else None
-    return dict(g=g, U=U, its=its, rr=rr, elapsed=el, setup_s=setup_s, stats=st, info=info, tuning=g.tuning(),
-                products=prod)
-
-
-def cpu_baseline(s, F_np, n_sample):
-    from threadpoolctl import threadpool_limits
-
-    from oracle.sequence import OracleSolver
-    with threadpool_limits(1):
-        o = OracleSolver(s["nx"], s["elem_to_sub"], s["coef"], elem_keep=s["elem_keep"],
-                         sub_to_subregion=s["sub_to_subregion"], R=s["R"])
-        t0 = time.perf_counter()
-        for k in range(n_sample):
-            o.solve(F_np[k], 1e-8)
-        el = time.perf_counter() - t0
-    return dict(value=n_sample / el, unit="solves/s", cores=1, kind="oracle",
-                sample="first %d right-hand sides of the same sequence (oracle setup excluded, "
-                       "as on the GPU), float64 NumPy/SciPy, one thread" % n_sample)
+def gbs(k):
+    return k["bytes"] / (k["us"] * 1e-6) / 1e9
 
 
 def _rhs_chunk(job):
     import workload
-    nx, first, n = job
-    return workload.rhs_sequence(nx, n, None, first=first)
+    nx, first, n, keep = job
+    return workload.rhs_sequence(nx, n, keep, first=first)
 
 
-def run_large(args):
-    """192^3 (13,824 subdomains): the float32-Neumann form with adaptive faces
-    and R = 40, on the leading right-hand sides of the sequence."""
-    from concurrent.futures import ProcessPoolExecutor
+def make_rhs(s, n_rhs):
+    """The sequence's load vectors on the host (worker processes for large
+    meshes; they are started before this process touches the GPU)."""
+    import numpy as np
 
     import workload
-    s = workload.workload("c192")
-    n_rhs = args.n_rhs or s["n_rhs"]
+    if s["nx"] < 128:
+        return workload.rhs_sequence(s["nx"], n_rhs, s["elem_keep"])
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(16, len(os.sched_getaffinity(0)), n_rhs))
+    chunk = (n_rhs + workers - 1) // workers
+    jobs = [(s["nx"], k, min(chunk, n_rhs - k), s["elem_keep"]) for k in range(0, n_rhs, chunk)]
+    with ProcessPoolExecutor(max_workers=len(jobs)) as ex:
+        return np.concatenate(list(ex.map(_rhs_chunk, jobs)))
+
+
+def cpu_baseline(name, s, n_gpu_subs, budget_s=20.0):
+    """The oracle as it stands (float64 NumPy/SciPy, BLAS threads on every
+    core this process may use), setup excluded, timed on a bounded sample."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import workload
+    from oracle.sequence import OracleSolver
+    cores = len(os.sched_getaffinity(0))
+    try:
+        model = [l.split(":", 1)[1].strip() for l in subprocess.run(["lscpu"], capture_output=True, text=True)
+                 .stdout.splitlines() if l.startswith("Model name")][0]
+    except Exception:
+        model = "unknown"
+    if name == "c192":
+        # the oracle's setup of the whole 192^3 problem (13,824 sparse local
+        # solvers built in Python loops) does not finish in bounded time: the
+        # sample is a 32^3 block of the same subdomains, levels and options
+        nx = CPU_SAMPLE_NX
+        m = nx // 8
+        o = OracleSolver(nx, workload.cube_partition(nx, 8), np.ones(nx ** 3),
+                         sub_to_subregion=workload.cube_subregions(m, 2), R=s["R"])
+        F = workload.rhs_sequence(nx, 40)
+        n_sub = m ** 3
+    else:
+        o = OracleSolver(s["nx"], s["elem_to_sub"], s["coef"], elem_keep=s["elem_keep"],
+                         sub_to_subregion=s["sub_to_subregion"], R=s["R"])
+        F = workload.rhs_sequence(s["nx"], min(s["n_rhs"], 40), s["elem_keep"])
+        n_sub = n_gpu_subs
+    its = []
     t0 = time.perf_counter()
-    chunk = max(1, (n_rhs + 15) // 16)
-    jobs = [(s["nx"], k, min(chunk, n_rhs - k)) for k in range(0, n_rhs, chunk)]
-    # worker processes (CPU only) are started before this process touches the GPU
-    with ProcessPoolExecutor(max_workers=min(16, len(jobs))) as ex:
-        parts = list(ex.map(_rhs_chunk, jobs))
+    for k in range(F.shape[0]):
+        its.append(o.solve(F[k], 1e-8)["iters"])
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    n = len(its)
+    scale = n_sub / n_gpu_subs
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    if name == "c192":
+        sample = ("oracle (setup excluded) on the first %d right-hand sides of the same generator on a 32^3-element "
+                  "block: 64 subdomains of 8^3, 8 subregions, R = %d, rtol 1e-8, iterations %s; %.2f solves/s "
+                  "there, scaled by 64/13,824 subdomains (the oracle's work per iteration is a loop over subdomains). "
+                  "Adaptive selection is left out of the sample: at tau = 10 it adds no constraint on this "
+                  "unit-coefficient workload (largest face eigenvalue below 2)" % (n, s["R"], its_fmt(its), n / el))
+    else:
+        sample = ("oracle (setup excluded) on the first %d right-hand sides of the same sequence, rtol 1e-8, "
+                  "iterations %s" % (n, its_fmt(its)))
+    return dict(value=n / el * scale, unit="solves/s", cores=cores, kind="oracle", sample=sample,
+                seconds=round(el, 2), cpu_model=model, blas_threads=threads)
+
+
+def roofline_of(k):
+    """roofline entry of one timed kernel (bddc_time_kernels)."""
+    a = gbs(k)
+    return dict(achieved=round(a, 1), frac=round(a / HBM_PEAK_GBS, 4), avg_launch_us=round(k["us"], 2),
+                algorithmic_bytes_per_launch=k["bytes"])
+
+
+def run_form(torch, g, F, rtol, steps, warmup, step_rhs, keep_u):
+    """Warm-up, reset, then `steps` timed steps; a step is `step_rhs`
+    consecutive right-hand sides of the sequence (recycling state carried
+    over; back at the start of the sequence with a reset)."""
+    n_rhs = F.shape[0]
+    spc = max(1, n_rhs // step_rhs)          # steps per sequence
+
+    def step(i):
+        j = i % spc
+        if j == 0:
+            g.reset_recycle()
+        return g.solve_sequence(F[j * step_rhs:(j + 1) * step_rhs], rtol)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    its, rrs, us = [], [], []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        U, it, rr = step(i)
+        its += it.tolist()
+        rrs += rr.tolist()
+        if keep_u and i < spc:
+            us.append(U)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info = g.solve_info()
+    out = dict(value=round(step_rhs * steps / el, 3), unit="solves/s", ms_per_step=round(1e3 * el / steps, 3),
+               iters=its_fmt(its), max_true_relres=max(rrs),
+               basis={"columns": info["deflation_cols"], "frozen": bool(info["frozen"]),
+                      "freeze_step": info["freeze_step"]})
+    return out, (torch.cat(us) if keep_u and us else None), its
+
+
+def run_roofline_only(args, s, spec):
+    """Set up, then only the timed kernel launches and a 256 MiB device copy
+    (for hardware-counter passes: the copy calibrates FETCH_SIZE/WRITE_SIZE)."""
     import torch
 
     from paper_2412_17543_amd.solver import Solver
-    F = torch.cat([torch.tensor(a, device="cuda") for a in parts])
-    del parts
+    g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"],
+               elem_keep=s["elem_keep"], R=s["R"], local_prec=spec["prec"],
+               adapt_tau=10.0 if spec["adapt"] else 0.0, adapt_max_per_face=10)
+    if args.pin:
+        g.set_launch(True, [int(v) for v in args.pin.split(",")])
+    kt = g.time_kernels(20)
+    src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")     # 256 MiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
     torch.cuda.synchronize()
-    gen_s = time.perf_counter() - t0
-    print("[bench] c192: %d right-hand sides generated in %.1f s" % (n_rhs, gen_s), file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"], R=s["R"],
-               local_prec=32, adapt_tau=10.0, adapt_max_per_face=10)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    print("[bench] c192: setup %.1f s" % setup_s, file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        g.reset_recycle()
-        g.solve_sequence(F, args.rtol)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.reset_recycle()
-        U, its, rr = g.solve_sequence(F, args.rtol)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    info = g.info()
-    line = {
-        "metric": "solves/s to FP64 rtol 1e-8, BDDC-DPCG with adaptive faces, 1 GPU",
-        "value": round(n_rhs * args.steps / el, 3),
-        "unit": "solves/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(1e3 * el / args.steps, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 (float32 Neumann operators)", "data": "synthetic",
-        "config": {"workload": "Q1 Poisson 192^3 elements (7,189,057 nodes), 13,824 subdomains of 8^3, three-level "
-                               "BDDC (1,728 subregions), adaptive faces tau 10 (at most 10 per face), float32 N_i "
-                               "and Phi_i, deflated PCG B4 R=40, drifting-Gaussian right-hand sides, rtol 1e-8",
-                   "n_rhs": n_rhs, "n_gamma": info["n_gamma"], "rtol": args.rtol},
-        "iters": its_fmt(its.tolist()),
-        "max_true_relres": float(rr.max()),
-        "s_per_sequence": round(el / args.steps, 4),
-        "setup_s": round(setup_s, 2),
-        "adaptive": g.adaptive_stats(),
-        "coarse": {k: info[k] for k in ("n_coarse", "corners", "faces", "level2_interface", "level3")},
-        "device_gb": round(info["device_bytes"] / 1e9, 2),
-        "rhs_generation_s": round(gen_s, 1),
-        "tuning": g.tuning(),
-    }
-    print(json.dumps(line), flush=True)
+    print(json.dumps({"kernels": kt, "copy_bytes_each_way": src.numel() * 8, "kernel_hash": kernel_hash(),
+                      "tuning": g.tuning()}), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain (kernel-by-kernel) FP64 form")
-    ap.add_argument("--cpu-sample", type=int, default=2)
-    ap.add_argument("--workload", default="c64", choices=("c64", "c3", "c96", "c192"),
-                    help="c64: 64^3 cube lattice (the headline configuration); c3: 64^3 with a spherical "
-                         "hole, 400 uneven RCB subdomains, log-normal coefficients; c192: 192^3, 13,824 "
-                         "subdomains, adaptive faces (tau 10), float32 Neumann operators, R = 40 (its own "
-                         "line: the float32 form only)")
+    ap.add_argument("--workload", default="c192", choices=tuple(WORKLOADS))
     ap.add_argument("--n-rhs", type=int, default=0, help="use the first N right-hand sides of the sequence")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="only the float64 forms")
     ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16 Neumann-operator form")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain (kernel-by-kernel) float64 form")
     ap.add_argument("--adjoint", action="store_true",
-                    help="also time the adjoint gradient of L = sum_k ||u_k - t_k||^2 (t_k = 0.9 u_k): one adjoint "
-                         "solve per right-hand side with the recycled basis, and the element gradient")
+                    help="also time the adjoint gradient of L = sum_k ||u_k - t_k||^2 (t_k = 0.9 u_k)")
     ap.add_argument("--pin", default=None,
-                    help="fixed product configuration of the float64 form: 8 comma-separated integers "
-                         "(Schur then Neumann: blocks per CU, per-subdomain split, waves, tiles in flight)")
-    ap.add_argument("--roofline-only", action="store_true",
-                    help="set up, run one sequence, then only the timed product launches and a 256 MiB device copy "
-                         "(for hardware-counter passes: the copy calibrates FETCH_SIZE/WRITE_SIZE)")
+                    help="fixed product configuration: 8 comma-separated integers (Schur then Neumann: blocks per "
+                         "CU, per-subdomain split, waves, tiles in flight); a 0 first entry keeps that product tuned")
+    ap.add_argument("--roofline-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures the single-GPU path only (one process, one MI355X); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "c192":
-        return run_large(args)
+    import workload
+    spec = WORKLOADS[args.workload]
+    s = workload.workload(args.workload)
+    if args.roofline_only:
+        return run_roofline_only(args, s, spec)
+    n_rhs = args.n_rhs or s["n_rhs"]
+    step_rhs = spec["step_rhs"] or n_rhs
+    n_rhs = max(step_rhs, n_rhs // step_rhs * step_rhs)
+    t0 = time.perf_counter()
+    F_np = make_rhs(s, n_rhs)
+    gen_s = time.perf_counter() - t0
+    print("[bench] %s: %d right-hand sides generated in %.1f s" % (args.workload, n_rhs, gen_s),
+          file=sys.stderr, flush=True)
 
-    import numpy as np
     import torch
 
-    import workload
     from paper_2412_17543_amd.solver import Solver
-
-    s = workload.workload(args.workload)
-    F_np = workload.rhs_sequence(s["nx"], s["n_rhs"], s["elem_keep"])
     F = torch.tensor(F_np, device="cuda")       # inputs resident in HBM before timing
+    del F_np
     torch.cuda.synchronize()
-    n_rhs = F.shape[0]
-    # product configuration: --pin, else the one the counter passes measured
-    # (profiles/traffic_<workload>.json, while the kernel sources are
-    # unchanged), else the autotuner's choice
-    traffic_file = os.path.join(ROOT, "profiles", "traffic_%s.json" % args.workload)
-    traffic_rec = None
-    if os.path.exists(traffic_file):
-        t = json.load(open(traffic_file))
-        if t.get("kernel_hash") == kernel_hash():
-            traffic_rec = t
-    pin_source = "autotuned"
+    head = spec["prec"]
+    others = [p for p in (64, 32, 16) if p != head and not (p != 64 and args.no_mixed)
+              and not (p == 16 and args.no_bf16)]
+    if args.no_mixed:
+        head = 64
+        others = []
+    t0 = time.perf_counter()
+    g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"],
+               elem_keep=s["elem_keep"], R=s["R"], local_prec=head, local_prec_set=others,
+               adapt_tau=10.0 if spec["adapt"] else 0.0, adapt_max_per_face=10)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print("[bench] setup %.1f s" % setup_s, file=sys.stderr, flush=True)
     if args.pin:
-        pin, pin_source = [int(v) for v in args.pin.split(",")], "command line"
-    elif traffic_rec is not None and not args.roofline_only:
-        pin, pin_source = [int(v) for v in traffic_rec["pin"].split(",")], "profiles/traffic_%s.json" % args.workload
-    else:
-        pin = None
-    if args.roofline_only:
-        g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"],
-                   elem_keep=s["elem_keep"], R=s["R"], product_cfg=pin)
-        pr = g.time_products(20)
-        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")     # 256 MiB
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"products": pr, "copy_bytes_each_way": src.numel() * 8, "kernel_hash": kernel_hash(),
-                          "tuning": g.tuning()}), flush=True)
-        return
+        g.set_launch(True, [int(v) for v in args.pin.split(",")])
+    info = g.info()
 
-    f64 = run_form(torch, Solver, s, F, args.rtol, args.steps, args.warmup, 64, True, pin=pin)
-    value = n_rhs * args.steps / f64["elapsed"]
-    st = f64["stats"]
-    pr = f64["products"]
-    # dominant kernel: the batched product with the longer launch, timed by
-    # back-to-back launches right after the timed region
-    dom = max(("schur", "neumann"), key=lambda k: pr[k]["us"])
-    avg_us = pr[dom]["us"]
-    achieved = pr[dom]["bytes"] / (avg_us * 1e-6) / 1e9
+    forms, Us = {}, {}
+    order = [head] + [p for p in others if p == 64] + [p for p in others if p != 64]
+    for p in order:
+        g.set_local_prec(p)
+        res, Us[p], its = run_form(torch, g, F, args.rtol, args.steps, args.warmup, step_rhs, keep_u=True)
+        res["kernels"] = {k: roofline_of(v) for k, v in g.time_kernels(20).items()}
+        res["tuning"] = g.tuning()
+        forms[p] = res
+        print("[bench] %s form: %.2f solves/s, iterations %s" % (PREC_NAME[p], res["value"], res["iters"]),
+              file=sys.stderr, flush=True)
+    if 64 in Us and Us[64] is not None:
+        U64 = Us[64]
+        for p in order:
+            if p != 64 and Us[p] is not None:
+                forms[p]["max_rel_diff_vs_fp64"] = float(max(
+                    ((Us[p][k] - U64[k]).abs().max() / U64[k].abs().max()).item() for k in range(U64.shape[0])))
+    del Us
+    plain = None
+    if not args.no_plain and 64 in order:
+        # the plain float64 form: kernels one by one with a host check after
+        # every iteration, untuned default product configuration
+        g.set_local_prec(64)
+        g.set_launch("plain", [0] * 8)
+        plain, _, _ = run_form(torch, g, F, args.rtol, args.steps, args.warmup, step_rhs, keep_u=False)
+        print("[bench] plain f64 form: %.2f solves/s" % plain["value"], file=sys.stderr, flush=True)
+    hf = forms[head]
+    k = hf["kernels"]
+    dom = max(("schur", "neumann"), key=lambda n: k[n]["avg_launch_us"])
+    dk = k[dom]
     traffic = None
-    if traffic_rec is not None and traffic_rec["pin"] == ",".join(str(v) for v in pin_of(f64["tuning"])):
-        traffic = traffic_rec["kernels"][dom]["bytes_per_launch"]
+    tf = os.path.join(ROOT, "profiles", "traffic_%s.json" % args.workload)
+    if os.path.exists(tf):
+        t = json.load(open(tf))
+        tun = hf["tuning"]["schur" if dom == "schur" else "neumann"]
+        cfg = [int(tun[x]) for x in ("blocks_per_cu", "per_subdomain", "waves", "unroll")]
+        if t.get("kernel_hash") == kernel_hash() and t.get("kernel") == dom and t.get("cfg") == cfg \
+                and t.get("prec") == (64 if dom == "schur" else head):
+            traffic = t["bytes_per_launch"]
+    kname = ("k_symv<double, %d, %d, OpSchur>" if dom == "schur" else "k_symv<%s, %%d, %%d, OpNeumann>" %
+             {64: "double", 32: "float", 16: "unsigned short"}[head])
+    tun = hf["tuning"][dom]
+    kname = kname % (int(tun["waves"]), int(tun["unroll"]))
     line = {
-        "metric": "solves/s to FP64 rtol 1e-8 + HBM GB/s, mixed vs FP64 BDDC-DPCG, 1 GPU",
-        "value": round(value, 3),
+        "metric": METRIC,
+        "value": hf["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * f64["elapsed"] / args.steps, 3),
+        "ms_per_step": hf["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if head == 64 else "f64+%s" % PREC_NAME[head],
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload],
-                   "n_rhs": n_rhs, "n_gamma": f64["info"]["n_gamma"], "rtol": args.rtol},
-        "iters": its_fmt(f64["its"].tolist()),
-        "basis": {"columns": int(f64["info"]["deflation_cols"]), "frozen": bool(f64["info"]["frozen"])},
-        "max_true_relres": float(f64["rr"].max()),
-        "s_per_sequence": round(f64["elapsed"] / args.steps, 4),
-        "setup_s": round(f64["setup_s"], 3),
-        "roofline": {"bound": "hbm", "kernel": "k_symv<double> (" + ("Schur S_i" if dom == "schur" else "Neumann N_i") + ")",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "avg_launch_us": round(avg_us, 2), "algorithmic_bytes_per_launch": pr[dom]["bytes"],
-                     "other_product": {k: {"avg_launch_us": round(v["us"], 2),
-                                           "GB/s": round(v["bytes"] / (v["us"] * 1e-6) / 1e9, 1)}
-                                       for k, v in pr.items() if k != dom}},
-        "kernel_ms_per_sequence_eager": {k: round(v["ms"], 3) for k, v in st.items() if v["count"]},
-        "tuning": f64["tuning"],
-        "pin": ",".join(str(v) for v in pin_of(f64["tuning"])),
-        "pin_source": pin_source,
+        "config": {"workload": spec["desc"], "form": "%s N_i and Phi_i storage, float64 elsewhere" % PREC_NAME[head],
+                   "n_rhs": n_rhs, "rhs_per_step": step_rhs, "n_gamma": info["n_gamma"],
+                   "n_coarse": info["n_coarse"], "rtol": args.rtol},
+        "iters": hf["iters"],
+        "basis": hf["basis"],
+        "max_true_relres": hf["max_true_relres"],
+        "setup_s": round(setup_s, 2),
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": dk["achieved"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": dk["frac"], "traffic": traffic, "avg_launch_us": dk["avg_launch_us"],
+                     "algorithmic_bytes_per_launch": dk["algorithmic_bytes_per_launch"],
+                     "precond_apply": dict(k["precond"], peak=HBM_PEAK_GBS),
+                     "kernels": k},
+        "forms": {},
+        "rhs_generation_s": round(gen_s, 1),
+        "device_gb": round(g.solve_info()["device_peak_bytes"] / 1e9, 2),
     }
-    plain_value = None
-    if not args.no_plain:
-        # the plain FP64 GPU form: kernels launched one by one with a host check
-        # after every iteration, default product configuration (no autotuning)
-        pl = run_form(torch, Solver, s, F, args.rtol, args.steps, args.warmup, 64, False, use_graph=False,
-                      autotune=False)
-        plain_value = n_rhs * args.steps / pl["elapsed"]
-        line["fp64_plain"] = {"value": round(plain_value, 3), "unit": "solves/s", "iters": its_fmt(pl["its"].tolist()),
-                              "max_true_relres": float(pl["rr"].max())}
-    if not args.no_mixed:
-        mx = run_form(torch, Solver, s, F, args.rtol, args.steps, args.warmup, 32, False)
-        ud = f64["U"]
-        err = max(float(((mx["U"][k] - ud[k]).abs().max() / ud[k].abs().max()).item()) for k in range(n_rhs))
-        mv = n_rhs * args.steps / mx["elapsed"]
-        line["mixed_fp32"] = {"value": round(mv, 3), "unit": "solves/s", "iters": its_fmt(mx["its"].tolist()),
-                              "max_true_relres": float(mx["rr"].max()), "max_rel_diff_vs_fp64": err,
-                              "speedup_vs_fp64": round(mv / value, 3)}
-        if plain_value:
-            line["mixed_fp32"]["speedup_vs_plain_fp64"] = round(mv / plain_value, 3)
-    if not args.no_bf16 and not args.no_mixed:
-        bf = run_form(torch, Solver, s, F, args.rtol, args.steps, args.warmup, 16, False)
-        ud = f64["U"]
-        err = max(float(((bf["U"][k] - ud[k]).abs().max() / ud[k].abs().max()).item()) for k in range(n_rhs))
-        bv = n_rhs * args.steps / bf["elapsed"]
-        line["mixed_bf16"] = {"value": round(bv, 3), "unit": "solves/s", "iters": its_fmt(bf["its"].tolist()),
-                              "max_true_relres": float(bf["rr"].max()), "max_rel_diff_vs_fp64": err,
-                              "speedup_vs_fp64": round(bv / value, 3)}
-        if plain_value:
-            line["mixed_bf16"]["speedup_vs_plain_fp64"] = round(bv / plain_value, 3)
+    if spec["adapt"]:
+        line["adaptive"] = g.adaptive_stats()
+    for p in order:
+        f = dict(forms[p])
+        f.pop("kernels")
+        f["precond_apply"] = forms[p]["kernels"]["precond"]
+        f["products"] = {n: forms[p]["kernels"][n] for n in ("schur", "neumann")}
+        if 64 in forms:
+            f["speedup_vs_fp64"] = round(forms[p]["value"] / forms[64]["value"], 3)
+        if plain:
+            f["speedup_vs_plain_fp64"] = round(forms[p]["value"] / plain["value"], 3)
+        line["forms"][PREC_NAME[p]] = f
+    if plain:
+        line["forms"]["f64_plain"] = plain
     if args.adjoint:
-        g = f64["g"]
-        U = f64["U"]
+        if 64 in order:
+            g.set_local_prec(64)
+        g.set_launch(True)
+        U, its, rr = g.solve_sequence(F, args.rtol)
         dLdu = 2.0 * (U - 0.9 * U)
         g.adjoint_grad(dLdu, U, args.rtol)          # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        reps = max(1, args.steps // max(1, n_rhs // step_rhs))
+        for _ in range(reps):
             grad, gF = g.adjoint_grad(dLdu, U, args.rtol)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        line["adjoint"] = {"value": round(n_rhs * args.steps / el, 3), "unit": "adjoint solves/s",
-                           "s_per_sequence": round(el / args.steps, 4),
-                           "grad_norm": float(grad.norm().item())}
+        line["adjoint"] = {"value": round(n_rhs * reps / el, 3), "unit": "adjoint solves/s",
+                           "s_per_sequence": round(el / reps, 4), "grad_norm": float(grad.norm().item())}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(s, F_np, args.cpu_sample)
+        line["cpu_baseline"] = cpu_baseline(args.workload, s, info["n_sub"])
     print(json.dumps(line), flush=True)
 
 

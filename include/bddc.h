@@ -123,19 +123,33 @@ typedef struct {
                                 of eq. eig-matrix whose eigenvalue exceeds tau
                                 (rows from eq. c-def restricted to the face);
                                 <= 0: off (default)                              */
+    int32_t local_prec_set;  /* further storage precisions of N_i and Phi_i to build
+                                at setup, from the same float64 solves, for
+                                bddc_set_local_prec: bit mask 1 float64, 2 float32,
+                                4 bfloat16 (local_prec is always built); 0 default */
+    int32_t coef_log;        /* 1: coef holds log-coefficients theta_e and the element
+                                coefficient is c_e = exp(theta_e); 0 (default): coef
+                                holds c_e itself                                   */
+    int32_t restart_every;   /* > 0: end a run of Algorithm 1 after this many passes
+                                without convergence; the true residual then replaces
+                                the recursive one and the iteration restarts from
+                                line 5 (as after a residual replacement; not in the
+                                paper).  0 (default): off                         */
 } bddc_opts;
 
 /* Fills *o with the defaults: corners+faces, diag weights, float64 local
- * operators, R = 0, B4, freeze 1e-5, ||r||/||b||, previous-solution guess,
- * max_it 1000, save_cap 256, graph-captured iteration, autotuned products,
- * automatic coarse form. */
+ * operators (and no other precision), R = 0, B4, freeze 1e-5, ||r||/||b||,
+ * previous-solution guess, max_it 1000, save_cap 256, iterations queued
+ * kernel by kernel ahead of the convergence poll (use_graph 2), autotuned
+ * products, automatic coarse form, no adaptive faces. */
 void bddc_default_opts(bddc_opts *o);
 
 /*
  * bddc_setup -- build the preconditioner and every operator of the solve.
  *   mesh, part, opts : host structs (see above).
- *   coef             : host, n_elem float64 element coefficients c_e > 0
- *                      (element matrix c_e * h * Kref, Section 2).
+ *   coef             : host or device, n_elem float64 element coefficients
+ *                      c_e > 0 (element matrix c_e * h * Kref, Section 2), or
+ *                      their logarithms when opts->coef_log is set.
  *   hip_stream       : hipStream_t (NULL = default stream) used for all work.
  *   out              : receives the new context.
  * Computes, all on the device: local matrices K_i, interior elimination and
@@ -214,7 +228,7 @@ int bddc_condense(bddc_ctx *ctx, const double *F, double *b);
  *  [4] corners [5] faces [6] edges [7] level-2 interface [8] level-2 interior
  *  [9] level-3 size [10] deflation columns now [11] frozen (0/1)
  *  [12] bytes of the Schur operators [13] bytes of the Neumann operators
- *  [14] max nB [15] total device bytes held
+ *  in use [14] max nB [15] device bytes held now
  */
 int bddc_info(const bddc_ctx *ctx, int64_t *info);
 
@@ -282,6 +296,61 @@ int bddc_tuning(const bddc_ctx *ctx, double *out);
  * Overwrites the products' partial buffers only.  Errors: EINVAL, EHIP.
  */
 int bddc_time_products(bddc_ctx *ctx, int32_t reps, double *out);
+
+/*
+ * bddc_set_local_prec -- make another storage precision of the
+ * constrained-Neumann operators N_i and coarse bases Phi_i the one the
+ * preconditioner applies (the float64 and mixed forms of Section 3.2's
+ * local solves on one set of operators).  prec: 64, 32 or 16; it must have
+ * been built at setup (local_prec or local_prec_set).  The Neumann product is
+ * re-tuned when autotune is on; the deflation basis and the previous solution
+ * are kept.  Synchronises the stream.  Errors: EINVAL (precision not built).
+ */
+int bddc_set_local_prec(bddc_ctx *ctx, int32_t prec);
+
+/*
+ * bddc_set_launch -- how the following solves launch their work (the
+ * batching forms of one set of operators): use_graph as in bddc_opts (2
+ * queued ahead of the convergence poll, 1 graph replays, 0 plain: a host
+ * check after every iteration); product_cfg (host int32[8], nullable: keep
+ * the current ones) as in bddc_opts, except that a product whose first entry
+ * is 0 takes the untuned default configuration.  Synchronises the stream.
+ * Errors: EINVAL (values), ENOMEM.
+ */
+int bddc_set_launch(bddc_ctx *ctx, int32_t use_graph, const int32_t *product_cfg);
+
+/*
+ * bddc_time_kernels -- measurement helper: `reps` back-to-back launches of
+ * each of the following, timed with HIP events on the context's stream
+ * (inputs: the current interface iterate and residual; only scratch buffers
+ * are overwritten).  out (host float64[n], n <= 12) receives pairs
+ * (microseconds per launch, algorithmic bytes per launch):
+ *   [0,1]  batched Schur product (Section 3.1, A p)
+ *   [2,3]  batched constrained-Neumann product (local part of eq. localCorr)
+ *   [4,5]  batched interior product K_II^{-1} v (condensation, recovery)
+ *   [6,7]  one whole preconditioner application z = M^{-1} r: the Neumann
+ *          product, the coarse levels, prolongation and assembly
+ *          (eqs. averaging_subdomain_solves, coarse_problem, localCorr)
+ *   [8,9]  the coarse levels alone
+ *   [10,11] prolongation and assembly alone
+ * Algorithmic bytes are those the method must move (operators in their
+ * stored precision, packed; gathered vectors and index lists once).
+ * Errors: EINVAL, EHIP.
+ */
+int bddc_time_kernels(bddc_ctx *ctx, int32_t reps, double *out, int32_t n);
+
+/*
+ * bddc_solve_info -- recycling and memory state, host int64 out[n] (n <= 10):
+ *  [0] recycling steps run (one per solve until frozen)  [1] of them refused
+ *  (the new W^T A W not positive definite: the old basis kept)
+ *  [2] basis frozen (eq. harmritzstopcrit, 0/1)  [3] the update at which it
+ *  froze, counted from 1 like the solves (-1: not frozen)  [4] residual
+ *  replacements in the last solve  [5] first search direction of the run the
+ *  last update used (those after the last replacement)  [6] deflation
+ *  columns  [7] device bytes held now  [8] most device bytes held at once
+ *  [9] local precision in use.
+ */
+int bddc_solve_info(const bddc_ctx *ctx, int64_t *out, int32_t n);
 
 /* Theta (selected harmonic Ritz values, host float64[R]) of the last update. */
 int bddc_ritz_values(const bddc_ctx *ctx, double *theta, int32_t cap, int32_t *count);

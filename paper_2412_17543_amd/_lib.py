@@ -32,7 +32,8 @@ class Opts(ctypes.Structure):
                 ("stop_rule", c_int32), ("init_guess", c_int32), ("max_it", c_int32),
                 ("save_cap", c_int32), ("use_graph", c_int32), ("autotune", c_int32),
                 ("coarse_form", c_int32), ("product_cfg", c_int32 * 8),
-                ("reorth", c_int32), ("adapt_max_per_face", c_int32), ("adapt_tau", c_double)]
+                ("reorth", c_int32), ("adapt_max_per_face", c_int32), ("adapt_tau", c_double),
+                ("local_prec_set", c_int32), ("coef_log", c_int32), ("restart_every", c_int32)]
 
 
 class BddcError(RuntimeError):
@@ -59,6 +60,10 @@ SIGNATURES = {
     "bddc_tuning": (c_int32, [c_void_p, POINTER(c_double)]),
     "bddc_time_products": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "bddc_adaptive_stats": (c_int32, [c_void_p, POINTER(c_double)]),
+    "bddc_set_local_prec": (c_int32, [c_void_p, c_int32]),
+    "bddc_set_launch": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "bddc_time_kernels": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_int32]),
+    "bddc_solve_info": (c_int32, [c_void_p, POINTER(c_int64), c_int32]),
     "bddc_face_constraints": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                         c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_double,
                                         c_int32, c_void_p, POINTER(c_int32), c_void_p, POINTER(c_int32)]),

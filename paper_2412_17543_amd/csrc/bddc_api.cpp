@@ -80,8 +80,9 @@ struct bddc_ctx {
     int prec = 64;
     int n_gamma = 0, n_sub = 0, nC = 0;
     int64_t n_nodes = 0;
-    std::vector<void *> allocs;
-    size_t dev_bytes = 0;
+    std::map<void *, size_t> allocs; // live device allocations and their sizes
+    size_t dev_bytes = 0;           // bytes held now
+    size_t dev_peak = 0;            // most bytes held at once
     size_t bytes_S = 0, bytes_N = 0;
     int n_cu = 256;
     bool allow8 = true;             // 8-wave product blocks fit in LDS
@@ -94,7 +95,9 @@ struct bddc_ctx {
     int32_t *d_pch_sub = nullptr, *d_pch_row = nullptr;   // prolongation blocks: subdomain, first row
     int n_pch = 0;
     double *d_K = nullptr, *d_S = nullptr, *d_KC = nullptr;
-    void *d_N = nullptr, *d_phir = nullptr;
+    void *d_N = nullptr, *d_phir = nullptr;      // Neumann operators in use (local precision c->prec)
+    void *d_Nx[3] = {}, *d_phirx[3] = {};        // the storage precisions built: float64, float32, bfloat16
+    int prec_built = 0;                          // bit mask of those: 1 float64, 2 float32, 4 bfloat16
     int32_t *d_asm_ptr = nullptr, *d_asm_idx = nullptr, *d_casm_ptr = nullptr, *d_casm_idx = nullptr;
     int max_nI = 0, max_nB = 0, max_nc = 0, max_nt = 0, max_ntc = 0, max_ntI = 0;
     std::vector<int32_t> h_nB, h_nI, h_nc, h_b_off, h_c_off, h_pos_sub, h_cpos_sub;
@@ -165,6 +168,7 @@ struct bddc_ctx {
     int32_t *d_status = nullptr;
     bool have_solve = false, have_hist = false;
     int last_iters = 0, last_restarts = 0, last_status = 0;
+    int seg_start = 0;              // first direction after the last residual replacement
     // graph of GRAPH_ITERS iterations (use_graph 1)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -190,8 +194,9 @@ int dalloc(bddc_ctx *c, T **p, size_t count) {
     void *q = nullptr;
     hipError_t e = hipMalloc(&q, count * sizeof(T));
     if (e != hipSuccess) return fail(BDDC_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-    c->allocs.push_back(q);
+    c->allocs[q] = count * sizeof(T);
     c->dev_bytes += count * sizeof(T);
+    c->dev_peak = std::max(c->dev_peak, c->dev_bytes);
     *p = (T *)q;
     return 0;
 }
@@ -217,8 +222,11 @@ int dupload(bddc_ctx *c, T **p, const std::vector<T> &v) {
 
 void dfree(bddc_ctx *c, void *p) {
     if (!p) return;
-    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
-    if (it != c->allocs.end()) c->allocs.erase(it);
+    auto it = c->allocs.find(p);
+    if (it != c->allocs.end()) {
+        c->dev_bytes -= it->second;
+        c->allocs.erase(it);
+    }
     (void)hipFree(p);
 }
 
@@ -236,6 +244,56 @@ void build_csr(int64_t ntarget, const std::vector<std::pair<int64_t, int32_t>> &
 int64_t ntiles_of(int n, int nc) {
     const int64_t nt = (n + TILE - 1) / TILE, ntc = (nc + TILE - 1) / TILE;
     return nt * (nt + 1) / 2 + nt * ntc;
+}
+
+// slot of a storage precision in d_Nx / d_phirx (-1: not a storage precision)
+int prec_slot(int prec) { return prec == 64 ? 0 : prec == 32 ? 1 : prec == 16 ? 2 : -1; }
+
+// Algorithmic bytes of one batched product (Schur or Neumann, prec = the
+// operator's storage precision): packed upper triangle (+ coarse basis),
+// gathered input and its index, output (+ coarse output).
+double product_bytes(const bddc_ctx *c, bool isN, int prec) {
+    const double eb = prec / 8.0;
+    double bytes = 0.0;
+    for (int i = 0; i < c->n_sub; ++i) {
+        const double n = c->h_nB[i], nci = isN ? c->h_nc[i] : 0;
+        bytes += (n * (n + 1) / 2 + n * nci) * eb + n * (8 + 4 + 8) + nci * 8;
+    }
+    return bytes;
+}
+
+// Algorithmic bytes of the coarse levels of one preconditioner application:
+// the dense coarse operator and the gather of r_C; or, for the subregion
+// chain, the level-2 blocks each phase reads (interior columns of the swept
+// subregion matrix, N and Phi of the level-2 interface, Phi again and the
+// interior-interface block for the correction), the level-3 inverse and the
+// coarse vectors.
+double coarse_bytes(const bddc_ctx *c) {
+    if (c->nC == 0) return 0.0;
+    double cp = 0.0;   // coarse partials gathered into r_C: index + value
+    for (int i = 0; i < c->n_sub; ++i) cp += (double)c->opN.nchunk[i] * c->h_nc[i] * 12.0;
+    const double vec = c->nC * (4.0 + 8.0 + 8.0);
+    if (c->coarse_dense) return (double)c->nC * c->ldm * 8.0 + cp + vec + c->nC * 8.0;
+    double b = cp + vec + (double)c->n3 * c->ld3 * 8.0;
+    for (const SubregionHost &r : c->st.sr) {
+        const double nL = (double)r.L.size(), nI = r.nI, nB = r.nB, n3 = (double)r.c3.size();
+        b += (nL * nI + nB * nB + nB * n3 + nB * n3 + nI * nB) * 8.0 + nL * (4.0 + 8.0);
+    }
+    return b;
+}
+
+// Algorithmic bytes of the prolongation and the assembly of z = M^{-1} r:
+// Neumann partials, D Phi_i rows, gathered u_C entries, the local w_i written
+// and read back, the assembly lists and z.
+double prolong_bytes(const bddc_ctx *c) {
+    const double eN = c->prec / 8.0;
+    double b = 0.0;
+    for (int i = 0; i < c->n_sub; ++i) {
+        const double n = c->h_nB[i], nci = c->nC > 0 ? c->h_nc[i] : 0;
+        b += c->opN.nchunk[i] * n * 8.0 + n * nci * eN + nci * 12.0 + n * 8.0;   // k_prolong
+        b += n * (4.0 + 8.0);                                                   // assembly entries
+    }
+    return b + (c->n_gamma + 1) * 4.0 + c->n_gamma * 8.0;
 }
 
 // -------------------------------------------------------------------- timing
@@ -434,7 +492,7 @@ void run_schur(bddc_ctx *c, const double *x, bool gated, bool dot) {
     a.dot = dot ? c->d_dotS : nullptr;
     a.ctl = c->d_ctl;
     a.gated = gated ? 1 : 0;
-    launch_symv(a, 64, c->opS.cfg, c->opS.smem, c->stream);
+    launch_symv(a, SYMV_SCHUR, 64, c->opS.cfg, c->opS.smem, c->stream);
 }
 
 // Arguments of the level-2/3 kernels with the level-1 coarse residual taken
@@ -469,6 +527,9 @@ void run_l2_chain(const bddc_ctx *c, const L2Args &l, hipStream_t st) {
     launch_l2_d(l, c->nsr, c->smem_l2d, st);
 }
 
+void run_coarse(bddc_ctx *c);
+void run_prolong_assemble(bddc_ctx *c, const double *r, double *z, bool gated, bool advance, bool reduce);
+
 // One BDDC application on r: local constrained-Neumann products and coarse
 // residuals, the coarse problem, assembly of z with the coarse prolongation
 // and the (r^T z, (AW)^T z) partials.  test: stopping test at the start
@@ -490,8 +551,15 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
         a.rr_part = c->d_rr; a.rr_n = c->vgrid;
         a.bb_part = c->d_bbp; a.bb_n = c->vgrid;
         a.res_hist = c->d_reshist; a.hist_cap = c->hist_cap;
-        launch_symv(a, c->prec, c->opN.cfg, c->opN.smem, c->stream);
+        launch_symv(a, SYMV_NEUMANN, c->prec, c->opN.cfg, c->opN.smem, c->stream);
     }
+    run_coarse(c);
+    run_prolong_assemble(c, r, z, gated, advance, reduce);
+}
+
+// Coarse levels of one BDDC application: u_C from the coarse partials of the
+// Neumann product (eq. coarse_problem; three levels as in Section 3.2).
+void run_coarse(bddc_ctx *c) {
     if (c->nC > 0) {
         TScope ts(c, TK_COARSE);
         const Gather rc = gather_of(c->opN, true);
@@ -506,6 +574,12 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
             run_l2_chain(c, l2_args(c, rc), c->stream);
         }
     }
+}
+
+// Prolongation w_i = u_i + D Phi_i u_C and assembly z = sum_i R_i^T w_i
+// (eq. averaging_subdomain_solves), with the (r^T z, (AW)^T z) partials when
+// `reduce` is set.
+void run_prolong_assemble(bddc_ctx *c, const double *r, double *z, bool gated, bool advance, bool reduce) {
     {
         TScope ts(c, TK_VEC);
         ProlArgs pa{};
@@ -686,7 +760,7 @@ void run_interior(bddc_ctx *c, const double *v) {
     a.x = v;
     a.ypart = c->opI.d_ypart;
     a.ctl = c->d_ctl;
-    launch_symv(a, 64, c->opI.cfg, c->opI.smem, c->stream);
+    launch_symv(a, SYMV_INTERIOR, 64, c->opI.cfg, c->opI.smem, c->stream);
 }
 
 // Condensation (Section 3.1): y_I = K_II^{-1} F_I, t_i = K_BI y_I,
@@ -784,8 +858,9 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     const bool want_hist = record && (strat == 3 || strat == 4);
     *c->h_flags = 0;
     c->rtol2_run = rtol * rtol;
+    const int every = c->opts.restart_every;
     launch_ctl_init(c->d_ctl, rtol * rtol, record ? 1 : 0, c->R > 0 ? c->d_state : nullptr, c->d_hflag, c->d_hprog,
-                    c->stream);
+                    every > 0 ? every : INT32_MAX, c->stream);
     if (!condensed) run_condense(c, F);                  // b, ||b||^2 partials
     if (!c->pre_schur) {
         if (c->opts.init_guess == 1) launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
@@ -802,14 +877,14 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     }
     run_precond(c, c->d_r, c->d_z, 2, false, false, true);  // first test, lines 5-6
     run_pupd(c, true, false, true, 2);                      // line 7 (the first test while recording)
-    int restarts = 0, rc;
+    int restarts = 0, rc, seg_start = 0;
     bool recovered = false;
     while (true) {
         if ((rc = run_loop(c))) return rc;
         run_true_residual(c, c->d_tmp);                  // float64 ||b - A x||
         // while recording, the loop's last pass applied M^{-1} to r_l before
         // its (deferred) stopping test and recorded rho_l, mu_l (Section 4.2)
-        const bool hist = want_hist && restarts == 0;
+        const bool hist = want_hist;
         // interior recovery from this x, enqueued behind the synchronisation's
         // copies so that the device works while the host waits (done again if
         // the solve goes on or x is reset)
@@ -824,11 +899,13 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
         }
         if (h.status != 0 || h.zero_rhs) break;
         if (h.true_rr < h.rtol2 * h.denom2 || h.iter >= c->opts.max_it) break;
-        // residual replacement, then continue from line 5 (iterations keep counting)
+        // residual replacement, then continue from line 5 (iterations keep
+        // counting); only the directions from here on are recycled
         ++restarts;
+        seg_start = h.j;
         recovered = false;
         launch_copy(c->n_gamma, c->d_tmp, c->d_r, c->stream);
-        launch_set_done(c->d_ctl, 0, c->stream);
+        launch_resume(c->d_ctl, every > 0 && h.iter < INT32_MAX - every ? h.iter + every : INT32_MAX, c->stream);
         // (while recording, the loop's last pass has advanced the direction index)
         run_precond(c, c->d_r, c->d_z, 0, false, !record, true);
         run_pupd(c, true, false, true, 0);
@@ -837,9 +914,10 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     const Ctl h = *c->h_ctl;
     c->last_iters = h.iter;
     c->last_restarts = restarts;
+    c->seg_start = seg_start;
     c->last_status = h.status;
     c->have_solve = true;
-    c->have_hist = want_hist && restarts == 0;
+    c->have_hist = want_hist;
     if (iters) *iters = h.iter;
     if (relres) *relres = (h.bb > 0 && !h.zero_rhs) ? std::sqrt(h.true_rr / h.bb) : 0.0;
     if (!recovered && (rc = run_recover(c, F, u))) return rc;
@@ -853,7 +931,7 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
 // positive definite.  Nothing here waits for the device; the outcome is
 // adopted at the next synchronisation (resolve_pending).
 int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol, const std::vector<double> &gww,
-                const std::vector<double> &theta, bool freeze) {
+                const std::vector<double> &theta, bool freeze, int j0) {
     const int ldy = (ncol + 7) / 8 * 8;
     std::memset(c->h_Y, 0, (size_t)m * ldy * sizeof(double));
     for (int q = 0; q < m; ++q)
@@ -863,8 +941,8 @@ int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol, cons
     GemmArgs g{};
     g.n = c->n_gamma; g.ld = c->ld; g.Y = c->d_Y; g.ncol = ncol; g.ldy = ldy;
     g.k1 = c->k; g.k2 = l;
-    g.V1[0] = c->d_W; g.V2[0] = c->d_P; g.out[0] = c->d_Wn;
-    g.V1[1] = c->d_AW; g.V2[1] = c->d_AP; g.out[1] = c->d_AWn;
+    g.V1[0] = c->d_W; g.V2[0] = c->d_P + (size_t)j0 * c->ld; g.out[0] = c->d_Wn;
+    g.V1[1] = c->d_AW; g.V2[1] = c->d_AP + (size_t)j0 * c->ld; g.out[1] = c->d_AWn;
     launch_recycle_gemm(g, c->stream);
     const int nb = c->gram_nb;
     GramArgs gr{};
@@ -909,9 +987,12 @@ int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol, cons
 int do_recycle(bddc_ctx *c) {
     if (c->R == 0 || c->frozen || !c->have_solve) return 0;
     c->have_solve = false;
-    if (c->last_status != 0 || c->last_restarts > 0) return 0;
+    if (c->last_status != 0) return 0;
     const int strat = c->opts.recycle_strategy;
-    const int l = std::min(c->last_iters, c->save_cap);
+    // the directions of one unbroken run: those after the last residual
+    // replacement (all of them without one), as many as were stored
+    const int j0 = c->seg_start;
+    const int l = std::max(0, std::min(c->last_iters, c->save_cap) - j0);
     const int k = c->k, m = k + l;
     c->n_updates++;
     if (strat == 1 || strat == 2) {
@@ -927,12 +1008,13 @@ int do_recycle(bddc_ctx *c) {
         if (ncol == 0) return 0;
         std::vector<double> Y((size_t)m * ncol, 0.0);
         for (int j = 0; j < ncol; ++j) Y[(size_t)cols[j] * ncol + j] = 1.0;
-        return apply_basis(c, Y, m, ncol, std::vector<double>(), std::vector<double>(), false);
+        return apply_basis(c, Y, m, ncol, std::vector<double>(), std::vector<double>(), false, j0);
     }
     if (m == 0 || !c->have_hist) return 0;
     // scalars of the last solve
     const size_t hn = (size_t)c->hist_cap;
-    const double *al = c->h_hist, *dd = c->h_hist + hn, *rho = c->h_hist + 2 * hn, *mu = c->h_hist + 3 * hn;
+    const double *al = c->h_hist + j0, *dd = c->h_hist + hn + j0, *rho = c->h_hist + 2 * hn + j0,
+                 *mu = c->h_hist + 3 * hn + (size_t)j0 * RMAX;
     // F = V^T A V = blockdiag(W^T A W, diag(d)) and G = V^T A M^{-1} A V from the
     // recurrences of Algorithm 1: M^{-1} A p_j = (z_j - z_{j+1}) / alpha_j
     std::vector<double> F((size_t)m * m, 0.0), G((size_t)m * m, 0.0);
@@ -1041,7 +1123,7 @@ int do_recycle(bddc_ctx *c) {
         }
         freeze = std::sqrt(num) <= c->opts.ritz_freeze_tol * std::sqrt(den);
     }
-    return apply_basis(c, Y, m, ncol, gww, thsel, freeze);
+    return apply_basis(c, Y, m, ncol, gww, thsel, freeze, j0);
 }
 
 // Wait for the device and adopt a pending basis update (end of a sequence).
@@ -1077,6 +1159,9 @@ void bddc_default_opts(bddc_opts *o) {
     o->coarse_form = 0;
     o->adapt_max_per_face = 10;
     o->adapt_tau = 0.0;
+    o->local_prec_set = 0;
+    o->coef_log = 0;
+    o->restart_every = 0;
 }
 
 const char *bddc_last_error(void) { return g_err.c_str(); }
@@ -1105,24 +1190,17 @@ int setup_operators(bddc_ctx *c) {
         op.dev.gB = c->d_gB;
         op.dev.nc = isN ? c->d_nc : nullptr;
         op.n_tiles = 0;
-        double bytes = 0.0;
-        const double eb = op.prec / 8.0;
-        for (int i = 0; i < nsub; ++i) {
-            const int nci = isN ? c->h_nc[i] : 0;
-            op.n_tiles += ntiles_of(c->h_nB[i], nci);
-            const double n = c->h_nB[i];
-            // packed upper triangle (+ coarse basis), gathered input and its
-            // index, output (+ coarse output)
-            bytes += (n * (n + 1) / 2 + n * nci) * eb + n * (8 + 4 + 8) + nci * 8;
-        }
-        op.bytes = bytes;
+        for (int i = 0; i < nsub; ++i) op.n_tiles += ntiles_of(c->h_nB[i], isN ? c->h_nc[i] : 0);
+        op.bytes = product_bytes(c, isN, op.prec);
         op.cfg = SymvCfg{4, 2};
         op.smem = symv_smem(op.prec, op.cfg.nw, c->max_nt, isN ? c->max_ntc : 0);
         int rc = build_worklist(c, op, product_blocks(c, op.n_tiles, op.bpc), op.per_sub);
         if (rc) return rc;
     }
-    const size_t need4 = std::max(symv_smem(64, 4, c->max_nt, 0), symv_smem(c->prec, 4, c->max_nt, c->max_ntc));
-    const size_t need8 = std::max(symv_smem(64, 8, c->max_nt, 0), symv_smem(c->prec, 8, c->max_nt, c->max_ntc));
+    // (LDS accumulators are float64 for a float64 Neumann batch, else float32)
+    const int pw = (c->prec_built & 1) ? 64 : 32;
+    const size_t need4 = std::max(symv_smem(64, 4, c->max_nt, 0), symv_smem(pw, 4, c->max_nt, c->max_ntc));
+    const size_t need8 = std::max(symv_smem(64, 8, c->max_nt, 0), symv_smem(pw, 8, c->max_nt, c->max_ntc));
     if (need4 > 160 * 1024) return fail(BDDC_EINVAL, "a subdomain interface is too large for the LDS-staged products");
     c->allow8 = need8 <= 160 * 1024;
     if (set_symv_smem_limit(c->allow8 ? need8 : need4)) return fail(BDDC_EHIP, "hipFuncSetAttribute (dynamic LDS) failed");
@@ -1211,7 +1289,7 @@ int setup_interior(bddc_ctx *c, const std::vector<int64_t> &k_off) {
     if (c->allow8 && symv_smem(64, 8, max_ntI, 0) > 160 * 1024) c->allow8 = false;
     const int nwmax = c->allow8 ? 8 : 4;
     const size_t lim = std::max(symv_smem(64, nwmax, std::max(c->max_nt, max_ntI), 0),
-                                symv_smem(c->prec, nwmax, c->max_nt, c->max_ntc));
+                                symv_smem((c->prec_built & 1) ? 64 : 32, nwmax, c->max_nt, c->max_ntc));
     if (set_symv_smem_limit(lim)) return fail(BDDC_EHIP, "hipFuncSetAttribute (dynamic LDS) failed");
     HIPCHK(hipMemsetAsync(c->d_tmpN, 0, (size_t)c->n_nodes * sizeof(double), c->stream));
     return build_worklist(c, op, product_blocks(c, op.n_tiles, op.bpc), op.per_sub);
@@ -1220,7 +1298,7 @@ int setup_interior(bddc_ctx *c, const std::vector<int64_t> &k_off) {
 // Tile-level autotuning of the two batched products on the operators just
 // built: work-list granularity (items per compute unit), waves per block and
 // tiles in flight per wave; the fastest of a few timed launches is kept.
-int tune_operators(bddc_ctx *c) {
+int tune_operators(bddc_ctx *c, int mask = 7) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1229,7 +1307,7 @@ int tune_operators(bddc_ctx *c) {
     OpHost *ops[3] = {&c->opS, &c->opN, &c->opI};
     for (int w = 0; w < 3 && rc == 0; ++w) {
         OpHost &op = *ops[w];
-        if (op.dev.n_blocks == 0) continue;
+        if (op.dev.n_blocks == 0 || !((mask >> w) & 1)) continue;
         const int ntc = op.dev.nc ? c->max_ntc : 0;
         const int mnt = op.interior ? c->max_ntI : c->max_nt;
         float best = 1e30f;
@@ -1248,9 +1326,9 @@ int tune_operators(bddc_ctx *c) {
                     SymvArgs a{};
                     a.op = op.dev; a.x = op.interior ? c->d_tmpN : c->d_x; a.ypart = op.d_ypart; a.cpart = op.d_cpart;
                     a.ctl = c->d_ctl;
-                    for (int r = 0; r < 2; ++r) launch_symv(a, op.prec, cfg, smem, c->stream);
+                    for (int r = 0; r < 2; ++r) launch_symv(a, (SymvOp)w, op.prec, cfg, smem, c->stream);
                     HIPCHK(hipEventRecord(e0, c->stream));
-                    for (int r = 0; r < 4; ++r) launch_symv(a, op.prec, cfg, smem, c->stream);
+                    for (int r = 0; r < 4; ++r) launch_symv(a, (SymvOp)w, op.prec, cfg, smem, c->stream);
                     HIPCHK(hipEventRecord(e1, c->stream));
                     HIPCHK(hipEventSynchronize(e1));
                     float ms = 0.f;
@@ -1409,6 +1487,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
     c->nC = (int)st.coarse.size();
     c->n_nodes = st.n_nodes;
     c->prec = c->opts.local_prec;
+    c->prec_built = (1 << prec_slot(c->prec)) | (c->opts.local_prec_set & 7);
     const int nsub = c->n_sub;
     const int eN = c->prec / 8;   // bytes per element of the local Neumann operators
 
@@ -1521,8 +1600,15 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         c->bytes_S = (size_t)s_off[nsub] * 8;
         c->bytes_N = (size_t)n_off[nsub] * eN;
         if ((rc = dalloc_tiles(c, &c->d_S, (size_t)s_off[nsub]))) return rc;
-        if ((rc = dalloc_tiles(c, (char **)&c->d_N, c->bytes_N))) return rc;
-        if ((rc = dalloc(c, (char **)&c->d_phir, (size_t)std::max<int64_t>(1, phr_off[nsub]) * eN))) return rc;
+        for (int p : {64, 32, 16}) {
+            if (!((c->prec_built >> prec_slot(p)) & 1)) continue;
+            const int e = p / 8, q = prec_slot(p);
+            if ((rc = dalloc_tiles(c, (char **)&c->d_Nx[q], (size_t)n_off[nsub] * e)) ||
+                (rc = dalloc(c, (char **)&c->d_phirx[q], (size_t)std::max<int64_t>(1, phr_off[nsub]) * e)))
+                return rc;
+        }
+        c->d_N = c->d_Nx[prec_slot(c->prec)];
+        c->d_phir = c->d_phirx[prec_slot(c->prec)];
         std::vector<PackDesc> ps(nsub), pn(nsub);
         std::vector<PtspDesc> pt(nsub);
         for (int i = 0; i < nsub; ++i) {
@@ -1539,7 +1625,8 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         PtspDesc *dpt;
         if ((rc = dupload(c, &dps, ps)) || (rc = dupload(c, &dpn, pn)) || (rc = dupload(c, &dpt, pt))) return rc;
         launch_pack(dps, nsub, 64, c->d_S, nullptr, s);
-        launch_pack(dpn, nsub, c->prec, c->d_N, c->d_phir, s);
+        for (int p : {64, 32, 16})   // each storage precision from the same float64 solves
+            if ((c->prec_built >> prec_slot(p)) & 1) launch_pack(dpn, nsub, p, c->d_Nx[prec_slot(p)], c->d_phirx[prec_slot(p)], s);
         launch_ptsp(dpt, nsub, s);
         HIPCHK(hipStreamSynchronize(s));
         dfree(c, dsd); dfree(c, dwd); dfree(c, dps); dfree(c, dpn); dfree(c, dpt);
@@ -1904,7 +1991,27 @@ int bddc_setup(const bddc_mesh *mesh, const bddc_partition *part, const double *
     if (o.max_it <= 0 || o.max_it > 100000 || o.save_cap < 0 || o.save_cap > 4096) { delete c; return fail(BDDC_EINVAL, "bad max_it or save_cap"); }
     if (o.use_graph < 0 || o.use_graph > 2) { delete c; return fail(BDDC_EINVAL, "use_graph must be 0, 1 or 2"); }
     if (!(o.constraints & (BDDC_CORNERS | BDDC_FACES | BDDC_EDGES))) { delete c; return fail(BDDC_EINVAL, "no constraints"); }
-    int rc = setup_impl(c, mesh, part, coef);
+    if (mesh->nx <= 0 || mesh->ny <= 0 || mesh->nz <= 0) { delete c; return fail(BDDC_EINVAL, "mesh sizes must be positive"); }
+    // element coefficients on the host (copied from device memory when given
+    // there), as c_e = exp(theta_e) when they are log-coefficients
+    const int64_t n_elem = (int64_t)mesh->nx * mesh->ny * mesh->nz;
+    std::vector<double> coef_h((size_t)n_elem);
+    {
+        hipPointerAttribute_t attr{};
+        const bool on_device = hipPointerGetAttributes(&attr, coef) == hipSuccess && attr.type == hipMemoryTypeDevice;
+        (void)hipGetLastError();   // a plain host pointer may leave an error behind
+        if (on_device) {
+            if (hipMemcpy(coef_h.data(), coef, (size_t)n_elem * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+                delete c;
+                return fail(BDDC_EHIP, "copy of the device coefficients failed");
+            }
+        } else {
+            std::memcpy(coef_h.data(), coef, (size_t)n_elem * sizeof(double));
+        }
+        if (o.coef_log)
+            for (double &v : coef_h) v = std::exp(v);
+    }
+    int rc = setup_impl(c, mesh, part, coef_h.data());
     if (rc) {
         std::string keep = g_err;
         bddc_destroy(c);
@@ -1977,6 +2084,8 @@ int bddc_reset_recycle(bddc_ctx *c) {
     c->n_updates = 0;
     c->update_refused = 0;
     c->have_solve = false;
+    c->last_restarts = 0;
+    c->seg_start = 0;
     c->pend = Pending();
     launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
     if (c->d_state) launch_set_state(c->d_state, 0, 1, c->stream);
@@ -2125,9 +2234,9 @@ int bddc_time_products(bddc_ctx *c, int32_t reps, double *out) {
         const OpHost &op = *ops[w];
         SymvArgs a{};
         a.op = op.dev; a.x = c->d_x; a.ypart = op.d_ypart; a.cpart = op.d_cpart; a.ctl = c->d_ctl;
-        launch_symv(a, op.prec, op.cfg, op.smem, c->stream);   // warm
+        launch_symv(a, (SymvOp)w, op.prec, op.cfg, op.smem, c->stream);   // warm
         hipError_t e = hipEventRecord(e0, c->stream);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) launch_symv(a, op.prec, op.cfg, op.smem, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) launch_symv(a, (SymvOp)w, op.prec, op.cfg, op.smem, c->stream);
         if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -2139,6 +2248,139 @@ int bddc_time_products(bddc_ctx *c, int32_t reps, double *out) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+int bddc_set_local_prec(bddc_ctx *c, int32_t prec) {
+    if (!c) return fail(BDDC_EINVAL, "null argument");
+    const int q = prec_slot(prec);
+    if (q < 0 || !((c->prec_built >> q) & 1) || !c->d_Nx[q])
+        return fail(BDDC_EINVAL, "local precision " + std::to_string(prec) + " was not built at setup (local_prec_set)");
+    if (prec == c->prec) return 0;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->prec = prec;
+    c->d_N = c->d_Nx[q];
+    c->d_phir = c->d_phirx[q];
+    OpHost &op = c->opN;
+    op.prec = prec;
+    op.dev.tiles = c->d_N;
+    op.bytes = product_bytes(c, true, prec);
+    c->bytes_N = (size_t)op.n_tiles * 256 * (size_t)(prec / 8);
+    c->t_bytes[TK_PREC] = op.bytes;
+    op.smem = symv_smem(prec, op.cfg.nw, c->max_nt, c->max_ntc);
+    if (c->opts.autotune) {
+        int rc = tune_operators(c, 2);
+        if (rc) return rc;
+    }
+    if (c->gexec) {   // the captured iteration launches the other precision's kernel
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    if (c->graph) {
+        (void)hipGraphDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int bddc_set_launch(bddc_ctx *c, int32_t use_graph, const int32_t *product_cfg) {
+    if (!c) return fail(BDDC_EINVAL, "null argument");
+    if (use_graph < 0 || use_graph > 2) return fail(BDDC_EINVAL, "use_graph must be 0, 1 or 2");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (product_cfg) {
+        OpHost *ops[2] = {&c->opS, &c->opN};
+        for (int w = 0; w < 2; ++w) {
+            const int32_t *pc = product_cfg + 4 * w;
+            OpHost &op = *ops[w];
+            if (pc[0] > 0) {
+                if ((pc[2] != 4 && pc[2] != 8) || (pc[3] != 2 && pc[3] != 4) || (pc[2] == 8 && !c->allow8))
+                    return fail(BDDC_EINVAL, "product_cfg: waves must be 4 or 8 (8 when it fits), tiles in flight 2 or 4");
+                op.bpc = pc[0];
+                op.per_sub = pc[1] != 0;
+                op.cfg = SymvCfg{pc[2], pc[3]};
+            } else {   // the untuned default
+                op.bpc = 6;
+                op.per_sub = true;
+                op.cfg = SymvCfg{4, 2};
+            }
+            op.smem = symv_smem(op.prec, op.cfg.nw, c->max_nt, w == 1 ? c->max_ntc : 0);
+            op.tuned_us = 0.f;
+            if (int rc = build_worklist(c, op, product_blocks(c, op.n_tiles, op.bpc), op.per_sub)) return rc;
+        }
+        if (c->opS.dev.n_blocks > 0) {
+            dfree(c, c->d_dotS);
+            if (int rc = dalloc(c, &c->d_dotS, (size_t)c->opS.dev.n_blocks)) return rc;
+        }
+    }
+    c->opts.use_graph = use_graph;
+    if (c->gexec) {   // the captured iteration holds the old kernels and buffers
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    if (c->graph) {
+        (void)hipGraphDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int bddc_time_kernels(bddc_ctx *c, int32_t reps, double *out, int32_t n) {
+    if (!c || !out || reps <= 0 || n < 0) return fail(BDDC_EINVAL, "null argument, reps <= 0 or n < 0");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int rc = 0;
+    double res[12] = {0};
+    auto timed = [&](int slot, double bytes, auto &&launch) {
+        if (rc) return;
+        launch();   // warm
+        hipError_t e = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) rc = fail(BDDC_EHIP, std::string("timing: ") + hipGetErrorString(e));
+        res[2 * slot] = 1e3 * ms / reps;
+        res[2 * slot + 1] = bytes;
+    };
+    const bool tk = c->timing;
+    c->timing = false;
+    launch_set_done(c->d_ctl, 0, c->stream);
+    const OpHost *ops[3] = {&c->opS, &c->opN, &c->opI};
+    for (int w = 0; w < 3; ++w) {
+        const OpHost &op = *ops[w];
+        SymvArgs a{};
+        a.op = op.dev; a.x = w == 2 ? c->d_tmpN : c->d_x; a.ypart = op.d_ypart; a.cpart = op.d_cpart; a.ctl = c->d_ctl;
+        double bytes = op.bytes;
+        if (w == 2) {   // packed K_II^{-1}, gathered input and index, output
+            bytes = 0.0;
+            for (int i = 0; i < c->n_sub; ++i) {
+                const double m = c->h_nI[i];
+                bytes += m * (m + 1) / 2 * 8.0 + m * (8 + 4 + 8);
+            }
+        }
+        timed(w, bytes, [&] { launch_symv(a, (SymvOp)w, op.prec, op.cfg, op.smem, c->stream); });
+    }
+    const double cb = coarse_bytes(c), pb = prolong_bytes(c);
+    timed(3, c->opN.bytes + cb + pb, [&] { run_precond(c, c->d_r, c->d_tmp, 0, false, false, false); });
+    timed(4, cb, [&] { run_coarse(c); });
+    timed(5, pb, [&] { run_prolong_assemble(c, c->d_r, c->d_tmp, false, false, false); });
+    c->timing = tk;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int k = 0; k < n && k < 12; ++k) out[k] = res[k];
+    return rc;
+}
+
+int bddc_solve_info(const bddc_ctx *c, int64_t *out, int32_t n) {
+    if (!c || !out || n < 0) return fail(BDDC_EINVAL, "null argument or n < 0");
+    const int64_t v[10] = {c->n_updates - c->update_refused, c->update_refused, c->frozen ? 1 : 0,
+                           c->frozen ? c->freeze_step : -1, c->last_restarts, c->seg_start, c->k,
+                           (int64_t)c->dev_bytes, (int64_t)c->dev_peak, c->prec};
+    for (int k = 0; k < n && k < 10; ++k) out[k] = v[k];
+    return 0;
 }
 
 int bddc_tuning(const bddc_ctx *c, double *out) {
@@ -2174,7 +2416,7 @@ void bddc_destroy(bddc_ctx *c) {
         if (e) (void)hipEventDestroy(e);
     if (c->sync_ev) (void)hipEventDestroy(c->sync_ev);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    for (void *p : c->allocs) (void)hipFree(p);
+    for (auto &a : c->allocs) (void)hipFree(a.first);
     c->allocs.clear();
     if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     if (c->h_sync) (void)hipHostFree(c->h_sync);

@@ -209,7 +209,8 @@ __device__ bool stop_eval(Ctl *c, const double *rr_part, int rr_n, const double 
         const bool conv = (first && bb == 0.0) || rr < c->rtol2 * denom2;
         const bool bad = !isfinite(rr);
         const bool maxed = !first && iter >= max_it;
-        const bool stop = conv || bad || maxed;
+        const bool run_end = !first && iter >= c->iter_stop;   // restart_every: end of a run
+        const bool stop = conv || bad || maxed || run_end;
         if (threadIdx.x == 0) {
             s_stop = stop ? 1 : 0;
             if (blockIdx.x == 0) {
@@ -302,7 +303,13 @@ __device__ __forceinline__ SymvItem load_item(const SymvItem *items, int i) {
 template <typename T, int U>
 constexpr int symv_waves_per_simd() { return (sizeof(T) == 8 && U == 4) ? 4 : 6; }
 
-template <typename T, int NW, int U>
+// Name tags of the three operator batches (the kernel is the same; only the
+// Neumann batch has coarse-basis tiles and a stopping test).
+struct OpSchur { static constexpr bool coarse = false; };
+struct OpNeumann { static constexpr bool coarse = true; };
+struct OpInterior { static constexpr bool coarse = false; };
+
+template <typename T, int NW, int U, typename OP>
 __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv(SymvArgs a) {
     using ACC = typename Acc<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -321,7 +328,7 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
     // used.
     SymvItem it = load_item(a.op.items, blockIdx.x);
     if (a.gated && block_done(a.ctl)) return;
-    const bool test_here = a.test && !(a.defer && a.ctl->record);
+    const bool test_here = OP::coarse && a.test && !(a.defer && a.ctl->record);
 
     // Tiles past w1 read as zero without a memory access (resource over tiles
     // [t, w1) for the stage starting at tile t), so the loads of the next U
@@ -349,7 +356,7 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
         for (int u = 0; u < U; ++u) fa[u].load(stage(w0), u, l);
         if (first && test_here && stop_test(a)) return;
         const int nt = (n + TILE - 1) / TILE;
-        const int ncs = it.nc;
+        const int ncs = OP::coarse ? it.nc : 0;
         const int ntc = (ncs + TILE - 1) / TILE;
         const int npad = nt * TILE;
         ACC *xs = reinterpret_cast<ACC *>(smem_raw);
@@ -1009,37 +1016,44 @@ size_t symv_smem(int prec, int nw, int max_nt, int max_ntc) {
     return acc * ((size_t)max_nt * TILE * (1 + nw) + (size_t)nw * max_ntc * TILE);
 }
 
-template <typename T>
+template <typename T, typename OP>
 static int set_limit_t(size_t bytes) {
-    const void *f[4] = {(const void *)k_symv<T, 4, 2>, (const void *)k_symv<T, 4, 4>,
-                        (const void *)k_symv<T, 8, 2>, (const void *)k_symv<T, 8, 4>};
+    const void *f[4] = {(const void *)k_symv<T, 4, 2, OP>, (const void *)k_symv<T, 4, 4, OP>,
+                        (const void *)k_symv<T, 8, 2, OP>, (const void *)k_symv<T, 8, 4, OP>};
     for (const void *p : f)
         if (hipFuncSetAttribute(p, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
     return 0;
 }
 
 int set_symv_smem_limit(size_t bytes) {
-    if (set_limit_t<double>(bytes) || set_limit_t<float>(bytes) || set_limit_t<uint16_t>(bytes)) return -1;
+    if (set_limit_t<double, OpSchur>(bytes) || set_limit_t<double, OpInterior>(bytes) ||
+        set_limit_t<double, OpNeumann>(bytes) || set_limit_t<float, OpNeumann>(bytes) ||
+        set_limit_t<uint16_t, OpNeumann>(bytes))
+        return -1;
     return 0;
 }
 
-template <typename T>
+template <typename T, typename OP>
 static void launch_symv_t(const SymvArgs &a, SymvCfg cfg, size_t smem, hipStream_t s) {
     const dim3 grid(a.op.n_blocks);
     if (cfg.nw == 8) {
-        if (cfg.unroll == 4) hipLaunchKernelGGL((k_symv<T, 8, 4>), grid, dim3(512), smem, s, a);
-        else hipLaunchKernelGGL((k_symv<T, 8, 2>), grid, dim3(512), smem, s, a);
+        if (cfg.unroll == 4) hipLaunchKernelGGL((k_symv<T, 8, 4, OP>), grid, dim3(512), smem, s, a);
+        else hipLaunchKernelGGL((k_symv<T, 8, 2, OP>), grid, dim3(512), smem, s, a);
     } else {
-        if (cfg.unroll == 4) hipLaunchKernelGGL((k_symv<T, 4, 4>), grid, dim3(256), smem, s, a);
-        else hipLaunchKernelGGL((k_symv<T, 4, 2>), grid, dim3(256), smem, s, a);
+        if (cfg.unroll == 4) hipLaunchKernelGGL((k_symv<T, 4, 4, OP>), grid, dim3(256), smem, s, a);
+        else hipLaunchKernelGGL((k_symv<T, 4, 2, OP>), grid, dim3(256), smem, s, a);
     }
 }
 
-void launch_symv(const SymvArgs &a, int prec, SymvCfg cfg, size_t smem, hipStream_t s) {
+// The Schur and interior operators are float64 only; the Neumann operators
+// come in the three storage precisions.
+void launch_symv(const SymvArgs &a, SymvOp op, int prec, SymvCfg cfg, size_t smem, hipStream_t s) {
     if (a.op.n_blocks <= 0) return;
-    if (prec == 64) launch_symv_t<double>(a, cfg, smem, s);
-    else if (prec == 32) launch_symv_t<float>(a, cfg, smem, s);
-    else launch_symv_t<uint16_t>(a, cfg, smem, s);
+    if (op == SYMV_SCHUR) launch_symv_t<double, OpSchur>(a, cfg, smem, s);
+    else if (op == SYMV_INTERIOR) launch_symv_t<double, OpInterior>(a, cfg, smem, s);
+    else if (prec == 64) launch_symv_t<double, OpNeumann>(a, cfg, smem, s);
+    else if (prec == 32) launch_symv_t<float, OpNeumann>(a, cfg, smem, s);
+    else launch_symv_t<uint16_t, OpNeumann>(a, cfg, smem, s);
 }
 
 void launch_update(const UpdArgs &a, int grid, hipStream_t s) {

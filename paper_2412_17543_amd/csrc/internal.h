@@ -150,6 +150,7 @@ struct Ctl {
     int32_t record;         // store P, AP for recycling
     int32_t zero_rhs;       // b == 0: the solution is x = 0
     int32_t pfirst;         // 1: the next search direction starts a cycle (beta = 0)
+    int32_t iter_stop;      // the run ends (without error) once iter reaches this
     int32_t *hflag;         // pinned host word set to 1 together with `done`
     double *hprog;          // pinned host doubles: ||r||^2 of the last test, its
                             // denominator, the iteration (read by the host to decide

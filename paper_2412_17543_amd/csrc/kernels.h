@@ -308,7 +308,9 @@ void launch_elem_grad(const GradArgs &a, hipStream_t s);
 void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s);
 void launch_fill(int64_t n, double v, double *dst, hipStream_t s);
 void launch_ctl_init(Ctl *ctl, double rtol2, int record, const RecState *state, int32_t *hflag, double *hprog,
-                     hipStream_t s);
+                     int iter_stop, hipStream_t s);
+// clear `done` and set the iteration at which the next run ends
+void launch_resume(Ctl *ctl, int iter_stop, hipStream_t s);
 void launch_set_done(Ctl *ctl, int v, hipStream_t s);
 void launch_set_state(RecState *state, int k, int ok, hipStream_t s);
 void launch_chol_inv(const CholArgs &a, hipStream_t s);
@@ -318,9 +320,13 @@ struct SymvCfg {
     int nw;                         // waves per block: 4 or 8
     int unroll;                     // tiles in flight per wave: 2 or 4
 };
+// which batch of operators a product streams: the three get kernels of
+// their own name (k_symv<T, waves, tiles in flight, OpSchur | OpNeumann |
+// OpInterior>) so that profiles time them apart
+enum SymvOp { SYMV_SCHUR = 0, SYMV_NEUMANN = 1, SYMV_INTERIOR = 2 };
 size_t symv_smem(int prec, int nw, int max_nt, int max_ntc);
 int set_symv_smem_limit(size_t bytes);
-void launch_symv(const SymvArgs &a, int prec, SymvCfg cfg, size_t smem, hipStream_t s);
+void launch_symv(const SymvArgs &a, SymvOp op, int prec, SymvCfg cfg, size_t smem, hipStream_t s);
 void launch_update(const UpdArgs &a, int grid, hipStream_t s);
 void launch_prolong(const ProlArgs &a, int prec, int nblocks, int max_nc, hipStream_t s);
 void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s);

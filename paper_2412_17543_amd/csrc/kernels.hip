@@ -512,10 +512,12 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, double v, double *dst) 
 // ---------------------------------------------------------------------------
 // control block and deflation-basis bookkeeping on the device
 // ---------------------------------------------------------------------------
-__global__ void k_ctl_init(Ctl *c, double rtol2, int record, const RecState *st, int32_t *hflag, double *hprog) {
+__global__ void k_ctl_init(Ctl *c, double rtol2, int record, const RecState *st, int32_t *hflag, double *hprog,
+                           int iter_stop) {
     if (threadIdx.x != 0) return;
     Ctl h{};
     h.rtol2 = rtol2;
+    h.iter_stop = iter_stop;
     h.record = record;
     h.k = st ? st->k : 0;
     h.hflag = hflag;
@@ -525,6 +527,13 @@ __global__ void k_ctl_init(Ctl *c, double rtol2, int record, const RecState *st,
 
 __global__ void k_set_done(Ctl *c, int v) {
     if (threadIdx.x == 0) c->done = v;
+}
+
+__global__ void k_resume(Ctl *c, int iter_stop) {
+    if (threadIdx.x == 0) {
+        c->done = 0;
+        c->iter_stop = iter_stop;
+    }
 }
 
 __global__ void k_set_state(RecState *st, int k, int ok) {
@@ -691,8 +700,11 @@ void launch_fill(int64_t n, double v, double *dst, hipStream_t s) {
 }
 
 void launch_ctl_init(Ctl *ctl, double rtol2, int record, const RecState *state, int32_t *hflag, double *hprog,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl, rtol2, record, state, hflag, hprog);
+                     int iter_stop, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl, rtol2, record, state, hflag, hprog, iter_stop);
+}
+void launch_resume(Ctl *ctl, int iter_stop, hipStream_t s) {
+    hipLaunchKernelGGL(k_resume, dim3(1), dim3(64), 0, s, ctl, iter_stop);
 }
 void launch_set_done(Ctl *ctl, int v, hipStream_t s) {
     hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, s, ctl, v);

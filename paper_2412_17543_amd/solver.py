@@ -38,7 +38,8 @@ class Solver:
                  weights="diag", constraints=("corners", "faces"), stop_rule="rhs",
                  init_guess="prev", max_it=1000, save_cap=256, freeze_tol=1e-5,
                  use_graph=True, autotune=True, coarse_form="auto", product_cfg=None, reorth=False,
-                 adapt_tau=0.0, adapt_max_per_face=10, device="cuda", stream=None):
+                 adapt_tau=0.0, adapt_max_per_face=10, local_prec_set=(), coef_log=False, restart_every=0,
+                 device="cuda", stream=None):
         lib = _lib.load()
         self.lib = lib
         self.device = torch.device(device)
@@ -52,11 +53,15 @@ class Solver:
         self.n_elem = nx * ny * nz
         self.n_nodes = (nx + 1) * (ny + 1) * (nz + 1)
         self._e2s = np.ascontiguousarray(elem_to_sub, dtype=np.int32)
-        self._coef = np.ascontiguousarray(coef, dtype=np.float64)
+        if isinstance(coef, torch.Tensor):
+            self._coef = coef.detach().to(dtype=torch.float64).contiguous()
+        else:
+            self._coef = np.ascontiguousarray(coef, dtype=np.float64)
         self._s2r = None if sub_to_subregion is None else np.ascontiguousarray(sub_to_subregion, dtype=np.int32)
         self._keep = None if elem_keep is None else np.ascontiguousarray(elem_keep, dtype=np.uint8)
         self._dir = None if node_dirichlet is None else np.ascontiguousarray(node_dirichlet, dtype=np.uint8)
-        assert self._e2s.size == self.n_elem and self._coef.size == self.n_elem
+        n_coef = self._coef.numel() if isinstance(self._coef, torch.Tensor) else self._coef.size
+        assert self._e2s.size == self.n_elem and n_coef == self.n_elem
         mesh = _lib.Mesh(nx, ny, nz, 1.0 / nx,
                          None if self._keep is None else self._keep.ctypes.data,
                          None if self._dir is None else self._dir.ctypes.data)
@@ -86,6 +91,9 @@ class Solver:
         o.reorth = 1 if reorth else 0
         o.adapt_tau = float(adapt_tau)
         o.adapt_max_per_face = int(adapt_max_per_face)
+        o.local_prec_set = sum({64: 1, 32: 2, 16: 4}[p] for p in local_prec_set)
+        o.coef_log = 1 if coef_log else 0
+        o.restart_every = int(restart_every)
         if product_cfg is not None:
             assert len(product_cfg) == 8
             for i, v in enumerate(product_cfg):
@@ -94,7 +102,8 @@ class Solver:
         torch.cuda.set_device(self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
-        check(lib.bddc_setup(ctypes.byref(mesh), ctypes.byref(part), self._coef.ctypes.data,
+        coef_ptr = self._coef.data_ptr() if isinstance(self._coef, torch.Tensor) else self._coef.ctypes.data
+        check(lib.bddc_setup(ctypes.byref(mesh), ctypes.byref(part), coef_ptr,
                              ctypes.byref(o), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
         self.ctx = ctx
         self.n_gamma = self.info()["n_gamma"]
@@ -126,6 +135,42 @@ class Solver:
         cnt = ctypes.c_int32()
         check(self.lib.bddc_ritz_values(self.ctx, buf, 64, ctypes.byref(cnt)))
         return np.frombuffer(buf, dtype=np.float64)[: cnt.value].copy()
+
+    SOLVE_INFO_KEYS = ("recycle_steps", "refused", "frozen", "freeze_step", "replacements", "run_start",
+                       "deflation_cols", "device_bytes", "device_peak_bytes", "local_prec")
+
+    def solve_info(self) -> dict:
+        """Recycling and memory state (bddc_solve_info)."""
+        a = (ctypes.c_int64 * 10)()
+        check(self.lib.bddc_solve_info(self.ctx, a, 10))
+        return dict(zip(self.SOLVE_INFO_KEYS, list(a)))
+
+    def set_local_prec(self, prec):
+        """Apply the Neumann operators in another storage precision built at setup."""
+        check(self.lib.bddc_set_local_prec(self.ctx, {64: 64, 32: 32, 16: 16, "fp64": 64, "fp32": 32,
+                                                      "bf16": 16}[prec]))
+
+    def set_launch(self, use_graph=True, product_cfg=None):
+        """Launch form of later solves ("queued"/True, "graph", "plain"/False)
+        and optionally the product configuration (8 ints; a product whose
+        first entry is 0 takes the untuned default)."""
+        ug = {True: 2, False: 0, "queued": 2, "graph": 1, "plain": 0}[use_graph]
+        cfg = None
+        if product_cfg is not None:
+            assert len(product_cfg) == 8
+            cfg = (ctypes.c_int32 * 8)(*[int(v) for v in product_cfg])
+        check(self.lib.bddc_set_launch(self.ctx, ug, cfg))
+
+    KERNEL_KEYS = ("schur", "neumann", "interior", "precond", "coarse", "prolong_assemble")
+
+    def time_kernels(self, reps=20) -> dict:
+        """Back-to-back launches timed with HIP events (bddc_time_kernels):
+        microseconds and algorithmic bytes per launch of the three batched
+        products, one preconditioner application and its coarse and
+        prolongation/assembly parts."""
+        a = (ctypes.c_double * 12)()
+        check(self.lib.bddc_time_kernels(self.ctx, reps, a, 12))
+        return {k: {"us": a[2 * i], "bytes": a[2 * i + 1]} for i, k in enumerate(self.KERNEL_KEYS)}
 
     TUNING_KEYS = ("blocks", "blocks_per_cu", "per_subdomain", "waves", "unroll", "best_us", "tiles")
 
@@ -238,10 +283,9 @@ class DPCGSolveFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, theta, F, spec):
-        coef = torch.exp(theta.detach()).double().cpu().numpy()
         s = dict(spec)
         rtol = s.pop("rtol", 1e-10)
-        solver = Solver(coef=coef, **s)
+        solver = Solver(coef=theta.detach(), coef_log=True, **s)
         U, its, rr = solver.solve_sequence(F.detach(), rtol)
         ctx.solver = solver
         ctx.rtol = rtol

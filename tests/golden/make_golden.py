@@ -60,9 +60,70 @@ def run(name, n_rhs, rtols):
         json.dump(out, f, indent=1)
 
 
+def run_full(name, n_rhs, rtol, tag):
+    """Every nodal value of the first n_rhs solutions (compressed .npz), with
+    iterations, true residuals and the recycling history."""
+    from oracle.recycle import ritz_change
+    s = workload.workload(name)
+    F = workload.rhs_sequence(s["nx"], n_rhs, s["elem_keep"])
+    t = time.time()
+    o = OracleSolver(s["nx"], s["elem_to_sub"], s["coef"], elem_keep=s["elem_keep"],
+                     sub_to_subregion=s["sub_to_subregion"], R=s["R"])
+    U, its, rr = [], [], []
+    for k in range(n_rhs):
+        r = o.solve(F[k], rtol)
+        U.append(r["u"])
+        its.append(r["iters"])
+        rr.append(r["true_relres"])
+        print(name, k, r["iters"], "%.1fs" % (time.time() - t), flush=True)
+    hist = o.rec.history
+    change = [ritz_change(hist[j], hist[j - 1]) if hist[j].size == hist[j - 1].size == s["R"] else -1.0
+              for j in range(1, len(hist))]
+    np.savez_compressed(os.path.join(HERE, "%s_%s.npz" % (name, tag)), u=np.array(U), iters=np.array(its),
+                        true_relres=np.array(rr), rtol=rtol, R=s["R"],
+                        freeze_step=-1 if o.rec.freeze_step is None else o.rec.freeze_step,
+                        ritz_change=np.array(change), n_gamma=o.ss.n_gamma, seconds=time.time() - t)
+
+
+def run_sequence(name, n_rhs, rtol, tag):
+    """The whole sequence: iterations, freeze step, relative change of the
+    selected harmonic Ritz values at every update, norms and 256 sampled
+    nodal values of every solution."""
+    from oracle.recycle import ritz_change
+    s = workload.workload(name)
+    F = workload.rhs_sequence(s["nx"], n_rhs, s["elem_keep"])
+    idx = sample_nodes(s["nx"])
+    t = time.time()
+    o = OracleSolver(s["nx"], s["elem_to_sub"], s["coef"], elem_keep=s["elem_keep"],
+                     sub_to_subregion=s["sub_to_subregion"], R=s["R"])
+    its, rr, un, us = [], [], [], []
+    for k in range(n_rhs):
+        r = o.solve(F[k], rtol)
+        its.append(r["iters"])
+        rr.append(r["true_relres"])
+        un.append(np.linalg.norm(r["u"]))
+        us.append(r["u"][idx])
+        print(name, k, r["iters"], o.rec.frozen, "%.1fs" % (time.time() - t), flush=True)
+    hist = o.rec.history
+    change = [ritz_change(hist[j], hist[j - 1]) if hist[j].size == hist[j - 1].size == s["R"] else -1.0
+              for j in range(1, len(hist))]
+    np.savez_compressed(os.path.join(HERE, "%s_%s.npz" % (name, tag)), iters=np.array(its),
+                        true_relres=np.array(rr), u_norm2=np.array(un), u_sample=np.array(us), sample_nodes=idx,
+                        rtol=rtol, R=s["R"], freeze_step=-1 if o.rec.freeze_step is None else o.rec.freeze_step,
+                        ritz_change=np.array(change), seconds=time.time() - t)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["c16", "c64"]
     if "c16" in which:
         run("c16", 10, (1e-8, 1e-10))
     if "c64" in which:
         run("c64", 5, (1e-10, 1e-8))
+    if "c64full" in which:          # every node, 5 right-hand sides, float64 parity tolerance
+        run_full("c64", 5, 1e-10, "full5")
+    if "c64seq" in which:           # the 50-step sequence of the benchmark, to its freeze
+        run_sequence("c64", 50, 1e-8, "seq50")
+    if "c3full" in which:           # holed cube, 400 uneven subdomains
+        run_full("c3", 5, 1e-10, "full5")
+    if "c96full" in which:          # 96^3 prefix of the differentiation workload
+        run_full("c96", 2, 1e-10, "full2")

@@ -1,0 +1,95 @@
+"""GPU parity of the recycling step (Section 4.2) against the oracle: the
+basis freeze of eq. harmritzstopcrit, the frozen-basis path after it, and the
+basis update from the last run of a solve that restarted.
+
+Tolerances as in the other float64 parity tests (rtol 1e-10: iterations
+within +-1, solutions to 1e-9); the freeze step must be equal: it comes from a
+repeated right-hand side, whose second solve takes zero iterations, so the
+selected harmonic Ritz values repeat to rounding (a change of ~1e-14 against
+the threshold 1e-5, where the earlier updates change them by more than 1e-3).
+"""
+import numpy as np
+import pytest
+
+import workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _pair(name, **kw):
+    from oracle.sequence import OracleSolver
+    from paper_2412_17543_amd.solver import Solver
+    s = workload.workload(name)
+    print("[gpu] setup %s %s" % (name, kw), flush=True)
+    g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"], **kw)
+    o = OracleSolver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"], **kw)
+    return s, g, o
+
+
+def _rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+
+
+@pytest.mark.parametrize("name", ["c16", "tiny3"])
+def test_freeze_on_a_repeated_rhs_matches_oracle(name):
+    torch = _torch()
+    s, g, o = _pair(name, R=4)
+    F = workload.rhs_sequence(s["nx"], 5)
+    seq = np.stack([F[0], F[1], F[2], F[2], F[3], F[4]])
+    U, its, rr = g.solve_sequence(torch.tensor(seq, device="cuda"), 1e-10)
+    uo, ito, rro = o.solve_sequence(seq, 1e-10)
+    info = g.solve_info()
+    print("[gpu] iters", its.tolist(), ito.tolist(), "freeze", info["freeze_step"], o.rec.freeze_step, flush=True)
+    assert o.rec.frozen and o.rec.freeze_step == 4
+    assert info["frozen"] == 1 and info["freeze_step"] == o.rec.freeze_step
+    assert its[3] == ito[3] == 0
+    assert np.all(np.abs(its - ito) <= 1)
+    for k in range(len(seq)):
+        assert _rel(U[k].cpu().numpy(), uo[k]) < 1e-9
+    assert np.all(rr < 1e-10)
+    # the values the basis froze with
+    np.testing.assert_allclose(np.sort(g.ritz_values()), np.sort(o.rec.theta), rtol=1e-6)
+    # the frozen basis serves later solves unchanged: no more recycling steps
+    steps = info["recycle_steps"]
+    U2, its2, _ = g.solve_sequence(torch.tensor(F[4:5], device="cuda"), 1e-10)
+    r2 = o.solve(F[4], 1e-10)
+    assert g.solve_info()["recycle_steps"] == steps
+    assert abs(int(its2[0]) - r2["iters"]) <= 1
+    assert _rel(U2[0].cpu().numpy(), r2["u"]) < 1e-9
+
+
+@pytest.mark.parametrize("name,every", [("c16", 5), ("tiny3", 4)])
+def test_update_after_restarts_matches_oracle(name, every):
+    # every run ends after `every` passes; the true residual replaces the
+    # recursive one and the iteration restarts (restart_every, both sides);
+    # each update uses the directions of the last run only
+    torch = _torch()
+    s, g, o = _pair(name, R=4, restart_every=every)
+    F = workload.rhs_sequence(s["nx"], 5)
+    its, ito, reps = [], [], []
+    for k in range(5):
+        U, it, rr = g.solve_sequence(torch.tensor(F[k:k + 1], device="cuda"), 1e-10)
+        r = o.solve(F[k], 1e-10)
+        info = g.solve_info()
+        its.append(int(it[0]))
+        ito.append(r["iters"])
+        reps.append((info["replacements"], r["restarts"], info["run_start"], r["seg_start"]))
+        assert _rel(U[0].cpu().numpy(), r["u"]) < 1e-9
+        assert rr[0] < 1e-10
+    print("[gpu] iters", its, ito, "restarts/run start", reps, flush=True)
+    assert np.all(np.abs(np.array(its) - np.array(ito)) <= 1)
+    for gr, orr, gs, os_ in reps:
+        assert abs(gr - orr) <= 1
+        if gr == orr:
+            assert gs == os_
+    assert any(r[0] > 0 for r in reps)
+    info = g.solve_info()
+    assert info["frozen"] == int(o.rec.frozen) and info["refused"] == 0 and info["deflation_cols"] == 4
+    assert info["recycle_steps"] == (o.rec.freeze_step if o.rec.frozen else 5)

@@ -272,9 +272,10 @@ def gaussian_centres(n_rhs: int, n_gauss: int = 4, drift: float = 0.01) -> np.nd
 
 
 def nodal_source(nx: int, k: int, centres: np.ndarray, width: float = 0.1,
-                 noise: float = 1e-3) -> np.ndarray:
-    """Nodal values of f_k = sum_g exp(-|x-c|^2/(2 w^2)) + noise * N(0,1)."""
-    x = node_coords(nx)
+                 noise: float = 1e-3, coords: np.ndarray | None = None) -> np.ndarray:
+    """Nodal values of f_k = sum_g exp(-|x-c|^2/(2 w^2)) + noise * N(0,1)
+    (``coords``: node_coords(nx), when the caller already has it)."""
+    x = node_coords(nx) if coords is None else coords
     f = np.zeros(x.shape[0])
     for c in centres[k]:
         f += np.exp(-((x - c) ** 2).sum(axis=1) / (2.0 * width * width))
@@ -285,7 +286,8 @@ def nodal_source(nx: int, k: int, centres: np.ndarray, width: float = 0.1,
 _M1 = np.array([[1.0 / 3.0, 1.0 / 6.0], [1.0 / 6.0, 1.0 / 3.0]])
 
 
-def consistent_load(nx: int, f_nodal: np.ndarray, elem_keep: np.ndarray | None = None) -> np.ndarray:
+def consistent_load(nx: int, f_nodal: np.ndarray, elem_keep: np.ndarray | None = None,
+                    elem_nodes: np.ndarray | None = None) -> np.ndarray:
     """Load vector F = M f of trilinear interpolant f with the consistent Q1 mass.
 
     This is input preparation (turning a nodal source into a load vector), the
@@ -293,7 +295,7 @@ def consistent_load(nx: int, f_nodal: np.ndarray, elem_keep: np.ndarray | None =
     """
     h = 1.0 / nx
     mref = np.kron(_M1, np.kron(_M1, _M1)) * h ** 3  # vertex v = a + 2b + 4c, x fastest
-    en = element_nodes(nx)
+    en = element_nodes(nx) if elem_nodes is None else elem_nodes
     if elem_keep is not None:
         en = en[elem_keep.astype(bool)]
     fe = f_nodal[en] @ mref.T
@@ -305,8 +307,10 @@ def rhs_sequence(nx: int, n_rhs: int, elem_keep: np.ndarray | None = None,
     """(n_rhs, n_nodes) float64 load vectors F_k, k = first .. first+n_rhs-1."""
     cen = gaussian_centres(first + n_rhs)
     out = np.empty((n_rhs, n_nodes(nx)))
+    x = node_coords(nx)
+    en = element_nodes(nx)
     for i in range(n_rhs):
-        out[i] = consistent_load(nx, nodal_source(nx, first + i, cen), elem_keep)
+        out[i] = consistent_load(nx, nodal_source(nx, first + i, cen, coords=x), elem_keep, elem_nodes=en)
     return out
 
 
