@@ -216,6 +216,20 @@ int bddc_adjoint_grad(bddc_ctx *ctx, const double *dLdu_seq, int32_t n_rhs, cons
 
 /* q = A p, the interface Schur complement product (Section 3.1, eq. Sug). */
 int bddc_apply_schur(bddc_ctx *ctx, const double *p, double *q);
+/*
+ * bddc_apply_schur_noalloc -- q = A p like bddc_apply_schur, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): it allocates nothing.  Its
+ * partial products live in a static device array of the library (8 MiB,
+ * 2^20 doubles, one per GPU, held until the process ends) instead of context
+ * memory; a context whose Schur product needs more (the partial products of
+ * all its work items, i.e. the sum over subdomains of work items times
+ * interface size, plus one double per vector block) is rejected with EINVAL.  Every call on one GPU shares that GPU's array and
+ * leaves its contents behind (nothing in it has to start at zero): calls that
+ * overlap on one GPU, from any stream or thread, race.  p, q: device, length
+ * n_gamma.  Synchronises the context's stream.  Errors: EINVAL, EHIP.
+ */
+int bddc_apply_schur_noalloc(bddc_ctx *ctx, const double *p, double *q);
 /* z = M^{-1} r, one BDDC application (eqs. averaging_subdomain_solves,
  * coarse_problem, localCorr; three levels when subregions were given). */
 int bddc_apply_precond(bddc_ctx *ctx, const double *r, double *z);

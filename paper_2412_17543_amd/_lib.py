@@ -51,6 +51,7 @@ SIGNATURES = {
     "bddc_adjoint_grad": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_double, c_void_p, c_void_p]),
     "bddc_apply_schur": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "bddc_apply_precond": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "bddc_apply_schur_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "bddc_condense": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "bddc_info": (c_int32, [c_void_p, POINTER(c_int64)]),
     "bddc_interface_nodes": (c_int32, [c_void_p, POINTER(c_int64)]),

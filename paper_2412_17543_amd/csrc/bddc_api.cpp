@@ -50,7 +50,8 @@ struct OpHost {
     std::vector<int32_t> nchunk;    // per subdomain
     int32_t *d_items = nullptr, *d_nchunk = nullptr, *d_pb = nullptr, *d_cb = nullptr;
     double *d_ypart = nullptr, *d_cpart = nullptr;
-    int64_t ypart_len = 0, cpart_len = 0;
+    int64_t ypart_len = 0, cpart_len = 0;   // allocated lengths of the partial buffers
+    int64_t ylen = 0;                       // partial entries the current work list writes
     // flat gather lists: interface node -> y partials, coarse DOF -> c partials
     int32_t *d_yptr = nullptr, *d_yidx = nullptr, *d_cptr = nullptr, *d_cidx = nullptr;
 };
@@ -428,6 +429,7 @@ int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
         op.cpart_len = clen;
     }
     op.nchunk = nch;
+    op.ylen = ylen;
     op.dev.items = reinterpret_cast<const SymvItem *>(op.d_items);
     op.dev.n_blocks = total > 0 ? nblocks : 0;
     op.dev.nchunk = op.d_nchunk;
@@ -1406,6 +1408,8 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         int ncu = 0;
         HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         c->n_cu = std::max(1, ncu);
+        double *sp = nullptr;      // resolve this device's static scratch now
+        if (int rc2 = noalloc_scratch(&sp, err)) return fail(rc2, err);
     }
     {
         const int nsub = st.n_sub;
@@ -2127,6 +2131,32 @@ int bddc_apply_schur(bddc_ctx *c, const double *p, double *q) {
     a.n = c->n_gamma; a.want_wtr = 0; a.q = gather_of(c->opS, false); a.b = nullptr; a.out = q;
     a.W = c->d_W; a.ld = c->ld; a.ctl = c->d_ctl; a.part = c->d_wp;
     launch_resid(a, 0, c->vgrid, c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int bddc_apply_schur_noalloc(bddc_ctx *c, const double *p, double *q) {
+    if (!c || !p || !q) return fail(BDDC_EINVAL, "null argument");
+    double *sp = nullptr;
+    std::string err;
+    if (int rc = noalloc_scratch(&sp, err)) return fail(rc, err);
+    const int64_t need = c->opS.ylen + c->vgrid;
+    if (need > noalloc_scratch_doubles())
+        return fail(BDDC_EINVAL, "bddc_apply_schur_noalloc: this context's Schur product needs " + std::to_string(need) +
+                                     " doubles of scratch; the static array holds " +
+                                     std::to_string(noalloc_scratch_doubles()) + " (use bddc_apply_schur)");
+    // the same kernels as bddc_apply_schur, with the partial products and the
+    // per-block norm partials in the static array
+    SymvArgs a{};
+    a.op = c->opS.dev;
+    a.x = p;
+    a.ypart = sp;
+    a.ctl = c->d_ctl;
+    launch_symv(a, SYMV_SCHUR, 64, c->opS.cfg, c->opS.smem, c->stream);
+    ResidArgs r{};
+    r.n = c->n_gamma; r.want_wtr = 0; r.q = Gather{c->opS.d_yptr, c->opS.d_yidx, sp}; r.b = nullptr; r.out = q;
+    r.W = c->d_W; r.ld = c->ld; r.ctl = c->d_ctl; r.part = sp + c->opS.ylen;
+    launch_resid(r, 0, c->vgrid, c->stream);
     HIPCHK(hipStreamSynchronize(c->stream));
     return 0;
 }

@@ -79,6 +79,10 @@ int constraint_rows(Structure &st, std::string &err);
 int build_level2(Structure &st, const bddc_partition *p, std::string &err);
 int add_coarse_dofs(Structure &st, const bddc_partition *p, const std::vector<CoarseDof> &extra, std::string &err);
 
+// static device scratch of the allocation-free entry point (noalloc.hip)
+int64_t noalloc_scratch_doubles();
+int noalloc_scratch(double **out, std::string &err);
+
 // host dense helpers (hostla.cpp)
 bool cholesky(std::vector<double> &a, int n);                       // in place, lower
 void chol_solve(const std::vector<double> &l, int n, double *x);
