@@ -97,10 +97,12 @@ def make_rhs(s, n_rhs):
         return workload.rhs_sequence(s["nx"], n_rhs, s["elem_keep"])
     from concurrent.futures import ProcessPoolExecutor
     workers = max(1, min(16, len(os.sched_getaffinity(0)), n_rhs))
-    chunk = (n_rhs + workers - 1) // workers
-    jobs = [(s["nx"], k, min(chunk, n_rhs - k), s["elem_keep"]) for k in range(0, n_rhs, chunk)]
-    with ProcessPoolExecutor(max_workers=len(jobs)) as ex:
-        return np.concatenate(list(ex.map(_rhs_chunk, jobs)))
+    out = np.empty((n_rhs, workload.n_nodes(s["nx"])))
+    jobs = [(s["nx"], k, 1, s["elem_keep"]) for k in range(n_rhs)]
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        for k, f in enumerate(ex.map(_rhs_chunk, jobs, chunksize=1)):
+            out[k] = f[0]
+    return out
 
 
 def cpu_baseline(name, s, n_gpu_subs, budget_s=20.0):

@@ -107,7 +107,10 @@ def run_sequence(name, n_rhs, rtol, tag):
     hist = o.rec.history
     change = [ritz_change(hist[j], hist[j - 1]) if hist[j].size == hist[j - 1].size == s["R"] else -1.0
               for j in range(1, len(hist))]
-    np.savez_compressed(os.path.join(HERE, "%s_%s.npz" % (name, tag)), iters=np.array(its),
+    theta = np.full((len(hist), s["R"]), np.nan)     # selected values of every update (NaN: fewer)
+    for j, h in enumerate(hist):
+        theta[j, :h.size] = h
+    np.savez_compressed(os.path.join(HERE, "%s_%s.npz" % (name, tag)), iters=np.array(its), theta=theta,
                         true_relres=np.array(rr), u_norm2=np.array(un), u_sample=np.array(us), sample_nodes=idx,
                         rtol=rtol, R=s["R"], freeze_step=-1 if o.rec.freeze_step is None else o.rec.freeze_step,
                         ritz_change=np.array(change), seconds=time.time() - t)

@@ -193,51 +193,76 @@ def test_adjoint_gradient_matches_oracle():
     assert _rel(gF, lam) <= 1e-8
 
 
-def test_adjoint_gradient_central_differences_through_gpu_solves():
+def _fd_err(fd, g):
+    """|g - FD| / max(|FD|, 1e-3 max |FD|), the per-entry measure of the
+    finite-difference checks."""
+    return np.abs(g - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
+
+
+def test_adjoint_gradient_50_elements_central_differences():
+    # 50 seeded element indices of the 16^3 mesh (2x2x2 subdomains, two
+    # levels), every solve at rtol 1e-13; central differences of step 1e-4:
+    # at 1e-6 the rounding of L alone puts even direct-solve differences
+    # 5e-4 off (the CPU pin of the step), at 1e-4 truncation (O(1e-8)) and
+    # rounding stay below 1e-5; each entry must agree to 1e-5
     torch = _torch()
     F, T, theta = _adjoint_problem()
-    L, g, _ = _gpu_loss_and_grad(torch, theta, F, T, R=0)
+    rtol = 1e-13
+    L, g, _ = _gpu_loss_and_grad(torch, theta, F, T, R=0, rtol=rtol)
     eps = 1e-4
-    idx = np.random.default_rng(6).choice(16 ** 3, 5, replace=False)
+    idx = workload.rng("fd").choice(16 ** 3, 50, replace=False)
     fd = []
     for e in idx:
         tp, tm = theta.copy(), theta.copy()
         tp[e] += eps
         tm[e] -= eps
-        Lp = _gpu_loss_and_grad(torch, tp, F, T, R=0)[0]
-        Lm = _gpu_loss_and_grad(torch, tm, F, T, R=0)[0]
+        Lp = _gpu_loss_and_grad(torch, tp, F, T, R=0, rtol=rtol)[0]
+        Lm = _gpu_loss_and_grad(torch, tm, F, T, R=0, rtol=rtol)[0]
         fd.append((Lp - Lm) / (2 * eps))
-    fd = np.array(fd)
-    err = np.abs(g[idx] - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(g).max())
-    print("[gpu] FD rel err", err, flush=True)
-    assert err.max() < 1e-5
+    err = _fd_err(np.array(fd), g[idx])
+    print("[gpu] per-element FD errors: max %.2e median %.2e" % (err.max(), np.median(err)), flush=True)
+    assert err.max() <= 1e-5
 
 
 def test_adjoint_gradient_50_random_directions():
-    # directional central differences, step 1e-6, along 50 seeded random
-    # directions in the space of element log-coefficients (16^3)
-    # (solves at rtol 1e-14: a step of 1e-6 turns a relative solve error e into
-    # an error of about e / 1e-6 in the difference quotient)
+    # directional central differences (step 1e-4) along 50 seeded random unit
+    # directions in the space of element log-coefficients (16^3), each
+    # direction to 1e-5
     torch = _torch()
     F, T, theta = _adjoint_problem()
-    L, g, _ = _gpu_loss_and_grad(torch, theta, F, T, R=0, rtol=1e-14)
-    eps = 1e-6
-    rng = np.random.default_rng(8)
+    rtol = 1e-13
+    L, g, _ = _gpu_loss_and_grad(torch, theta, F, T, R=0, rtol=rtol)
+    eps = 1e-4
+    rng = workload.rng("fd", 1)
     fd, gv = [], []
     for _ in range(50):
         v = rng.standard_normal(theta.size)
         v /= np.linalg.norm(v)
-        Lp = _gpu_loss_and_grad(torch, theta + eps * v, F, T, R=0, rtol=1e-14)[0]
-        Lm = _gpu_loss_and_grad(torch, theta - eps * v, F, T, R=0, rtol=1e-14)[0]
+        Lp = _gpu_loss_and_grad(torch, theta + eps * v, F, T, R=0, rtol=rtol)[0]
+        Lm = _gpu_loss_and_grad(torch, theta - eps * v, F, T, R=0, rtol=rtol)[0]
         fd.append((Lp - Lm) / (2 * eps))
         gv.append(g @ v)
-    fd, gv = np.array(fd), np.array(gv)
-    rel = np.linalg.norm(fd - gv) / np.linalg.norm(fd)
-    worst = np.max(np.abs(fd - gv) / np.maximum(np.abs(fd), 1e-3 * np.linalg.norm(g)))
-    print("[gpu] directional FD: relative error %.2e over the 50 directions, worst single %.2e" % (rel, worst),
-          flush=True)
-    assert rel < 1e-5
-    assert worst < 1e-4
+    err = _fd_err(np.array(fd), np.array(gv))
+    print("[gpu] directional FD errors: max %.2e median %.2e" % (err.max(), np.median(err)), flush=True)
+    assert err.max() <= 1e-5
+
+
+def test_adjoint_rhs_gradient_10_directions():
+    # L is quadratic in F: a central difference along any direction is exact
+    # up to rounding, so a large step is used and the agreement is tight
+    torch = _torch()
+    F, T, theta = _adjoint_problem()
+    L, g, gF = _gpu_loss_and_grad(torch, theta, F, T, R=4, rtol=1e-13)
+    rng = workload.rng("fd", 2)
+    free = (np.arange(F.shape[1]) % 17) != 16
+    for _ in range(10):
+        d = rng.standard_normal(F.shape) * free
+        eps = 1e-2 * np.abs(F).max() / np.abs(d).max()
+        Lp = _gpu_loss_and_grad(torch, theta, F + eps * d, T, R=4, rtol=1e-13)[0]
+        Lm = _gpu_loss_and_grad(torch, theta, F - eps * d, T, R=4, rtol=1e-13)[0]
+        fd = (Lp - Lm) / (2 * eps)
+        an = float((gF * d).sum())
+        assert abs(fd - an) <= 1e-8 * abs(an), (fd, an)
 
 
 def _hole_solver(name, **kw):

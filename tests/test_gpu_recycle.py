@@ -90,6 +90,11 @@ def test_update_after_restarts_matches_oracle(name, every):
         if gr == orr:
             assert gs == os_
     assert any(r[0] > 0 for r in reps)
+    # (directions whose A-norm^2 is below 1e-12 of the largest are dropped
+    # from V = [W, P] on both sides, so short final runs near convergence add
+    # few columns)
     info = g.solve_info()
-    assert info["frozen"] == int(o.rec.frozen) and info["refused"] == 0 and info["deflation_cols"] == 4
+    assert info["frozen"] == int(o.rec.frozen) and info["refused"] == 0
+    assert info["deflation_cols"] == o.rec.W.shape[1]
     assert info["recycle_steps"] == (o.rec.freeze_step if o.rec.frozen else 5)
+    np.testing.assert_allclose(np.sort(g.ritz_values()), np.sort(o.rec.theta), rtol=1e-6)

@@ -54,3 +54,33 @@ def test_rhs_gradient_is_adjoint():
     Lm = adjoint.loss(nx, theta, F - eps * d, T)
     fr = q1.free_nodes(nx)
     np.testing.assert_allclose((Lp - Lm) / (2 * eps), (lam[:, fr] * d[:, fr]).sum(), rtol=1e-7)
+
+
+def test_central_difference_step_floor_16():
+    # Why the finite-difference checks use a step of 1e-4: with sparse direct
+    # solves (the oracle's most accurate path) L carries a rounding error
+    # e_L ~ 1e-14 L, which a central difference of step s turns into an error
+    # e_L / s in dL/dtheta_e, while the truncation error is O(s^2).  Per
+    # element, dL/dtheta_e is ~1e-3 L at most, so at s = 1e-6 the rounding
+    # term alone reaches ~1e-5..1e-3 of the largest entry, and at s = 1e-4 it
+    # drops a hundredfold while the truncation error (~1e-8) stays far below.
+    nx = 16
+    F = workload.rhs_sequence(nx, 3)
+    g = np.random.default_rng(4)
+    T = q1.direct_solve(nx, np.exp(0.5 * g.standard_normal(nx ** 3)), F)
+    theta = 0.3 * g.standard_normal(nx ** 3)
+    L, grad, lam, U = adjoint.loss_and_grad(nx, theta, F, T)
+    idx = workload.rng("fd").choice(nx ** 3, 20, replace=False)
+
+    def fd(eps):
+        out = []
+        for e in idx:
+            tp, tm = theta.copy(), theta.copy()
+            tp[e] += eps
+            tm[e] -= eps
+            out.append((adjoint.loss(nx, tp, F, T) - adjoint.loss(nx, tm, F, T)) / (2 * eps))
+        out = np.array(out)
+        return np.abs(grad[idx] - out) / np.maximum(np.abs(out), 1e-3 * np.abs(out).max())
+    e6, e4 = fd(1e-6), fd(1e-4)
+    assert e4.max() < 1e-5, e4
+    assert e6.max() > 10 * e4.max()      # the rounding floor at 1e-6

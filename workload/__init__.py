@@ -272,32 +272,52 @@ def gaussian_centres(n_rhs: int, n_gauss: int = 4, drift: float = 0.01) -> np.nd
 
 
 def nodal_source(nx: int, k: int, centres: np.ndarray, width: float = 0.1,
-                 noise: float = 1e-3, coords: np.ndarray | None = None) -> np.ndarray:
-    """Nodal values of f_k = sum_g exp(-|x-c|^2/(2 w^2)) + noise * N(0,1)
-    (``coords``: node_coords(nx), when the caller already has it)."""
-    x = node_coords(nx) if coords is None else coords
-    f = np.zeros(x.shape[0])
+                 noise: float = 1e-3) -> np.ndarray:
+    """Nodal values of f_k = sum_g exp(-|x-c|^2/(2 w^2)) + noise * N(0,1) on the
+    (nx+1)^3 grid of the unit cube.  Each Gaussian is the product of three
+    one-dimensional factors, formed as an outer product."""
+    t = np.arange(nx + 1) / nx
+    f = np.zeros((nx + 1, nx + 1, nx + 1))                 # (z, y, x), x fastest
     for c in centres[k]:
-        f += np.exp(-((x - c) ** 2).sum(axis=1) / (2.0 * width * width))
-    f += noise * rng("noise", k).standard_normal(x.shape[0])
+        g = [np.exp(-((t - c[d]) ** 2) / (2.0 * width * width)) for d in range(3)]
+        f += g[2][:, None, None] * (g[1][None, :, None] * g[0][None, None, :])
+    f = f.ravel()
+    f += noise * rng("noise", k).standard_normal(f.size)
     return f
 
 
 _M1 = np.array([[1.0 / 3.0, 1.0 / 6.0], [1.0 / 6.0, 1.0 / 3.0]])
 
 
-def consistent_load(nx: int, f_nodal: np.ndarray, elem_keep: np.ndarray | None = None,
-                    elem_nodes: np.ndarray | None = None) -> np.ndarray:
+def _mass_1d(v: np.ndarray, axis: int) -> np.ndarray:
+    """Apply the assembled one-dimensional mass matrix (unit spacing: 2/3 on
+    the diagonal, 1/3 at both ends, 1/6 beside it) along one axis."""
+    v = np.moveaxis(v, axis, 0)
+    out = v * (2.0 / 3.0)
+    out[0] = v[0] / 3.0
+    out[-1] = v[-1] / 3.0
+    out[1:] += v[:-1] / 6.0
+    out[:-1] += v[1:] / 6.0
+    return np.moveaxis(out, 0, axis)
+
+
+def consistent_load(nx: int, f_nodal: np.ndarray, elem_keep: np.ndarray | None = None) -> np.ndarray:
     """Load vector F = M f of trilinear interpolant f with the consistent Q1 mass.
 
     This is input preparation (turning a nodal source into a load vector), the
-    same for every consumer; M_e = h^3 (M1 (x) M1 (x) M1).
+    same for every consumer; M_e = h^3 (M1 (x) M1 (x) M1).  On the whole box the
+    assembled M is the Kronecker product of three one-dimensional mass
+    matrices and is applied axis by axis; with removed elements it is
+    assembled element by element.
     """
     h = 1.0 / nx
+    if elem_keep is None:
+        v = f_nodal.reshape(nx + 1, nx + 1, nx + 1)
+        for axis in range(3):
+            v = _mass_1d(v, axis)
+        return (v * h ** 3).ravel()
     mref = np.kron(_M1, np.kron(_M1, _M1)) * h ** 3  # vertex v = a + 2b + 4c, x fastest
-    en = element_nodes(nx) if elem_nodes is None else elem_nodes
-    if elem_keep is not None:
-        en = en[elem_keep.astype(bool)]
+    en = element_nodes(nx)[elem_keep.astype(bool)]
     fe = f_nodal[en] @ mref.T
     return np.bincount(en.ravel(), weights=fe.ravel(), minlength=n_nodes(nx))
 
@@ -307,10 +327,8 @@ def rhs_sequence(nx: int, n_rhs: int, elem_keep: np.ndarray | None = None,
     """(n_rhs, n_nodes) float64 load vectors F_k, k = first .. first+n_rhs-1."""
     cen = gaussian_centres(first + n_rhs)
     out = np.empty((n_rhs, n_nodes(nx)))
-    x = node_coords(nx)
-    en = element_nodes(nx)
     for i in range(n_rhs):
-        out[i] = consistent_load(nx, nodal_source(nx, first + i, cen, coords=x), elem_keep, elem_nodes=en)
+        out[i] = consistent_load(nx, nodal_source(nx, first + i, cen), elem_keep)
     return out
 
 
