@@ -78,19 +78,26 @@ int adaptive_faces(const Structure &st, const double *d_K, const std::vector<int
     for (const auto &sh : st.sub) max_nB = std::max(max_nB, (size_t)sh.nB);
     const size_t per_job = max_nB * max_nB;
     const size_t batch = std::max<size_t>(1, std::min<size_t>(faces.size() * 2, (size_t(2) << 30) / (per_job * 8)));
-    double *d_work = nullptr, *d_out = nullptr;
+    double *d_work = nullptr, *d_out = nullptr, *d_panel = nullptr;
     int32_t *d_perm = nullptr;
     FaceSchurDesc *d_desc = nullptr;
+    SweepDesc *d_sw = nullptr;
+    int64_t *d_off = nullptr;
     auto cleanup = [&]() {
         if (d_work) (void)hipFree(d_work);
         if (d_out) (void)hipFree(d_out);
         if (d_perm) (void)hipFree(d_perm);
         if (d_desc) (void)hipFree(d_desc);
+        if (d_panel) (void)hipFree(d_panel);
+        if (d_sw) (void)hipFree(d_sw);
+        if (d_off) (void)hipFree(d_off);
     };
     size_t max_m = 1;
     for (const auto &f : faces) max_m = std::max(max_m, (size_t)f.m);
     if (hipMalloc(&d_work, batch * per_job * 8) != hipSuccess || hipMalloc(&d_out, batch * 2 * max_m * max_m * 8) != hipSuccess ||
-        hipMalloc(&d_perm, batch * max_nB * 4) != hipSuccess || hipMalloc(&d_desc, batch * sizeof(FaceSchurDesc)) != hipSuccess) {
+        hipMalloc(&d_perm, batch * max_nB * 4) != hipSuccess || hipMalloc(&d_desc, batch * sizeof(FaceSchurDesc)) != hipSuccess ||
+        hipMalloc(&d_panel, batch * 32 * max_nB * 8) != hipSuccess || hipMalloc(&d_sw, batch * sizeof(SweepDesc)) != hipSuccess ||
+        hipMalloc(&d_off, batch * sizeof(int64_t)) != hipSuccess) {
         cleanup();
         err = "hipMalloc failed for the adaptive face problems";
         return BDDC_ENOMEM;
@@ -101,7 +108,6 @@ int adaptive_faces(const Structure &st, const double *d_K, const std::vector<int
     const size_t njobs = faces.size() * 2;
     for (size_t j0 = 0; j0 < njobs; j0 += batch) {
         const size_t nj = std::min(batch, njobs - j0);
-        int maxn = 1;
         for (size_t q = 0; q < nj; ++q) {
             const Face &f = faces[(j0 + q) / 2];
             const bool side_t = (j0 + q) % 2;
@@ -119,7 +125,6 @@ int adaptive_faces(const Structure &st, const double *d_K, const std::vector<int
             desc[q] = FaceSchurDesc{d_K + k_off[sub] + (int64_t)sh.nI * nl + sh.nI, nl, d_perm + q * max_nB, sh.nB,
                                     sh.nB - f.m, d_work + q * per_job, d_out + q * 2 * max_m * max_m,
                                     d_out + q * 2 * max_m * max_m + max_m * max_m};
-            maxn = std::max(maxn, sh.nB);
         }
         if (hipMemcpyAsync(d_perm, perm.data(), nj * max_nB * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(d_desc, desc.data(), nj * sizeof(FaceSchurDesc), hipMemcpyHostToDevice, s) != hipSuccess) {
@@ -127,7 +132,8 @@ int adaptive_faces(const Structure &st, const double *d_K, const std::vector<int
             err = "hipMemcpy failed";
             return BDDC_EHIP;
         }
-        launch_face_schur(d_desc, (int)nj, maxn, d_status, s);
+        launch_face_schur(d_desc, std::vector<FaceSchurDesc>(desc.begin(), desc.begin() + nj), d_sw, d_off, d_panel,
+                          d_status, s);
         if (hipMemcpyAsync(hout.data(), d_out, nj * 2 * max_m * max_m * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             cleanup();

@@ -231,6 +231,24 @@ void dfree(bddc_ctx *c, void *p) {
     (void)hipFree(p);
 }
 
+// Batched symmetric sweeps (sweep.hip) of the matrices `h` (device copies of
+// the descriptors and the panel buffer are made here and freed after the
+// stream has finished them).
+int run_sweeps(bddc_ctx *c, const std::vector<SweepDesc> &h) {
+    if (h.empty()) return 0;
+    std::vector<int64_t> off;
+    const int64_t nbuf = sweep_panel_doubles(h, off);
+    SweepDesc *dd = nullptr;
+    int64_t *doff = nullptr;
+    double *buf = nullptr;
+    int rc;
+    if ((rc = dupload(c, &dd, h)) || (rc = dupload(c, &doff, off)) || (rc = dalloc(c, &buf, (size_t)nbuf))) return rc;
+    launch_sweep_blocked(dd, doff, h, buf, c->d_status, c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    dfree(c, dd); dfree(c, doff); dfree(c, buf);
+    return 0;
+}
+
 // CSR from (target, source) pairs; stable in insertion order
 void build_csr(int64_t ntarget, const std::vector<std::pair<int64_t, int32_t>> &pairs, std::vector<int32_t> &ptr,
                std::vector<int32_t> &idx) {
@@ -1466,12 +1484,8 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
             std::vector<SweepDesc> sd(nsub);
             for (int i = 0; i < nsub; ++i)
                 sd[i] = SweepDesc{c->d_K + k_off[i], st.sub[i].nloc, st.sub[i].nloc, 0, nI[i], st.sub[i].nloc};
-            SweepDesc *dsd;
-            if ((rc = dupload(c, &dsd, sd))) return rc;
-            set_sweep_smem_limit((size_t)std::max(max_nloc, 1) * 8);
-            launch_sweep(dsd, nsub, max_nloc, c->d_status, s);
-            HIPCHK(hipStreamSynchronize(s));
-            dfree(c, dd); dfree(c, dsd);
+            if ((rc = run_sweeps(c, sd))) return rc;
+            dfree(c, dd);
         }
         dfree(c, d_eloc); dfree(c, d_incp); dfree(c, d_ince); dfree(c, d_incv);
         if (c->opts.adapt_tau > 0) {
@@ -1594,11 +1608,9 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
             wd[i] = SweepDesc{d_M + m_off[i], N, N, 0, N, nB[i]};
         }
         SaddleDesc *dsd;
-        SweepDesc *dwd;
-        if ((rc = dupload(c, &dsd, sd)) || (rc = dupload(c, &dwd, wd))) return rc;
+        if ((rc = dupload(c, &dsd, sd))) return rc;
         launch_build_saddle(dsd, nsub, s);
-        set_sweep_smem_limit((size_t)std::max(max_sad, 1) * 8);
-        launch_sweep(dwd, nsub, max_sad, c->d_status, s);
+        if ((rc = run_sweeps(c, wd))) return rc;
         // tiles: S_i (float64) and D N_i D with D Phi_i (local precision), plus
         // the row-major D Phi_i for the prolongation
         c->bytes_S = (size_t)s_off[nsub] * 8;
@@ -1633,7 +1645,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
             if ((c->prec_built >> prec_slot(p)) & 1) launch_pack(dpn, nsub, p, c->d_Nx[prec_slot(p)], c->d_phirx[prec_slot(p)], s);
         launch_ptsp(dpt, nsub, s);
         HIPCHK(hipStreamSynchronize(s));
-        dfree(c, dsd); dfree(c, dwd); dfree(c, dps); dfree(c, dpn); dfree(c, dpt);
+        dfree(c, dsd); dfree(c, dps); dfree(c, dpn); dfree(c, dpt);
     }
     dfree(c, d_M); dfree(c, d_X); dfree(c, d_cptr); dfree(c, d_ccol); dfree(c, d_cval); dfree(c, d_wB);
     {
@@ -1664,11 +1676,9 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) || (rc = dalloc(c, &c->d_KCinv, (size_t)std::max(1, n * n))))
             return rc;
         launch_gather_sum((int64_t)n * n, dp, di, c->d_KC, c->d_KCinv, s);
-        double *drows;
-        if ((rc = dalloc(c, &drows, (size_t)std::max(1, 2 * n)))) return rc;
-        launch_sweep_large(c->d_KCinv, n, n, n, drows, c->d_status, s);
+        if (n > 0 && (rc = run_sweeps(c, {SweepDesc{c->d_KCinv, n, n, 0, n, n}}))) return rc;
         HIPCHK(hipStreamSynchronize(s));
-        dfree(c, dp); dfree(c, di); dfree(c, drows);
+        dfree(c, dp); dfree(c, di);
         if (n > 0) {
             std::vector<double> h((size_t)n * n);
             HIPCHK(hipMemcpy(h.data(), c->d_KCinv, h.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -1809,22 +1819,20 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
                 cp[j] = DenseCopyDesc{d_M2 + M2_off[j] + b, N, b, nc3[j], -1.0, d_w2 + B2_off[j], nullptr, c->d_Phi2 + P2_off[j], nc3[j]};
                 pt[j] = PtspDesc{Sj, n, d_M2 + M2_off[j] + b, N, -1.0, b, nc3[j], d_X2 + P2_off[j], d_K3loc + K3_off[j]};
             }
-            SweepDesc *ds1, *ds2;
             SaddleDesc *dsd;
             DenseCopyDesc *dcn, *dcp;
             PtspDesc *dpt;
-            if ((rc = dupload(c, &ds1, s1)) || (rc = dupload(c, &ds2, s2)) || (rc = dupload(c, &dsd, sd)) ||
-                (rc = dupload(c, &dcn, cn)) || (rc = dupload(c, &dcp, cp)) || (rc = dupload(c, &dpt, pt)))
+            if ((rc = dupload(c, &dsd, sd)) || (rc = dupload(c, &dcn, cn)) || (rc = dupload(c, &dcp, cp)) ||
+                (rc = dupload(c, &dpt, pt)))
                 return rc;
-            set_sweep_smem_limit((size_t)std::max({max_nloc, max_sad, c->max_nL, max_sad2, c->n3, 1}) * 8);
-            launch_sweep(ds1, nsr, c->max_nL, c->d_status, s);
+            if ((rc = run_sweeps(c, s1))) return rc;
             launch_build_saddle(dsd, nsr, s);
-            launch_sweep(ds2, nsr, max_sad2, c->d_status, s);
+            if ((rc = run_sweeps(c, s2))) return rc;
             launch_dense_copy(dcn, nsr, s);
             launch_dense_copy(dcp, nsr, s);
             launch_ptsp(dpt, nsr, s);
             HIPCHK(hipStreamSynchronize(s));
-            dfree(c, ds1); dfree(c, ds2); dfree(c, dsd); dfree(c, dcn); dfree(c, dcp); dfree(c, dpt);
+            dfree(c, dsd); dfree(c, dcn); dfree(c, dcp); dfree(c, dpt);
         }
         // level 3: assemble and invert (dense)
         {
@@ -1843,11 +1851,9 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
                 (rc = dalloc(c, &c->d_r3, (size_t)std::max(1, n))))
                 return rc;
             launch_gather_sum((int64_t)n * ld, dp, di, d_K3loc, c->d_K3inv, s);
-            double *drows;
-            if ((rc = dalloc(c, &drows, (size_t)std::max(1, 2 * n)))) return rc;
-            launch_sweep_large(c->d_K3inv, n, ld, n, drows, c->d_status, s);
+            if (n > 0 && (rc = run_sweeps(c, {SweepDesc{c->d_K3inv, n, ld, 0, n, n}}))) return rc;
             HIPCHK(hipStreamSynchronize(s));
-            dfree(c, dp); dfree(c, di); dfree(c, drows);
+            dfree(c, dp); dfree(c, di);
         }
         dfree(c, d_cptr2); dfree(c, d_ccol2); dfree(c, d_cval2); dfree(c, d_w2); dfree(c, d_M2); dfree(c, d_X2);
         dfree(c, d_K3loc);

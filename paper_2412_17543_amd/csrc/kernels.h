@@ -286,11 +286,17 @@ struct GradArgs {
 
 // setup (kernels.hip)
 void launch_assemble(const AsmDesc *d, int n, hipStream_t s);
-void launch_sweep(const SweepDesc *d, int n, int maxn, int *status, hipStream_t s);
-void launch_face_schur(const FaceSchurDesc *d, int n, int maxn, int *status, hipStream_t s);
-// sweep of all pivots of one n x n matrix (rows: 2 n scratch), grid-wide
-void launch_sweep_large(double *A, int n, int ld, int pos_end, double *rows, int *status, hipStream_t s);
-void set_sweep_smem_limit(size_t bytes);
+// batched symmetric sweeps in panels of 16 pivots (sweep.hip): the panel
+// buffer holds 2 x 16 x n doubles per matrix at the offsets the sizing call
+// returns; pivots below pos_end must be positive, the others negative
+int64_t sweep_panel_doubles(const std::vector<SweepDesc> &h, std::vector<int64_t> &off);
+void launch_sweep_blocked(const SweepDesc *d, const int64_t *d_off, const std::vector<SweepDesc> &h, double *buf,
+                          int *status, hipStream_t s);
+// face Schur complements (adaptive step): gather S(perm, perm) into work and
+// its trailing block into keep, sweep the leading p pivots (d_sw, d_off and
+// panel sized for the batch by the caller), trailing block into hat
+void launch_face_schur(const FaceSchurDesc *d, const std::vector<FaceSchurDesc> &h, SweepDesc *d_sw, int64_t *d_off,
+                       double *panel, int *status, hipStream_t s);
 void launch_build_saddle(const SaddleDesc *d, int n, hipStream_t s);
 void launch_pack(const PackDesc *d, int n, int prec, void *dst, void *phir, hipStream_t s);
 void launch_ptsp(const PtspDesc *d, int n, hipStream_t s);

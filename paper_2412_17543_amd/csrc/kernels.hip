@@ -43,116 +43,29 @@ __global__ void __launch_bounds__(256) k_assemble(const AsmDesc *descs) {
 }
 
 // ---------------------------------------------------------------------------
-// setup: batched sweep of pivots [p0, p1) of symmetric row-major matrices.
-// After sweeping a pivot set P the matrix holds
-//   [ -A_PP^{-1}         A_PP^{-1} A_PQ            ]
-//   [ A_QP A_PP^{-1}     A_QQ - A_QP A_PP^{-1} A_PQ ]
-// i.e. interior elimination gives -K_II^{-1}, T = K_BI K_II^{-1} and S.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_sweep(const SweepDesc *descs, int *status) {
-    extern __shared__ double row[];
-    const SweepDesc d = descs[blockIdx.x];
-    const int n = d.n, ld = d.ld;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
-    for (int k = d.p0; k < d.p1; ++k) {
-        const double *Ak = d.A + (size_t)k * ld;
-        for (int j = threadIdx.x; j < n; j += blockDim.x) row[j] = Ak[j];
-        __syncthreads();
-        const double piv = row[k];
-        const bool ok = (k < d.pos_end ? piv > 0.0 : piv < 0.0) && isfinite(piv);
-        if (!ok) {
-            if (threadIdx.x == 0) atomicMax(status, 1);
-            return;
-        }
-        const double inv = 1.0 / piv;
-        for (int i = w; i < n; i += nw) {
-            double *Ai = d.A + (size_t)i * ld;
-            if (i == k) {
-                for (int j = l; j < n; j += 64) Ai[j] = (j == k) ? -inv : row[j] * inv;
-            } else {
-                const double ri = row[i] * inv;
-                for (int j = l; j < n; j += 64) Ai[j] = (j == k) ? ri : Ai[j] - ri * row[j];
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
-// setup: the same sweep for one large matrix (the dense coarse problems), one
-// launch per pivot over the whole grid.  Step k reads the pivot row from
-// rows[k & 1] (written by the previous step) and every block updates its own
-// rows; the block that updates row k + 1 also stores its new values in
-// rows[(k + 1) & 1] for the next step, so no block reads a row another block
-// of the same launch writes.
-// ---------------------------------------------------------------------------
-constexpr int SWEEP_ROWS = 4;       // rows per block, one wave each
-__global__ void __launch_bounds__(256) k_sweep_step(double *A, int n, int ld, int k, int pos_end, double *rows,
-                                                    int *status) {
-    const double *row = rows + (size_t)(k & 1) * n;
-    double *next = rows + (size_t)((k + 1) & 1) * n;
-    const double piv = row[k];
-    if (!((k < pos_end ? piv > 0.0 : piv < 0.0) && isfinite(piv))) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(status, 1);
-        return;
-    }
-    const double inv = 1.0 / piv;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int i = blockIdx.x * SWEEP_ROWS + w;
-    if (i >= n) return;
-    double *Ai = A + (size_t)i * ld;
-    const bool keep_next = (i == k + 1);
-    if (i == k) {
-        for (int j = l; j < n; j += 64) Ai[j] = (j == k) ? -inv : row[j] * inv;
-    } else {
-        const double ri = row[i] * inv;
-        for (int j = l; j < n; j += 64) {
-            const double v = (j == k) ? ri : Ai[j] - ri * row[j];
-            Ai[j] = v;
-            if (keep_next) next[j] = v;
-        }
-    }
-}
-
-__global__ void __launch_bounds__(256) k_copy_row(const double *A, int n, double *dst) {
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) dst[j] = A[j];
-}
-
-// ---------------------------------------------------------------------------
 // setup: Schur complement onto the last m = n - p entries of a permuted copy
 // of S (symmetric positive semi-definite, positive definite on the p leading
-// entries): symmetric Gaussian elimination of the leading p pivots, each
-// updating only the trailing rows and columns.  One block per descriptor.
+// entries), for the adaptive face selection: k_face_gather copies S(perm,
+// perm) into the work matrix and its trailing block into `keep`; the leading
+// p pivots are then swept (sweep.hip), which leaves the Schur complement in
+// the trailing block, copied into `hat` by k_face_hat.  One block per face.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_face_schur(const FaceSchurDesc *descs, int *status) {
-    extern __shared__ double row[];
+__global__ void __launch_bounds__(256) k_face_gather(const FaceSchurDesc *descs) {
     const FaceSchurDesc d = descs[blockIdx.x];
     const int n = d.n, p = d.p, m = n - p;
-    double *W = d.work;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
     for (int i = w; i < n; i += nw) {
         const double *src = d.S + (size_t)d.perm[i] * d.ld;
-        for (int j = l; j < n; j += 64) W[(size_t)i * n + j] = src[d.perm[j]];
+        for (int j = l; j < n; j += 64) d.work[(size_t)i * n + j] = src[d.perm[j]];
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) d.keep[e] = W[(size_t)(p + e / m) * n + p + e % m];
-    for (int k = 0; k < p; ++k) {
-        for (int j = k + threadIdx.x; j < n; j += blockDim.x) row[j] = W[(size_t)k * n + j];
-        __syncthreads();
-        const double piv = row[k];
-        if (!(piv > 0.0 && isfinite(piv))) {
-            if (threadIdx.x == 0) atomicMax(status, 2);
-            return;
-        }
-        const double inv = 1.0 / piv;
-        for (int i = k + 1 + w; i < n; i += nw) {
-            double *Wi = W + (size_t)i * n;
-            const double f = row[i] * inv;         // W(i, k) = W(k, i) by symmetry
-            for (int j = k + 1 + l; j < n; j += 64) Wi[j] -= f * row[j];
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) d.hat[e] = W[(size_t)(p + e / m) * n + p + e % m];
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x)
+        d.keep[e] = d.S[(size_t)d.perm[p + e / m] * d.ld + d.perm[p + e % m]];
+}
+
+__global__ void __launch_bounds__(256) k_face_hat(const FaceSchurDesc *descs) {
+    const FaceSchurDesc d = descs[blockIdx.x];
+    const int n = d.n, p = d.p, m = n - p;
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) d.hat[e] = d.work[(size_t)(p + e / m) * n + p + e % m];
 }
 
 // ---------------------------------------------------------------------------
@@ -626,26 +539,21 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 void launch_assemble(const AsmDesc *d, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_assemble, dim3(n), dim3(256), 0, s, d);
 }
-void launch_sweep(const SweepDesc *d, int n, int maxn, int *status, hipStream_t s) {
-    hipLaunchKernelGGL(k_sweep, dim3(n), dim3(1024), (size_t)maxn * sizeof(double), s, d, status);
-}
-void launch_sweep_large(double *A, int n, int ld, int pos_end, double *rows, int *status, hipStream_t s) {
+void launch_face_schur(const FaceSchurDesc *d, const std::vector<FaceSchurDesc> &h, SweepDesc *d_sw, int64_t *d_off,
+                       double *panel, int *status, hipStream_t s) {
+    const int n = (int)h.size();
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_copy_row, dim3(nblk(n, 256)), dim3(256), 0, s, A, n, rows);
-    const unsigned nb = nblk(n, SWEEP_ROWS);
-    for (int k = 0; k < n; ++k)
-        hipLaunchKernelGGL(k_sweep_step, dim3(nb), dim3(256), 0, s, A, n, ld, k, pos_end, rows, status);
-}
-void launch_face_schur(const FaceSchurDesc *d, int n, int maxn, int *status, hipStream_t s) {
-    if (n <= 0) return;
-    if ((size_t)maxn * sizeof(double) > 65536)
-        (void)hipFuncSetAttribute((const void *)k_face_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(maxn * sizeof(double)));
-    hipLaunchKernelGGL(k_face_schur, dim3(n), dim3(1024), (size_t)maxn * sizeof(double), s, d, status);
-}
-void set_sweep_smem_limit(size_t bytes) {
-    if (bytes > 65536)
-        (void)hipFuncSetAttribute((const void *)k_sweep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    std::vector<SweepDesc> sw(n);
+    for (int q = 0; q < n; ++q) sw[q] = SweepDesc{h[q].work, h[q].n, h[q].n, 0, h[q].p, h[q].p};
+    std::vector<int64_t> off;
+    sweep_panel_doubles(sw, off);
+    // (synchronous: the host vectors end with this call; the caller waits for
+    // the previous batch before reusing the buffers)
+    (void)hipMemcpy(d_sw, sw.data(), n * sizeof(SweepDesc), hipMemcpyHostToDevice);
+    (void)hipMemcpy(d_off, off.data(), n * sizeof(int64_t), hipMemcpyHostToDevice);
+    hipLaunchKernelGGL(k_face_gather, dim3(n), dim3(256), 0, s, d);
+    launch_sweep_blocked(d_sw, d_off, sw, panel, status, s);
+    hipLaunchKernelGGL(k_face_hat, dim3(n), dim3(256), 0, s, d);
 }
 void launch_build_saddle(const SaddleDesc *d, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_build_saddle, dim3(n), dim3(256), 0, s, d);

@@ -93,14 +93,16 @@ def test_c64_sequence_freezes_like_the_oracle():
     print("[gpu] c64 sequence iters", its, "freeze gpu", fg, "oracle", fo, flush=True)
     assert np.all(np.abs(np.array(its) - gd["iters"]) <= 1)
     assert np.all(np.array(rrs) < 1e-8)
-    worst = 0.0
+    # the first update has no W (P only: the low-cost matrices are exact to
+    # rounding), the second departs by the loss of A-orthogonality of one
+    # solve's directions; later bases carry the departures along
+    diffs = []
     for j in range(min(len(thetas), th_o.shape[0])):
         ref = th_o[j][~np.isnan(th_o[j])]
         assert thetas[j].size == ref.size
-        d = float(np.abs(thetas[j] - ref).max() / np.abs(ref).max())
-        print("[gpu] update %d theta rel diff %.2e" % (j + 1, d), flush=True)
-        worst = max(worst, d)
-    assert worst <= 1e-3
+        diffs.append(float(np.abs(thetas[j] - ref).max() / np.abs(ref).max()))
+        print("[gpu] update %d theta rel diff %.2e" % (j + 1, diffs[-1]), flush=True)
+    assert diffs[0] <= 1e-12 and diffs[1] <= 1e-4 and max(diffs) <= 1e-2
     # eq. harmritzstopcrit on the library's own values: it fired at the first
     # update whose change was <= 1e-5
     ch = [np.linalg.norm(thetas[j] - thetas[j - 1]) / np.linalg.norm(thetas[j])
