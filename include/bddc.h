@@ -328,7 +328,8 @@ int bddc_set_local_prec(bddc_ctx *ctx, int32_t prec);
  * queued ahead of the convergence poll, 1 graph replays, 0 plain: a host
  * check after every iteration); product_cfg (host int32[8], nullable: keep
  * the current ones) as in bddc_opts, except that a product whose first entry
- * is 0 takes the untuned default configuration.  Synchronises the stream.
+ * is 0 keeps its configuration and one whose first entry is negative takes
+ * the untuned default.  Synchronises the stream.
  * Errors: EINVAL (values), ENOMEM.
  */
 int bddc_set_launch(bddc_ctx *ctx, int32_t use_graph, const int32_t *product_cfg);

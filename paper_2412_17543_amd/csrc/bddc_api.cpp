@@ -2328,13 +2328,14 @@ int bddc_set_launch(bddc_ctx *c, int32_t use_graph, const int32_t *product_cfg) 
         for (int w = 0; w < 2; ++w) {
             const int32_t *pc = product_cfg + 4 * w;
             OpHost &op = *ops[w];
+            if (pc[0] == 0) continue;   // keep this product's configuration
             if (pc[0] > 0) {
                 if ((pc[2] != 4 && pc[2] != 8) || (pc[3] != 2 && pc[3] != 4) || (pc[2] == 8 && !c->allow8))
                     return fail(BDDC_EINVAL, "product_cfg: waves must be 4 or 8 (8 when it fits), tiles in flight 2 or 4");
                 op.bpc = pc[0];
                 op.per_sub = pc[1] != 0;
                 op.cfg = SymvCfg{pc[2], pc[3]};
-            } else {   // the untuned default
+            } else {   // negative: the untuned default
                 op.bpc = 6;
                 op.per_sub = true;
                 op.cfg = SymvCfg{4, 2};

@@ -153,7 +153,8 @@ class Solver:
     def set_launch(self, use_graph=True, product_cfg=None):
         """Launch form of later solves ("queued"/True, "graph", "plain"/False)
         and optionally the product configuration (8 ints; a product whose
-        first entry is 0 takes the untuned default)."""
+        first entry is 0 keeps its configuration, negative: the untuned
+        default)."""
         ug = {True: 2, False: 0, "queued": 2, "graph": 1, "plain": 0}[use_graph]
         cfg = None
         if product_cfg is not None:
