@@ -276,110 +276,123 @@ __global__ void __launch_bounds__(256) k_scatter_gamma(int n, const int32_t *gam
 }
 
 // ---------------------------------------------------------------------------
-// recycling: out[:, c] = sum_q V[:, q] Y[q][c] with V = [V1, V2] column-major
-// (leading dimension ld); blockIdx.y selects [W, P] or [AW, AP].  One row per
-// thread, all NC output columns in registers.  Y is the same for every lane:
-// it is read through the constant address space (scalar loads, operands of
-// the FMAs straight from scalar registers), and every entry of V is read
-// once.  The loads of GEMM_CHUNK columns of V are issued together, so that a
-// wave has that many in flight.  Y rows hold ldy >= ncol entries and the
-// buffer has NC entries of slack past row m-1 (columns >= ncol are read but
-// not stored).
+// recycling (Section 4.2) on the matrix cores, v_mfma_f64_16x16x4f64 (lane
+// layout: A[i][k] and B[k][j] in lane i (j) + 16 k; result (i, j) in lane
+// j + 16 (i % 4), register i / 4).
+//
+// k_recycle_gemm: out[:, c] = sum_q V[:, q] Y[q][c] with V = [V1, V2]
+// column-major (leading dimension ld); blockIdx.y selects [W, P] or
+// [AW, AP].  Each wave takes 16 rows and forms out^T = Y^T V^T for them, 16
+// columns per tile (NT tiles): the B operand is 16 consecutive rows of one
+// column of V (one coalesced load per lane and step of 4 columns), the A
+// operand entries of Y (a few KB, read through the cache), and each result
+// register holds 16 consecutive rows of one output column.
 // ---------------------------------------------------------------------------
-constexpr int GEMM_CHUNK = 16;
-template <int NC>
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+template <int NT>
 __global__ void __launch_bounds__(256) k_recycle_gemm(GemmArgs a) {
-    typedef const __attribute__((address_space(4))) double CD;
-    CD *Y = (CD *)a.Y;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     const double *V1 = a.V1[y], *V2 = a.V2[y];
+    const int w = threadIdx.x >> 6, L = threadIdx.x & 63, li = L & 15, lk = L >> 4;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 16;
+    if (r0 >= a.n) return;                           // (the whole wave)
+    const int64_t row = r0 + li;
+    const bool rok = row < a.n;
     const int m = a.k1 + a.k2;
-    const int gc = min(g, a.n - 1);          // rows past n load row n-1 and store nothing
-    double acc[NC];
+    dvec4 acc[NT];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    for (int q = 0; q < m; q += GEMM_CHUNK) {
-        double v[GEMM_CHUNK];
+    for (int t = 0; t < NT; ++t) acc[t] = dvec4{0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < m; q0 += 4) {
+        const int q = q0 + lk;
+        double b = 0.0;
+        if (q < m && rok) b = (q < a.k1 ? V1 + (int64_t)q * a.ld : V2 + (int64_t)(q - a.k1) * a.ld)[row];
 #pragma unroll
-        for (int u = 0; u < GEMM_CHUNK; ++u) {
-            const int qq = min(q + u, m - 1);   // past m: a valid column, weight 0
-            const double *col = qq < a.k1 ? V1 + (size_t)qq * a.ld : V2 + (size_t)(qq - a.k1) * a.ld;
-            v[u] = col[gc];
-        }
-#pragma unroll
-        for (int u = 0; u < GEMM_CHUNK; ++u) {
-            const int qq = min(q + u, m - 1);
-            const bool live = q + u < m;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const double yv = Y[(size_t)qq * a.ldy + c];
-                acc[c] += v[u] * (live ? yv : 0.0);
-            }
+        for (int t = 0; t < NT; ++t) {
+            const int c = 16 * t + li;
+            const double av = (q < m && c < a.ncol) ? a.Y[(int64_t)q * a.ldy + c] : 0.0;
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[t], 0, 0, 0);
         }
     }
-    if (g < a.n) {
+    if (!rok) return;
+    double *out = a.out[y];
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-            if (c < a.ncol) a.out[y][(size_t)c * a.ld + g] = acc[c];
-    }
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = 16 * t + lk + 4 * r;
+            if (c < a.ncol) out[(int64_t)c * a.ld + row] = acc[t][r];
+        }
 }
 
-// Gram partials: block b sums X^T Y (k x k, X and Y column-major n x k) over
-// its row range in slabs of GRAM_ROWS rows staged in LDS (padded rows, no
-// bank conflicts).  The pairs are taken in 2 x 2 blocks (kb = ceil(k/2) per
-// side), block t -> p in {2 (t/kb), +1}, q in {2 (t%kb), +1}, at most four
-// per thread.  part[(p*k+q) * nblocks + b]; a column reduction finishes the
-// (deterministic) sum.
+// ---------------------------------------------------------------------------
+// Gram product X^T Y (k x k, k <= 64) of two column-major n x k blocks:
+// per-block partials part[(p k + q) nblocks + block].  A block takes
+// consecutive chunks of GRAM_ROWS rows, stages both blocks of the chunk in
+// LDS (coalesced column loads), and each of its 4 waves multiplies its 16
+// rows of the chunk on the matrix cores into all T x T output tiles
+// (T = ceil(k / 16)); the waves' sums are added in wave order at the end.
+// ---------------------------------------------------------------------------
 constexpr int GRAM_ROWS = 64;
+template <int T>
 __global__ void __launch_bounds__(256) k_gram(GramArgs a) {
-    __shared__ double xs[RMAX][GRAM_ROWS + 1];
-    __shared__ double ys[RMAX][GRAM_ROWS + 1];
-    const int k = a.k, kb = (k + 1) / 2;
+    __shared__ double xs[16 * T][GRAM_ROWS + 1];
+    __shared__ double ys[16 * T][GRAM_ROWS + 1];
+    const int k = a.k;
+    const int w = threadIdx.x >> 6, L = threadIdx.x & 63, li = L & 15, lk = L >> 4;
     const int64_t per = (a.n + gridDim.x - 1) / gridDim.x;
     const int64_t g0 = (int64_t)blockIdx.x * per, g1 = min((int64_t)a.n, g0 + per);
-    constexpr int NB = (RMAX / 2) * (RMAX / 2) / 256;     // pair blocks per thread
-    double acc[NB][4];
+    dvec4 acc[T][T];
 #pragma unroll
-    for (int u = 0; u < NB; ++u)
+    for (int p = 0; p < T; ++p)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+        for (int q = 0; q < T; ++q) acc[p][q] = dvec4{0.0, 0.0, 0.0, 0.0};
     for (int64_t s0 = g0; s0 < g1; s0 += GRAM_ROWS) {
         const int nr = (int)min((int64_t)GRAM_ROWS, g1 - s0);
         __syncthreads();
-        for (int t = threadIdx.x; t < GRAM_ROWS * k; t += blockDim.x) {
+        for (int t = threadIdx.x; t < GRAM_ROWS * 16 * T; t += blockDim.x) {
             const int rr = t % GRAM_ROWS, c = t / GRAM_ROWS;
-            const bool ok = rr < nr;
+            const bool ok = rr < nr && c < k;
             xs[c][rr] = ok ? a.X[(int64_t)c * a.ld + s0 + rr] : 0.0;
             ys[c][rr] = ok ? a.Y[(int64_t)c * a.ld + s0 + rr] : 0.0;
         }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < NB; ++u) {
-            const int b = threadIdx.x + u * 256;
-            if (b < kb * kb) {
-                const int p0 = 2 * (b / kb), q0 = 2 * (b % kb);
-                const int p1 = min(p0 + 1, k - 1), q1 = min(q0 + 1, k - 1);
-                for (int rr = 0; rr < nr; ++rr) {
-                    const double x0 = xs[p0][rr], x1 = xs[p1][rr], y0 = ys[q0][rr], y1 = ys[q1][rr];
-                    acc[u][0] += x0 * y0;
-                    acc[u][1] += x0 * y1;
-                    acc[u][2] += x1 * y0;
-                    acc[u][3] += x1 * y1;
-                }
+        for (int s = 0; s < 4; ++s) {
+            const int rr = 16 * w + 4 * s + lk;
+            double av[T], bv[T];
+#pragma unroll
+            for (int p = 0; p < T; ++p) {
+                av[p] = xs[16 * p + li][rr];
+                bv[p] = ys[16 * p + li][rr];
             }
+#pragma unroll
+            for (int p = 0; p < T; ++p)
+#pragma unroll
+                for (int q = 0; q < T; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
         }
     }
+    // waves' sums in wave order through LDS (xs reused: 16 T x 16 T <= its size)
+    double *sum = &xs[0][0];
+    for (int wv = 0; wv < 4; ++wv) {
+        __syncthreads();
+        if (w == wv) {
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-        const int b = threadIdx.x + u * 256;
-        if (b >= kb * kb) continue;
-        const int p0 = 2 * (b / kb), q0 = 2 * (b % kb);
+            for (int p = 0; p < T; ++p)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int p = p0 + (v >> 1), q = q0 + (v & 1);
-            if (p < k && q < k) a.part[(int64_t)(p * k + q) * gridDim.x + blockIdx.x] = acc[u][v];
+                for (int q = 0; q < T; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = 16 * p + lk + 4 * r, j = 16 * q + li;
+                        const double v = acc[p][q][r];
+                        sum[i * 16 * T + j] = wv == 0 ? v : sum[i * 16 * T + j] + v;
+                    }
         }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+        const int i = e / k, j = e % k;
+        a.part[(int64_t)e * gridDim.x + blockIdx.x] = sum[i * 16 * T + j];
     }
 }
 
@@ -589,13 +602,17 @@ void launch_scatter_gamma(int n, const int32_t *gamma, const double *x, double *
 }
 void launch_recycle_gemm(const GemmArgs &a, hipStream_t s) {
     if (a.n <= 0) return;
-    const dim3 grid(nblk(a.n, 256), 2);
-    if (a.ncol <= 16) hipLaunchKernelGGL(k_recycle_gemm<16>, grid, dim3(256), 0, s, a);
-    else if (a.ncol <= 32) hipLaunchKernelGGL(k_recycle_gemm<32>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_recycle_gemm<64>, grid, dim3(256), 0, s, a);
+    const dim3 grid(nblk(a.n, 64), 2);                // 64 rows per block
+    if (a.ncol <= 16) hipLaunchKernelGGL(k_recycle_gemm<1>, grid, dim3(256), 0, s, a);
+    else if (a.ncol <= 32) hipLaunchKernelGGL(k_recycle_gemm<2>, grid, dim3(256), 0, s, a);
+    else if (a.ncol <= 48) hipLaunchKernelGGL(k_recycle_gemm<3>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_recycle_gemm<4>, grid, dim3(256), 0, s, a);
 }
 void launch_gram(const GramArgs &a, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_gram, dim3(nblocks), dim3(256), 0, s, a);
+    if (a.k <= 16) hipLaunchKernelGGL(k_gram<1>, dim3(nblocks), dim3(256), 0, s, a);
+    else if (a.k <= 32) hipLaunchKernelGGL(k_gram<2>, dim3(nblocks), dim3(256), 0, s, a);
+    else if (a.k <= 48) hipLaunchKernelGGL(k_gram<3>, dim3(nblocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_gram<4>, dim3(nblocks), dim3(256), 0, s, a);
 }
 void launch_elem_grad(const GradArgs &a, hipStream_t s) {
     if (a.n_elem > 0) hipLaunchKernelGGL(k_elem_grad, dim3(nblk(a.n_elem, 256)), dim3(256), 0, s, a);
