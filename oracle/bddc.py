@@ -38,6 +38,15 @@ the details to its reference; the reading used here:
     (dense Cholesky);
   * one application: interior pre-solve, interface residual, level-2 BDDC on
     the interface, interior post-correction (harmonic extension).
+
+Pure Neumann problem (no Dirichlet node; Section 2, the semidefinite case of
+eq. systems, and Section 4.1, its closing paragraph): K, A and the coarsest
+matrix (K_C for two levels, the level-3 matrix for three) are semidefinite,
+their null spaces spanned by the constant function; the local constrained
+problems stay nonsingular.  Reading: the coarsest problem is solved with the
+Moore-Penrose pseudo-inverse (its plain definition), which is what a singular
+coarse solve on consistent data needs; the constant itself is handled by the
+deflation basis (dpcg.py).
 """
 from __future__ import annotations
 
@@ -225,7 +234,7 @@ class _LocalSaddle:
 class Level2:
     """M_2^{-1} approximating K_C^{-1}: BDDC with subdomains as elements."""
 
-    def __init__(self, n_coarse, S1, is_corner, KC_loc, cidx, sub_to_subregion, is_adaptive=None):
+    def __init__(self, n_coarse, S1, is_corner, KC_loc, cidx, sub_to_subregion, is_adaptive=None, singular=False):
         self.nC = n_coarse
         s2r = np.asarray(sub_to_subregion)
         self.n_sr = int(s2r.max()) + 1
@@ -324,7 +333,11 @@ class Level2:
                 K3[np.ix_(d["c3"], d["c3"])] += sad.KC
             self.loc.append(d)
         self.K3 = K3
-        self.K3_cho = sla.cho_factor(K3) if self.n3 else None
+        self.singular = singular
+        if singular:
+            self.K3_pinv = np.linalg.pinv(K3, rcond=1e-10, hermitian=True) if self.n3 else None
+        else:
+            self.K3_cho = sla.cho_factor(K3) if self.n3 else None
 
     def _kii(self, d, v):
         return sla.cho_solve(d["KII_cho"], v) if d["KII_cho"] is not None else np.zeros(0)
@@ -345,7 +358,10 @@ class Level2:
             us.append(d["sad"].neumann(gj))
             if d["c3"].size:
                 r3[d["c3"]] += d["sad"].Phi.T @ gj
-        u3 = sla.cho_solve(self.K3_cho, r3) if self.n3 else np.zeros(0)
+        if not self.n3:
+            u3 = np.zeros(0)
+        else:
+            u3 = self.K3_pinv @ r3 if self.singular else sla.cho_solve(self.K3_cho, r3)
         xG = np.zeros(self.gamma2.size)
         for d, u in zip(self.loc, us):
             w = u + (d["sad"].Phi @ u3[d["c3"]] if d["c3"].size else 0.0)
@@ -396,19 +412,27 @@ class BDDC:
             self.loc.append(_LocalSaddle(d["K"], d["Bpos"], C))
         KC_loc = [s.KC for s in self.loc]
         self.three_level = sub_to_subregion is not None
+        # no Dirichlet node: the constant function has zero energy
+        self.singular = not bool((ss.used & ss.dir).any())
         if self.three_level:
-            self.level2 = Level2(self.nC, S1, is_corner, KC_loc, self.cidx, sub_to_subregion, is_adaptive)
+            self.level2 = Level2(self.nC, S1, is_corner, KC_loc, self.cidx, sub_to_subregion, is_adaptive,
+                                 self.singular)
         else:
             KC = np.zeros((self.nC, self.nC))
             for i, s in enumerate(self.loc):
                 KC[np.ix_(self.cidx[i], self.cidx[i])] += s.KC
             self.KC = KC
-            self.KC_cho = sla.cho_factor(KC) if self.nC else None
+            if self.singular:
+                self.KC_pinv = np.linalg.pinv(KC, rcond=1e-10, hermitian=True) if self.nC else None
+            else:
+                self.KC_cho = sla.cho_factor(KC) if self.nC else None
 
     def coarse_solve(self, rC):
         if self.three_level:
             return self.level2.apply(rC)
-        return sla.cho_solve(self.KC_cho, rC) if self.nC else np.zeros(0)
+        if not self.nC:
+            return np.zeros(0)
+        return self.KC_pinv @ rC if self.singular else sla.cho_solve(self.KC_cho, rC)
 
     def apply(self, r):
         """z = M^{-1} r (eqs. averaging_subdomain_solves, coarse_problem, localCorr)."""

@@ -31,6 +31,14 @@ the first search direction after the last replacement, so that the directions
 offered for recycling, P[seg_start:], come from one unbroken run of Algorithm 1
 with the same W.
 
+``null_vec`` (Section 4.1, closing paragraph: for a semidefinite A with a
+known null space, a basis vector of it is added as a column of W).  Reading:
+such a column w0 (A w0 = 0) enters the projections of Algorithm 1 with the
+Euclidean inner product, i.e. its "A W" column is w0 itself, so that
+W^T A W stays nonsingular, mu_0 = w0^T z / w0^T w0 and every search direction
+(and, from a guess orthogonal to it, the iterate) stays orthogonal to w0; the
+other columns of W must be orthogonal to w0.
+
 ``restart_every`` (not in the paper; 0 = off) ends a run after that many
 passes without convergence: the true residual is then evaluated and, unless it
 meets the tolerance, replaces the recursive one and the iteration restarts
@@ -42,12 +50,15 @@ import numpy as np
 
 
 def dpcg(apply_A, apply_M, b, x_init=None, W=None, rtol=1e-8, max_it=1000,
-         stop="rhs", reorth=False, record=True, restart_every=0):
+         stop="rhs", reorth=False, record=True, restart_every=0, null_vec=None):
     n = b.size
     if W is None:
         W = np.zeros((n, 0))
+    AW = np.column_stack([apply_A(W[:, c]) for c in range(W.shape[1])]) if W.shape[1] else np.zeros((n, 0))
+    if null_vec is not None:
+        W = np.column_stack([null_vec, W])
+        AW = np.column_stack([null_vec, AW])
     k = W.shape[1]
-    AW = np.column_stack([apply_A(W[:, c]) for c in range(k)]) if k else np.zeros((n, 0))
     WAW = W.T @ AW
     WAW = 0.5 * (WAW + WAW.T)
 

@@ -19,8 +19,8 @@ class OracleSolver:
     def __init__(self, nx, elem_to_sub, coef, elem_keep=None, sub_to_subregion=None,
                  weight_kind="diag", constraints=("corners", "faces"), R=0, strategy="B4",
                  freeze_tol=1e-5, stop="rhs", init_guess="prev", all_corners=False, reorth=False,
-                 adaptive=None, restart_every=0):
-        self.ss = Substructuring(nx, elem_to_sub, coef, elem_keep)
+                 adaptive=None, restart_every=0, dirichlet=None):
+        self.ss = Substructuring(nx, elem_to_sub, coef, elem_keep, dirichlet)
         self.M = BDDC(self.ss, weight_kind, constraints, sub_to_subregion, all_corners, adaptive)
         self.rec = Recycler(R, strategy, freeze_tol)
         self.stop = stop
@@ -28,6 +28,10 @@ class OracleSolver:
         self.reorth = reorth
         self.restart_every = restart_every
         self.x_prev = np.zeros(self.ss.n_gamma)
+        # pure Neumann (Section 4.1): the constant interface vector joins W
+        self.null_vec = None
+        if self.M.singular:
+            self.null_vec = np.ones(self.ss.n_gamma) / np.sqrt(self.ss.n_gamma)
 
     def reset(self):
         self.rec = Recycler(self.rec.R, self.rec.strategy, self.rec.freeze_tol)
@@ -39,7 +43,7 @@ class OracleSolver:
         W = self.rec.basis(ss.n_gamma)
         x0 = self.x_prev if self.init_guess == "prev" else np.zeros(ss.n_gamma)
         res = dpcg(ss.apply_A, self.M.apply, b, x0, W, rtol, max_it, self.stop, reorth=self.reorth,
-                   restart_every=self.restart_every)
+                   restart_every=self.restart_every, null_vec=self.null_vec)
         self.x_prev = res["x"]
         if update:
             Ps = res["P"][res["seg_start"]:]            # the run after the last replacement

@@ -332,6 +332,15 @@ def rhs_sequence(nx: int, n_rhs: int, elem_keep: np.ndarray | None = None,
     return out
 
 
+def consistent_neumann(nx: int, F: np.ndarray, elem_keep: np.ndarray | None = None) -> np.ndarray:
+    """Load vectors made consistent for the pure Neumann problem (no Dirichlet
+    node: K has the constants as null space, so F must sum to zero): the
+    source is shifted by a constant, F - c M 1, with c = sum(F) / sum(M 1)."""
+    m = consistent_load(nx, np.ones(n_nodes(nx)), elem_keep)
+    F = np.atleast_2d(F)
+    return F - np.outer(F.sum(axis=1) / m.sum(), m)
+
+
 # ----------------------------------------------------------------------------
 # named workloads
 # ----------------------------------------------------------------------------
@@ -351,6 +360,9 @@ def workload(name: str) -> dict:
       50 right-hand sides.
     * ``c3s``: the same construction at 24^3 with 24 subdomains in 3
       subregions (parity-test size).
+    * ``c16n``, ``tiny3n``: ``c16`` and ``tiny3`` without Dirichlet nodes (the
+      pure Neumann problem; ``node_dirichlet`` all zero, right-hand sides made
+      consistent with ``consistent_neumann``).
     """
     specs = {
         "tiny": dict(nx=8, sub=4, group=0, R=0, n_rhs=3),
@@ -362,7 +374,8 @@ def workload(name: str) -> dict:
     }
     if name in ("c3", "c3s"):
         return _hole_workload(name)
-    s = dict(specs[name])
+    neumann = name.endswith("n") and name[:-1] in specs
+    s = dict(specs[name[:-1] if neumann else name])
     nx, sub, group = s["nx"], s["sub"], s["group"]
     m = nx // sub
     s["elem_to_sub"] = cube_partition(nx, sub)
@@ -376,6 +389,7 @@ def workload(name: str) -> dict:
     s["coef"] = np.ones(nx ** 3)
     s["elem_keep"] = None
     s["name"] = name
+    s["node_dirichlet"] = np.zeros(n_nodes(nx), dtype=np.uint8) if neumann else None
     return s
 
 
@@ -392,4 +406,5 @@ def _hole_workload(name: str) -> dict:
     s["sub_to_subregion"] = rcb_subregions(nx, part, keep, n_sr)
     s["n_subregion"] = n_sr
     s["coef"] = lognormal_coef(nx ** 3, 0.5)
+    s["node_dirichlet"] = None
     return s
