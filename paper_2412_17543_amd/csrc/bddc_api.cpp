@@ -135,6 +135,10 @@ struct bddc_ctx {
            *d_t2 = nullptr, *d_rB2 = nullptr, *d_u2 = nullptr, *d_c3loc = nullptr, *d_u3 = nullptr;
     // deflation / recycling
     int R = 0, k = 0, save_cap = 0, kmax = 0;
+    // pure Neumann problem (no Dirichlet node): column 0 of W is the constant
+    // interface vector w0 = 1 / sqrt(n_gamma), with w0 itself as its "A W"
+    // column, and the recycled columns follow it
+    int nullc = 0;
     int64_t ld = 0;
     double *d_W = nullptr, *d_AW = nullptr, *d_Wn = nullptr, *d_AWn = nullptr, *d_P = nullptr, *d_AP = nullptr;
     double *d_WAWinv = nullptr, *d_Y = nullptr, *d_WAWnew = nullptr, *d_WAWsym = nullptr, *d_invnew = nullptr;
@@ -681,7 +685,7 @@ void run_resid(bddc_ctx *c, double *out, bool want_wtr) {
 void enqueue_iteration(bddc_ctx *c) {
     run_schur(c, c->d_p, true, true);                    // line 9: A p_j, p_j^T A p_j
     run_update(c);                                       // lines 9-11
-    if (c->opts.reorth && c->R > 0) run_reorth(c);       // optional line
+    if (c->opts.reorth && c->R + c->nullc > 0) run_reorth(c);   // optional line
     run_precond(c, c->d_r, c->d_z, 1, true, true, true); // stopping test, line 13
     run_pupd(c, false, false, true, 1);                  // lines 14-16 (the test while recording)
 }
@@ -879,7 +883,8 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     *c->h_flags = 0;
     c->rtol2_run = rtol * rtol;
     const int every = c->opts.restart_every;
-    launch_ctl_init(c->d_ctl, rtol * rtol, record ? 1 : 0, c->R > 0 ? c->d_state : nullptr, c->d_hflag, c->d_hprog,
+    launch_ctl_init(c->d_ctl, rtol * rtol, record ? 1 : 0, c->R + c->nullc > 0 ? c->d_state : nullptr, c->d_hflag,
+                    c->d_hprog,
                     every > 0 ? every : INT32_MAX, c->stream);
     if (!condensed) run_condense(c, F);                  // b, ||b||^2 partials
     if (!c->pre_schur) {
@@ -887,7 +892,7 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
         run_schur(c, c->d_x, false, false);              // r = b - A x_{-1}
     }
     c->pre_schur = false;
-    run_resid(c, c->d_r, c->R > 0);
+    run_resid(c, c->d_r, c->R + c->nullc > 0);
     {
         TScope ts(c, TK_VEC);
         DeflArgs d{};                                     // Alg. 1 lines 3-4 (k = 0: ||r||^2 only)
@@ -952,18 +957,23 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
 // adopted at the next synchronisation (resolve_pending).
 int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol, const std::vector<double> &gww,
                 const std::vector<double> &theta, bool freeze, int j0) {
+    // (Y: m = recycled columns + stored directions rows, ncol recycled columns)
     const int ldy = (ncol + 7) / 8 * 8;
     std::memset(c->h_Y, 0, (size_t)m * ldy * sizeof(double));
     for (int q = 0; q < m; ++q)
         for (int j = 0; j < ncol; ++j) c->h_Y[(size_t)q * ldy + j] = Y[(size_t)q * ncol + j];
     HIPCHK(hipMemcpyAsync(c->d_Y, c->h_Y, (size_t)m * ldy * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    const int l = m - c->k;
+    // recycled columns only: a pure Neumann problem's constant column 0 stays
+    // in place in W, A W and the new buffers (set at setup)
+    const int nc0 = c->nullc, k1 = c->k - nc0, l = m - k1;
+    const size_t o0 = (size_t)nc0 * c->ld;
     GemmArgs g{};
     g.n = c->n_gamma; g.ld = c->ld; g.Y = c->d_Y; g.ncol = ncol; g.ldy = ldy;
-    g.k1 = c->k; g.k2 = l;
-    g.V1[0] = c->d_W; g.V2[0] = c->d_P + (size_t)j0 * c->ld; g.out[0] = c->d_Wn;
-    g.V1[1] = c->d_AW; g.V2[1] = c->d_AP + (size_t)j0 * c->ld; g.out[1] = c->d_AWn;
+    g.k1 = k1; g.k2 = l;
+    g.V1[0] = c->d_W + o0; g.V2[0] = c->d_P + (size_t)j0 * c->ld; g.out[0] = c->d_Wn + o0;
+    g.V1[1] = c->d_AW + o0; g.V2[1] = c->d_AP + (size_t)j0 * c->ld; g.out[1] = c->d_AWn + o0;
     launch_recycle_gemm(g, c->stream);
+    ncol += nc0;                    // the Gram product, Cholesky and commit cover all columns
     const int nb = c->gram_nb;
     GramArgs gr{};
     gr.n = c->n_gamma; gr.k = ncol; gr.ld = c->ld; gr.X = c->d_Wn; gr.Y = c->d_AWn; gr.part = c->d_gp;
@@ -1013,7 +1023,9 @@ int do_recycle(bddc_ctx *c) {
     // replacement (all of them without one), as many as were stored
     const int j0 = c->seg_start;
     const int l = std::max(0, std::min(c->last_iters, c->save_cap) - j0);
-    const int k = c->k, m = k + l;
+    // the recycled columns of W (after the constant one of a pure Neumann problem)
+    const int nc0 = c->nullc, kt = c->k, k = kt - nc0, m = k + l;
+    auto waw = [&](int i, int j) { return c->WAW[(size_t)(i + nc0) * kt + j + nc0]; };
     c->n_updates++;
     if (strat == 1 || strat == 2) {
         // B1: first R search directions; B2: sliding window of the last R
@@ -1034,13 +1046,13 @@ int do_recycle(bddc_ctx *c) {
     // scalars of the last solve
     const size_t hn = (size_t)c->hist_cap;
     const double *al = c->h_hist + j0, *dd = c->h_hist + hn + j0, *rho = c->h_hist + 2 * hn + j0,
-                 *mu = c->h_hist + 3 * hn + (size_t)j0 * RMAX;
+                 *mu = c->h_hist + 3 * hn + (size_t)j0 * RMAX + nc0;
     // F = V^T A V = blockdiag(W^T A W, diag(d)) and G = V^T A M^{-1} A V from the
     // recurrences of Algorithm 1: M^{-1} A p_j = (z_j - z_{j+1}) / alpha_j
     std::vector<double> F((size_t)m * m, 0.0), G((size_t)m * m, 0.0);
     for (int i = 0; i < k; ++i)
         for (int j = 0; j < k; ++j) {
-            F[(size_t)i * m + j] = c->WAW[(size_t)i * k + j];
+            F[(size_t)i * m + j] = waw(i, j);
             G[(size_t)i * m + j] = c->GWW[(size_t)i * k + j];
         }
     for (int j = 0; j < l; ++j) {
@@ -1055,7 +1067,7 @@ int do_recycle(bddc_ctx *c) {
         for (int i = 0; i < k; ++i) {
             double s = 0.0;
             for (int q = 0; q < k; ++q)
-                s += c->WAW[(size_t)i * k + q] * (mu[(size_t)j * RMAX + q] - mu[(size_t)(j + 1) * RMAX + q]);
+                s += waw(i, q) * (mu[(size_t)j * RMAX + q] - mu[(size_t)(j + 1) * RMAX + q]);
             s /= al[j];
             G[(size_t)i * m + k + j] = s;
             G[(size_t)(k + j) * m + i] = s;
@@ -1189,6 +1201,75 @@ const char *bddc_last_error(void) { return g_err.c_str(); }
 }  // extern "C"
 
 namespace {
+
+// Pure Neumann problem: column 0 of W (and of A W, by the reading that it
+// enters the projections with the Euclidean inner product) is the constant
+// interface vector w0 = 1/sqrt(n_gamma), its block of W^T A W (and W^T W) is
+// 1, and the basis holds it alone after setup and after a reset.
+void init_null_column(bddc_ctx *c) {
+    if (!c->nullc) return;
+    const double v = 1.0 / std::sqrt((double)c->n_gamma);
+    for (double *w : {c->d_W, c->d_AW, c->d_Wn, c->d_AWn})
+        if (w) launch_fill(c->n_gamma, v, w, c->stream);
+    launch_fill(1, 1.0, c->d_WAWinv, c->stream);
+    launch_fill(1, 1.0, c->d_WWinv, c->stream);
+    if (c->d_state) launch_set_state(c->d_state, 1, 1, c->stream);
+    c->k = 1;
+    c->WAW.assign(1, 1.0);
+}
+
+// Values of the level-1 coarse DOFs on the constant function 1 (the null
+// vector of the coarse matrix of a pure Neumann problem): 1 for corners and
+// averages, the sum of the weights for weighted rows (0 for the adaptive
+// rows, which are orthogonal to the face average).
+std::vector<double> coarse_null_vector(const Structure &st) {
+    std::vector<double> e(st.coarse.size(), 1.0);
+    for (size_t q = 0; q < st.coarse.size(); ++q) {
+        const CoarseDof &d = st.coarse[q];
+        if (d.wts.empty()) continue;
+        double s = 0.0;
+        for (double w : d.wts) s += w;
+        e[q] = s;
+    }
+    return e;
+}
+
+// Mean of the diagonal of an n x n matrix with leading dimension ld.
+double diag_mean(const double *A, int n, int64_t ld, int &rc) {
+    std::vector<double> d((size_t)std::max(n, 1));
+    rc = 0;
+    if (n == 0) return 1.0;
+    if (hipMemcpy2D(d.data(), sizeof(double), A, (size_t)(ld + 1) * sizeof(double), sizeof(double), n,
+                    hipMemcpyDeviceToHost) != hipSuccess) {
+        rc = fail(BDDC_EHIP, "hipMemcpy2D of a coarse diagonal failed");
+        return 1.0;
+    }
+    double s = 0.0;
+    for (double x : d) s += x;
+    return s / n;
+}
+
+// Inverse of a semidefinite coarsest matrix K with null vector e (pure
+// Neumann problem), in the sweep's sign convention: the sweep of K + a e e^T
+// (a = mean diagonal / e^T e) leaves -(K + a e e^T)^{-1}; adding
+// e e^T / (a (e^T e)^2) gives -K^+, since (K + a e e^T)^{-1} and K^+ agree on
+// e's complement and (K + a e e^T)^{-1} e = e / (a e^T e).
+int sweep_semidefinite(bddc_ctx *c, double *A, int n, int64_t ld, const std::vector<double> &e) {
+    double ee = 0.0;
+    for (double x : e) ee += x * x;
+    if (n == 0 || !(ee > 0.0)) return fail(BDDC_ESINGULAR, "semidefinite coarse matrix without a null vector");
+    int rc;
+    const double a = diag_mean(A, n, ld, rc) / ee;
+    if (rc) return rc;
+    double *de;
+    if ((rc = dupload(c, &de, e))) return rc;
+    launch_rank1(A, ld, n, de, a, c->stream);
+    if ((rc = run_sweeps(c, {SweepDesc{A, n, (int)ld, 0, n, n}}))) return rc;
+    launch_rank1(A, ld, n, de, 1.0 / (a * ee * ee), c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    dfree(c, de);
+    return 0;
+}
 
 // Product blocks for `per_cu` blocks per compute unit, at most one per 16
 // tiles.
@@ -1420,6 +1501,18 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
     int rc = build_structure(mesh, part, coef, &c->opts, st, err);
     if (rc) return fail(rc, err);
     hipStream_t s = c->stream;
+    // pure Neumann problem: no kept element touches a Dirichlet node
+    if (mesh->node_dirichlet) {
+        bool any = false;
+        const int64_t n1x = mesh->nx + 1, n1y = mesh->ny + 1;
+        for (int64_t e = 0; e < st.n_elem && !any; ++e) {
+            if (mesh->elem_keep && !mesh->elem_keep[e]) continue;
+            const int64_t ex = e % mesh->nx, ey = (e / mesh->nx) % mesh->ny, ez = e / ((int64_t)mesh->nx * mesh->ny);
+            for (int v = 0; v < 8 && !any; ++v)
+                any = mesh->node_dirichlet[(ex + (v & 1)) + n1x * ((ey + ((v >> 1) & 1)) + n1y * (ez + (v >> 2)))] != 0;
+        }
+        c->nullc = any ? 0 : 1;
+    }
     {
         int dev = 0;
         HIPCHK(hipGetDevice(&dev));
@@ -1676,7 +1769,11 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) || (rc = dalloc(c, &c->d_KCinv, (size_t)std::max(1, n * n))))
             return rc;
         launch_gather_sum((int64_t)n * n, dp, di, c->d_KC, c->d_KCinv, s);
-        if (n > 0 && (rc = run_sweeps(c, {SweepDesc{c->d_KCinv, n, n, 0, n, n}}))) return rc;
+        if (n > 0 && c->nullc) {
+            if ((rc = sweep_semidefinite(c, c->d_KCinv, n, n, coarse_null_vector(st)))) return rc;
+        } else if (n > 0 && (rc = run_sweeps(c, {SweepDesc{c->d_KCinv, n, n, 0, n, n}}))) {
+            return rc;
+        }
         HIPCHK(hipStreamSynchronize(s));
         dfree(c, dp); dfree(c, di);
         if (n > 0) {
@@ -1851,7 +1948,18 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
                 (rc = dalloc(c, &c->d_r3, (size_t)std::max(1, n))))
                 return rc;
             launch_gather_sum((int64_t)n * ld, dp, di, d_K3loc, c->d_K3inv, s);
-            if (n > 0 && (rc = run_sweeps(c, {SweepDesc{c->d_K3inv, n, ld, 0, n, n}}))) return rc;
+            if (n > 0 && c->nullc) {
+                // the level-3 values of the constant: means of its level-1 values
+                const std::vector<double> e1 = coarse_null_vector(st);
+                std::vector<double> e3(n, 0.0);
+                for (int m3 = 0; m3 < n; ++m3) {
+                    for (int32_t q : st.dof3_members[m3]) e3[m3] += e1[q];
+                    e3[m3] /= (double)st.dof3_members[m3].size();
+                }
+                if ((rc = sweep_semidefinite(c, c->d_K3inv, n, ld, e3))) return rc;
+            } else if (n > 0 && (rc = run_sweeps(c, {SweepDesc{c->d_K3inv, n, ld, 0, n, n}}))) {
+                return rc;
+            }
             HIPCHK(hipStreamSynchronize(s));
             dfree(c, dp); dfree(c, di);
         }
@@ -1872,7 +1980,8 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
     const int ng = c->n_gamma;
     c->ld = ng;
     c->R = c->opts.recycle_R;
-    c->kmax = kmax_bucket(c->R);
+    if (c->R + c->nullc > RMAX) return fail(BDDC_EINVAL, "recycle_R plus the constant column exceeds 64");
+    c->kmax = kmax_bucket(c->R + c->nullc);
     c->save_cap = c->R > 0 ? c->opts.save_cap : 0;
     c->hist_cap = c->opts.max_it + 2;
     c->vgrid = std::max(1, std::min(VGRID, (ng + 255) / 256));
@@ -1920,7 +2029,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
     {
         // W, AW always exist (k = 0 columns are never read); the recycling
         // buffers only with R > 0
-        const size_t cols = (size_t)std::max(1, c->R);
+        const size_t cols = (size_t)std::max(1, c->R + c->nullc);
         // (+ RMAX: the recycling product reads up to 64 entries past a row)
         const int ymax = std::max((c->R + c->save_cap) * ((c->R + 7) / 8 * 8), RMAX * RMAX) + RMAX;
         if ((rc = dalloc(c, &c->d_W, cols * ng)) || (rc = dalloc(c, &c->d_AW, cols * ng)) ||
@@ -1944,6 +2053,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
             c->coarse_dense = true;
         }
     }
+    init_null_column(c);
     if (c->opts.autotune && (rc = tune_operators(c))) return rc;
     {   // pinned configurations
         OpHost *ops[2] = {&c->opS, &c->opN};
@@ -2099,6 +2209,7 @@ int bddc_reset_recycle(bddc_ctx *c) {
     c->pend = Pending();
     launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
     if (c->d_state) launch_set_state(c->d_state, 0, 1, c->stream);
+    init_null_column(c);
     HIPCHK(hipStreamSynchronize(c->stream));
     return 0;
 }

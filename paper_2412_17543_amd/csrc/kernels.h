@@ -286,6 +286,7 @@ struct GradArgs {
 
 // setup (kernels.hip)
 void launch_assemble(const AsmDesc *d, int n, hipStream_t s);
+void launch_rank1(double *A, int64_t ld, int n, const double *e, double coef, hipStream_t s);
 // batched symmetric sweeps in panels of 16 pivots (sweep.hip): the panel
 // buffer holds 2 x 16 x n doubles per matrix at the offsets the sizing call
 // returns; pivots below pos_end must be positive, the others negative

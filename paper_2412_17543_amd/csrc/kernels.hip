@@ -544,11 +544,22 @@ __global__ void __launch_bounds__(256) k_commit(CommitArgs a) {
     }
 }
 
+// A <- A + coef e e^T (n x n, leading dimension ld)
+__global__ void __launch_bounds__(256) k_rank1(double *A, int64_t ld, int n, const double *e, double coef) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * n) return;
+    const int i = (int)(t / n), j = (int)(t % n);
+    A[i * ld + j] += coef * e[i] * e[j];
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+void launch_rank1(double *A, int64_t ld, int n, const double *e, double coef, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_rank1, dim3(nblk((int64_t)n * n, 256)), dim3(256), 0, s, A, ld, n, e, coef);
+}
 void launch_assemble(const AsmDesc *d, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_assemble, dim3(n), dim3(256), 0, s, d);
 }
