@@ -218,6 +218,58 @@ def run_roofline_only(args, s, spec):
                       "tuning": g.tuning()}), flush=True)
 
 
+def run_study(args):
+    """The paper's parameter studies on synthetic sequences, one JSON line:
+    stopping rule x initial guess without recycling (Tab. no_recycling),
+    the recycling strategies B1-B4 at R = 20 (Tab. recycling_cases), the
+    basis size R for B4 (Tab. recycling_base), and the adaptive threshold tau
+    with card/diag weights (Tab. recycling_case2).  Each row: iterations as
+    min-max(avg), seconds per right-hand side and per iteration (float64,
+    queued launches), setup seconds; the coarse space for the tau study."""
+    import numpy as np
+    import torch
+
+    import workload
+    from paper_2412_17543_amd.solver import Solver
+    name = args.workload if args.workload != "c192" else ("c3" if args.study == "tau" else "c64")
+    s = workload.workload(name)
+    F = torch.tensor(make_rhs(s, args.n_rhs or s["n_rhs"]), device="cuda")
+    n_rhs = F.shape[0]
+    if args.study == "stopping":
+        cases = [dict(stop_rule=r, init_guess=gs, R=0) for r in ("r0", "rhs") for gs in ("zero", "prev")]
+    elif args.study == "strategies":
+        cases = [dict(R=0)] + [dict(R=20, strategy=b) for b in ("B1", "B2", "B3", "B4")]
+    elif args.study == "rsweep":
+        cases = [dict(R=r, strategy="B4") for r in (0, 5, 10, 20, 40, 60)]
+    else:
+        cases = [dict(R=20, adapt_tau=t, weights=w) for w in ("card", "diag") for t in (0.0, 10.0, 5.0, 3.0, 2.0)]
+    rows = []
+    for kw in cases:
+        t0 = time.perf_counter()
+        g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"],
+                   elem_keep=s["elem_keep"], **kw)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        g.solve_sequence(F, args.rtol)                   # warm-up
+        g.reset_recycle()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U, its, rr = g.solve_sequence(F, args.rtol)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        info = g.info()
+        row = dict(kw, iters=its_fmt(its.tolist()), iters_first=int(its[0]), s_per_rhs=round(el / n_rhs, 5),
+                   s_per_iteration=round(el / max(1, int(its.sum())), 6), setup_s=round(setup, 2),
+                   max_true_relres=float(rr.max()), frozen=bool(info["frozen"]), n_coarse=info["n_coarse"])
+        if kw.get("adapt_tau", 0) > 0:
+            row["adaptive"] = g.adaptive_stats()
+        rows.append(row)
+        print("[study] %s" % row, file=sys.stderr, flush=True)
+        g.close()
+    print(json.dumps({"study": args.study, "workload": WORKLOADS[name]["desc"], "n_rhs": n_rhs, "rtol": args.rtol,
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,12 +288,16 @@ def main():
                     help="fixed product configuration: 8 comma-separated integers (Schur then Neumann: blocks per "
                          "CU, per-subdomain split, waves, tiles in flight); a 0 first entry keeps that product tuned")
     ap.add_argument("--roofline-only", action="store_true")
+    ap.add_argument("--study", default=None, choices=("stopping", "strategies", "rsweep", "tau"),
+                    help="a parameter study instead of the benchmark line (64^3 sequence; tau: holed cube)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures the single-GPU path only (one process, one MI355X); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.study:
+        return run_study(args)
     import workload
     spec = WORKLOADS[args.workload]
     s = workload.workload(args.workload)
