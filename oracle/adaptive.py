@@ -23,7 +23,9 @@ Every eigenvector with lambda > tau, largest first and at most
 antisymmetric on shared nodes, c_t = -c_s) are orthonormalised against the
 face's existing rows (Gram-Schmidt, twice) and become one new coarse DOF of
 both s and t; a row whose norm after the projection is below 1e-8 of the
-norm of the face part is dropped.  Only level-1 faces are enriched.
+norm of the face part is dropped.  The same functions serve level 2 (the
+coarse problem's faces between subregions; bddc.Level2), with subregions as
+the subdomains and coarse DOFs as the nodes.
 
 Section 3.3 leaves Pi, E_st and the restriction of c to its reference; the
 reading above is the one the GPU library implements as well.
@@ -110,7 +112,7 @@ def constraint_covector(ss, D, dofs, s, t, S_dense, w):
 
 
 def adaptive_dofs(ss, D, dofs, tau, max_per_face=10, S_dense=None):
-    """New coarse DOFs for every level-1 face (the list `dofs` is not changed).
+    """New coarse DOFs for every face of `dofs` (the list is not changed).
 
     Returns (new DOFs, per-face records (s, t, eigenvalues descending, rows
     added)).

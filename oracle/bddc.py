@@ -36,6 +36,16 @@ the details to its reference; the reading used here:
     no-strict-superset test, neighbours being coarse DOFs sharing a subdomain;
   * level-2 weights are 'card' (1/|S2|); the level-3 problem is solved exactly
     (dense Cholesky);
+  * adaptivity at level 2 (optional; Section 3.3 applied to the coarse
+    problem, as adaptive multilevel BDDC does on every level): every level-2
+    face (a glob shared by two subregions) gets the pencil of eq. eig-matrix
+    with subregions in the role of subdomains, A_st built from the subregion
+    Schur complements S2_j = K2_j / K2_j(interior) on the level-2 interface,
+    the level-2 'card' weights in E_st and the shared level-3 DOFs in Pi; the
+    rows of eq. c-def (same selection, restriction to the face and
+    orthonormalisation as at level 1) become level-3 DOFs of kind
+    "adaptive2", appended after the initial ones, each shared by the two
+    subregions with the row's entries as weights;
   * one application: interior pre-solve, interface residual, level-2 BDDC on
     the interface, interior post-correction (harmonic extension).
 
@@ -231,10 +241,19 @@ class _LocalSaddle:
 # level 2 (coarse problem preconditioned by BDDC over subregions)
 # ---------------------------------------------------------------------------
 
+def level2_schur(K, B, I):
+    """K(B, B) - K(B, I) K(I, I)^{-1} K(I, B), dense."""
+    S = K[np.ix_(B, B)]
+    if I.size:
+        S = S - K[np.ix_(B, I)] @ np.linalg.solve(K[np.ix_(I, I)], K[np.ix_(I, B)])
+    return S
+
+
 class Level2:
     """M_2^{-1} approximating K_C^{-1}: BDDC with subdomains as elements."""
 
-    def __init__(self, n_coarse, S1, is_corner, KC_loc, cidx, sub_to_subregion, is_adaptive=None, singular=False):
+    def __init__(self, n_coarse, S1, is_corner, KC_loc, cidx, sub_to_subregion, is_adaptive=None, singular=False,
+                 adaptive2=None):
         self.nC = n_coarse
         s2r = np.asarray(sub_to_subregion)
         self.n_sr = int(s2r.max()) + 1
@@ -306,6 +325,10 @@ class Level2:
                 continue
             mem = np.array(sorted(mem))
             dofs3.append(dict(kind="face", dofs=mem, wts=np.full(mem.size, 1.0 / mem.size), subs=S2[mem[0]]))
+        self.adapt2_info = []
+        if adaptive2 is not None:
+            new, self.adapt2_info = self._adaptive_level2(dofs3, mult2, *adaptive2)
+            dofs3 = dofs3 + new
         self.dofs3 = dofs3
         self.n3 = len(dofs3)
         # per-subregion split, constraints, local saddle problems
@@ -338,6 +361,27 @@ class Level2:
             self.K3_pinv = np.linalg.pinv(K3, rcond=1e-10, hermitian=True) if self.n3 else None
         else:
             self.K3_cho = sla.cho_factor(K3) if self.n3 else None
+
+    def _adaptive_level2(self, dofs3, mult2, tau, per_face):
+        """Level-3 DOFs from the level-2 face pencils (eqs. eig-matrix, c-def
+        with subregions as the subdomains)."""
+        from types import SimpleNamespace
+
+        from .adaptive import adaptive_dofs
+        subs, D2, S2 = [], [], []
+        for j in range(self.n_sr):
+            Lj, Kj = self.L[j], self.K2[j]
+            isB = mult2[Lj] >= 2
+            B, I = np.flatnonzero(isB), np.flatnonzero(~isB)
+            S = level2_schur(Kj, B, I)
+            subs.append({"nodes_B": Lj[B]})                  # ascending coarse DOF ids
+            D2.append(1.0 / mult2[Lj[B]])
+            S2.append(0.5 * (S + S.T))
+        view = SimpleNamespace(sub=subs)
+        dv = [dict(kind=d["kind"], nodes=d["dofs"], wts=d["wts"], subs=d["subs"]) for d in dofs3]
+        new, info = adaptive_dofs(view, D2, dv, tau, per_face, S_dense=S2)
+        self.S2_dense, self.D2 = S2, D2
+        return [dict(kind="adaptive2", dofs=d["nodes"], wts=d["wts"], subs=d["subs"]) for d in new], info
 
     def _kii(self, d, v):
         return sla.cho_solve(d["KII_cho"], v) if d["KII_cho"] is not None else np.zeros(0)
@@ -382,7 +426,7 @@ class BDDC:
     """M^{-1} of Section 3.2 on the interface problem of a ``Substructuring``."""
 
     def __init__(self, ss, weight_kind="diag", constraints=("corners", "faces"),
-                 sub_to_subregion=None, all_corners=False, adaptive=None):
+                 sub_to_subregion=None, all_corners=False, adaptive=None, adaptive2=None):
         self.ss = ss
         self.dofs = coarse_dofs(ss, constraints, all_corners)
         self.D = weights(ss, weight_kind)
@@ -416,7 +460,7 @@ class BDDC:
         self.singular = not bool((ss.used & ss.dir).any())
         if self.three_level:
             self.level2 = Level2(self.nC, S1, is_corner, KC_loc, self.cidx, sub_to_subregion, is_adaptive,
-                                 self.singular)
+                                 self.singular, adaptive2)
         else:
             KC = np.zeros((self.nC, self.nC))
             for i, s in enumerate(self.loc):

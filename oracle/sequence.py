@@ -19,9 +19,9 @@ class OracleSolver:
     def __init__(self, nx, elem_to_sub, coef, elem_keep=None, sub_to_subregion=None,
                  weight_kind="diag", constraints=("corners", "faces"), R=0, strategy="B4",
                  freeze_tol=1e-5, stop="rhs", init_guess="prev", all_corners=False, reorth=False,
-                 adaptive=None, restart_every=0, dirichlet=None):
+                 adaptive=None, restart_every=0, dirichlet=None, adaptive2=None):
         self.ss = Substructuring(nx, elem_to_sub, coef, elem_keep, dirichlet)
-        self.M = BDDC(self.ss, weight_kind, constraints, sub_to_subregion, all_corners, adaptive)
+        self.M = BDDC(self.ss, weight_kind, constraints, sub_to_subregion, all_corners, adaptive, adaptive2)
         self.rec = Recycler(R, strategy, freeze_tol)
         self.stop = stop
         self.init_guess = init_guess

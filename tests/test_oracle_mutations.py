@@ -118,3 +118,26 @@ def test_freeze_criterion_mistakes_are_caught(monkeypatch, mistake):
     monkeypatch.setattr(recycle, "ritz_change", bad)
     with pytest.raises(AssertionError):
         _freeze_pins(tr)
+
+
+def test_level2_schur_without_interior_elimination_is_caught(monkeypatch):
+    from tests import test_oracle_adaptive2 as t2
+    monkeypatch.setattr(bddc, "level2_schur", lambda K, B, I: K[np.ix_(B, B)])
+    with pytest.raises(AssertionError):
+        t2.test_face_eigenvalue_is_the_coarse_condition_number()
+
+
+def test_level2_rows_restricted_to_the_wrong_side_are_caught(monkeypatch):
+    # c restricted to the t-copies (c_t = -c_s) flips each row's sign only,
+    # which the span ignores; restricting to a shifted set of positions does not
+    from tests import test_oracle_adaptive2 as t2
+    orig = adaptive.adaptive_dofs
+
+    def bad(*a, **k):
+        new, info = orig(*a, **k)
+        for d in new:
+            d["wts"] = np.roll(d["wts"], 1)
+        return new, info
+    monkeypatch.setattr(adaptive, "adaptive_dofs", bad)
+    with pytest.raises(AssertionError):
+        t2.test_face_eigenvalue_is_the_coarse_condition_number()
