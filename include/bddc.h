@@ -135,13 +135,20 @@ typedef struct {
                                 the recursive one and the iteration restarts from
                                 line 5 (as after a residual replacement; not in the
                                 paper).  0 (default): off                         */
+    double  adapt2_tau;      /* three levels: > 0 enriches every level-2 face (coarse
+                                DOFs shared by two subregions) in the same way, with
+                                subregions as the subdomains, the subregion Schur
+                                complements as A_s and the level-3 DOFs they share in
+                                Pi (Section 3.3 applied to the coarse problem); the
+                                rows become level-3 DOFs; <= 0: off (default)    */
+    int32_t adapt2_max_per_face; /* at most this many rows per level-2 face (10)  */
 } bddc_opts;
 
 /* Fills *o with the defaults: corners+faces, diag weights, float64 local
  * operators (and no other precision), R = 0, B4, freeze 1e-5, ||r||/||b||,
  * previous-solution guess, max_it 1000, save_cap 256, iterations queued
  * kernel by kernel ahead of the convergence poll (use_graph 2), autotuned
- * products, automatic coarse form, no adaptive faces. */
+ * products, automatic coarse form, no adaptive faces at either level. */
 void bddc_default_opts(bddc_opts *o);
 
 /*
@@ -253,6 +260,8 @@ int bddc_info(const bddc_ctx *ctx, int64_t *info);
  * seconds spent.  All zero when adapt_tau <= 0.
  */
 int bddc_adaptive_stats(const bddc_ctx *ctx, double *out);
+/* The same four figures for the level-2 faces (opts->adapt2_tau). */
+int bddc_adaptive2_stats(const bddc_ctx *ctx, double *out);
 
 /*
  * bddc_face_constraints -- one face problem of the adaptive selection in the

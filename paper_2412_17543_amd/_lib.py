@@ -33,7 +33,8 @@ class Opts(ctypes.Structure):
                 ("save_cap", c_int32), ("use_graph", c_int32), ("autotune", c_int32),
                 ("coarse_form", c_int32), ("product_cfg", c_int32 * 8),
                 ("reorth", c_int32), ("adapt_max_per_face", c_int32), ("adapt_tau", c_double),
-                ("local_prec_set", c_int32), ("coef_log", c_int32), ("restart_every", c_int32)]
+                ("local_prec_set", c_int32), ("coef_log", c_int32), ("restart_every", c_int32),
+                ("adapt2_tau", c_double), ("adapt2_max_per_face", c_int32)]
 
 
 class BddcError(RuntimeError):
@@ -61,6 +62,7 @@ SIGNATURES = {
     "bddc_tuning": (c_int32, [c_void_p, POINTER(c_double)]),
     "bddc_time_products": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "bddc_adaptive_stats": (c_int32, [c_void_p, POINTER(c_double)]),
+    "bddc_adaptive2_stats": (c_int32, [c_void_p, POINTER(c_double)]),
     "bddc_set_local_prec": (c_int32, [c_void_p, c_int32]),
     "bddc_set_launch": (c_int32, [c_void_p, c_int32, c_void_p]),
     "bddc_time_kernels": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_int32]),

@@ -207,3 +207,128 @@ int adaptive_faces(const Structure &st, const double *d_K, const std::vector<int
 }
 
 }  // namespace bddc
+
+namespace bddc {
+
+// Adaptivity at level 2 (Section 3.3 on the coarse problem of the multilevel
+// method): subregions in the role of subdomains, level-1 coarse DOFs in the
+// role of nodes, the subregion Schur complements S2_j (K2_j with its interior
+// coarse DOFs eliminated) in the role of S_i, the level-2 card weights as D,
+// and the level-3 DOFs that two subregions share as the constraints of Pi.
+// Every level-2 face gets the jump-space pencil above; its rows (over the
+// face's coarse DOFs) become level-3 DOFs of the two subregions.
+int adaptive_level2(const Structure &st, const std::vector<std::vector<double>> &S2,
+                    const std::vector<char> &floating, double tau, int max_per_face, std::vector<Level3Dof> &extra,
+                    AdaptStats &stats, std::string &err) {
+    const auto t0 = std::chrono::steady_clock::now();
+    extra.clear();
+    stats = AdaptStats{};
+    std::vector<int32_t> faces;
+    for (int m3 = 0; m3 < st.n3; ++m3)
+        if (st.dof3_kind[m3] == 1 && st.dof3_subs[m3].size() == 2) faces.push_back(m3);
+    stats.faces = (int)faces.size();
+    std::vector<FaceOutput> res(faces.size());
+    std::vector<int> rcs(faces.size(), 0);
+    std::atomic<size_t> next{0};
+    // H = S(G,G) - S(G,O) S(O,O)^{-1} S(O,G) of one side, O = the rest of its interface
+    auto side = [&](int j, const std::vector<int32_t> &pg, std::vector<double> &H, std::vector<double> &K) -> bool {
+        const SubregionHost &r = st.sr[j];
+        const int n = r.nB, m = (int)pg.size();
+        const double *S = S2[j].data();
+        std::vector<char> inG(n, 0);
+        for (int32_t k : pg) inG[k] = 1;
+        std::vector<int32_t> po;
+        for (int k = 0; k < n; ++k)
+            if (!inG[k]) po.push_back(k);
+        const int no = (int)po.size();
+        K.assign((size_t)m * m, 0.0);
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) K[(size_t)a * m + b] = S[(size_t)pg[a] * n + pg[b]];
+        H = K;
+        if (no == 0) return true;
+        std::vector<double> Loo((size_t)no * no);
+        for (int a = 0; a < no; ++a)
+            for (int b = 0; b < no; ++b) Loo[(size_t)a * no + b] = S[(size_t)po[a] * n + po[b]];
+        if (!cholesky(Loo, no)) return false;
+        std::vector<double> X((size_t)no * m), col(no);
+        for (int b = 0; b < m; ++b) {
+            for (int a = 0; a < no; ++a) col[a] = S[(size_t)po[a] * n + pg[b]];
+            chol_solve(Loo, no, col.data());
+            for (int a = 0; a < no; ++a) X[(size_t)a * m + b] = col[a];
+        }
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) {
+                double t = 0.0;
+                for (int q = 0; q < no; ++q) t += S[(size_t)pg[a] * n + po[q]] * X[(size_t)q * m + b];
+                H[(size_t)a * m + b] -= t;
+            }
+        for (int a = 0; a < m; ++a)
+            for (int b = a + 1; b < m; ++b) {
+                const double v = 0.5 * (H[(size_t)a * m + b] + H[(size_t)b * m + a]);
+                H[(size_t)a * m + b] = H[(size_t)b * m + a] = v;
+            }
+        return true;
+    };
+    auto worker = [&]() {
+        for (size_t fi = next++; fi < faces.size(); fi = next++) {
+            const int m3 = faces[fi];
+            const int j = st.dof3_subs[m3][0], k = st.dof3_subs[m3][1];
+            const SubregionHost &a = st.sr[j], &b = st.sr[k];
+            std::vector<int32_t> ps, pt, G;          // shared coarse ids, ascending
+            for (int p = 0, q = 0; p < a.nB && q < b.nB;) {
+                const int32_t ca = a.L[a.nI + p], cb = b.L[b.nI + q];
+                if (ca == cb) { ps.push_back(p++); pt.push_back(q++); G.push_back(ca); }
+                else if (ca < cb) ++p;
+                else ++q;
+            }
+            const int m = (int)G.size();
+            auto pos = [&](int32_t cid) {
+                auto it = std::lower_bound(G.begin(), G.end(), cid);
+                return (it == G.end() || *it != cid) ? -1 : (int)(it - G.begin());
+            };
+            std::vector<int32_t> fpos;
+            for (int32_t cid : st.dof3_members[m3]) fpos.push_back(pos(cid));
+            std::vector<double> Ds(m), Dt(m), B, Hs, Ht, Ks, Kt;
+            for (int q = 0; q < m; ++q) { Ds[q] = a.w[ps[q]]; Dt[q] = b.w[pt[q]]; }
+            int nb = 0;
+            for (int32_t d3 : a.c3) {
+                if (!std::binary_search(b.c3.begin(), b.c3.end(), d3)) continue;
+                std::vector<double> rw(m, 0.0);
+                const auto &mem = st.dof3_members[d3];
+                for (size_t q = 0; q < mem.size(); ++q) {
+                    const int p = pos(mem[q]);
+                    if (p < 0) { rcs[fi] = BDDC_EINVAL; break; }
+                    rw[p] = st.dof3_wts[d3][q];
+                }
+                if (rcs[fi]) break;
+                B.insert(B.end(), rw.begin(), rw.end());
+                ++nb;
+            }
+            if (rcs[fi] || std::count(fpos.begin(), fpos.end(), -1)) { rcs[fi] = BDDC_EINVAL; continue; }
+            if (!side(j, ps, Hs, Ks) || !side(k, pt, Ht, Kt)) { rcs[fi] = BDDC_ESINGULAR; continue; }
+            FaceInput in{m, Hs.data(), Ht.data(), Ks.data(), Kt.data(), Ds.data(), Dt.data(), floating[j] != 0,
+                         floating[k] != 0, nb, B.data(), (int)fpos.size(), fpos.data()};
+            rcs[fi] = face_rows(in, tau, max_per_face, res[fi]);
+        }
+    };
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned q = 1; q < nth; ++q) pool.emplace_back(worker);
+    worker();
+    for (auto &th : pool) th.join();
+    for (size_t fi = 0; fi < faces.size(); ++fi) {
+        if (rcs[fi]) {
+            err = rcs[fi] == BDDC_EINVAL ? "level-2 face constraint outside the shared coarse DOFs"
+                                         : "singular level-2 face problem";
+            return rcs[fi];
+        }
+        if (!res[fi].lam.empty()) stats.lam_max = std::max(stats.lam_max, res[fi].lam[0]);
+        const int m3 = faces[fi];
+        for (const auto &row : res[fi].rows) extra.push_back(Level3Dof{st.dof3_members[m3], row, st.dof3_subs[m3]});
+    }
+    stats.added = (int)extra.size();
+    stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return BDDC_OK;
+}
+
+}  // namespace bddc

@@ -38,4 +38,12 @@ int adaptive_faces(const Structure &st, const double *d_K, const std::vector<int
                    int max_per_face, int32_t *d_status, hipStream_t s, std::vector<CoarseDof> &extra,
                    AdaptStats &stats, std::string &err);
 
+// Every level-2 face (three levels): S2 holds each subregion's Schur
+// complement on its level-2 interface (row-major nB x nB, the order of
+// SubregionHost::L after the interior ids); floating marks subregions whose
+// subdomains all lack Dirichlet nodes.  New rows are returned as level-3 DOFs.
+int adaptive_level2(const Structure &st, const std::vector<std::vector<double>> &S2,
+                    const std::vector<char> &floating, double tau, int max_per_face, std::vector<Level3Dof> &extra,
+                    AdaptStats &stats, std::string &err);
+
 }  // namespace bddc

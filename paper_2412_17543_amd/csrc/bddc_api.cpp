@@ -162,6 +162,7 @@ struct bddc_ctx {
     SyncBuf *d_sync = nullptr;      // device image of SyncBuf (holds d_ctl, d_state, d_WAWsym)
     bool pre_schur = false;         // A x of the next solve's initial residual already enqueued
     AdaptStats adapt;               // adaptive face selection at setup
+    AdaptStats adapt2;              // the same at level 2
     double *d_hblk = nullptr;       // device image of h_hist (holds the four histories)
     double *h_Y = nullptr;          // pinned staging of the recycling coefficients
     int hcopy = 0;
@@ -1194,6 +1195,8 @@ void bddc_default_opts(bddc_opts *o) {
     o->local_prec_set = 0;
     o->coef_log = 0;
     o->restart_every = 0;
+    o->adapt2_tau = 0.0;
+    o->adapt2_max_per_face = 10;
 }
 
 const char *bddc_last_error(void) { return g_err.c_str(); }
@@ -1222,6 +1225,80 @@ void init_null_column(bddc_ctx *c) {
 // vector of the coarse matrix of a pure Neumann problem): 1 for corners and
 // averages, the sum of the weights for weighted rows (0 for the adaptive
 // rows, which are orthogonal to the face average).
+// Gather lists of the subregion matrices K2_j = sum over the member
+// subdomains i of K_Ci (dense nL_j x nL_j at K2_off[j], ids in SubregionHost::L
+// order): entry -> positions in the packed K_Ci.
+void k2_csr(const Structure &st, const std::vector<int32_t> &nc, const std::vector<int64_t> &kc_off,
+            const std::vector<int64_t> &K2_off, std::vector<int32_t> &ptr, std::vector<int32_t> &idx) {
+    std::vector<std::pair<int64_t, int32_t>> pr;
+    std::vector<int32_t> pos(st.coarse.size(), -1);
+    for (int j = 0; j < st.n_sr; ++j) {
+        const auto &L = st.sr[j].L;
+        const int64_t nL = (int64_t)L.size();
+        for (size_t a = 0; a < L.size(); ++a) pos[L[a]] = (int32_t)a;
+        for (int32_t i : st.sr[j].subs)
+            for (int qa = 0; qa < nc[i]; ++qa)
+                for (int qb = 0; qb < nc[i]; ++qb)
+                    pr.push_back({K2_off[j] + (int64_t)pos[st.sub[i].cidx[qa]] * nL + pos[st.sub[i].cidx[qb]],
+                                  (int32_t)(kc_off[i] + qa * nc[i] + qb)});
+        for (size_t a = 0; a < L.size(); ++a) pos[L[a]] = -1;
+    }
+    build_csr(K2_off[st.n_sr], pr, ptr, idx);
+}
+
+// Adaptivity at level 2: the subregion Schur complements on the device
+// (assemble K2_j, sweep its interior coarse DOFs), the face pencils on the
+// host, the new rows appended to the level-3 DOFs.
+int adapt_level2(bddc_ctx *c, const std::vector<int32_t> &nc, const std::vector<int64_t> &kc_off) {
+    Structure &st = c->st;
+    const int nsr = st.n_sr;
+    hipStream_t s = c->stream;
+    std::vector<int64_t> K2_off(nsr + 1, 0);
+    for (int j = 0; j < nsr; ++j) K2_off[j + 1] = K2_off[j] + (int64_t)st.sr[j].L.size() * st.sr[j].L.size();
+    std::vector<int32_t> ptr, idx;
+    k2_csr(st, nc, kc_off, K2_off, ptr, idx);
+    int32_t *dp = nullptr, *di = nullptr;
+    double *dK = nullptr;
+    int rc;
+    if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) ||
+        (rc = dalloc(c, &dK, (size_t)std::max<int64_t>(1, K2_off[nsr]))))
+        return rc;
+    launch_gather_sum(K2_off[nsr], dp, di, c->d_KC, dK, s);
+    std::vector<SweepDesc> sw(nsr);
+    for (int j = 0; j < nsr; ++j) {
+        const int n = (int)st.sr[j].L.size();
+        sw[j] = SweepDesc{dK + K2_off[j], n, n, 0, st.sr[j].nI, n};
+    }
+    if ((rc = run_sweeps(c, sw))) return rc;
+    std::vector<double> h((size_t)K2_off[nsr]);
+    HIPCHK(hipMemcpyAsync(h.data(), dK, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    dfree(c, dp); dfree(c, di); dfree(c, dK);
+    int32_t st_h = 0;
+    HIPCHK(hipMemcpy(&st_h, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (st_h) return fail(BDDC_ESINGULAR, "non-positive pivot in a subregion interior elimination");
+    std::vector<std::vector<double>> S2(nsr);
+    std::vector<char> floating(nsr, 1);
+    for (int j = 0; j < nsr; ++j) {
+        const SubregionHost &r = st.sr[j];
+        const int n = (int)r.L.size();
+        S2[j].resize((size_t)r.nB * r.nB);
+        for (int a = 0; a < r.nB; ++a)
+            for (int b = 0; b < r.nB; ++b)
+                S2[j][(size_t)a * r.nB + b] = h[K2_off[j] + (int64_t)(r.nI + a) * n + r.nI + b];
+        for (int32_t i : r.subs)
+            for (int32_t l : st.sub[i].elem_loc)
+                if (l < 0) floating[j] = 0;
+    }
+    std::vector<Level3Dof> extra;
+    std::string err;
+    if ((rc = adaptive_level2(st, S2, floating, c->opts.adapt2_tau, std::max(0, c->opts.adapt2_max_per_face), extra,
+                              c->adapt2, err)) ||
+        (rc = add_level3_dofs(st, extra, err)))
+        return fail(rc, err);
+    return 0;
+}
+
 std::vector<double> coarse_null_vector(const Structure &st) {
     std::vector<double> e(st.coarse.size(), 1.0);
     for (size_t q = 0; q < st.coarse.size(); ++q) {
@@ -1784,6 +1861,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         dfree(c, c->d_KCinv);
         c->d_KCinv = nullptr;
     } else {
+        if (c->opts.adapt2_tau > 0 && (rc = adapt_level2(c, nc, kc_off))) return rc;
         const int nsr = st.n_sr;
         c->nsr = nsr;
         c->n3 = st.n3;
@@ -1860,20 +1938,8 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         }
         // K2_j = sum over member subdomains of K_Ci (subdomains as elements)
         {
-            std::vector<std::pair<int64_t, int32_t>> pr;
-            std::vector<int32_t> pos(c->nC, -1);
-            for (int j = 0; j < nsr; ++j) {
-                const auto &L = st.sr[j].L;
-                for (size_t a = 0; a < L.size(); ++a) pos[L[a]] = (int32_t)a;
-                for (int32_t i : st.sr[j].subs)
-                    for (int qa = 0; qa < nc[i]; ++qa)
-                        for (int qb = 0; qb < nc[i]; ++qb)
-                            pr.push_back({K2_off[j] + (int64_t)pos[st.sub[i].cidx[qa]] * nL[j] + pos[st.sub[i].cidx[qb]],
-                                          (int32_t)(kc_off[i] + qa * nc[i] + qb)});
-                for (size_t a = 0; a < L.size(); ++a) pos[L[a]] = -1;
-            }
             std::vector<int32_t> ptr, idx;
-            build_csr(K2_off[nsr], pr, ptr, idx);
+            k2_csr(st, nc, kc_off, K2_off, ptr, idx);
             int32_t *dp, *di;
             if ((rc = dupload(c, &dp, ptr)) || (rc = dupload(c, &di, idx)) || (rc = dalloc(c, &c->d_K2, (size_t)K2_off[nsr])))
                 return rc;
@@ -1949,13 +2015,12 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
                 return rc;
             launch_gather_sum((int64_t)n * ld, dp, di, d_K3loc, c->d_K3inv, s);
             if (n > 0 && c->nullc) {
-                // the level-3 values of the constant: means of its level-1 values
+                // the level-3 values of the constant: its level-1 values under the level-3 rows
                 const std::vector<double> e1 = coarse_null_vector(st);
                 std::vector<double> e3(n, 0.0);
-                for (int m3 = 0; m3 < n; ++m3) {
-                    for (int32_t q : st.dof3_members[m3]) e3[m3] += e1[q];
-                    e3[m3] /= (double)st.dof3_members[m3].size();
-                }
+                for (int m3 = 0; m3 < n; ++m3)
+                    for (size_t q = 0; q < st.dof3_members[m3].size(); ++q)
+                        e3[m3] += st.dof3_wts[m3][q] * e1[st.dof3_members[m3][q]];
                 if ((rc = sweep_semidefinite(c, c->d_K3inv, n, ld, e3))) return rc;
             } else if (n > 0 && (rc = run_sweeps(c, {SweepDesc{c->d_K3inv, n, ld, 0, n, n}}))) {
                 return rc;
@@ -2321,6 +2386,15 @@ int bddc_adaptive_stats(const bddc_ctx *c, double *out) {
     out[1] = c->adapt.added;
     out[2] = c->adapt.lam_max;
     out[3] = c->adapt.seconds;
+    return 0;
+}
+
+int bddc_adaptive2_stats(const bddc_ctx *c, double *out) {
+    if (!c || !out) return fail(BDDC_EINVAL, "null argument");
+    out[0] = c->adapt2.faces;
+    out[1] = c->adapt2.added;
+    out[2] = c->adapt2.lam_max;
+    out[3] = c->adapt2.seconds;
     return 0;
 }
 

@@ -70,7 +70,16 @@ struct Structure {
     std::vector<int32_t> gamma2;       // level-1 coarse ids on the level-2 interface
     std::vector<std::vector<int32_t>> dof3_members;  // level-3 DOF -> level-1 coarse ids
     std::vector<std::vector<int32_t>> dof3_subs;     // level-3 DOF -> subregions
-    int n3 = 0, n3_corner = 0, n3_face = 0;
+    std::vector<std::vector<double>> dof3_wts;       // its weights on those coarse ids
+    std::vector<int8_t> dof3_kind;                   // 0 corner, 1 face, 3 level-1 adaptive row, 4 level-2 adaptive row
+    int n3 = 0, n3_corner = 0, n3_face = 0, n3_adaptive = 0;
+};
+
+// A level-3 DOF added by the adaptive selection at level 2.
+struct Level3Dof {
+    std::vector<int32_t> members;   // level-1 coarse ids (a level-2 face)
+    std::vector<double> wts;
+    std::vector<int32_t> subs;      // the two subregions
 };
 
 int build_structure(const bddc_mesh *m, const bddc_partition *p, const double *coef,
@@ -78,6 +87,7 @@ int build_structure(const bddc_mesh *m, const bddc_partition *p, const double *c
 int constraint_rows(Structure &st, std::string &err);
 int build_level2(Structure &st, const bddc_partition *p, std::string &err);
 int add_coarse_dofs(Structure &st, const bddc_partition *p, const std::vector<CoarseDof> &extra, std::string &err);
+int add_level3_dofs(Structure &st, const std::vector<Level3Dof> &extra, std::string &err);
 
 // static device scratch of the allocation-free entry point (noalloc.hip)
 int64_t noalloc_scratch_doubles();

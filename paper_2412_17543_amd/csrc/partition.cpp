@@ -299,6 +299,37 @@ int constraint_rows(Structure &st, std::string &err) {
 
 // Level-2 structure (three levels): subregion DOF lists, level-2 interface,
 // globs, corners and face averages (the level-3 unknowns), constraint rows.
+// Per subregion: its level-3 DOFs (ascending) and their rows over its
+// level-2 interface positions (CSR).
+static int level3_rows(Structure &st, std::string &err) {
+    st.n3 = (int)st.dof3_members.size();
+    std::vector<int32_t> posL(st.coarse.size(), -1);
+    for (SubregionHost &r : st.sr) {
+        r.c3.clear();
+        r.c_ptr.clear();
+        r.c_col.clear();
+        r.c_val.clear();
+    }
+    for (int m3 = 0; m3 < st.n3; ++m3)
+        for (int32_t j : st.dof3_subs[m3]) st.sr[j].c3.push_back(m3);
+    for (SubregionHost &r : st.sr) {
+        for (int k = 0; k < r.nB; ++k) posL[r.L[r.nI + k]] = k;
+        r.c_ptr.assign(1, 0);
+        for (int32_t m3 : r.c3) {
+            const auto &mem = st.dof3_members[m3];
+            const auto &w = st.dof3_wts[m3];
+            for (size_t q = 0; q < mem.size(); ++q) {
+                if (posL[mem[q]] < 0) { err = "level-2 constraint outside its subregion interface"; return BDDC_EINVAL; }
+                r.c_col.push_back(posL[mem[q]]);
+                r.c_val.push_back(w[q]);
+            }
+            r.c_ptr.push_back((int32_t)r.c_col.size());
+        }
+        for (int k = 0; k < r.nB; ++k) posL[r.L[r.nI + k]] = -1;
+    }
+    return BDDC_OK;
+}
+
 int build_level2(Structure &st, const bddc_partition *p, std::string &err) {
     const int nC = (int)st.coarse.size();
     const int nsub = st.n_sub;
@@ -306,7 +337,9 @@ int build_level2(Structure &st, const bddc_partition *p, std::string &err) {
     st.gamma2.clear();
     st.dof3_members.clear();
     st.dof3_subs.clear();
-    st.n3 = st.n3_corner = st.n3_face = 0;
+    st.dof3_wts.clear();
+    st.dof3_kind.clear();
+    st.n3 = st.n3_corner = st.n3_face = st.n3_adaptive = 0;
     st.three = p->n_subregion > 0;
     if (!st.three) return BDDC_OK;
     const int nsr = p->n_subregion;
@@ -375,6 +408,8 @@ int build_level2(Structure &st, const bddc_partition *p, std::string &err) {
         if ((gm[root].size() == 1 || in_glob <= 1) && !superset) {
             st.dof3_members.push_back({c});
             st.dof3_subs.push_back(S2[c]);
+            st.dof3_wts.push_back({1.0});
+            st.dof3_kind.push_back(0);
             st.n3_corner++;
         }
     }
@@ -382,34 +417,32 @@ int build_level2(Structure &st, const bddc_partition *p, std::string &err) {
         if (st.coarse[c].kind != 3) continue;
         st.dof3_members.push_back({c});
         st.dof3_subs.push_back(S2[c]);
+        st.dof3_wts.push_back({1.0});
+        st.dof3_kind.push_back(3);
     }
     for (auto &kv : gm) {
         if (S2[kv.second[0]].size() != 2) continue;
         st.dof3_members.push_back(kv.second);
         st.dof3_subs.push_back(S2[kv.second[0]]);
+        st.dof3_wts.push_back(std::vector<double>(kv.second.size(), 1.0 / (double)kv.second.size()));
+        st.dof3_kind.push_back(1);
         st.n3_face++;
     }
-    st.n3 = (int)st.dof3_members.size();
-    std::vector<int32_t> posL(nC, -1);
-    for (int m3 = 0; m3 < st.n3; ++m3)
-        for (int32_t j : st.dof3_subs[m3]) st.sr[j].c3.push_back(m3);
-    for (int j = 0; j < nsr; ++j) {
-        SubregionHost &r = st.sr[j];
-        for (int k = 0; k < r.nB; ++k) posL[r.L[r.nI + k]] = k;
-        r.c_ptr.assign(1, 0);
-        for (int32_t m3 : r.c3) {
-            const auto &mem = st.dof3_members[m3];
-            double w = 1.0 / (double)mem.size();
-            for (int32_t c : mem) {
-                if (posL[c] < 0) { err = "level-2 constraint outside its subregion interface"; return BDDC_EINVAL; }
-                r.c_col.push_back(posL[c]);
-                r.c_val.push_back(w);
-            }
-            r.c_ptr.push_back((int32_t)r.c_col.size());
-        }
-        for (int k = 0; k < r.nB; ++k) posL[r.L[r.nI + k]] = -1;
+    return level3_rows(st, err);
+}
+
+// Appends level-3 DOFs (adaptive rows of the level-2 faces) and rebuilds the
+// subregions' constraint rows.
+int add_level3_dofs(Structure &st, const std::vector<Level3Dof> &extra, std::string &err) {
+    if (extra.empty()) return BDDC_OK;
+    for (const Level3Dof &d : extra) {
+        st.dof3_members.push_back(d.members);
+        st.dof3_subs.push_back(d.subs);
+        st.dof3_wts.push_back(d.wts);
+        st.dof3_kind.push_back(4);
+        st.n3_adaptive++;
     }
-    return BDDC_OK;
+    return level3_rows(st, err);
 }
 
 // Appends coarse DOFs (adaptive face rows, Section 3.3) and rebuilds every

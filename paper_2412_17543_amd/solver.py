@@ -39,6 +39,7 @@ class Solver:
                  init_guess="prev", max_it=1000, save_cap=256, freeze_tol=1e-5,
                  use_graph=True, autotune=True, coarse_form="auto", product_cfg=None, reorth=False,
                  adapt_tau=0.0, adapt_max_per_face=10, local_prec_set=(), coef_log=False, restart_every=0,
+                 adapt2_tau=0.0, adapt2_max_per_face=10,
                  device="cuda", stream=None):
         lib = _lib.load()
         self.lib = lib
@@ -94,6 +95,8 @@ class Solver:
         o.local_prec_set = sum({64: 1, 32: 2, 16: 4}[p] for p in local_prec_set)
         o.coef_log = 1 if coef_log else 0
         o.restart_every = int(restart_every)
+        o.adapt2_tau = float(adapt2_tau)
+        o.adapt2_max_per_face = int(adapt2_max_per_face)
         if product_cfg is not None:
             assert len(product_cfg) == 8
             for i, v in enumerate(product_cfg):
@@ -123,6 +126,12 @@ class Solver:
         added, largest face eigenvalue before enrichment, seconds."""
         a = (ctypes.c_double * 4)()
         check(self.lib.bddc_adaptive_stats(self.ctx, a))
+        return dict(faces=int(a[0]), added=int(a[1]), lam_max=float(a[2]), seconds=float(a[3]))
+
+    def adaptive2_stats(self) -> dict:
+        """The same for the level-2 faces (three levels, adapt2_tau > 0)."""
+        a = (ctypes.c_double * 4)()
+        check(self.lib.bddc_adaptive2_stats(self.ctx, a))
         return dict(faces=int(a[0]), added=int(a[1]), lam_max=float(a[2]), seconds=float(a[3]))
 
     def interface_nodes(self) -> np.ndarray:

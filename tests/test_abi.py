@@ -53,6 +53,7 @@ def test_default_opts(lib):
     assert o.recycle_strategy == 4 and o.ritz_freeze_tol == 1e-5 and o.max_it == 1000
     assert o.use_graph == 2 and o.autotune == 1 and o.save_cap == 256 and o.coarse_form == 0
     assert o.adapt_tau == 0.0 and o.adapt_max_per_face == 10
+    assert o.adapt2_tau == 0.0 and o.adapt2_max_per_face == 10
 
 
 def _setup(lib, nx=4, e2s=None, coef=None, **ov):

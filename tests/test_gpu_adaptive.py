@@ -98,3 +98,52 @@ def test_threshold_above_every_eigenvalue_changes_nothing():
     assert g1.adaptive_stats()["added"] == 0 and g1.adaptive_stats()["faces"] == 12
     r = torch.tensor(np.random.default_rng(4).standard_normal(g0.n_gamma), device="cuda")
     assert _rel(g1.apply_precond(r).cpu().numpy(), g0.apply_precond(r).cpu().numpy()) < 1e-14
+
+
+def _level2_pair(e2s, coef, s2r, nx, tau2, tau1=0.0, R=0):
+    from oracle.sequence import OracleSolver
+    from paper_2412_17543_amd.solver import Solver
+    print("[gpu] level-2 adaptive setup nx %d tau2 %g tau1 %g" % (nx, tau2, tau1), flush=True)
+    g = Solver(nx, e2s, coef, sub_to_subregion=s2r, adapt_tau=tau1, adapt2_tau=tau2, R=R)
+    o = OracleSolver(nx, e2s, coef, sub_to_subregion=s2r, adaptive=(tau1, 10) if tau1 > 0 else None,
+                     adaptive2=(tau2, 10), R=R)
+    return g, o
+
+
+def _level2_counts_match(g, o):
+    st = g.adaptive2_stats()
+    info = o.M.level2.adapt2_info
+    added = sum(d["kind"] == "adaptive2" for d in o.M.level2.dofs3)
+    print("[gpu] level-2 adaptive", st, "oracle added", added, "n3", o.M.level2.n3, flush=True)
+    assert st["faces"] == len(info)
+    assert st["added"] == added > 0
+    np.testing.assert_allclose(st["lam_max"], max(i["lam"][0] for i in info), rtol=1e-8)
+    assert g.info()["level3"] == o.M.level2.n3
+
+
+def test_level2_faces_two_subregions_match_oracle():
+    torch = _torch()
+    from tests.test_oracle_adaptive2 import two_subregion_problem
+    ss, s2r = two_subregion_problem()
+    g, o = _level2_pair(workload.cube_partition(16, 4), ss.coef, s2r, 16, 2.5, R=4)
+    _level2_counts_match(g, o)
+    _precond_parity(torch, g, o)
+    F = workload.rhs_sequence(16, 3)
+    U, its, rr = g.solve_sequence(torch.tensor(F, device="cuda"), 1e-10)
+    uo, ito, _ = o.solve_sequence(F, 1e-10)
+    print("[gpu] two-subregion level-2 iters gpu %s oracle %s" % (its.tolist(), ito.tolist()), flush=True)
+    assert np.all(np.abs(its - ito) <= 1)
+    for k in range(len(F)):
+        assert _rel(U[k].cpu().numpy(), uo[k]) <= 1e-9
+
+
+def test_level2_faces_with_level1_rows_match_oracle():
+    # eight subregions, both levels enriched: the level-1 rows on the level-2
+    # interface are level-3 DOFs of their own and enter the level-2 pencils' Pi
+    torch = _torch()
+    s = workload.workload("tiny3")
+    coef = np.exp(2.5 * np.random.default_rng(7).standard_normal(16 ** 3))
+    g, o = _level2_pair(s["elem_to_sub"], coef, s["sub_to_subregion"], 16, 2.0, tau1=10.0)
+    assert g.adaptive_stats()["added"] == o.M.counts()["adaptive"] > 0
+    _level2_counts_match(g, o)
+    _precond_parity(torch, g, o)
