@@ -26,6 +26,9 @@ Modules:
                   vectors (Section 4.2, eqs. harmonicRitz, harmritzstopcrit)
   sequence     -- a right-hand-side sequence solved with recycling
   adjoint      -- adjoint gradient of a least-squares loss w.r.t. log-coefficients
+  block        -- the adjoint systems solved as one block (block deflated PCG,
+                  breakdown-free form; an extension, not in the paper)
+  adaptive     -- adaptive face constraints (Section 3.3), levels 1 and 2
 
 Parity status of each piece (what pins it) is listed in the tests and in the
 design notes; the three-level iteration counts are pinned only by the

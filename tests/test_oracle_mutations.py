@@ -141,3 +141,29 @@ def test_level2_rows_restricted_to_the_wrong_side_are_caught(monkeypatch):
     monkeypatch.setattr(adaptive, "adaptive_dofs", bad)
     with pytest.raises(AssertionError):
         t2.test_face_eigenvalue_is_the_coarse_condition_number()
+
+
+def test_block_beta_with_wrong_sign_is_caught(monkeypatch):
+    from oracle import block
+    from tests import test_oracle_block as tbk
+    orig = block.orth
+    src = block.block_dpcg
+
+    def bad_block(apply_A, apply_M, B, W=None, rtol=1e-8, max_it=1000):
+        n, s = B.shape
+        X = np.zeros((n, s)); R = B.copy(); P = np.zeros((n, 0)); Q = np.zeros((n, 0))
+        bn = np.linalg.norm(B, axis=0); it = 0; ranks = []
+        if W is not None and W.shape[1]:
+            return src(apply_A, apply_M, B, W, rtol, max_it)
+        while it < max_it and not np.all(np.linalg.norm(R, axis=0) <= rtol * bn):
+            Z = apply_M(R)
+            if P.shape[1]:
+                Z = Z + P @ np.linalg.solve(P.T @ Q, Q.T @ Z)     # planted: + instead of -
+            P = orig(Z); ranks.append(P.shape[1])
+            Q = apply_A(P)
+            alpha = np.linalg.solve(P.T @ Q, P.T @ R)
+            X = X + P @ alpha; R = R - Q @ alpha; it += 1
+        return dict(x=X, iters=it, relres=None, ranks=ranks)
+    monkeypatch.setattr(block, "block_dpcg", bad_block)
+    with pytest.raises(AssertionError):
+        tbk.test_one_column_is_algorithm_1()
