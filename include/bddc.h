@@ -216,6 +216,27 @@ int bddc_reset_recycle(bddc_ctx *ctx);
 int bddc_adjoint_grad(bddc_ctx *ctx, const double *dLdu_seq, int32_t n_rhs, const double *u_seq,
                       double rtol, double *grad_logcoef, double *grad_rhs_seq);
 
+/*
+ * bddc_adjoint_grad_block -- bddc_adjoint_grad with the n_rhs adjoint
+ * systems (Appendix-B step 1 of the gradient: same BDDC, same current
+ * deflation basis W) solved together as one block: block deflated PCG in the
+ * breakdown-free form (an orthonormal search block whose linearly dependent
+ * directions are dropped; every direction A-orthogonal to W as in
+ * Algorithm 1; x_{-1} = 0), stopping when every column meets the stopping
+ * rule of the options (eq. stopping_rhs or stopping_residual) at rtol.  The
+ * Schur and Neumann products of a block read each operator tile once per 16
+ * columns on the matrix cores.  Not in the paper: an extension for the
+ * adjoint right-hand sides, which are all known at once.
+ * Arguments as bddc_adjoint_grad; iters: host int32, block iterations
+ * (nullable).  Needs n_rhs <= 32, the float64 Neumann operators (local_prec
+ * 64 or local_prec_set bit 1), a problem with Dirichlet nodes, and every
+ * subdomain interface small enough for the block product's LDS (about 540
+ * nodes); otherwise EINVAL.  Errors: ENOTCONV (outputs hold the last
+ * iterate), EBREAKDOWN, ENOMEM, EHIP.
+ */
+int bddc_adjoint_grad_block(bddc_ctx *ctx, const double *dLdu_seq, int32_t n_rhs, const double *u_seq, double rtol,
+                            double *grad_logcoef, double *grad_rhs_seq, int32_t *iters);
+
 /* ----- single operator applications on interface vectors (for testing) -----
  * Interface vectors are float64 device arrays of length bddc_info(...)[1] in
  * increasing node order of the interface nodes (free nodes shared by >= 2

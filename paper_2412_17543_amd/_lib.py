@@ -50,6 +50,8 @@ SIGNATURES = {
     "recycle_update": (c_int32, [c_void_p]),
     "bddc_reset_recycle": (c_int32, [c_void_p]),
     "bddc_adjoint_grad": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_double, c_void_p, c_void_p]),
+    "bddc_adjoint_grad_block": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_double, c_void_p, c_void_p,
+                                          POINTER(c_int32)]),
     "bddc_apply_schur": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "bddc_apply_precond": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "bddc_apply_schur_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p]),

@@ -552,8 +552,20 @@ void run_l2_chain(const bddc_ctx *c, const L2Args &l, hipStream_t st) {
     launch_l2_d(l, c->nsr, c->smem_l2d, st);
 }
 
-void run_coarse(bddc_ctx *c);
-void run_prolong_assemble(bddc_ctx *c, const double *r, double *z, bool gated, bool advance, bool reduce);
+// Where one column's local results come from when they are not the
+// Neumann product's own partials (the block products of the block adjoint):
+// u_i partials (nchunk, pb layout), the coarse partials and the float64 D Phi_i.
+struct PrecSrc {
+    const double *upart;
+    const int32_t *nchunk, *pb;
+    Gather rc;
+    const void *phir;
+    int prec;
+};
+
+void run_coarse(bddc_ctx *c, const Gather *rc_in = nullptr);
+void run_prolong_assemble(bddc_ctx *c, const double *r, double *z, bool gated, bool advance, bool reduce,
+                          const PrecSrc *src = nullptr);
 
 // One BDDC application on r: local constrained-Neumann products and coarse
 // residuals, the coarse problem, assembly of z with the coarse prolongation
@@ -584,10 +596,10 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
 
 // Coarse levels of one BDDC application: u_C from the coarse partials of the
 // Neumann product (eq. coarse_problem; three levels as in Section 3.2).
-void run_coarse(bddc_ctx *c) {
+void run_coarse(bddc_ctx *c, const Gather *rc_in) {
     if (c->nC > 0) {
         TScope ts(c, TK_COARSE);
-        const Gather rc = gather_of(c->opN, true);
+        const Gather rc = rc_in ? *rc_in : gather_of(c->opN, true);
         if (c->coarse_dense) {
             CoarseDenseArgs ca{};
             ca.ctl = c->d_ctl; ca.n = c->nC; ca.rc = rc; ca.r = c->d_rC;
@@ -604,18 +616,21 @@ void run_coarse(bddc_ctx *c) {
 // Prolongation w_i = u_i + D Phi_i u_C and assembly z = sum_i R_i^T w_i
 // (eq. averaging_subdomain_solves), with the (r^T z, (AW)^T z) partials when
 // `reduce` is set.
-void run_prolong_assemble(bddc_ctx *c, const double *r, double *z, bool gated, bool advance, bool reduce) {
+void run_prolong_assemble(bddc_ctx *c, const double *r, double *z, bool gated, bool advance, bool reduce,
+                          const PrecSrc *src) {
     {
         TScope ts(c, TK_VEC);
         ProlArgs pa{};
         pa.ctl = c->d_ctl; pa.gated = gated ? 1 : 0;
         pa.nB = c->d_nB; pa.b_off = c->d_b_off; pa.nc = c->d_nc; pa.c_off = c->d_c_off; pa.cidx = c->d_cidx;
-        pa.nchunk = c->opN.d_nchunk; pa.pb = c->opN.d_pb; pa.upart = c->opN.d_ypart;
-        pa.phir = c->d_phir; pa.phr_off = c->d_phr_off;
+        pa.nchunk = src ? src->nchunk : c->opN.d_nchunk;
+        pa.pb = src ? src->pb : c->opN.d_pb;
+        pa.upart = src ? src->upart : c->opN.d_ypart;
+        pa.phir = src ? src->phir : c->d_phir; pa.phr_off = c->d_phr_off;
         pa.uC = c->nC > 0 ? c->d_uC : nullptr;
         pa.wloc = c->d_wloc;
         pa.ch_sub = c->d_pch_sub; pa.ch_row = c->d_pch_row;
-        launch_prolong(pa, c->prec, c->n_pch, c->max_nc, c->stream);
+        launch_prolong(pa, src ? src->prec : c->prec, c->n_pch, c->max_nc, c->stream);
         ZasmArgs a{};
         a.n = c->n_gamma;
         a.w.ptr = c->d_asm_ptr; a.w.idx = c->d_asm_idx; a.w.part = c->d_wloc;
@@ -2277,6 +2292,291 @@ int bddc_reset_recycle(bddc_ctx *c) {
     init_null_column(c);
     HIPCHK(hipStreamSynchronize(c->stream));
     return 0;
+}
+
+// ------------------------------------------------------------- block adjoint
+// The adjoint systems of a sequence solved together: block deflated PCG in
+// the breakdown-free form (an orthonormal search block P whose dependent
+// directions are dropped), every direction A-orthogonal to W as in
+// Algorithm 1.  The n x s block products (Schur, Neumann with the coarse
+// rows) read every tile once for 16 columns (k_symm); the coarse levels and
+// the prolongation run column by column on the single-vector kernels; the
+// s x s algebra is on the host (three synchronisations per iteration).
+namespace {
+
+constexpr int BMAX = 32;            // columns of one block solve
+
+struct BlockWork {
+    BlockItem *itemsS = nullptr, *itemsN = nullptr;
+    int32_t *ones = nullptr;
+    double *B = nullptr, *X = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr;
+    double *yS = nullptr, *yN = nullptr, *cN = nullptr, *gp = nullptr, *gout = nullptr, *coef = nullptr;
+    double *h = nullptr;             // pinned: 4 Gram results, then 6 coefficient slots
+    int64_t ylen = 0, clen = 0;
+    size_t smem = 0;
+    static constexpr int GSZ = 64 * 64, CSZ = 96 * 64;
+};
+
+void free_block(bddc_ctx *c, BlockWork &b) {
+    dfree(c, b.itemsS); dfree(c, b.itemsN); dfree(c, b.ones);
+    dfree(c, b.B); dfree(c, b.X); dfree(c, b.R); dfree(c, b.Z); dfree(c, b.P); dfree(c, b.Q);
+    dfree(c, b.yS); dfree(c, b.yN); dfree(c, b.cN); dfree(c, b.gp); dfree(c, b.gout); dfree(c, b.coef);
+    if (b.h) (void)hipHostFree(b.h);
+    b = BlockWork{};
+}
+
+int alloc_block(bddc_ctx *c, BlockWork &b) {
+    const int nsub = c->n_sub;
+    std::vector<BlockItem> is(nsub), in(nsub);
+    int64_t ts = 0, tn = 0;
+    for (int i = 0; i < nsub; ++i) {
+        is[i] = BlockItem{ts, c->h_nB[i], 0, c->h_b_off[i], c->h_c_off[i]};
+        in[i] = BlockItem{tn, c->h_nB[i], c->h_nc[i], c->h_b_off[i], c->h_c_off[i]};
+        ts += ntiles_of(c->h_nB[i], 0);
+        tn += ntiles_of(c->h_nB[i], c->h_nc[i]);
+    }
+    b.ylen = std::max<int64_t>(1, (int64_t)c->h_b_off[nsub - 1] + c->h_nB[nsub - 1]);
+    b.clen = std::max<int64_t>(1, (int64_t)c->h_c_off[nsub - 1] + c->h_nc[nsub - 1]);
+    const size_t nv = (size_t)c->ld * BMAX;
+    int rc;
+    std::vector<int32_t> ones(nsub, 1);
+    if ((rc = dupload(c, &b.itemsS, is)) || (rc = dupload(c, &b.itemsN, in)) || (rc = dupload(c, &b.ones, ones)) ||
+        (rc = dalloc(c, &b.B, nv)) || (rc = dalloc(c, &b.X, nv)) || (rc = dalloc(c, &b.R, nv)) ||
+        (rc = dalloc(c, &b.Z, nv)) || (rc = dalloc(c, &b.P, nv)) || (rc = dalloc(c, &b.Q, nv)) ||
+        (rc = dalloc(c, &b.yS, (size_t)b.ylen * BMAX)) || (rc = dalloc(c, &b.yN, (size_t)b.ylen * BMAX)) ||
+        (rc = dalloc(c, &b.cN, (size_t)b.clen * BMAX)) ||
+        (rc = dalloc(c, &b.gp, (size_t)c->gram_nb * BlockWork::GSZ)) ||
+        (rc = dalloc(c, &b.gout, (size_t)4 * BlockWork::GSZ)) || (rc = dalloc(c, &b.coef, (size_t)6 * BlockWork::CSZ)))
+        return rc;
+    if (hipHostMalloc((void **)&b.h, sizeof(double) * (4 * BlockWork::GSZ + 6 * BlockWork::CSZ)) != hipSuccess)
+        return fail(BDDC_ENOMEM, "hipHostMalloc failed (block adjoint)");
+    // partial slots that no kernel writes (none with one chunk per subdomain) stay zero
+    launch_fill((int64_t)b.ylen * BMAX, 0.0, b.yN, c->stream);
+    launch_fill((int64_t)b.clen * BMAX, 0.0, b.cN, c->stream);
+    b.smem = symm_smem_bytes(c->max_nB, c->max_nc);
+    return 0;
+}
+
+// X^T Y (kx x ky, row-major) into Gram slot `slot` (device), copy to the
+// pinned host slot; the caller synchronises.
+void block_gram(bddc_ctx *c, BlockWork &b, const double *X, int kx, const double *Y, int ky, int slot) {
+    if (kx <= 0 || ky <= 0) return;
+    GramArgs g{};
+    g.n = c->n_gamma; g.k = kx; g.k2 = ky; g.ld = c->ld; g.X = X; g.Y = Y; g.part = b.gp;
+    launch_gram(g, c->gram_nb, c->stream);
+    ReduceArgs r{};
+    r.part = b.gp; r.n = c->gram_nb; r.ncol = kx * ky; r.out = b.gout + (size_t)slot * BlockWork::GSZ;
+    launch_reduce(r, c->stream);
+    (void)hipMemcpyAsync(b.h + (size_t)slot * BlockWork::GSZ, r.out, sizeof(double) * kx * ky, hipMemcpyDeviceToHost,
+                         c->stream);
+}
+
+// out = [V1, V2] Y (Y: (k1 + k2) x ncol row-major, host, coefficient slot
+// `slot`); out may be V1 (each wave reads its rows before writing them).
+int block_gemm(bddc_ctx *c, BlockWork &b, const double *V1, int k1, const double *V2, int k2,
+               const std::vector<double> &Y, int ncol, double *out, int slot) {
+    if (ncol <= 0) return 0;
+    double *hy = b.h + 4 * BlockWork::GSZ + (size_t)slot * BlockWork::CSZ;
+    double *dy = b.coef + (size_t)slot * BlockWork::CSZ;
+    std::copy(Y.begin(), Y.end(), hy);
+    HIPCHK(hipMemcpyAsync(dy, hy, sizeof(double) * Y.size(), hipMemcpyHostToDevice, c->stream));
+    GemmArgs g{};
+    g.n = c->n_gamma; g.ld = c->ld;
+    g.V1[0] = V1; g.k1 = k1; g.V2[0] = V2 ? V2 : V1; g.k2 = k2;
+    g.Y = dy; g.ncol = ncol; g.ldy = ncol; g.out[0] = out;
+    launch_recycle_gemm(g, c->stream, 1);
+    return 0;
+}
+
+void block_A(bddc_ctx *c, BlockWork &b, const double *X, int ncols, double *out) {
+    TScope ts(c, TK_SCHUR);
+    BlockSymvArgs a{};
+    a.tiles = c->d_S; a.items = b.itemsS; a.gB = c->d_gB; a.X = X; a.ldx = c->ld; a.ncols = ncols;
+    a.ypart = b.yS; a.ylen = b.ylen;
+    launch_symm(a, c->n_sub, false, b.smem, c->stream);
+    launch_gather_block(c->n_gamma, c->d_asm_ptr, c->d_asm_idx, b.yS, b.ylen, out, c->ld, ncols, c->stream);
+}
+
+void block_M(bddc_ctx *c, BlockWork &b, const double *R, int ncols, double *Z) {
+    {
+        TScope ts(c, TK_PREC);
+        BlockSymvArgs a{};
+        a.tiles = (const double *)c->d_Nx[prec_slot(64)]; a.items = b.itemsN; a.gB = c->d_gB; a.X = R; a.ldx = c->ld;
+        a.ncols = ncols; a.ypart = b.yN; a.ylen = b.ylen; a.cpart = b.cN; a.clen = b.clen;
+        launch_symm(a, c->n_sub, true, b.smem, c->stream);
+    }
+    for (int j = 0; j < ncols; ++j) {
+        PrecSrc src{b.yN + (size_t)j * b.ylen, b.ones, c->d_b_off,
+                    Gather{c->d_casm_ptr, c->d_casm_idx, b.cN + (size_t)j * b.clen}, c->d_phirx[prec_slot(64)], 64};
+        run_coarse(c, &src.rc);
+        run_prolong_assemble(c, R + (size_t)j * c->ld, Z + (size_t)j * c->ld, false, false, false, &src);
+    }
+}
+
+// X = G^{-1} Bm for a k x k SPD G (row-major) and k x m Bm; false if G is not SPD
+bool spd_solve(std::vector<double> G, int k, const double *Bm, int m, std::vector<double> &X) {
+    X.assign((size_t)k * m, 0.0);
+    if (k == 0) return true;
+    for (int i = 0; i < k; ++i)
+        for (int j = i + 1; j < k; ++j) G[(size_t)i * k + j] = G[(size_t)j * k + i] = 0.5 * (G[(size_t)i * k + j] + G[(size_t)j * k + i]);
+    if (!cholesky(G, k)) return false;
+    std::vector<double> col(k);
+    for (int j = 0; j < m; ++j) {
+        for (int i = 0; i < k; ++i) col[i] = Bm[(size_t)i * m + j];
+        chol_solve(G, k, col.data());
+        for (int i = 0; i < k; ++i) X[(size_t)i * m + j] = col[i];
+    }
+    return true;
+}
+
+// [I; C] as a (k + r) x k coefficient matrix (identity on the first block)
+std::vector<double> stack_identity(int k, const std::vector<double> &C, int r, double sign) {
+    std::vector<double> Y((size_t)(k + r) * k, 0.0);
+    for (int i = 0; i < k; ++i) Y[(size_t)i * k + i] = 1.0;
+    for (int q = 0; q < r; ++q)
+        for (int j = 0; j < k; ++j) Y[(size_t)(k + q) * k + j] = sign * C[(size_t)q * k + j];
+    return Y;
+}
+
+}  // namespace
+
+static int block_solve(bddc_ctx *c, BlockWork &b, int s, double rtol, int *iters_out) {
+    const int m = c->k;                               // deflation columns (the current basis)
+    const int ld = c->ld;
+    std::vector<double> WAW(c->WAW.begin(), c->WAW.end()), T, Cm;
+    int rc;
+    // X_0 = W (W^T A W)^{-1} W^T B, R_0 = B - A W (...)
+    launch_fill((int64_t)ld * s, 0.0, b.X, c->stream);
+    launch_copy((int64_t)ld * s, b.B, b.R, c->stream);
+    block_gram(c, b, b.B, s, b.B, s, 0);
+    if (m > 0) block_gram(c, b, c->d_W, m, b.B, s, 1);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<double> bb(s), r0(s);
+    for (int j = 0; j < s; ++j) bb[j] = b.h[(size_t)j * s + j];
+    if (m > 0) {
+        if (!spd_solve(WAW, m, b.h + BlockWork::GSZ, s, T)) return fail(BDDC_EBREAKDOWN, "W^T A W not positive definite");
+        if ((rc = block_gemm(c, b, c->d_W, m, nullptr, 0, T, s, b.X, 0))) return rc;
+        std::vector<double> Y = stack_identity(s, T, m, -1.0);
+        if ((rc = block_gemm(c, b, b.R, s, c->d_AW, m, Y, s, b.R, 1))) return rc;
+    }
+    int r = 0, it = 0;                                // columns of P
+    const int stop_r0 = c->opts.stop_rule == 1;
+    std::vector<double> Gpq;
+    for (;;) {
+        // residual norms, Z = M^{-1} R and its products with Q and A W
+        block_gram(c, b, b.R, s, b.R, s, 0);
+        block_M(c, b, b.R, s, b.Z);
+        if (m > 0) block_gram(c, b, c->d_AW, m, b.Z, s, 1);
+        if (r > 0) block_gram(c, b, b.Q, r, b.Z, s, 2);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        bool done = true;
+        for (int j = 0; j < s; ++j) {
+            const double rr = b.h[(size_t)j * s + j];
+            if (it == 0) r0[j] = rr;
+            const double den = stop_r0 ? r0[j] : bb[j];
+            if (!(rr <= rtol * rtol * den)) done = false;
+            if (!std::isfinite(rr)) return fail(BDDC_EBREAKDOWN, "block PCG: non-finite residual");
+        }
+        if (done) break;
+        if (it >= c->opts.max_it) { *iters_out = it; return fail(BDDC_ENOTCONV, "max_it reached (block adjoint)"); }
+        // Y = Z - W (W^T A W)^{-1} (A W)^T Z - P (P^T Q)^{-1} Q^T Z
+        if (m > 0) {
+            if (!spd_solve(WAW, m, b.h + BlockWork::GSZ, s, T)) return fail(BDDC_EBREAKDOWN, "W^T A W not positive definite");
+            if ((rc = block_gemm(c, b, b.Z, s, c->d_W, m, stack_identity(s, T, m, -1.0), s, b.Z, 0))) return rc;
+        }
+        if (r > 0) {
+            if (!spd_solve(Gpq, r, b.h + 2 * BlockWork::GSZ, s, T)) return fail(BDDC_EBREAKDOWN, "P^T A P not positive definite");
+            if ((rc = block_gemm(c, b, b.Z, s, b.P, r, stack_identity(s, T, r, -1.0), s, b.Z, 1))) return rc;
+        }
+        // P = orth(Y): eigenvectors of Y^T Y above 1e-12 of the largest eigenvalue
+        block_gram(c, b, b.Z, s, b.Z, s, 3);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        {
+            std::vector<double> G(b.h + 3 * BlockWork::GSZ, b.h + 3 * BlockWork::GSZ + (size_t)s * s), lam, V;
+            for (int i = 0; i < s; ++i)
+                for (int j = i + 1; j < s; ++j) G[(size_t)i * s + j] = G[(size_t)j * s + i] = 0.5 * (G[(size_t)i * s + j] + G[(size_t)j * s + i]);
+            sym_eig(G, s, lam, V);
+            const double top = lam.empty() ? 0.0 : lam[s - 1];
+            std::vector<int> keep;
+            for (int q = 0; q < s; ++q)
+                if (top > 0.0 && lam[q] > 1e-12 * top) keep.push_back(q);
+            r = (int)keep.size();
+            if (r == 0) { *iters_out = it; return fail(BDDC_EBREAKDOWN, "block PCG: empty search block"); }
+            Cm.assign((size_t)s * r, 0.0);
+            for (int i = 0; i < s; ++i)
+                for (int q = 0; q < r; ++q) Cm[(size_t)i * r + q] = V[(size_t)i * s + keep[q]] / std::sqrt(lam[keep[q]]);
+        }
+        if ((rc = block_gemm(c, b, b.Z, s, nullptr, 0, Cm, r, b.P, 2))) return rc;
+        // Q = A P; alpha = (P^T Q)^{-1} P^T R
+        block_A(c, b, b.P, r, b.Q);
+        block_gram(c, b, b.P, r, b.Q, r, 0);
+        block_gram(c, b, b.P, r, b.R, s, 1);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        Gpq.assign(b.h, b.h + (size_t)r * r);
+        std::vector<double> alpha;
+        if (!spd_solve(Gpq, r, b.h + BlockWork::GSZ, s, alpha)) return fail(BDDC_EBREAKDOWN, "P^T A P not positive definite");
+        if ((rc = block_gemm(c, b, b.X, s, b.P, r, stack_identity(s, alpha, r, 1.0), s, b.X, 3)) ||
+            (rc = block_gemm(c, b, b.R, s, b.Q, r, stack_identity(s, alpha, r, -1.0), s, b.R, 4)))
+            return rc;
+        ++it;
+    }
+    *iters_out = it;
+    return 0;
+}
+
+int bddc_adjoint_grad_block(bddc_ctx *c, const double *dLdu_seq, int32_t n_rhs, const double *u_seq, double rtol,
+                            double *grad_logcoef, double *grad_rhs_seq, int32_t *iters) {
+    if (!c || !dLdu_seq || !u_seq || !grad_logcoef || !grad_rhs_seq || n_rhs < 0 || !(rtol > 0))
+        return fail(BDDC_EINVAL, "bad bddc_adjoint_grad_block argument");
+    if (n_rhs > BMAX) return fail(BDDC_EINVAL, "bddc_adjoint_grad_block: at most 32 right-hand sides");
+    if (c->nullc) return fail(BDDC_EINVAL, "bddc_adjoint_grad_block: not for the pure Neumann problem");
+    if (!(c->prec_built & 1))
+        return fail(BDDC_EINVAL, "bddc_adjoint_grad_block: needs the float64 Neumann operators (local_prec 64 or local_prec_set bit 1)");
+    if (symm_smem_bytes(c->max_nB, c->max_nc) > 160 * 1024)
+        return fail(BDDC_EINVAL, "bddc_adjoint_grad_block: a subdomain interface is too large for the block product");
+    if (iters) *iters = 0;
+    if (n_rhs == 0) {
+        launch_fill(c->st.n_elem, 0.0, grad_logcoef, c->stream);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return 0;
+    }
+    // adopt a basis update still pending from the last forward solve
+    if (c->pend.active) {
+        int rc0;
+        if ((rc0 = end_sync_issue(c, false)) || (rc0 = end_sync_wait(c))) return rc0;
+    }
+    if (set_symm_smem_limit(symm_smem_bytes(c->max_nB, c->max_nc))) return fail(BDDC_EHIP, "hipFuncSetAttribute (block product LDS) failed");
+    BlockWork b;
+    int rc = alloc_block(c, b);
+    double *xsave = nullptr;
+    if (!rc) rc = dalloc(c, &xsave, c->n_gamma);
+    if (rc) { free_block(c, b); return rc; }
+    launch_copy(c->n_gamma, c->d_x, xsave, c->stream);
+    launch_set_done(c->d_ctl, 0, c->stream);
+    for (int k = 0; k < n_rhs; ++k) {
+        run_condense(c, dLdu_seq + (size_t)k * c->n_nodes);
+        launch_copy(c->n_gamma, c->d_b, b.B + (size_t)k * c->ld, c->stream);
+    }
+    int it = 0;
+    rc = block_solve(c, b, n_rhs, rtol, &it);
+    if (iters) *iters = it;
+    if (rc == 0 || rc == BDDC_ENOTCONV) {
+        for (int k = 0; k < n_rhs; ++k) {
+            launch_copy(c->n_gamma, b.X + (size_t)k * c->ld, c->d_x, c->stream);
+            run_recover(c, dLdu_seq + (size_t)k * c->n_nodes, grad_rhs_seq + (size_t)k * c->n_nodes);
+        }
+        GradArgs g{};
+        g.n_elem = c->st.n_elem; g.n_nodes = c->n_nodes; g.nx = c->st.nx; g.ny = c->st.ny; g.nz = c->st.nz;
+        g.n_rhs = n_rhs; g.keep = c->d_keep; g.free_node = c->d_free; g.coefh = c->d_coefh;
+        g.lam = grad_rhs_seq; g.u = u_seq; g.grad = grad_logcoef;
+        launch_elem_grad(g, c->stream);
+    }
+    launch_copy(c->n_gamma, xsave, c->d_x, c->stream);
+    c->have_solve = false;
+    (void)hipStreamSynchronize(c->stream);
+    dfree(c, xsave);
+    free_block(c, b);
+    return rc;
 }
 
 int bddc_adjoint_grad(bddc_ctx *c, const double *dLdu_seq, int32_t n_rhs, const double *u_seq, double rtol,

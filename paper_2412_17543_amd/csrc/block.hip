@@ -1,0 +1,159 @@
+// Block products of the block adjoint (several right-hand sides at once):
+// the batched symmetric products y_i = S_i x_i (Schur) and, with the coarse
+// rows, u_i = D N_i D g_i and c_i = (D Phi_i)^T g_i (Neumann, eq. localCorr)
+// for 16 columns at a time, on the matrix cores, and the assembly of the
+// per-subdomain results.
+//
+// k_symm: one block per (subdomain, 16-column chunk), 4 waves.  The block
+// stages X_i (n x 16) in LDS, then walks the packed upper-triangle tiles one
+// tile row I at a time; inside a row, wave w takes the tiles q = w, w + 4, ...
+// (J = I + q):
+//   row part    Y_I += T X_J          (accumulated in the wave's registers)
+//   column part Y_J += T^T X_I, J > I (added to LDS; each J once per row)
+//   coarse tile C_{J - nt} += T^T X_I (Neumann only; T holds rows of D Phi_i)
+// After the row the waves' row parts are added into Y_I in wave order, so
+// every entry is summed in a fixed order (the product is reproducible bit by
+// bit).  A tile is loaded once (two 16-byte loads per lane, the layout of
+// tile_index), written to the wave's LDS slot in row-major order and read
+// back as MFMA operands: v_mfma_f64_16x16x4f64 takes A[i][k] and B[k][j] in
+// lane i (j) + 16 k and returns (i, j) in lane j + 16 (i % 4), register i / 4.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace bddc {
+
+namespace {
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+constexpr int XS = 17;              // LDS row stride (doubles) of X, Y and a tile
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool COARSE>
+__global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
+    extern __shared__ __align__(16) double sm[];
+    const BlockItem it = a.items[blockIdx.x];
+    const int c0 = 16 * (int)blockIdx.y;
+    const int n = it.n, nt = (n + 15) / 16, npad = 16 * nt;
+    const int nc = COARSE ? it.nc : 0, ntc = (nc + 15) / 16;
+    double *xs = sm;                                   // npad x 16 (stride XS)
+    double *ys = xs + (size_t)npad * XS;               // (npad + 16 ntc) x 16
+    double *ts = ys + (size_t)(npad + 16 * ntc) * XS;  // 4 tiles of 16 x 16
+    double *red = ts + 4 * 16 * XS;                    // 4 x 256
+    const int tid = threadIdx.x, w = tid >> 6, L = tid & 63, li = L & 15, lk = L >> 4;
+    const int32_t *gb = a.gB + it.xoff;
+    for (int e = tid; e < 16 * npad; e += 256) {
+        const int cc = e / npad, k = e - cc * npad, col = c0 + cc;
+        xs[k * XS + cc] = (k < n && col < a.ncols) ? a.X[(int64_t)col * a.ldx + gb[k]] : 0.0;
+    }
+    for (int e = tid; e < (npad + 16 * ntc) * XS; e += 256) ys[e] = 0.0;
+    __syncthreads();
+    double *tw = ts + w * 16 * XS;
+    const double *tiles = a.tiles + it.tile * 256;
+    int64_t base = 0;                                  // first tile of row I
+    for (int I = 0; I < nt; ++I) {
+        const int len = nt - I + ntc;
+        dvec4 racc = {0.0, 0.0, 0.0, 0.0};
+        for (int q = w; q < len; q += 4) {
+            const int J = I + q;
+            const dvec2 *tp = reinterpret_cast<const dvec2 *>(tiles + (base + q) * 256);
+            const dvec2 v01 = tp[L], v23 = tp[64 + L];
+            tw[(4 * lk + 0) * XS + li] = v01.x;
+            tw[(4 * lk + 1) * XS + li] = v01.y;
+            tw[(4 * lk + 2) * XS + li] = v23.x;
+            tw[(4 * lk + 3) * XS + li] = v23.y;
+            wave_sync();
+            if (J < nt) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    racc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[li * XS + 4 * s + lk],
+                                                                xs[(16 * J + 4 * s + lk) * XS + li], racc, 0, 0, 0);
+            }
+            if (J > I) {
+                dvec4 cacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    cacc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[(4 * s + lk) * XS + li],
+                                                                xs[(16 * I + 4 * s + lk) * XS + li], cacc, 0, 0, 0);
+                const int r0 = J < nt ? 16 * J : npad + 16 * (J - nt);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ys[(r0 + 4 * r + lk) * XS + li] += cacc[r];
+            }
+            wave_sync();
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[w * 256 + (4 * r + lk) * 16 + li] = racc[r];
+        __syncthreads();
+        {
+            const int row = tid >> 4, col = tid & 15;
+            ys[(16 * I + row) * XS + col] += ((red[tid] + red[256 + tid]) + red[512 + tid]) + red[768 + tid];
+        }
+        __syncthreads();
+        base += len;
+    }
+    for (int e = tid; e < 16 * n; e += 256) {
+        const int cc = e / n, k = e - cc * n, col = c0 + cc;
+        if (col < a.ncols) a.ypart[(int64_t)col * a.ylen + it.xoff + k] = ys[k * XS + cc];
+    }
+    if (COARSE) {
+        for (int e = tid; e < 16 * nc; e += 256) {
+            const int cc = e / nc, q = e - cc * nc, col = c0 + cc;
+            if (col < a.ncols) a.cpart[(int64_t)col * a.clen + it.coff + q] = ys[(npad + q) * XS + cc];
+        }
+    }
+}
+
+// out[g + col ldo] = sum of part[col plen + idx[e]], e in [ptr[g], ptr[g+1])
+__global__ void __launch_bounds__(256) k_gather_block(int n, const int32_t *ptr, const int32_t *idx,
+                                                      const double *part, int64_t plen, double *out, int64_t ldo,
+                                                      int ncols) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const int e0 = ptr[g], e1 = ptr[g + 1];
+    for (int col = blockIdx.y; col < ncols; col += gridDim.y) {
+        const double *p = part + (int64_t)col * plen;
+        double s = 0.0;
+        for (int e = e0; e < e1; ++e) s += p[idx[e]];
+        out[g + (int64_t)col * ldo] = s;
+    }
+}
+
+}  // namespace
+
+size_t symm_smem_bytes(int max_n, int max_nc) {
+    const int npad = 16 * ((max_n + 15) / 16), ncpad = 16 * ((max_nc + 15) / 16);
+    return sizeof(double) * ((size_t)(2 * npad + ncpad) * XS + 4 * 16 * XS + 4 * 256);
+}
+
+int set_symm_smem_limit(size_t bytes) {
+    if (hipFuncSetAttribute((const void *)k_symm<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+            hipSuccess ||
+        hipFuncSetAttribute((const void *)k_symm<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+            hipSuccess)
+        return 1;
+    return 0;
+}
+
+void launch_symm(const BlockSymvArgs &a, int nsub, bool coarse, size_t smem, hipStream_t s) {
+    if (nsub <= 0 || a.ncols <= 0) return;
+    const dim3 grid(nsub, (a.ncols + 15) / 16);
+    if (coarse) hipLaunchKernelGGL(k_symm<true>, grid, dim3(256), smem, s, a);
+    else hipLaunchKernelGGL(k_symm<false>, grid, dim3(256), smem, s, a);
+}
+
+void launch_gather_block(int n, const int32_t *ptr, const int32_t *idx, const double *part, int64_t plen, double *out,
+                         int64_t ldo, int ncols, hipStream_t s) {
+    if (n <= 0 || ncols <= 0) return;
+    hipLaunchKernelGGL(k_gather_block, dim3((n + 255) / 256, std::min(ncols, 8)), dim3(256), 0, s, n, ptr, idx, part,
+                       plen, out, ldo, ncols);
+}
+
+}  // namespace bddc

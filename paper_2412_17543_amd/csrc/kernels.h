@@ -254,6 +254,7 @@ struct GemmArgs {
 struct GramArgs {
     int n, k;
     int64_t ld;
+    int k2;                         // columns of Y (0: k)
     const double *X, *Y;
     double *part;
 };
@@ -309,8 +310,28 @@ void launch_cond_asm(const CondAsmArgs &a, int grid, hipStream_t s);
 void launch_rec_rhs(const RecArgs &a, int nsub, int max_nB, hipStream_t s);
 void launch_rec_out(const RecArgs &a, int nsub, hipStream_t s);
 void launch_scatter_gamma(int n, const int32_t *gamma, const double *x, double *u, hipStream_t s);
-void launch_recycle_gemm(const GemmArgs &a, hipStream_t s);
+void launch_recycle_gemm(const GemmArgs &a, hipStream_t s, int ny = 2);   // ny: outputs (1 or 2)
 void launch_gram(const GramArgs &a, int nblocks, hipStream_t s);
+
+// ============================================================ block products (block.hip)
+struct BlockItem {                  // one subdomain of a block product
+    int64_t tile;                   // its first tile (in tiles) in the packed operator
+    int32_t n, nc;                  // interface size, coarse rows (Neumann; 0 for Schur)
+    int32_t xoff, coff;             // offsets in the local interface / coarse arrays
+};
+struct BlockSymvArgs {
+    const double *tiles;            // float64 tiles (Schur, or Neumann with the coarse rows)
+    const BlockItem *items;
+    const int32_t *gB;              // local interface position -> interface index
+    const double *X; int64_t ldx; int ncols;   // input block, column-major
+    double *ypart; int64_t ylen;    // y of subdomain i, column c: ypart[c ylen + xoff_i + k]
+    double *cpart; int64_t clen;    // coarse: cpart[c clen + coff_i + q]
+};
+size_t symm_smem_bytes(int max_n, int max_nc);
+int set_symm_smem_limit(size_t bytes);
+void launch_symm(const BlockSymvArgs &a, int nsub, bool coarse, size_t smem, hipStream_t s);
+void launch_gather_block(int n, const int32_t *ptr, const int32_t *idx, const double *part, int64_t plen, double *out,
+                         int64_t ldo, int ncols, hipStream_t s);
 void launch_elem_grad(const GradArgs &a, hipStream_t s);
 void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s);
 void launch_fill(int64_t n, double v, double *dst, hipStream_t s);

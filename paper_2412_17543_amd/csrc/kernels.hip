@@ -326,8 +326,8 @@ __global__ void __launch_bounds__(256) k_recycle_gemm(GemmArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Gram product X^T Y (k x k, k <= 64) of two column-major n x k blocks:
-// per-block partials part[(p k + q) nblocks + block].  A block takes
+// Gram product X^T Y (k x k2, both <= 64) of two column-major blocks (n x k
+// and n x k2): per-block partials part[(p k2 + q) nblocks + block].  A block takes
 // consecutive chunks of GRAM_ROWS rows, stages both blocks of the chunk in
 // LDS (coalesced column loads), and each of its 4 waves multiplies its 16
 // rows of the chunk on the matrix cores into all T x T output tiles
@@ -338,7 +338,7 @@ template <int T>
 __global__ void __launch_bounds__(256) k_gram(GramArgs a) {
     __shared__ double xs[16 * T][GRAM_ROWS + 1];
     __shared__ double ys[16 * T][GRAM_ROWS + 1];
-    const int k = a.k;
+    const int k = a.k, k2 = a.k2;
     const int w = threadIdx.x >> 6, L = threadIdx.x & 63, li = L & 15, lk = L >> 4;
     const int64_t per = (a.n + gridDim.x - 1) / gridDim.x;
     const int64_t g0 = (int64_t)blockIdx.x * per, g1 = min((int64_t)a.n, g0 + per);
@@ -352,9 +352,8 @@ __global__ void __launch_bounds__(256) k_gram(GramArgs a) {
         __syncthreads();
         for (int t = threadIdx.x; t < GRAM_ROWS * 16 * T; t += blockDim.x) {
             const int rr = t % GRAM_ROWS, c = t / GRAM_ROWS;
-            const bool ok = rr < nr && c < k;
-            xs[c][rr] = ok ? a.X[(int64_t)c * a.ld + s0 + rr] : 0.0;
-            ys[c][rr] = ok ? a.Y[(int64_t)c * a.ld + s0 + rr] : 0.0;
+            xs[c][rr] = rr < nr && c < k ? a.X[(int64_t)c * a.ld + s0 + rr] : 0.0;
+            ys[c][rr] = rr < nr && c < k2 ? a.Y[(int64_t)c * a.ld + s0 + rr] : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -390,8 +389,8 @@ __global__ void __launch_bounds__(256) k_gram(GramArgs a) {
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-        const int i = e / k, j = e % k;
+    for (int e = threadIdx.x; e < k * k2; e += blockDim.x) {
+        const int i = e / k2, j = e % k2;
         a.part[(int64_t)e * gridDim.x + blockIdx.x] = sum[i * 16 * T + j];
     }
 }
@@ -611,18 +610,21 @@ void launch_rec_out(const RecArgs &a, int nsub, hipStream_t s) {
 void launch_scatter_gamma(int n, const int32_t *gamma, const double *x, double *u, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_scatter_gamma, dim3(nblk(n, 256)), dim3(256), 0, s, n, gamma, x, u);
 }
-void launch_recycle_gemm(const GemmArgs &a, hipStream_t s) {
+void launch_recycle_gemm(const GemmArgs &a, hipStream_t s, int ny) {
     if (a.n <= 0) return;
-    const dim3 grid(nblk(a.n, 64), 2);                // 64 rows per block
+    const dim3 grid(nblk(a.n, 64), ny);               // 64 rows per block
     if (a.ncol <= 16) hipLaunchKernelGGL(k_recycle_gemm<1>, grid, dim3(256), 0, s, a);
     else if (a.ncol <= 32) hipLaunchKernelGGL(k_recycle_gemm<2>, grid, dim3(256), 0, s, a);
     else if (a.ncol <= 48) hipLaunchKernelGGL(k_recycle_gemm<3>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_recycle_gemm<4>, grid, dim3(256), 0, s, a);
 }
-void launch_gram(const GramArgs &a, int nblocks, hipStream_t s) {
-    if (a.k <= 16) hipLaunchKernelGGL(k_gram<1>, dim3(nblocks), dim3(256), 0, s, a);
-    else if (a.k <= 32) hipLaunchKernelGGL(k_gram<2>, dim3(nblocks), dim3(256), 0, s, a);
-    else if (a.k <= 48) hipLaunchKernelGGL(k_gram<3>, dim3(nblocks), dim3(256), 0, s, a);
+void launch_gram(const GramArgs &a0, int nblocks, hipStream_t s) {
+    GramArgs a = a0;
+    if (a.k2 <= 0) a.k2 = a.k;
+    const int km = std::max(a.k, a.k2);
+    if (km <= 16) hipLaunchKernelGGL(k_gram<1>, dim3(nblocks), dim3(256), 0, s, a);
+    else if (km <= 32) hipLaunchKernelGGL(k_gram<2>, dim3(nblocks), dim3(256), 0, s, a);
+    else if (km <= 48) hipLaunchKernelGGL(k_gram<3>, dim3(nblocks), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_gram<4>, dim3(nblocks), dim3(256), 0, s, a);
 }
 void launch_elem_grad(const GradArgs &a, hipStream_t s) {

@@ -270,6 +270,20 @@ class Solver:
                                          _ptr(g), _ptr(gF)))
         return g, gF
 
+    def adjoint_grad_block(self, dLdu, u, rtol=1e-10):
+        """adjoint_grad with the adjoint systems solved as one block
+        (bddc_adjoint_grad_block).  Returns (grad, dL/dF, block iterations)."""
+        dLdu = self._dev(dLdu)
+        u = self._dev(u)
+        if dLdu.dim() == 1:
+            dLdu, u = dLdu[None], u[None]
+        g = torch.empty(self.n_elem, dtype=torch.float64, device=self.device)
+        gF = torch.empty_like(dLdu)
+        it = ctypes.c_int32(0)
+        check(self.lib.bddc_adjoint_grad_block(self.ctx, _ptr(dLdu), dLdu.shape[0], _ptr(u), rtol,
+                                               _ptr(g), _ptr(gF), ctypes.byref(it)))
+        return g, gF, it.value
+
     def close(self):
         if getattr(self, "ctx", None):
             self.lib.bddc_destroy(self.ctx)
