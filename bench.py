@@ -223,7 +223,8 @@ def run_study(args):
     stopping rule x initial guess without recycling (Tab. no_recycling),
     the recycling strategies B1-B4 at R = 20 (Tab. recycling_cases), the
     basis size R for B4 (Tab. recycling_base), and the adaptive threshold tau
-    with card/diag weights (Tab. recycling_case2).  Each row: iterations as
+    with card/diag weights (Tab. recycling_case2), plus two rows with the
+    level-2 faces enriched as well.  Each row: iterations as
     min-max(avg), seconds per right-hand side and per iteration (float64,
     queued launches), setup seconds; the coarse space for the tau study."""
     import numpy as np
@@ -243,6 +244,7 @@ def run_study(args):
         cases = [dict(R=r, strategy="B4") for r in (0, 5, 10, 20, 40, 60)]
     else:
         cases = [dict(R=20, adapt_tau=t, weights=w) for w in ("card", "diag") for t in (0.0, 10.0, 5.0, 3.0, 2.0)]
+        cases += [dict(R=20, adapt_tau=3.0, weights="diag", adapt2_tau=t2) for t2 in (3.0, 2.0)]
     rows = []
     for kw in cases:
         t0 = time.perf_counter()
@@ -263,6 +265,9 @@ def run_study(args):
                    max_true_relres=float(rr.max()), frozen=bool(info["frozen"]), n_coarse=info["n_coarse"])
         if kw.get("adapt_tau", 0) > 0:
             row["adaptive"] = g.adaptive_stats()
+        if kw.get("adapt2_tau", 0) > 0:
+            row["adaptive_level2"] = g.adaptive2_stats()
+            row["n_level3"] = info["level3"]
         rows.append(row)
         print("[study] %s" % row, file=sys.stderr, flush=True)
         g.close()
@@ -448,6 +453,27 @@ def main():
         el = time.perf_counter() - t0
         line["adjoint"] = {"value": round(n_rhs * reps / el, 3), "unit": "adjoint solves/s",
                            "s_per_sequence": round(el / reps, 4), "grad_norm": float(grad.norm().item())}
+        # the same adjoint systems solved as blocks of at most 32 columns
+        chunks = [(k, min(n_rhs, k + 32)) for k in range(0, n_rhs, 32)]
+
+        def block_grad():
+            total, its = None, []
+            for k0, k1 in chunks:
+                gk, _, it = g.adjoint_grad_block(dLdu[k0:k1], U[k0:k1], args.rtol)
+                total = gk if total is None else total + gk
+                its.append(it)
+            return total, its
+        block_grad()                                # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            gb, bits = block_grad()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        line["adjoint"]["block"] = {"value": round(n_rhs * reps / el, 3), "unit": "adjoint solves/s",
+                                    "s_per_sequence": round(el / reps, 4), "block_iterations": bits,
+                                    "max_rel_diff_vs_column_by_column":
+                                        float(((gb - grad).abs().max() / grad.abs().max()).item())}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, s, info["n_sub"])
     print(json.dumps(line), flush=True)

@@ -4,7 +4,8 @@
 // for 16 columns at a time, on the matrix cores, and the assembly of the
 // per-subdomain results.
 //
-// k_symm: one block per (subdomain, 16-column chunk), 4 waves.  The block
+// k_symm: one block per (subdomain, 16-column chunk), 4 waves; a wave keeps
+// PF tiles in flight (a fixed ring of load slots, reissued on every step).  The block
 // stages X_i (n x 16) in LDS, then walks the packed upper-triangle tiles one
 // tile row I at a time; inside a row, wave w takes the tiles q = w, w + 4, ...
 // (J = I + q):
@@ -30,6 +31,15 @@ typedef double dvec4 __attribute__((ext_vector_type(4)));
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 constexpr int XS = 17;              // LDS row stride (doubles) of X, Y and a tile
+constexpr int PF = 8;               // tiles each wave has in flight (one wave per SIMD: registers to spare)
+
+// Workgroup barrier that orders LDS only: the tile loads in flight are not
+// waited for (a plain __syncthreads() would drain them at every row end).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -37,68 +47,145 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+typedef unsigned int uvec4 __attribute__((ext_vector_type(4)));
+
+// Raw buffer over `bytes` bytes from p: loads at or past the end return zero
+// without a memory access.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)min(bytes, (int64_t)INT32_MAX), 0x00020000);
+}
+
+// The tiles of one wave in order: rows I = 0, 1, ... and in row I the tiles
+// q = w, w + 4, ... (len = nt - I + ntc of them); `tile` is the index in the
+// subdomain's packed sequence, past the end once the wave has no more.
+struct TileSeq {
+    int I, q, nt, ntc, w;
+    int64_t base;
+    __device__ void norm() {
+        while (I < nt && q >= nt - I + ntc) { base += nt - I + ntc; ++I; q = w; }
+    }
+    __device__ void next() { q += 4; norm(); }
+    __device__ int64_t tile(int64_t total) const { return I < nt ? base + q : total; }
+};
+
 template <bool COARSE>
 __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
     extern __shared__ __align__(16) double sm[];
-    const BlockItem it = a.items[blockIdx.x];
-    const int c0 = 16 * (int)blockIdx.y;
+    // the column chunks of one subdomain are adjacent blocks: they run at the
+    // same time, so the second reads the tiles from the shared cache
+    const int nch = (a.ncols + 15) / 16;
+    const BlockItem it = a.items[blockIdx.x / nch];
+    const int c0 = 16 * (int)(blockIdx.x % nch);
     const int n = it.n, nt = (n + 15) / 16, npad = 16 * nt;
     const int nc = COARSE ? it.nc : 0, ntc = (nc + 15) / 16;
+    const int64_t total = (int64_t)nt * (nt + 1) / 2 + (int64_t)nt * ntc;
     double *xs = sm;                                   // npad x 16 (stride XS)
     double *ys = xs + (size_t)npad * XS;               // (npad + 16 ntc) x 16
     double *ts = ys + (size_t)(npad + 16 * ntc) * XS;  // 4 tiles of 16 x 16
     double *red = ts + 4 * 16 * XS;                    // 4 x 256
     const int tid = threadIdx.x, w = tid >> 6, L = tid & 63, li = L & 15, lk = L >> 4;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
     const int32_t *gb = a.gB + it.xoff;
-    for (int e = tid; e < 16 * npad; e += 256) {
-        const int cc = e / npad, k = e - cc * npad, col = c0 + cc;
-        xs[k * XS + cc] = (k < n && col < a.ncols) ? a.X[(int64_t)col * a.ldx + gb[k]] : 0.0;
+    // the wave's first PF tiles are requested before anything else
+    const __amdgpu_buffer_rsrc_t rs = raw_rsrc(a.tiles + it.tile * 256, total * 2048);
+    TileSeq ld{0, wu, nt, ntc, wu, 0};
+    ld.norm();
+    uvec4 fa[PF], fb[PF];
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+        const int off = (int)ld.tile(total) * 2048 + L * 16;
+        fa[d] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        fb[d] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 1024, 0, 0);
+        ld.next();
+    }
+    // X_i: 8 entries per thread at a time, all index loads before the gathers
+    for (int e0 = tid; e0 < 16 * npad; e0 += 256 * 8) {
+        int gi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + 256 * u, cc = e / npad, k = e - cc * npad;
+            gi[u] = (e < 16 * npad && k < n && c0 + cc < a.ncols) ? gb[k] : -1;
+        }
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + 256 * u, cc = e / npad;
+            v[u] = gi[u] >= 0 ? a.X[(int64_t)(c0 + cc) * a.ldx + gi[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + 256 * u, cc = e / npad, k = e - cc * npad;
+            if (e < 16 * npad) xs[k * XS + cc] = v[u];
+        }
     }
     for (int e = tid; e < (npad + 16 * ntc) * XS; e += 256) ys[e] = 0.0;
     __syncthreads();
     double *tw = ts + w * 16 * XS;
-    const double *tiles = a.tiles + it.tile * 256;
-    int64_t base = 0;                                  // first tile of row I
-    for (int I = 0; I < nt; ++I) {
-        const int len = nt - I + ntc;
-        dvec4 racc = {0.0, 0.0, 0.0, 0.0};
-        for (int q = w; q < len; q += 4) {
-            const int J = I + q;
-            const dvec2 *tp = reinterpret_cast<const dvec2 *>(tiles + (base + q) * 256);
-            const dvec2 v01 = tp[L], v23 = tp[64 + L];
-            tw[(4 * lk + 0) * XS + li] = v01.x;
-            tw[(4 * lk + 1) * XS + li] = v01.y;
-            tw[(4 * lk + 2) * XS + li] = v23.x;
-            tw[(4 * lk + 3) * XS + li] = v23.y;
-            wave_sync();
-            if (J < nt) {
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    racc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[li * XS + 4 * s + lk],
-                                                                xs[(16 * J + 4 * s + lk) * XS + li], racc, 0, 0, 0);
-            }
-            if (J > I) {
-                dvec4 cacc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    cacc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[(4 * s + lk) * XS + li],
-                                                                xs[(16 * I + 4 * s + lk) * XS + li], cacc, 0, 0, 0);
-                const int r0 = J < nt ? 16 * J : npad + 16 * (J - nt);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) ys[(r0 + 4 * r + lk) * XS + li] += cacc[r];
-            }
-            wave_sync();
-        }
+    dvec4 racc = {0.0, 0.0, 0.0, 0.0};
+    int rows_done = 0;
+    // end of row I: the waves' row parts into Y_I in wave order (every wave
+    // passes here once per row, in row order)
+    auto row_end = [&](int I) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) red[w * 256 + (4 * r + lk) * 16 + li] = racc[r];
-        __syncthreads();
+        lds_barrier();
         {
             const int row = tid >> 4, col = tid & 15;
             ys[(16 * I + row) * XS + col] += ((red[tid] + red[256 + tid]) + red[512 + tid]) + red[768 + tid];
         }
-        __syncthreads();
-        base += len;
+        lds_barrier();
+        racc = dvec4{0.0, 0.0, 0.0, 0.0};
+    };
+    TileSeq cur{0, wu, nt, ntc, wu, 0};
+    cur.norm();
+    // one tile from ring slot d, whose load is then reissued for the tile PF
+    // places later (slots are never copied, so no wait but for slot d's own load)
+    auto step = [&](uvec4 &sa, uvec4 &sb) {
+        const bool valid = cur.I < nt;                 // (wave-uniform)
+        const int I = cur.I, J = cur.I + cur.q;
+        if (valid) {
+            while (rows_done < I) row_end(rows_done++);
+            tw[(4 * lk + 0) * XS + li] = __hiloint2double(sa.y, sa.x);
+            tw[(4 * lk + 1) * XS + li] = __hiloint2double(sa.w, sa.z);
+            tw[(4 * lk + 2) * XS + li] = __hiloint2double(sb.y, sb.x);
+            tw[(4 * lk + 3) * XS + li] = __hiloint2double(sb.w, sb.z);
+        }
+        // reissued on every step (past the end: a zero read, no access), so
+        // that the count of loads in flight is the same on every path
+        const int off = (int)ld.tile(total) * 2048 + L * 16;
+        sa = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        sb = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 1024, 0, 0);
+        ld.next();
+        if (!valid) return;
+        wave_sync();
+        if (J < nt) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                racc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[li * XS + 4 * s + lk],
+                                                            xs[(16 * J + 4 * s + lk) * XS + li], racc, 0, 0, 0);
+        }
+        if (J > I) {
+            dvec4 cacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                cacc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[(4 * s + lk) * XS + li],
+                                                            xs[(16 * I + 4 * s + lk) * XS + li], cacc, 0, 0, 0);
+            const int r0 = J < nt ? 16 * J : npad + 16 * (J - nt);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ys[(r0 + 4 * r + lk) * XS + li] += cacc[r];
+        }
+        wave_sync();
+        cur.next();
+    };
+    while (cur.I < nt) {
+#pragma unroll
+        for (int d = 0; d < PF; ++d) step(fa[d], fb[d]);
     }
+    while (rows_done < nt) row_end(rows_done++);
+    // loads issued past the wave's last tile read nothing; make sure none is
+    // outstanding at exit
+#pragma unroll
+    for (int d = 0; d < PF; ++d) asm volatile("" ::"v"(fa[d]), "v"(fb[d]));
     for (int e = tid; e < 16 * n; e += 256) {
         const int cc = e / n, k = e - cc * n, col = c0 + cc;
         if (col < a.ncols) a.ypart[(int64_t)col * a.ylen + it.xoff + k] = ys[k * XS + cc];
@@ -144,7 +231,7 @@ int set_symm_smem_limit(size_t bytes) {
 
 void launch_symm(const BlockSymvArgs &a, int nsub, bool coarse, size_t smem, hipStream_t s) {
     if (nsub <= 0 || a.ncols <= 0) return;
-    const dim3 grid(nsub, (a.ncols + 15) / 16);
+    const dim3 grid(nsub * ((a.ncols + 15) / 16));
     if (coarse) hipLaunchKernelGGL(k_symm<true>, grid, dim3(256), smem, s, a);
     else hipLaunchKernelGGL(k_symm<false>, grid, dim3(256), smem, s, a);
 }
