@@ -421,7 +421,8 @@ def main():
                      "kernels": k},
         "forms": {},
         "rhs_generation_s": round(gen_s, 1),
-        "device_gb": round(g.solve_info()["device_peak_bytes"] / 1e9, 2),
+        "device_peak_gb": round(g.solve_info()["device_peak_bytes"] / 1e9, 2),
+        "device_held_gb": round(g.solve_info()["device_bytes"] / 1e9, 2),
     }
     if spec["adapt"]:
         line["adaptive"] = g.adaptive_stats()

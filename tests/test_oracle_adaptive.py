@@ -144,3 +144,37 @@ def test_three_levels_with_enriched_faces():
     assert np.abs(Minv - Minv.T).max() <= 1e-12 * np.abs(Minv).max()
     assert lam[0] >= 1 - 1e-10
     assert lam[-1] < lam0[-1]
+
+
+def test_three_level_operator_depends_only_on_the_rows_span(monkeypatch):
+    # reading of the level-2 treatment of adaptive rows: each row on the
+    # level-2 interface is a level-3 unknown of its own, so M^{-1} must not
+    # change when a row's sign is flipped or two rows of one face are
+    # rotated into each other (same span)
+    from tests.test_oracle_bddc import _problem, _rand_coef
+    ss, s2r = _problem(16, 4, _rand_coef(16, 2.5, seed=7), group=2)
+    orig = ad.adaptive_dofs
+    M0 = BDDC(ss, sub_to_subregion=s2r, adaptive=(4.0, 10))
+    new0, _ = orig(ss, weights(ss, "diag"), coarse_dofs(ss), 4.0, 10)
+    by_face = {}
+    for k, d in enumerate(new0):
+        by_face.setdefault(tuple(d["nodes"]), []).append(k)
+    pair = next(v for v in by_face.values() if len(v) >= 2)
+
+    def mixed(*a, **kw):
+        new, info = orig(*a, **kw)
+        new = [dict(d) for d in new]
+        new[0]["wts"] = -new[0]["wts"]
+        c, s_ = np.cos(0.7), np.sin(0.7)
+        i, j = pair[0], pair[1]
+        wi, wj = new[i]["wts"].copy(), new[j]["wts"].copy()
+        new[i]["wts"], new[j]["wts"] = c * wi + s_ * wj, -s_ * wi + c * wj
+        return new, info
+    monkeypatch.setattr(ad, "adaptive_dofs", mixed)
+    M1 = BDDC(ss, sub_to_subregion=s2r, adaptive=(4.0, 10))
+    assert M1.counts()["adaptive"] == M0.counts()["adaptive"] >= 2
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        r = rng.standard_normal(ss.n_gamma)
+        a, b = M0.apply(r), M1.apply(r)
+        assert np.abs(a - b).max() <= 1e-10 * np.abs(a).max()
