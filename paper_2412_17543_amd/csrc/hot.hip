@@ -484,21 +484,55 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
 // partials of the Schur product), q = sum_i R_i^T q_i, x += alpha p,
 // r -= alpha q; per-block ||r||^2; the product is kept as AP_j for recycling.
 // ---------------------------------------------------------------------------
+// Operands of nodes gb, gb + stride, ..., UN of them: q from its partial
+// products (in list order, as gather_sum adds them), x, p, r.  The pointer,
+// index and partial loads of all UN nodes are issued together (three round
+// trips for the group instead of three per node).
+constexpr int UPD_UN = 4;
+constexpr int UPD_SLOTS = 8;        // partials per node fetched in the first pass
+__device__ __forceinline__ void upd_load(const UpdArgs &a, int64_t gb, int64_t stride, double (&q)[UPD_UN],
+                                         double (&xv)[UPD_UN], double (&pv)[UPD_UN], double (&rv)[UPD_UN]) {
+    int e0[UPD_UN], e1[UPD_UN];
+#pragma unroll
+    for (int u = 0; u < UPD_UN; ++u) {
+        const int64_t g = gb + u * stride;
+        const bool ok = g < a.n;
+        e0[u] = ok ? a.q.ptr[g] : 0;
+        e1[u] = ok ? a.q.ptr[g + 1] : 0;
+        xv[u] = ok ? a.x[g] : 0.0;
+        pv[u] = ok ? a.p[g] : 0.0;
+        rv[u] = ok ? a.r[g] : 0.0;
+    }
+    int id[UPD_UN][UPD_SLOTS];
+#pragma unroll
+    for (int u = 0; u < UPD_UN; ++u)
+#pragma unroll
+        for (int m = 0; m < UPD_SLOTS; ++m) id[u][m] = e0[u] + m < e1[u] ? a.q.idx[e0[u] + m] : -1;
+#pragma unroll
+    for (int u = 0; u < UPD_UN; ++u) {
+        double v[UPD_SLOTS];
+#pragma unroll
+        for (int m = 0; m < UPD_SLOTS; ++m) v[m] = id[u][m] >= 0 ? a.q.part[id[u][m]] : 0.0;
+        double sum = 0.0;
+#pragma unroll
+        for (int m = 0; m < UPD_SLOTS; ++m)
+            if (id[u][m] >= 0) sum += v[m];
+        for (int e = e0[u] + UPD_SLOTS; e < e1[u]; ++e) sum += a.q.part[a.q.idx[e]];
+        q[u] = sum;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_update(UpdArgs a) {
     __shared__ double red[16];
     Ctl *c = a.ctl;
     if (c->done) return;
     const int j = c->j;
-    // the operands of this thread's first node do not depend on alpha: their
-    // loads are issued before the reduction
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double q0 = 0.0, x0 = 0.0, p0 = 0.0, r0 = 0.0;
-    if (g0 < a.n) {
-        q0 = gather_sum(a.q, g0);
-        x0 = a.x[g0];
-        p0 = a.p[g0];
-        r0 = a.r[g0];
-    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // the operands of this thread's first nodes do not depend on alpha: their
+    // loads are issued before the reduction
+    double q[UPD_UN], xv[UPD_UN], pv[UPD_UN], rv[UPD_UN];
+    upd_load(a, g0, stride, q, xv, pv, rv);
     const double pAp = block_sum_contig(a.dot, a.dot_n, red);
     const double alpha = (j < a.hist_cap ? a.rho_hist[j] : 0.0) / pAp;
     const bool bad = !(pAp > 0.0) || !isfinite(alpha) || j >= a.hist_cap;
@@ -511,16 +545,20 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs a) {
     if (bad) return;
     const bool rec = a.AP && c->record && j < a.cap;
     double rr = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t g = g0; g < a.n; g += stride) {
-        const bool first = g == g0;
-        const double q = first ? q0 : gather_sum(a.q, g);
-        const double xi = (first ? x0 : a.x[g]) + alpha * (first ? p0 : a.p[g]);
-        const double ri = (first ? r0 : a.r[g]) - alpha * q;
-        a.x[g] = xi;
-        a.r[g] = ri;
-        rr += ri * ri;
-        if (rec) a.AP[(int64_t)j * a.ld + g] = q;
+    for (int64_t gb = g0; gb < a.n; gb += UPD_UN * stride) {
+        if (gb != g0) upd_load(a, gb, stride, q, xv, pv, rv);
+#pragma unroll
+        for (int u = 0; u < UPD_UN; ++u) {
+            const int64_t g = gb + u * stride;
+            if (g < a.n) {
+                const double xi = xv[u] + alpha * pv[u];
+                const double ri = rv[u] - alpha * q[u];
+                a.x[g] = xi;
+                a.r[g] = ri;
+                rr += ri * ri;
+                if (rec) a.AP[(int64_t)j * a.ld + g] = q[u];
+            }
+        }
     }
     rr = block_sum(rr, red);
     if (threadIdx.x == 0) a.rr_part[blockIdx.x] = rr;
@@ -705,9 +743,17 @@ __global__ void __launch_bounds__(256) k_pupd(PupdArgs a) {
         a.p[g0] = p;
         if (rec) a.P[(int64_t)j * a.ld + g0] = p;
     }
+    // the other nodes the same way: all KM loads of a node issued at once
+    // (columns q >= k read as zero without an access), same summation order
+    const __amdgpu_buffer_rsrc_t wr = vec_rsrc(a.W, (int64_t)k * a.ld);
     for (int64_t g = g0 + stride; g < a.n; g += stride) {
+        double w[KM > 0 ? KM : 1];
+#pragma unroll
+        for (int q = 0; q < KM; ++q) w[q] = ld_rc(wr, (int64_t)q * a.ld + g);
         double p = a.z[g] + beta * a.p[g];
-        for (int q = 0; q < k; ++q) p -= a.W[(int64_t)q * a.ld + g] * mu[q];
+#pragma unroll
+        for (int q = 0; q < KM; ++q)
+            if (q < k) p -= w[q] * mu[q];
         a.p[g] = p;
         if (rec) a.P[(int64_t)j * a.ld + g] = p;
     }
@@ -1067,7 +1113,7 @@ void launch_prolong(const ProlArgs &a, int prec, int nblocks, int max_nc, hipStr
     else hipLaunchKernelGGL(k_prolong<uint16_t>, dim3(nblocks), dim3(256), smem, s, a);
 }
 
-int kmax_bucket(int k) { return k == 0 ? 0 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
+int kmax_bucket(int k) { return k == 0 ? 0 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : k <= 48 ? 48 : 64; }
 
 void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s) {
     switch (kmax) {
@@ -1075,6 +1121,7 @@ void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s) {
         case 8: hipLaunchKernelGGL(k_zasm<8>, dim3(grid), dim3(256), 0, s, a); break;
         case 16: hipLaunchKernelGGL(k_zasm<16>, dim3(grid), dim3(256), 0, s, a); break;
         case 32: hipLaunchKernelGGL(k_zasm<32>, dim3(grid), dim3(256), 0, s, a); break;
+        case 48: hipLaunchKernelGGL(k_zasm<48>, dim3(grid), dim3(256), 0, s, a); break;
         default: hipLaunchKernelGGL(k_zasm<64>, dim3(grid), dim3(256), 0, s, a); break;
     }
 }
@@ -1085,6 +1132,7 @@ void launch_pupd(const PupdArgs &a, int kmax, int grid, hipStream_t s) {
         case 8: hipLaunchKernelGGL(k_pupd<8>, dim3(grid), dim3(256), 0, s, a); break;
         case 16: hipLaunchKernelGGL(k_pupd<16>, dim3(grid), dim3(256), 0, s, a); break;
         case 32: hipLaunchKernelGGL(k_pupd<32>, dim3(grid), dim3(256), 0, s, a); break;
+        case 48: hipLaunchKernelGGL(k_pupd<48>, dim3(grid), dim3(256), 0, s, a); break;
         default: hipLaunchKernelGGL(k_pupd<64>, dim3(grid), dim3(256), 0, s, a); break;
     }
 }
@@ -1095,6 +1143,7 @@ void launch_resid(const ResidArgs &a, int kmax, int grid, hipStream_t s) {
         case 8: hipLaunchKernelGGL(k_resid<8>, dim3(grid), dim3(256), 0, s, a); break;
         case 16: hipLaunchKernelGGL(k_resid<16>, dim3(grid), dim3(256), 0, s, a); break;
         case 32: hipLaunchKernelGGL(k_resid<32>, dim3(grid), dim3(256), 0, s, a); break;
+        case 48: hipLaunchKernelGGL(k_resid<48>, dim3(grid), dim3(256), 0, s, a); break;
         default: hipLaunchKernelGGL(k_resid<64>, dim3(grid), dim3(256), 0, s, a); break;
     }
 }
@@ -1105,6 +1154,7 @@ void launch_defl_init(const DeflArgs &a, int kmax, int grid, hipStream_t s) {
         case 8: hipLaunchKernelGGL(k_defl_init<8>, dim3(grid), dim3(256), 0, s, a); break;
         case 16: hipLaunchKernelGGL(k_defl_init<16>, dim3(grid), dim3(256), 0, s, a); break;
         case 32: hipLaunchKernelGGL(k_defl_init<32>, dim3(grid), dim3(256), 0, s, a); break;
+        case 48: hipLaunchKernelGGL(k_defl_init<48>, dim3(grid), dim3(256), 0, s, a); break;
         default: hipLaunchKernelGGL(k_defl_init<64>, dim3(grid), dim3(256), 0, s, a); break;
     }
 }
@@ -1123,6 +1173,10 @@ void launch_reorth(const ReorthArgs &a, int kmax, int grid, hipStream_t s) {
         case 32:
             hipLaunchKernelGGL(k_wtr<32>, dim3(grid), dim3(256), 0, s, a);
             hipLaunchKernelGGL(k_reorth<32>, dim3(grid), dim3(256), 0, s, a);
+            break;
+        case 48:
+            hipLaunchKernelGGL(k_wtr<48>, dim3(grid), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(k_reorth<48>, dim3(grid), dim3(256), 0, s, a);
             break;
         default:
             hipLaunchKernelGGL(k_wtr<64>, dim3(grid), dim3(256), 0, s, a);
