@@ -142,6 +142,11 @@ typedef struct {
                                 Pi (Section 3.3 applied to the coarse problem); the
                                 rows become level-3 DOFs; <= 0: off (default)    */
     int32_t adapt2_max_per_face; /* at most this many rows per level-2 face (10)  */
+    int32_t adapt_lobpcg_it; /* > 0: the face pencils (both levels) by LOBPCG for
+                                the adapt_max_per_face largest pairs, at most this
+                                many iterations (the paper's limit: 15); their Ritz
+                                values are lower bounds of the pencil's eigenvalues.
+                                0 (default): every pencil solved exactly (dense)  */
 } bddc_opts;
 
 /* Fills *o with the defaults: corners+faces, diag weights, float64 local
@@ -301,6 +306,16 @@ int bddc_face_constraints(int32_t m, const double *Hs, const double *Ht, const d
                           const double *Ds, const double *Dt, int32_t floating_s, int32_t floating_t, int32_t nb,
                           const double *B, int32_t nf, const int32_t *fpos, double tau, int32_t max_rows,
                           double *lam, int32_t *n_lam, double *rows, int32_t *n_rows);
+/* bddc_face_constraints with the largest max_rows pairs found by LOBPCG (at
+ * most max_it >= 1 iterations, starting block of cosines of spread
+ * frequencies, Rayleigh-Ritz on [X, R, P] in a B-orthonormalised basis):
+ * lam (capacity max(max_rows, 1)) holds its Ritz values, descending; iters
+ * (nullable) the iterations taken.  Errors as bddc_face_constraints. */
+int bddc_face_constraints_lobpcg(int32_t m, const double *Hs, const double *Ht, const double *Ks, const double *Kt,
+                                 const double *Ds, const double *Dt, int32_t floating_s, int32_t floating_t, int32_t nb,
+                                 const double *B, int32_t nf, const int32_t *fpos, double tau, int32_t max_rows,
+                                 int32_t max_it, double *lam, int32_t *n_lam, double *rows, int32_t *n_rows,
+                                 int32_t *iters);
 
 /* Interface node ids (host int64 out[n_gamma]) in interface-vector order. */
 int bddc_interface_nodes(const bddc_ctx *ctx, int64_t *out);

@@ -34,7 +34,7 @@ class Opts(ctypes.Structure):
                 ("coarse_form", c_int32), ("product_cfg", c_int32 * 8),
                 ("reorth", c_int32), ("adapt_max_per_face", c_int32), ("adapt_tau", c_double),
                 ("local_prec_set", c_int32), ("coef_log", c_int32), ("restart_every", c_int32),
-                ("adapt2_tau", c_double), ("adapt2_max_per_face", c_int32)]
+                ("adapt2_tau", c_double), ("adapt2_max_per_face", c_int32), ("adapt_lobpcg_it", c_int32)]
 
 
 class BddcError(RuntimeError):
@@ -72,6 +72,10 @@ SIGNATURES = {
     "bddc_face_constraints": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                         c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_double,
                                         c_int32, c_void_p, POINTER(c_int32), c_void_p, POINTER(c_int32)]),
+    "bddc_face_constraints_lobpcg": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                               c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_double,
+                                               c_int32, c_int32, c_void_p, POINTER(c_int32), c_void_p,
+                                               POINTER(c_int32), POINTER(c_int32)]),
     "bddc_destroy": (None, [c_void_p]),
     "bddc_last_error": (c_char_p, []),
 }

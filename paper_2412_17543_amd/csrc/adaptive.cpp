@@ -32,7 +32,7 @@
 namespace bddc {
 
 int adaptive_faces(const Structure &st, const double *d_K, const std::vector<int64_t> &k_off, double tau,
-                   int max_per_face, int32_t *d_status, hipStream_t s, std::vector<CoarseDof> &extra,
+                   int max_per_face, int lobpcg_it, int32_t *d_status, hipStream_t s, std::vector<CoarseDof> &extra,
                    AdaptStats &stats, std::string &err) {
     const auto t0 = std::chrono::steady_clock::now();
     extra.clear();
@@ -180,7 +180,7 @@ int adaptive_faces(const Structure &st, const double *d_K, const std::vector<int
             FaceInput in{f.m, Hh[2 * fi].data(), Hh[2 * fi + 1].data(), Kh[2 * fi].data(), Kh[2 * fi + 1].data(),
                          Ds.data(), Dt.data(), floating[f.s] != 0, floating[f.t] != 0, nb, B.data(),
                          (int)f.fpos.size(), f.fpos.data()};
-            rcs[fi] = face_rows(in, tau, max_per_face, res[fi]);
+            rcs[fi] = face_rows(in, tau, max_per_face, res[fi], lobpcg_it);
         }
     };
     const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -218,8 +218,8 @@ namespace bddc {
 // Every level-2 face gets the jump-space pencil above; its rows (over the
 // face's coarse DOFs) become level-3 DOFs of the two subregions.
 int adaptive_level2(const Structure &st, const std::vector<std::vector<double>> &S2,
-                    const std::vector<char> &floating, double tau, int max_per_face, std::vector<Level3Dof> &extra,
-                    AdaptStats &stats, std::string &err) {
+                    const std::vector<char> &floating, double tau, int max_per_face, int lobpcg_it,
+                    std::vector<Level3Dof> &extra, AdaptStats &stats, std::string &err) {
     const auto t0 = std::chrono::steady_clock::now();
     extra.clear();
     stats = AdaptStats{};
@@ -308,7 +308,7 @@ int adaptive_level2(const Structure &st, const std::vector<std::vector<double>> 
             if (!side(j, ps, Hs, Ks) || !side(k, pt, Ht, Kt)) { rcs[fi] = BDDC_ESINGULAR; continue; }
             FaceInput in{m, Hs.data(), Ht.data(), Ks.data(), Kt.data(), Ds.data(), Dt.data(), floating[j] != 0,
                          floating[k] != 0, nb, B.data(), (int)fpos.size(), fpos.data()};
-            rcs[fi] = face_rows(in, tau, max_per_face, res[fi]);
+            rcs[fi] = face_rows(in, tau, max_per_face, res[fi], lobpcg_it);
         }
     };
     const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));

@@ -29,13 +29,17 @@ struct AdaptStats {
     double lam_max = 0.0, seconds = 0.0;
 };
 
-int face_rows(const FaceInput &in, double tau, int max_rows, FaceOutput &out);
+// lobpcg_it > 0: the max_rows largest pairs by LOBPCG with at most that many
+// iterations (out.lam then holds only those Ritz values), else the whole
+// pencil by a dense symmetric eigensolver.
+int face_rows(const FaceInput &in, double tau, int max_rows, FaceOutput &out, int lobpcg_it = 0,
+              int *lobpcg_iters = nullptr);
 
 // Every level-1 face of `st`: Schur complements on the device (S_i in the
 // swept local matrices d_K at k_off), the pencils on the host; the new rows
 // are returned as coarse DOFs of kind 3.
 int adaptive_faces(const Structure &st, const double *d_K, const std::vector<int64_t> &k_off, double tau,
-                   int max_per_face, int32_t *d_status, hipStream_t s, std::vector<CoarseDof> &extra,
+                   int max_per_face, int lobpcg_it, int32_t *d_status, hipStream_t s, std::vector<CoarseDof> &extra,
                    AdaptStats &stats, std::string &err);
 
 // Every level-2 face (three levels): S2 holds each subregion's Schur
@@ -43,7 +47,7 @@ int adaptive_faces(const Structure &st, const double *d_K, const std::vector<int
 // SubregionHost::L after the interior ids); floating marks subregions whose
 // subdomains all lack Dirichlet nodes.  New rows are returned as level-3 DOFs.
 int adaptive_level2(const Structure &st, const std::vector<std::vector<double>> &S2,
-                    const std::vector<char> &floating, double tau, int max_per_face, std::vector<Level3Dof> &extra,
-                    AdaptStats &stats, std::string &err);
+                    const std::vector<char> &floating, double tau, int max_per_face, int lobpcg_it,
+                    std::vector<Level3Dof> &extra, AdaptStats &stats, std::string &err);
 
 }  // namespace bddc

@@ -1212,6 +1212,7 @@ void bddc_default_opts(bddc_opts *o) {
     o->restart_every = 0;
     o->adapt2_tau = 0.0;
     o->adapt2_max_per_face = 10;
+    o->adapt_lobpcg_it = 0;
 }
 
 const char *bddc_last_error(void) { return g_err.c_str(); }
@@ -1307,8 +1308,8 @@ int adapt_level2(bddc_ctx *c, const std::vector<int32_t> &nc, const std::vector<
     }
     std::vector<Level3Dof> extra;
     std::string err;
-    if ((rc = adaptive_level2(st, S2, floating, c->opts.adapt2_tau, std::max(0, c->opts.adapt2_max_per_face), extra,
-                              c->adapt2, err)) ||
+    if ((rc = adaptive_level2(st, S2, floating, c->opts.adapt2_tau, std::max(0, c->opts.adapt2_max_per_face),
+                              c->opts.adapt_lobpcg_it, extra, c->adapt2, err)) ||
         (rc = add_level3_dofs(st, extra, err)))
         return fail(rc, err);
     return 0;
@@ -1679,6 +1680,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
             std::vector<CoarseDof> extra;
             AdaptStats as;
             if ((rc = adaptive_faces(st, c->d_K, k_off, c->opts.adapt_tau, std::max(0, c->opts.adapt_max_per_face),
+                                     c->opts.adapt_lobpcg_it,
                                      c->d_status, s, extra, as, err)))
                 return fail(rc, err);
             if ((rc = add_coarse_dofs(st, part, extra, err))) return fail(rc, err);
@@ -2711,6 +2713,31 @@ int bddc_face_constraints(int32_t m, const double *Hs, const double *Ht, const d
     FaceOutput out;
     int rc = face_rows(in, tau, max_rows, out);
     if (rc) return fail(rc, "face problem: no Cholesky factor of H_s + H_t");
+    *n_lam = (int32_t)out.lam.size();
+    for (size_t i = 0; i < out.lam.size(); ++i) lam[i] = out.lam[i];
+    *n_rows = (int32_t)out.rows.size();
+    for (size_t r = 0; r < out.rows.size(); ++r)
+        for (int q = 0; q < nf; ++q) rows[r * nf + q] = out.rows[r][q];
+    return 0;
+}
+
+int bddc_face_constraints_lobpcg(int32_t m, const double *Hs, const double *Ht, const double *Ks, const double *Kt,
+                                 const double *Ds, const double *Dt, int32_t floating_s, int32_t floating_t, int32_t nb,
+                                 const double *B, int32_t nf, const int32_t *fpos, double tau, int32_t max_rows,
+                                 int32_t max_it, double *lam, int32_t *n_lam, double *rows, int32_t *n_rows,
+                                 int32_t *iters) {
+    if (m < 0 || nb < 0 || nf < 0 || max_rows < 0 || max_it < 1 || !n_lam || !n_rows ||
+        (m > 0 && (!Hs || !Ht || !Ks || !Kt || !Ds || !Dt || !lam)) || (nb > 0 && !B) || (nf > 0 && !fpos) ||
+        (max_rows > 0 && nf > 0 && !rows))
+        return fail(BDDC_EINVAL, "bad bddc_face_constraints_lobpcg argument");
+    for (int q = 0; q < nf; ++q)
+        if (fpos[q] < 0 || fpos[q] >= m) return fail(BDDC_EINVAL, "face position out of range");
+    FaceInput in{m, Hs, Ht, Ks, Kt, Ds, Dt, floating_s != 0, floating_t != 0, nb, B, nf, fpos};
+    FaceOutput out;
+    int its = 0;
+    int rc = face_rows(in, tau, max_rows, out, max_it, &its);
+    if (rc) return fail(rc, "face problem: no Cholesky factor of H_s + H_t");
+    if (iters) *iters = its;
     *n_lam = (int32_t)out.lam.size();
     for (size_t i = 0; i < out.lam.size(); ++i) lam[i] = out.lam[i];
     *n_rows = (int32_t)out.rows.size();

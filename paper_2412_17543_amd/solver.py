@@ -39,7 +39,7 @@ class Solver:
                  init_guess="prev", max_it=1000, save_cap=256, freeze_tol=1e-5,
                  use_graph=True, autotune=True, coarse_form="auto", product_cfg=None, reorth=False,
                  adapt_tau=0.0, adapt_max_per_face=10, local_prec_set=(), coef_log=False, restart_every=0,
-                 adapt2_tau=0.0, adapt2_max_per_face=10,
+                 adapt2_tau=0.0, adapt2_max_per_face=10, adapt_lobpcg_it=0,
                  device="cuda", stream=None):
         lib = _lib.load()
         self.lib = lib
@@ -97,6 +97,7 @@ class Solver:
         o.restart_every = int(restart_every)
         o.adapt2_tau = float(adapt2_tau)
         o.adapt2_max_per_face = int(adapt2_max_per_face)
+        o.adapt_lobpcg_it = int(adapt_lobpcg_it)
         if product_cfg is not None:
             assert len(product_cfg) == 8
             for i, v in enumerate(product_cfg):

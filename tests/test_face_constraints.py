@@ -119,3 +119,72 @@ def test_argument_errors(lib):
     rc = lib.bddc_face_constraints(2, _p(z), _p(z), _p(z), _p(z), _p(z), _p(z), 0, 0, 0, None, 1, _p(fpos), 1.0, 1,
                                    _p(z), ctypes.byref(nl), _p(z), ctypes.byref(nr))
     assert rc != 0 and b"range" in lib.bddc_last_error()
+
+
+def native_face_lobpcg(lib, ss, D, dofs, face, S, tau, max_rows, max_it):
+    f = face_inputs(ss, D, dofs, face, S)
+    m, fpos = f["m"], f["fpos"]
+    lam = np.zeros(max(max_rows, 1))
+    out = np.zeros(max(max_rows, 1) * fpos.size)
+    nl, nr, it = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    rc = lib.bddc_face_constraints_lobpcg(m, _p(f["Hs"]), _p(f["Ht"]), _p(f["Ks"]), _p(f["Kt"]), _p(f["Ds"]),
+                                          _p(f["Dt"]), int(f["floating"][0]), int(f["floating"][1]), f["B"].shape[0],
+                                          _p(f["B"]), fpos.size, _p(fpos), tau, max_rows, max_it, _p(lam),
+                                          ctypes.byref(nl), _p(out), ctypes.byref(nr), ctypes.byref(it))
+    assert rc == 0, lib.bddc_last_error()
+    return lam[: nl.value], out[: nr.value * fpos.size].reshape(nr.value, fpos.size), it.value
+
+
+def _lobpcg_problem():
+    # 16^3 in eight 8^3 subdomains: about 80 shared nodes per face, so a block
+    # of 10 with its residuals and directions spans a small part of the pencil
+    s = workload.workload("c16")
+    coef = np.exp(2.0 * np.random.default_rng(5).standard_normal(s["nx"] ** 3))
+    ss = Substructuring(s["nx"], s["elem_to_sub"], coef)
+    D = weights(ss, "diag")
+    dofs = coarse_dofs(ss)
+    S = [ss.dense_S(i) for i in range(ss.n_sub)]
+    return ss, D, dofs, S
+
+
+def test_lobpcg_converged_equals_the_exact_pencil(lib):
+    # run to convergence, LOBPCG's k largest Ritz pairs are the pencil's k
+    # largest eigenpairs: the oracle's eigenvalues (exact pencil, pair space)
+    # and the same spans of new rows
+    ss, D, dofs, S = _lobpcg_problem()
+    tau, k = 2.0, 4
+    new, info = ad.adaptive_dofs(ss, D, dofs, tau, k, S_dense=S)
+    fdofs = [d for d in dofs if d["kind"] == "face"]
+    rows_total = 0
+    for i, face in enumerate(fdofs):
+        lam, rows, it = native_face_lobpcg(lib, ss, D, dofs, face, S, tau, k, 500)
+        lam_o = info[i]["lam"][:k]
+        assert it < 500
+        np.testing.assert_allclose(lam, lam_o[: lam.size], rtol=1e-8, atol=1e-9 * lam_o[0])
+        ro = np.array([d["wts"] for d in new if d["subs"] == face["subs"]]).reshape(-1, fpos_size(face))
+        assert rows.shape[0] == ro.shape[0] == info[i]["added"]
+        if rows.shape[0]:
+            sv = np.linalg.svd(rows @ ro.T, compute_uv=False)
+            np.testing.assert_allclose(sv, 1.0, atol=1e-6)
+        rows_total += rows.shape[0]
+    assert rows_total > 0
+
+
+def test_lobpcg_capped_at_15_gives_lower_bounds(lib):
+    # Rayleigh-Ritz values on any subspace are bounded by the pencil's
+    # eigenvalues (the q-th largest Ritz value <= the q-th largest eigenvalue),
+    # so with the paper's 15-iteration cap the selection can only shrink
+    ss, D, dofs, S = _lobpcg_problem()
+    tau, k = 2.0, 10
+    _, info = ad.adaptive_dofs(ss, D, dofs, tau, k, S_dense=S)
+    fdofs = [d for d in dofs if d["kind"] == "face"]
+    for i, face in enumerate(fdofs):
+        lam, rows, it = native_face_lobpcg(lib, ss, D, dofs, face, S, tau, k, 15)
+        lam_o = info[i]["lam"]
+        assert it <= 15
+        assert np.all(lam <= lam_o[: lam.size] * (1 + 1e-10) + 1e-12 * lam_o[0])
+        assert rows.shape[0] <= info[i]["added"]
+        # and close: on these faces 15 iterations put every Ritz value within
+        # 1e-2 of its eigenvalue (the largest within ~1e-3; full convergence
+        # takes 50-110 iterations)
+        np.testing.assert_allclose(lam, lam_o[: lam.size], rtol=1e-2)

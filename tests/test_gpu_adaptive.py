@@ -147,3 +147,36 @@ def test_level2_faces_with_level1_rows_match_oracle():
     assert g.adaptive_stats()["added"] == o.M.counts()["adaptive"] > 0
     _level2_counts_match(g, o)
     _precond_parity(torch, g, o)
+
+
+def test_lobpcg_face_solver():
+    # the face pencils by LOBPCG: run to convergence the preconditioner is the
+    # exact-pencil one (oracle, 1e-7 on M r); with the paper's cap of 15
+    # iterations the Ritz values are lower bounds, so no more rows are added
+    # and the solves still converge to the tolerance
+    torch = _torch()
+    from oracle.sequence import OracleSolver
+    from paper_2412_17543_amd.solver import Solver
+    s = workload.workload("c16")
+    coef = np.exp(2.0 * np.random.default_rng(5).standard_normal(16 ** 3))
+    o = OracleSolver(16, s["elem_to_sub"], coef, adaptive=(2.0, 10), R=0)
+    print("[gpu] lobpcg face solver setups", flush=True)
+    ge = Solver(16, s["elem_to_sub"], coef, adapt_tau=2.0)
+    gc = Solver(16, s["elem_to_sub"], coef, adapt_tau=2.0, adapt_lobpcg_it=500)
+    g15 = Solver(16, s["elem_to_sub"], coef, adapt_tau=2.0, adapt_lobpcg_it=15)
+    se, sc, s15 = ge.adaptive_stats(), gc.adaptive_stats(), g15.adaptive_stats()
+    print("[gpu] lobpcg stats exact %s converged %s capped %s oracle %d" % (se, sc, s15, o.M.counts()["adaptive"]),
+          flush=True)
+    assert se["added"] == sc["added"] == o.M.counts()["adaptive"] > 0
+    np.testing.assert_allclose(sc["lam_max"], se["lam_max"], rtol=1e-8)
+    assert s15["added"] <= se["added"] and s15["lam_max"] <= se["lam_max"] * (1 + 1e-10)
+    rng = np.random.default_rng(11)
+    for _ in range(2):
+        r = rng.standard_normal(o.ss.n_gamma)
+        z = gc.apply_precond(torch.tensor(r, device="cuda")).cpu().numpy()
+        assert _rel(z, o.M.apply(r)) < 1e-7
+    F = torch.tensor(workload.rhs_sequence(16, 3), device="cuda")
+    _, it_e, _ = ge.solve_sequence(F, 1e-10)
+    _, it_15, rr = g15.solve_sequence(F, 1e-10)
+    print("[gpu] lobpcg iterations exact %s capped %s" % (it_e.tolist(), it_15.tolist()), flush=True)
+    assert np.all(rr < 1e-10) and np.all(it_15 <= it_e + 2)
