@@ -552,20 +552,8 @@ void run_l2_chain(const bddc_ctx *c, const L2Args &l, hipStream_t st) {
     launch_l2_d(l, c->nsr, c->smem_l2d, st);
 }
 
-// Where one column's local results come from when they are not the
-// Neumann product's own partials (the block products of the block adjoint):
-// u_i partials (nchunk, pb layout), the coarse partials and the float64 D Phi_i.
-struct PrecSrc {
-    const double *upart;
-    const int32_t *nchunk, *pb;
-    Gather rc;
-    const void *phir;
-    int prec;
-};
-
-void run_coarse(bddc_ctx *c, const Gather *rc_in = nullptr);
-void run_prolong_assemble(bddc_ctx *c, const double *r, double *z, bool gated, bool advance, bool reduce,
-                          const PrecSrc *src = nullptr);
+void run_coarse(bddc_ctx *c);
+void run_prolong_assemble(bddc_ctx *c, const double *r, double *z, bool gated, bool advance, bool reduce);
 
 // One BDDC application on r: local constrained-Neumann products and coarse
 // residuals, the coarse problem, assembly of z with the coarse prolongation
@@ -596,10 +584,10 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
 
 // Coarse levels of one BDDC application: u_C from the coarse partials of the
 // Neumann product (eq. coarse_problem; three levels as in Section 3.2).
-void run_coarse(bddc_ctx *c, const Gather *rc_in) {
+void run_coarse(bddc_ctx *c) {
     if (c->nC > 0) {
         TScope ts(c, TK_COARSE);
-        const Gather rc = rc_in ? *rc_in : gather_of(c->opN, true);
+        const Gather rc = gather_of(c->opN, true);
         if (c->coarse_dense) {
             CoarseDenseArgs ca{};
             ca.ctl = c->d_ctl; ca.n = c->nC; ca.rc = rc; ca.r = c->d_rC;
@@ -616,21 +604,18 @@ void run_coarse(bddc_ctx *c, const Gather *rc_in) {
 // Prolongation w_i = u_i + D Phi_i u_C and assembly z = sum_i R_i^T w_i
 // (eq. averaging_subdomain_solves), with the (r^T z, (AW)^T z) partials when
 // `reduce` is set.
-void run_prolong_assemble(bddc_ctx *c, const double *r, double *z, bool gated, bool advance, bool reduce,
-                          const PrecSrc *src) {
+void run_prolong_assemble(bddc_ctx *c, const double *r, double *z, bool gated, bool advance, bool reduce) {
     {
         TScope ts(c, TK_VEC);
         ProlArgs pa{};
         pa.ctl = c->d_ctl; pa.gated = gated ? 1 : 0;
         pa.nB = c->d_nB; pa.b_off = c->d_b_off; pa.nc = c->d_nc; pa.c_off = c->d_c_off; pa.cidx = c->d_cidx;
-        pa.nchunk = src ? src->nchunk : c->opN.d_nchunk;
-        pa.pb = src ? src->pb : c->opN.d_pb;
-        pa.upart = src ? src->upart : c->opN.d_ypart;
-        pa.phir = src ? src->phir : c->d_phir; pa.phr_off = c->d_phr_off;
+        pa.nchunk = c->opN.d_nchunk; pa.pb = c->opN.d_pb; pa.upart = c->opN.d_ypart;
+        pa.phir = c->d_phir; pa.phr_off = c->d_phr_off;
         pa.uC = c->nC > 0 ? c->d_uC : nullptr;
         pa.wloc = c->d_wloc;
         pa.ch_sub = c->d_pch_sub; pa.ch_row = c->d_pch_row;
-        launch_prolong(pa, src ? src->prec : c->prec, c->n_pch, c->max_nc, c->stream);
+        launch_prolong(pa, c->prec, c->n_pch, c->max_nc, c->stream);
         ZasmArgs a{};
         a.n = c->n_gamma;
         a.w.ptr = c->d_asm_ptr; a.w.idx = c->d_asm_idx; a.w.part = c->d_wloc;
@@ -2314,6 +2299,10 @@ struct BlockWork {
     double *B = nullptr, *X = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr;
     double *yS = nullptr, *yN = nullptr, *cN = nullptr, *gp = nullptr, *gout = nullptr, *coef = nullptr;
     double *h = nullptr;             // pinned: 4 Gram results, then 6 coefficient slots
+    // per-column buffers of the coarse levels and the prolongation
+    double *rC = nullptr, *uC = nullptr, *wloc = nullptr, *vI2 = nullptr, *t2 = nullptr, *rB2 = nullptr,
+           *u2 = nullptr, *c3loc = nullptr, *u3 = nullptr, *r3 = nullptr;
+    int64_t i2len = 1, b2len = 1, c3len = 1, n3len = 1, nclen = 1;
     int64_t ylen = 0, clen = 0;
     size_t smem = 0;
     static constexpr int GSZ = 64 * 64, CSZ = 96 * 64;
@@ -2323,6 +2312,8 @@ void free_block(bddc_ctx *c, BlockWork &b) {
     dfree(c, b.itemsS); dfree(c, b.itemsN); dfree(c, b.ones);
     dfree(c, b.B); dfree(c, b.X); dfree(c, b.R); dfree(c, b.Z); dfree(c, b.P); dfree(c, b.Q);
     dfree(c, b.yS); dfree(c, b.yN); dfree(c, b.cN); dfree(c, b.gp); dfree(c, b.gout); dfree(c, b.coef);
+    dfree(c, b.rC); dfree(c, b.uC); dfree(c, b.wloc); dfree(c, b.vI2); dfree(c, b.t2); dfree(c, b.rB2);
+    dfree(c, b.u2); dfree(c, b.c3loc); dfree(c, b.u3); dfree(c, b.r3);
     if (b.h) (void)hipHostFree(b.h);
     b = BlockWork{};
 }
@@ -2352,6 +2343,21 @@ int alloc_block(bddc_ctx *c, BlockWork &b) {
         return rc;
     if (hipHostMalloc((void **)&b.h, sizeof(double) * (4 * BlockWork::GSZ + 6 * BlockWork::CSZ)) != hipSuccess)
         return fail(BDDC_ENOMEM, "hipHostMalloc failed (block adjoint)");
+    b.nclen = std::max(1, c->nC);
+    if (c->three) {
+        int64_t i2 = 0, b2 = 0, c3 = 0;
+        for (const SubregionHost &r : c->st.sr) { i2 += r.nI; b2 += r.nB; c3 += (int64_t)r.c3.size(); }
+        b.i2len = std::max<int64_t>(1, i2);
+        b.b2len = std::max<int64_t>(1, b2);
+        b.c3len = std::max<int64_t>(1, c3);
+        b.n3len = std::max(1, c->n3);
+    }
+    if ((rc = dalloc(c, &b.rC, (size_t)b.nclen * BMAX)) || (rc = dalloc(c, &b.uC, (size_t)b.nclen * BMAX)) ||
+        (rc = dalloc(c, &b.wloc, (size_t)b.ylen * BMAX)) || (rc = dalloc(c, &b.vI2, (size_t)b.i2len * BMAX)) ||
+        (rc = dalloc(c, &b.t2, (size_t)b.b2len * BMAX)) || (rc = dalloc(c, &b.rB2, (size_t)b.b2len * BMAX)) ||
+        (rc = dalloc(c, &b.u2, (size_t)b.b2len * BMAX)) || (rc = dalloc(c, &b.c3loc, (size_t)b.c3len * BMAX)) ||
+        (rc = dalloc(c, &b.u3, (size_t)b.n3len * BMAX)) || (rc = dalloc(c, &b.r3, (size_t)b.n3len * BMAX)))
+        return rc;
     // partial slots that no kernel writes (none with one chunk per subdomain) stay zero
     launch_fill((int64_t)b.ylen * BMAX, 0.0, b.yN, c->stream);
     launch_fill((int64_t)b.clen * BMAX, 0.0, b.cN, c->stream);
@@ -2407,12 +2413,50 @@ void block_M(bddc_ctx *c, BlockWork &b, const double *R, int ncols, double *Z) {
         a.ncols = ncols; a.ypart = b.yN; a.ylen = b.ylen; a.cpart = b.cN; a.clen = b.clen;
         launch_symm(a, c->n_sub, true, b.smem, c->stream);
     }
-    for (int j = 0; j < ncols; ++j) {
-        PrecSrc src{b.yN + (size_t)j * b.ylen, b.ones, c->d_b_off,
-                    Gather{c->d_casm_ptr, c->d_casm_idx, b.cN + (size_t)j * b.clen}, c->d_phirx[prec_slot(64)], 64};
-        run_coarse(c, &src.rc);
-        run_prolong_assemble(c, R + (size_t)j * c->ld, Z + (size_t)j * c->ld, false, false, false, &src);
+    // the coarse levels, the prolongation and the assembly of all columns at
+    // once: the single-vector kernels with one grid row per column
+    const Gather rc{c->d_casm_ptr, c->d_casm_idx, b.cN};
+    if (c->nC > 0) {
+        TScope ts(c, TK_COARSE);
+        if (c->coarse_dense) {
+            CoarseDenseArgs ca{};
+            ca.ctl = c->d_ctl; ca.n = c->nC; ca.rc = rc; ca.r = b.rC; ca.M = c->d_Mc; ca.ldm = c->ldm;
+            ca.sign = c->three ? 1.0 : -1.0; ca.u = b.uC;
+            ca.cs_rc = b.clen; ca.cs_r = b.nclen; ca.cs_u = b.nclen;
+            launch_coarse_dense(ca, c->stream, ncols);
+        } else {
+            L2Args l = l2_args(c, rc);
+            l.vI2 = b.vI2; l.t2 = b.t2; l.rB2 = b.rB2; l.u2 = b.u2; l.c3loc = b.c3loc; l.u3 = b.u3; l.uC = b.uC;
+            l.cs_rc = b.clen; l.cs_vI2 = b.i2len; l.cs_t2 = b.b2len; l.cs_rB2 = b.b2len; l.cs_u2 = b.b2len;
+            l.cs_c3loc = b.c3len; l.cs_u3 = b.n3len; l.cs_uC = b.nclen;
+            launch_l2_a(l, c->nsr, c->max_nL, c->stream, ncols);
+            launch_l2_b(l, c->nsr, c->max_nL, c->stream, ncols);
+            CoarseDenseArgs l3{};
+            l3.ctl = c->d_ctl; l3.n = c->n3; l3.rc = Gather{c->d_asm3_ptr, c->d_asm3_idx, b.c3loc}; l3.r = b.r3;
+            l3.M = c->d_K3inv; l3.ldm = c->ld3; l3.sign = -1.0; l3.u = b.u3;
+            l3.cs_rc = b.c3len; l3.cs_r = b.n3len; l3.cs_u = b.n3len;
+            launch_coarse_dense(l3, c->stream, ncols);
+            launch_l2_d(l, c->nsr, c->smem_l2d, c->stream, ncols);
+        }
     }
+    TScope ts(c, TK_VEC);
+    ProlArgs pa{};
+    pa.ctl = c->d_ctl; pa.gated = 0;
+    pa.nB = c->d_nB; pa.b_off = c->d_b_off; pa.nc = c->d_nc; pa.c_off = c->d_c_off; pa.cidx = c->d_cidx;
+    pa.nchunk = b.ones; pa.pb = c->d_b_off; pa.upart = b.yN;
+    pa.phir = c->d_phirx[prec_slot(64)]; pa.phr_off = c->d_phr_off;
+    pa.uC = c->nC > 0 ? b.uC : nullptr;
+    pa.wloc = b.wloc;
+    pa.ch_sub = c->d_pch_sub; pa.ch_row = c->d_pch_row;
+    pa.cs_u = b.ylen; pa.cs_uC = b.nclen; pa.cs_w = b.ylen;
+    launch_prolong(pa, 64, c->n_pch, c->max_nc, c->stream, ncols);
+    ZasmArgs za{};
+    za.n = c->n_gamma;
+    za.w = Gather{c->d_asm_ptr, c->d_asm_idx, b.wloc};
+    za.r = R; za.z = Z; za.AW = c->d_AW; za.ld = c->ld; za.part = nullptr;
+    za.ctl = c->d_ctl; za.gated = 0; za.advance = 0;
+    za.cs_w = b.ylen; za.cs_r = c->ld; za.cs_z = c->ld;
+    launch_zasm(za, c->kmax, c->vgrid, c->stream, ncols);
 }
 
 // X = G^{-1} Bm for a k x k SPD G (row-major) and k x m Bm; false if G is not SPD

@@ -588,6 +588,12 @@ __global__ void __launch_bounds__(256) k_prolong(ProlArgs a) {
     extern __shared__ double uCl[];
     constexpr int PF = 16, CF = 4;      // basis entries / partials of a row requested early
     if (a.gated && a.ctl->done) return;
+    {
+        const int64_t col = blockIdx.y;  // one column per grid row (block products)
+        a.upart += col * a.cs_u;
+        if (a.uC) a.uC += col * a.cs_uC;
+        a.wloc += col * a.cs_w;
+    }
     // 512 rows of one subdomain per block (large subdomains take several)
     const int i = a.ch_sub[blockIdx.x], r0 = a.ch_row[blockIdx.x];
     const int n = a.nB[i], C = a.nchunk[i];
@@ -644,7 +650,13 @@ __global__ void __launch_bounds__(256) k_zasm(ZasmArgs a) {
     __shared__ double res[KM + 1];
     Ctl *c = a.ctl;
     if (a.gated && c->done) return;
-    if (a.advance && blockIdx.x == 0 && threadIdx.x == 0) c->j = c->j + 1;
+    if (a.advance && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) c->j = c->j + 1;
+    {
+        const int64_t col = blockIdx.y;  // one column per grid row (block products; no partials)
+        a.w.part += col * a.cs_w;
+        a.r += col * a.cs_r;
+        a.z += col * a.cs_z;
+    }
     const int k = a.part ? c->k : 0;
     double acc[KM + 1];
 #pragma unroll
@@ -908,8 +920,16 @@ __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
 // Two levels: r_C = sum_i R_Ci^T c_i, u_C = K_C^{-1} r_C with the dense
 // inverse (stored negated by the sweep); block b computes rows [64b, 64b+64).
 // r_C assembled once from the coarse partials (fixed order).
+__device__ __forceinline__ void coarse_cols(CoarseDenseArgs &a) {
+    const int64_t col = blockIdx.y;     // one column per grid row (block products)
+    a.rc.part += col * a.cs_rc;
+    a.r += col * a.cs_r;
+    a.u += col * a.cs_u;
+}
+
 __global__ void __launch_bounds__(256) k_coarse_rhs(CoarseDenseArgs a) {
     if (a.ctl->done) return;
+    coarse_cols(a);
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q < a.n) a.r[q] = gather_sum(a.rc, q);
 }
@@ -930,6 +950,7 @@ template <int ROWS>
 __global__ void __launch_bounds__(ROWS * 64) k_coarse_dense(CoarseDenseArgs a) {
     extern __shared__ double rs[];
     if (a.ctl->done) return;
+    coarse_cols(a);
     const int n = a.n, ldm = (int)a.ldm;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int row = blockIdx.x * ROWS + w;
@@ -976,6 +997,18 @@ __global__ void __launch_bounds__(ROWS * 64) k_coarse_dense(CoarseDenseArgs a) {
     if (live && l == 0) a.u[row] = a.sign * t;
 }
 
+__device__ __forceinline__ void l2_cols(L2Args &a) {
+    const int64_t col = blockIdx.y;     // one column per grid row (block products)
+    a.rc.part += col * a.cs_rc;
+    a.vI2 += col * a.cs_vI2;
+    a.t2 += col * a.cs_t2;
+    a.rB2 += col * a.cs_rB2;
+    a.u2 += col * a.cs_u2;
+    a.c3loc += col * a.cs_c3loc;
+    a.u3 += col * a.cs_u3;
+    a.uC += col * a.cs_uC;
+}
+
 // Level 2, phase A (one block per subregion): the subregion's coarse
 // residual r_L, interior pre-solve v_I = K_II^{-1} r_I and its interface
 // coupling t = K_BI K_II^{-1} r_I (from the swept subregion matrix).
@@ -983,6 +1016,7 @@ __global__ void __launch_bounds__(256) k_l2_a(L2Args a) {
     extern __shared__ double rL[];
     __shared__ double part[4][64];
     if (a.ctl->done) return;
+    l2_cols(a);
     const int j = blockIdx.x;
     const int nL = a.nL[j], nI = a.nI2[j];
     const int loff = a.L_off[j];
@@ -1001,6 +1035,7 @@ __global__ void __launch_bounds__(256) k_l2_b(L2Args a) {
     extern __shared__ double gs[];
     __shared__ double part[4][64];
     if (a.ctl->done) return;
+    l2_cols(a);
     const int j = blockIdx.x;
     const int nB = a.nL[j] - a.nI2[j];
     const int b2 = a.B2_off[j];
@@ -1026,6 +1061,7 @@ __global__ void __launch_bounds__(256) k_l2_d(L2Args a) {
     extern __shared__ double sm[];
     __shared__ double part[4][64];
     if (a.ctl->done) return;
+    l2_cols(a);
     double *uCL = sm;                 // nL: x_I then x_G
     const int j = blockIdx.x;
     const int nL = a.nL[j], nI = a.nI2[j], nB = nL - nI;
@@ -1106,23 +1142,24 @@ void launch_update(const UpdArgs &a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_update, dim3(grid), dim3(256), 0, s, a);
 }
 
-void launch_prolong(const ProlArgs &a, int prec, int nblocks, int max_nc, hipStream_t s) {
+void launch_prolong(const ProlArgs &a, int prec, int nblocks, int max_nc, hipStream_t s, int ncols) {
     const size_t smem = (size_t)std::max(1, max_nc) * 8;
-    if (prec == 64) hipLaunchKernelGGL(k_prolong<double>, dim3(nblocks), dim3(256), smem, s, a);
-    else if (prec == 32) hipLaunchKernelGGL(k_prolong<float>, dim3(nblocks), dim3(256), smem, s, a);
-    else hipLaunchKernelGGL(k_prolong<uint16_t>, dim3(nblocks), dim3(256), smem, s, a);
+    const dim3 grid(nblocks, ncols);
+    if (prec == 64) hipLaunchKernelGGL(k_prolong<double>, grid, dim3(256), smem, s, a);
+    else if (prec == 32) hipLaunchKernelGGL(k_prolong<float>, grid, dim3(256), smem, s, a);
+    else hipLaunchKernelGGL(k_prolong<uint16_t>, grid, dim3(256), smem, s, a);
 }
 
 int kmax_bucket(int k) { return k == 0 ? 0 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : k <= 48 ? 48 : 64; }
 
-void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s) {
+void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s, int ncols) {
     switch (kmax) {
-        case 0: hipLaunchKernelGGL(k_zasm<0>, dim3(grid), dim3(256), 0, s, a); break;
-        case 8: hipLaunchKernelGGL(k_zasm<8>, dim3(grid), dim3(256), 0, s, a); break;
-        case 16: hipLaunchKernelGGL(k_zasm<16>, dim3(grid), dim3(256), 0, s, a); break;
-        case 32: hipLaunchKernelGGL(k_zasm<32>, dim3(grid), dim3(256), 0, s, a); break;
-        case 48: hipLaunchKernelGGL(k_zasm<48>, dim3(grid), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_zasm<64>, dim3(grid), dim3(256), 0, s, a); break;
+        case 0: hipLaunchKernelGGL(k_zasm<0>, dim3(grid, ncols), dim3(256), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(k_zasm<8>, dim3(grid, ncols), dim3(256), 0, s, a); break;
+        case 16: hipLaunchKernelGGL(k_zasm<16>, dim3(grid, ncols), dim3(256), 0, s, a); break;
+        case 32: hipLaunchKernelGGL(k_zasm<32>, dim3(grid, ncols), dim3(256), 0, s, a); break;
+        case 48: hipLaunchKernelGGL(k_zasm<48>, dim3(grid, ncols), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_zasm<64>, dim3(grid, ncols), dim3(256), 0, s, a); break;
     }
 }
 
@@ -1189,19 +1226,19 @@ void launch_reduce(const ReduceArgs &a, hipStream_t s) {
     if (a.ncol > 0) hipLaunchKernelGGL(k_reduce, dim3(a.ncol), dim3(256), 0, s, a);
 }
 
-void launch_coarse_dense(const CoarseDenseArgs &a, hipStream_t s) {
+void launch_coarse_dense(const CoarseDenseArgs &a, hipStream_t s, int ncols) {
     if (a.n <= 0) return;
-    hipLaunchKernelGGL(k_coarse_rhs, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_coarse_rhs, dim3((a.n + 255) / 256, ncols), dim3(256), 0, s, a);
     const size_t smem = (size_t)coarse_dense_staged((int)a.ldm) * 8;
-    if (a.n > 4096) hipLaunchKernelGGL(k_coarse_dense<8>, dim3((a.n + 7) / 8), dim3(512), smem, s, a);
-    else hipLaunchKernelGGL(k_coarse_dense<4>, dim3((a.n + 3) / 4), dim3(256), smem, s, a);
+    if (a.n > 4096) hipLaunchKernelGGL(k_coarse_dense<8>, dim3((a.n + 7) / 8, ncols), dim3(512), smem, s, a);
+    else hipLaunchKernelGGL(k_coarse_dense<4>, dim3((a.n + 3) / 4, ncols), dim3(256), smem, s, a);
 }
 
-void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
-    hipLaunchKernelGGL(k_l2_a, dim3(nsr), dim3(256), (size_t)max_nL * 8, s, a);
+void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s, int ncols) {
+    hipLaunchKernelGGL(k_l2_a, dim3(nsr, ncols), dim3(256), (size_t)max_nL * 8, s, a);
 }
-void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s) {
-    hipLaunchKernelGGL(k_l2_b, dim3(nsr), dim3(256), (size_t)max_nL * 8, s, a);
+void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s, int ncols) {
+    hipLaunchKernelGGL(k_l2_b, dim3(nsr, ncols), dim3(256), (size_t)max_nL * 8, s, a);
 }
 size_t l2_d_smem(int max_nL) { return (size_t)std::max(1, max_nL) * 8; }
 
@@ -1211,8 +1248,8 @@ int set_l2_d_smem_limit(size_t bytes) {
                ? 0 : -1;
 }
 
-void launch_l2_d(const L2Args &a, int nsr, size_t smem, hipStream_t s) {
-    hipLaunchKernelGGL(k_l2_d, dim3(nsr), dim3(256), smem, s, a);
+void launch_l2_d(const L2Args &a, int nsr, size_t smem, hipStream_t s, int ncols) {
+    hipLaunchKernelGGL(k_l2_d, dim3(nsr, ncols), dim3(256), smem, s, a);
 }
 
 }  // namespace bddc

@@ -106,6 +106,7 @@ struct ProlArgs {                   // w_i = u_i + D Phi_i u_C (eq. averaging_su
     const double *uC;               // level-1 coarse solution (nullable: no coarse space)
     double *wloc;
     const int32_t *ch_sub, *ch_row; // block b: subdomain ch_sub[b], rows ch_row[b] .. +511
+    int64_t cs_u, cs_uC, cs_w;      // several columns (blockIdx.y): strides of upart, uC, wloc
 };
 
 struct ZasmArgs {                   // z = sum_i R_i^T w_i, rho, (AW)^T z
@@ -117,6 +118,7 @@ struct ZasmArgs {                   // z = sum_i R_i^T w_i, rho, (AW)^T z
     double *part;                   // nullable: (r^T z, (AW)^T z) per block, column-major
     Ctl *ctl;
     int gated, advance;
+    int64_t cs_w, cs_r, cs_z;       // several columns (blockIdx.y; no partials): strides
 };
 
 struct PupdArgs {                   // Alg. 1, lines 14-16 (line 7 when first)
@@ -188,6 +190,7 @@ struct CoarseDenseArgs {
     const double *M; int64_t ldm;   // rows padded to an even length (16-byte aligned)
     double sign;
     double *u;
+    int64_t cs_rc, cs_r, cs_u;      // several columns (blockIdx.y): strides of rc.part, r, u
 };
 
 struct L2Args {
@@ -210,6 +213,8 @@ struct L2Args {
     const int64_t *ph_off;
     const int32_t *c3o, *n3p;
     int n3, max_nL;
+    // several columns (blockIdx.y): strides of rc.part and the per-column buffers
+    int64_t cs_rc, cs_vI2, cs_t2, cs_rB2, cs_u2, cs_c3loc, cs_u3, cs_uC;
 };
 
 
@@ -356,19 +361,19 @@ size_t symv_smem(int prec, int nw, int max_nt, int max_ntc);
 int set_symv_smem_limit(size_t bytes);
 void launch_symv(const SymvArgs &a, SymvOp op, int prec, SymvCfg cfg, size_t smem, hipStream_t s);
 void launch_update(const UpdArgs &a, int grid, hipStream_t s);
-void launch_prolong(const ProlArgs &a, int prec, int nblocks, int max_nc, hipStream_t s);
-void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s);
+void launch_prolong(const ProlArgs &a, int prec, int nblocks, int max_nc, hipStream_t s, int ncols = 1);
+void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s, int ncols = 1);
 void launch_pupd(const PupdArgs &a, int kmax, int grid, hipStream_t s);
 void launch_resid(const ResidArgs &a, int kmax, int grid, hipStream_t s);
 void launch_defl_init(const DeflArgs &a, int kmax, int grid, hipStream_t s);
 void launch_reduce(const ReduceArgs &a, hipStream_t s);
 void launch_reorth(const ReorthArgs &a, int kmax, int grid, hipStream_t s);
-void launch_coarse_dense(const CoarseDenseArgs &a, hipStream_t s);
-void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s);
-void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s);
+void launch_coarse_dense(const CoarseDenseArgs &a, hipStream_t s, int ncols = 1);
+void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s, int ncols = 1);
+void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s, int ncols = 1);
 size_t l2_d_smem(int max_nL);
 int set_l2_d_smem_limit(size_t bytes);
-void launch_l2_d(const L2Args &a, int nsr, size_t smem, hipStream_t s);
+void launch_l2_d(const L2Args &a, int nsr, size_t smem, hipStream_t s, int ncols = 1);
 // deflation-column bucket of the templated reductions (0, 8, 16, 32, 64)
 int kmax_bucket(int k);
 
