@@ -65,10 +65,13 @@ CPU_SAMPLE_NX = 32
 
 
 def kernel_hash():
-    """Hash of the sources of the product kernel (traffic figures are only
-    used while it is unchanged)."""
+    """Hash of the product kernel's source (hot.hip up to the end of k_symv,
+    devutil.h, internal.h): traffic figures are only used while it is
+    unchanged."""
     h = hashlib.sha256()
-    for f in ("hot.hip", "devutil.h", "kernels.h", "internal.h"):
+    hot = open(os.path.join(ROOT, "paper_2412_17543_amd", "csrc", "hot.hip"), "rb").read()
+    h.update(hot[: hot.index(b"// Operands of nodes gb")])
+    for f in ("devutil.h", "internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2412_17543_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

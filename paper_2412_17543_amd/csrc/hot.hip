@@ -488,8 +488,8 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
 // products (in list order, as gather_sum adds them), x, p, r.  The pointer,
 // index and partial loads of all UN nodes are issued together (three round
 // trips for the group instead of three per node).
-constexpr int UPD_UN = 4;
 constexpr int UPD_SLOTS = 8;        // partials per node fetched in the first pass
+template <int UPD_UN>
 __device__ __forceinline__ void upd_load(const UpdArgs &a, int64_t gb, int64_t stride, double (&q)[UPD_UN],
                                          double (&xv)[UPD_UN], double (&pv)[UPD_UN], double (&rv)[UPD_UN]) {
     int e0[UPD_UN], e1[UPD_UN];
@@ -522,6 +522,8 @@ __device__ __forceinline__ void upd_load(const UpdArgs &a, int64_t gb, int64_t s
     }
 }
 
+// UPD_UN nodes per pass: 4 when every thread has several nodes, else 1
+template <int UPD_UN>
 __global__ void __launch_bounds__(256) k_update(UpdArgs a) {
     __shared__ double red[16];
     Ctl *c = a.ctl;
@@ -532,7 +534,7 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs a) {
     // the operands of this thread's first nodes do not depend on alpha: their
     // loads are issued before the reduction
     double q[UPD_UN], xv[UPD_UN], pv[UPD_UN], rv[UPD_UN];
-    upd_load(a, g0, stride, q, xv, pv, rv);
+    upd_load<UPD_UN>(a, g0, stride, q, xv, pv, rv);
     const double pAp = block_sum_contig(a.dot, a.dot_n, red);
     const double alpha = (j < a.hist_cap ? a.rho_hist[j] : 0.0) / pAp;
     const bool bad = !(pAp > 0.0) || !isfinite(alpha) || j >= a.hist_cap;
@@ -546,7 +548,7 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs a) {
     const bool rec = a.AP && c->record && j < a.cap;
     double rr = 0.0;
     for (int64_t gb = g0; gb < a.n; gb += UPD_UN * stride) {
-        if (gb != g0) upd_load(a, gb, stride, q, xv, pv, rv);
+        if (gb != g0) upd_load<UPD_UN>(a, gb, stride, q, xv, pv, rv);
 #pragma unroll
         for (int u = 0; u < UPD_UN; ++u) {
             const int64_t g = gb + u * stride;
@@ -1139,7 +1141,8 @@ void launch_symv(const SymvArgs &a, SymvOp op, int prec, SymvCfg cfg, size_t sme
 }
 
 void launch_update(const UpdArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_update, dim3(grid), dim3(256), 0, s, a);
+    if (a.n > (int64_t)grid * 256 * 2) hipLaunchKernelGGL(k_update<4>, dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_update<1>, dim3(grid), dim3(256), 0, s, a);
 }
 
 void launch_prolong(const ProlArgs &a, int prec, int nblocks, int max_nc, hipStream_t s, int ncols) {
