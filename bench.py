@@ -296,6 +296,8 @@ def main():
                     help="fixed product configuration: 8 comma-separated integers (Schur then Neumann: blocks per "
                          "CU, per-subdomain split, waves, tiles in flight); a 0 first entry keeps that product tuned")
     ap.add_argument("--roofline-only", action="store_true")
+    ap.add_argument("--adapt2-tau", type=float, default=0.0,
+                    help="also enrich the level-2 faces with this threshold (0: off)")
     ap.add_argument("--study", default=None, choices=("stopping", "strategies", "rsweep", "tau"),
                     help="a parameter study instead of the benchmark line (64^3 sequence; tau: holed cube)")
     args = ap.parse_args()
@@ -335,7 +337,8 @@ def main():
     t0 = time.perf_counter()
     g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"],
                elem_keep=s["elem_keep"], R=s["R"], local_prec=head, local_prec_set=others,
-               adapt_tau=10.0 if spec["adapt"] else 0.0, adapt_max_per_face=10)
+               adapt_tau=10.0 if spec["adapt"] else 0.0, adapt_max_per_face=10,
+               adapt2_tau=args.adapt2_tau, adapt2_max_per_face=10)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print("[bench] setup %.1f s" % setup_s, file=sys.stderr, flush=True)
@@ -429,6 +432,8 @@ def main():
     }
     if spec["adapt"]:
         line["adaptive"] = g.adaptive_stats()
+    if args.adapt2_tau > 0:
+        line["adaptive_level2"] = dict(g.adaptive2_stats(), tau=args.adapt2_tau, level3=info["level3"])
     for p in order:
         f = dict(forms[p])
         f.pop("kernels")
