@@ -46,7 +46,7 @@ WORKLOADS = {
     "c192": dict(desc="Q1 Poisson 192^3 elements (7,189,057 nodes), 13,824 subdomains of 8^3, three-level BDDC "
                       "(1,728 subregions), adaptive faces tau 10 (at most 10 per face), deflated PCG B4 R=40, "
                       "200 drifting-Gaussian right-hand sides, rtol 1e-8",
-                 prec=32, step_rhs=10, adapt=True),
+                 prec=32, step_rhs=10, adapt=True, launch="graph"),
     "c64": dict(desc="Q1 Poisson 64^3 elements (274,625 nodes), 512 subdomains of 8^3, three-level BDDC "
                      "(64 subregions), deflated PCG B4 R=20, 50 drifting-Gaussian right-hand sides, rtol 1e-8",
                 prec=64, step_rhs=0, adapt=False),
@@ -296,6 +296,8 @@ def main():
                     help="fixed product configuration: 8 comma-separated integers (Schur then Neumann: blocks per "
                          "CU, per-subdomain split, waves, tiles in flight); a 0 first entry keeps that product tuned")
     ap.add_argument("--roofline-only", action="store_true")
+    ap.add_argument("--launch", default=None, choices=("queued", "graph"),
+                    help="launch form of the timed iterations (default: the workload's)")
     ap.add_argument("--adapt2-tau", type=float, default=0.0,
                     help="also enrich the level-2 faces with this threshold (0: off)")
     ap.add_argument("--study", default=None, choices=("stopping", "strategies", "rsweep", "tau"),
@@ -359,6 +361,9 @@ def main():
         pin_source = "profiles/traffic_%s.json" % args.workload
     info = g.info()
 
+    # iterations queued kernel by kernel, or replays of a captured hipGraph
+    launch = args.launch or spec.get("launch", "queued")
+    g.set_launch(launch)
     forms, Us = {}, {}
     order = [head] + [p for p in others if p == 64] + [p for p in others if p != 64]
     for p in order:
@@ -414,7 +419,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec["desc"], "form": "%s N_i and Phi_i storage, float64 elsewhere" % PREC_NAME[head],
                    "n_rhs": n_rhs, "rhs_per_step": step_rhs, "n_gamma": info["n_gamma"],
-                   "n_coarse": info["n_coarse"], "rtol": args.rtol},
+                   "n_coarse": info["n_coarse"], "rtol": args.rtol, "launch": launch},
         "iters": hf["iters"],
         "basis": hf["basis"],
         "max_true_relres": hf["max_true_relres"],
