@@ -1686,7 +1686,6 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
     std::vector<int64_t> k_off(nsub + 1, 0), s_off(nsub + 1, 0), n_off(nsub + 1, 0), kc_off(nsub + 1, 0),
         m_off(nsub + 1, 0), x_off(nsub + 1, 0), phr_off(nsub + 1, 0);
     std::vector<int32_t> gB, nodesI, cidx, pos_sub, cpos_sub;
-    int max_sad = 0, max_nloc = 0;
     for (int i = 0; i < nsub; ++i) {
         const SubHost &sh = st.sub[i];
         nI[i] = sh.nI; nB[i] = sh.nB; nc[i] = (int)sh.cidx.size();
@@ -1711,8 +1710,6 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         c->max_nc = std::max(c->max_nc, nc[i]);
         c->max_nt = std::max(c->max_nt, (sh.nB + TILE - 1) / TILE);
         c->max_ntc = std::max(c->max_ntc, (nc[i] + TILE - 1) / TILE);
-        max_sad = std::max(max_sad, sh.nB + nc[i]);
-        max_nloc = std::max(max_nloc, sh.nloc);
     }
     if (b_off[nsub] > INT32_MAX / 2) return fail(BDDC_EINVAL, "too many local interface entries");
     {   // prolongation blocks: 512 interface rows of one subdomain each
@@ -1873,7 +1870,6 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         std::vector<int64_t> K2_off(nsr + 1, 0), N2_off(nsr + 1, 0), P2_off(nsr + 1, 0), M2_off(nsr + 1, 0),
             K3_off(nsr + 1, 0);
         std::vector<double> w2all;
-        int max_sad2 = 0;
         for (int j = 0; j < nsr; ++j) {
             const SubregionHost &r = st.sr[j];
             nL[j] = (int)r.L.size(); nI2[j] = r.nI; nc3[j] = (int)r.c3.size();
@@ -1892,7 +1888,6 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
             w2all.insert(w2all.end(), r.w.begin(), r.w.end());
             for (int k = 0; k < r.nB; ++k) pos_sr.push_back(j);
             c->max_nL = std::max(c->max_nL, nL[j]);
-            max_sad2 = std::max(max_sad2, r.nB + nc3[j]);
         }
         if ((size_t)c->max_nL * 8 > 65536) return fail(BDDC_EINVAL, "a subregion has too many coarse DOFs");
         {
@@ -2159,138 +2154,15 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
     return 0;
 }
 
-}  // namespace
-
-extern "C" {
-
-int bddc_setup(const bddc_mesh *mesh, const bddc_partition *part, const double *coef, const bddc_opts *opts,
-               void *hip_stream, bddc_ctx **out) {
-    if (!mesh || !part || !coef || !out) return fail(BDDC_EINVAL, "null argument");
-    *out = nullptr;
-    bddc_ctx *c = new bddc_ctx();
-    c->stream = (hipStream_t)hip_stream;
-    if (opts) c->opts = *opts;
-    else bddc_default_opts(&c->opts);
-    const bddc_opts &o = c->opts;
-    if (o.local_prec != 64 && o.local_prec != 32 && o.local_prec != 16) { delete c; return fail(BDDC_EINVAL, "local_prec must be 64, 32 or 16"); }
-    if (o.recycle_R < 0 || o.recycle_R > RMAX) { delete c; return fail(BDDC_EINVAL, "recycle_R out of range [0, 64]"); }
-    if (o.recycle_strategy < 1 || o.recycle_strategy > 4) { delete c; return fail(BDDC_EINVAL, "recycle_strategy must be 1..4"); }
-    if (o.max_it <= 0 || o.max_it > 100000 || o.save_cap < 0 || o.save_cap > 4096) { delete c; return fail(BDDC_EINVAL, "bad max_it or save_cap"); }
-    if (o.use_graph < 0 || o.use_graph > 2) { delete c; return fail(BDDC_EINVAL, "use_graph must be 0, 1 or 2"); }
-    if (!(o.constraints & (BDDC_CORNERS | BDDC_FACES | BDDC_EDGES))) { delete c; return fail(BDDC_EINVAL, "no constraints"); }
-    if (mesh->nx <= 0 || mesh->ny <= 0 || mesh->nz <= 0) { delete c; return fail(BDDC_EINVAL, "mesh sizes must be positive"); }
-    // element coefficients on the host (copied from device memory when given
-    // there), as c_e = exp(theta_e) when they are log-coefficients
-    const int64_t n_elem = (int64_t)mesh->nx * mesh->ny * mesh->nz;
-    std::vector<double> coef_h((size_t)n_elem);
-    {
-        hipPointerAttribute_t attr{};
-        const bool on_device = hipPointerGetAttributes(&attr, coef) == hipSuccess && attr.type == hipMemoryTypeDevice;
-        (void)hipGetLastError();   // a plain host pointer may leave an error behind
-        if (on_device) {
-            if (hipMemcpy(coef_h.data(), coef, (size_t)n_elem * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
-                delete c;
-                return fail(BDDC_EHIP, "copy of the device coefficients failed");
-            }
-        } else {
-            std::memcpy(coef_h.data(), coef, (size_t)n_elem * sizeof(double));
-        }
-        if (o.coef_log)
-            for (double &v : coef_h) v = std::exp(v);
-    }
-    int rc = setup_impl(c, mesh, part, coef_h.data());
-    if (rc) {
-        std::string keep = g_err;
-        bddc_destroy(c);
-        g_err = keep;
-        return rc;
-    }
-    *out = c;
-    return 0;
-}
-
-int dpcg_solve(bddc_ctx *c, const double *rhs_seq, int32_t n_rhs, double rtol, double *x_seq, int32_t *iters,
-               double *true_relres) {
-    if (!c || (!rhs_seq && n_rhs > 0) || (!x_seq && n_rhs > 0) || n_rhs < 0 || !(rtol > 0))
-        return fail(BDDC_EINVAL, "bad dpcg_solve argument");
-    bool condensed = false;
-    c->pre_schur = false;
-    for (int k = 0; k < n_rhs; ++k) {
-        int it = 0;
-        double rr = 0.0;
-        int rc = solve_one(c, rhs_seq + (size_t)k * c->n_nodes, x_seq + (size_t)k * c->n_nodes, rtol, true, condensed,
-                           &it, &rr);
-        if (iters) iters[k] = it;
-        if (true_relres) true_relres[k] = rr;
-        if (rc) { (void)settle(c); if (c->timing) flush_timing(c); return rc; }
-        // the next right-hand side is condensed while the host solves the
-        // small recycling eigenproblem
-        condensed = k + 1 < n_rhs;
-        if (condensed) {
-            run_condense(c, rhs_seq + (size_t)(k + 1) * c->n_nodes);
-            // A x_{-1} of the next initial residual does not depend on the
-            // deflation basis.  With the previous solution as x_{-1} it is the
-            // product the true residual just formed, still in the Schur
-            // partials (nothing in between writes them); otherwise it runs
-            // here, ahead of the basis update
-            if (c->opts.init_guess == 1) {
-                launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
-                run_schur(c, c->d_x, false, false);
-            } else if (c->h_ctl->zero_rhs) {
-                run_schur(c, c->d_x, false, false);    // x was reset to 0 after that product
-            }
-            c->pre_schur = true;
-        }
-        {
-            TScope ts(c, TK_REC);
-            rc = do_recycle(c);
-        }
-        if (rc) { c->pre_schur = false; (void)settle(c); if (c->timing) flush_timing(c); return rc; }
-    }
-    c->pre_schur = false;
-    int rc = settle(c);
-    if (c->timing) flush_timing(c);
-    return rc;
-}
-
-int recycle_update(bddc_ctx *c) {
-    if (!c) return fail(BDDC_EINVAL, "null context");
-    int rc = do_recycle(c);
-    if (rc) return rc;
-    return settle(c);
-}
-
-int bddc_reset_recycle(bddc_ctx *c) {
-    if (!c) return fail(BDDC_EINVAL, "null context");
-    c->k = 0;
-    c->WAW.clear();
-    c->GWW.clear();
-    c->theta.clear();
-    c->frozen = false;
-    c->freeze_step = -1;
-    c->n_updates = 0;
-    c->update_refused = 0;
-    c->have_solve = false;
-    c->last_restarts = 0;
-    c->seg_start = 0;
-    c->pend = Pending();
-    launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
-    if (c->d_state) launch_set_state(c->d_state, 0, 1, c->stream);
-    init_null_column(c);
-    HIPCHK(hipStreamSynchronize(c->stream));
-    return 0;
-}
-
 // ------------------------------------------------------------- block adjoint
 // The adjoint systems of a sequence solved together: block deflated PCG in
 // the breakdown-free form (an orthonormal search block P whose dependent
 // directions are dropped), every direction A-orthogonal to W as in
 // Algorithm 1.  The n x s block products (Schur, Neumann with the coarse
-// rows) read every tile once for 16 columns (k_symm); the coarse levels and
-// the prolongation run column by column on the single-vector kernels; the
-// s x s algebra is on the host (three synchronisations per iteration).
-namespace {
-
+// rows) read every tile once for 16 columns (k_symm); the coarse levels, the
+// prolongation and the assembly run on the single-vector kernels with one
+// grid row per column; the s x s algebra is on the host (three
+// synchronisations per iteration).
 constexpr int BMAX = 32;            // columns of one block solve
 
 struct BlockWork {
@@ -2484,9 +2356,9 @@ std::vector<double> stack_identity(int k, const std::vector<double> &C, int r, d
     return Y;
 }
 
-}  // namespace
 
-static int block_solve(bddc_ctx *c, BlockWork &b, int s, double rtol, int *iters_out) {
+
+int block_solve(bddc_ctx *c, BlockWork &b, int s, double rtol, int *iters_out) {
     const int m = c->k;                               // deflation columns (the current basis)
     const int ld = c->ld;
     std::vector<double> WAW(c->WAW.begin(), c->WAW.end()), T, Cm;
@@ -2567,6 +2439,128 @@ static int block_solve(bddc_ctx *c, BlockWork &b, int s, double rtol, int *iters
         ++it;
     }
     *iters_out = it;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bddc_setup(const bddc_mesh *mesh, const bddc_partition *part, const double *coef, const bddc_opts *opts,
+               void *hip_stream, bddc_ctx **out) {
+    if (!mesh || !part || !coef || !out) return fail(BDDC_EINVAL, "null argument");
+    *out = nullptr;
+    bddc_ctx *c = new bddc_ctx();
+    c->stream = (hipStream_t)hip_stream;
+    if (opts) c->opts = *opts;
+    else bddc_default_opts(&c->opts);
+    const bddc_opts &o = c->opts;
+    if (o.local_prec != 64 && o.local_prec != 32 && o.local_prec != 16) { delete c; return fail(BDDC_EINVAL, "local_prec must be 64, 32 or 16"); }
+    if (o.recycle_R < 0 || o.recycle_R > RMAX) { delete c; return fail(BDDC_EINVAL, "recycle_R out of range [0, 64]"); }
+    if (o.recycle_strategy < 1 || o.recycle_strategy > 4) { delete c; return fail(BDDC_EINVAL, "recycle_strategy must be 1..4"); }
+    if (o.max_it <= 0 || o.max_it > 100000 || o.save_cap < 0 || o.save_cap > 4096) { delete c; return fail(BDDC_EINVAL, "bad max_it or save_cap"); }
+    if (o.use_graph < 0 || o.use_graph > 2) { delete c; return fail(BDDC_EINVAL, "use_graph must be 0, 1 or 2"); }
+    if (!(o.constraints & (BDDC_CORNERS | BDDC_FACES | BDDC_EDGES))) { delete c; return fail(BDDC_EINVAL, "no constraints"); }
+    if (mesh->nx <= 0 || mesh->ny <= 0 || mesh->nz <= 0) { delete c; return fail(BDDC_EINVAL, "mesh sizes must be positive"); }
+    // element coefficients on the host (copied from device memory when given
+    // there), as c_e = exp(theta_e) when they are log-coefficients
+    const int64_t n_elem = (int64_t)mesh->nx * mesh->ny * mesh->nz;
+    std::vector<double> coef_h((size_t)n_elem);
+    {
+        hipPointerAttribute_t attr{};
+        const bool on_device = hipPointerGetAttributes(&attr, coef) == hipSuccess && attr.type == hipMemoryTypeDevice;
+        (void)hipGetLastError();   // a plain host pointer may leave an error behind
+        if (on_device) {
+            if (hipMemcpy(coef_h.data(), coef, (size_t)n_elem * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+                delete c;
+                return fail(BDDC_EHIP, "copy of the device coefficients failed");
+            }
+        } else {
+            std::memcpy(coef_h.data(), coef, (size_t)n_elem * sizeof(double));
+        }
+        if (o.coef_log)
+            for (double &v : coef_h) v = std::exp(v);
+    }
+    int rc = setup_impl(c, mesh, part, coef_h.data());
+    if (rc) {
+        std::string keep = g_err;
+        bddc_destroy(c);
+        g_err = keep;
+        return rc;
+    }
+    *out = c;
+    return 0;
+}
+
+int dpcg_solve(bddc_ctx *c, const double *rhs_seq, int32_t n_rhs, double rtol, double *x_seq, int32_t *iters,
+               double *true_relres) {
+    if (!c || (!rhs_seq && n_rhs > 0) || (!x_seq && n_rhs > 0) || n_rhs < 0 || !(rtol > 0))
+        return fail(BDDC_EINVAL, "bad dpcg_solve argument");
+    bool condensed = false;
+    c->pre_schur = false;
+    for (int k = 0; k < n_rhs; ++k) {
+        int it = 0;
+        double rr = 0.0;
+        int rc = solve_one(c, rhs_seq + (size_t)k * c->n_nodes, x_seq + (size_t)k * c->n_nodes, rtol, true, condensed,
+                           &it, &rr);
+        if (iters) iters[k] = it;
+        if (true_relres) true_relres[k] = rr;
+        if (rc) { (void)settle(c); if (c->timing) flush_timing(c); return rc; }
+        // the next right-hand side is condensed while the host solves the
+        // small recycling eigenproblem
+        condensed = k + 1 < n_rhs;
+        if (condensed) {
+            run_condense(c, rhs_seq + (size_t)(k + 1) * c->n_nodes);
+            // A x_{-1} of the next initial residual does not depend on the
+            // deflation basis.  With the previous solution as x_{-1} it is the
+            // product the true residual just formed, still in the Schur
+            // partials (nothing in between writes them); otherwise it runs
+            // here, ahead of the basis update
+            if (c->opts.init_guess == 1) {
+                launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
+                run_schur(c, c->d_x, false, false);
+            } else if (c->h_ctl->zero_rhs) {
+                run_schur(c, c->d_x, false, false);    // x was reset to 0 after that product
+            }
+            c->pre_schur = true;
+        }
+        {
+            TScope ts(c, TK_REC);
+            rc = do_recycle(c);
+        }
+        if (rc) { c->pre_schur = false; (void)settle(c); if (c->timing) flush_timing(c); return rc; }
+    }
+    c->pre_schur = false;
+    int rc = settle(c);
+    if (c->timing) flush_timing(c);
+    return rc;
+}
+
+int recycle_update(bddc_ctx *c) {
+    if (!c) return fail(BDDC_EINVAL, "null context");
+    int rc = do_recycle(c);
+    if (rc) return rc;
+    return settle(c);
+}
+
+int bddc_reset_recycle(bddc_ctx *c) {
+    if (!c) return fail(BDDC_EINVAL, "null context");
+    c->k = 0;
+    c->WAW.clear();
+    c->GWW.clear();
+    c->theta.clear();
+    c->frozen = false;
+    c->freeze_step = -1;
+    c->n_updates = 0;
+    c->update_refused = 0;
+    c->have_solve = false;
+    c->last_restarts = 0;
+    c->seg_start = 0;
+    c->pend = Pending();
+    launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
+    if (c->d_state) launch_set_state(c->d_state, 0, 1, c->stream);
+    init_null_column(c);
+    HIPCHK(hipStreamSynchronize(c->stream));
     return 0;
 }
 
