@@ -180,3 +180,48 @@ def test_lobpcg_face_solver():
     _, it_15, rr = g15.solve_sequence(F, 1e-10)
     print("[gpu] lobpcg iterations exact %s capped %s" % (it_e.tolist(), it_15.tolist()), flush=True)
     assert np.all(rr < 1e-10) and np.all(it_15 <= it_e + 2)
+
+
+def test_level2_faces_pure_neumann_match_oracle():
+    # no Dirichlet node: every subregion floats, so both sides of every
+    # level-2 face pencil are singular (the constant in the null space)
+    torch = _torch()
+    from oracle.bddc import BDDC
+    from oracle.substructure import Substructuring
+    from paper_2412_17543_amd.solver import Solver
+    s = workload.workload("tiny3n")
+    print("[gpu] level-2 adaptive, pure Neumann", flush=True)
+    g = Solver(s["nx"], s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"],
+               node_dirichlet=s["node_dirichlet"], adapt2_tau=2.0)
+    ss = Substructuring(s["nx"], s["elem_to_sub"], s["coef"], dirichlet=s["node_dirichlet"].astype(bool))
+    M = BDDC(ss, sub_to_subregion=s["sub_to_subregion"], adaptive2=(2.0, 10))
+    added = sum(d["kind"] == "adaptive2" for d in M.level2.dofs3)
+    st = g.adaptive2_stats()
+    assert M.singular and st["added"] == added > 0 and g.info()["level3"] == M.level2.n3
+    np.testing.assert_allclose(st["lam_max"], max(i["lam"][0] for i in M.level2.adapt2_info), rtol=1e-8)
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        r = rng.standard_normal(ss.n_gamma)
+        r -= r.mean()                                   # a consistent residual
+        z = g.apply_precond(torch.tensor(r, device="cuda")).cpu().numpy()
+        assert _rel(z, M.apply(r)) < 1e-9
+
+
+def test_level2_faces_by_lobpcg_match_the_exact_pencils():
+    # both levels enriched with the pencils solved by LOBPCG run to
+    # convergence: the same rows (up to their span) as the exact solve
+    torch = _torch()
+    s = workload.workload("tiny3")
+    coef = np.exp(2.5 * np.random.default_rng(7).standard_normal(16 ** 3))
+    g, o = _level2_pair(s["elem_to_sub"], coef, s["sub_to_subregion"], 16, 2.0, tau1=10.0)
+    from paper_2412_17543_amd.solver import Solver
+    gl = Solver(16, s["elem_to_sub"], coef, sub_to_subregion=s["sub_to_subregion"], adapt_tau=10.0,
+                adapt2_tau=2.0, adapt_lobpcg_it=500)
+    assert gl.adaptive_stats()["added"] == g.adaptive_stats()["added"]
+    assert gl.adaptive2_stats()["added"] == g.adaptive2_stats()["added"] > 0
+    assert gl.info()["level3"] == o.M.level2.n3
+    rng = np.random.default_rng(5)
+    for _ in range(2):
+        r = rng.standard_normal(o.ss.n_gamma)
+        z = gl.apply_precond(torch.tensor(r, device="cuda")).cpu().numpy()
+        assert _rel(z, o.M.apply(r)) < 1e-7
