@@ -3,7 +3,9 @@ against oracle results stored by tests/golden/make_golden.py (which calls the
 oracle only):
 
 * 64^3, 512 subdomains, three levels, R = 20: every nodal value of the first 5
-  solutions at rtol 1e-10 (float64: iterations +-1, error <= 1e-9), and the
+  solutions at rtol 1e-10 (float64: iterations +-1, error <= 1e-9), the float32
+  and bfloat16 forms at rtol 1e-8 (error <= 1e-7, at most 10% more iterations
+  than float64), and the
   whole 50-step sequence at rtol 1e-8 in the benchmark's launch form:
   iterations +-1 at every step, the selected harmonic Ritz values of every
   update, the basis freeze (eq. harmritzstopcrit) within two updates of the
@@ -64,6 +66,26 @@ def test_c64_every_node_five_rhs():
     assert np.all(np.abs(its - gd["iters"]) <= 1)
     assert np.all(rr < 1e-10)
     assert err <= 1e-9
+
+
+@pytest.mark.parametrize("prec", [32, 16])
+def test_c64_mixed_forms_every_node(prec):
+    # FP32 / BF16 Neumann operators and coarse bases (FP64 everywhere else)
+    # at rtol 1e-8: every node of 5 solutions within 1e-7 of the oracle, at
+    # most 10% more iterations than the FP64 form at the same tolerance
+    torch = _torch()
+    gd = _gold("c64_full5")
+    s, g = _solver("c64", local_prec=prec, local_prec_set=(64,))
+    F = torch.tensor(workload.rhs_sequence(64, 5), device="cuda")
+    U, its, rr = g.solve_sequence(F, 1e-8)
+    g.set_local_prec(64)
+    g.reset_recycle()
+    _, it64, _ = g.solve_sequence(F, 1e-8)
+    err = _max_rel(U, gd["u"])
+    print("[gpu] c64 prec %d iters" % prec, its.tolist(), "f64", it64.tolist(), "max rel err %.2e" % err, flush=True)
+    assert np.all(rr < 1e-8)
+    assert its.sum() <= 1.1 * it64.sum() + 1
+    assert err <= 1e-7
 
 
 def test_c64_sequence_freezes_like_the_oracle():
