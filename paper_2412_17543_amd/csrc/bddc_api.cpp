@@ -265,10 +265,6 @@ void build_csr(int64_t ntarget, const std::vector<std::pair<int64_t, int32_t>> &
     for (auto &p : pairs) idx[fill[p.first]++] = p.second;
 }
 
-int64_t ntiles_of(int n, int nc) {
-    const int64_t nt = (n + TILE - 1) / TILE, ntc = (nc + TILE - 1) / TILE;
-    return nt * (nt + 1) / 2 + nt * ntc;
-}
 
 // slot of a storage precision in d_Nx / d_phirx (-1: not a storage precision)
 int prec_slot(int prec) { return prec == 64 ? 0 : prec == 32 ? 1 : prec == 16 ? 2 : -1; }
@@ -361,8 +357,9 @@ void flush_timing(bddc_ctx *c) {
 
 // ------------------------------------------------------------- work lists
 // Split the work of a batched product over `nblocks` blocks and lay out the
-// partial buffers (one partial vector per segment).  Balanced: the
-// concatenated tile sequence of all subdomains is cut into nblocks equal
+// partial buffers (one partial vector per segment).  Work is counted in the
+// operators' 256-entry slots (tiles, then the strip of the ragged tail rows).
+// Balanced: the concatenated slot sequence of all subdomains is cut into nblocks equal
 // ranges, each range into segments inside single subdomains (a block may
 // span subdomains).  Per subdomain: every subdomain is cut into about
 // tiles / (total / nblocks) equal segments, one block each (a block never
@@ -376,7 +373,7 @@ int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
     const std::vector<int32_t> &sizes = op.interior ? c->h_nI : c->h_nB;
     std::vector<int64_t> start(nsub + 1, 0);
     for (int i = 0; i < nsub; ++i) {
-        start[i + 1] = start[i] + ntiles_of(sizes[i], op.dev.nc ? c->h_nc[i] : 0);
+        start[i + 1] = start[i] + op_slots(sizes[i], op.dev.nc ? c->h_nc[i] : 0);
         xoff[i + 1] = xoff[i] + sizes[i];
     }
     const int64_t total = start[nsub];
@@ -1369,7 +1366,7 @@ int setup_operators(bddc_ctx *c) {
         op.dev.gB = c->d_gB;
         op.dev.nc = isN ? c->d_nc : nullptr;
         op.n_tiles = 0;
-        for (int i = 0; i < nsub; ++i) op.n_tiles += ntiles_of(c->h_nB[i], isN ? c->h_nc[i] : 0);
+        for (int i = 0; i < nsub; ++i) op.n_tiles += op_slots(c->h_nB[i], isN ? c->h_nc[i] : 0);
         op.bytes = product_bytes(c, isN, op.prec);
         op.cfg = SymvCfg{4, 2};
         op.smem = symv_smem(op.prec, op.cfg.nw, c->max_nt, isN ? c->max_ntc : 0);
@@ -1395,7 +1392,7 @@ int setup_interior(bddc_ctx *c, const std::vector<int64_t> &k_off) {
     const int nsub = c->n_sub;
     const Structure &st = c->st;
     std::vector<int64_t> ki_off(nsub + 1, 0);
-    for (int i = 0; i < nsub; ++i) ki_off[i + 1] = ki_off[i] + ntiles_of(c->h_nI[i], 0) * 256;
+    for (int i = 0; i < nsub; ++i) ki_off[i + 1] = ki_off[i] + op_slots(c->h_nI[i], 0) * 256;
     int rc;
     if ((rc = dupload(c, &c->d_ki_off, ki_off)) || (rc = dalloc_tiles(c, &c->d_KI, (size_t)std::max<int64_t>(1, ki_off[nsub]))))
         return rc;
@@ -1694,8 +1691,8 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         b_off[i + 1] = b_off[i] + sh.nB;
         c_off[i + 1] = c_off[i] + nc[i];
         k_off[i + 1] = k_off[i] + (int64_t)sh.nloc * sh.nloc;
-        s_off[i + 1] = s_off[i] + ntiles_of(sh.nB, 0) * 256;
-        n_off[i + 1] = n_off[i] + ntiles_of(sh.nB, nc[i]) * 256;
+        s_off[i + 1] = s_off[i] + op_slots(sh.nB, 0) * 256;
+        n_off[i + 1] = n_off[i] + op_slots(sh.nB, nc[i]) * 256;
         kc_off[i + 1] = kc_off[i] + (int64_t)nc[i] * nc[i];
         m_off[i + 1] = m_off[i] + (int64_t)(sh.nB + nc[i]) * (sh.nB + nc[i]);
         x_off[i + 1] = x_off[i] + (int64_t)sh.nB * nc[i];
@@ -2197,8 +2194,8 @@ int alloc_block(bddc_ctx *c, BlockWork &b) {
     for (int i = 0; i < nsub; ++i) {
         is[i] = BlockItem{ts, c->h_nB[i], 0, c->h_b_off[i], c->h_c_off[i]};
         in[i] = BlockItem{tn, c->h_nB[i], c->h_nc[i], c->h_b_off[i], c->h_c_off[i]};
-        ts += ntiles_of(c->h_nB[i], 0);
-        tn += ntiles_of(c->h_nB[i], c->h_nc[i]);
+        ts += op_slots(c->h_nB[i], 0);
+        tn += op_slots(c->h_nB[i], c->h_nc[i]);
     }
     b.ylen = std::max<int64_t>(1, (int64_t)c->h_b_off[nsub - 1] + c->h_nB[nsub - 1]);
     b.clen = std::max<int64_t>(1, (int64_t)c->h_c_off[nsub - 1] + c->h_nc[nsub - 1]);

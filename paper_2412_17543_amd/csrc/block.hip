@@ -14,7 +14,8 @@
 //   coarse tile C_{J - nt} += T^T X_I (Neumann only; T holds rows of D Phi_i)
 // After the row the waves' row parts are added into Y_I in wave order, so
 // every entry is summed in a fixed order (the product is reproducible bit by
-// bit).  A tile is loaded once (two 16-byte loads per lane, the layout of
+// bit).  The ragged tail rows (n % 16 of them, stored as a strip after the
+// tiles) follow as one more tile row.  A tile is loaded once (two 16-byte loads per lane, the layout of
 // tile_index), written to the wave's LDS slot in row-major order and read
 // back as MFMA operands: v_mfma_f64_16x16x4f64 takes A[i][k] and B[k][j] in
 // lane i (j) + 16 k and returns (i, j) in lane j + 16 (i % 4), register i / 4.
@@ -76,9 +77,9 @@ __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
     const int nch = (a.ncols + 15) / 16;
     const BlockItem it = a.items[blockIdx.x / nch];
     const int c0 = 16 * (int)(blockIdx.x % nch);
-    const int n = it.n, nt = (n + 15) / 16, npad = 16 * nt;
+    const int n = it.n, nt = n / 16, npad = 16 * ((n + 15) / 16);   // nt: full tile rows
     const int nc = COARSE ? it.nc : 0, ntc = (nc + 15) / 16;
-    const int64_t total = (int64_t)nt * (nt + 1) / 2 + (int64_t)nt * ntc;
+    const int64_t total = full_tiles(n, nc);
     double *xs = sm;                                   // npad x 16 (stride XS)
     double *ys = xs + (size_t)npad * XS;               // (npad + 16 ntc) x 16
     double *ts = ys + (size_t)(npad + 16 * ntc) * XS;  // 4 tiles of 16 x 16
@@ -186,6 +187,58 @@ __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
     // outstanding at exit
 #pragma unroll
     for (int d = 0; d < PF; ++d) asm volatile("" ::"v"(fa[d]), "v"(fb[d]));
+    // The ragged tail rows n0 + r, r < rem, stored whole as a row-major strip
+    // after the tiles: one more tile row, whose 16-column chunks are the node
+    // chunks q < nt (row part and column part, as for a tile), the corner
+    // q = nt (the full rem x rem block: row part only) and the coarse chunks
+    // (column part only).  Wave w takes the chunks q = w, w + 4, ...; a
+    // chunk's rows of Y (or C) belong to that wave alone.
+    const int rem = n % 16;
+    if (rem > 0) {
+        const int n0 = 16 * nt, m = n + nc, nq = nt + 1 + ntc;
+        const double *sp = a.tiles + (it.tile + total) * 256;
+        constexpr int G = 4;        // chunks whose entries are requested together
+        for (int q0 = wu; q0 < nq; q0 += 4 * G) {
+            double v[G][4];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int q = q0 + 4 * g;
+                const int cb = q < nt ? 16 * q : q == nt ? n0 : n + 16 * (q - nt - 1);
+                const int cv = q < nt ? 16 : q == nt ? rem : min(16, nc - 16 * (q - nt - 1));
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int r = 4 * lk + s;
+                    v[g][s] = (q < nq && r < rem && li < cv) ? sp[(int64_t)r * m + cb + li] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int q = q0 + 4 * g;
+                if (q >= nq) break;                        // (wave-uniform)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) tw[(4 * lk + s) * XS + li] = v[g][s];
+                wave_sync();
+                if (q <= nt) {          // row part: Y_rag += T X_q (the corner: X rows n0..)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        racc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[li * XS + 4 * s + lk],
+                                                                    xs[(16 * q + 4 * s + lk) * XS + li], racc, 0, 0, 0);
+                }
+                if (q != nt) {          // column part: Y_q (or C) += T^T X_rag
+                    dvec4 cacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        cacc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[(4 * s + lk) * XS + li],
+                                                                    xs[(n0 + 4 * s + lk) * XS + li], cacc, 0, 0, 0);
+                    const int r0 = q < nt ? 16 * q : npad + 16 * (q - nt - 1);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) ys[(r0 + 4 * r + lk) * XS + li] += cacc[r];
+                }
+                wave_sync();
+            }
+        }
+        row_end(nt);                // the waves' row parts into Y rows n0.. in wave order
+    }
     for (int e = tid; e < 16 * n; e += 256) {
         const int cc = e / n, k = e - cc * n, col = c0 + cc;
         if (col < a.ncols) a.ypart[(int64_t)col * a.ylen + it.xoff + k] = ys[k * XS + cc];

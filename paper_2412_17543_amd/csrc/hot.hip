@@ -316,6 +316,9 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
     __shared__ double red[16];
     constexpr int NT = NW * 64;
     constexpr int GATHER_PER_THREAD = NT >= 512 ? 1 : 512 / NT;
+    constexpr int SR = 4;           // strip rows per pass (registers)
+    // the first pass requested with the gathered values where registers allow
+    constexpr bool STRIP_EARLY = sizeof(T) == 2 || (sizeof(T) == 4 && U == 2) || (sizeof(T) == 8 && U == 4 && !OP::coarse);
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g4 = 4 * (l >> 4), cl = l & 15;
     const int wu = __builtin_amdgcn_readfirstlane(w);     // wave-uniform control flow
     // Segment records are block-uniform: read through the constant address
@@ -341,7 +344,13 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
         const int n = it.n;
         const T *tb = reinterpret_cast<const T *>(a.op.tiles) + (int64_t)it.tile * 256;
         const int32_t *gb = a.op.gB + it.x_off;
-        const int span = it.t1 - it.t0;
+        const int ncs = OP::coarse ? it.nc : 0;
+        const int ntf = n / TILE, ntc = (ncs + TILE - 1) / TILE;   // full tile rows, coarse tiles per row
+        const int ntl = full_tiles(n, ncs);                        // the tiles; the strip's slots follow
+        // the waves split the segment's tiles; the segment holding slot ntl
+        // also takes the ragged tail's strip (after its tiles)
+        const int span = max(min(it.t1, ntl) - it.t0, 0);
+        const bool strip_here = (n % TILE) != 0 && it.t0 <= ntl && ntl < it.t1;
         const int w0 = it.t0 + (int)((int64_t)span * wu / NW);
         const int w1 = it.t0 + (int)((int64_t)span * (wu + 1) / NW);
         auto stage = [&](int t) {
@@ -355,10 +364,7 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
     #pragma unroll
         for (int u = 0; u < U; ++u) fa[u].load(stage(w0), u, l);
         if (first && test_here && stop_test(a)) return;
-        const int nt = (n + TILE - 1) / TILE;
-        const int ncs = OP::coarse ? it.nc : 0;
-        const int ntc = (ncs + TILE - 1) / TILE;
-        const int npad = nt * TILE;
+        const int npad = ((n + TILE - 1) / TILE) * TILE;
         ACC *xs = reinterpret_cast<ACC *>(smem_raw);
         ACC *yw = xs + npad;
         ACC *cw = yw + NW * npad;
@@ -366,6 +372,16 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
     #pragma unroll
         for (int j = 0; j < GATHER_PER_THREAD; ++j) xv[j] = a.x[gi[j]];
         asm volatile("" ::: "memory");                        // (the gathered values before fb)
+        // the strip segment: its first SR rows at column tid, requested before
+        // the second tile stage and applied right after the staging below
+        const int rem = n % TILE, m = n + ncs, n0 = n - rem;
+        const T *sp = tb + (int64_t)ntl * 256;
+        T sv[SR];
+        if (STRIP_EARLY && strip_here) {
+    #pragma unroll
+            for (int r = 0; r < SR; ++r) sv[r] = (r < rem && tid < m) ? sp[(int64_t)r * m + tid] : (T)0;
+        }
+        asm volatile("" ::: "memory");
     #pragma unroll
         for (int u = 0; u < U; ++u) fb[u].load(stage(w0 + U), u, l);
     #pragma unroll
@@ -380,12 +396,35 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
 
         ACC *myy = yw + wu * npad;
         ACC *myc = cw + wu * ntc * TILE;
+        // Ragged tail rows n0 + r (r < n % 16), stored whole: rows r0..r0+SR-1 at
+        // column k = k0 + tid (entries v, zero past the strip).  The thread
+        // adds S[n0+r][k] x[n0+r] into y_k (node columns below n0) or
+        // c_(k-n) (coarse columns); the products S[n0+r][k] x_k of the node
+        // columns are summed over the wave and added into y_(n0+r).  Every
+        // addition goes into the thread's own wave's partials, in a fixed order.
+        auto strip_rows = [&](int k0, int r0, const T (&v)[SR]) {
+            const int k = k0 + tid;
+            const ACC xk = k < n ? xs[k] : (ACC)0;
+            ACC t = (ACC)0;
+    #pragma unroll
+            for (int r = 0; r < SR; ++r) {
+                if (r0 + r < rem) {
+                    const ACC vr = (ACC)to_d(v[r]);
+                    t += vr * xs[n0 + r0 + r];
+                    const ACC sr = wave_sum(vr * xk);
+                    if (l == 0) myy[n0 + r0 + r] += sr;
+                }
+            }
+            if (k < n0) myy[k] += t;
+            else if (k >= n && k < m) myc[k - n] += t;
+        };
+        if (STRIP_EARLY && strip_here) strip_rows(0, 0, sv);
         if (w0 >= w1) {
     #pragma unroll
             for (int u = 0; u < U; ++u) { fa[u].settle(); fb[u].settle(); }
         } else {
             int I = 0, rs = 0;
-            while (rs + (nt - I + ntc) <= w0) { rs += nt - I + ntc; ++I; }
+            while (rs + (ntf - I + ntc) <= w0) { rs += ntf - I + ntc; ++I; }
             int J = I + (w0 - rs);
             ACC xi[4], ra[4];
     #pragma unroll
@@ -400,23 +439,23 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
                     ACC v[4];
                     f[u].get(v);
                     // no direct part in coarse columns, nor past the range
-                    const ACC xj = (live && J < nt) ? xs[J * TILE + cl] : (ACC)0;
+                    const ACC xj = (live && J < ntf) ? xs[J * TILE + cl] : (ACC)0;
     #pragma unroll
                     for (int q = 0; q < 4; ++q) ra[q] += v[q] * xj;
                     const ACC s = col_sum4(v[0] * xi[0] + v[1] * xi[1] + v[2] * xi[2] + v[3] * xi[3]);
                     if (!live) continue;
                     if (J != I && l < 16) {
-                        ACC *dst = (J < nt) ? (myy + J * TILE) : (myc + (J - nt) * TILE);
+                        ACC *dst = (J < ntf) ? (myy + J * TILE) : (myc + (J - ntf) * TILE);
                         dst[cl] += s;
                     }
-                    if (++J == nt + ntc) {
+                    if (++J == ntf + ntc) {
                         const ACC m = row_sum4(ra, cl);
                         if ((cl & 3) == 0) myy[I * TILE + g4 + (cl >> 2)] += m;
     #pragma unroll
                         for (int q = 0; q < 4; ++q) ra[q] = (ACC)0;
                         ++I;
                         J = I;
-                        if (I < nt) {
+                        if (I < ntf) {
     #pragma unroll
                             for (int q = 0; q < 4; ++q) xi[q] = xs[I * TILE + g4 + q];
                         }
@@ -447,6 +486,18 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
             if (J != I) {   // flush a partly processed tile row
                 const ACC m = row_sum4(ra, cl);
                 if ((cl & 3) == 0) myy[I * TILE + g4 + (cl >> 2)] += m;
+            }
+        }
+        if (strip_here) {   // the rest of the strip (more than SR rows, or columns past NT)
+            for (int k0 = 0; k0 < m; k0 += NT) {
+                for (int r0 = 0; r0 < rem; r0 += SR) {
+                    if (STRIP_EARLY && k0 == 0 && r0 == 0) continue;
+                    T v[SR];
+    #pragma unroll
+                    for (int r = 0; r < SR; ++r)
+                        v[r] = (r0 + r < rem && k0 + tid < m) ? sp[(int64_t)(r0 + r) * m + k0 + tid] : (T)0;
+                    strip_rows(k0, r0, v);
+                }
             }
         }
         __syncthreads();

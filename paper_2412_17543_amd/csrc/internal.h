@@ -12,6 +12,22 @@
 namespace bddc {
 
 constexpr int TILE = 16;          // symmetric operators are stored as 16x16 tiles
+
+// Packed symmetric operator of n rows (+ nc coarse-basis columns) in slots of
+// 256 entries: the full 16-row tile rows I < n / 16, each the tiles
+// (I, I..nt-1) of the upper triangle then (I, nt..nt+ntc-1) of the coarse
+// block (nt = n / 16, ntc = ceil(nc / 16)); then the last n % 16 rows (the
+// ragged tail) as a row-major strip of n + nc entries per row (the full rows:
+// node columns, then coarse columns), padded to whole slots.  Tiles past the
+// triangle's last full row would be mostly zero padding.
+__host__ __device__ inline int full_tiles(int n, int nc) {
+    const int nt = n / TILE, ntc = (nc + TILE - 1) / TILE;
+    return nt * (nt + 1) / 2 + nt * ntc;
+}
+__host__ __device__ inline int64_t strip_len(int n, int nc) { return (int64_t)(n % TILE) * (n + nc); }
+__host__ __device__ inline int64_t op_slots(int n, int nc) {
+    return full_tiles(n, nc) + (strip_len(n, nc) + 255) / 256;
+}
 // zeroed bytes after every packed tile array: the product kernel's prefetch
 // of up to 8 tiles past a work range stays inside the allocation
 constexpr int64_t TILE_TAIL_BYTES = 8 * 256 * 8;

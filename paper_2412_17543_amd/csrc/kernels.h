@@ -40,11 +40,12 @@ struct SymvItem {
     int32_t next, pad0, pad1, pad2;
 };
 
-// A batch of packed symmetric operators.  Tile row I of subdomain i holds the
-// tiles (I, I..nt-1) of the upper triangle and, when `nc` is set, ntc extra
-// tiles of the coarse basis rows (I, nt..nt+ntc-1).  The concatenated tile
-// sequence of all subdomains is cut into n_blocks ranges, one per block, and
-// each range into segments inside single subdomains.  Segment c of
+// A batch of packed symmetric operators in the slot layout of full_tiles and
+// strip_len: the tiles of the full tile rows (with the coarse-basis tiles
+// when `nc` is set), then the strip of the ragged tail rows.  The
+// concatenated slot sequence of all subdomains is cut into n_blocks ranges,
+// one per block, and each range into segments inside single subdomains; the
+// segment holding a subdomain's first strip slot also applies the strip.  Segment c of
 // subdomain i writes its partial products to ypart[pb[i] + c * nB[i] + k]
 // and, with a coarse basis, cpart[cb[i] + c * nc[i] + q].
 struct OpDev {

@@ -106,11 +106,13 @@ __global__ void __launch_bounds__(256) k_build_saddle(const SaddleDesc *descs) {
 
 
 // ---------------------------------------------------------------------------
-// setup: pack a symmetric n x n block (+ an n x nc block) into 16x16 tiles
-// (element order of tile_index).  Tile row I holds tiles (I, I..nt-1) then
-// (I, nt..nt+ntc-1).  Value = sign * src[i][j] * D[i] * D[j] (coarse-basis
-// block: sign * phi[i][q] * D[i]); with phr >= 0 the coarse-basis block is
-// also written row-major (n rows of nc values) for the prolongation.
+// setup: pack a symmetric n x n block (+ an n x nc block) in the slot layout
+// of full_tiles / strip_len: 16x16 tiles (element order of tile_index) of the
+// full tile rows, tile row I holding (I, I..nt-1) then (I, nt..nt+ntc-1);
+// then the ragged tail rows, row-major over the n node and nc coarse
+// columns.  Value = sign * src[i][j] * D[i] * D[j] (coarse-basis block:
+// sign * phi[i][q] * D[i]); with phr >= 0 the coarse-basis block is also
+// written row-major (n rows of nc values) for the prolongation.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void store_conv(double *p, double v) { *p = v; }
 __device__ __forceinline__ void store_conv(float *p, double v) { *p = (float)v; }
@@ -125,7 +127,19 @@ __device__ __forceinline__ void store_conv(uint16_t *p, double v) {
 template <typename T>
 __global__ void __launch_bounds__(256) k_pack(const PackDesc *descs, T *dst, T *phir) {
     const PackDesc d = descs[blockIdx.x];
-    const int nt = (d.n + TILE - 1) / TILE, ntc = (d.nc + TILE - 1) / TILE;
+    const int nt = d.n / TILE, ntc = (d.nc + TILE - 1) / TILE, n0 = nt * TILE;
+    // value of row gi (< n) at node column gj (< n) or coarse column n + gq
+    auto node = [&](int gi, int gj) {
+        double v = d.sign * d.src[(size_t)gi * d.ld + gj];
+        if (d.D) v *= d.D[gi] * d.D[gj];
+        return v;
+    };
+    auto coarse = [&](int gi, int gq) {
+        double v = d.sign * d.phi[(size_t)gi * d.ldphi + gq];
+        if (d.D) v *= d.D[gi];
+        if (d.phr >= 0) store_conv(phir + d.phr + (int64_t)gi * d.nc + gq, v);
+        return v;
+    };
     int64_t base = 0;
     for (int I = 0; I < nt; ++I) {
         const int nrow = nt - I + ntc;
@@ -135,22 +149,20 @@ __global__ void __launch_bounds__(256) k_pack(const PackDesc *descs, T *dst, T *
             const int gi = I * TILE + r;
             double v = 0.0;
             if (J < nt) {
-                const int gj = J * TILE + c;
-                if (gi < d.n && gj < d.n) {
-                    v = d.sign * d.src[(size_t)gi * d.ld + gj];
-                    if (d.D) v *= d.D[gi] * d.D[gj];
-                }
+                v = node(gi, J * TILE + c);
             } else {
                 const int gq = (J - nt) * TILE + c;
-                if (gi < d.n && gq < d.nc) {
-                    v = d.sign * d.phi[(size_t)gi * d.ldphi + gq];
-                    if (d.D) v *= d.D[gi];
-                    if (d.phr >= 0) store_conv(phir + d.phr + (int64_t)gi * d.nc + gq, v);
-                }
+                if (gq < d.nc) v = coarse(gi, gq);
             }
             store_conv(dst + d.dst + (base + q) * 256 + tile_index(r, c, (int)sizeof(T)), v);
         }
         base += nrow;
+    }
+    const int m = d.n + d.nc;
+    T *sp = dst + d.dst + base * 256;
+    for (int64_t e = threadIdx.x; e < strip_len(d.n, d.nc); e += blockDim.x) {
+        const int r = (int)(e / m), k = (int)(e - (int64_t)r * m);
+        store_conv(sp + e, k < d.n ? node(n0 + r, k) : coarse(n0 + r, k - d.n));
     }
 }
 
