@@ -402,7 +402,8 @@ int bddc_time_kernels(bddc_ctx *ctx, int32_t reps, double *out, int32_t n);
 /*
  * bddc_solve_info -- recycling and memory state, host int64 out[n] (n <= 10):
  *  [0] recycling steps run (one per solve until frozen)  [1] of them refused
- *  (the new W^T A W not positive definite: the old basis kept)
+ *  (the new W^T A W not positive definite: the new basis, computed over the
+ *  old one, is dropped and the next update starts from the stored directions)
  *  [2] basis frozen (eq. harmritzstopcrit, 0/1)  [3] the update at which it
  *  froze, counted from 1 like the solves (-1: not frozen)  [4] residual
  *  replacements in the last solve  [5] first search direction of the run the

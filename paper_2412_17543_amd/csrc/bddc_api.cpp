@@ -140,7 +140,7 @@ struct bddc_ctx {
     // column, and the recycled columns follow it
     int nullc = 0;
     int64_t ld = 0;
-    double *d_W = nullptr, *d_AW = nullptr, *d_Wn = nullptr, *d_AWn = nullptr, *d_P = nullptr, *d_AP = nullptr;
+    double *d_W = nullptr, *d_AW = nullptr, *d_P = nullptr, *d_AP = nullptr;
     double *d_WAWinv = nullptr, *d_Y = nullptr, *d_WAWnew = nullptr, *d_WAWsym = nullptr, *d_invnew = nullptr;
     // re-orthogonalisation: (W^T W)^{-1} of the basis in use and of the new one,
     // W^T r partials, a scratch state for the Cholesky of W^T W
@@ -843,7 +843,13 @@ void resolve_pending(bddc_ctx *c) {
             c->freeze_step = c->n_updates;
         }
     } else {
-        c->update_refused++;   // W^T A W not positive definite: the old basis stays
+        // W^T A W of the new basis not positive definite: it was written over
+        // the old one, so the recycled columns are dropped
+        c->update_refused++;
+        c->k = c->nullc;
+        c->WAW.assign(c->nullc, 1.0);
+        c->GWW.clear();
+        c->theta.clear();
     }
 }
 
@@ -949,10 +955,12 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     return 0;
 }
 
-// W_new = [W, P] Y, AW_new = [AW, AP] Y, then on the device: Gram W_new^T A W_new,
-// Cholesky and inverse, and the commit of W, AW and the inverse when it is
-// positive definite.  Nothing here waits for the device; the outcome is
-// adopted at the next synchronisation (resolve_pending).
+// W <- [W, P] Y, AW <- [AW, AP] Y in place (each row of the product reads
+// only the same row of its operands, and every wave reads its rows before
+// writing them), then on the device: Gram W^T A W of the new basis, Cholesky
+// and inverse, and the commit of the inverse when it is positive definite
+// (else the basis is dropped).  Nothing here waits for the device; the
+// outcome is adopted at the next synchronisation (resolve_pending).
 int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol, const std::vector<double> &gww,
                 const std::vector<double> &theta, bool freeze, int j0) {
     // (Y: m = recycled columns + stored directions rows, ncol recycled columns)
@@ -968,13 +976,13 @@ int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol, cons
     GemmArgs g{};
     g.n = c->n_gamma; g.ld = c->ld; g.Y = c->d_Y; g.ncol = ncol; g.ldy = ldy;
     g.k1 = k1; g.k2 = l;
-    g.V1[0] = c->d_W + o0; g.V2[0] = c->d_P + (size_t)j0 * c->ld; g.out[0] = c->d_Wn + o0;
-    g.V1[1] = c->d_AW + o0; g.V2[1] = c->d_AP + (size_t)j0 * c->ld; g.out[1] = c->d_AWn + o0;
+    g.V1[0] = c->d_W + o0; g.V2[0] = c->d_P + (size_t)j0 * c->ld; g.out[0] = c->d_W + o0;
+    g.V1[1] = c->d_AW + o0; g.V2[1] = c->d_AP + (size_t)j0 * c->ld; g.out[1] = c->d_AW + o0;
     launch_recycle_gemm(g, c->stream);
     ncol += nc0;                    // the Gram product, Cholesky and commit cover all columns
     const int nb = c->gram_nb;
     GramArgs gr{};
-    gr.n = c->n_gamma; gr.k = ncol; gr.ld = c->ld; gr.X = c->d_Wn; gr.Y = c->d_AWn; gr.part = c->d_gp;
+    gr.n = c->n_gamma; gr.k = ncol; gr.ld = c->ld; gr.X = c->d_W; gr.Y = c->d_AW; gr.part = c->d_gp;
     launch_gram(gr, nb, c->stream);
     ReduceArgs r{};
     r.part = c->d_gp; r.n = nb; r.ncol = ncol * ncol; r.out = c->d_WAWnew;
@@ -984,7 +992,7 @@ int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol, cons
     launch_chol_inv(ch, c->stream);
     if (c->opts.reorth) {   // (W^T W)^{-1} of the new basis
         GramArgs gw{};
-        gw.n = c->n_gamma; gw.k = ncol; gw.ld = c->ld; gw.X = c->d_Wn; gw.Y = c->d_Wn; gw.part = c->d_gp;
+        gw.n = c->n_gamma; gw.k = ncol; gw.ld = c->ld; gw.X = c->d_W; gw.Y = c->d_W; gw.part = c->d_gp;
         launch_gram(gw, nb, c->stream);
         ReduceArgs rw{};
         rw.part = c->d_gp; rw.n = nb; rw.ncol = ncol * ncol; rw.out = c->d_WWnew;
@@ -994,9 +1002,8 @@ int apply_basis(bddc_ctx *c, const std::vector<double> &Y, int m, int ncol, cons
         launch_chol_inv(cw, c->stream);
     }
     CommitArgs cm{};
-    cm.n = (int64_t)ncol * c->ld; cm.ncol = ncol;
-    cm.Wn = c->d_Wn; cm.AWn = c->d_AWn; cm.inv_new = c->d_invnew;
-    cm.W = c->d_W; cm.AW = c->d_AW; cm.inv = c->d_WAWinv; cm.state = c->d_state;
+    cm.ncol = ncol; cm.nullc = nc0;
+    cm.inv_new = c->d_invnew; cm.inv = c->d_WAWinv; cm.state = c->d_state;
     if (c->opts.reorth) { cm.ww_new = c->d_WWinvnew; cm.ww = c->d_WWinv; }
     launch_commit(cm, c->stream);
     c->pend.active = true;
@@ -1210,7 +1217,7 @@ namespace {
 void init_null_column(bddc_ctx *c) {
     if (!c->nullc) return;
     const double v = 1.0 / std::sqrt((double)c->n_gamma);
-    for (double *w : {c->d_W, c->d_AW, c->d_Wn, c->d_AWn})
+    for (double *w : {c->d_W, c->d_AW})
         if (w) launch_fill(c->n_gamma, v, w, c->stream);
     launch_fill(1, 1.0, c->d_WAWinv, c->stream);
     launch_fill(1, 1.0, c->d_WWinv, c->stream);
@@ -2095,8 +2102,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
             (rc = dalloc(c, &c->d_Y, (size_t)ymax)))
             return rc;
         HIPCHK(hipHostMalloc((void **)&c->h_Y, sizeof(double) * (size_t)ymax, hipHostMallocDefault));
-        if (c->R > 0 && ((rc = dalloc(c, &c->d_Wn, cols * ng)) || (rc = dalloc(c, &c->d_AWn, cols * ng)) ||
-                         (rc = dalloc(c, &c->d_P, (size_t)std::max(1, c->save_cap) * ng)) ||
+        if (c->R > 0 && ((rc = dalloc(c, &c->d_P, (size_t)std::max(1, c->save_cap) * ng)) ||
                          (rc = dalloc(c, &c->d_AP, (size_t)std::max(1, c->save_cap) * ng))))
             return rc;
     }

@@ -273,11 +273,11 @@ struct CholArgs {                   // new W^T A W: Cholesky, inverse, commit fl
     RecState *state;
 };
 
-struct CommitArgs {                 // W, AW <- Wn, AWn and the inverse, when state->ok
-    int64_t n;                      // ncol * ld elements
+struct CommitArgs {                 // the new basis's inverse when state->ok, else the basis dropped
     int ncol;
-    const double *Wn, *AWn, *inv_new;
-    double *W, *AW, *inv;
+    int nullc;                      // leading null-space columns kept on a drop (0 or 1)
+    const double *inv_new;
+    double *inv;
     const double *ww_new;           // nullable: (W^T W)^{-1} of the new basis
     double *ww;
     RecState *state;

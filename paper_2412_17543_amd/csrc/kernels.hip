@@ -539,19 +539,23 @@ __global__ void __launch_bounds__(64) k_chol_inv(CholArgs a) {
     if (t == 0) a.state->ok = 1;
 }
 
+// The new basis was written over W and A W; its (W^T A W)^{-1} (and
+// (W^T W)^{-1}) replace the old ones when the Cholesky succeeded.  Otherwise
+// the basis is dropped: the size returns to the null-space columns, whose
+// block of both inverses is 1.
 __global__ void __launch_bounds__(256) k_commit(CommitArgs a) {
-    if (!a.state->ok) return;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
-        a.W[g] = a.Wn[g];
-        a.AW[g] = a.AWn[g];
-    }
-    if (blockIdx.x == 0) {
+    if (a.state->ok) {
         for (int e = threadIdx.x; e < a.ncol * a.ncol; e += blockDim.x) {
             a.inv[e] = a.inv_new[e];
             if (a.ww_new) a.ww[e] = a.ww_new[e];
         }
         if (threadIdx.x == 0) a.state->k = a.ncol;
+    } else if (threadIdx.x == 0) {
+        a.state->k = a.nullc;
+        if (a.nullc) {
+            a.inv[0] = 1.0;
+            if (a.ww) a.ww[0] = 1.0;
+        }
     }
 }
 
@@ -666,8 +670,7 @@ void launch_chol_inv(const CholArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), 0, s, a);
 }
 void launch_commit(const CommitArgs &a, hipStream_t s) {
-    const int64_t nb = std::min<int64_t>(1024, std::max<int64_t>(1, (a.n + 255) / 256));
-    hipLaunchKernelGGL(k_commit, dim3((unsigned)nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(256), 0, s, a);
 }
 
 }  // namespace bddc
