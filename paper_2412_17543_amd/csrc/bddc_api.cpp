@@ -101,6 +101,15 @@ struct bddc_ctx {
     int prec_built = 0;                          // bit mask of those: 1 float64, 2 float32, 4 bfloat16
     int32_t *d_asm_ptr = nullptr, *d_asm_idx = nullptr, *d_casm_ptr = nullptr, *d_casm_idx = nullptr;
     int max_nI = 0, max_nB = 0, max_nc = 0, max_nt = 0, max_ntc = 0, max_ntI = 0;
+    // condensation of up to CBLK right-hand sides per pass over the interior
+    // tiles (k_symm): per-column partials, condensed b and ||b||^2 partials
+    int cblk_state = 0;             // 0 not set up, 1 ready, -1 unavailable (LDS)
+    size_t cblk_smem = 0;
+    int64_t cblk_ylen = 0;
+    BlockItem *d_cblk_items = nullptr;
+    int32_t *d_cblk_ones = nullptr;
+    double *d_cblk_y = nullptr, *d_cblk_b = nullptr, *d_cblk_bbp = nullptr;
+    double *d_cblk_x = nullptr, *d_cblk_t = nullptr;   // interface solutions, recovery right-hand sides
     std::vector<int32_t> h_nB, h_nI, h_nc, h_b_off, h_c_off, h_pos_sub, h_cpos_sub;
     std::vector<int32_t> h_asm_ptr, h_asm_idx, h_casm_ptr, h_casm_idx;
     OpHost opS, opN, opI;           // Schur, Neumann, interior inverse K_II^{-1}
@@ -801,6 +810,101 @@ void run_condense(bddc_ctx *c, const double *F) {
     launch_cond_asm(b, c->vgrid, c->stream);
 }
 
+constexpr int CBLK = 16;            // right-hand sides condensed per pass over the interior tiles
+
+// The buffers of the block condensation, allocated on first use; unavailable
+// when an interior is too large for the block product's LDS staging.
+int cblk_setup(bddc_ctx *c) {
+    if (c->cblk_state) return 0;
+    const int nsub = c->n_sub;
+    c->cblk_smem = symm_smem_bytes(c->max_nI, 0);
+    if (c->cblk_smem > 160 * 1024) { c->cblk_state = -1; return 0; }
+    std::vector<BlockItem> items(nsub);
+    std::vector<int32_t> ones(nsub, 1);
+    int64_t slot = 0, y = 0;
+    for (int i = 0; i < nsub; ++i) {
+        items[i] = BlockItem{slot, c->h_nI[i], 0, (int32_t)y, 0};
+        slot += op_slots(c->h_nI[i], 0);
+        y += c->h_nI[i];
+    }
+    if (y > INT32_MAX) { c->cblk_state = -1; return 0; }
+    c->cblk_ylen = std::max<int64_t>(1, y);
+    int rc;
+    if ((rc = dupload(c, &c->d_cblk_items, items)) || (rc = dupload(c, &c->d_cblk_ones, ones)) ||
+        (rc = dalloc(c, &c->d_cblk_y, (size_t)c->cblk_ylen * CBLK)) ||
+        (rc = dalloc(c, &c->d_cblk_b, (size_t)c->ld * CBLK)) ||
+        (rc = dalloc(c, &c->d_cblk_bbp, (size_t)c->vgrid * CBLK)) ||
+        (rc = dalloc(c, &c->d_cblk_x, (size_t)c->ld * CBLK)) ||
+        (rc = dalloc(c, &c->d_cblk_t, (size_t)c->n_nodes * CBLK)))
+        return rc;
+    c->cblk_state = 1;
+    return 0;
+}
+
+// Condensation (Section 3.1) of the g <= CBLK right-hand sides F[0..g) (rows
+// of n_nodes): y_I = K_II^{-1} F_I for all of them in one pass over the
+// interior tiles, then t_i = K_BI y_I and b per column, into the group buffers.
+int run_condense_block(bddc_ctx *c, const double *F, int g) {
+    TScope ts(c, TK_COND);
+    if (set_symm_smem_limit(c->cblk_smem)) return fail(BDDC_EHIP, "hipFuncSetAttribute (block product LDS) failed");
+    BlockSymvArgs a{};
+    a.tiles = c->d_KI; a.items = c->d_cblk_items; a.gB = c->d_nodesI;
+    a.X = F; a.ldx = c->n_nodes; a.ncols = g;
+    a.ypart = c->d_cblk_y; a.ylen = c->cblk_ylen;
+    launch_symm(a, c->n_sub, false, c->cblk_smem, c->stream);
+    for (int q = 0; q < g; ++q) {
+        CondArgs ca{};
+        ca.nI = c->d_nI; ca.nB = c->d_nB; ca.i_off = c->d_i_off; ca.b_off = c->d_b_off;
+        ca.nchunk = c->d_cblk_ones; ca.pb = c->d_i_off; ca.ypart = c->d_cblk_y + (size_t)q * c->cblk_ylen;
+        ca.kbi_ptr = c->d_kbi_ptr; ca.kbi_col = c->d_kbi_col; ca.kbi_val = c->d_kbi_val; ca.t = c->d_locq;
+        launch_cond_local(ca, c->n_sub, c->max_nI, c->stream);
+        CondAsmArgs b{};
+        b.n = c->n_gamma; b.gamma = c->d_gamma; b.ptr = c->d_asm_ptr; b.idx = c->d_asm_idx;
+        b.F = F + (size_t)q * c->n_nodes; b.loc = c->d_locq;
+        b.b = c->d_cblk_b + (size_t)q * c->ld; b.part = c->d_cblk_bbp + (size_t)q * c->vgrid;
+        launch_cond_asm(b, c->vgrid, c->stream);
+    }
+    return 0;
+}
+
+// b and its ||b||^2 partials of column q of the condensed group
+void take_condensed(bddc_ctx *c, int q) {
+    launch_copy(c->n_gamma, c->d_cblk_b + (size_t)q * c->ld, c->d_b, c->stream);
+    launch_copy(c->vgrid, c->d_cblk_bbp + (size_t)q * c->vgrid, c->d_bbp, c->stream);
+}
+
+// Interior recovery (Section 3.1) of g <= CBLK solutions at once: for each
+// column q, F[q] (rows of n_nodes) and the interface solution in column q of
+// d_cblk_x give K_IB x_B; x_I = K_II^{-1} (F_I - K_IB x_B) for all columns in
+// one pass over the interior tiles; u[q] = (x_I, x_G).
+int run_recover_block(bddc_ctx *c, const double *F, double *u, int g) {
+    TScope ts(c, TK_COND);
+    RecArgs a{};
+    a.nI = c->d_nI; a.nB = c->d_nB; a.i_off = c->d_i_off; a.b_off = c->d_b_off; a.nodesI = c->d_nodesI;
+    a.gB = c->d_gB;
+    a.kib_ptr = c->d_kib_ptr; a.kib_col = c->d_kib_col; a.kib_val = c->d_kib_val;
+    a.nchunk = c->d_cblk_ones; a.pb = c->d_i_off;
+    for (int q = 0; q < g; ++q) {
+        a.x = c->d_cblk_x + (size_t)q * c->ld; a.F = F + (size_t)q * c->n_nodes;
+        a.out = c->d_cblk_t + (size_t)q * c->n_nodes;
+        launch_rec_rhs(a, c->n_sub, c->max_nB, c->stream);
+    }
+    if (set_symm_smem_limit(c->cblk_smem)) return fail(BDDC_EHIP, "hipFuncSetAttribute (block product LDS) failed");
+    BlockSymvArgs b{};
+    b.tiles = c->d_KI; b.items = c->d_cblk_items; b.gB = c->d_nodesI;
+    b.X = c->d_cblk_t; b.ldx = c->n_nodes; b.ncols = g;
+    b.ypart = c->d_cblk_y; b.ylen = c->cblk_ylen;
+    launch_symm(b, c->n_sub, false, c->cblk_smem, c->stream);
+    for (int q = 0; q < g; ++q) {
+        double *uq = u + (size_t)q * c->n_nodes;
+        a.ypart = c->d_cblk_y + (size_t)q * c->cblk_ylen; a.u = uq;
+        launch_fill(c->n_nodes, 0.0, uq, c->stream);
+        launch_rec_out(a, c->n_sub, c->stream);
+        launch_scatter_gamma(c->n_gamma, c->d_gamma, c->d_cblk_x + (size_t)q * c->ld, uq, c->stream);
+    }
+    return 0;
+}
+
 // Interior recovery (Section 3.1): x_I = K_II^{-1} (F_I - K_IB x_B), u = (x_I, x_G).
 int run_recover(bddc_ctx *c, const double *F, double *u) {
     TScope ts(c, TK_COND);
@@ -879,6 +983,7 @@ int end_sync_wait(bddc_ctx *c) {
 
 // One right-hand side: condense (unless already done), Algorithm 1 from
 // x_prev, recover.  The stream is synchronised once, after the loop.
+// u null: the interior recovery is left to the caller (block recovery).
 int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle, bool condensed, int *iters,
               double *relres) {
     const bool record = recycle && c->R > 0 && !c->frozen;
@@ -918,7 +1023,7 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
         // copies so that the device works while the host waits (done again if
         // the solve goes on or x is reset)
         if ((rc = end_sync_issue(c, hist))) return rc;
-        if ((rc = run_recover(c, F, u))) return rc;
+        if (u && (rc = run_recover(c, F, u))) return rc;
         recovered = true;
         if ((rc = end_sync_wait(c))) return rc;
         const Ctl &h = *c->h_ctl;
@@ -949,7 +1054,7 @@ int solve_one(bddc_ctx *c, const double *F, double *u, double rtol, bool recycle
     c->have_hist = want_hist;
     if (iters) *iters = h.iter;
     if (relres) *relres = (h.bb > 0 && !h.zero_rhs) ? std::sqrt(h.true_rr / h.bb) : 0.0;
-    if (!recovered && (rc = run_recover(c, F, u))) return rc;
+    if (u && !recovered && (rc = run_recover(c, F, u))) return rc;
     if (h.status == BDDC_EBREAKDOWN) return fail(BDDC_EBREAKDOWN, "PCG breakdown (r^T z <= 0, p^T A p <= 0 or NaN)");
     if (h.status == BDDC_ENOTCONV) return fail(BDDC_ENOTCONV, "max_it reached");
     return 0;
@@ -2501,19 +2606,45 @@ int dpcg_solve(bddc_ctx *c, const double *rhs_seq, int32_t n_rhs, double rtol, d
         return fail(BDDC_EINVAL, "bad dpcg_solve argument");
     bool condensed = false;
     c->pre_schur = false;
+    // several right-hand sides: condensed CBLK at a time in one pass over the
+    // interior tiles, and their interiors recovered likewise after the group's
+    // last solve (the results are those of the one-at-a-time forms)
+    if (n_rhs > 1) {
+        int rc = cblk_setup(c);
+        if (rc) return rc;
+    }
+    const bool blk = n_rhs > 1 && c->cblk_state == 1;
+    int g0 = 0, gn = 0;                 // the condensed group: right-hand sides [g0, g0 + gn)
     for (int k = 0; k < n_rhs; ++k) {
         int it = 0;
         double rr = 0.0;
-        int rc = solve_one(c, rhs_seq + (size_t)k * c->n_nodes, x_seq + (size_t)k * c->n_nodes, rtol, true, condensed,
-                           &it, &rr);
+        if (blk) {
+            if (k >= g0 + gn) {
+                g0 = k;
+                gn = std::min(CBLK, n_rhs - k);
+                if (int rc = run_condense_block(c, rhs_seq + (size_t)k * c->n_nodes, gn)) return rc;
+            }
+            take_condensed(c, k - g0);
+            condensed = true;
+        }
+        int rc = solve_one(c, rhs_seq + (size_t)k * c->n_nodes, blk ? nullptr : x_seq + (size_t)k * c->n_nodes, rtol,
+                           true, condensed, &it, &rr);
         if (iters) iters[k] = it;
         if (true_relres) true_relres[k] = rr;
+        if (blk) {   // the group's interiors are recovered together after its last solve (or a failure)
+            launch_copy(c->n_gamma, c->d_x, c->d_cblk_x + (size_t)(k - g0) * c->ld, c->stream);
+            if (rc || k == g0 + gn - 1) {
+                const int r2 = run_recover_block(c, rhs_seq + (size_t)g0 * c->n_nodes, x_seq + (size_t)g0 * c->n_nodes,
+                                                 k - g0 + 1);
+                if (!rc) rc = r2;
+            }
+        }
         if (rc) { (void)settle(c); if (c->timing) flush_timing(c); return rc; }
         // the next right-hand side is condensed while the host solves the
         // small recycling eigenproblem
         condensed = k + 1 < n_rhs;
         if (condensed) {
-            run_condense(c, rhs_seq + (size_t)(k + 1) * c->n_nodes);
+            if (!blk) run_condense(c, rhs_seq + (size_t)(k + 1) * c->n_nodes);
             // A x_{-1} of the next initial residual does not depend on the
             // deflation basis.  With the previous solution as x_{-1} it is the
             // product the true residual just formed, still in the Schur

@@ -7,7 +7,9 @@ of 48 to 64 nodes, two sizes without a tail).  Against the FP64
 oracle: Schur products (1e-12), preconditioner (1e-9), an FP64 sequence with
 a recycled basis (iterations +-1, solutions 1e-9); and the block products of
 the block adjoint (16-column tiles on the matrix cores) against the
-column-by-column adjoint (1e-9).
+column-by-column adjoint (1e-9).  Also: a 20-right-hand-side call (interior
+condensation and recovery grouped 16 + 4 per pass over the interior tiles)
+against 20 one-right-hand-side calls (iterations +-1, solutions 1e-9).
 """
 import numpy as np
 import pytest
@@ -99,3 +101,22 @@ def test_ragged_block_adjoint_equals_column_by_column():
     print("[gpu] ragged block adjoint: %d block iterations" % it, flush=True)
     assert _rel(lam2.cpu().numpy(), lam1.cpu().numpy()) <= 1e-9
     assert _rel(g2.cpu().numpy(), g1.cpu().numpy()) <= 1e-9
+
+
+def test_grouped_condensation_and_recovery_equal_one_at_a_time():
+    # one call with 20 right-hand sides condenses and recovers them in groups
+    # of 16 and 4 (block products over the interior tiles); 20 calls of one
+    # right-hand side take the one-vector path; same recycling sequence
+    torch = _torch()
+    from paper_2412_17543_amd.solver import Solver
+    s = workload.workload("tiny3")
+    F = torch.tensor(workload.rhs_sequence(16, 20), device="cuda")
+    g1 = Solver(16, s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"], R=4)
+    U1, it1, rr1 = g1.solve_sequence(F, 1e-10)
+    g2 = Solver(16, s["elem_to_sub"], s["coef"], sub_to_subregion=s["sub_to_subregion"], R=4)
+    res = [g2.solve_sequence(F[k:k + 1], 1e-10) for k in range(20)]
+    U2 = torch.cat([r[0] for r in res])
+    it2 = np.concatenate([r[1] for r in res])
+    print("[gpu] grouped iterations", it1.tolist(), "one at a time", it2.tolist(), flush=True)
+    assert np.all(np.abs(it1 - it2) <= 1)
+    assert _rel(U1.cpu().numpy(), U2.cpu().numpy()) <= 1e-9
