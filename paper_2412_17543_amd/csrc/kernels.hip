@@ -315,15 +315,25 @@ __global__ void __launch_bounds__(256) k_recycle_gemm(GemmArgs a) {
     dvec4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = dvec4{0.0, 0.0, 0.0, 0.0};
-    for (int q0 = 0; q0 < m; q0 += 4) {
-        const int q = q0 + lk;
-        double b = 0.0;
-        if (q < m && rok) b = (q < a.k1 ? V1 + (int64_t)q * a.ld : V2 + (int64_t)(q - a.k1) * a.ld)[row];
+    // B operands GQ steps (4 GQ columns of V) at a time, all requested before
+    // the first is used
+    constexpr int GQ = 8;
+    for (int q1 = 0; q1 < m; q1 += 4 * GQ) {
+        double b[GQ];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int c = 16 * t + li;
-            const double av = (q < m && c < a.ncol) ? a.Y[(int64_t)q * a.ldy + c] : 0.0;
-            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[t], 0, 0, 0);
+        for (int u = 0; u < GQ; ++u) {
+            const int q = q1 + 4 * u + lk;
+            b[u] = (q < m && rok) ? (q < a.k1 ? V1 + (int64_t)q * a.ld : V2 + (int64_t)(q - a.k1) * a.ld)[row] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < GQ; ++u) {
+            const int q = q1 + 4 * u + lk;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int c = 16 * t + li;
+                const double av = (q < m && c < a.ncol) ? a.Y[(int64_t)q * a.ldy + c] : 0.0;
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[u], acc[t], 0, 0, 0);
+            }
         }
     }
     if (!rok) return;
@@ -347,7 +357,7 @@ __global__ void __launch_bounds__(256) k_recycle_gemm(GemmArgs a) {
 // ---------------------------------------------------------------------------
 constexpr int GRAM_ROWS = 64;
 template <int T>
-__global__ void __launch_bounds__(256) k_gram(GramArgs a) {
+__global__ void __launch_bounds__(256, T <= 3 ? 2 : 1) k_gram(GramArgs a) {
     __shared__ double xs[16 * T][GRAM_ROWS + 1];
     __shared__ double ys[16 * T][GRAM_ROWS + 1];
     const int k = a.k, k2 = a.k2;
@@ -359,15 +369,30 @@ __global__ void __launch_bounds__(256) k_gram(GramArgs a) {
     for (int p = 0; p < T; ++p)
 #pragma unroll
         for (int q = 0; q < T; ++q) acc[p][q] = dvec4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t s0 = g0; s0 < g1; s0 += GRAM_ROWS) {
+    // a chunk's entries (4 T per thread and block) are all requested before
+    // any is stored, and the next chunk's while the current one is multiplied
+    constexpr int PER = GRAM_ROWS * 16 * T / 256;
+    double vx[PER], vy[PER];
+    auto fetch = [&](int64_t s0) {
         const int nr = (int)min((int64_t)GRAM_ROWS, g1 - s0);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int t = threadIdx.x + 256 * u, rr = t % GRAM_ROWS, c = t / GRAM_ROWS;
+            vx[u] = rr < nr && c < k ? a.X[(int64_t)c * a.ld + s0 + rr] : 0.0;
+            vy[u] = rr < nr && c < k2 ? a.Y[(int64_t)c * a.ld + s0 + rr] : 0.0;
+        }
+    };
+    if (g0 < g1) fetch(g0);
+    for (int64_t s0 = g0; s0 < g1; s0 += GRAM_ROWS) {
         __syncthreads();
-        for (int t = threadIdx.x; t < GRAM_ROWS * 16 * T; t += blockDim.x) {
-            const int rr = t % GRAM_ROWS, c = t / GRAM_ROWS;
-            xs[c][rr] = rr < nr && c < k ? a.X[(int64_t)c * a.ld + s0 + rr] : 0.0;
-            ys[c][rr] = rr < nr && c < k2 ? a.Y[(int64_t)c * a.ld + s0 + rr] : 0.0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int t = threadIdx.x + 256 * u, rr = t % GRAM_ROWS, c = t / GRAM_ROWS;
+            xs[c][rr] = vx[u];
+            ys[c][rr] = vy[u];
         }
         __syncthreads();
+        if (s0 + GRAM_ROWS < g1) fetch(s0 + GRAM_ROWS);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int rr = 16 * w + 4 * s + lk;
