@@ -140,6 +140,10 @@ struct bddc_ctx {
     double *d_Mc = nullptr, *d_rC = nullptr;
     int64_t ldm = 0;
     int64_t *d_K2_off = nullptr, *d_N2_off = nullptr, *d_P2_off = nullptr;
+    // level-3 inverse also as its upper triangle in 64 x 64 blocks (large levels)
+    int nb3 = 0;
+    double *d_K3s = nullptr, *d_K3part = nullptr;
+    int32_t *d_K3bI = nullptr;
     double *d_K2 = nullptr, *d_N2 = nullptr, *d_Phi2 = nullptr, *d_K3inv = nullptr, *d_r3 = nullptr, *d_vI2 = nullptr,
            *d_t2 = nullptr, *d_rB2 = nullptr, *d_u2 = nullptr, *d_c3loc = nullptr, *d_u3 = nullptr;
     // deflation / recycling
@@ -303,7 +307,8 @@ double coarse_bytes(const bddc_ctx *c) {
     for (int i = 0; i < c->n_sub; ++i) cp += (double)c->opN.nchunk[i] * c->h_nc[i] * 12.0;
     const double vec = c->nC * (4.0 + 8.0 + 8.0);
     if (c->coarse_dense) return (double)c->nC * c->ldm * 8.0 + cp + vec + c->nC * 8.0;
-    double b = cp + vec + (double)c->n3 * c->ld3 * 8.0;
+    const double n3 = c->n3;
+    double b = cp + vec + (c->d_K3s ? n3 * (n3 + 1) / 2 * 8.0 : n3 * c->ld3 * 8.0);
     for (const SubregionHost &r : c->st.sr) {
         const double nL = (double)r.L.size(), nI = r.nI, nB = r.nB, n3 = (double)r.c3.size();
         b += (nL * nI + nB * nB + nB * n3 + nB * n3 + nI * nB) * 8.0 + nL * (4.0 + 8.0);
@@ -550,11 +555,19 @@ void run_l2_chain(const bddc_ctx *c, const L2Args &l, hipStream_t st) {
     launch_l2_a(l, c->nsr, c->max_nL, st);
     launch_l2_b(l, c->nsr, c->max_nL, st);
     // level 3: r3 = sum of the subregion contributions, u3 = K3^{-1} r3 with
-    // the dense inverse (stored negated, rows padded to ld3)
+    // the inverse's upper triangle in blocks, or the dense inverse (stored
+    // negated, rows padded to ld3)
     CoarseDenseArgs l3{};
     l3.ctl = c->d_ctl; l3.n = c->n3; l3.rc = Gather{c->d_asm3_ptr, c->d_asm3_idx, c->d_c3loc}; l3.r = c->d_r3;
     l3.M = c->d_K3inv; l3.ldm = c->ld3; l3.sign = -1.0; l3.u = c->d_u3;
-    launch_coarse_dense(l3, st);
+    if (c->d_K3s) {
+        SymBlkArgs sb{};
+        sb.ctl = c->d_ctl; sb.n = c->n3; sb.nb = c->nb3; sb.B = c->d_K3s; sb.bI = c->d_K3bI; sb.r = c->d_r3;
+        sb.part = c->d_K3part; sb.u = c->d_u3;
+        launch_coarse_symblk(l3, sb, st);
+    } else {
+        launch_coarse_dense(l3, st);
+    }
     launch_l2_d(l, c->nsr, c->smem_l2d, st);
 }
 
@@ -2130,6 +2143,21 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
                 if ((rc = sweep_semidefinite(c, c->d_K3inv, n, ld, e3))) return rc;
             } else if (n > 0 && (rc = run_sweeps(c, {SweepDesc{c->d_K3inv, n, ld, 0, n, n}}))) {
                 return rc;
+            }
+            // large levels: the upper triangle in 64 x 64 blocks for the
+            // single-vector product (half the bytes per application)
+            if (n >= 512) {
+                const int nb = (n + 63) / 64;
+                const int64_t nbt = (int64_t)nb * (nb + 1) / 2;
+                std::vector<int32_t> bI;
+                bI.reserve(nbt);
+                for (int I = 0; I < nb; ++I)
+                    for (int J = I; J < nb; ++J) bI.push_back(I);
+                c->nb3 = nb;
+                if ((rc = dupload(c, &c->d_K3bI, bI)) || (rc = dalloc(c, &c->d_K3s, (size_t)nbt * 4096)) ||
+                    (rc = dalloc(c, &c->d_K3part, (size_t)nbt * 128)))
+                    return rc;
+                launch_pack_symblk(c->d_K3inv, ld, n, nb, c->d_K3bI, -1.0, c->d_K3s, s);
             }
             HIPCHK(hipStreamSynchronize(s));
             dfree(c, dp); dfree(c, di);

@@ -1050,6 +1050,89 @@ __global__ void __launch_bounds__(ROWS * 64) k_coarse_dense(CoarseDenseArgs a) {
     if (live && l == 0) a.u[row] = a.sign * t;
 }
 
+// Level-3 coarse product with the upper triangle of the (symmetric) inverse
+// in 64 x 64 blocks: half the bytes of the full matrix.  One block of
+// threads per matrix block (I, J); thread t takes row i = t / 4, columns
+// 16 (t % 4) .. + 15 (a wave reads 16 whole rows, 8 KB in one piece).  The
+// row part B x_J is summed over the quad of the row; for J > I the column
+// part B^T x_I over the 16 rows of the wave (row rotations within 16 lanes,
+// then the row-swap permutes) and the 4 waves in order.
+constexpr int DPP_ROR4 = 0x124;     // row_ror:4 within 16 lanes
+__device__ __forceinline__ int symblk_start(int I, int nb) { return I * nb - I * (I - 1) / 2; }
+
+__global__ void __launch_bounds__(256) k_symblk(SymBlkArgs a) {
+    __shared__ double colw[4][64];
+    __shared__ double xsh[128];     // x_J, then x_I
+    if (a.ctl->done) return;
+    const int b = blockIdx.x;
+    const int t = threadIdx.x, i = t >> 2, q = t & 3, w = t >> 6, l = t & 63;
+    const double2 *rp = reinterpret_cast<const double2 *>(a.B + (int64_t)b * 4096 + i * 64 + 16 * q);
+    double2 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = rp[k];
+    const int I = a.bI[b], J = I + (b - symblk_start(I, a.nb));
+    // x_J and x_I staged once (range-checked loads: zero past n, no branch)
+    const __amdgpu_buffer_rsrc_t rr = vec_rsrc(a.r, a.n);
+    if (t < 128) xsh[t] = ld_rc(rr, t < 64 ? 64 * J + t : 64 * I + t - 64);
+    __syncthreads();
+    double xj[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) xj[c] = xsh[16 * q + c];
+    const double xi = xsh[64 + i];
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += v[k].x * xj[2 * k] + v[k].y * xj[2 * k + 1];
+    s += dpp<DPP_XOR1>(s);
+    s += dpp<DPP_XOR2>(s);
+    if (q == 0) a.part[(int64_t)b * 128 + i] = s;
+    if (J == I) return;             // (block-uniform) a diagonal block holds both triangles
+    double cs[16];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { cs[2 * k] = v[k].x * xi; cs[2 * k + 1] = v[k].y * xi; }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        double u = cs[k] + dpp<DPP_ROR4>(cs[k]);
+        u += dpp<DPP_ROR8>(u);
+        cs[k] = col_sum4(u);        // the wave's 16 rows of column 16 q + k
+    }
+    if (l < 4) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) colw[w][16 * q + k] = cs[k];
+    }
+    __syncthreads();
+    if (t < 64) a.part[(int64_t)b * 128 + 64 + t] = ((colw[0][t] + colw[1][t]) + colw[2][t]) + colw[3][t];
+}
+
+// u on the rows of panel P: the column sums of blocks (I, P), I < P, then the
+// row sums of blocks (P, J), J >= P, split over 4 waves and added in order.
+__global__ void __launch_bounds__(256) k_symblk_sum(SymBlkArgs a) {
+    __shared__ double red[4][64];
+    if (a.ctl->done) return;
+    const int P = blockIdx.x, t = threadIdx.x, i = t & 63, sq = t >> 6, nb = a.nb;
+    // 8 terms of the thread requested at a time (past the last term: an index
+    // past the buffer, which reads as zero), added in increasing order
+    const int64_t np = (int64_t)nb * (nb + 1) / 2 * 128;
+    const __amdgpu_buffer_rsrc_t pr = vec_rsrc(a.part, np);
+    double acc = 0.0;
+    for (int k0 = sq; k0 < nb; k0 += 32) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + 4 * u;
+            const int64_t e = k >= nb ? np
+                            : k < P ? (int64_t)(symblk_start(k, nb) + P - k) * 128 + 64 + i
+                                    : (int64_t)(symblk_start(P, nb) + k - P) * 128 + i;
+            v[u] = ld_rc(pr, e);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    red[sq][i] = acc;
+    __syncthreads();
+    const int g = 64 * P + t;
+    if (t < 64 && g < a.n) a.u[g] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+}
+
 __device__ __forceinline__ void l2_cols(L2Args &a) {
     const int64_t col = blockIdx.y;     // one column per grid row (block products)
     a.rc.part += col * a.cs_rc;
@@ -1286,6 +1369,13 @@ void launch_coarse_dense(const CoarseDenseArgs &a, hipStream_t s, int ncols) {
     const size_t smem = (size_t)coarse_dense_staged((int)a.ldm) * 8;
     if (a.n > 4096) hipLaunchKernelGGL(k_coarse_dense<8>, dim3((a.n + 7) / 8, ncols), dim3(512), smem, s, a);
     else hipLaunchKernelGGL(k_coarse_dense<4>, dim3((a.n + 3) / 4, ncols), dim3(256), smem, s, a);
+}
+
+void launch_coarse_symblk(const CoarseDenseArgs &g, const SymBlkArgs &a, hipStream_t s) {
+    if (a.n <= 0) return;
+    hipLaunchKernelGGL(k_coarse_rhs, dim3((g.n + 255) / 256), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(k_symblk, dim3(a.nb * (a.nb + 1) / 2), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_symblk_sum, dim3(a.nb), dim3(256), 0, s, a);
 }
 
 void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s, int ncols) {

@@ -194,6 +194,20 @@ struct CoarseDenseArgs {
     int64_t cs_rc, cs_r, cs_u;      // several columns (blockIdx.y): strides of rc.part, r, u
 };
 
+// Symmetric product u = K r with the upper triangle of K in 64 x 64 blocks
+// (I, J >= I), each row-major and zero past n; block (I, J) has index
+// I nb - I (I - 1) / 2 + J - I and bI[b] = I.  Per block: 64 row sums, then
+// (J > I) 64 column sums, in part[128 b ...]; a second pass adds them.
+struct SymBlkArgs {
+    Ctl *ctl;
+    int n, nb;                      // order, 64-row panels
+    const double *B;
+    const int32_t *bI;
+    const double *r;
+    double *part;
+    double *u;
+};
+
 struct L2Args {
     Ctl *ctl;
     Gather rc;                      // level-1 coarse residual from the coarse partials
@@ -370,6 +384,10 @@ void launch_defl_init(const DeflArgs &a, int kmax, int grid, hipStream_t s);
 void launch_reduce(const ReduceArgs &a, hipStream_t s);
 void launch_reorth(const ReorthArgs &a, int kmax, int grid, hipStream_t s);
 void launch_coarse_dense(const CoarseDenseArgs &a, hipStream_t s, int ncols = 1);
+// u = K r for the block layout of SymBlkArgs (r first gathered like the dense form's)
+void launch_coarse_symblk(const CoarseDenseArgs &g, const SymBlkArgs &a, hipStream_t s);
+void launch_pack_symblk(const double *M, int64_t ldm, int n, int nb, const int32_t *bI, double sign, double *B,
+                        hipStream_t s);
 void launch_l2_a(const L2Args &a, int nsr, int max_nL, hipStream_t s, int ncols = 1);
 void launch_l2_b(const L2Args &a, int nsr, int max_nL, hipStream_t s, int ncols = 1);
 size_t l2_d_smem(int max_nL);

@@ -167,6 +167,17 @@ __global__ void __launch_bounds__(256) k_pack(const PackDesc *descs, T *dst, T *
 }
 
 
+// setup: the upper triangle of a symmetric n x n row-major matrix (sign
+// folded in) as 64 x 64 row-major blocks (I, J >= I), zero past n
+__global__ void __launch_bounds__(256) k_pack_symblk(const double *M, int64_t ldm, int n, int nb, const int32_t *bI,
+                                                     double sign, double *B) {
+    const int b = blockIdx.x, I = bI[b], J = I + (b - (I * nb - I * (I - 1) / 2));
+    for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+        const int gi = 64 * I + (e >> 6), gj = 64 * J + (e & 63);
+        B[(int64_t)b * 4096 + e] = (gi < n && gj < n) ? sign * M[(int64_t)gi * ldm + gj] : 0.0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // setup: K_C = Phi^T S Phi (coarse element matrices, eq. coarse_problem)
 // ---------------------------------------------------------------------------
@@ -626,6 +637,10 @@ void launch_pack(const PackDesc *d, int n, int prec, void *dst, void *phir, hipS
     if (prec == 64) hipLaunchKernelGGL(k_pack<double>, dim3(n), dim3(256), 0, s, d, (double *)dst, (double *)phir);
     else if (prec == 32) hipLaunchKernelGGL(k_pack<float>, dim3(n), dim3(256), 0, s, d, (float *)dst, (float *)phir);
     else hipLaunchKernelGGL(k_pack<uint16_t>, dim3(n), dim3(256), 0, s, d, (uint16_t *)dst, (uint16_t *)phir);
+}
+void launch_pack_symblk(const double *M, int64_t ldm, int n, int nb, const int32_t *bI, double sign, double *B,
+                        hipStream_t s) {
+    if (nb > 0) hipLaunchKernelGGL(k_pack_symblk, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, M, ldm, n, nb, bI, sign, B);
 }
 void launch_ptsp(const PtspDesc *d, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_ptsp, dim3(n), dim3(256), 0, s, d);
