@@ -14,9 +14,10 @@
 //   coarse tile C_{J - nt} += T^T X_I (Neumann only; T holds rows of D Phi_i)
 // After the row the waves' row parts are added into Y_I in wave order, so
 // every entry is summed in a fixed order (the product is reproducible bit by
-// bit).  The ragged tail rows (n % 16 of them, stored as a strip after the
-// tiles) follow as one more tile row.  A tile is loaded once (two 16-byte loads per lane, the layout of
-// tile_index), written to the wave's LDS slot in row-major order and read
+// bit).  A short ragged tail stored as a strip after the tiles (uses_strip)
+// follows as one more tile row.  A tile is loaded once (two 16-byte loads
+// per lane, the layout of tile_index), written to the wave's LDS slot in
+// row-major order and read
 // back as MFMA operands: v_mfma_f64_16x16x4f64 takes A[i][k] and B[k][j] in
 // lane i (j) + 16 k and returns (i, j) in lane j + 16 (i % 4), register i / 4.
 #include <hip/hip_runtime.h>
@@ -77,8 +78,8 @@ __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
     const int nch = (a.ncols + 15) / 16;
     const BlockItem it = a.items[blockIdx.x / nch];
     const int c0 = 16 * (int)(blockIdx.x % nch);
-    const int n = it.n, nt = n / 16, npad = 16 * ((n + 15) / 16);   // nt: full tile rows
-    const int nc = COARSE ? it.nc : 0, ntc = (nc + 15) / 16;
+    const int n = it.n, nc = COARSE ? it.nc : 0, ntc = (nc + 15) / 16;
+    const int nt = tile_rows(n, nc), npad = 16 * ((n + 15) / 16);   // nt: tile rows (without a strip's rows)
     const int64_t total = full_tiles(n, nc);
     double *xs = sm;                                   // npad x 16 (stride XS)
     double *ys = xs + (size_t)npad * XS;               // (npad + 16 ntc) x 16
@@ -193,7 +194,7 @@ __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
     // q = nt (the full rem x rem block: row part only) and the coarse chunks
     // (column part only).  Wave w takes the chunks q = w, w + 4, ...; a
     // chunk's rows of Y (or C) belong to that wave alone.
-    const int rem = n % 16;
+    const int rem = uses_strip(n, nc) ? n % 16 : 0;
     if (rem > 0) {
         const int n0 = 16 * nt, m = n + nc, nq = nt + 1 + ntc;
         const double *sp = a.tiles + (it.tile + total) * 256;

@@ -297,7 +297,7 @@ __device__ __forceinline__ void cm_matvec(const double *M, int64_t ldm, int r0, 
 __device__ __forceinline__ SymvItem load_item(const SymvItem *items, int i) {
     typedef const __attribute__((address_space(4))) int32_t CInt;
     CInt *q = (CInt *)(items + i);
-    return SymvItem{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], 0, 0, 0};
+    return SymvItem{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9], q[10], q[11]};
 }
 
 template <typename T, int U>
@@ -345,12 +345,12 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
         const T *tb = reinterpret_cast<const T *>(a.op.tiles) + (int64_t)it.tile * 256;
         const int32_t *gb = a.op.gB + it.x_off;
         const int ncs = OP::coarse ? it.nc : 0;
-        const int ntf = n / TILE, ntc = (ncs + TILE - 1) / TILE;   // full tile rows, coarse tiles per row
-        const int ntl = full_tiles(n, ncs);                        // the tiles; the strip's slots follow
+        const int ntf = it.ntf, ntc = (ncs + TILE - 1) / TILE;   // tile rows, coarse tiles per row
+        const int ntl = it.ntl;                                  // the tiles; a strip's slots follow
         // the waves split the segment's tiles; the segment holding slot ntl
         // also takes the ragged tail's strip (after its tiles)
         const int span = max(min(it.t1, ntl) - it.t0, 0);
-        const bool strip_here = (n % TILE) != 0 && it.t0 <= ntl && ntl < it.t1;
+        const bool strip_here = it.strip && it.t0 <= ntl && ntl < it.t1;
         const int w0 = it.t0 + (int)((int64_t)span * wu / NW);
         const int w1 = it.t0 + (int)((int64_t)span * (wu + 1) / NW);
         auto stage = [&](int t) {

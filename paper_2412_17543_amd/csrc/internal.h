@@ -14,17 +14,26 @@ namespace bddc {
 constexpr int TILE = 16;          // symmetric operators are stored as 16x16 tiles
 
 // Packed symmetric operator of n rows (+ nc coarse-basis columns) in slots of
-// 256 entries: the full 16-row tile rows I < n / 16, each the tiles
-// (I, I..nt-1) of the upper triangle then (I, nt..nt+ntc-1) of the coarse
-// block (nt = n / 16, ntc = ceil(nc / 16)); then the last n % 16 rows (the
-// ragged tail) as a row-major strip of n + nc entries per row (the full rows:
-// node columns, then coarse columns), padded to whole slots.  Tiles past the
-// triangle's last full row would be mostly zero padding.
+// 256 entries: 16-row tile rows, tile row I holding the tiles (I, I..nt-1) of
+// the upper triangle then (I, nt..nt+ntc-1) of the coarse block (ntc =
+// ceil(nc / 16)).  A short ragged tail (n % 16 = 1..8 rows, rows of at most
+// 512 entries) is stored after the nt = n / 16 full tile rows as a row-major
+// strip of its whole rows (node columns, then coarse columns), padded to
+// whole slots: its tile column would be mostly zero padding.  Otherwise the
+// last tile row and column are zero-padded (nt = ceil(n / 16)) -- a long
+// strip would cost the product more round trips than its padding costs bytes.
+__host__ __device__ inline bool uses_strip(int n, int nc) {
+    const int rem = n % TILE;
+    return rem != 0 && rem <= 8 && n + nc <= 512;
+}
+__host__ __device__ inline int tile_rows(int n, int nc) { return uses_strip(n, nc) ? n / TILE : (n + TILE - 1) / TILE; }
 __host__ __device__ inline int full_tiles(int n, int nc) {
-    const int nt = n / TILE, ntc = (nc + TILE - 1) / TILE;
+    const int nt = tile_rows(n, nc), ntc = (nc + TILE - 1) / TILE;
     return nt * (nt + 1) / 2 + nt * ntc;
 }
-__host__ __device__ inline int64_t strip_len(int n, int nc) { return (int64_t)(n % TILE) * (n + nc); }
+__host__ __device__ inline int64_t strip_len(int n, int nc) {
+    return uses_strip(n, nc) ? (int64_t)(n % TILE) * (n + nc) : 0;
+}
 __host__ __device__ inline int64_t op_slots(int n, int nc) {
     return full_tiles(n, nc) + (strip_len(n, nc) + 255) / 256;
 }

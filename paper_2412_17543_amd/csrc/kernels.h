@@ -37,12 +37,13 @@ struct AsmDesc {
 struct SymvItem {
     int32_t tile, t0, t1, n;
     int32_t nc, x_off, yoff, coff;
-    int32_t next, pad0, pad1, pad2;
+    int32_t next;
+    int32_t ntf, ntl, strip;        // the subdomain's tile rows, tiles, 1 if its tail is a strip
 };
 
-// A batch of packed symmetric operators in the slot layout of full_tiles and
-// strip_len: the tiles of the full tile rows (with the coarse-basis tiles
-// when `nc` is set), then the strip of the ragged tail rows.  The
+// A batch of packed symmetric operators in the slot layout of tile_rows and
+// strip_len: the tiles (with the coarse-basis tiles when `nc` is set), then,
+// for a short ragged tail, the strip of its rows.  The
 // concatenated slot sequence of all subdomains is cut into n_blocks ranges,
 // one per block, and each range into segments inside single subdomains; the
 // segment holding a subdomain's first strip slot also applies the strip.  Segment c of

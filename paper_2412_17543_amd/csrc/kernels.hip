@@ -107,9 +107,9 @@ __global__ void __launch_bounds__(256) k_build_saddle(const SaddleDesc *descs) {
 
 // ---------------------------------------------------------------------------
 // setup: pack a symmetric n x n block (+ an n x nc block) in the slot layout
-// of full_tiles / strip_len: 16x16 tiles (element order of tile_index) of the
-// full tile rows, tile row I holding (I, I..nt-1) then (I, nt..nt+ntc-1);
-// then the ragged tail rows, row-major over the n node and nc coarse
+// of tile_rows / strip_len: 16x16 tiles (element order of tile_index), tile
+// row I holding (I, I..nt-1) then (I, nt..nt+ntc-1), zero past n; then, with
+// a strip, the ragged tail rows, row-major over the n node and nc coarse
 // columns.  Value = sign * src[i][j] * D[i] * D[j] (coarse-basis block:
 // sign * phi[i][q] * D[i]); with phr >= 0 the coarse-basis block is also
 // written row-major (n rows of nc values) for the prolongation.
@@ -127,7 +127,7 @@ __device__ __forceinline__ void store_conv(uint16_t *p, double v) {
 template <typename T>
 __global__ void __launch_bounds__(256) k_pack(const PackDesc *descs, T *dst, T *phir) {
     const PackDesc d = descs[blockIdx.x];
-    const int nt = d.n / TILE, ntc = (d.nc + TILE - 1) / TILE, n0 = nt * TILE;
+    const int nt = tile_rows(d.n, d.nc), ntc = (d.nc + TILE - 1) / TILE, n0 = nt * TILE;
     // value of row gi (< n) at node column gj (< n) or coarse column n + gq
     auto node = [&](int gi, int gj) {
         double v = d.sign * d.src[(size_t)gi * d.ld + gj];
@@ -149,10 +149,11 @@ __global__ void __launch_bounds__(256) k_pack(const PackDesc *descs, T *dst, T *
             const int gi = I * TILE + r;
             double v = 0.0;
             if (J < nt) {
-                v = node(gi, J * TILE + c);
+                const int gj = J * TILE + c;
+                if (gi < d.n && gj < d.n) v = node(gi, gj);
             } else {
                 const int gq = (J - nt) * TILE + c;
-                if (gq < d.nc) v = coarse(gi, gq);
+                if (gi < d.n && gq < d.nc) v = coarse(gi, gq);
             }
             store_conv(dst + d.dst + (base + q) * 256 + tile_index(r, c, (int)sizeof(T)), v);
         }

@@ -2,8 +2,9 @@
 operator layout: a one-element subdomain at a corner of the cube (interface
 of 7 nodes: no full 16-row tile, the whole operator is the ragged-tail
 strip; one interior node) carved out of a 2 x 2 x 2 partition of 8^3
-(interfaces of 52 to 68 nodes with ragged tails of 4 and 13 rows; interiors
-of 48 to 64 nodes, two sizes without a tail).  Against the FP64
+(interfaces of 52 to 68 nodes: ragged tails of 4 rows stored as strips and
+of 13 rows as zero-padded tiles; interiors of 48 to 64 nodes, two sizes
+without a tail, one with an 8-row strip).  Against the FP64
 oracle: Schur products (1e-12), preconditioner (1e-9), an FP64 sequence with
 a recycled basis (iterations +-1, solutions 1e-9); and the block products of
 the block adjoint (16-column tiles on the matrix cores) against the
