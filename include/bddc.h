@@ -185,9 +185,14 @@ int bddc_setup(const bddc_mesh *mesh, const bddc_partition *part, const double *
  *                 interface problem at exit, recomputed in float64.
  * Each solve condenses F_k to the interface, runs Algorithm 1 from the
  * previous solution with the current deflation basis, recovers the interior
- * and, unless the basis is frozen, calls recycle_update.  On ENOTCONV the
- * outputs of the failing solve hold the last iterate and iters = max_it;
- * later right-hand sides are not solved.
+ * and, unless the basis is frozen, calls recycle_update.  With n_rhs > 1 the
+ * interior products of condensation and recovery run for up to 16 right-hand
+ * sides per pass over the interior operators: a group is condensed before its
+ * first solve and its interiors recovered after its last (same results; the
+ * first such call allocates the group buffers, about 1.8 GB at 192^3, unless
+ * an interior is too large for the block product's LDS staging).  On
+ * ENOTCONV the outputs of the failing solve hold the last iterate and iters =
+ * max_it; later right-hand sides are not solved.
  */
 int dpcg_solve(bddc_ctx *ctx, const double *rhs_seq, int32_t n_rhs, double rtol,
                double *x_seq, int32_t *iters, double *true_relres);
@@ -199,8 +204,9 @@ int dpcg_solve(bddc_ctx *ctx, const double *rhs_seq, int32_t n_rhs, double rtol,
  * largest harmonic Ritz values), W <- V Y, A W <- [A W, A P] Y, W^T A W by a
  * float64 Gram product, freeze test of eq. harmritzstopcrit.  dpcg_solve
  * calls it after every solve; calling it again without a new solve is a no-op.
- * Errors: ESINGULAR when the new W^T A W is not positive definite (the old
- * basis is kept).
+ * The new basis is computed over the old one; when its W^T A W is not
+ * positive definite the update is refused and the recycled columns are
+ * dropped (counted by bddc_solve_info).
  */
 int recycle_update(bddc_ctx *ctx);
 
