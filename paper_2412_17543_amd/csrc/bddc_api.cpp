@@ -2784,17 +2784,41 @@ int bddc_adjoint_grad_block(bddc_ctx *c, const double *dLdu_seq, int32_t n_rhs, 
     if (rc) { free_block(c, b); return rc; }
     launch_copy(c->n_gamma, c->d_x, xsave, c->stream);
     launch_set_done(c->d_ctl, 0, c->stream);
-    for (int k = 0; k < n_rhs; ++k) {
-        run_condense(c, dLdu_seq + (size_t)k * c->n_nodes);
-        launch_copy(c->n_gamma, c->d_b, b.B + (size_t)k * c->ld, c->stream);
+    // condensation and recovery: CBLK right-hand sides per pass over the
+    // interior operators when the block product can stage them
+    if (n_rhs > 1 && (rc = cblk_setup(c))) { dfree(c, xsave); free_block(c, b); return rc; }
+    const bool grouped = n_rhs > 1 && c->cblk_state == 1;
+    for (int g0 = 0; g0 < n_rhs; g0 += CBLK) {
+        const int gn = std::min(CBLK, n_rhs - g0);
+        if (grouped && (rc = run_condense_block(c, dLdu_seq + (size_t)g0 * c->n_nodes, gn))) break;
+        for (int q = 0; q < gn; ++q) {
+            const int k = g0 + q;
+            if (!grouped) run_condense(c, dLdu_seq + (size_t)k * c->n_nodes);
+            launch_copy(c->n_gamma, grouped ? c->d_cblk_b + (size_t)q * c->ld : c->d_b, b.B + (size_t)k * c->ld,
+                        c->stream);
+        }
     }
+    if (rc) { launch_copy(c->n_gamma, xsave, c->d_x, c->stream); (void)hipStreamSynchronize(c->stream); dfree(c, xsave); free_block(c, b); return rc; }
+    // (set_symm_smem_limit again: the grouped condensation set its own)
+    if (set_symm_smem_limit(symm_smem_bytes(c->max_nB, c->max_nc))) rc = fail(BDDC_EHIP, "hipFuncSetAttribute (block product LDS) failed");
     int it = 0;
-    rc = block_solve(c, b, n_rhs, rtol, &it);
+    if (!rc) rc = block_solve(c, b, n_rhs, rtol, &it);
     if (iters) *iters = it;
     if (rc == 0 || rc == BDDC_ENOTCONV) {
-        for (int k = 0; k < n_rhs; ++k) {
-            launch_copy(c->n_gamma, b.X + (size_t)k * c->ld, c->d_x, c->stream);
-            run_recover(c, dLdu_seq + (size_t)k * c->n_nodes, grad_rhs_seq + (size_t)k * c->n_nodes);
+        for (int g0 = 0; g0 < n_rhs; g0 += CBLK) {
+            const int gn = std::min(CBLK, n_rhs - g0);
+            if (grouped) {
+                for (int q = 0; q < gn; ++q)
+                    launch_copy(c->n_gamma, b.X + (size_t)(g0 + q) * c->ld, c->d_cblk_x + (size_t)q * c->ld, c->stream);
+                int r2 = run_recover_block(c, dLdu_seq + (size_t)g0 * c->n_nodes, grad_rhs_seq + (size_t)g0 * c->n_nodes, gn);
+                if (r2 && (rc == 0 || rc == BDDC_ENOTCONV)) rc = r2;
+            } else {
+                for (int q = 0; q < gn; ++q) {
+                    const int k = g0 + q;
+                    launch_copy(c->n_gamma, b.X + (size_t)k * c->ld, c->d_x, c->stream);
+                    run_recover(c, dLdu_seq + (size_t)k * c->n_nodes, grad_rhs_seq + (size_t)k * c->n_nodes);
+                }
+            }
         }
         GradArgs g{};
         g.n_elem = c->st.n_elem; g.n_nodes = c->n_nodes; g.nx = c->st.nx; g.ny = c->st.ny; g.nz = c->st.nz;
@@ -2820,9 +2844,25 @@ int bddc_adjoint_grad(bddc_ctx *c, const double *dLdu_seq, int32_t n_rhs, const 
     if (rc) return rc;
     launch_copy(c->n_gamma, c->d_x, xsave, c->stream);
     launch_fill(c->n_gamma, 0.0, c->d_x, c->stream);
-    for (int k = 0; k < n_rhs && rc == 0; ++k)
-        rc = solve_one(c, dLdu_seq + (size_t)k * c->n_nodes, grad_rhs_seq + (size_t)k * c->n_nodes, rtol, false, false,
-                       nullptr, nullptr);
+    // condensation and recovery grouped as in dpcg_solve
+    if (n_rhs > 1 && (rc = cblk_setup(c))) { dfree(c, xsave); return rc; }
+    const bool grouped = n_rhs > 1 && c->cblk_state == 1;
+    for (int g0 = 0; g0 < n_rhs && rc == 0; g0 += CBLK) {
+        const int gn = std::min(CBLK, n_rhs - g0);
+        if (grouped && (rc = run_condense_block(c, dLdu_seq + (size_t)g0 * c->n_nodes, gn))) break;
+        int k = g0;
+        for (; k < g0 + gn && rc == 0; ++k) {
+            if (grouped) take_condensed(c, k - g0);
+            rc = solve_one(c, dLdu_seq + (size_t)k * c->n_nodes, grouped ? nullptr : grad_rhs_seq + (size_t)k * c->n_nodes,
+                           rtol, false, grouped, nullptr, nullptr);
+            if (grouped) launch_copy(c->n_gamma, c->d_x, c->d_cblk_x + (size_t)(k - g0) * c->ld, c->stream);
+        }
+        if (grouped) {
+            const int r2 = run_recover_block(c, dLdu_seq + (size_t)g0 * c->n_nodes, grad_rhs_seq + (size_t)g0 * c->n_nodes,
+                                             k - g0);
+            if (!rc) rc = r2;
+        }
+    }
     c->have_solve = false;
     launch_copy(c->n_gamma, xsave, c->d_x, c->stream);
     if (rc == 0) {
