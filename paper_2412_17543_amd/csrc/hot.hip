@@ -715,14 +715,22 @@ __global__ void __launch_bounds__(256) k_zasm(ZasmArgs a) {
 #pragma unroll
     for (int q = 0; q <= KM; ++q) acc[q] = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const __amdgpu_buffer_rsrc_t awr = vec_rsrc(a.AW, (int64_t)k * a.ld);
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += stride) {
+        // the node's (AW) and r entries are requested with its gather, not
+        // after the store of z (which the compiler may not move them past)
+        double aw[KM > 0 ? KM : 1], rg = 0.0;
+        if (a.part) {
+            rg = a.r[g];
+#pragma unroll
+            for (int q = 0; q < KM; ++q) aw[q] = ld_rc(awr, (int64_t)q * a.ld + g);
+        }
         const double z = gather_sum(a.w, g);
         a.z[g] = z;
         if (a.part) {
-            acc[0] += a.r[g] * z;
-            const __amdgpu_buffer_rsrc_t awr = vec_rsrc(a.AW, (int64_t)k * a.ld);
+            acc[0] += rg * z;
 #pragma unroll
-            for (int q = 0; q < KM; ++q) acc[1 + q] += ld_rc(awr, (int64_t)q * a.ld + g) * z;
+            for (int q = 0; q < KM; ++q) acc[1 + q] += aw[q] * z;
         }
     }
     if (!a.part) return;
