@@ -48,12 +48,12 @@ struct OpHost {
     double bytes = 0;               // algorithmic bytes of one product
     bool interior = false;          // interior operators (sizes nI, no gather lists)
     std::vector<int32_t> nchunk;    // per subdomain
-    int32_t *d_items = nullptr, *d_nchunk = nullptr, *d_pb = nullptr, *d_cb = nullptr;
-    double *d_ypart = nullptr, *d_cpart = nullptr;
-    int64_t ypart_len = 0, cpart_len = 0;   // allocated lengths of the partial buffers
-    int64_t ylen = 0;                       // partial entries the current work list writes
-    // flat gather lists: interface node -> y partials, coarse DOF -> c partials
-    int32_t *d_yptr = nullptr, *d_yidx = nullptr, *d_cptr = nullptr, *d_cidx = nullptr;
+    int32_t *d_items = nullptr, *d_nchunk = nullptr, *d_pb = nullptr;
+    double *d_ypart = nullptr;
+    int64_t ypart_len = 0;          // allocated length of the partial buffer
+    int64_t ylen = 0;               // partial entries the current work list writes
+    // flat gather list: interface node -> y partials
+    int32_t *d_yptr = nullptr, *d_yidx = nullptr;
 };
 
 // Pinned host block filled by the per-solve synchronisation.
@@ -91,8 +91,8 @@ struct bddc_ctx {
     // level 1
     int32_t *d_nB = nullptr, *d_nI = nullptr, *d_b_off = nullptr, *d_i_off = nullptr, *d_nc = nullptr,
             *d_c_off = nullptr, *d_gB = nullptr, *d_nodesI = nullptr, *d_cidx = nullptr, *d_gamma = nullptr,
-            *d_pos_sub = nullptr, *d_cpos_sub = nullptr;
-    int64_t *d_k_off = nullptr, *d_s_off = nullptr, *d_n_off = nullptr, *d_phr_off = nullptr;
+            *d_pos_sub = nullptr;
+    int64_t *d_k_off = nullptr, *d_s_off = nullptr, *d_phr_off = nullptr;
     int32_t *d_pch_sub = nullptr, *d_pch_row = nullptr;   // prolongation blocks: subdomain, first row
     int n_pch = 0;
     double *d_K = nullptr, *d_S = nullptr, *d_KC = nullptr;
@@ -100,7 +100,8 @@ struct bddc_ctx {
     void *d_Nx[3] = {}, *d_phirx[3] = {};        // the storage precisions built: float64, float32, bfloat16
     int prec_built = 0;                          // bit mask of those: 1 float64, 2 float32, 4 bfloat16
     int32_t *d_asm_ptr = nullptr, *d_asm_idx = nullptr, *d_casm_ptr = nullptr, *d_casm_idx = nullptr;
-    int max_nI = 0, max_nB = 0, max_nc = 0, max_nt = 0, max_ntc = 0, max_ntI = 0;
+    double *d_crest = nullptr;                   // coarse restriction partials, one per (subdomain, coarse DOF)
+    int max_nI = 0, max_nB = 0, max_nc = 0, max_nt = 0, max_ntI = 0;
     // condensation of up to CBLK right-hand sides per pass over the interior
     // tiles (k_symm): per-column partials, condensed b and ||b||^2 partials
     int cblk_state = 0;             // 0 not set up, 1 ready, -1 unavailable (LDS)
@@ -110,7 +111,7 @@ struct bddc_ctx {
     int32_t *d_cblk_ones = nullptr;
     double *d_cblk_y = nullptr, *d_cblk_b = nullptr, *d_cblk_bbp = nullptr;
     double *d_cblk_x = nullptr, *d_cblk_t = nullptr;   // interface solutions, recovery right-hand sides
-    std::vector<int32_t> h_nB, h_nI, h_nc, h_b_off, h_c_off, h_pos_sub, h_cpos_sub;
+    std::vector<int32_t> h_nB, h_nI, h_nc, h_b_off, h_c_off, h_pos_sub;
     std::vector<int32_t> h_asm_ptr, h_asm_idx, h_casm_ptr, h_casm_idx;
     OpHost opS, opN, opI;           // Schur, Neumann, interior inverse K_II^{-1}
     int64_t *d_ki_off = nullptr;
@@ -283,28 +284,33 @@ void build_csr(int64_t ntarget, const std::vector<std::pair<int64_t, int32_t>> &
 int prec_slot(int prec) { return prec == 64 ? 0 : prec == 32 ? 1 : prec == 16 ? 2 : -1; }
 
 // Algorithmic bytes of one batched product (Schur or Neumann, prec = the
-// operator's storage precision): packed upper triangle (+ coarse basis),
-// gathered input and its index, output (+ coarse output).
-double product_bytes(const bddc_ctx *c, bool isN, int prec) {
+// operator's storage precision): packed upper triangle, gathered input and
+// its index, output.
+double product_bytes(const bddc_ctx *c, int prec) {
     const double eb = prec / 8.0;
     double bytes = 0.0;
     for (int i = 0; i < c->n_sub; ++i) {
-        const double n = c->h_nB[i], nci = isN ? c->h_nc[i] : 0;
-        bytes += (n * (n + 1) / 2 + n * nci) * eb + n * (8 + 4 + 8) + nci * 8;
+        const double n = c->h_nB[i];
+        bytes += n * (n + 1) / 2 * eb + n * (8 + 4 + 8);
     }
     return bytes;
 }
 
 // Algorithmic bytes of the coarse levels of one preconditioner application:
-// the dense coarse operator and the gather of r_C; or, for the subregion
+// the restriction (D Phi_i rows, gathered r and its index, one partial per
+// local coarse DOF), the dense coarse operator and the gather of r_C; or, for the subregion
 // chain, the level-2 blocks each phase reads (interior columns of the swept
 // subregion matrix, N and Phi of the level-2 interface, Phi again and the
 // interior-interface block for the correction), the level-3 inverse and the
 // coarse vectors.
 double coarse_bytes(const bddc_ctx *c) {
     if (c->nC == 0) return 0.0;
-    double cp = 0.0;   // coarse partials gathered into r_C: index + value
-    for (int i = 0; i < c->n_sub; ++i) cp += (double)c->opN.nchunk[i] * c->h_nc[i] * 12.0;
+    const double eN = c->prec / 8.0;
+    double cp = 0.0;   // restriction, and its partials gathered into r_C (index + value)
+    for (int i = 0; i < c->n_sub; ++i) {
+        const double n = c->h_nB[i], nci = c->h_nc[i];
+        cp += n * nci * eN + n * (8.0 + 4.0) + nci * 8.0 + nci * 12.0;
+    }
     const double vec = c->nC * (4.0 + 8.0 + 8.0);
     if (c->coarse_dense) return (double)c->nC * c->ldm * 8.0 + cp + vec + c->nC * 8.0;
     const double n3 = c->n3;
@@ -382,12 +388,12 @@ int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
     const int nsub = c->n_sub;
     struct Seg { int k; int64_t t0, t1; int32_t c; };
     std::vector<std::vector<Seg>> blk;   // segments of every block, in order
-    std::vector<int32_t> nch(nsub, 0), pb(nsub), cb(nsub), xoff(nsub + 1, 0);
-    int64_t ylen = 0, clen = 0;
+    std::vector<int32_t> nch(nsub, 0), pb(nsub), xoff(nsub + 1, 0);
+    int64_t ylen = 0;
     const std::vector<int32_t> &sizes = op.interior ? c->h_nI : c->h_nB;
     std::vector<int64_t> start(nsub + 1, 0);
     for (int i = 0; i < nsub; ++i) {
-        start[i + 1] = start[i] + op_slots(sizes[i], op.dev.nc ? c->h_nc[i] : 0);
+        start[i + 1] = start[i] + op_slots(sizes[i]);
         xoff[i + 1] = xoff[i] + sizes[i];
     }
     const int64_t total = start[nsub];
@@ -419,21 +425,16 @@ int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
         }
     }
     for (int k = 0; k < nsub; ++k) {
-        const int nci = op.dev.nc ? c->h_nc[k] : 0;
         pb[k] = (int32_t)ylen;
-        cb[k] = (int32_t)clen;
         ylen += (int64_t)nch[k] * sizes[k];
-        clen += (int64_t)nch[k] * nci;
     }
-    if (ylen > INT32_MAX || clen > INT32_MAX) return fail(BDDC_EINVAL, "operator partial buffers exceed int32 indexing");
+    if (ylen > INT32_MAX) return fail(BDDC_EINVAL, "operator partial buffers exceed int32 indexing");
     // block b's first segment at index b, its others appended and chained
-    std::vector<SymvItem> items(std::max(nblocks, 1), SymvItem{0, 0, 0, 0, 0, 0, 0, 0, -1, 0, 0, 0});
+    std::vector<SymvItem> items(std::max(nblocks, 1), SymvItem{0, 0, 0, 0, 0, 0, -1, 0, 0, 0});
     auto record = [&](const Seg &g) {
-        const int nci = op.dev.nc ? c->h_nc[g.k] : 0;
         const int n = sizes[g.k];
-        return SymvItem{(int32_t)start[g.k], (int32_t)g.t0, (int32_t)g.t1, n, nci, xoff[g.k],
-                        pb[g.k] + g.c * n, cb[g.k] + g.c * nci, -1,
-                        tile_rows(n, nci), full_tiles(n, nci), uses_strip(n, nci) ? 1 : 0};
+        return SymvItem{(int32_t)start[g.k], (int32_t)g.t0, (int32_t)g.t1, n, xoff[g.k], pb[g.k] + g.c * n, -1,
+                        tile_rows(n), full_tiles(n), uses_strip(n) ? 1 : 0};
     };
     for (int b = 0; b < nblocks; ++b) {
         int prev = b;
@@ -447,22 +448,16 @@ int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
             }
         }
     }
-    dfree(c, op.d_items); dfree(c, op.d_nchunk); dfree(c, op.d_pb); dfree(c, op.d_cb);
+    dfree(c, op.d_items); dfree(c, op.d_nchunk); dfree(c, op.d_pb);
     std::vector<int32_t> raw(items.size() * (sizeof(SymvItem) / 4));
     std::memcpy(raw.data(), items.data(), items.size() * sizeof(SymvItem));
     int rc;
-    if ((rc = dupload(c, &op.d_items, raw)) || (rc = dupload(c, &op.d_nchunk, nch)) || (rc = dupload(c, &op.d_pb, pb)) ||
-        (rc = dupload(c, &op.d_cb, cb)))
+    if ((rc = dupload(c, &op.d_items, raw)) || (rc = dupload(c, &op.d_nchunk, nch)) || (rc = dupload(c, &op.d_pb, pb)))
         return rc;
     if (ylen > op.ypart_len) {
         dfree(c, op.d_ypart);
         if ((rc = dalloc(c, &op.d_ypart, (size_t)ylen))) return rc;
         op.ypart_len = ylen;
-    }
-    if (clen > op.cpart_len) {
-        dfree(c, op.d_cpart);
-        if ((rc = dalloc(c, &op.d_cpart, (size_t)std::max<int64_t>(1, clen)))) return rc;
-        op.cpart_len = clen;
     }
     op.nchunk = nch;
     op.ylen = ylen;
@@ -470,7 +465,6 @@ int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
     op.dev.n_blocks = total > 0 ? nblocks : 0;
     op.dev.nchunk = op.d_nchunk;
     op.dev.pb = op.d_pb;
-    op.dev.cb = op.d_cb;
     if (op.interior) return 0;      // interior entries have one owner: no lists
     // flat gather lists, owners in assembly order, items in increasing order
     {
@@ -488,20 +482,6 @@ int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
         dfree(c, op.d_yptr); dfree(c, op.d_yidx);
         if ((rc = dupload(c, &op.d_yptr, ptr)) || (rc = dupload(c, &op.d_yidx, idx))) return rc;
     }
-    if (op.dev.nc) {
-        std::vector<int32_t> ptr(c->nC + 1, 0), idx;
-        for (int t = 0; t < c->nC; ++t) {
-            for (int e = c->h_casm_ptr[t]; e < c->h_casm_ptr[t + 1]; ++e) {
-                const int pos = c->h_casm_idx[e];
-                const int i = c->h_cpos_sub[pos];
-                const int q = pos - c->h_c_off[i];
-                for (int cc = 0; cc < nch[i]; ++cc) idx.push_back(cb[i] + cc * c->h_nc[i] + q);
-            }
-            ptr[t + 1] = (int32_t)idx.size();
-        }
-        dfree(c, op.d_cptr); dfree(c, op.d_cidx);
-        if ((rc = dupload(c, &op.d_cptr, ptr)) || (rc = dupload(c, &op.d_cidx, idx))) return rc;
-    }
     return 0;
 }
 
@@ -512,12 +492,7 @@ int sync_ctl(bddc_ctx *c) {
     return 0;
 }
 
-Gather gather_of(const OpHost &op, bool coarse) {
-    Gather g{};
-    if (coarse) { g.ptr = op.d_cptr; g.idx = op.d_cidx; g.part = op.d_cpart; }
-    else { g.ptr = op.d_yptr; g.idx = op.d_yidx; g.part = op.d_ypart; }
-    return g;
-}
+Gather gather_of(const OpHost &op) { return Gather{op.d_yptr, op.d_yidx, op.d_ypart}; }
 
 // Schur products y_i = S_i x_i of every subdomain (partials in opS); with
 // `dot`, per-item x_i^T y_i partials for p^T A p.
@@ -573,13 +548,13 @@ void run_l2_chain(const bddc_ctx *c, const L2Args &l, hipStream_t st) {
     launch_l2_d(l, c->nsr, c->smem_l2d, st);
 }
 
-void run_coarse(bddc_ctx *c);
+void run_coarse(bddc_ctx *c, const double *r, hipStream_t st);
 void run_prolong_assemble(bddc_ctx *c, const double *r, double *z, bool gated, bool advance, bool reduce);
 
-// One BDDC application on r: local constrained-Neumann products and coarse
-// residuals, the coarse problem, assembly of z with the coarse prolongation
-// and the (r^T z, (AW)^T z) partials.  test: stopping test at the start
-// (0 none, 1 in the loop, 2 first test of a solve).
+// One BDDC application on r: local constrained-Neumann products, the coarse
+// levels, assembly of z with the coarse prolongation and the (r^T z,
+// (AW)^T z) partials.  test: stopping test at the start (0 none, 1 in the
+// loop, 2 first test of a solve).
 void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, bool advance, bool reduce) {
     {
         TScope ts(c, TK_PREC);
@@ -587,7 +562,6 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
         a.op = c->opN.dev;
         a.x = r;
         a.ypart = c->opN.d_ypart;
-        a.cpart = c->opN.d_cpart;
         a.ctl = c->d_ctl;
         a.gated = gated ? 1 : 0;
         a.test = test;
@@ -599,26 +573,33 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
         a.res_hist = c->d_reshist; a.hist_cap = c->hist_cap;
         launch_symv(a, SYMV_NEUMANN, c->prec, c->opN.cfg, c->opN.smem, c->stream);
     }
-    run_coarse(c);
+    run_coarse(c, r, c->stream);
     run_prolong_assemble(c, r, z, gated, advance, reduce);
 }
 
-// Coarse levels of one BDDC application: u_C from the coarse partials of the
-// Neumann product (eq. coarse_problem; three levels as in Section 3.2).
-void run_coarse(bddc_ctx *c) {
-    if (c->nC > 0) {
-        TScope ts(c, TK_COARSE);
-        const Gather rc = gather_of(c->opN, true);
-        if (c->coarse_dense) {
-            CoarseDenseArgs ca{};
-            ca.ctl = c->d_ctl; ca.n = c->nC; ca.rc = rc; ca.r = c->d_rC;
-            ca.M = c->d_Mc; ca.ldm = c->ldm;
-            ca.sign = c->three ? 1.0 : -1.0;
-            ca.u = c->d_uC;
-            launch_coarse_dense(ca, c->stream);
-        } else {
-            run_l2_chain(c, l2_args(c, rc), c->stream);
-        }
+// Coarse levels of one BDDC application on stream st: the coarse residual
+// r_C = sum_i R_Ci^T (D Phi_i)^T R_i r, then u_C (eq. coarse_problem; three
+// levels as in Section 3.2).
+void run_coarse(bddc_ctx *c, const double *r, hipStream_t st) {
+    if (c->nC == 0) return;
+    TScope ts(c, TK_COARSE);
+    CrestArgs ra{};
+    ra.ctl = c->d_ctl;
+    ra.nB = c->d_nB; ra.b_off = c->d_b_off; ra.gB = c->d_gB; ra.nc = c->d_nc; ra.c_off = c->d_c_off;
+    ra.phir = c->d_phir; ra.phr_off = c->d_phr_off;
+    ra.X = r; ra.ldx = 0; ra.part = c->d_crest; ra.cs = 0; ra.ncols = 1;
+    ra.rows = (int)crest_rows(c->max_nB, 1);
+    launch_crest(ra, c->prec, c->n_sub, st);
+    const Gather rc{c->d_casm_ptr, c->d_casm_idx, c->d_crest};
+    if (c->coarse_dense) {
+        CoarseDenseArgs ca{};
+        ca.ctl = c->d_ctl; ca.n = c->nC; ca.rc = rc; ca.r = c->d_rC;
+        ca.M = c->d_Mc; ca.ldm = c->ldm;
+        ca.sign = c->three ? 1.0 : -1.0;
+        ca.u = c->d_uC;
+        launch_coarse_dense(ca, st);
+    } else {
+        run_l2_chain(c, l2_args(c, rc), st);
     }
 }
 
@@ -679,7 +660,7 @@ void run_update(bddc_ctx *c) {
     TScope ts(c, TK_VEC);
     UpdArgs a{};
     a.n = c->n_gamma;
-    a.q = gather_of(c->opS, false);
+    a.q = gather_of(c->opS);
     a.p = c->d_p; a.x = c->d_x; a.r = c->d_r;
     a.AP = c->d_AP; a.ld = c->ld; a.cap = c->save_cap;
     a.dot = c->d_dotS; a.dot_n = c->opS.dev.n_blocks;
@@ -695,7 +676,7 @@ void run_resid(bddc_ctx *c, double *out, bool want_wtr) {
     TScope ts(c, TK_VEC);
     ResidArgs a{};
     a.n = c->n_gamma; a.want_wtr = want_wtr ? 1 : 0;
-    a.q = gather_of(c->opS, false);
+    a.q = gather_of(c->opS);
     a.b = c->d_b; a.out = out;
     a.W = c->d_W; a.ld = c->ld;
     a.ctl = c->d_ctl;
@@ -832,14 +813,14 @@ constexpr int CBLK = 16;            // right-hand sides condensed per pass over 
 int cblk_setup(bddc_ctx *c) {
     if (c->cblk_state) return 0;
     const int nsub = c->n_sub;
-    c->cblk_smem = symm_smem_bytes(c->max_nI, 0);
+    c->cblk_smem = symm_smem_bytes(c->max_nI);
     if (c->cblk_smem > 160 * 1024) { c->cblk_state = -1; return 0; }
     std::vector<BlockItem> items(nsub);
     std::vector<int32_t> ones(nsub, 1);
     int64_t slot = 0, y = 0;
     for (int i = 0; i < nsub; ++i) {
-        items[i] = BlockItem{slot, c->h_nI[i], 0, (int32_t)y, 0};
-        slot += op_slots(c->h_nI[i], 0);
+        items[i] = BlockItem{slot, c->h_nI[i], (int32_t)y};
+        slot += op_slots(c->h_nI[i]);
         y += c->h_nI[i];
     }
     if (y > INT32_MAX) { c->cblk_state = -1; return 0; }
@@ -866,7 +847,7 @@ int run_condense_block(bddc_ctx *c, const double *F, int g) {
     a.tiles = c->d_KI; a.items = c->d_cblk_items; a.gB = c->d_nodesI;
     a.X = F; a.ldx = c->n_nodes; a.ncols = g;
     a.ypart = c->d_cblk_y; a.ylen = c->cblk_ylen;
-    launch_symm(a, c->n_sub, false, c->cblk_smem, c->stream);
+    launch_symm(a, c->n_sub, c->cblk_smem, c->stream);
     for (int q = 0; q < g; ++q) {
         CondArgs ca{};
         ca.nI = c->d_nI; ca.nB = c->d_nB; ca.i_off = c->d_i_off; ca.b_off = c->d_b_off;
@@ -909,7 +890,7 @@ int run_recover_block(bddc_ctx *c, const double *F, double *u, int g) {
     b.tiles = c->d_KI; b.items = c->d_cblk_items; b.gB = c->d_nodesI;
     b.X = c->d_cblk_t; b.ldx = c->n_nodes; b.ncols = g;
     b.ypart = c->d_cblk_y; b.ylen = c->cblk_ylen;
-    launch_symm(b, c->n_sub, false, c->cblk_smem, c->stream);
+    launch_symm(b, c->n_sub, c->cblk_smem, c->stream);
     for (int q = 0; q < g; ++q) {
         double *uq = u + (size_t)q * c->n_nodes;
         a.ypart = c->d_cblk_y + (size_t)q * c->cblk_ylen; a.u = uq;
@@ -1487,23 +1468,22 @@ int setup_operators(bddc_ctx *c) {
         const bool isN = w == 1;
         op.prec = isN ? c->prec : 64;
         op.dev.tiles = isN ? c->d_N : (const void *)c->d_S;
-        op.dev.t_off = isN ? c->d_n_off : c->d_s_off;
+        op.dev.t_off = c->d_s_off;   // the two batches share the layout
         op.dev.nB = c->d_nB;
         op.dev.b_off = c->d_b_off;
         op.dev.gB = c->d_gB;
-        op.dev.nc = isN ? c->d_nc : nullptr;
         op.n_tiles = 0;
-        for (int i = 0; i < nsub; ++i) op.n_tiles += op_slots(c->h_nB[i], isN ? c->h_nc[i] : 0);
-        op.bytes = product_bytes(c, isN, op.prec);
+        for (int i = 0; i < nsub; ++i) op.n_tiles += op_slots(c->h_nB[i]);
+        op.bytes = product_bytes(c, op.prec);
         op.cfg = SymvCfg{4, 2};
-        op.smem = symv_smem(op.prec, op.cfg.nw, c->max_nt, isN ? c->max_ntc : 0);
+        op.smem = symv_smem(op.prec, op.cfg.nw, c->max_nt);
         int rc = build_worklist(c, op, product_blocks(c, op.n_tiles, op.bpc), op.per_sub);
         if (rc) return rc;
     }
     // (LDS accumulators are float64 for a float64 Neumann batch, else float32)
     const int pw = (c->prec_built & 1) ? 64 : 32;
-    const size_t need4 = std::max(symv_smem(64, 4, c->max_nt, 0), symv_smem(pw, 4, c->max_nt, c->max_ntc));
-    const size_t need8 = std::max(symv_smem(64, 8, c->max_nt, 0), symv_smem(pw, 8, c->max_nt, c->max_ntc));
+    const size_t need4 = std::max(symv_smem(64, 4, c->max_nt), symv_smem(pw, 4, c->max_nt));
+    const size_t need8 = std::max(symv_smem(64, 8, c->max_nt), symv_smem(pw, 8, c->max_nt));
     if (need4 > 160 * 1024) return fail(BDDC_EINVAL, "a subdomain interface is too large for the LDS-staged products");
     c->allow8 = need8 <= 160 * 1024;
     if (set_symv_smem_limit(c->allow8 ? need8 : need4)) return fail(BDDC_EHIP, "hipFuncSetAttribute (dynamic LDS) failed");
@@ -1519,7 +1499,7 @@ int setup_interior(bddc_ctx *c, const std::vector<int64_t> &k_off) {
     const int nsub = c->n_sub;
     const Structure &st = c->st;
     std::vector<int64_t> ki_off(nsub + 1, 0);
-    for (int i = 0; i < nsub; ++i) ki_off[i + 1] = ki_off[i] + op_slots(c->h_nI[i], 0) * 256;
+    for (int i = 0; i < nsub; ++i) ki_off[i + 1] = ki_off[i] + op_slots(c->h_nI[i]) * 256;
     int rc;
     if ((rc = dupload(c, &c->d_ki_off, ki_off)) || (rc = dalloc_tiles(c, &c->d_KI, (size_t)std::max<int64_t>(1, ki_off[nsub]))))
         return rc;
@@ -1581,18 +1561,17 @@ int setup_interior(bddc_ctx *c, const std::vector<int64_t> &k_off) {
     op.dev.nB = c->d_nI;
     op.dev.b_off = c->d_i_off;
     op.dev.gB = c->d_nodesI;
-    op.dev.nc = nullptr;
     op.n_tiles = ki_off[nsub] / 256;
     op.cfg = SymvCfg{4, 2};
     int max_ntI = 0;
     for (int i = 0; i < nsub; ++i) max_ntI = std::max(max_ntI, (c->h_nI[i] + TILE - 1) / TILE);
-    if (symv_smem(64, 4, max_ntI, 0) > 160 * 1024) return fail(BDDC_EINVAL, "a subdomain interior is too large for the LDS-staged products");
+    if (symv_smem(64, 4, max_ntI) > 160 * 1024) return fail(BDDC_EINVAL, "a subdomain interior is too large for the LDS-staged products");
     c->max_ntI = max_ntI;
-    op.smem = symv_smem(64, 4, max_ntI, 0);
-    if (c->allow8 && symv_smem(64, 8, max_ntI, 0) > 160 * 1024) c->allow8 = false;
+    op.smem = symv_smem(64, 4, max_ntI);
+    if (c->allow8 && symv_smem(64, 8, max_ntI) > 160 * 1024) c->allow8 = false;
     const int nwmax = c->allow8 ? 8 : 4;
-    const size_t lim = std::max(symv_smem(64, nwmax, std::max(c->max_nt, max_ntI), 0),
-                                symv_smem((c->prec_built & 1) ? 64 : 32, nwmax, c->max_nt, c->max_ntc));
+    const size_t lim = std::max(symv_smem(64, nwmax, std::max(c->max_nt, max_ntI)),
+                                symv_smem((c->prec_built & 1) ? 64 : 32, nwmax, c->max_nt));
     if (set_symv_smem_limit(lim)) return fail(BDDC_EHIP, "hipFuncSetAttribute (dynamic LDS) failed");
     HIPCHK(hipMemsetAsync(c->d_tmpN, 0, (size_t)c->n_nodes * sizeof(double), c->stream));
     return build_worklist(c, op, product_blocks(c, op.n_tiles, op.bpc), op.per_sub);
@@ -1611,7 +1590,6 @@ int tune_operators(bddc_ctx *c, int mask = 7) {
     for (int w = 0; w < 3 && rc == 0; ++w) {
         OpHost &op = *ops[w];
         if (op.dev.n_blocks == 0 || !((mask >> w) & 1)) continue;
-        const int ntc = op.dev.nc ? c->max_ntc : 0;
         const int mnt = op.interior ? c->max_ntI : c->max_nt;
         float best = 1e30f;
         int best_bpc = op.bpc;
@@ -1621,9 +1599,9 @@ int tune_operators(bddc_ctx *c, int mask = 7) {
         auto time_cfg = [&](int bpc, bool ps, SymvCfg cfg, int reps, float &ms) -> int {
             int r0 = build_worklist(c, op, product_blocks(c, op.n_tiles, bpc), ps);
             if (r0) return r0;
-            const size_t smem = symv_smem(op.prec, cfg.nw, mnt, ntc);
+            const size_t smem = symv_smem(op.prec, cfg.nw, mnt);
             SymvArgs a{};
-            a.op = op.dev; a.x = op.interior ? c->d_tmpN : c->d_x; a.ypart = op.d_ypart; a.cpart = op.d_cpart;
+            a.op = op.dev; a.x = op.interior ? c->d_tmpN : c->d_x; a.ypart = op.d_ypart;
             a.ctl = c->d_ctl;
             for (int r = 0; r < 2; ++r) launch_symv(a, (SymvOp)w, op.prec, cfg, smem, c->stream);
             HIPCHK(hipEventRecord(e0, c->stream));
@@ -1671,7 +1649,7 @@ int tune_operators(bddc_ctx *c, int mask = 7) {
         op.cfg = best_cfg;
         op.bpc = best_bpc;
         op.per_sub = best_ps;
-        op.smem = symv_smem(op.prec, best_cfg.nw, mnt, ntc);
+        op.smem = symv_smem(op.prec, best_cfg.nw, mnt);
         op.tuned_us = best * 1e3f / 4;
     }
     (void)hipEventDestroy(e0);
@@ -1834,9 +1812,9 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
 
     // -------------------------------------------------- level-1 metadata
     std::vector<int32_t> nI(nsub), nB(nsub), nc(nsub), i_off(nsub + 1, 0), b_off(nsub + 1, 0), c_off(nsub + 1, 0);
-    std::vector<int64_t> k_off(nsub + 1, 0), s_off(nsub + 1, 0), n_off(nsub + 1, 0), kc_off(nsub + 1, 0),
+    std::vector<int64_t> k_off(nsub + 1, 0), s_off(nsub + 1, 0), kc_off(nsub + 1, 0),
         m_off(nsub + 1, 0), x_off(nsub + 1, 0), phr_off(nsub + 1, 0);
-    std::vector<int32_t> gB, nodesI, cidx, pos_sub, cpos_sub;
+    std::vector<int32_t> gB, nodesI, cidx, pos_sub;
     for (int i = 0; i < nsub; ++i) {
         const SubHost &sh = st.sub[i];
         nI[i] = sh.nI; nB[i] = sh.nB; nc[i] = (int)sh.cidx.size();
@@ -1845,8 +1823,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         b_off[i + 1] = b_off[i] + sh.nB;
         c_off[i + 1] = c_off[i] + nc[i];
         k_off[i + 1] = k_off[i] + (int64_t)sh.nloc * sh.nloc;
-        s_off[i + 1] = s_off[i] + op_slots(sh.nB, 0) * 256;
-        n_off[i + 1] = n_off[i] + op_slots(sh.nB, nc[i]) * 256;
+        s_off[i + 1] = s_off[i] + op_slots(sh.nB) * 256;
         kc_off[i + 1] = kc_off[i] + (int64_t)nc[i] * nc[i];
         m_off[i + 1] = m_off[i] + (int64_t)(sh.nB + nc[i]) * (sh.nB + nc[i]);
         x_off[i + 1] = x_off[i] + (int64_t)sh.nB * nc[i];
@@ -1855,12 +1832,10 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         nodesI.insert(nodesI.end(), sh.nodes.begin(), sh.nodes.begin() + sh.nI);
         cidx.insert(cidx.end(), sh.cidx.begin(), sh.cidx.end());
         pos_sub.insert(pos_sub.end(), sh.nB, i);
-        cpos_sub.insert(cpos_sub.end(), nc[i], i);
         c->max_nI = std::max(c->max_nI, sh.nI);
         c->max_nB = std::max(c->max_nB, sh.nB);
         c->max_nc = std::max(c->max_nc, nc[i]);
         c->max_nt = std::max(c->max_nt, (sh.nB + TILE - 1) / TILE);
-        c->max_ntc = std::max(c->max_ntc, (nc[i] + TILE - 1) / TILE);
     }
     if (b_off[nsub] > INT32_MAX / 2) return fail(BDDC_EINVAL, "too many local interface entries");
     {   // prolongation blocks: 512 interface rows of one subdomain each
@@ -1870,17 +1845,16 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         c->n_pch = (int)ch_sub.size();
         if ((rc = dupload(c, &c->d_pch_sub, ch_sub)) || (rc = dupload(c, &c->d_pch_row, ch_row))) return rc;
     }
-    c->h_nB = nB; c->h_nI = nI; c->h_nc = nc; c->h_pos_sub = pos_sub; c->h_cpos_sub = cpos_sub;
+    c->h_nB = nB; c->h_nI = nI; c->h_nc = nc; c->h_pos_sub = pos_sub;
     c->h_b_off.assign(b_off.begin(), b_off.end() - 1);
     c->h_c_off.assign(c_off.begin(), c_off.end() - 1);
     if ((rc = dupload(c, &c->d_nI, nI)) || (rc = dupload(c, &c->d_nB, nB)) || (rc = dupload(c, &c->d_nc, nc)) ||
         (rc = dupload(c, &c->d_i_off, i_off)) || (rc = dupload(c, &c->d_b_off, b_off)) ||
         (rc = dupload(c, &c->d_c_off, c_off)) || (rc = dupload(c, &c->d_k_off, k_off)) ||
-        (rc = dupload(c, &c->d_s_off, s_off)) || (rc = dupload(c, &c->d_n_off, n_off)) ||
+        (rc = dupload(c, &c->d_s_off, s_off)) ||
         (rc = dupload(c, &c->d_phr_off, phr_off)) || (rc = dupload(c, &c->d_gB, gB)) ||
         (rc = dupload(c, &c->d_nodesI, nodesI)) || (rc = dupload(c, &c->d_cidx, cidx)) ||
-        (rc = dupload(c, &c->d_gamma, st.gamma)) || (rc = dupload(c, &c->d_pos_sub, pos_sub)) ||
-        (rc = dupload(c, &c->d_cpos_sub, cpos_sub)))
+        (rc = dupload(c, &c->d_gamma, st.gamma)) || (rc = dupload(c, &c->d_pos_sub, pos_sub)))
         return rc;
     // interface assembly lists (owner-computes, ordered by subdomain)
     {
@@ -1897,6 +1871,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         build_csr(c->nC, pr, ptr, idx);
         if ((rc = dupload(c, &c->d_casm_ptr, ptr)) || (rc = dupload(c, &c->d_casm_idx, idx))) return rc;
         c->h_casm_ptr = ptr; c->h_casm_idx = idx;
+        if ((rc = dalloc(c, &c->d_crest, (size_t)std::max(1, c_off[nsub])))) return rc;
     }
 
     // -------------------------------------------------- constrained Neumann operators
@@ -1931,15 +1906,16 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         if ((rc = dupload(c, &dsd, sd))) return rc;
         launch_build_saddle(dsd, nsub, s);
         if ((rc = run_sweeps(c, wd))) return rc;
-        // tiles: S_i (float64) and D N_i D with D Phi_i (local precision), plus
-        // the row-major D Phi_i for the prolongation
+        // tiles: S_i (float64) and D N_i D (local precision) in the same
+        // layout, plus the row-major D Phi_i for the coarse restriction and
+        // the prolongation
         c->bytes_S = (size_t)s_off[nsub] * 8;
-        c->bytes_N = (size_t)n_off[nsub] * eN;
+        c->bytes_N = (size_t)s_off[nsub] * eN;
         if ((rc = dalloc_tiles(c, &c->d_S, (size_t)s_off[nsub]))) return rc;
         for (int p : {64, 32, 16}) {
             if (!((c->prec_built >> prec_slot(p)) & 1)) continue;
             const int e = p / 8, q = prec_slot(p);
-            if ((rc = dalloc_tiles(c, (char **)&c->d_Nx[q], (size_t)n_off[nsub] * e)) ||
+            if ((rc = dalloc_tiles(c, (char **)&c->d_Nx[q], (size_t)s_off[nsub] * e)) ||
                 (rc = dalloc(c, (char **)&c->d_phirx[q], (size_t)std::max<int64_t>(1, phr_off[nsub]) * e)))
                 return rc;
         }
@@ -1951,7 +1927,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
             const int nl = st.sub[i].nloc, N = nB[i] + nc[i];
             const double *Sblk = c->d_K + k_off[i] + (int64_t)nI[i] * nl + nI[i];
             ps[i] = PackDesc{Sblk, nl, nB[i], 1.0, nullptr, nullptr, 0, 0, s_off[i], -1};
-            pn[i] = PackDesc{d_M + m_off[i], N, nB[i], -1.0, d_wB + b_off[i], d_M + m_off[i] + nB[i], N, nc[i], n_off[i],
+            pn[i] = PackDesc{d_M + m_off[i], N, nB[i], -1.0, d_wB + b_off[i], d_M + m_off[i] + nB[i], N, nc[i], s_off[i],
                              phr_off[i]};
             pt[i] = PtspDesc{Sblk, nl, d_M + m_off[i] + nB[i], N, -1.0, nB[i], nc[i], d_X + x_off[i], nullptr};
         }
@@ -2293,7 +2269,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
             op.bpc = pc[0];
             op.per_sub = pc[1] != 0;
             op.cfg = SymvCfg{pc[2], pc[3]};
-            op.smem = symv_smem(op.prec, op.cfg.nw, c->max_nt, w == 1 ? c->max_ntc : 0);
+            op.smem = symv_smem(op.prec, op.cfg.nw, c->max_nt);
             op.tuned_us = 0.f;
             if ((rc = build_worklist(c, op, product_blocks(c, op.n_tiles, op.bpc), op.per_sub))) return rc;
         }
@@ -2331,7 +2307,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
 constexpr int BMAX = 32;            // columns of one block solve
 
 struct BlockWork {
-    BlockItem *itemsS = nullptr, *itemsN = nullptr;
+    BlockItem *items = nullptr;     // one per subdomain (the Schur and Neumann tiles share the layout)
     int32_t *ones = nullptr;
     double *B = nullptr, *X = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr;
     double *yS = nullptr, *yN = nullptr, *cN = nullptr, *gp = nullptr, *gout = nullptr, *coef = nullptr;
@@ -2346,7 +2322,7 @@ struct BlockWork {
 };
 
 void free_block(bddc_ctx *c, BlockWork &b) {
-    dfree(c, b.itemsS); dfree(c, b.itemsN); dfree(c, b.ones);
+    dfree(c, b.items); dfree(c, b.ones);
     dfree(c, b.B); dfree(c, b.X); dfree(c, b.R); dfree(c, b.Z); dfree(c, b.P); dfree(c, b.Q);
     dfree(c, b.yS); dfree(c, b.yN); dfree(c, b.cN); dfree(c, b.gp); dfree(c, b.gout); dfree(c, b.coef);
     dfree(c, b.rC); dfree(c, b.uC); dfree(c, b.wloc); dfree(c, b.vI2); dfree(c, b.t2); dfree(c, b.rB2);
@@ -2357,20 +2333,18 @@ void free_block(bddc_ctx *c, BlockWork &b) {
 
 int alloc_block(bddc_ctx *c, BlockWork &b) {
     const int nsub = c->n_sub;
-    std::vector<BlockItem> is(nsub), in(nsub);
-    int64_t ts = 0, tn = 0;
+    std::vector<BlockItem> is(nsub);
+    int64_t ts = 0;
     for (int i = 0; i < nsub; ++i) {
-        is[i] = BlockItem{ts, c->h_nB[i], 0, c->h_b_off[i], c->h_c_off[i]};
-        in[i] = BlockItem{tn, c->h_nB[i], c->h_nc[i], c->h_b_off[i], c->h_c_off[i]};
-        ts += op_slots(c->h_nB[i], 0);
-        tn += op_slots(c->h_nB[i], c->h_nc[i]);
+        is[i] = BlockItem{ts, c->h_nB[i], c->h_b_off[i]};
+        ts += op_slots(c->h_nB[i]);
     }
     b.ylen = std::max<int64_t>(1, (int64_t)c->h_b_off[nsub - 1] + c->h_nB[nsub - 1]);
     b.clen = std::max<int64_t>(1, (int64_t)c->h_c_off[nsub - 1] + c->h_nc[nsub - 1]);
     const size_t nv = (size_t)c->ld * BMAX;
     int rc;
     std::vector<int32_t> ones(nsub, 1);
-    if ((rc = dupload(c, &b.itemsS, is)) || (rc = dupload(c, &b.itemsN, in)) || (rc = dupload(c, &b.ones, ones)) ||
+    if ((rc = dupload(c, &b.items, is)) || (rc = dupload(c, &b.ones, ones)) ||
         (rc = dalloc(c, &b.B, nv)) || (rc = dalloc(c, &b.X, nv)) || (rc = dalloc(c, &b.R, nv)) ||
         (rc = dalloc(c, &b.Z, nv)) || (rc = dalloc(c, &b.P, nv)) || (rc = dalloc(c, &b.Q, nv)) ||
         (rc = dalloc(c, &b.yS, (size_t)b.ylen * BMAX)) || (rc = dalloc(c, &b.yN, (size_t)b.ylen * BMAX)) ||
@@ -2398,7 +2372,7 @@ int alloc_block(bddc_ctx *c, BlockWork &b) {
     // partial slots that no kernel writes (none with one chunk per subdomain) stay zero
     launch_fill((int64_t)b.ylen * BMAX, 0.0, b.yN, c->stream);
     launch_fill((int64_t)b.clen * BMAX, 0.0, b.cN, c->stream);
-    b.smem = symm_smem_bytes(c->max_nB, c->max_nc);
+    b.smem = symm_smem_bytes(c->max_nB);
     return 0;
 }
 
@@ -2436,46 +2410,58 @@ int block_gemm(bddc_ctx *c, BlockWork &b, const double *V1, int k1, const double
 void block_A(bddc_ctx *c, BlockWork &b, const double *X, int ncols, double *out) {
     TScope ts(c, TK_SCHUR);
     BlockSymvArgs a{};
-    a.tiles = c->d_S; a.items = b.itemsS; a.gB = c->d_gB; a.X = X; a.ldx = c->ld; a.ncols = ncols;
+    a.tiles = c->d_S; a.items = b.items; a.gB = c->d_gB; a.X = X; a.ldx = c->ld; a.ncols = ncols;
     a.ypart = b.yS; a.ylen = b.ylen;
-    launch_symm(a, c->n_sub, false, b.smem, c->stream);
+    launch_symm(a, c->n_sub, b.smem, c->stream);
     launch_gather_block(c->n_gamma, c->d_asm_ptr, c->d_asm_idx, b.yS, b.ylen, out, c->ld, ncols, c->stream);
 }
 
+// The coarse levels of block_M on stream st: restriction of all columns,
+// then the coarse problems (one grid row per column).
+void block_coarse(bddc_ctx *c, BlockWork &b, const double *R, int ncols, hipStream_t st) {
+    TScope ts(c, TK_COARSE);
+    CrestArgs ra{};
+    ra.ctl = c->d_ctl;
+    ra.nB = c->d_nB; ra.b_off = c->d_b_off; ra.gB = c->d_gB; ra.nc = c->d_nc; ra.c_off = c->d_c_off;
+    ra.phir = c->d_phirx[prec_slot(64)]; ra.phr_off = c->d_phr_off;
+    ra.X = R; ra.ldx = c->ld; ra.part = b.cN; ra.cs = b.clen; ra.ncols = ncols;
+    ra.rows = (int)crest_rows(c->max_nB, ncols);
+    launch_crest(ra, 64, c->n_sub, st);
+    const Gather rc{c->d_casm_ptr, c->d_casm_idx, b.cN};
+    if (c->coarse_dense) {
+        CoarseDenseArgs ca{};
+        ca.ctl = c->d_ctl; ca.n = c->nC; ca.rc = rc; ca.r = b.rC; ca.M = c->d_Mc; ca.ldm = c->ldm;
+        ca.sign = c->three ? 1.0 : -1.0; ca.u = b.uC;
+        ca.cs_rc = b.clen; ca.cs_r = b.nclen; ca.cs_u = b.nclen;
+        launch_coarse_dense(ca, st, ncols);
+    } else {
+        L2Args l = l2_args(c, rc);
+        l.vI2 = b.vI2; l.t2 = b.t2; l.rB2 = b.rB2; l.u2 = b.u2; l.c3loc = b.c3loc; l.u3 = b.u3; l.uC = b.uC;
+        l.cs_rc = b.clen; l.cs_vI2 = b.i2len; l.cs_t2 = b.b2len; l.cs_rB2 = b.b2len; l.cs_u2 = b.b2len;
+        l.cs_c3loc = b.c3len; l.cs_u3 = b.n3len; l.cs_uC = b.nclen;
+        launch_l2_a(l, c->nsr, c->max_nL, st, ncols);
+        launch_l2_b(l, c->nsr, c->max_nL, st, ncols);
+        CoarseDenseArgs l3{};
+        l3.ctl = c->d_ctl; l3.n = c->n3; l3.rc = Gather{c->d_asm3_ptr, c->d_asm3_idx, b.c3loc}; l3.r = b.r3;
+        l3.M = c->d_K3inv; l3.ldm = c->ld3; l3.sign = -1.0; l3.u = b.u3;
+        l3.cs_rc = b.c3len; l3.cs_r = b.n3len; l3.cs_u = b.n3len;
+        launch_coarse_dense(l3, st, ncols);
+        launch_l2_d(l, c->nsr, c->smem_l2d, st, ncols);
+    }
+}
+
+// BDDC on ncols columns of R (stride ld) into Z: the block products of the
+// float64 Neumann operators, then the coarse levels, prolongation and
+// assembly with the single-vector kernels, one grid row per column.
 void block_M(bddc_ctx *c, BlockWork &b, const double *R, int ncols, double *Z) {
     {
         TScope ts(c, TK_PREC);
         BlockSymvArgs a{};
-        a.tiles = (const double *)c->d_Nx[prec_slot(64)]; a.items = b.itemsN; a.gB = c->d_gB; a.X = R; a.ldx = c->ld;
-        a.ncols = ncols; a.ypart = b.yN; a.ylen = b.ylen; a.cpart = b.cN; a.clen = b.clen;
-        launch_symm(a, c->n_sub, true, b.smem, c->stream);
+        a.tiles = (const double *)c->d_Nx[prec_slot(64)]; a.items = b.items; a.gB = c->d_gB; a.X = R; a.ldx = c->ld;
+        a.ncols = ncols; a.ypart = b.yN; a.ylen = b.ylen;
+        launch_symm(a, c->n_sub, b.smem, c->stream);
     }
-    // the coarse levels, the prolongation and the assembly of all columns at
-    // once: the single-vector kernels with one grid row per column
-    const Gather rc{c->d_casm_ptr, c->d_casm_idx, b.cN};
-    if (c->nC > 0) {
-        TScope ts(c, TK_COARSE);
-        if (c->coarse_dense) {
-            CoarseDenseArgs ca{};
-            ca.ctl = c->d_ctl; ca.n = c->nC; ca.rc = rc; ca.r = b.rC; ca.M = c->d_Mc; ca.ldm = c->ldm;
-            ca.sign = c->three ? 1.0 : -1.0; ca.u = b.uC;
-            ca.cs_rc = b.clen; ca.cs_r = b.nclen; ca.cs_u = b.nclen;
-            launch_coarse_dense(ca, c->stream, ncols);
-        } else {
-            L2Args l = l2_args(c, rc);
-            l.vI2 = b.vI2; l.t2 = b.t2; l.rB2 = b.rB2; l.u2 = b.u2; l.c3loc = b.c3loc; l.u3 = b.u3; l.uC = b.uC;
-            l.cs_rc = b.clen; l.cs_vI2 = b.i2len; l.cs_t2 = b.b2len; l.cs_rB2 = b.b2len; l.cs_u2 = b.b2len;
-            l.cs_c3loc = b.c3len; l.cs_u3 = b.n3len; l.cs_uC = b.nclen;
-            launch_l2_a(l, c->nsr, c->max_nL, c->stream, ncols);
-            launch_l2_b(l, c->nsr, c->max_nL, c->stream, ncols);
-            CoarseDenseArgs l3{};
-            l3.ctl = c->d_ctl; l3.n = c->n3; l3.rc = Gather{c->d_asm3_ptr, c->d_asm3_idx, b.c3loc}; l3.r = b.r3;
-            l3.M = c->d_K3inv; l3.ldm = c->ld3; l3.sign = -1.0; l3.u = b.u3;
-            l3.cs_rc = b.c3len; l3.cs_r = b.n3len; l3.cs_u = b.n3len;
-            launch_coarse_dense(l3, c->stream, ncols);
-            launch_l2_d(l, c->nsr, c->smem_l2d, c->stream, ncols);
-        }
-    }
+    if (c->nC > 0) block_coarse(c, b, R, ncols, c->stream);
     TScope ts(c, TK_VEC);
     ProlArgs pa{};
     pa.ctl = c->d_ctl; pa.gated = 0;
@@ -2763,7 +2749,7 @@ int bddc_adjoint_grad_block(bddc_ctx *c, const double *dLdu_seq, int32_t n_rhs, 
     if (c->nullc) return fail(BDDC_EINVAL, "bddc_adjoint_grad_block: not for the pure Neumann problem");
     if (!(c->prec_built & 1))
         return fail(BDDC_EINVAL, "bddc_adjoint_grad_block: needs the float64 Neumann operators (local_prec 64 or local_prec_set bit 1)");
-    if (symm_smem_bytes(c->max_nB, c->max_nc) > 160 * 1024)
+    if (symm_smem_bytes(c->max_nB) > 160 * 1024)
         return fail(BDDC_EINVAL, "bddc_adjoint_grad_block: a subdomain interface is too large for the block product");
     if (iters) *iters = 0;
     if (n_rhs == 0) {
@@ -2776,7 +2762,7 @@ int bddc_adjoint_grad_block(bddc_ctx *c, const double *dLdu_seq, int32_t n_rhs, 
         int rc0;
         if ((rc0 = end_sync_issue(c, false)) || (rc0 = end_sync_wait(c))) return rc0;
     }
-    if (set_symm_smem_limit(symm_smem_bytes(c->max_nB, c->max_nc))) return fail(BDDC_EHIP, "hipFuncSetAttribute (block product LDS) failed");
+    if (set_symm_smem_limit(symm_smem_bytes(c->max_nB))) return fail(BDDC_EHIP, "hipFuncSetAttribute (block product LDS) failed");
     BlockWork b;
     int rc = alloc_block(c, b);
     double *xsave = nullptr;
@@ -2800,7 +2786,7 @@ int bddc_adjoint_grad_block(bddc_ctx *c, const double *dLdu_seq, int32_t n_rhs, 
     }
     if (rc) { launch_copy(c->n_gamma, xsave, c->d_x, c->stream); (void)hipStreamSynchronize(c->stream); dfree(c, xsave); free_block(c, b); return rc; }
     // (set_symm_smem_limit again: the grouped condensation set its own)
-    if (set_symm_smem_limit(symm_smem_bytes(c->max_nB, c->max_nc))) rc = fail(BDDC_EHIP, "hipFuncSetAttribute (block product LDS) failed");
+    if (set_symm_smem_limit(symm_smem_bytes(c->max_nB))) rc = fail(BDDC_EHIP, "hipFuncSetAttribute (block product LDS) failed");
     int it = 0;
     if (!rc) rc = block_solve(c, b, n_rhs, rtol, &it);
     if (iters) *iters = it;
@@ -2881,7 +2867,7 @@ int bddc_apply_schur(bddc_ctx *c, const double *p, double *q) {
     if (!c || !p || !q) return fail(BDDC_EINVAL, "null argument");
     run_schur(c, p, false, false);
     ResidArgs a{};
-    a.n = c->n_gamma; a.want_wtr = 0; a.q = gather_of(c->opS, false); a.b = nullptr; a.out = q;
+    a.n = c->n_gamma; a.want_wtr = 0; a.q = gather_of(c->opS); a.b = nullptr; a.out = q;
     a.W = c->d_W; a.ld = c->ld; a.ctl = c->d_ctl; a.part = c->d_wp;
     launch_resid(a, 0, c->vgrid, c->stream);
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -3050,7 +3036,7 @@ int bddc_time_products(bddc_ctx *c, int32_t reps, double *out) {
     for (int w = 0; w < 2 && rc == 0; ++w) {
         const OpHost &op = *ops[w];
         SymvArgs a{};
-        a.op = op.dev; a.x = c->d_x; a.ypart = op.d_ypart; a.cpart = op.d_cpart; a.ctl = c->d_ctl;
+        a.op = op.dev; a.x = c->d_x; a.ypart = op.d_ypart; a.ctl = c->d_ctl;
         launch_symv(a, (SymvOp)w, op.prec, op.cfg, op.smem, c->stream);   // warm
         hipError_t e = hipEventRecord(e0, c->stream);
         for (int r = 0; r < reps && e == hipSuccess; ++r) launch_symv(a, (SymvOp)w, op.prec, op.cfg, op.smem, c->stream);
@@ -3080,10 +3066,10 @@ int bddc_set_local_prec(bddc_ctx *c, int32_t prec) {
     OpHost &op = c->opN;
     op.prec = prec;
     op.dev.tiles = c->d_N;
-    op.bytes = product_bytes(c, true, prec);
+    op.bytes = product_bytes(c, prec);
     c->bytes_N = (size_t)op.n_tiles * 256 * (size_t)(prec / 8);
     c->t_bytes[TK_PREC] = op.bytes;
-    op.smem = symv_smem(prec, op.cfg.nw, c->max_nt, c->max_ntc);
+    op.smem = symv_smem(prec, op.cfg.nw, c->max_nt);
     if (c->opts.autotune) {
         int rc = tune_operators(c, 2);
         if (rc) return rc;
@@ -3121,7 +3107,7 @@ int bddc_set_launch(bddc_ctx *c, int32_t use_graph, const int32_t *product_cfg) 
                 op.per_sub = true;
                 op.cfg = SymvCfg{4, 2};
             }
-            op.smem = symv_smem(op.prec, op.cfg.nw, c->max_nt, w == 1 ? c->max_ntc : 0);
+            op.smem = symv_smem(op.prec, op.cfg.nw, c->max_nt);
             op.tuned_us = 0.f;
             if (int rc = build_worklist(c, op, product_blocks(c, op.n_tiles, op.bpc), op.per_sub)) return rc;
         }
@@ -3170,7 +3156,7 @@ int bddc_time_kernels(bddc_ctx *c, int32_t reps, double *out, int32_t n) {
     for (int w = 0; w < 3; ++w) {
         const OpHost &op = *ops[w];
         SymvArgs a{};
-        a.op = op.dev; a.x = w == 2 ? c->d_tmpN : c->d_x; a.ypart = op.d_ypart; a.cpart = op.d_cpart; a.ctl = c->d_ctl;
+        a.op = op.dev; a.x = w == 2 ? c->d_tmpN : c->d_x; a.ypart = op.d_ypart; a.ctl = c->d_ctl;
         double bytes = op.bytes;
         if (w == 2) {   // packed K_II^{-1}, gathered input and index, output
             bytes = 0.0;
@@ -3183,7 +3169,7 @@ int bddc_time_kernels(bddc_ctx *c, int32_t reps, double *out, int32_t n) {
     }
     const double cb = coarse_bytes(c), pb = prolong_bytes(c);
     timed(3, c->opN.bytes + cb + pb, [&] { run_precond(c, c->d_r, c->d_tmp, 0, false, false, false); });
-    timed(4, cb, [&] { run_coarse(c); });
+    timed(4, cb, [&] { run_coarse(c, c->d_r, c->stream); });
     timed(5, pb, [&] { run_prolong_assemble(c, c->d_r, c->d_tmp, false, false, false); });
     c->timing = tk;
     (void)hipEventDestroy(e0);

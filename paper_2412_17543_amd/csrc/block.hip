@@ -1,8 +1,8 @@
-// Block products of the block adjoint (several right-hand sides at once):
-// the batched symmetric products y_i = S_i x_i (Schur) and, with the coarse
-// rows, u_i = D N_i D g_i and c_i = (D Phi_i)^T g_i (Neumann, eq. localCorr)
-// for 16 columns at a time, on the matrix cores, and the assembly of the
-// per-subdomain results.
+// Block products of the block adjoint and of grouped condensation (several
+// right-hand sides at once): the batched symmetric products y_i = S_i x_i
+// (Schur), u_i = D N_i D g_i (Neumann, eq. localCorr) or K_II^{-1} b_i
+// (interior), 16 columns at a time, on the matrix cores, and the assembly of
+// the per-subdomain results.
 //
 // k_symm: one block per (subdomain, 16-column chunk), 4 waves; a wave keeps
 // PF tiles in flight (a fixed ring of load slots, reissued on every step).  The block
@@ -11,7 +11,6 @@
 // (J = I + q):
 //   row part    Y_I += T X_J          (accumulated in the wave's registers)
 //   column part Y_J += T^T X_I, J > I (added to LDS; each J once per row)
-//   coarse tile C_{J - nt} += T^T X_I (Neumann only; T holds rows of D Phi_i)
 // After the row the waves' row parts are added into Y_I in wave order, so
 // every entry is summed in a fixed order (the product is reproducible bit by
 // bit).  A short ragged tail stored as a strip after the tiles (uses_strip)
@@ -58,19 +57,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *p, int64_
 }
 
 // The tiles of one wave in order: rows I = 0, 1, ... and in row I the tiles
-// q = w, w + 4, ... (len = nt - I + ntc of them); `tile` is the index in the
+// q = w, w + 4, ... (nt - I of them); `tile` is the index in the
 // subdomain's packed sequence, past the end once the wave has no more.
 struct TileSeq {
-    int I, q, nt, ntc, w;
+    int I, q, nt, w;
     int64_t base;
     __device__ void norm() {
-        while (I < nt && q >= nt - I + ntc) { base += nt - I + ntc; ++I; q = w; }
+        while (I < nt && q >= nt - I) { base += nt - I; ++I; q = w; }
     }
     __device__ void next() { q += 4; norm(); }
     __device__ int64_t tile(int64_t total) const { return I < nt ? base + q : total; }
 };
 
-template <bool COARSE>
 __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
     extern __shared__ __align__(16) double sm[];
     // the column chunks of one subdomain are adjacent blocks: they run at the
@@ -78,19 +76,19 @@ __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
     const int nch = (a.ncols + 15) / 16;
     const BlockItem it = a.items[blockIdx.x / nch];
     const int c0 = 16 * (int)(blockIdx.x % nch);
-    const int n = it.n, nc = COARSE ? it.nc : 0, ntc = (nc + 15) / 16;
-    const int nt = tile_rows(n, nc), npad = 16 * ((n + 15) / 16);   // nt: tile rows (without a strip's rows)
-    const int64_t total = full_tiles(n, nc);
+    const int n = it.n;
+    const int nt = tile_rows(n), npad = 16 * ((n + 15) / 16);   // nt: tile rows (without a strip's rows)
+    const int64_t total = full_tiles(n);
     double *xs = sm;                                   // npad x 16 (stride XS)
-    double *ys = xs + (size_t)npad * XS;               // (npad + 16 ntc) x 16
-    double *ts = ys + (size_t)(npad + 16 * ntc) * XS;  // 4 tiles of 16 x 16
+    double *ys = xs + (size_t)npad * XS;               // npad x 16
+    double *ts = ys + (size_t)npad * XS;               // 4 tiles of 16 x 16
     double *red = ts + 4 * 16 * XS;                    // 4 x 256
     const int tid = threadIdx.x, w = tid >> 6, L = tid & 63, li = L & 15, lk = L >> 4;
     const int wu = __builtin_amdgcn_readfirstlane(w);
     const int32_t *gb = a.gB + it.xoff;
     // the wave's first PF tiles are requested before anything else
     const __amdgpu_buffer_rsrc_t rs = raw_rsrc(a.tiles + it.tile * 256, total * 2048);
-    TileSeq ld{0, wu, nt, ntc, wu, 0};
+    TileSeq ld{0, wu, nt, wu, 0};
     ld.norm();
     uvec4 fa[PF], fb[PF];
 #pragma unroll
@@ -120,7 +118,7 @@ __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
             if (e < 16 * npad) xs[k * XS + cc] = v[u];
         }
     }
-    for (int e = tid; e < (npad + 16 * ntc) * XS; e += 256) ys[e] = 0.0;
+    for (int e = tid; e < npad * XS; e += 256) ys[e] = 0.0;
     __syncthreads();
     double *tw = ts + w * 16 * XS;
     dvec4 racc = {0.0, 0.0, 0.0, 0.0};
@@ -138,7 +136,7 @@ __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
         lds_barrier();
         racc = dvec4{0.0, 0.0, 0.0, 0.0};
     };
-    TileSeq cur{0, wu, nt, ntc, wu, 0};
+    TileSeq cur{0, wu, nt, wu, 0};
     cur.norm();
     // one tile from ring slot d, whose load is then reissued for the tile PF
     // places later (slots are never copied, so no wait but for slot d's own load)
@@ -160,21 +158,18 @@ __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
         ld.next();
         if (!valid) return;
         wave_sync();
-        if (J < nt) {
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-                racc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[li * XS + 4 * s + lk],
-                                                            xs[(16 * J + 4 * s + lk) * XS + li], racc, 0, 0, 0);
-        }
+        for (int s = 0; s < 4; ++s)
+            racc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[li * XS + 4 * s + lk],
+                                                        xs[(16 * J + 4 * s + lk) * XS + li], racc, 0, 0, 0);
         if (J > I) {
             dvec4 cacc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int s = 0; s < 4; ++s)
                 cacc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[(4 * s + lk) * XS + li],
                                                             xs[(16 * I + 4 * s + lk) * XS + li], cacc, 0, 0, 0);
-            const int r0 = J < nt ? 16 * J : npad + 16 * (J - nt);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) ys[(r0 + 4 * r + lk) * XS + li] += cacc[r];
+            for (int r = 0; r < 4; ++r) ys[(16 * J + 4 * r + lk) * XS + li] += cacc[r];
         }
         wave_sync();
         cur.next();
@@ -189,14 +184,13 @@ __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
 #pragma unroll
     for (int d = 0; d < PF; ++d) asm volatile("" ::"v"(fa[d]), "v"(fb[d]));
     // The ragged tail rows n0 + r, r < rem, stored whole as a row-major strip
-    // after the tiles: one more tile row, whose 16-column chunks are the node
-    // chunks q < nt (row part and column part, as for a tile), the corner
-    // q = nt (the full rem x rem block: row part only) and the coarse chunks
-    // (column part only).  Wave w takes the chunks q = w, w + 4, ...; a
-    // chunk's rows of Y (or C) belong to that wave alone.
-    const int rem = uses_strip(n, nc) ? n % 16 : 0;
+    // after the tiles: one more tile row, whose 16-column chunks are the
+    // chunks q < nt (row part and column part, as for a tile) and the corner
+    // q = nt (the full rem x rem block: row part only).  Wave w takes the
+    // chunks q = w, w + 4, ...; a chunk's rows of Y belong to that wave alone.
+    const int rem = uses_strip(n) ? n % 16 : 0;
     if (rem > 0) {
-        const int n0 = 16 * nt, m = n + nc, nq = nt + 1 + ntc;
+        const int n0 = 16 * nt, nq = nt + 1;
         const double *sp = a.tiles + (it.tile + total) * 256;
         constexpr int G = 4;        // chunks whose entries are requested together
         for (int q0 = wu; q0 < nq; q0 += 4 * G) {
@@ -204,12 +198,12 @@ __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int q = q0 + 4 * g;
-                const int cb = q < nt ? 16 * q : q == nt ? n0 : n + 16 * (q - nt - 1);
-                const int cv = q < nt ? 16 : q == nt ? rem : min(16, nc - 16 * (q - nt - 1));
+                const int cb = q < nt ? 16 * q : n0;
+                const int cv = q < nt ? 16 : rem;
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const int r = 4 * lk + s;
-                    v[g][s] = (q < nq && r < rem && li < cv) ? sp[(int64_t)r * m + cb + li] : 0.0;
+                    v[g][s] = (q < nq && r < rem && li < cv) ? sp[(int64_t)r * n + cb + li] : 0.0;
                 }
             }
 #pragma unroll
@@ -219,21 +213,19 @@ __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
 #pragma unroll
                 for (int s = 0; s < 4; ++s) tw[(4 * lk + s) * XS + li] = v[g][s];
                 wave_sync();
-                if (q <= nt) {          // row part: Y_rag += T X_q (the corner: X rows n0..)
+                // row part: Y_rag += T X_q (the corner: X rows n0..)
 #pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        racc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[li * XS + 4 * s + lk],
-                                                                    xs[(16 * q + 4 * s + lk) * XS + li], racc, 0, 0, 0);
-                }
-                if (q != nt) {          // column part: Y_q (or C) += T^T X_rag
+                for (int s = 0; s < 4; ++s)
+                    racc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[li * XS + 4 * s + lk],
+                                                                xs[(16 * q + 4 * s + lk) * XS + li], racc, 0, 0, 0);
+                if (q != nt) {          // column part: Y_q += T^T X_rag
                     dvec4 cacc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                     for (int s = 0; s < 4; ++s)
                         cacc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[(4 * s + lk) * XS + li],
                                                                     xs[(n0 + 4 * s + lk) * XS + li], cacc, 0, 0, 0);
-                    const int r0 = q < nt ? 16 * q : npad + 16 * (q - nt - 1);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) ys[(r0 + 4 * r + lk) * XS + li] += cacc[r];
+                    for (int r = 0; r < 4; ++r) ys[(16 * q + 4 * r + lk) * XS + li] += cacc[r];
                 }
                 wave_sync();
             }
@@ -243,12 +235,6 @@ __global__ void __launch_bounds__(256) k_symm(BlockSymvArgs a) {
     for (int e = tid; e < 16 * n; e += 256) {
         const int cc = e / n, k = e - cc * n, col = c0 + cc;
         if (col < a.ncols) a.ypart[(int64_t)col * a.ylen + it.xoff + k] = ys[k * XS + cc];
-    }
-    if (COARSE) {
-        for (int e = tid; e < 16 * nc; e += 256) {
-            const int cc = e / nc, q = e - cc * nc, col = c0 + cc;
-            if (col < a.ncols) a.cpart[(int64_t)col * a.clen + it.coff + q] = ys[(npad + q) * XS + cc];
-        }
     }
 }
 
@@ -269,25 +255,21 @@ __global__ void __launch_bounds__(256) k_gather_block(int n, const int32_t *ptr,
 
 }  // namespace
 
-size_t symm_smem_bytes(int max_n, int max_nc) {
-    const int npad = 16 * ((max_n + 15) / 16), ncpad = 16 * ((max_nc + 15) / 16);
-    return sizeof(double) * ((size_t)(2 * npad + ncpad) * XS + 4 * 16 * XS + 4 * 256);
+size_t symm_smem_bytes(int max_n) {
+    const int npad = 16 * ((max_n + 15) / 16);
+    return sizeof(double) * ((size_t)2 * npad * XS + 4 * 16 * XS + 4 * 256);
 }
 
 int set_symm_smem_limit(size_t bytes) {
-    if (hipFuncSetAttribute((const void *)k_symm<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
-            hipSuccess ||
-        hipFuncSetAttribute((const void *)k_symm<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
-            hipSuccess)
-        return 1;
-    return 0;
+    return hipFuncSetAttribute((const void *)k_symm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+                   hipSuccess
+               ? 1
+               : 0;
 }
 
-void launch_symm(const BlockSymvArgs &a, int nsub, bool coarse, size_t smem, hipStream_t s) {
+void launch_symm(const BlockSymvArgs &a, int nsub, size_t smem, hipStream_t s) {
     if (nsub <= 0 || a.ncols <= 0) return;
-    const dim3 grid(nsub * ((a.ncols + 15) / 16));
-    if (coarse) hipLaunchKernelGGL(k_symm<true>, grid, dim3(256), smem, s, a);
-    else hipLaunchKernelGGL(k_symm<false>, grid, dim3(256), smem, s, a);
+    hipLaunchKernelGGL(k_symm, dim3(nsub * ((a.ncols + 15) / 16)), dim3(256), smem, s, a);
 }
 
 void launch_gather_block(int n, const int32_t *ptr, const int32_t *idx, const double *part, int64_t plen, double *out,

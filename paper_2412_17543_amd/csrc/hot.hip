@@ -6,7 +6,8 @@
 // graph and replayed:
 //   k_symv (S)   q_i = S_i p_i                      Alg. 1 line 9 (A p)
 //   k_update     alpha, x += alpha p, r -= alpha q  lines 9-11
-//   k_symv (N)   stopping test (Section 5); u_i = D N_i D r_i, c_i = (D Phi_i)^T r_i
+//   k_symv (N)   stopping test (Section 5); u_i = D N_i D r_i
+//   k_crest      c_i = (D Phi_i)^T r_i (coarse residual partials)
 //   coarse       k_coarse_dense (two levels, or three levels in explicit form);
 //                three levels as a chain: k_l2_a, k_l2_b, level 3 by the
 //                dense product, k_l2_d
@@ -297,17 +298,17 @@ __device__ __forceinline__ void cm_matvec(const double *M, int64_t ldm, int r0, 
 __device__ __forceinline__ SymvItem load_item(const SymvItem *items, int i) {
     typedef const __attribute__((address_space(4))) int32_t CInt;
     CInt *q = (CInt *)(items + i);
-    return SymvItem{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9], q[10], q[11]};
+    return SymvItem{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9]};
 }
 
 template <typename T, int U>
 constexpr int symv_waves_per_simd() { return (sizeof(T) == 8 && U == 4) ? 4 : 6; }
 
 // Name tags of the three operator batches (the kernel is the same; only the
-// Neumann batch has coarse-basis tiles and a stopping test).
-struct OpSchur { static constexpr bool coarse = false; };
-struct OpNeumann { static constexpr bool coarse = true; };
-struct OpInterior { static constexpr bool coarse = false; };
+// Neumann batch makes the stopping test).
+struct OpSchur { static constexpr bool test = false; };
+struct OpNeumann { static constexpr bool test = true; };
+struct OpInterior { static constexpr bool test = false; };
 
 template <typename T, int NW, int U, typename OP>
 __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv(SymvArgs a) {
@@ -318,7 +319,8 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
     constexpr int GATHER_PER_THREAD = NT >= 512 ? 1 : 512 / NT;
     constexpr int SR = 4;           // strip rows per pass (registers)
     // the first pass requested with the gathered values where registers allow
-    constexpr bool STRIP_EARLY = sizeof(T) == 2 || (sizeof(T) == 4 && U == 2) || (sizeof(T) == 8 && U == 4 && !OP::coarse);
+    // (not beside the stopping test's registers in the float64 Neumann batch)
+    constexpr bool STRIP_EARLY = sizeof(T) == 2 || (sizeof(T) == 4 && U == 2) || (sizeof(T) == 8 && U == 4 && !OP::test);
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g4 = 4 * (l >> 4), cl = l & 15;
     const int wu = __builtin_amdgcn_readfirstlane(w);     // wave-uniform control flow
     // Segment records are block-uniform: read through the constant address
@@ -331,7 +333,7 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
     // used.
     SymvItem it = load_item(a.op.items, blockIdx.x);
     if (a.gated && block_done(a.ctl)) return;
-    const bool test_here = OP::coarse && a.test && !(a.defer && a.ctl->record);
+    const bool test_here = OP::test && a.test && !(a.defer && a.ctl->record);
 
     // Tiles past w1 read as zero without a memory access (resource over tiles
     // [t, w1) for the stage starting at tile t), so the loads of the next U
@@ -344,9 +346,8 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
         const int n = it.n;
         const T *tb = reinterpret_cast<const T *>(a.op.tiles) + (int64_t)it.tile * 256;
         const int32_t *gb = a.op.gB + it.x_off;
-        const int ncs = OP::coarse ? it.nc : 0;
-        const int ntf = it.ntf, ntc = (ncs + TILE - 1) / TILE;   // tile rows, coarse tiles per row
-        const int ntl = it.ntl;                                  // the tiles; a strip's slots follow
+        const int ntf = it.ntf;     // tile rows
+        const int ntl = it.ntl;     // the tiles; a strip's slots follow
         // the waves split the segment's tiles; the segment holding slot ntl
         // also takes the ragged tail's strip (after its tiles)
         const int span = max(min(it.t1, ntl) - it.t0, 0);
@@ -367,19 +368,18 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
         const int npad = ((n + TILE - 1) / TILE) * TILE;
         ACC *xs = reinterpret_cast<ACC *>(smem_raw);
         ACC *yw = xs + npad;
-        ACC *cw = yw + NW * npad;
         double xv[GATHER_PER_THREAD];
     #pragma unroll
         for (int j = 0; j < GATHER_PER_THREAD; ++j) xv[j] = a.x[gi[j]];
         asm volatile("" ::: "memory");                        // (the gathered values before fb)
         // the strip segment: its first SR rows at column tid, requested before
         // the second tile stage and applied right after the staging below
-        const int rem = n % TILE, m = n + ncs, n0 = n - rem;
+        const int rem = n % TILE, n0 = n - rem;
         const T *sp = tb + (int64_t)ntl * 256;
         T sv[SR];
         if (STRIP_EARLY && strip_here) {
     #pragma unroll
-            for (int r = 0; r < SR; ++r) sv[r] = (r < rem && tid < m) ? sp[(int64_t)r * m + tid] : (T)0;
+            for (int r = 0; r < SR; ++r) sv[r] = (r < rem && tid < n) ? sp[(int64_t)r * n + tid] : (T)0;
         }
         asm volatile("" ::: "memory");
     #pragma unroll
@@ -391,17 +391,15 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
         }
         for (int k = tid + GATHER_PER_THREAD * NT; k < npad; k += NT) xs[k] = k < n ? (ACC)a.x[gb[k]] : (ACC)0;
         for (int k = tid; k < NW * npad; k += NT) yw[k] = (ACC)0;
-        for (int k = tid; k < NW * ntc * TILE; k += NT) cw[k] = (ACC)0;
         __syncthreads();
 
         ACC *myy = yw + wu * npad;
-        ACC *myc = cw + wu * ntc * TILE;
         // Ragged tail rows n0 + r (r < n % 16), stored whole: rows r0..r0+SR-1 at
         // column k = k0 + tid (entries v, zero past the strip).  The thread
-        // adds S[n0+r][k] x[n0+r] into y_k (node columns below n0) or
-        // c_(k-n) (coarse columns); the products S[n0+r][k] x_k of the node
-        // columns are summed over the wave and added into y_(n0+r).  Every
-        // addition goes into the thread's own wave's partials, in a fixed order.
+        // adds S[n0+r][k] x[n0+r] into y_k (columns below n0); the products
+        // S[n0+r][k] x_k are summed over the wave and added into y_(n0+r).
+        // Every addition goes into the thread's own wave's partials, in a
+        // fixed order.
         auto strip_rows = [&](int k0, int r0, const T (&v)[SR]) {
             const int k = k0 + tid;
             const ACC xk = k < n ? xs[k] : (ACC)0;
@@ -416,7 +414,6 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
                 }
             }
             if (k < n0) myy[k] += t;
-            else if (k >= n && k < m) myc[k - n] += t;
         };
         if (STRIP_EARLY && strip_here) strip_rows(0, 0, sv);
         if (w0 >= w1) {
@@ -424,7 +421,7 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
             for (int u = 0; u < U; ++u) { fa[u].settle(); fb[u].settle(); }
         } else {
             int I = 0, rs = 0;
-            while (rs + (ntf - I + ntc) <= w0) { rs += ntf - I + ntc; ++I; }
+            while (rs + (ntf - I) <= w0) { rs += ntf - I; ++I; }
             int J = I + (w0 - rs);
             ACC xi[4], ra[4];
     #pragma unroll
@@ -438,17 +435,15 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
                     const bool live = t + u < w1;
                     ACC v[4];
                     f[u].get(v);
-                    // no direct part in coarse columns, nor past the range
+                    // no direct part past the range (J < ntf holds for a live
+                    // tile; the test keeps the float64 Schur variants free of spills)
                     const ACC xj = (live && J < ntf) ? xs[J * TILE + cl] : (ACC)0;
     #pragma unroll
                     for (int q = 0; q < 4; ++q) ra[q] += v[q] * xj;
                     const ACC s = col_sum4(v[0] * xi[0] + v[1] * xi[1] + v[2] * xi[2] + v[3] * xi[3]);
                     if (!live) continue;
-                    if (J != I && l < 16) {
-                        ACC *dst = (J < ntf) ? (myy + J * TILE) : (myc + (J - ntf) * TILE);
-                        dst[cl] += s;
-                    }
-                    if (++J == ntf + ntc) {
+                    if (J != I && l < 16) myy[J * TILE + cl] += s;
+                    if (++J == ntf) {
                         const ACC m = row_sum4(ra, cl);
                         if ((cl & 3) == 0) myy[I * TILE + g4 + (cl >> 2)] += m;
     #pragma unroll
@@ -489,13 +484,13 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
             }
         }
         if (strip_here) {   // the rest of the strip (more than SR rows, or columns past NT)
-            for (int k0 = 0; k0 < m; k0 += NT) {
+            for (int k0 = 0; k0 < n; k0 += NT) {
                 for (int r0 = 0; r0 < rem; r0 += SR) {
                     if (STRIP_EARLY && k0 == 0 && r0 == 0) continue;
                     T v[SR];
     #pragma unroll
                     for (int r = 0; r < SR; ++r)
-                        v[r] = (r0 + r < rem && k0 + tid < m) ? sp[(int64_t)(r0 + r) * m + k0 + tid] : (T)0;
+                        v[r] = (r0 + r < rem && k0 + tid < n) ? sp[(int64_t)(r0 + r) * n + k0 + tid] : (T)0;
                     strip_rows(k0, r0, v);
                 }
             }
@@ -510,15 +505,6 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
             const double y = (double)s;
             yp[k] = y;
             dot += (double)xs[k] * y;
-        }
-        if (ncs) {
-            double *cp = a.cpart + it.coff;
-            for (int k = tid; k < ncs; k += NW * 64) {
-                ACC s = (ACC)0;
-    #pragma unroll
-                for (int q = 0; q < NW; ++q) s += cw[q * ntc * TILE + k];
-                cp[k] = (double)s;
-            }
         }
         __syncthreads();   // LDS is reused by the next segment
         if (it.next < 0) break;
@@ -634,6 +620,53 @@ __device__ __forceinline__ double ld_rc_as<float>(__amdgpu_buffer_rsrc_t r, int 
 template <>
 __device__ __forceinline__ double ld_rc_as<uint16_t>(__amdgpu_buffer_rsrc_t r, int i) {
     return (double)dev::bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, i * 2, 0, 0));
+}
+
+// Coarse residual partials c_i = (D Phi_i)^T R_i x of every subdomain (the
+// right-hand side of eq. coarse_problem), from the row-major D Phi_i rows
+// the prolongation reads: one block per subdomain, one float64 partial per
+// (column, local coarse DOF).  The gathered x is staged in LDS, `rows` rows
+// of all columns at a time; a thread owns one (column, DOF) pair and one
+// residue class of the rows, and the classes are added in order, so the
+// result does not depend on timing.
+template <typename T>
+__global__ void __launch_bounds__(256) k_crest(CrestArgs a) {
+    extern __shared__ double xs[];          // [ncols][rows]
+    __shared__ double red[256];
+    if (a.ctl->done) return;
+    const int i = blockIdx.x, n = a.nB[i], nci = a.nc[i], np = nci * a.ncols, R = a.rows;
+    const int32_t *gb = a.gB + a.b_off[i];
+    const T *ph = reinterpret_cast<const T *>(a.phir) + a.phr_off[i];
+    for (int p0 = 0; p0 < np; p0 += 256) {  // pairs (column, DOF), DOF fastest
+        const int pc = min(256, np - p0), G = 256 / pc;
+        const int g = threadIdx.x / pc, p = p0 + threadIdx.x - g * pc;
+        const int col = p / nci, q = p - col * nci;
+        double acc = 0.0;
+        for (int k0 = 0; k0 < n; k0 += R) {
+            const int m = min(R, n - k0);
+            __syncthreads();                // the previous rows are used
+            for (int e = threadIdx.x; e < a.ncols * m; e += 256) {
+                const int cc = e / m, kk = e - cc * m;
+                xs[cc * R + kk] = a.X[cc * a.ldx + gb[k0 + kk]];
+            }
+            __syncthreads();
+            if (g < G) {
+                const T *pr = ph + (int64_t)k0 * nci + q;
+                const double *xc = xs + col * R;
+#pragma unroll 4
+                for (int k = g; k < m; k += G) acc += to_d(pr[(int64_t)k * nci]) * xc[k];
+            }
+        }
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        if (threadIdx.x < pc) {
+            double s = 0.0;
+            for (int h = 0; h < G; ++h) s += red[h * pc + threadIdx.x];
+            const int pp = p0 + threadIdx.x, cc = pp / nci;
+            a.part[cc * a.cs + a.c_off[i] + (pp - cc * nci)] = s;
+        }
+        __syncthreads();                    // red is reused by the next pairs
+    }
 }
 
 template <typename T>
@@ -1237,9 +1270,9 @@ __global__ void __launch_bounds__(256) k_l2_d(L2Args a) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-size_t symv_smem(int prec, int nw, int max_nt, int max_ntc) {
+size_t symv_smem(int prec, int nw, int max_nt) {
     const size_t acc = prec == 64 ? 8 : 4;
-    return acc * ((size_t)max_nt * TILE * (1 + nw) + (size_t)nw * max_ntc * TILE);
+    return acc * (size_t)max_nt * TILE * (1 + nw);
 }
 
 template <typename T, typename OP>
@@ -1285,6 +1318,20 @@ void launch_symv(const SymvArgs &a, SymvOp op, int prec, SymvCfg cfg, size_t sme
 void launch_update(const UpdArgs &a, int grid, hipStream_t s) {
     if (a.n > (int64_t)grid * 256 * 2) hipLaunchKernelGGL(k_update<4>, dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_update<1>, dim3(grid), dim3(256), 0, s, a);
+}
+
+// LDS rows of the restriction: the whole subdomain for one column, up to
+// 4096 staged values for several
+size_t crest_rows(int max_nB, int ncols) {
+    return (size_t)std::max(1, std::min(max_nB, 4096 / std::max(1, ncols)));
+}
+
+void launch_crest(const CrestArgs &a, int prec, int nsub, hipStream_t s) {
+    if (nsub <= 0) return;
+    const size_t smem = (size_t)a.ncols * a.rows * 8;
+    if (prec == 64) hipLaunchKernelGGL(k_crest<double>, dim3(nsub), dim3(256), smem, s, a);
+    else if (prec == 32) hipLaunchKernelGGL(k_crest<float>, dim3(nsub), dim3(256), smem, s, a);
+    else hipLaunchKernelGGL(k_crest<uint16_t>, dim3(nsub), dim3(256), smem, s, a);
 }
 
 void launch_prolong(const ProlArgs &a, int prec, int nblocks, int max_nc, hipStream_t s, int ncols) {

@@ -13,30 +13,24 @@ namespace bddc {
 
 constexpr int TILE = 16;          // symmetric operators are stored as 16x16 tiles
 
-// Packed symmetric operator of n rows (+ nc coarse-basis columns) in slots of
-// 256 entries: 16-row tile rows, tile row I holding the tiles (I, I..nt-1) of
-// the upper triangle then (I, nt..nt+ntc-1) of the coarse block (ntc =
-// ceil(nc / 16)).  A short ragged tail (n % 16 = 1..8 rows, rows of at most
-// 512 entries) is stored after the nt = n / 16 full tile rows as a row-major
-// strip of its whole rows (node columns, then coarse columns), padded to
-// whole slots: its tile column would be mostly zero padding.  Otherwise the
-// last tile row and column are zero-padded (nt = ceil(n / 16)) -- a long
+// Packed symmetric operator of n rows in slots of 256 entries: 16-row tile
+// rows, tile row I holding the tiles (I, I..nt-1) of the upper triangle.  A
+// short ragged tail (n % 16 = 1..8 rows, n <= 512) is stored after the
+// nt = n / 16 full tile rows as a row-major strip of its whole rows, padded
+// to whole slots: its tile column would be mostly zero padding.  Otherwise
+// the last tile row and column are zero-padded (nt = ceil(n / 16)) -- a long
 // strip would cost the product more round trips than its padding costs bytes.
-__host__ __device__ inline bool uses_strip(int n, int nc) {
+__host__ __device__ inline bool uses_strip(int n) {
     const int rem = n % TILE;
-    return rem != 0 && rem <= 8 && n + nc <= 512;
+    return rem != 0 && rem <= 8 && n <= 512;
 }
-__host__ __device__ inline int tile_rows(int n, int nc) { return uses_strip(n, nc) ? n / TILE : (n + TILE - 1) / TILE; }
-__host__ __device__ inline int full_tiles(int n, int nc) {
-    const int nt = tile_rows(n, nc), ntc = (nc + TILE - 1) / TILE;
-    return nt * (nt + 1) / 2 + nt * ntc;
+__host__ __device__ inline int tile_rows(int n) { return uses_strip(n) ? n / TILE : (n + TILE - 1) / TILE; }
+__host__ __device__ inline int full_tiles(int n) {
+    const int nt = tile_rows(n);
+    return nt * (nt + 1) / 2;
 }
-__host__ __device__ inline int64_t strip_len(int n, int nc) {
-    return uses_strip(n, nc) ? (int64_t)(n % TILE) * (n + nc) : 0;
-}
-__host__ __device__ inline int64_t op_slots(int n, int nc) {
-    return full_tiles(n, nc) + (strip_len(n, nc) + 255) / 256;
-}
+__host__ __device__ inline int64_t strip_len(int n) { return uses_strip(n) ? (int64_t)(n % TILE) * n : 0; }
+__host__ __device__ inline int64_t op_slots(int n) { return full_tiles(n) + (strip_len(n) + 255) / 256; }
 // zeroed bytes after every packed tile array: the product kernel's prefetch
 // of up to 8 tiles past a work range stays inside the allocation
 constexpr int64_t TILE_TAIL_BYTES = 8 * 256 * 8;
@@ -145,11 +139,11 @@ struct PackDesc {
     int n;
     double sign;
     const double *D;               // nullable row/col scaling
-    const double *phi; int ldphi;  // nullable n x nc block (scaled by D rows)
+    const double *phi; int ldphi;  // nullable n x nc coarse basis (scaled by D rows)
     int nc;
     int64_t dst;                   // element offset of the first tile
-    int64_t phr;                   // element offset of the row-major copy of
-                                   // the (D-scaled) coarse-basis rows, or -1
+    int64_t phr;                   // element offset of the row-major
+                                   // (D-scaled) coarse-basis rows, or -1
 };
 
 struct PtspDesc {                  // K_C = Phi^T S Phi

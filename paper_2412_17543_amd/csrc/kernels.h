@@ -28,35 +28,32 @@ struct AsmDesc {
 // ======================================================== operator products
 // One segment of a batched symmetric product: tiles [t0, t1) of the packed
 // tile sequence of one subdomain, whose tiles start at tile `tile` of the
-// operator array; the subdomain has n rows and nc coarse columns, and its
-// input entries are x[gB[x_off + k]], k < n.  The segment writes its partial
-// products to ypart[yoff + k] and cpart[coff + q].  Item b is the first
+// operator array; the subdomain has n rows, and its input entries are
+// x[gB[x_off + k]], k < n.  The segment writes its partial products to
+// ypart[yoff + k].  Item b is the first
 // segment of block b, `next` the index of the block's next one (-1: none);
 // an empty item (t0 == t1, n == 0) does nothing.  All that a block needs to
 // start a segment is in this one record.
 struct SymvItem {
     int32_t tile, t0, t1, n;
-    int32_t nc, x_off, yoff, coff;
-    int32_t next;
+    int32_t x_off, yoff, next;
     int32_t ntf, ntl, strip;        // the subdomain's tile rows, tiles, 1 if its tail is a strip
 };
 
 // A batch of packed symmetric operators in the slot layout of tile_rows and
-// strip_len: the tiles (with the coarse-basis tiles when `nc` is set), then,
-// for a short ragged tail, the strip of its rows.  The
+// strip_len: the tiles, then, for a short ragged tail, the strip of its
+// rows.  The
 // concatenated slot sequence of all subdomains is cut into n_blocks ranges,
 // one per block, and each range into segments inside single subdomains; the
 // segment holding a subdomain's first strip slot also applies the strip.  Segment c of
-// subdomain i writes its partial products to ypart[pb[i] + c * nB[i] + k]
-// and, with a coarse basis, cpart[cb[i] + c * nc[i] + q].
+// subdomain i writes its partial products to ypart[pb[i] + c * nB[i] + k].
 struct OpDev {
     const void *tiles;
     const int64_t *t_off;
     const int32_t *nB, *b_off, *gB;
-    const int32_t *nc;              // nullable
     const SymvItem *items;          // n_blocks first segments, then the others
     int n_blocks;
-    const int32_t *nchunk, *pb, *cb;
+    const int32_t *nchunk, *pb;
 };
 
 // Assembled entry t is the sum of part[idx[e]] for e in [ptr[t], ptr[t+1]):
@@ -69,7 +66,7 @@ struct Gather {
 struct SymvArgs {
     OpDev op;
     const double *x;                // global interface vector
-    double *ypart, *cpart;
+    double *ypart;
     double *dot;                    // nullable: per-item x_i^T y_i partials
     Ctl *ctl;
     int gated;                      // return when ctl->done
@@ -95,6 +92,17 @@ struct UpdArgs {                    // Alg. 1, lines 9-11
     double *d_hist, *a_hist;
     const double *rho_hist;
     int hist_cap;
+};
+
+struct CrestArgs {                  // c_i = (D Phi_i)^T R_i x (right-hand side of eq. coarse_problem)
+    Ctl *ctl;                       // returns when ctl->done
+    const int32_t *nB, *b_off, *gB, *nc, *c_off;
+    const void *phir;               // D Phi_i rows, local precision
+    const int64_t *phr_off;
+    const double *X; int64_t ldx;   // ncols columns of the interface vector
+    double *part; int64_t cs;       // partial of column j, DOF q of subdomain i: part[j * cs + c_off[i] + q]
+    int ncols;
+    int rows;                       // rows of gathered x staged in LDS at a time (ncols * rows doubles)
 };
 
 struct ProlArgs {                   // w_i = u_i + D Phi_i u_C (eq. averaging_subdomain_solves)
@@ -337,20 +345,19 @@ void launch_gram(const GramArgs &a, int nblocks, hipStream_t s);
 // ============================================================ block products (block.hip)
 struct BlockItem {                  // one subdomain of a block product
     int64_t tile;                   // its first tile (in tiles) in the packed operator
-    int32_t n, nc;                  // interface size, coarse rows (Neumann; 0 for Schur)
-    int32_t xoff, coff;             // offsets in the local interface / coarse arrays
+    int32_t n;                      // rows
+    int32_t xoff;                   // offset in the local interface (or interior) arrays
 };
 struct BlockSymvArgs {
-    const double *tiles;            // float64 tiles (Schur, or Neumann with the coarse rows)
+    const double *tiles;            // float64 tiles
     const BlockItem *items;
     const int32_t *gB;              // local interface position -> interface index
     const double *X; int64_t ldx; int ncols;   // input block, column-major
     double *ypart; int64_t ylen;    // y of subdomain i, column c: ypart[c ylen + xoff_i + k]
-    double *cpart; int64_t clen;    // coarse: cpart[c clen + coff_i + q]
 };
-size_t symm_smem_bytes(int max_n, int max_nc);
+size_t symm_smem_bytes(int max_n);
 int set_symm_smem_limit(size_t bytes);
-void launch_symm(const BlockSymvArgs &a, int nsub, bool coarse, size_t smem, hipStream_t s);
+void launch_symm(const BlockSymvArgs &a, int nsub, size_t smem, hipStream_t s);
 void launch_gather_block(int n, const int32_t *ptr, const int32_t *idx, const double *part, int64_t plen, double *out,
                          int64_t ldo, int ncols, hipStream_t s);
 void launch_elem_grad(const GradArgs &a, hipStream_t s);
@@ -373,10 +380,12 @@ struct SymvCfg {
 // their own name (k_symv<T, waves, tiles in flight, OpSchur | OpNeumann |
 // OpInterior>) so that profiles time them apart
 enum SymvOp { SYMV_SCHUR = 0, SYMV_NEUMANN = 1, SYMV_INTERIOR = 2 };
-size_t symv_smem(int prec, int nw, int max_nt, int max_ntc);
+size_t symv_smem(int prec, int nw, int max_nt);
 int set_symv_smem_limit(size_t bytes);
 void launch_symv(const SymvArgs &a, SymvOp op, int prec, SymvCfg cfg, size_t smem, hipStream_t s);
 void launch_update(const UpdArgs &a, int grid, hipStream_t s);
+void launch_crest(const CrestArgs &a, int prec, int nsub, hipStream_t s);
+size_t crest_rows(int max_nB, int ncols);
 void launch_prolong(const ProlArgs &a, int prec, int nblocks, int max_nc, hipStream_t s, int ncols = 1);
 void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s, int ncols = 1);
 void launch_pupd(const PupdArgs &a, int kmax, int grid, hipStream_t s);

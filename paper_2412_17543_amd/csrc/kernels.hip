@@ -106,13 +106,12 @@ __global__ void __launch_bounds__(256) k_build_saddle(const SaddleDesc *descs) {
 
 
 // ---------------------------------------------------------------------------
-// setup: pack a symmetric n x n block (+ an n x nc block) in the slot layout
+// setup: pack a symmetric n x n block in the slot layout
 // of tile_rows / strip_len: 16x16 tiles (element order of tile_index), tile
-// row I holding (I, I..nt-1) then (I, nt..nt+ntc-1), zero past n; then, with
-// a strip, the ragged tail rows, row-major over the n node and nc coarse
-// columns.  Value = sign * src[i][j] * D[i] * D[j] (coarse-basis block:
-// sign * phi[i][q] * D[i]); with phr >= 0 the coarse-basis block is also
-// written row-major (n rows of nc values) for the prolongation.
+// row I holding (I, I..nt-1), zero past n; then, with a strip, the ragged
+// tail rows, row-major.  Value = sign * src[i][j] * D[i] * D[j].  With
+// phr >= 0 the coarse basis sign * phi[i][q] * D[i] is written row-major (n
+// rows of nc values) for the coarse restriction and the prolongation.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void store_conv(double *p, double v) { *p = v; }
 __device__ __forceinline__ void store_conv(float *p, double v) { *p = (float)v; }
@@ -127,43 +126,35 @@ __device__ __forceinline__ void store_conv(uint16_t *p, double v) {
 template <typename T>
 __global__ void __launch_bounds__(256) k_pack(const PackDesc *descs, T *dst, T *phir) {
     const PackDesc d = descs[blockIdx.x];
-    const int nt = tile_rows(d.n, d.nc), ntc = (d.nc + TILE - 1) / TILE, n0 = nt * TILE;
-    // value of row gi (< n) at node column gj (< n) or coarse column n + gq
+    const int nt = tile_rows(d.n), n0 = nt * TILE;
     auto node = [&](int gi, int gj) {
         double v = d.sign * d.src[(size_t)gi * d.ld + gj];
         if (d.D) v *= d.D[gi] * d.D[gj];
         return v;
     };
-    auto coarse = [&](int gi, int gq) {
-        double v = d.sign * d.phi[(size_t)gi * d.ldphi + gq];
-        if (d.D) v *= d.D[gi];
-        if (d.phr >= 0) store_conv(phir + d.phr + (int64_t)gi * d.nc + gq, v);
-        return v;
-    };
     int64_t base = 0;
     for (int I = 0; I < nt; ++I) {
-        const int nrow = nt - I + ntc;
+        const int nrow = nt - I;
         for (int e = threadIdx.x; e < nrow * 256; e += blockDim.x) {
             const int q = e >> 8, r = (e >> 4) & 15, c = e & 15;
-            const int J = I + q;
-            const int gi = I * TILE + r;
-            double v = 0.0;
-            if (J < nt) {
-                const int gj = J * TILE + c;
-                if (gi < d.n && gj < d.n) v = node(gi, gj);
-            } else {
-                const int gq = (J - nt) * TILE + c;
-                if (gi < d.n && gq < d.nc) v = coarse(gi, gq);
-            }
+            const int gi = I * TILE + r, gj = (I + q) * TILE + c;
+            const double v = (gi < d.n && gj < d.n) ? node(gi, gj) : 0.0;
             store_conv(dst + d.dst + (base + q) * 256 + tile_index(r, c, (int)sizeof(T)), v);
         }
         base += nrow;
     }
-    const int m = d.n + d.nc;
     T *sp = dst + d.dst + base * 256;
-    for (int64_t e = threadIdx.x; e < strip_len(d.n, d.nc); e += blockDim.x) {
-        const int r = (int)(e / m), k = (int)(e - (int64_t)r * m);
-        store_conv(sp + e, k < d.n ? node(n0 + r, k) : coarse(n0 + r, k - d.n));
+    for (int64_t e = threadIdx.x; e < strip_len(d.n); e += blockDim.x) {
+        const int r = (int)(e / d.n), k = (int)(e - (int64_t)r * d.n);
+        store_conv(sp + e, node(n0 + r, k));
+    }
+    if (d.phr >= 0 && d.phi) {
+        for (int64_t e = threadIdx.x; e < (int64_t)d.n * d.nc; e += blockDim.x) {
+            const int gi = (int)(e / d.nc), q = (int)(e - (int64_t)gi * d.nc);
+            double v = d.sign * d.phi[(size_t)gi * d.ldphi + q];
+            if (d.D) v *= d.D[gi];
+            store_conv(phir + d.phr + e, v);
+        }
     }
 }
 
