@@ -392,12 +392,13 @@ int bddc_set_launch(bddc_ctx *ctx, int32_t use_graph, const int32_t *product_cfg
  * are overwritten).  out (host float64[n], n <= 12) receives pairs
  * (microseconds per launch, algorithmic bytes per launch):
  *   [0,1]  batched Schur product (Section 3.1, A p)
- *   [2,3]  batched constrained-Neumann product (local part of eq. localCorr)
+ *   [2,3]  batched constrained-Neumann product (local part of eq. localCorr,
+ *          with the coarse restriction (D Phi_i)^T r_i of eq. coarse_problem)
  *   [4,5]  batched interior product K_II^{-1} v (condensation, recovery)
  *   [6,7]  one whole preconditioner application z = M^{-1} r: the Neumann
  *          product, the coarse levels, prolongation and assembly
  *          (eqs. averaging_subdomain_solves, coarse_problem, localCorr)
- *   [8,9]  the coarse levels alone
+ *   [8,9]  the coarse levels alone (from the restriction's partials)
  *   [10,11] prolongation and assembly alone
  * Algorithmic bytes are those the method must move (operators in their
  * stored precision, packed; gathered vectors and index lists once).

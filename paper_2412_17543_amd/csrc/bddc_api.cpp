@@ -285,32 +285,28 @@ int prec_slot(int prec) { return prec == 64 ? 0 : prec == 32 ? 1 : prec == 16 ? 
 
 // Algorithmic bytes of one batched product (Schur or Neumann, prec = the
 // operator's storage precision): packed upper triangle, gathered input and
-// its index, output.
-double product_bytes(const bddc_ctx *c, int prec) {
+// its index, output; with `coarse` (Neumann with a coarse space) also D Phi_i
+// and the coarse partials of the restriction.
+double product_bytes(const bddc_ctx *c, int prec, bool coarse) {
     const double eb = prec / 8.0;
     double bytes = 0.0;
     for (int i = 0; i < c->n_sub; ++i) {
-        const double n = c->h_nB[i];
-        bytes += n * (n + 1) / 2 * eb + n * (8 + 4 + 8);
+        const double n = c->h_nB[i], nci = coarse ? c->h_nc[i] : 0;
+        bytes += (n * (n + 1) / 2 + n * nci) * eb + n * (8 + 4 + 8) + nci * 8;
     }
     return bytes;
 }
 
 // Algorithmic bytes of the coarse levels of one preconditioner application:
-// the restriction (D Phi_i rows, gathered r and its index, one partial per
-// local coarse DOF), the dense coarse operator and the gather of r_C; or, for the subregion
+// the gather of r_C from the coarse partials, and the dense coarse operator; or, for the subregion
 // chain, the level-2 blocks each phase reads (interior columns of the swept
 // subregion matrix, N and Phi of the level-2 interface, Phi again and the
 // interior-interface block for the correction), the level-3 inverse and the
 // coarse vectors.
 double coarse_bytes(const bddc_ctx *c) {
     if (c->nC == 0) return 0.0;
-    const double eN = c->prec / 8.0;
-    double cp = 0.0;   // restriction, and its partials gathered into r_C (index + value)
-    for (int i = 0; i < c->n_sub; ++i) {
-        const double n = c->h_nB[i], nci = c->h_nc[i];
-        cp += n * nci * eN + n * (8.0 + 4.0) + nci * 8.0 + nci * 12.0;
-    }
+    double cp = 0.0;   // coarse partials gathered into r_C: index + value
+    for (int i = 0; i < c->n_sub; ++i) cp += c->h_nc[i] * 12.0;
     const double vec = c->nC * (4.0 + 8.0 + 8.0);
     if (c->coarse_dense) return (double)c->nC * c->ldm * 8.0 + cp + vec + c->nC * 8.0;
     const double n3 = c->n3;
@@ -430,11 +426,11 @@ int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
     }
     if (ylen > INT32_MAX) return fail(BDDC_EINVAL, "operator partial buffers exceed int32 indexing");
     // block b's first segment at index b, its others appended and chained
-    std::vector<SymvItem> items(std::max(nblocks, 1), SymvItem{0, 0, 0, 0, 0, 0, -1, 0, 0, 0});
+    std::vector<SymvItem> items(std::max(nblocks, 1), SymvItem{0, 0, 0, 0, 0, 0, -1, 0, 0, 0, 0});
     auto record = [&](const Seg &g) {
         const int n = sizes[g.k];
         return SymvItem{(int32_t)start[g.k], (int32_t)g.t0, (int32_t)g.t1, n, xoff[g.k], pb[g.k] + g.c * n, -1,
-                        tile_rows(n), full_tiles(n), uses_strip(n) ? 1 : 0};
+                        tile_rows(n), full_tiles(n), uses_strip(n) ? 1 : 0, g.k};
     };
     for (int b = 0; b < nblocks; ++b) {
         int prev = b;
@@ -548,8 +544,17 @@ void run_l2_chain(const bddc_ctx *c, const L2Args &l, hipStream_t st) {
     launch_l2_d(l, c->nsr, c->smem_l2d, st);
 }
 
-void run_coarse(bddc_ctx *c, const double *r, hipStream_t st);
+void run_coarse(bddc_ctx *c, hipStream_t st);
 void run_prolong_assemble(bddc_ctx *c, const double *r, double *z, bool gated, bool advance, bool reduce);
+
+// Coarse restriction of a single-vector Neumann product: the first segment
+// of every subdomain writes c_i = (D Phi_i)^T x_i (none without a coarse space).
+void set_restriction(const bddc_ctx *c, SymvArgs &a) {
+    if (c->nC == 0) return;
+    a.cpart = c->d_crest;
+    a.phir = c->d_phir; a.phr_off = c->d_phr_off;
+    a.nc = c->d_nc; a.c_off = c->d_c_off;
+}
 
 // One BDDC application on r: local constrained-Neumann products, the coarse
 // levels, assembly of z with the coarse prolongation and the (r^T z,
@@ -571,25 +576,19 @@ void run_precond(bddc_ctx *c, const double *r, double *z, int test, bool gated, 
         a.rr_part = c->d_rr; a.rr_n = c->vgrid;
         a.bb_part = c->d_bbp; a.bb_n = c->vgrid;
         a.res_hist = c->d_reshist; a.hist_cap = c->hist_cap;
+        set_restriction(c, a);
         launch_symv(a, SYMV_NEUMANN, c->prec, c->opN.cfg, c->opN.smem, c->stream);
     }
-    run_coarse(c, r, c->stream);
+    run_coarse(c, c->stream);
     run_prolong_assemble(c, r, z, gated, advance, reduce);
 }
 
 // Coarse levels of one BDDC application on stream st: the coarse residual
-// r_C = sum_i R_Ci^T (D Phi_i)^T R_i r, then u_C (eq. coarse_problem; three
-// levels as in Section 3.2).
-void run_coarse(bddc_ctx *c, const double *r, hipStream_t st) {
+// r_C = sum_i R_Ci^T c_i from the partials of the Neumann product, then u_C
+// (eq. coarse_problem; three levels as in Section 3.2).
+void run_coarse(bddc_ctx *c, hipStream_t st) {
     if (c->nC == 0) return;
     TScope ts(c, TK_COARSE);
-    CrestArgs ra{};
-    ra.ctl = c->d_ctl;
-    ra.nB = c->d_nB; ra.b_off = c->d_b_off; ra.gB = c->d_gB; ra.nc = c->d_nc; ra.c_off = c->d_c_off;
-    ra.phir = c->d_phir; ra.phr_off = c->d_phr_off;
-    ra.X = r; ra.ldx = 0; ra.part = c->d_crest; ra.cs = 0; ra.ncols = 1;
-    ra.rows = (int)crest_rows(c->max_nB, 1);
-    launch_crest(ra, c->prec, c->n_sub, st);
     const Gather rc{c->d_casm_ptr, c->d_casm_idx, c->d_crest};
     if (c->coarse_dense) {
         CoarseDenseArgs ca{};
@@ -1474,7 +1473,7 @@ int setup_operators(bddc_ctx *c) {
         op.dev.gB = c->d_gB;
         op.n_tiles = 0;
         for (int i = 0; i < nsub; ++i) op.n_tiles += op_slots(c->h_nB[i]);
-        op.bytes = product_bytes(c, op.prec);
+        op.bytes = product_bytes(c, op.prec, isN && c->nC > 0);
         op.cfg = SymvCfg{4, 2};
         op.smem = symv_smem(op.prec, op.cfg.nw, c->max_nt);
         int rc = build_worklist(c, op, product_blocks(c, op.n_tiles, op.bpc), op.per_sub);
@@ -1603,6 +1602,7 @@ int tune_operators(bddc_ctx *c, int mask = 7) {
             SymvArgs a{};
             a.op = op.dev; a.x = op.interior ? c->d_tmpN : c->d_x; a.ypart = op.d_ypart;
             a.ctl = c->d_ctl;
+            if (w == 1) set_restriction(c, a);
             for (int r = 0; r < 2; ++r) launch_symv(a, (SymvOp)w, op.prec, cfg, smem, c->stream);
             HIPCHK(hipEventRecord(e0, c->stream));
             for (int r = 0; r < reps; ++r) launch_symv(a, (SymvOp)w, op.prec, cfg, smem, c->stream);
@@ -1827,7 +1827,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         kc_off[i + 1] = kc_off[i] + (int64_t)nc[i] * nc[i];
         m_off[i + 1] = m_off[i] + (int64_t)(sh.nB + nc[i]) * (sh.nB + nc[i]);
         x_off[i + 1] = x_off[i] + (int64_t)sh.nB * nc[i];
-        phr_off[i + 1] = phr_off[i] + (int64_t)sh.nB * nc[i];
+        phr_off[i + 1] = phr_off[i] + (int64_t)phi_ld(sh.nB) * nc[i];
         gB.insert(gB.end(), sh.gB.begin(), sh.gB.end());
         nodesI.insert(nodesI.end(), sh.nodes.begin(), sh.nodes.begin() + sh.nI);
         cidx.insert(cidx.end(), sh.cidx.begin(), sh.cidx.end());
@@ -1907,7 +1907,7 @@ int setup_impl(bddc_ctx *c, const bddc_mesh *mesh, const bddc_partition *part, c
         launch_build_saddle(dsd, nsub, s);
         if ((rc = run_sweeps(c, wd))) return rc;
         // tiles: S_i (float64) and D N_i D (local precision) in the same
-        // layout, plus the row-major D Phi_i for the coarse restriction and
+        // layout, plus the column-major D Phi_i for the coarse restriction and
         // the prolongation
         c->bytes_S = (size_t)s_off[nsub] * 8;
         c->bytes_N = (size_t)s_off[nsub] * eN;
@@ -2425,8 +2425,8 @@ void block_coarse(bddc_ctx *c, BlockWork &b, const double *R, int ncols, hipStre
     ra.nB = c->d_nB; ra.b_off = c->d_b_off; ra.gB = c->d_gB; ra.nc = c->d_nc; ra.c_off = c->d_c_off;
     ra.phir = c->d_phirx[prec_slot(64)]; ra.phr_off = c->d_phr_off;
     ra.X = R; ra.ldx = c->ld; ra.part = b.cN; ra.cs = b.clen; ra.ncols = ncols;
-    ra.rows = (int)crest_rows(c->max_nB, ncols);
-    launch_crest(ra, 64, c->n_sub, st);
+    ra.cols = crest_cols(64, c->max_nB, ncols);
+    launch_crest(ra, 64, c->n_sub, c->max_nB, st);
     const Gather rc{c->d_casm_ptr, c->d_casm_idx, b.cN};
     if (c->coarse_dense) {
         CoarseDenseArgs ca{};
@@ -3037,6 +3037,7 @@ int bddc_time_products(bddc_ctx *c, int32_t reps, double *out) {
         const OpHost &op = *ops[w];
         SymvArgs a{};
         a.op = op.dev; a.x = c->d_x; a.ypart = op.d_ypart; a.ctl = c->d_ctl;
+        if (w == 1) set_restriction(c, a);
         launch_symv(a, (SymvOp)w, op.prec, op.cfg, op.smem, c->stream);   // warm
         hipError_t e = hipEventRecord(e0, c->stream);
         for (int r = 0; r < reps && e == hipSuccess; ++r) launch_symv(a, (SymvOp)w, op.prec, op.cfg, op.smem, c->stream);
@@ -3066,7 +3067,7 @@ int bddc_set_local_prec(bddc_ctx *c, int32_t prec) {
     OpHost &op = c->opN;
     op.prec = prec;
     op.dev.tiles = c->d_N;
-    op.bytes = product_bytes(c, prec);
+    op.bytes = product_bytes(c, prec, c->nC > 0);
     c->bytes_N = (size_t)op.n_tiles * 256 * (size_t)(prec / 8);
     c->t_bytes[TK_PREC] = op.bytes;
     op.smem = symv_smem(prec, op.cfg.nw, c->max_nt);
@@ -3157,6 +3158,7 @@ int bddc_time_kernels(bddc_ctx *c, int32_t reps, double *out, int32_t n) {
         const OpHost &op = *ops[w];
         SymvArgs a{};
         a.op = op.dev; a.x = w == 2 ? c->d_tmpN : c->d_x; a.ypart = op.d_ypart; a.ctl = c->d_ctl;
+        if (w == 1) set_restriction(c, a);
         double bytes = op.bytes;
         if (w == 2) {   // packed K_II^{-1}, gathered input and index, output
             bytes = 0.0;
@@ -3169,7 +3171,7 @@ int bddc_time_kernels(bddc_ctx *c, int32_t reps, double *out, int32_t n) {
     }
     const double cb = coarse_bytes(c), pb = prolong_bytes(c);
     timed(3, c->opN.bytes + cb + pb, [&] { run_precond(c, c->d_r, c->d_tmp, 0, false, false, false); });
-    timed(4, cb, [&] { run_coarse(c, c->d_r, c->stream); });
+    timed(4, cb, [&] { run_coarse(c, c->stream); });
     timed(5, pb, [&] { run_prolong_assemble(c, c->d_r, c->d_tmp, false, false, false); });
     c->timing = tk;
     (void)hipEventDestroy(e0);

@@ -6,8 +6,8 @@
 // graph and replayed:
 //   k_symv (S)   q_i = S_i p_i                      Alg. 1 line 9 (A p)
 //   k_update     alpha, x += alpha p, r -= alpha q  lines 9-11
-//   k_symv (N)   stopping test (Section 5); u_i = D N_i D r_i
-//   k_crest      c_i = (D Phi_i)^T r_i (coarse residual partials)
+//   k_symv (N)   stopping test (Section 5); u_i = D N_i D r_i and the
+//                coarse residual partials c_i = (D Phi_i)^T r_i
 //   coarse       k_coarse_dense (two levels, or three levels in explicit form);
 //                three levels as a chain: k_l2_a, k_l2_b, level 3 by the
 //                dense product, k_l2_d
@@ -298,17 +298,80 @@ __device__ __forceinline__ void cm_matvec(const double *M, int64_t ldm, int r0, 
 __device__ __forceinline__ SymvItem load_item(const SymvItem *items, int i) {
     typedef const __attribute__((address_space(4))) int32_t CInt;
     CInt *q = (CInt *)(items + i);
-    return SymvItem{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9]};
+    return SymvItem{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9], q[10]};
 }
 
 template <typename T, int U>
 constexpr int symv_waves_per_simd() { return (sizeof(T) == 8 && U == 4) ? 4 : 6; }
 
+// Dot product, in float64 and entry order, of the V = 16 / sizeof(T) entries
+// of one 16-byte vector with V consecutive values of x.
+template <typename T, typename X>
+__device__ __forceinline__ double dot16(const uvec4 &v, const X *x) {
+    if constexpr (sizeof(T) == 8) {
+        return __hiloint2double(v.y, v.x) * (double)x[0] + __hiloint2double(v.w, v.z) * (double)x[1];
+    } else if constexpr (sizeof(T) == 4) {
+        return (((double)__uint_as_float(v.x) * (double)x[0] + (double)__uint_as_float(v.y) * (double)x[1]) +
+                (double)__uint_as_float(v.z) * (double)x[2]) +
+               (double)__uint_as_float(v.w) * (double)x[3];
+    } else {
+        const unsigned int u[4] = {v.x, v.y, v.z, v.w};
+        double s = 0.0;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            s += (double)dev::bf16_to_f32((uint16_t)(u[h] & 0xffffu)) * (double)x[2 * h];
+            s += (double)dev::bf16_to_f32((uint16_t)(u[h] >> 16)) * (double)x[2 * h + 1];
+        }
+        return s;
+    }
+}
+
+// Coarse restriction c_i = (D Phi_i)^T x_i of subdomain `sub` (n rows), with
+// x_i staged in LDS (zero past n to a multiple of 16): wave w takes the
+// coarse DOFs w, w + NW, ..., QB of them at a time; a lane dots the 16-byte
+// pieces V l, V l + 64 V, ... of each DOF's column-major row with x, JM
+// pieces per round trip, and the wave's sum (fixed order) is the partial.
+// Pieces of DOFs past nc_i read as zero through the range check.
+template <typename T, int NW, typename X>
+__device__ __forceinline__ void coarse_tail(const SymvArgs &a, int sub, int n, const X *xs, int wu, int l) {
+    constexpr int V = 16 / (int)sizeof(T), W = 64 * V, QB = sizeof(T) == 2 ? 1 : 2, JM = 2;
+    const int nci = a.nc[sub], ld = phi_ld(n);
+    const __amdgpu_buffer_rsrc_t pr =
+        tile_rsrc(reinterpret_cast<const T *>(a.phir) + a.phr_off[sub], nci * ld * (int)sizeof(T));
+    double *cp = a.cpart + a.c_off[sub];
+    for (int q0 = wu; q0 < nci; q0 += NW * QB) {
+        double acc[QB];
+#pragma unroll
+        for (int qi = 0; qi < QB; ++qi) acc[qi] = 0.0;
+        for (int p0 = V * l; p0 < ld; p0 += JM * W) {
+            uvec4 f[QB][JM];
+#pragma unroll
+            for (int qi = 0; qi < QB; ++qi)
+#pragma unroll
+                for (int jj = 0; jj < JM; ++jj)
+                    f[qi][jj] = p0 + jj * W < ld ? __builtin_amdgcn_raw_buffer_load_b128(
+                                                       pr, ((q0 + NW * qi) * ld + p0 + jj * W) * (int)sizeof(T), 0, 0)
+                                                 : uvec4{0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int qi = 0; qi < QB; ++qi)
+#pragma unroll
+                for (int jj = 0; jj < JM; ++jj)
+                    if (p0 + jj * W < ld) acc[qi] += dot16<T>(f[qi][jj], xs + p0 + jj * W);
+        }
+#pragma unroll
+        for (int qi = 0; qi < QB; ++qi) {
+            const double s = wave_sum(acc[qi]);
+            const int q = q0 + NW * qi;
+            if (l == 0 && q < nci) cp[q] = s;
+        }
+    }
+}
+
 // Name tags of the three operator batches (the kernel is the same; only the
-// Neumann batch makes the stopping test).
-struct OpSchur { static constexpr bool test = false; };
-struct OpNeumann { static constexpr bool test = true; };
-struct OpInterior { static constexpr bool test = false; };
+// Neumann batch makes the stopping test and the coarse restriction).
+struct OpSchur { static constexpr bool neumann = false; };
+struct OpNeumann { static constexpr bool neumann = true; };
+struct OpInterior { static constexpr bool neumann = false; };
 
 template <typename T, int NW, int U, typename OP>
 __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv(SymvArgs a) {
@@ -320,7 +383,7 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
     constexpr int SR = 4;           // strip rows per pass (registers)
     // the first pass requested with the gathered values where registers allow
     // (not beside the stopping test's registers in the float64 Neumann batch)
-    constexpr bool STRIP_EARLY = sizeof(T) == 2 || (sizeof(T) == 4 && U == 2) || (sizeof(T) == 8 && U == 4 && !OP::test);
+    constexpr bool STRIP_EARLY = sizeof(T) == 2 || (sizeof(T) == 4 && U == 2) || (sizeof(T) == 8 && U == 4 && !OP::neumann);
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g4 = 4 * (l >> 4), cl = l & 15;
     const int wu = __builtin_amdgcn_readfirstlane(w);     // wave-uniform control flow
     // Segment records are block-uniform: read through the constant address
@@ -333,7 +396,7 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
     // used.
     SymvItem it = load_item(a.op.items, blockIdx.x);
     if (a.gated && block_done(a.ctl)) return;
-    const bool test_here = OP::test && a.test && !(a.defer && a.ctl->record);
+    const bool test_here = OP::neumann && a.test && !(a.defer && a.ctl->record);
 
     // Tiles past w1 read as zero without a memory access (resource over tiles
     // [t, w1) for the stage starting at tile t), so the loads of the next U
@@ -506,6 +569,9 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
             yp[k] = y;
             dot += (double)xs[k] * y;
         }
+        if constexpr (OP::neumann) {   // the subdomain's first segment: its coarse restriction
+            if (a.cpart && it.t0 == 0) coarse_tail<T, NW>(a, it.sub, n, xs, wu, l);
+        }
         __syncthreads();   // LDS is reused by the next segment
         if (it.next < 0) break;
         it = load_item(a.op.items, it.next);
@@ -623,50 +689,76 @@ __device__ __forceinline__ double ld_rc_as<uint16_t>(__amdgpu_buffer_rsrc_t r, i
 }
 
 // Coarse residual partials c_i = (D Phi_i)^T R_i x of every subdomain (the
-// right-hand side of eq. coarse_problem), from the row-major D Phi_i rows
-// the prolongation reads: one block per subdomain, one float64 partial per
-// (column, local coarse DOF).  The gathered x is staged in LDS, `rows` rows
-// of all columns at a time; a thread owns one (column, DOF) pair and one
-// residue class of the rows, and the classes are added in order, so the
-// result does not depend on timing.
+// right-hand side of eq. coarse_problem) for several columns at once (the
+// block products; a single-vector Neumann product computes them itself):
+// one block per subdomain, one float64 partial per (column, local coarse
+// DOF).  D Phi_i is stored
+// column-major, so each coarse DOF's entries are one contiguous row: wave w
+// takes the DOFs w, w + 4, ...; a lane holds 16-byte pieces of QB of them
+// (JM pieces each per round trip, the first requested before the gather of
+// x), dots them with the gathered x staged in LDS (zero past n), and the
+// wave's sum gives the partial (a fixed order: the result does not depend
+// on timing).  Pieces of DOFs past nc_i read as zero through the range check.
 template <typename T>
 __global__ void __launch_bounds__(256) k_crest(CrestArgs a) {
-    extern __shared__ double xs[];          // [ncols][rows]
-    __shared__ double red[256];
+    constexpr int V = 16 / (int)sizeof(T), W = 64 * V, QB = 4, JM = 2;
+    extern __shared__ double xs[];          // [cols][XL]
     if (a.ctl->done) return;
-    const int i = blockIdx.x, n = a.nB[i], nci = a.nc[i], np = nci * a.ncols, R = a.rows;
+    const int i = blockIdx.x, n = a.nB[i], nci = a.nc[i];
+    if (nci == 0) return;
+    const int ld = phi_ld(n), J = (ld + W - 1) / W, XL = J * W;   // pieces per DOF row, staged length
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
     const int32_t *gb = a.gB + a.b_off[i];
-    const T *ph = reinterpret_cast<const T *>(a.phir) + a.phr_off[i];
-    for (int p0 = 0; p0 < np; p0 += 256) {  // pairs (column, DOF), DOF fastest
-        const int pc = min(256, np - p0), G = 256 / pc;
-        const int g = threadIdx.x / pc, p = p0 + threadIdx.x - g * pc;
-        const int col = p / nci, q = p - col * nci;
-        double acc = 0.0;
-        for (int k0 = 0; k0 < n; k0 += R) {
-            const int m = min(R, n - k0);
-            __syncthreads();                // the previous rows are used
-            for (int e = threadIdx.x; e < a.ncols * m; e += 256) {
-                const int cc = e / m, kk = e - cc * m;
-                xs[cc * R + kk] = a.X[cc * a.ldx + gb[k0 + kk]];
-            }
-            __syncthreads();
-            if (g < G) {
-                const T *pr = ph + (int64_t)k0 * nci + q;
-                const double *xc = xs + col * R;
-#pragma unroll 4
-                for (int k = g; k < m; k += G) acc += to_d(pr[(int64_t)k * nci]) * xc[k];
-            }
+    const __amdgpu_buffer_rsrc_t pr =
+        tile_rsrc(reinterpret_cast<const T *>(a.phir) + a.phr_off[i], nci * ld * (int)sizeof(T));
+    uvec4 f[QB][JM];
+    auto issue = [&](int q0, int jb) {
+#pragma unroll
+        for (int qi = 0; qi < QB; ++qi)
+#pragma unroll
+            for (int jj = 0; jj < JM; ++jj)
+                f[qi][jj] = jb + jj < J ? __builtin_amdgcn_raw_buffer_load_b128(
+                                              pr, ((q0 + 4 * qi) * ld + (jb + jj) * W + V * l) * (int)sizeof(T), 0, 0)
+                                        : uvec4{0u, 0u, 0u, 0u};
+    };
+    issue(w, 0);
+    bool held = true;                       // f holds (DOFs from w, pieces 0..JM-1)
+    for (int c0 = 0; c0 < a.ncols; c0 += a.cols) {
+        const int cg = min(a.cols, a.ncols - c0);
+        __syncthreads();                    // the previous columns are used
+        for (int e = threadIdx.x; e < cg * XL; e += 256) {
+            const int cc = e / XL, k = e - cc * XL;
+            xs[e] = k < n ? a.X[(int64_t)(c0 + cc) * a.ldx + gb[k]] : 0.0;
         }
-        red[threadIdx.x] = acc;
         __syncthreads();
-        if (threadIdx.x < pc) {
-            double s = 0.0;
-            for (int h = 0; h < G; ++h) s += red[h * pc + threadIdx.x];
-            const int pp = p0 + threadIdx.x, cc = pp / nci;
-            a.part[cc * a.cs + a.c_off[i] + (pp - cc * nci)] = s;
+        for (int q0 = w; q0 < nci; q0 += 4 * QB) {
+            for (int cc = 0; cc < cg; ++cc) {
+                double acc[QB];
+#pragma unroll
+                for (int qi = 0; qi < QB; ++qi) acc[qi] = 0.0;
+                for (int jb = 0; jb < J; jb += JM) {
+                    if (!held) issue(q0, jb);
+                    held = false;
+#pragma unroll
+                    for (int qi = 0; qi < QB; ++qi)
+#pragma unroll
+                        for (int jj = 0; jj < JM; ++jj)
+                            if (jb + jj < J) acc[qi] += dot16<T>(f[qi][jj], xs + cc * XL + (jb + jj) * W + V * l);
+                }
+#pragma unroll
+                for (int qi = 0; qi < QB; ++qi) {
+                    const double s = wave_sum(acc[qi]);
+                    const int q = q0 + 4 * qi;
+                    if (l == 0 && q < nci) a.part[(int64_t)(c0 + cc) * a.cs + a.c_off[i] + q] = s;
+                }
+            }
         }
-        __syncthreads();                    // red is reused by the next pairs
     }
+    // a wave without DOFs leaves its first requests unused: none outstanding at exit
+#pragma unroll
+    for (int qi = 0; qi < QB; ++qi)
+#pragma unroll
+        for (int jj = 0; jj < JM; ++jj) asm volatile("" ::"v"(f[qi][jj]));
 }
 
 template <typename T>
@@ -683,17 +775,18 @@ __global__ void __launch_bounds__(256) k_prolong(ProlArgs a) {
     // 512 rows of one subdomain per block (large subdomains take several)
     const int i = a.ch_sub[blockIdx.x], r0 = a.ch_row[blockIdx.x];
     const int n = a.nB[i], C = a.nchunk[i];
-    const int nci = a.uC ? a.nc[i] : 0;
+    const int nci = a.uC ? a.nc[i] : 0, ld = phi_ld(n);
     const int32_t *ci = a.cidx + a.c_off[i];
-    const T *ph = reinterpret_cast<const T *>(a.phir) + a.phr_off[i];
+    const T *ph = reinterpret_cast<const T *>(a.phir) + a.phr_off[i];   // column-major, rows of ld
     const double *up = a.upart + a.pb[i];
     double *wl = a.wloc + a.b_off[i];
     // The first CF partial sums and PF basis entries of this thread's first
     // two rows do not depend on u_C: they are requested before its gather,
     // through range-checked loads (no conditions; entries past the
     // subdomain's arrays read as zero, other rows' entries are not used).
+    // Consecutive threads read consecutive entries of each basis column.
     const __amdgpu_buffer_rsrc_t ur = vec_rsrc(up, (int64_t)C * n);
-    const __amdgpu_buffer_rsrc_t pr = tile_rsrc(ph, n * nci * (int)sizeof(T));
+    const __amdgpu_buffer_rsrc_t pr = tile_rsrc(ph, nci * ld * (int)sizeof(T));
     const int k0 = r0 + threadIdx.x, k1 = r0 + threadIdx.x + 256;
     double u0[CF], u1[CF], pr0[PF], pr1[PF];
 #pragma unroll
@@ -703,8 +796,8 @@ __global__ void __launch_bounds__(256) k_prolong(ProlArgs a) {
     }
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
-        pr0[q] = ld_rc_as<T>(pr, k0 * nci + q);
-        pr1[q] = ld_rc_as<T>(pr, k1 * nci + q);
+        pr0[q] = ld_rc_as<T>(pr, q * ld + k0);
+        pr1[q] = ld_rc_as<T>(pr, q * ld + k1);
     }
     for (int q = threadIdx.x; q < nci; q += blockDim.x) uCl[q] = a.uC[ci[q]];
     __syncthreads();
@@ -712,12 +805,11 @@ __global__ void __launch_bounds__(256) k_prolong(ProlArgs a) {
     auto row = [&](int k, const double (&u)[CF], const double (&r)[PF]) {
         double w = 0.0;
         for (int cc = 0; cc < C; ++cc) w += cc < CF ? u[cc] : up[(int64_t)cc * n + k];
-        const T *rk = ph + (int64_t)k * nci;
 #pragma unroll
         for (int q = 0; q < PF; ++q)
             if (q < nci) w += r[q] * uCl[q];
 #pragma unroll 8
-        for (int q = PF; q < nci; ++q) w += to_d(rk[q]) * uCl[q];
+        for (int q = PF; q < nci; ++q) w += to_d(ph[(int64_t)q * ld + k]) * uCl[q];
         wl[k] = w;
     };
     if (k0 < n) row(k0, u0, pr0);
@@ -1320,15 +1412,20 @@ void launch_update(const UpdArgs &a, int grid, hipStream_t s) {
     else hipLaunchKernelGGL(k_update<1>, dim3(grid), dim3(256), 0, s, a);
 }
 
-// LDS rows of the restriction: the whole subdomain for one column, up to
-// 4096 staged values for several
-size_t crest_rows(int max_nB, int ncols) {
-    return (size_t)std::max(1, std::min(max_nB, 4096 / std::max(1, ncols)));
+// staged length of the gathered x of the restriction for interfaces of up
+// to max_nB entries (whole 16-byte pieces of a wave)
+static int crest_xl(int prec, int max_nB) {
+    const int W = 64 * (128 / prec);
+    return (phi_ld(std::max(1, max_nB)) + W - 1) / W * W;
+}
+// columns staged at a time: up to 4096 values (32 KiB of LDS)
+int crest_cols(int prec, int max_nB, int ncols) {
+    return std::max(1, std::min(ncols, 4096 / crest_xl(prec, max_nB)));
 }
 
-void launch_crest(const CrestArgs &a, int prec, int nsub, hipStream_t s) {
-    if (nsub <= 0) return;
-    const size_t smem = (size_t)a.ncols * a.rows * 8;
+void launch_crest(const CrestArgs &a, int prec, int nsub, int max_nB, hipStream_t s) {
+    if (nsub <= 0 || a.ncols <= 0) return;
+    const size_t smem = (size_t)a.cols * crest_xl(prec, max_nB) * 8;
     if (prec == 64) hipLaunchKernelGGL(k_crest<double>, dim3(nsub), dim3(256), smem, s, a);
     else if (prec == 32) hipLaunchKernelGGL(k_crest<float>, dim3(nsub), dim3(256), smem, s, a);
     else hipLaunchKernelGGL(k_crest<uint16_t>, dim3(nsub), dim3(256), smem, s, a);

@@ -31,6 +31,9 @@ __host__ __device__ inline int full_tiles(int n) {
 }
 __host__ __device__ inline int64_t strip_len(int n) { return uses_strip(n) ? (int64_t)(n % TILE) * n : 0; }
 __host__ __device__ inline int64_t op_slots(int n) { return full_tiles(n) + (strip_len(n) + 255) / 256; }
+// Row length of the column-major D Phi_i (n_c rows of n entries, zero to a
+// multiple of 8 entries: 16-byte aligned rows in every storage precision).
+__host__ __device__ inline int phi_ld(int n) { return (n + 7) & ~7; }
 // zeroed bytes after every packed tile array: the product kernel's prefetch
 // of up to 8 tiles past a work range stays inside the allocation
 constexpr int64_t TILE_TAIL_BYTES = 8 * 256 * 8;
@@ -142,8 +145,8 @@ struct PackDesc {
     const double *phi; int ldphi;  // nullable n x nc coarse basis (scaled by D rows)
     int nc;
     int64_t dst;                   // element offset of the first tile
-    int64_t phr;                   // element offset of the row-major
-                                   // (D-scaled) coarse-basis rows, or -1
+    int64_t phr;                   // element offset of the column-major
+                                   // (D-scaled) coarse basis, or -1
 };
 
 struct PtspDesc {                  // K_C = Phi^T S Phi

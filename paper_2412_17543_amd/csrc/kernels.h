@@ -38,6 +38,7 @@ struct SymvItem {
     int32_t tile, t0, t1, n;
     int32_t x_off, yoff, next;
     int32_t ntf, ntl, strip;        // the subdomain's tile rows, tiles, 1 if its tail is a strip
+    int32_t sub;                    // the subdomain
 };
 
 // A batch of packed symmetric operators in the slot layout of tile_rows and
@@ -68,6 +69,12 @@ struct SymvArgs {
     const double *x;                // global interface vector
     double *ypart;
     double *dot;                    // nullable: per-item x_i^T y_i partials
+    // Neumann batch with a coarse space: the first segment of subdomain i
+    // also writes c_i = (D Phi_i)^T x_i to cpart[c_off[i] + q] (nullable)
+    double *cpart;
+    const void *phir;               // D Phi_i, column-major (rows of phi_ld(n) entries), local precision
+    const int64_t *phr_off;
+    const int32_t *nc, *c_off;
     Ctl *ctl;
     int gated;                      // return when ctl->done
     // stopping test made at the start (Section 5), on the residual whose
@@ -97,12 +104,12 @@ struct UpdArgs {                    // Alg. 1, lines 9-11
 struct CrestArgs {                  // c_i = (D Phi_i)^T R_i x (right-hand side of eq. coarse_problem)
     Ctl *ctl;                       // returns when ctl->done
     const int32_t *nB, *b_off, *gB, *nc, *c_off;
-    const void *phir;               // D Phi_i rows, local precision
+    const void *phir;               // D Phi_i, column-major (rows of phi_ld(n) entries), local precision
     const int64_t *phr_off;
     const double *X; int64_t ldx;   // ncols columns of the interface vector
     double *part; int64_t cs;       // partial of column j, DOF q of subdomain i: part[j * cs + c_off[i] + q]
     int ncols;
-    int rows;                       // rows of gathered x staged in LDS at a time (ncols * rows doubles)
+    int cols;                       // columns whose gathered x is staged in LDS at a time
 };
 
 struct ProlArgs {                   // w_i = u_i + D Phi_i u_C (eq. averaging_subdomain_solves)
@@ -111,7 +118,7 @@ struct ProlArgs {                   // w_i = u_i + D Phi_i u_C (eq. averaging_su
     const int32_t *nB, *b_off, *nc, *c_off, *cidx;
     const int32_t *nchunk, *pb;     // Neumann work items per subdomain, partial bases
     const double *upart;
-    const void *phir;               // D Phi_i rows, local precision
+    const void *phir;               // D Phi_i, column-major (rows of phi_ld(n) entries), local precision
     const int64_t *phr_off;
     const double *uC;               // level-1 coarse solution (nullable: no coarse space)
     double *wloc;
@@ -384,8 +391,8 @@ size_t symv_smem(int prec, int nw, int max_nt);
 int set_symv_smem_limit(size_t bytes);
 void launch_symv(const SymvArgs &a, SymvOp op, int prec, SymvCfg cfg, size_t smem, hipStream_t s);
 void launch_update(const UpdArgs &a, int grid, hipStream_t s);
-void launch_crest(const CrestArgs &a, int prec, int nsub, hipStream_t s);
-size_t crest_rows(int max_nB, int ncols);
+void launch_crest(const CrestArgs &a, int prec, int nsub, int max_nB, hipStream_t s);
+int crest_cols(int prec, int max_nB, int ncols);
 void launch_prolong(const ProlArgs &a, int prec, int nblocks, int max_nc, hipStream_t s, int ncols = 1);
 void launch_zasm(const ZasmArgs &a, int kmax, int grid, hipStream_t s, int ncols = 1);
 void launch_pupd(const PupdArgs &a, int kmax, int grid, hipStream_t s);

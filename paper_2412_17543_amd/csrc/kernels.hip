@@ -110,8 +110,9 @@ __global__ void __launch_bounds__(256) k_build_saddle(const SaddleDesc *descs) {
 // of tile_rows / strip_len: 16x16 tiles (element order of tile_index), tile
 // row I holding (I, I..nt-1), zero past n; then, with a strip, the ragged
 // tail rows, row-major.  Value = sign * src[i][j] * D[i] * D[j].  With
-// phr >= 0 the coarse basis sign * phi[i][q] * D[i] is written row-major (n
-// rows of nc values) for the coarse restriction and the prolongation.
+// phr >= 0 the coarse basis sign * phi[i][q] * D[i] is written column-major
+// (nc rows of phi_ld(n) values, zero past n) for the coarse restriction and
+// the prolongation.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void store_conv(double *p, double v) { *p = v; }
 __device__ __forceinline__ void store_conv(float *p, double v) { *p = (float)v; }
@@ -149,10 +150,14 @@ __global__ void __launch_bounds__(256) k_pack(const PackDesc *descs, T *dst, T *
         store_conv(sp + e, node(n0 + r, k));
     }
     if (d.phr >= 0 && d.phi) {
-        for (int64_t e = threadIdx.x; e < (int64_t)d.n * d.nc; e += blockDim.x) {
-            const int gi = (int)(e / d.nc), q = (int)(e - (int64_t)gi * d.nc);
-            double v = d.sign * d.phi[(size_t)gi * d.ldphi + q];
-            if (d.D) v *= d.D[gi];
+        const int ld = phi_ld(d.n);
+        for (int64_t e = threadIdx.x; e < (int64_t)d.nc * ld; e += blockDim.x) {
+            const int q = (int)(e / ld), gi = (int)(e - (int64_t)q * ld);
+            double v = 0.0;
+            if (gi < d.n) {
+                v = d.sign * d.phi[(size_t)gi * d.ldphi + q];
+                if (d.D) v *= d.D[gi];
+            }
             store_conv(phir + d.phr + e, v);
         }
     }
