@@ -339,6 +339,33 @@ def test_pinned_product_configuration():
         _solver("tiny3", product_cfg=[2, 1, 5, 2, 0, 0, 0, 0])
 
 
+@pytest.mark.parametrize("name,nsub,pin_n", [("tiny3", 64, [8, 0, 4, 2]), ("c16", 8, [8, 1, 8, 4]),
+                                              ("c16", 8, [8, 0, 8, 4])])
+def test_split_neumann_products_restrict_once(name, nsub, pin_n):
+    """The coarse restriction c_i = (D Phi_i)^T r_i is formed by the first
+    work segment of each subdomain inside the Neumann product.  With many
+    small blocks (balanced ranges, or several chunks per subdomain) every
+    subdomain is split over blocks, and the preconditioner must still match
+    the oracle's (eqs. averaging_subdomain_solves, coarse_problem); the
+    float32 operators (another tail variant) agree to their precision."""
+    torch = _torch()
+    pin = [3, 1, 4, 2] + pin_n
+    g = _solver(name, product_cfg=pin, local_prec_set=(32,))
+    t = g.tuning()["neumann"]
+    assert (t["per_subdomain"], t["waves"], t["unroll"]) == tuple(pin_n[1:])
+    assert t["blocks"] > nsub                    # more blocks than subdomains
+    o = _oracle(name)
+    rng = np.random.default_rng(5)
+    for _ in range(2):
+        r = rng.standard_normal(o.ss.n_gamma)
+        z = g.apply_precond(torch.tensor(r, device="cuda")).cpu().numpy()
+        assert _rel(z, o.M.apply(r)) < 1e-9
+        g.set_local_prec(32)
+        z32 = g.apply_precond(torch.tensor(r, device="cuda")).cpu().numpy()
+        g.set_local_prec(64)
+        assert _rel(z32, z) < 1e-5
+
+
 def test_reorthogonalisation_matches_oracle():
     torch = _torch()
     F = workload.rhs_sequence(16, 5)
