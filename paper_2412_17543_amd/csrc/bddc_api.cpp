@@ -408,6 +408,27 @@ int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
         std::stable_sort(blk.begin(), blk.end(), [](const std::vector<Seg> &x, const std::vector<Seg> &y) {
             return x[0].t1 - x[0].t0 > y[0].t1 - y[0].t0;
         });
+        // XCD-aware order: consecutive blocks go to the 8 XCDs in turn, each
+        // with its own L2.  Subdomain indices, like the interface numbering,
+        // run through the domain in slabs, so inside every run of equal
+        // length block p takes a subdomain of slab p mod 8 where one is left:
+        // each XCD then gathers its inputs from about an eighth of the
+        // interface vector.  (The results do not depend on the order.)
+        constexpr int NX = 8;
+        for (size_t r0 = 0; r0 < blk.size();) {
+            const int64_t len = blk[r0][0].t1 - blk[r0][0].t0;
+            size_t r1 = r0;
+            while (r1 < blk.size() && blk[r1][0].t1 - blk[r1][0].t0 == len) ++r1;
+            std::vector<std::vector<std::vector<Seg>>> slab(NX);
+            for (size_t p = r0; p < r1; ++p) slab[(int64_t)blk[p][0].k * NX / nsub].push_back(blk[p]);
+            std::vector<size_t> next(NX, 0);
+            for (size_t p = r0; p < r1; ++p) {
+                int g = (int)(p % NX);
+                while (next[g] == slab[g].size()) g = (g + 1) % NX;   // (some slab has one left)
+                blk[p] = slab[g][next[g]++];
+            }
+            r0 = r1;
+        }
     } else {
         blk.resize(nblocks);
         int i = 0;
