@@ -447,11 +447,11 @@ int build_worklist(bddc_ctx *c, OpHost &op, int nblocks, bool per_sub) {
     }
     if (ylen > INT32_MAX) return fail(BDDC_EINVAL, "operator partial buffers exceed int32 indexing");
     // block b's first segment at index b, its others appended and chained
-    std::vector<SymvItem> items(std::max(nblocks, 1), SymvItem{0, 0, 0, 0, 0, 0, -1, 0, 0, 0, 0});
+    std::vector<SymvItem> items(std::max(nblocks, 1), SymvItem{0, 0, 0, 0, 0, 0, -1, 0, 0, 0, 0, 0});
     auto record = [&](const Seg &g) {
         const int n = sizes[g.k];
         return SymvItem{(int32_t)start[g.k], (int32_t)g.t0, (int32_t)g.t1, n, xoff[g.k], pb[g.k] + g.c * n, -1,
-                        tile_rows(n), full_tiles(n), uses_strip(n) ? 1 : 0, g.k};
+                        tile_rows(n), full_tiles(n), uses_strip(n) ? 1 : 0, g.k, g.c};
     };
     for (int b = 0; b < nblocks; ++b) {
         int prev = b;

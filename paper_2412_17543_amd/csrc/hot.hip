@@ -298,7 +298,7 @@ __device__ __forceinline__ void cm_matvec(const double *M, int64_t ldm, int r0, 
 __device__ __forceinline__ SymvItem load_item(const SymvItem *items, int i) {
     typedef const __attribute__((address_space(4))) int32_t CInt;
     CInt *q = (CInt *)(items + i);
-    return SymvItem{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9], q[10]};
+    return SymvItem{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9], q[10], q[11]};
 }
 
 template <typename T, int U>
@@ -327,19 +327,23 @@ __device__ __forceinline__ double dot16(const uvec4 &v, const X *x) {
 }
 
 // Coarse restriction c_i = (D Phi_i)^T x_i of subdomain `sub` (n rows), with
-// x_i staged in LDS (zero past n to a multiple of 16): wave w takes the
-// coarse DOFs w, w + NW, ..., QB of them at a time; a lane dots the 16-byte
+// x_i staged in LDS (zero past n to a multiple of 16), for the DOFs q = c,
+// c + C, ... of segment c of the subdomain's C (so that a split subdomain
+// shares the work): wave w takes the w-th, (w + NW)-th, ... of those DOFs,
+// QB of them at a time; a lane dots the 16-byte
 // pieces V l, V l + 64 V, ... of each DOF's column-major row with x, JM
 // pieces per round trip, and the wave's sum (fixed order) is the partial.
-// Pieces of DOFs past nc_i read as zero through the range check.
+// Pieces of DOFs past nc_i read as zero through the range check (t past
+// the segment's count gives q >= nc_i).
 template <typename T, int NW, typename X>
-__device__ __forceinline__ void coarse_tail(const SymvArgs &a, int sub, int n, const X *xs, int wu, int l) {
+__device__ __forceinline__ void coarse_tail(const SymvArgs &a, int sub, int c, int n, const X *xs, int wu, int l) {
     constexpr int V = 16 / (int)sizeof(T), W = 64 * V, QB = sizeof(T) == 2 ? 1 : 2, JM = 2;
-    const int nci = a.nc[sub], ld = phi_ld(n);
+    const int C = a.op.nchunk[sub], nci = a.nc[sub], ld = phi_ld(n);
+    const int nq = nci > c ? (nci - c + C - 1) / C : 0;   // this segment's DOFs
     const __amdgpu_buffer_rsrc_t pr =
         tile_rsrc(reinterpret_cast<const T *>(a.phir) + a.phr_off[sub], nci * ld * (int)sizeof(T));
     double *cp = a.cpart + a.c_off[sub];
-    for (int q0 = wu; q0 < nci; q0 += NW * QB) {
+    for (int t0 = wu; t0 < nq; t0 += NW * QB) {
         double acc[QB];
 #pragma unroll
         for (int qi = 0; qi < QB; ++qi) acc[qi] = 0.0;
@@ -350,7 +354,8 @@ __device__ __forceinline__ void coarse_tail(const SymvArgs &a, int sub, int n, c
 #pragma unroll
                 for (int jj = 0; jj < JM; ++jj)
                     f[qi][jj] = p0 + jj * W < ld ? __builtin_amdgcn_raw_buffer_load_b128(
-                                                       pr, ((q0 + NW * qi) * ld + p0 + jj * W) * (int)sizeof(T), 0, 0)
+                                                       pr, ((c + C * (t0 + NW * qi)) * ld + p0 + jj * W) * (int)sizeof(T),
+                                                       0, 0)
                                                  : uvec4{0u, 0u, 0u, 0u};
 #pragma unroll
             for (int qi = 0; qi < QB; ++qi)
@@ -361,8 +366,8 @@ __device__ __forceinline__ void coarse_tail(const SymvArgs &a, int sub, int n, c
 #pragma unroll
         for (int qi = 0; qi < QB; ++qi) {
             const double s = wave_sum(acc[qi]);
-            const int q = q0 + NW * qi;
-            if (l == 0 && q < nci) cp[q] = s;
+            const int t = t0 + NW * qi;
+            if (l == 0 && t < nq) cp[c + C * t] = s;
         }
     }
 }
@@ -569,8 +574,8 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
             yp[k] = y;
             dot += (double)xs[k] * y;
         }
-        if constexpr (OP::neumann) {   // the subdomain's first segment: its coarse restriction
-            if (a.cpart && it.t0 == 0) coarse_tail<T, NW>(a, it.sub, n, xs, wu, l);
+        if constexpr (OP::neumann) {   // this segment's share of the coarse restriction
+            if (a.cpart) coarse_tail<T, NW>(a, it.sub, it.chunk, n, xs, wu, l);
         }
         __syncthreads();   // LDS is reused by the next segment
         if (it.next < 0) break;

@@ -38,7 +38,7 @@ struct SymvItem {
     int32_t tile, t0, t1, n;
     int32_t x_off, yoff, next;
     int32_t ntf, ntl, strip;        // the subdomain's tile rows, tiles, 1 if its tail is a strip
-    int32_t sub;                    // the subdomain
+    int32_t sub, chunk;             // the subdomain, and this segment's index among its segments
 };
 
 // A batch of packed symmetric operators in the slot layout of tile_rows and
@@ -69,8 +69,9 @@ struct SymvArgs {
     const double *x;                // global interface vector
     double *ypart;
     double *dot;                    // nullable: per-item x_i^T y_i partials
-    // Neumann batch with a coarse space: the first segment of subdomain i
-    // also writes c_i = (D Phi_i)^T x_i to cpart[c_off[i] + q] (nullable)
+    // Neumann batch with a coarse space: segment c of the C segments of
+    // subdomain i also writes the DOFs q = c, c + C, ... of c_i = (D Phi_i)^T
+    // x_i to cpart[c_off[i] + q] (nullable)
     double *cpart;
     const void *phir;               // D Phi_i, column-major (rows of phi_ld(n) entries), local precision
     const int64_t *phr_off;
