@@ -457,7 +457,11 @@ __global__ void __launch_bounds__(NW * 64, (symv_waves_per_simd<T, U>())) k_symv
             const int k = tid + j * NT;
             if (k < npad) xs[k] = k < n ? (ACC)xv[j] : (ACC)0;
         }
-        for (int k = tid + GATHER_PER_THREAD * NT; k < npad; k += NT) xs[k] = k < n ? (ACC)a.x[gb[k]] : (ACC)0;
+        if (npad > GATHER_PER_THREAD * NT) {   // long interfaces: indices through 32-bit offsets
+            const __amdgpu_buffer_rsrc_t gr = tile_rsrc(gb, n * 4);
+            for (int k = tid + GATHER_PER_THREAD * NT; k < npad; k += NT)
+                xs[k] = k < n ? (ACC)a.x[(int)__builtin_amdgcn_raw_buffer_load_b32(gr, k * 4, 0, 0)] : (ACC)0;
+        }
         for (int k = tid; k < NW * npad; k += NT) yw[k] = (ACC)0;
         __syncthreads();
 
